@@ -1,0 +1,20 @@
+"""MI355X-native soft-sphere DEM timestep (spheres + axis-aligned walls).
+
+The compute path lives in ``libdem_hip.so`` (hand-written HIP for gfx950,
+C ABI declared in ``include/dem.h``); ``paper_2301_00611_amd.dem`` is a thin
+ctypes binding with the same names.  ``paper_2301_00611_amd.scenes`` holds
+the seeded synthetic input generators.  The binding is imported lazily so
+that the generators can be used without the compiled library.
+"""
+
+__all__ = ["dem", "scenes"]
+
+
+def __getattr__(name):
+    if name == "dem":
+        from . import dem as _dem
+        return _dem
+    if name == "scenes":
+        from . import scenes as _scenes
+        return _scenes
+    raise AttributeError(name)

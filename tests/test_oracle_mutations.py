@@ -1,0 +1,60 @@
+"""The oracle's pins must catch plausible slips.
+
+Each case applies one deliberate mistake to a private copy of the oracle's
+C source (a dropped term, a flipped sign, a wrong factor), builds it, and
+runs the pin tests against that build: at least one pin must fail.  The
+mistakes are planted in the oracle on the CPU only.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "dem_oracle.c")
+
+MUTATIONS = {
+    "drop_twist_term": ("cross3(fs_old, spinv, inc2);", "inc2[0] = inc2[1] = inc2[2] = 0.0;"),
+    "drop_plane_rotation": ("cross3(fs_old, rot, inc1);", "inc1[0] = inc1[1] = inc1[2] = 0.0;"),
+    "drop_ratcheting_factor": ("alpha = (R1 + R2) / l;", "alpha = 1.0;"),
+    "shear_increment_sign": ("- ks * dt * vs[k];", "+ ks * dt * vs[k];"),
+    "torque_branch_of_2": ("cross3(br2, f2, ct->t2);", "cross3(br1, f2, ct->t2);"),
+    "normal_force_sign": ("fn[k] = fn_mag * n[k];", "fn[k] = -fn_mag * n[k];"),
+    "damping_without_half_step": ("(v0[k] + a * dt / 2.0)", "(v0[k])"),
+    "damping_excludes_gravity": ("f[k] = F_in[k] + b->m * s->p.gravity[k];", "f[k] = F_in[k];"),
+    "elastic_energy_factor": ("*e_el += 0.5 * (fn_mag * fn_mag / kn)", "*e_el += 1.0 * (fn_mag * fn_mag / kn)"),
+    "no_image_velocity": ("for (int k = 0; k < 3; ++k) v2[k] += sv[k] / dt;", ""),
+    "no_convective_term": ("(s->p.homo_deform == 2 ? a2[k] * dt : 0.0)", "0.0"),
+    "kinetic_energy_missing": ("en->kin = 0.5 * b->m * dot3(b->v, b->v);", "en->kin = 0.0;"),
+    "inertia_rounding": ("b->I = 2.0 * b->m * r * r / 5.0;", "b->I = 0.4 * b->m * r * r;"),
+    "shear_stiffness_without_poisson": ("double s1 = (m1->young * m1->poisson) * (2.0 * R1);",
+                                        "double s1 = (m1->young) * (2.0 * R1);"),
+    "friction_max_not_min": ("*tanphi = tan(m1->friction < m2->friction ? m1->friction : m2->friction);",
+                             "*tanphi = tan(m1->friction > m2->friction ? m1->friction : m2->friction);"),
+    "wall_reference_radius": ("R1 = b2->r;\n        R2 = b2->r;", "R1 = 0.5 * b2->r;\n        R2 = b2->r;"),
+    "plastic_work_without_fmax": ("*e_plast += (fs_norm - fmax) * fmax / ks;", "*e_plast += (fs_norm - fmax) / ks;"),
+    "rotation_angle_doubled": ("double half = 0.5 * wn * dt;", "double half = wn * dt;"),
+    "overlap_dependent_branch": ("rw[k] = R2 * w2[k] + R1 * w1[k];",
+                                 "rw[k] = (R2 - 0.5 * pen) * w2[k] + (R1 - 0.5 * pen) * w1[k];"),
+    "gravity_work_sign": ("en->grav += -b->m * s->p.gravity[k] * v0[k] * dt;",
+                          "en->grav += b->m * s->p.gravity[k] * v0[k] * dt;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_catch_mutation(name, tmp_path):
+    before, after = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(before) == 1, f"mutation anchor not found: {name}"
+    mutated = tmp_path / "dem_oracle_mutated.c"
+    mutated.write_text(src.replace(before, after))
+    lib = tmp_path / "libdem_oracle_mutated.so"
+    subprocess.run(["gcc", "-std=c99", "-D_DEFAULT_SOURCE", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+                    "-I", os.path.join(ROOT, "oracle"), "-o", str(lib), str(mutated), "-lm"], check=True)
+    env = dict(os.environ, DEM_ORACLE_LIB=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       env=env, capture_output=True, text=True, cwd=ROOT, timeout=600)
+    assert r.returncode != 0, f"no pin caught mutation {name}:\n{r.stdout[-2000:]}"
+    assert "FAILED" in r.stdout

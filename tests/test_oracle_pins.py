@@ -1,0 +1,593 @@
+"""Pins of the FP64 oracle against what the documentation and mechanics fix.
+
+Each test checks the oracle against something other than itself: a number
+printed in the documentation (tests/golden/worked_examples.txt), a closed
+form, an invariant, or an independent brute-force routine written here.
+They are chosen so that a plausible slip in the oracle (a dropped term, a
+wrong sign, a swapped operand) fails at least one of them; the comment of
+each test names what it guards.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from conftest import matches_printed, read_golden
+from oracle import OracleScene
+
+GOLD = read_golden("worked_examples.txt")
+
+
+def default_material(s):
+    return s.add_material(float(GOLD["default_density"][0]), float(GOLD["default_young"][0]),
+                          float(GOLD["default_poisson"][0]), float(GOLD["default_friction"][0]))
+
+
+# ---------------------------------------------------------------- P1, P2, E1
+
+def test_mass_inertia_worked_example():
+    """Section 1.2.2 prints m and I of a unit sphere of density 1000:
+    guards the mass formula and the 2/5 m r^2 inertia, digit for digit."""
+    s = OracleScene(dt=1.0)
+    s.add_material(1000.0, 1e7, 0.3, 0.5)
+    s.add_spheres([[0, 0, 0]], [1.0])
+    m, inertia = s.get_mass()
+    assert matches_printed(m[0], GOLD["mass_r1_rho1000"])
+    assert matches_printed(inertia[0], GOLD["inertia_r1_rho1000"])
+
+
+def test_pwave_timestep_worked_example():
+    """Section 2.4.17 SpherePWaveTimeStep(1e-3, 2400, 30e9)."""
+    s = OracleScene(dt=1.0)
+    s.add_material(2400.0, 30e9, 0.3, 0.5)
+    s.add_spheres([[0, 0, 0], [1, 0, 0]], [1e-3, 2e-3])
+    assert matches_printed(s.pwave_dt(), GOLD["pwave_r1e-3_rho2400_E30e9"])
+
+
+def test_energy_trace_worked_example():
+    """Section 2.4.12 energy example, two steps of a falling sphere with
+    damping 0.4: pins eq. 2.9's sign rule applied to gravity, the leapfrog
+    update, and that energies use the mid-step velocity v-."""
+    s = OracleScene(dt=1.0)
+    default_material(s)
+    s.add_spheres([[0, 0, 0]], [1.0])
+    dt = s.pwave_dt()
+    assert dt == 0.01
+    s = OracleScene(dt=dt, gravity=(0, 0, -10), damping=0.4)
+    default_material(s)
+    s.add_spheres([[0, 0, 0]], [1.0])
+    s.step(1)
+    e1 = s.get_energy()
+    assert all(abs(v) == 0.0 for v in e1.values())
+    s.step(1)
+    e = s.get_energy()
+    assert matches_printed(e["grav_work"], GOLD["energy_step2_gravWork"])
+    assert matches_printed(e["kinetic"], GOLD["energy_step2_kinTrans"])
+    assert matches_printed(e["kin_rot"], GOLD["energy_step2_kinRot"])
+    assert matches_printed(e["damp_dissip"], GOLD["energy_step2_nonviscDamp"])
+    assert matches_printed(e["total"], GOLD["energy_step2_total"])
+    # the exact values behind the printed digits: with a = 0.6 g after damping
+    m = s.get_mass()[0][0]
+    assert e["grav_work"] == pytest.approx(-m * 0.006, rel=1e-14)
+    assert e["kinetic"] == pytest.approx(m * 0.0018, rel=1e-14)
+    assert e["damp_dissip"] == pytest.approx(m * 0.0024, rel=1e-14)
+    assert s.get_state()["vel"][0, 2] == pytest.approx(-0.12, rel=1e-14)
+
+
+# ------------------------------------------------------------ free motion
+
+def test_free_fall_is_exact_leapfrog_parabola():
+    """No contact, no damping: v_n = v0 + n g dt, x_n = x0 + dt sum v_k."""
+    dt = 1e-4
+    g = np.array([0.3, -1.0, -9.81])
+    s = OracleScene(dt=dt, gravity=g, damping=0.0)
+    s.add_material(2600.0, 1e7, 0.3, 0.5)
+    v0 = np.array([0.1, 0.2, 0.3])
+    s.add_spheres([[0, 0, 0]], [1e-3], vel=[v0])
+    n = 500
+    s.step(n)
+    st = s.get_state()
+    k = np.arange(1, n + 1)
+    x_expected = v0 * n * dt + g * dt * dt * k.sum()
+    np.testing.assert_allclose(st["vel"][0], v0 + n * g * dt, rtol=1e-12)
+    np.testing.assert_allclose(st["pos"][0], x_expected, rtol=1e-11)
+
+
+def test_free_spin_quaternion():
+    """Constant angular velocity: q(n dt) is the rotation by |w| n dt about
+    w (guards the rotation vector w+ dt of the orientation update)."""
+    dt = 1e-3
+    s = OracleScene(dt=dt)
+    s.add_material(2600.0, 1e7, 0.3, 0.5)
+    w = np.array([1.0, -2.0, 0.5])
+    s.add_spheres([[0, 0, 0]], [1e-3], angvel=[w])
+    n = 1000
+    s.step(n)
+    q = s.get_state()["ori"][0]
+    wn = np.linalg.norm(w)
+    half = 0.5 * wn * n * dt
+    expected = np.concatenate([[math.cos(half)], w / wn * math.sin(half)])
+    np.testing.assert_allclose(q, expected, atol=1e-12)
+
+
+# ------------------------------------------------------------ contacts
+
+def _pair_scene(dt, r=1e-3, rho=2600.0, E=1e7, nu=0.3, phi=0.5, gap=0.0, vrel=0.1, damping=0.0):
+    s = OracleScene(dt=dt, damping=damping)
+    s.add_material(rho, E, nu, phi)
+    x2 = 2 * r + gap
+    s.add_spheres([[0, 0, 0], [x2, 0, 0]], [r, r], vel=[[vrel / 2, 0, 0], [-vrel / 2, 0, 0]])
+    return s
+
+
+def _head_on(dt_fraction):
+    r, rho, E, vrel = 1e-3, 2600.0, 1e7, 0.1
+    m = 4.0 / 3.0 * math.pi * r ** 3 * rho
+    kn = E * r  # two equal spheres: compliance 2/(E D), section 2.3.9 Ip2
+    tc = math.pi * math.sqrt((m / 2) / kn)
+    dt = tc * dt_fraction
+    s = _pair_scene(dt, r=r, rho=rho, E=E, gap=1e-7, vrel=vrel)
+    start = end = None
+    maxpen = 0.0
+    for i in range(int(3 / dt_fraction)):
+        s.step(1)
+        c = s.get_contacts()
+        if len(c) and start is None:
+            start = i
+        if len(c):
+            maxpen = max(maxpen, c["pen"].max())
+            assert c["kn"][0] == pytest.approx(kn, rel=1e-15)
+        if start is not None and not len(c):
+            end = i
+            break
+    v = s.get_state()["vel"]
+    e = (v[1, 0] - v[0, 0]) / vrel
+    return (end - start) * dt, tc, e, maxpen, vrel * math.sqrt((m / 2) / kn), dt
+
+
+def test_head_on_collision_closed_form():
+    """Frictionless head-on impact of a linear spring: duration
+    pi sqrt(m*/kn), restitution 1, peak overlap v sqrt(m*/kn).  Guards the
+    normal force (sign, magnitude kn*pen) and the equal-sphere stiffness."""
+    t_meas, tc, e, pmax, pexp, dt = _head_on(1 / 200)
+    assert abs(t_meas - tc) <= 2 * dt
+    assert abs(e - 1.0) <= 2e-3
+    assert pmax == pytest.approx(pexp, rel=2e-3)
+    t2, _, e2, _, _, dt2 = _head_on(1 / 2000)
+    assert abs(t2 - tc) <= 2 * dt2
+    assert abs(e2 - 1.0) < abs(e - 1.0) or abs(e2 - 1.0) < 2e-4
+
+
+def _floor_scene(dt, pen0, gravity, phi=0.5, damping=0.0, blocked=None, vel=None, angvel=None,
+                 wall_phi=None, r=1e-3, E=1e7, nu=0.3):
+    s = OracleScene(dt=dt, gravity=gravity, damping=damping)
+    sm = s.add_material(2600.0, E, nu, phi)
+    wm = sm if wall_phi is None else s.add_material(2600.0, E, nu, wall_phi)
+    s.add_wall(2, 0.0, 1, wm)
+    s.add_spheres([[0, 0, r - pen0]], [r], vel=vel, angvel=angvel, default_mat=sm,
+                  blocked=None if blocked is None else [blocked])
+    return s
+
+
+def test_static_overlap_on_floor():
+    """A damped sphere settles on a wall at pen = m g / kn with kn = E r
+    (Ig2_Wall_Sphere_ScGeom: the wall's reference radius is the sphere's)."""
+    r, E = 1e-3, 1e7
+    m = 4.0 / 3.0 * math.pi * r ** 3 * 2600.0
+    dt = 0.5 * r * math.sqrt(2600.0 / E)
+    s = _floor_scene(dt, 0.0, (0, 0, -9.81), damping=0.2)
+    s.step(20000)
+    c = s.get_contacts()
+    assert len(c) == 1 and c["is_wall"][0] == 1 and c["id1"][0] == 0
+    assert c["kn"][0] == pytest.approx(E * r, rel=1e-15)
+    assert c["ks"][0] == pytest.approx(0.3 * E * r, rel=1e-15)
+    assert c["pen"][0] == pytest.approx(m * 9.81 / (E * r), rel=1e-6)
+    np.testing.assert_allclose(c["normal"][0], [0, 0, 1])
+
+
+def test_sliding_block_acceleration():
+    """A sphere with rotations blocked slides down a slope (tilted gravity):
+    a = g (sin t - tan(phi) cos t).  The wall's friction angle is the smaller
+    one, so this also checks tan(min(phi1, phi2))."""
+    r, E, g, theta, phi = 1e-3, 1e7, 9.81, 0.5, 0.3
+    m = 4.0 / 3.0 * math.pi * r ** 3 * 2600.0
+    kn = E * r
+    grav = (g * math.sin(theta), 0.0, -g * math.cos(theta))
+    pen0 = m * g * math.cos(theta) / kn
+    dt = 0.5 * r * math.sqrt(2600.0 / E)
+    s = _floor_scene(dt, pen0, grav, phi=0.9, wall_phi=phi, blocked=8 | 16 | 32)
+    s.step(200)
+    v1 = s.get_state()["vel"][1, 0]
+    s.step(1000)
+    v2 = s.get_state()["vel"][1, 0]
+    a = (v2 - v1) / (1000 * dt)
+    assert a == pytest.approx(g * (math.sin(theta) - math.tan(phi) * math.cos(theta)), rel=1e-6)
+    fs = s.get_contacts()["fs"][0]
+    assert fs[0] < 0  # friction on the sphere opposes sliding
+
+
+def test_sticking_below_friction_angle():
+    """Below the friction angle the sphere sticks: the shear spring, loaded
+    from zero, oscillates up to twice the static offset m g sin(t)/ks (the
+    slope is chosen so that twice the load stays under the Coulomb cap)."""
+    r, E, g, theta, phi = 1e-3, 1e7, 9.81, 0.1, 0.3
+    m = 4.0 / 3.0 * math.pi * r ** 3 * 2600.0
+    grav = (g * math.sin(theta), 0.0, -g * math.cos(theta))
+    pen0 = m * g * math.cos(theta) / (E * r)
+    dt = 0.5 * r * math.sqrt(2600.0 / E)
+    s = _floor_scene(dt, pen0, grav, phi=phi, blocked=8 | 16 | 32)
+    xs = []
+    for _ in range(40):
+        s.step(50)
+        xs.append(s.get_state()["pos"][1, 0])
+    # elastic shear spring: bounded oscillation around the static offset
+    static = m * g * math.sin(theta) / (0.3 * E * r)
+    assert max(abs(x) for x in xs) <= 2.05 * static
+    assert s.get_energy()["plastic_dissip"] == 0.0
+
+
+def test_sliding_to_rolling():
+    """A sphere launched without spin on a rough floor ends rolling at
+    v = 5/7 v0, w = v/r, and friction dissipates m v0^2 / 7.  Guards the
+    torque sign and lever arm (-r2 n) x F and the shear-force sign."""
+    r, E, g, v0 = 1e-3, 1e7, 9.81, 0.1
+    m = 4.0 / 3.0 * math.pi * r ** 3 * 2600.0
+    pen0 = m * g / (E * r)
+    dt = 0.5 * r * math.sqrt(2600.0 / E)
+    s = _floor_scene(dt, pen0, (0, 0, -g), phi=0.5, vel=[[v0, 0, 0]])
+    s.step(3000)
+    # the tangential contact spring keeps a small undamped oscillation (a few
+    # steps long): average it out over the last 1000 steps
+    vs, ws = [], []
+    for _ in range(1000):
+        s.step(1)
+        st = s.get_state()
+        vs.append(st["vel"][1, 0])
+        ws.append(st["angvel"][1, 1])
+    v, w = np.mean(vs), np.mean(ws)
+    assert v == pytest.approx(5 / 7 * v0, rel=5e-3)
+    assert w * r == pytest.approx(v, rel=5e-3)
+    e = s.get_energy()
+    assert e["plastic_dissip"] == pytest.approx(m * v0 ** 2 / 7, rel=1e-2)
+
+
+def test_ratchet_cycle_closes():
+    """Ig2_Sphere_Sphere_ScGeom.avoidGranularRatcheting: body 1 fixed, body
+    2 pushed along the normal, rotated by a, pulled back, rotated by -a.
+    With radius branches the shear returns to zero; a branch that depends
+    on the overlap (e.g. contact point - centre) would leave a residual."""
+    r = 1e-3
+    dt = 1e-6
+    s = OracleScene(dt=dt)
+    s.add_material(2600.0, 1e7, 0.3, 1.5)
+    pen0 = 1e-5
+    s.add_spheres([[0, 0, 0], [2 * r - pen0, 0, 0]], [r, r], blocked=[63, 63])
+    k = 100
+    dx, a = 2e-5, 2e-3
+    n = s.num_bodies
+    phases = [((-dx / (k * dt), 0, 0), (0, 0, 0)), ((0, 0, 0), (0, 0, a / (k * dt))),
+              ((dx / (k * dt), 0, 0), (0, 0, 0)), ((0, 0, 0), (0, 0, -a / (k * dt)))]
+    peak = 0.0
+    for v, w in phases:
+        vel = np.zeros((n, 3))
+        ang = np.zeros((n, 3))
+        vel[1] = v
+        ang[1] = w
+        s.set_state(vel=vel, angvel=ang)
+        s.step(k)
+        peak = max(peak, np.linalg.norm(s.get_contacts()["fs"][0]))
+    ks = 0.3 * 1e7 * r
+    assert peak == pytest.approx(ks * r * a, rel=1e-3)
+    assert np.linalg.norm(s.get_contacts()["fs"][0]) <= 1e-9 * ks * r * a
+
+
+def _rigid_rotation(axis_kind):
+    """Two overlapping spheres carrying a shear force, rotated as one rigid
+    body at rate W.  Returns (Fs after K steps, Fs0 rotated by W t, normal)."""
+    r, dt, K, W = 1e-3, 1e-6, 2000, 400.0
+    s = OracleScene(dt=dt)
+    s.add_material(2600.0, 1e7, 0.3, 1.5)
+    pen = 2e-5
+    x = np.array([[0.0, 0, 0], [2 * r - pen, 0, 0]])
+    s.add_spheres(x, [r, r], blocked=[63, 63])
+    n0 = np.array([1.0, 0, 0])
+    fs0 = np.array([0.0, 0.3, -0.4]) * 1e-3
+    s.set_contacts([0], [1], fs=[fs0], nprev=[n0])
+    Wv = np.array([0.0, 0.0, W]) if axis_kind == "perp" else np.array([W, 0.0, 0.0])
+    centre = x.mean(axis=0)
+    for _ in range(K):
+        p = s.get_state()["pos"]
+        vel = np.cross(Wv, p - centre)
+        s.set_state(vel=vel, angvel=np.tile(Wv, (2, 1)))
+        s.step(1)
+    c = s.get_contacts()
+    th = W * K * dt
+    u = Wv / W
+    rot = (np.cos(th) * np.eye(3) + np.sin(th) * np.array([[0, -u[2], u[1]], [u[2], 0, -u[0]], [-u[1], u[0], 0]])
+           + (1 - np.cos(th)) * np.outer(u, u))
+    return c["fs"][0], rot @ fs0, c["normal"][0], fs0
+
+
+@pytest.mark.parametrize("axis_kind", ["perp", "twist"])
+def test_shear_objectivity_under_rigid_rotation(axis_kind):
+    """Section 2.1.3: the shear vector must follow a rigid motion of the
+    pair.  'perp' (rotation about an axis normal to n) exercises the
+    n_prev x n term and the (r1+r2)/l factor; 'twist' (rotation about n)
+    exercises the dt/2 n.(w1+w2) term."""
+    fs, fs_expected, n, fs0 = _rigid_rotation(axis_kind)
+    assert np.linalg.norm(fs - fs_expected) <= 2e-3 * np.linalg.norm(fs0)
+    assert abs(np.dot(fs, n)) <= 2e-3 * np.linalg.norm(fs0)
+    assert np.linalg.norm(fs) == pytest.approx(np.linalg.norm(fs0), rel=2e-3)
+
+
+# ------------------------------------------------------------ many bodies
+
+def _gas(n=150, box=0.013, seed=3, phi=0.5, periodic=False, vscale=0.05, damping=0.0, gravity=(0, 0, 0),
+         walls=False, dt_fraction=0.5):
+    """A small random packing squeezed by 12 % so that many pairs overlap;
+    optionally in a periodic cube of side `box`, or closed by 6 walls."""
+    from paper_2301_00611_amd.scenes import compressed_cloud, random_velocities
+    pos, rad = compressed_cloud(n, box, 0.8e-3, 1.2e-3, 0.88, seed)
+    v, w = random_velocities(n, vscale, seed + 1)
+    dt = dt_fraction * 0.8e-3 * math.sqrt(2600.0 / 1e7)
+    s = OracleScene(dt=dt, damping=damping, gravity=gravity, periodic=periodic,
+                    hsize=np.eye(3) * box if periodic else None)
+    m = s.add_material(2600.0, 1e7, 0.3, phi)
+    if walls:
+        for axis in range(3):
+            for p in (0.0, box):
+                s.add_wall(axis, p, 0, m)
+    s.add_spheres(pos, rad, vel=v, angvel=w * 0.1)
+    return s
+
+
+def test_linear_momentum_conserved():
+    """Action-reaction: F on #1 is exactly -F on #2, so the total momentum
+    of a free (periodic) packing only changes by rounding."""
+    s = _gas(periodic=True)
+    m = s.get_mass()[0]
+    p0 = (m[:, None] * s.get_state()["vel"]).sum(axis=0)
+    scale = (m * np.linalg.norm(s.get_state()["vel"], axis=1)).sum()
+    ncontacts = 0
+    for _ in range(20):
+        s.step(50)
+        ncontacts += len(s.get_contacts())
+    assert ncontacts > 100
+    p1 = (m[:, None] * s.get_state()["vel"]).sum(axis=0)
+    assert np.linalg.norm(p1 - p0) <= 1e-13 * scale
+
+
+def test_angular_momentum_drift_bounded():
+    """With radius lever arms (sphericalBodies) a contact's torque about the
+    origin is -pen n x F, so sum(x x m v + I w) drifts by at most
+    sum pen |Fs| dt per step."""
+    s = _gas(seed=5)
+    m, inertia = s.get_mass()
+
+    def L(st):
+        return (np.cross(st["pos"], m[:, None] * st["vel"]) + inertia[:, None] * st["angvel"]).sum(axis=0)
+
+    dt = 0.5 * 0.8e-3 * math.sqrt(2600.0 / 1e7)
+    L0 = L(s.get_state())
+    bound = 0.0
+    for _ in range(400):
+        s.step(1)
+        c = s.get_contacts()
+        if len(c):
+            bound += (c["pen"] * np.linalg.norm(c["fs"], axis=1)).sum() * dt
+    drift = np.linalg.norm(L(s.get_state()) - L0)
+    assert drift <= 1.01 * bound + 1e-12 * np.abs(L0).sum() + 1e-30
+    assert bound > 0.0
+
+
+def _energy_series(dt_fraction, steps):
+    s = _gas(phi=0.0, seed=7, vscale=0.2, walls=True, dt_fraction=dt_fraction)
+    E, K = [], []
+    for _ in range(100):
+        s.step(steps // 100)
+        e = s.get_energy()
+        assert e["plastic_dissip"] == 0.0
+        E.append(e["kinetic"] + e["kin_rot"] + e["elastic"])
+        K.append(e["kinetic"] + e["kin_rot"])
+    E, K = np.array(E), np.array(K)
+    return (E[-20:].mean() - E[:20].mean()) / E[:20].mean(), E.std() / K.std()
+
+
+def test_elastic_energy_conserved_frictionless():
+    """phi = 0, no damping, no gravity, elastic walls: E_kin + E_rot + E_el
+    is conserved up to the time discretisation.  The kinetic terms use v-
+    while the elastic one uses x, so E fluctuates by O(dt): halving dt must
+    halve the fluctuation (a wrong elastic-energy factor would leave it
+    O(1)) and shrink the drift (O(dt^2))."""
+    drift1, fluct1 = _energy_series(0.25, 5000)
+    drift2, fluct2 = _energy_series(0.125, 10000)
+    assert fluct2 < 0.6 * fluct1
+    assert fluct2 < 0.1
+    assert abs(drift2) <= 1e-3
+    assert abs(drift2) < abs(drift1) or abs(drift2) < 2e-4
+
+
+def test_coulomb_bound_every_step():
+    s = _gas(seed=11, vscale=0.3, phi=0.3, damping=0.1)
+    eps = np.finfo(float).eps
+    seen = 0
+    for _ in range(300):
+        s.step(1)
+        c = s.get_contacts()
+        if not len(c):
+            continue
+        fs = np.linalg.norm(c["fs"], axis=1)
+        fn = np.linalg.norm(c["fn"], axis=1)
+        assert np.all(fs <= math.tan(0.3) * fn * (1 + 4 * eps) + 1e-300)
+        seen += int((fs > 0.99 * math.tan(0.3) * fn).sum())
+    assert seen > 0  # some contacts actually slide
+
+
+def test_energy_budget_closes_with_walls():
+    """Total energy of a damped, frictional, gravitating run with walls stays
+    at its initial value up to O(dt) (regression figure, loose bound)."""
+    from paper_2301_00611_amd.scenes import cloud_box
+    sc = cloud_box(n=200, box=0.015, seed=2)
+    s = OracleScene(dt=1.0)
+    s.add_material(2600.0, 1e7, 0.3, 0.5)
+    s.add_spheres(sc.pos, sc.radius)
+    dt = 0.5 * s.pwave_dt()
+    s = OracleScene(dt=dt, gravity=sc.gravity, damping=sc.damping)
+    mat = s.add_material(2600.0, 1e7, 0.3, 0.5)
+    for w in sc.walls:
+        s.add_wall(w.axis, w.position, w.sense, mat)
+    s.add_spheres(sc.pos, sc.radius)
+    s.step(3000)
+    e = s.get_energy()
+    scale = abs(e["grav_work"])
+    assert scale > 0
+    assert abs(e["total"]) <= 2e-2 * scale
+
+
+def _sort_and_sweep_pairs(pos, rad):
+    """Independent pair finder: sort centres on x, sweep while the x gap is
+    below r_i + r_max, apply the exact predicate |d|^2 < (r1 + r2)^2 with the
+    same left-to-right evaluation."""
+    order = np.argsort(pos[:, 0], kind="stable")
+    rmax = rad.max()
+    pairs = set()
+    for a in range(len(order)):
+        i = order[a]
+        for b in range(a + 1, len(order)):
+            j = order[b]
+            if pos[j, 0] - pos[i, 0] > rad[i] + rmax:
+                break
+            lo, hi = (i, j) if i < j else (j, i)
+            d = pos[hi] - pos[lo]
+            dd = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]
+            s = rad[lo] + rad[hi]
+            if dd < s * s:
+                pairs.add((int(lo), int(hi)))
+    return pairs
+
+
+def test_pair_detection_matches_independent_sweep():
+    from paper_2301_00611_amd.scenes import compressed_cloud
+    pos, rad = compressed_cloud(400, 0.02, 0.5e-3, 1.5e-3, 0.95, 21)
+    s = OracleScene(dt=1e-6)
+    s.add_material(2600.0, 1e7, 0.3, 0.5)
+    s.add_spheres(pos, rad)
+    id1, id2, _ = s.detect_pairs()
+    got = set(zip(id1.tolist(), id2.tolist()))
+    assert got == _sort_and_sweep_pairs(pos, rad)
+    assert len(got) > 50
+
+
+def test_spot_step_matches_full_step():
+    """The spot mode (k bodies against all) gives the same forces and new
+    state as the full step, bit for bit (same order of operations)."""
+    s = _gas(seed=13, vscale=0.1, damping=0.2, gravity=(0, 0, -9.81))
+    s.step(30)
+    ids = np.arange(0, 150, 7)
+    spot = s.spot_step(ids)
+    s.step(1)
+    st = s.get_state()
+    for key in ("force", "torque", "pos", "vel", "angvel", "ori"):
+        np.testing.assert_array_equal(spot[key], st[key][ids])
+
+
+# ------------------------------------------------------------ walls, DOFs
+
+def test_wall_sense_one_sided():
+    """Wall.sense: +1 / -1 interact from that side only, 0 from both.  A
+    sphere crossing a one-sided wall is pushed back to its side (overlap
+    r + |delta|); a sphere that does not reach the plane never touches."""
+    r, z = 1e-3, 0.5e-3
+    for sense, nz, pen in ((1, 1.0, r - z), (0, 1.0, r - z), (-1, -1.0, r + z)):
+        s = OracleScene(dt=1e-6)
+        m = s.add_material(2600.0, 1e7, 0.3, 0.5)
+        s.add_wall(2, 0.0, sense, m)
+        s.add_spheres([[0, 0, z], [0, 0, -1.5 * r], [0, 0, 3 * r]], [r, r, r])
+        s.step(1)
+        c = s.get_contacts()
+        assert len(c) == 1 and c["id2"][0] == 1
+        assert c["normal"][0][2] == nz
+        assert c["pen"][0] == pytest.approx(pen, rel=1e-12)
+
+
+def test_blocked_dofs_keep_velocity():
+    """State.blockedDOFs: blocked components keep their (prescribed)
+    velocity under gravity and contacts; free ones accelerate."""
+    s = OracleScene(dt=1e-5, gravity=(0, 0, -9.81))
+    s.add_material(2600.0, 1e7, 0.3, 0.5)
+    s.add_spheres([[0, 0, 0]], [1e-3], vel=[[0.5, 0, 0.1]], blocked=[4])
+    s.step(100)
+    v = s.get_state()["vel"][0]
+    assert v[2] == 0.1 and v[0] == 0.5
+    assert s.get_state()["pos"][0][2] == pytest.approx(100 * 1e-5 * 0.1, rel=1e-12)
+
+
+# ------------------------------------------------------------ periodic cell
+
+def test_affine_motion_in_periodic_cell():
+    """Cell.homoDeform = 2: a force-free particle follows x = F(t) x0 with
+    F(t) the cell's integrated transformation (exact up to rounding); with
+    homoDeform = 1 the convective term is missing and it lags."""
+    L = np.array([[0.0, 0.0, 1.0], [0.0, -0.3, 0.0], [0.2, 0.0, 0.0]])
+    x0 = np.array([0.01, 0.02, 0.03])
+    res = {}
+    for hd in (2, 1):
+        s = OracleScene(dt=1e-3, periodic=True, hsize=np.eye(3) * 0.1, velgrad=L, homo_deform=hd)
+        s.add_material(2600.0, 1e7, 0.3, 0.5)
+        s.add_spheres([x0], [1e-3])
+        s.step(200)
+        _, trsf = s.get_cell()
+        res[hd] = np.linalg.norm(s.get_state()["pos"][0] - trsf @ x0)
+    assert res[2] <= 1e-15
+    assert res[1] > 1e-9
+
+
+def _sheared_pair(shift_cells):
+    """Two overlapping spheres in a simple-shear cell; the second one is
+    displaced by an integer combination of cell vectors."""
+    H = np.eye(3) * 0.01
+    L = np.array([[0.0, 0.0, 2.0], [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    s = OracleScene(dt=2e-7, periodic=True, hsize=H, velgrad=L, homo_deform=2)
+    s.add_material(2600.0, 1e7, 0.3, 0.5)
+    x1 = np.array([0.004, 0.005, 0.0095])
+    x2 = x1 + np.array([0.3e-3, 0.2e-3, 1.9e-3]) + H @ np.asarray(shift_cells, dtype=float)
+    s.add_spheres([x1, x2], [1e-3, 1e-3], vel=[[0.01, 0, 0], [-0.02, 0.01, 0]], angvel=[[0, 5, 0], [1, 0, 0]])
+    return s
+
+
+def test_periodic_translation_invariance():
+    """Section 2.1.6 (cellDist): the same pair with #2 moved by a cell
+    vector (here across the sheared z boundary) must feel the same forces,
+    step after step, including the image's velocity (H - H_prev) c / dt."""
+    a = _sheared_pair((0, 0, 0))
+    b = _sheared_pair((0, 0, -1))
+    together = 0
+    for _ in range(400):
+        a.step(1)
+        b.step(1)
+        ca, cb = a.get_contacts(), b.get_contacts()
+        assert len(ca) == len(cb)
+        if not len(ca):
+            break
+        together += 1
+        assert tuple(cb["cell"][0]) == (0, 0, 1)
+        for key in ("fn", "fs"):
+            scale = np.linalg.norm(ca[key][0]) + 1e-30
+            assert np.linalg.norm(ca[key][0] - cb[key][0]) <= 1e-9 * scale
+        assert np.linalg.norm(ca["fs"][0]) > 0
+    assert together > 100
+
+
+def test_periodic_pair_detection_through_images():
+    """Brute-force images: a pair separated by almost one cell is in contact
+    through the image; the reported cell shift is the one that makes
+    x2 + H c - x1 short."""
+    H = np.array([[0.01, 0.002, 0.0], [0.0, 0.01, 0.0], [0.0, 0.0, 0.01]])
+    s = OracleScene(dt=1e-7, periodic=True, hsize=H, homo_deform=2)
+    s.add_material(2600.0, 1e7, 0.3, 0.5)
+    x1 = np.array([0.0005, 0.005, 0.005])
+    x2 = x1 + H @ np.array([1.0, 0, 0]) - np.array([1.5e-3, 0, 0]) + np.array([0.0, 0.0, 0.0])
+    s.add_spheres([x1, x2 + H @ np.array([2.0, 0, 0])], [1e-3, 1e-3])
+    id1, id2, cell = s.detect_pairs()
+    assert len(id1) == 1
+    assert tuple(cell[0]) == (-3, 0, 0)
