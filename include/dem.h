@@ -1,0 +1,219 @@
+/*
+ * dem.h -- C ABI of libdem_hip.so, an MI355X (gfx950) implementation of one
+ * soft-sphere discrete-element timestep over spheres and axis-aligned walls,
+ * as described in the Yade DEM documentation (3rd ed., arXiv 2301.00611):
+ *
+ *   collider (section 2.1.1, InsertionSortCollider role)  -> Morton sort +
+ *       cell-list sweep on the GPU, re-run only when a body may have moved
+ *       farther than the Verlet distance (eq. 2.3-2.4);
+ *   Ig2_Sphere_Sphere_ScGeom / Ig2_Wall_Sphere_ScGeom (section 2.1.3, class
+ *       ScGeom): normal, overlap, contact point, shear update;
+ *   Ip2_FrictMat_FrictMat_FrictPhys (section 2.1.2): kn, ks, tan(phi);
+ *   Law2_ScGeom_FrictPhys_CundallStrack (section 2.1.4): linear normal force,
+ *       incremental shear spring, Mohr-Coulomb cap;
+ *   force/torque sum (ForceContainer), deterministic, no float atomics;
+ *   NewtonIntegrator (section 2.1.5): gravity, Cundall damping eq. 2.9,
+ *       leapfrog, spherical rotation; periodic Cell (section 2.1.6).
+ *
+ * Conventions
+ *   Ids: one id space over walls and spheres, in insertion order from 0
+ *     (O.bodies.append returns sequential ids).  Ids never change; the
+ *     library reorders bodies internally but always speaks ids.
+ *   Contacts: sphere-sphere contacts have #1 = lower id; a wall-sphere
+ *     contact always has the wall as #1.  The normal points from #1 to #2
+ *     (class ScGeom.normal).  Forces are those sustained by #2 (class
+ *     FrictPhys.normalForce / shearForce).  `cell` is the periodic image of
+ *     #2 (Interaction.cellDist).
+ *   Matrices are 3x3 row-major; the cell vectors are the columns of hsize.
+ *   Units are SI.  All floating-point arguments are double.
+ *
+ * Ownership
+ *   Every input array is deep-copied before the call returns.  Outputs go to
+ *   caller-allocated buffers whose size the caller states; DEM_ECAPACITY
+ *   reports the size needed.  The scene (or batch) owns all device memory;
+ *   dem_destroy / dem_batch_destroy free it.  A batch's scene views own
+ *   nothing and must not be destroyed.
+ *
+ * Errors
+ *   Every call returns DEM_OK (0) or a dem_status code; dem_last_error()
+ *   returns a thread-local message valid until the next call on that thread.
+ *   After any error except DEM_EDEVICE the scene is unchanged and usable.
+ *
+ * Threading: a scene is not thread-safe; distinct scenes may be used from
+ * distinct threads.
+ */
+#ifndef DEM_H
+#define DEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DEM_ABI_VERSION 1
+
+typedef int32_t dem_status;
+enum {
+    DEM_OK = 0,
+    DEM_EINVAL = 1,       /* bad argument (NULL, n < 0, r <= 0, bad axis/sense, ...) */
+    DEM_ERANGE = 2,       /* body id out of range */
+    DEM_ENOENT = 3,       /* no such object */
+    DEM_ECAPACITY = 4,    /* caller buffer too small; *out_count holds the size needed */
+    DEM_ENOMEM = 5,       /* device or host allocation failed */
+    DEM_EDEVICE = 6,      /* HIP runtime error; message holds the HIP error string */
+    DEM_ENONFINITE = 7,   /* NaN/Inf in positions or velocities after a step */
+    DEM_EPERIODIC = 8,    /* periodic cell too small for the spheres and Verlet distance */
+    DEM_EUNSTABLE = 9     /* overlap exceeded a sphere radius ("numerically exploding") */
+};
+
+enum { DEM_FP64 = 0, DEM_FP32_MIXED = 1 };
+
+typedef struct dem_scene dem_scene;
+typedef struct dem_batch dem_batch;
+
+typedef struct {
+    double dt;            /* timestep [s] (> 0) */
+    double gravity[3];    /* NewtonIntegrator.gravity [m/s^2] */
+    double damping;       /* NewtonIntegrator.damping, Cundall lambda in [0, 1) */
+    int32_t damp_rot;     /* 1: apply eq. 2.9 to torques too (default 1) */
+    double verlet_dist;   /* Delta L [m]; < 0 means -verlet_dist * (smallest radius)
+                             (InsertionSortCollider.verletDist, default -0.5) */
+    int32_t precision;    /* DEM_FP64 or DEM_FP32_MIXED */
+    int32_t periodic;     /* 1: periodic cell (no walls allowed) */
+    double hsize[9];      /* Cell.hSize, columns are the cell vectors */
+    double velgrad[9];    /* Cell.velGrad */
+    int32_t homo_deform;  /* Cell.homoDeform 0, 1 or 2 (default 2) */
+    int32_t track_energy; /* 1: accumulate the energy terms every step */
+    int32_t device;       /* HIP device ordinal */
+    void* stream;         /* hipStream_t to run on, or NULL for a library-owned stream */
+} dem_params;
+
+/* One real contact. */
+typedef struct {
+    int64_t id1, id2;
+    int32_t cell[3];
+    int32_t is_wall;
+    double normal[3];     /* unit, from #1 to #2 */
+    double pen;           /* overlap (> 0 for a touching pair) */
+    double point[3];      /* contact point, middle of the overlap */
+    double fn[3];         /* normal force on #2 */
+    double fs[3];         /* shear force on #2 (after the Coulomb cap) */
+    double kn, ks;
+} dem_contact;
+
+/* Shear history record, for checkpoint/restore and tests. */
+typedef struct {
+    int64_t id1, id2;
+    int32_t cell[3];
+    int32_t pad;
+    double fs[3];         /* shear force on #2 */
+    double nprev[3];      /* normal of the previous step */
+} dem_history;
+
+typedef struct {
+    double kinetic;        /* sum 1/2 m |v-|^2 of the last step */
+    double kin_rot;        /* sum 1/2 I |w-|^2 of the last step */
+    double elastic;        /* sum 1/2 |Fn|^2/kn + 1/2 |Fs|^2/ks of the last step */
+    double grav_work;      /* cumulative work of gravity, negated */
+    double damp_dissip;    /* cumulative energy removed by eq. 2.9 */
+    double plastic_dissip; /* cumulative Coulomb slip work */
+    double total;          /* sum of the above */
+} dem_energy;
+
+typedef struct {
+    int64_t iter;            /* steps done */
+    double time;             /* simulated time [s] */
+    int64_t n_spheres, n_walls;
+    int64_t n_contacts_ss;   /* real sphere-sphere contacts at the last step */
+    int64_t n_contacts_sw;   /* real sphere-wall contacts at the last step */
+    int64_t n_candidates;    /* candidate pairs kept by the last broad phase */
+    int64_t rebuilds;        /* broad-phase runs so far */
+    int64_t contact_steps;   /* sum over steps of the real contacts */
+    double coordination;     /* 2 C_ss / N_spheres (utils.avgNumInteractions) */
+    double verlet_dist;      /* Delta L in use [m] */
+} dem_stats;
+
+int32_t dem_abi_version(void);
+const char* dem_last_error(void);
+/* Fill *p with the documentation's defaults (damping 0.2, verletDist -0.5,
+ * homoDeform 2, FP64, energy tracking off, device 0, no stream, dt = 0). */
+void dem_params_default(dem_params* p);
+
+dem_status dem_create(const dem_params* p, dem_scene** out);
+dem_status dem_destroy(dem_scene* s);
+
+/* FrictMat (section 2.3.1 materials): density > 0 [kg/m3], young > 0 [Pa],
+ * poisson in (-1, 0.5], friction_angle in [0, pi/2) [rad]. */
+dem_status dem_add_material(dem_scene* s, double density, double young, double poisson,
+                            double friction_angle, int32_t* out_mat);
+/* Append n spheres (ids out_first_id .. +n-1).  pos3 [n*3], radius [n] are
+ * required; vel3, angvel3 [n*3], mat [n], blocked [n] may be NULL (zero /
+ * default_mat / none).  blocked bits 1,2,4 = x,y,z translation, 8,16,32 =
+ * rotation (State.blockedDOFs): a blocked component keeps its velocity.
+ * Mass = 4/3 pi r^3 rho, inertia = 2 m r^2 / 5.  Host buffers. */
+dem_status dem_add_spheres(dem_scene* s, int64_t n, const double* pos3, const double* radius,
+                           const double* vel3, const double* angvel3, const int32_t* mat,
+                           int32_t default_mat, const uint8_t* blocked, int64_t* out_first_id);
+/* Infinite plane normal to axis (0,1,2) at `position`; sense -1/0/+1
+ * (class Wall): the side(s) it interacts with.  Walls do not move. */
+dem_status dem_add_wall(dem_scene* s, int32_t axis, double position, int32_t sense, int32_t mat,
+                        int64_t* out_id);
+
+/* utils.PWaveTimeStep: min over spheres of r / sqrt(E / rho). */
+dem_status dem_pwave_dt(dem_scene* s, double* out);
+dem_status dem_set_dt(dem_scene* s, double dt);
+/* Periodic scenes: replace Cell.velGrad (applied from the next step). */
+dem_status dem_set_velgrad(dem_scene* s, const double* velgrad9);
+dem_status dem_get_cell(dem_scene* s, double* hsize9, double* trsf9);
+
+/* Advance nsteps steps (O.run(n, wait=True)); returns when they are done. */
+dem_status dem_step(dem_scene* s, int64_t nsteps);
+
+/* State of `count` bodies starting at id first_id, in id order, into HOST
+ * buffers; any pointer may be NULL.  force3/torque3 are the resultants of
+ * the last step's contacts (gravity excluded; walls get the reaction).  For
+ * a wall, pos3[axis] is its position and the rest is 0. */
+dem_status dem_get_state(dem_scene* s, int64_t first_id, int64_t count, double* pos3, double* vel3,
+                         double* angvel3, double* ori4, double* force3, double* torque3);
+/* Same, into DEVICE buffers on the scene's device (e.g. torch tensors); the
+ * copy is ordered on the scene's stream and complete when the call returns. */
+dem_status dem_get_state_device(dem_scene* s, int64_t first_id, int64_t count, double* pos3,
+                                double* vel3, double* angvel3, double* ori4);
+/* Overwrite the state of every sphere (ids in order; walls skipped); any
+ * pointer may be NULL.  Forces a broad-phase run before the next step. */
+dem_status dem_set_state(dem_scene* s, const double* pos3, const double* vel3,
+                         const double* angvel3, const double* ori4);
+/* Mass and inertia of every body (0 for walls). */
+dem_status dem_get_mass(dem_scene* s, double* mass, double* inertia);
+
+/* Real contacts of the last step, sorted by (min id, max id, cell). */
+dem_status dem_get_contacts(dem_scene* s, int64_t capacity, dem_contact* out, int64_t* out_count);
+/* Shear history (all real contacts); dem_set_history replaces it and forces
+ * a broad-phase run (the records are carried onto the new candidate list). */
+dem_status dem_get_history(dem_scene* s, int64_t capacity, dem_history* out, int64_t* out_count);
+dem_status dem_set_history(dem_scene* s, int64_t n, const dem_history* in);
+
+dem_status dem_get_energy(dem_scene* s, dem_energy* out);
+dem_status dem_get_stats(dem_scene* s, dem_stats* out);
+/* Average device duration [ms] of each kernel family over the last
+ * dem_step call (names: "contact", "integrate", "rebuild"), measured with
+ * HIP events when timing is on. */
+dem_status dem_set_timing(dem_scene* s, int32_t on);
+dem_status dem_get_timing(dem_scene* s, const char* name, double* avg_ms, int64_t* launches);
+
+/* Batched scenes: n_scenes independent scenes advanced together by the same
+ * kernels (one bodies arena, per-scene parameters).  per_scene[i].periodic
+ * must be 0; precision, device and stream are taken from per_scene[0]. */
+dem_status dem_batch_create(int32_t n_scenes, const dem_params* per_scene, dem_batch** out);
+/* Non-owning view of scene i: use it with dem_add_*, dem_get_*, dem_pwave_dt.
+ * dem_step on a view is refused: step the whole batch. */
+dem_status dem_batch_scene(dem_batch* b, int32_t i, dem_scene** view);
+dem_status dem_batch_step(dem_batch* b, int64_t nsteps);
+dem_status dem_batch_stats(dem_batch* b, dem_stats* out);
+dem_status dem_batch_destroy(dem_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,513 @@
+// broadphase.hip -- the collider's role (section 2.1.1, InsertionSortCollider)
+// rebuilt for the GPU: bodies are binned in cells no smaller than the largest
+// candidate distance (2 r_max + 2 Delta L), sorted by the Morton code of their
+// cell, and each body sweeps the 27 cells around its own for candidates whose
+// enlarged spheres overlap (distance < r_i + r_j + 2 Delta L).  The run is
+// needed only when some body may have moved farther than Delta L since the
+// last one (eq. 2.3-2.4).  Candidate pairs are stored once (owner = #1 of the
+// contact); every body keeps a row of its candidate pairs sorted by partner
+// id, and the shear history of surviving pairs is carried over by id.
+#include "dem_internal.hpp"
+
+#include <cfloat>
+
+namespace dem {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr uint32_t kEmpty = 0xffffffffu;
+
+__device__ inline uint64_t spread3(uint64_t v)
+{
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+__device__ inline uint32_t compact3(uint64_t v)
+{
+    v &= 0x1249249249249249ull;
+    v = (v ^ (v >> 2)) & 0x10c30c30c30c30c3ull;
+    v = (v ^ (v >> 4)) & 0x100f00f00f00f00full;
+    v = (v ^ (v >> 8)) & 0x1f0000ff0000ffull;
+    v = (v ^ (v >> 16)) & 0x1f00000000ffffull;
+    v = (v ^ (v >> 32)) & 0x1fffffull;
+    return (uint32_t)v;
+}
+
+__device__ inline uint64_t morton3(int x, int y, int z)
+{
+    return spread3((uint64_t)x) | (spread3((uint64_t)y) << 1) | (spread3((uint64_t)z) << 2);
+}
+
+__device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Pack an integer image shift (each component in [-512, 511]) so that
+// unsigned comparison orders shifts lexicographically.
+__device__ inline int32_t pack_cell(int cx, int cy, int cz)
+{
+    return (int32_t)(((uint32_t)(cx + 512) << 20) | ((uint32_t)(cy + 512) << 10) | (uint32_t)(cz + 512));
+}
+__device__ inline void unpack_cell(int32_t p, int* c)
+{
+    uint32_t u = (uint32_t)p;
+    c[0] = (int)((u >> 20) & 1023u) - 512;
+    c[1] = (int)((u >> 10) & 1023u) - 512;
+    c[2] = (int)(u & 1023u) - 512;
+}
+// packed (0, 0, 0): the shift of every aperiodic pair and every wall pair
+constexpr int32_t kCellZero = (int32_t)((512u << 20) | (512u << 10) | 512u);
+__device__ inline int32_t neg_cell(int32_t p)
+{
+    int c[3];
+    unpack_cell(p, c);
+    return pack_cell(-c[0], -c[1], -c[2]);
+}
+
+// Cell of a body and, in a periodic cell, its integer period.
+template <bool PERIODIC>
+__device__ inline void cell_of(const SceneParams& P, double x, double y, double z, int* c, int* per)
+{
+    if (!PERIODIC) {
+        c[0] = clampi((int)floor((x - P.origin[0]) * P.inv_h[0]), 0, P.dims[0] - 1);
+        c[1] = clampi((int)floor((y - P.origin[1]) * P.inv_h[1]), 0, P.dims[1] - 1);
+        c[2] = clampi((int)floor((z - P.origin[2]) * P.inv_h[2]), 0, P.dims[2] - 1);
+        per[0] = per[1] = per[2] = 0;
+        return;
+    }
+    const double* M = P.Hinv;
+    double f[3] = {M[0] * x + M[1] * y + M[2] * z, M[3] * x + M[4] * y + M[5] * z, M[6] * x + M[7] * y + M[8] * z};
+    for (int k = 0; k < 3; ++k) {
+        double p = floor(f[k]);
+        per[k] = (int)p;
+        c[k] = clampi((int)floor((f[k] - p) * P.inv_h[k]), 0, P.dims[k] - 1);
+    }
+}
+
+__device__ inline unsigned long long ord_bits(double v)
+{
+    unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+}
+
+// ------------------------------------------------------------------ bounds
+
+__global__ void __launch_bounds__(kBlock) k_bounds(Bodies b, int nslots, int batched,
+                                                   unsigned long long* __restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < nslots;
+    const int s = valid && batched ? (int)b.scene[i] : 0;
+    unsigned long long v[6];
+    if (valid) {
+        v[0] = ~ord_bits(b.x[i]);
+        v[1] = ~ord_bits(b.y[i]);
+        v[2] = ~ord_bits(b.z[i]);
+        v[3] = ord_bits(b.x[i]);
+        v[4] = ord_bits(b.y[i]);
+        v[5] = ord_bits(b.z[i]);
+    } else {
+        for (int k = 0; k < 6; ++k) v[k] = 0ull;
+    }
+    // every value is reduced as a maximum (minima are stored complemented)
+    const int s0 = __shfl(s, 0, 64);
+    const bool uniform = __all(!valid || s == s0);
+    if (uniform) {
+        for (int k = 0; k < 6; ++k)
+            for (int off = 32; off > 0; off >>= 1) {
+                unsigned long long o = __shfl_xor(v[k], off, 64);
+                v[k] = o > v[k] ? o : v[k];
+            }
+        if ((threadIdx.x & 63) == 0 && __any(valid))
+            for (int k = 0; k < 6; ++k) atomicMax(&out[s0 * 6 + k], v[k]);
+    } else if (valid) {
+        for (int k = 0; k < 6; ++k) atomicMax(&out[s * 6 + k], v[k]);
+    }
+}
+
+__global__ void k_bounds_decode(unsigned long long* __restrict__ bits, double* __restrict__ out, int n6)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n6) return;
+    unsigned long long v = bits[i];
+    if (i % 6 < 3) v = ~v;
+    unsigned long long raw = (v & 0x8000000000000000ull) ? (v & 0x7fffffffffffffffull) : ~v;
+    out[i] = __longlong_as_double((long long)raw);
+}
+
+// -------------------------------------------------------------------- keys
+
+template <bool BATCHED, bool PERIODIC>
+__global__ void __launch_bounds__(kBlock) k_keys(GridArgs g, uint64_t* __restrict__ keys,
+                                                 uint32_t* __restrict__ vals)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.nslots) return;
+    const int s = BATCHED ? (int)g.bod.scene[i] : 0;
+    const SceneParams& P = (BATCHED || PERIODIC) ? g.scenes[s] : g.scene0;
+    int c[3], per[3];
+    cell_of<PERIODIC>(P, g.bod.x[i], g.bod.y[i], g.bod.z[i], c, per);
+    uint64_t key = morton3(c[0], c[1], c[2]);
+    if (BATCHED) key |= (uint64_t)s << (3 * g.morton_bits);
+    keys[i] = key;
+    vals[i] = (uint32_t)i;
+    if (PERIODIC) g.bod.period[i] = pack_cell(per[0], per[1], per[2]);
+}
+
+// ----------------------------------------------------------------- permute
+
+__global__ void __launch_bounds__(kBlock) k_permute(Bodies src, Bodies dst, const uint32_t* __restrict__ order,
+                                                    int nslots, int batched, int periodic,
+                                                    int32_t* __restrict__ slot_of_id)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nslots) return;
+    const uint32_t o = order[i];
+    dst.x[i] = src.x[o];
+    dst.y[i] = src.y[o];
+    dst.z[i] = src.z[o];
+    dst.vx[i] = src.vx[o];
+    dst.vy[i] = src.vy[o];
+    dst.vz[i] = src.vz[o];
+    dst.wx[i] = src.wx[o];
+    dst.wy[i] = src.wy[o];
+    dst.wz[i] = src.wz[o];
+    dst.qw[i] = src.qw[o];
+    dst.qx[i] = src.qx[o];
+    dst.qy[i] = src.qy[o];
+    dst.qz[i] = src.qz[o];
+    dst.rad[i] = src.rad[o];
+    dst.mass[i] = src.mass[o];
+    dst.mat[i] = src.mat[o];
+    dst.blocked[i] = src.blocked[o];
+    const int32_t id = src.id[o];
+    dst.id[i] = id;
+    if (batched) dst.scene[i] = src.scene[o];
+    if (periodic) dst.period[i] = src.period[o];
+    slot_of_id[id] = i;
+}
+
+// ------------------------------------------------------------------- cells
+
+__device__ inline int cell_linear(const GridArgs& g, uint64_t key, const SceneParams** Pout)
+{
+    const uint64_t mmask = (g.morton_bits * 3 >= 64) ? ~0ull : ((1ull << (3 * g.morton_bits)) - 1ull);
+    const int s = g.nscenes > 1 ? (int)(key >> (3 * g.morton_bits)) : 0;
+    const SceneParams& P = g.nscenes > 1 ? g.scenes[s] : g.scene0;
+    *Pout = &P;
+    const uint64_t m = key & mmask;
+    const int cx = (int)compact3(m), cy = (int)compact3(m >> 1), cz = (int)compact3(m >> 2);
+    return P.cell_offset + cx + P.dims[0] * (cy + P.dims[1] * cz);
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void __launch_bounds__(kBlock) k_cells(GridArgs g, const uint64_t* __restrict__ keys,
+                                                  uint32_t* __restrict__ cell_start, uint32_t* __restrict__ cell_end,
+                                                  int ncells)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.nslots) return;
+    const uint64_t k = keys[i];
+    const SceneParams* P;
+    const int lin = cell_linear(g, k, &P);
+    if (lin < 0 || lin >= ncells) return;
+    if (i == 0 || keys[i - 1] != k) cell_start[lin] = (uint32_t)i;
+    if (i == g.nslots - 1 || keys[i + 1] != k) cell_end[lin] = (uint32_t)(i + 1);
+}
+
+// ------------------------------------------------------------------- sweep
+
+// Visit every candidate of home slot i (27 cells, then the scene's walls).
+// f(partner_slot_or_wall, partner_id, packed_cell) is called per candidate.
+template <bool BATCHED, bool PERIODIC, typename F>
+__device__ inline void for_each_candidate(const SweepArgs& a, int i, F&& f)
+{
+    const GridArgs& g = a.g;
+    const Bodies& B = g.bod;
+    const int s = BATCHED ? (int)B.scene[i] : 0;
+    const SceneParams& P = (BATCHED || PERIODIC) ? g.scenes[s] : g.scene0;
+    const double xi = B.x[i], yi = B.y[i], zi = B.z[i], ri = B.rad[i];
+    const int32_t myid = B.id[i];
+    const double reach = 2.0 * P.verlet;
+    int c[3], per_i[3];
+    cell_of<PERIODIC>(P, xi, yi, zi, c, per_i);
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                int n[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
+                int w[3] = {0, 0, 0};
+                bool skip = false;
+                for (int k = 0; k < 3; ++k) {
+                    if (n[k] < 0) {
+                        if (!PERIODIC) skip = true;
+                        n[k] += P.dims[k];
+                        w[k] = -1;
+                    } else if (n[k] >= P.dims[k]) {
+                        if (!PERIODIC) skip = true;
+                        n[k] -= P.dims[k];
+                        w[k] = 1;
+                    }
+                }
+                if (skip) continue;
+                const int lin = P.cell_offset + n[0] + P.dims[0] * (n[1] + P.dims[1] * n[2]);
+                const uint32_t st = a.cell_start[lin];
+                if (st == kEmpty) continue;
+                const uint32_t en = a.cell_end[lin];
+                for (uint32_t j = st; j < en; ++j) {
+                    if ((int)j == i) continue;
+                    const double rj = B.rad[j];
+                    const double sc = (ri + rj) + reach;
+                    double ddx, ddy, ddz;
+                    int32_t packed = kCellZero;
+                    if (PERIODIC) {
+                        int pj[3];
+                        unpack_cell(B.period[j], pj);
+                        const int cc[3] = {per_i[0] - pj[0] + w[0], per_i[1] - pj[1] + w[1], per_i[2] - pj[2] + w[2]};
+                        packed = pack_cell(cc[0], cc[1], cc[2]);
+                        // evaluate from the lower id's side so that both bodies of
+                        // a pair take the same decision
+                        const bool from_i = myid < B.id[j];
+                        const int sg = from_i ? 1 : -1;
+                        const double* H = P.H;
+                        const double sx = (H[0] * (sg * cc[0]) + H[1] * (sg * cc[1])) + H[2] * (sg * cc[2]);
+                        const double sy = (H[3] * (sg * cc[0]) + H[4] * (sg * cc[1])) + H[5] * (sg * cc[2]);
+                        const double sz = (H[6] * (sg * cc[0]) + H[7] * (sg * cc[1])) + H[8] * (sg * cc[2]);
+                        const double ax = from_i ? xi : B.x[j], ay = from_i ? yi : B.y[j], az = from_i ? zi : B.z[j];
+                        const double bx = from_i ? B.x[j] : xi, by = from_i ? B.y[j] : yi, bz = from_i ? B.z[j] : zi;
+                        ddx = (bx + sx) - ax;
+                        ddy = (by + sy) - ay;
+                        ddz = (bz + sz) - az;
+                    } else {
+                        ddx = B.x[j] - xi;
+                        ddy = B.y[j] - yi;
+                        ddz = B.z[j] - zi;
+                    }
+                    const double dd = (ddx * ddx + ddy * ddy) + ddz * ddz;
+                    if (dd < sc * sc) f((int32_t)j, B.id[j], packed);
+                }
+            }
+    for (int k = 0; k < P.wall_count; ++k) {
+        const int wi = P.wall_begin + k;
+        const Wall W = a.walls[wi];
+        const double xa = W.axis == 0 ? xi : (W.axis == 1 ? yi : zi);
+        const double delta = xa - W.pos;
+        if (fabs(delta) < ri + reach) f(-1 - wi, W.id, kCellZero);
+    }
+}
+
+template <bool BATCHED, bool PERIODIC>
+__global__ void __launch_bounds__(kBlock) k_sweep_count(SweepArgs a)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.g.nslots) return;
+    uint32_t n = 0;
+    for_each_candidate<BATCHED, PERIODIC>(a, i, [&](int32_t, int32_t, int32_t) { ++n; });
+    a.count[i] = n;
+}
+
+template <bool BATCHED, bool PERIODIC>
+__global__ void __launch_bounds__(kBlock) k_sweep_fill(SweepArgs a)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.g.nslots) return;
+    const int beg = a.row_start[i];
+    const int cap = a.row_start[i + 1] - beg;
+    const int32_t myid = a.g.bod.id[i];
+    int n = 0;
+    for_each_candidate<BATCHED, PERIODIC>(a, i, [&](int32_t slot, int32_t pid, int32_t cell) {
+        if (n < cap) {
+            a.ent_slot[beg + n] = slot;
+            a.ent_pid[beg + n] = pid;
+            a.ent_cell[beg + n] = cell;
+        }
+        ++n;
+    });
+    // sort the row by (partner id, image): this fixes the order of the force sum
+    for (int p = 1; p < cap; ++p) {
+        const int32_t ks = a.ent_slot[beg + p], kp = a.ent_pid[beg + p], kc = a.ent_cell[beg + p];
+        int q = p - 1;
+        while (q >= 0) {
+            const int32_t qp = a.ent_pid[beg + q];
+            const int32_t qc = a.ent_cell[beg + q];
+            if (qp < kp || (qp == kp && (uint32_t)qc <= (uint32_t)kc)) break;
+            a.ent_slot[beg + q + 1] = a.ent_slot[beg + q];
+            a.ent_pid[beg + q + 1] = qp;
+            a.ent_cell[beg + q + 1] = qc;
+            --q;
+        }
+        a.ent_slot[beg + q + 1] = ks;
+        a.ent_pid[beg + q + 1] = kp;
+        a.ent_cell[beg + q + 1] = kc;
+    }
+    for (int p = 0; p < cap; ++p) {
+        const int32_t slot = a.ent_slot[beg + p];
+        a.ent_own[beg + p] = (slot < 0 || myid < a.ent_pid[beg + p]) ? 1u : 0u;
+    }
+}
+
+// -------------------------------------------------------- pairs and history
+
+__global__ void __launch_bounds__(kBlock) k_pair_build(PairBuildArgs a)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.nslots) return;
+    const int beg = a.row_start[i], end = a.row_start[i + 1];
+    const int32_t myid = a.bod.id[i];
+    for (int e = beg; e < end; ++e) {
+        const int32_t slot = a.ent_slot[e];
+        if (a.ent_own[e]) {
+            const uint32_t k = a.own_scan[e];
+            if (slot < 0) {
+                a.pr.a[k] = slot;
+                a.pr.b[k] = i;
+                a.rows.ent[e] = k;
+            } else {
+                a.pr.a[k] = i;
+                a.pr.b[k] = slot;
+                a.rows.ent[e] = k | kNegSign;
+            }
+            a.pr.cell[k] = a.ent_cell[e];
+            a.pr.pid[k] = a.ent_pid[e];
+        } else {
+            // the pair is owned by the partner: find this body in its row
+            const int32_t want = neg_cell(a.ent_cell[e]);
+            const int jb = a.row_start[slot], je = a.row_start[slot + 1];
+            uint32_t k = kPairMask;
+            for (int f = jb; f < je; ++f)
+                if (a.ent_pid[f] == myid && a.ent_cell[f] == want && a.ent_own[f]) {
+                    k = a.own_scan[f];
+                    break;
+                }
+            a.rows.ent[e] = k;
+        }
+    }
+    a.hist_new.own_begin[myid] = (int32_t)a.own_scan[beg];
+    a.hist_new.own_count[myid] = (int32_t)(a.own_scan[end] - a.own_scan[beg]);
+}
+
+__global__ void __launch_bounds__(kBlock) k_carry_over(PairBuildArgs a, int old_nbodies)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.npairs) return;
+    const int32_t sa = a.pr.a[k], sb = a.pr.b[k];
+    const int32_t owner = sa >= 0 ? a.bod.id[sa] : a.bod.id[sb];
+    const int32_t partner = a.pr.pid[k];
+    const int32_t cell = a.pr.cell[k];
+    double fx = 0.0, fy = 0.0, fz = 0.0, nx = 0.0, ny = 0.0, nz = 0.0;
+    if (a.has_old && owner < old_nbodies) {
+        const int lo = a.hist_old.own_begin[owner];
+        const int cnt = a.hist_old.own_count[owner];
+        for (int q = lo; q < lo + cnt; ++q) {
+            if (a.hist_old.pid[q] == partner && a.hist_old.cell[q] == cell) {
+                fx = a.hist_old.fsx[q];
+                fy = a.hist_old.fsy[q];
+                fz = a.hist_old.fsz[q];
+                nx = a.hist_old.nx[q];
+                ny = a.hist_old.ny[q];
+                nz = a.hist_old.nz[q];
+                break;
+            }
+        }
+    }
+    a.pr.fsx[k] = fx;
+    a.pr.fsy[k] = fy;
+    a.pr.fsz[k] = fz;
+    a.pr.nx[k] = nx;
+    a.pr.ny[k] = ny;
+    a.pr.nz[k] = nz;
+}
+
+inline int nblocks(long n) { return (int)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+void launch_bounds(const Bodies& b, const uint16_t* scene, int nslots, int nscenes, double* out6, hipStream_t st)
+{
+    (void)scene;
+    // out6 doubles as the scratch for the ordered bits (same size)
+    unsigned long long* bits = reinterpret_cast<unsigned long long*>(out6);
+    (void)hipMemsetAsync(bits, 0, sizeof(unsigned long long) * 6 * nscenes, st);
+    if (nslots > 0)
+        hipLaunchKernelGGL(k_bounds, dim3(nblocks(nslots)), dim3(kBlock), 0, st, b, nslots, nscenes > 1 ? 1 : 0, bits);
+    hipLaunchKernelGGL(k_bounds_decode, dim3(nblocks(6 * nscenes)), dim3(kBlock), 0, st, bits, out6, 6 * nscenes);
+}
+
+void launch_keys(const GridArgs& g, uint64_t* keys, uint32_t* vals, hipStream_t st)
+{
+    if (g.nslots <= 0) return;
+    const bool batched = g.nscenes > 1;
+    const bool periodic = g.scene0.periodic != 0;
+    dim3 grid(nblocks(g.nslots)), blk(kBlock);
+    if (batched)
+        hipLaunchKernelGGL((k_keys<true, false>), grid, blk, 0, st, g, keys, vals);
+    else if (periodic)
+        hipLaunchKernelGGL((k_keys<false, true>), grid, blk, 0, st, g, keys, vals);
+    else
+        hipLaunchKernelGGL((k_keys<false, false>), grid, blk, 0, st, g, keys, vals);
+}
+
+void launch_permute(const Bodies& src, const Bodies& dst, const uint32_t* order, int nslots, bool batched,
+                    bool periodic, int32_t* slot_of_id, hipStream_t st)
+{
+    if (nslots <= 0) return;
+    hipLaunchKernelGGL(k_permute, dim3(nblocks(nslots)), dim3(kBlock), 0, st, src, dst, order, nslots,
+                       batched ? 1 : 0, periodic ? 1 : 0, slot_of_id);
+}
+
+void launch_cells(const GridArgs& g, const uint64_t* sorted_keys, uint32_t* cell_start, uint32_t* cell_end,
+                  int ncells, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill_u32, dim3(nblocks(ncells)), dim3(kBlock), 0, st, cell_start, kEmpty, ncells);
+    hipLaunchKernelGGL(k_fill_u32, dim3(nblocks(ncells)), dim3(kBlock), 0, st, cell_end, 0u, ncells);
+    if (g.nslots > 0)
+        hipLaunchKernelGGL(k_cells, dim3(nblocks(g.nslots)), dim3(kBlock), 0, st, g, sorted_keys, cell_start,
+                           cell_end, ncells);
+}
+
+void launch_sweep_count(const SweepArgs& a, hipStream_t st)
+{
+    if (a.g.nslots <= 0) return;
+    dim3 grid(nblocks(a.g.nslots)), blk(kBlock);
+    if (a.g.nscenes > 1)
+        hipLaunchKernelGGL((k_sweep_count<true, false>), grid, blk, 0, st, a);
+    else if (a.g.scene0.periodic)
+        hipLaunchKernelGGL((k_sweep_count<false, true>), grid, blk, 0, st, a);
+    else
+        hipLaunchKernelGGL((k_sweep_count<false, false>), grid, blk, 0, st, a);
+}
+
+void launch_sweep_fill(const SweepArgs& a, hipStream_t st)
+{
+    if (a.g.nslots <= 0) return;
+    dim3 grid(nblocks(a.g.nslots)), blk(kBlock);
+    if (a.g.nscenes > 1)
+        hipLaunchKernelGGL((k_sweep_fill<true, false>), grid, blk, 0, st, a);
+    else if (a.g.scene0.periodic)
+        hipLaunchKernelGGL((k_sweep_fill<false, true>), grid, blk, 0, st, a);
+    else
+        hipLaunchKernelGGL((k_sweep_fill<false, false>), grid, blk, 0, st, a);
+}
+
+void launch_pair_build(const PairBuildArgs& a, hipStream_t st)
+{
+    if (a.nslots <= 0) return;
+    hipLaunchKernelGGL(k_pair_build, dim3(nblocks(a.nslots)), dim3(kBlock), 0, st, a);
+}
+
+void launch_carry_over(const PairBuildArgs& a, hipStream_t st, int old_nbodies)
+{
+    if (a.npairs <= 0) return;
+    hipLaunchKernelGGL(k_carry_over, dim3(nblocks(a.npairs)), dim3(kBlock), 0, st, a, old_nbodies);
+}
+
+}  // namespace dem

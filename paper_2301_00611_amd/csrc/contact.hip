@@ -1,0 +1,376 @@
+// contact.hip -- the InteractionLoop for one fixed set of functors: one
+// thread per candidate pair runs the exact contact test, the ScGeom update
+// (class ScGeom; section 2.1.3), Ip2_FrictMat_FrictMat_FrictPhys (section
+// 2.1.2) and Law2_ScGeom_FrictPhys_CundallStrack (section 2.1.4), and writes
+// the pair's shear history and its force on #2.  No scatter happens here:
+// each body sums its pairs later, in a fixed order (integrate.hip).
+//
+// FP64 mode computes everything in double.  FP32-mixed mode keeps the
+// contact test, the branch length and the overlap in double (they are
+// differences of absolute positions), then evaluates the normal, the
+// relative velocity, the stiffnesses and the forces in float; the shear
+// force history stays double (the float increment is added to it).
+#include "dem_internal.hpp"
+
+namespace dem {
+
+namespace {
+
+constexpr int kMaxBlock = 1024;
+
+template <typename T>
+struct V3 {
+    T x, y, z;
+};
+template <typename T>
+__device__ inline V3<T> v3(T x, T y, T z) { return {x, y, z}; }
+template <typename T>
+__device__ inline V3<T> operator+(V3<T> a, V3<T> b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <typename T>
+__device__ inline V3<T> operator-(V3<T> a, V3<T> b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <typename T>
+__device__ inline V3<T> operator*(T s, V3<T> a) { return {s * a.x, s * a.y, s * a.z}; }
+template <typename T>
+__device__ inline T dot(V3<T> a, V3<T> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <typename T>
+__device__ inline V3<T> cross(V3<T> a, V3<T> b)
+{
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+template <typename T, typename U>
+__device__ inline V3<T> cvt(V3<U> a) { return {(T)a.x, (T)a.y, (T)a.z}; }
+
+// The exact contact test of two spheres: |d|^2 < (r1 + r2)^2 with
+// d = (x2 + H c) - x1, evaluated left to right with no fused multiply-add,
+// so that the pair set is identical bit for bit to a plain FP64 evaluation.
+struct SpherePairTest {
+    double dx, dy, dz, dd;
+    bool real;
+};
+template <bool PERIODIC>
+__device__ __attribute__((noinline)) SpherePairTest sphere_pair_test(double x1, double y1, double z1, double x2,
+                                                                      double y2, double z2, double r1, double r2,
+                                                                      const double* H, int cx, int cy, int cz)
+{
+#pragma clang fp contract(off)
+    SpherePairTest t;
+    if (PERIODIC) {
+        const double sx = (H[0] * (double)cx + H[1] * (double)cy) + H[2] * (double)cz;
+        const double sy = (H[3] * (double)cx + H[4] * (double)cy) + H[5] * (double)cz;
+        const double sz = (H[6] * (double)cx + H[7] * (double)cy) + H[8] * (double)cz;
+        t.dx = (x2 + sx) - x1;
+        t.dy = (y2 + sy) - y1;
+        t.dz = (z2 + sz) - z1;
+    } else {
+        t.dx = x2 - x1;
+        t.dy = y2 - y1;
+        t.dz = z2 - z1;
+    }
+    t.dd = (t.dx * t.dx + t.dy * t.dy) + t.dz * t.dz;
+    const double s = r1 + r2;
+    t.real = t.dd < s * s;
+    return t;
+}
+
+__device__ inline void unpack_cell(int32_t p, int* c)
+{
+    uint32_t u = (uint32_t)p;
+    c[0] = (int)((u >> 20) & 1023u) - 512;
+    c[1] = (int)((u >> 10) & 1023u) - 512;
+    c[2] = (int)(u & 1023u) - 512;
+}
+
+__device__ inline int logical_block(int nb)
+{
+    // blocks are dispatched round-robin over the 8 XCDs; give each XCD a
+    // contiguous range of work so neighbouring pairs share its L2
+    const int b = blockIdx.x;
+    const int xcd = b & 7, idx = b >> 3;
+    const int q = nb >> 3, r = nb & 7;
+    return xcd * q + (xcd < r ? xcd : r) + idx;
+}
+
+struct ContactPartial {
+    double el, plast;
+    unsigned long long ss, sw;
+};
+
+template <int PREC, bool BATCHED, bool PERIODIC>
+__global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restrict__ args)
+{
+    using R = typename std::conditional<PREC == DEM_FP32_MIXED, float, double>::type;
+    // the arguments live in device memory so that a captured graph stays
+    // valid across broad-phase runs (pair count and buffers change there)
+    const StepArgs& a = *args;
+    if (a.ctr->stall) return;
+    const int k = logical_block(gridDim.x) * blockDim.x + threadIdx.x;
+    ContactPartial part = {0.0, 0.0, 0ull, 0ull};
+    bool unstable = false;
+    if (k < a.npairs) {
+        const Bodies& B = a.bod;
+        const Pairs& P = a.pr;
+        const int32_t sa = P.a[k];
+        const int32_t sb = P.b[k];
+        const int s = BATCHED ? (int)B.scene[sb] : 0;
+        const SceneParams& S = (BATCHED || PERIODIC) ? a.scenes[s] : a.scene0;
+        const double dt = S.dt;
+
+        const double x2 = B.x[sb], y2 = B.y[sb], z2 = B.z[sb], r2 = B.rad[sb];
+        const int m2 = B.mat[sb];
+        const bool wall = sa < 0;
+        double x1 = 0.0, y1 = 0.0, z1 = 0.0, r1 = 0.0;
+        int m1;
+        Wall W;
+        if (!wall) {
+            x1 = B.x[sa];
+            y1 = B.y[sa];
+            z1 = B.z[sa];
+            r1 = B.rad[sa];
+            m1 = B.mat[sa];
+        } else {
+            W = a.walls[-1 - sa];
+            m1 = W.mat;
+        }
+
+        // ---- exact test, normal, overlap (always in double)
+        bool real;
+        double pen, inv_l = 0.0, l = 0.0;
+        V3<double> n64;
+        int cc[3] = {0, 0, 0};
+        if (!wall) {
+            if (PERIODIC) unpack_cell(P.cell[k], cc);
+            const SpherePairTest t =
+                sphere_pair_test<PERIODIC>(x1, y1, z1, x2, y2, z2, r1, r2, S.H, cc[0], cc[1], cc[2]);
+            real = t.real;
+            l = sqrt(t.dd);
+            inv_l = 1.0 / l;
+            n64 = v3(t.dx * inv_l, t.dy * inv_l, t.dz * inv_l);
+            pen = (r1 + r2) - l;
+            if (pen < 0.0) pen = 0.0;
+        } else {
+            const double xa = W.axis == 0 ? x2 : (W.axis == 1 ? y2 : z2);
+            const double delta = xa - W.pos;
+            real = fabs(delta) < r2;
+            const double sg = W.sense != 0 ? (double)W.sense : (delta >= 0.0 ? 1.0 : -1.0);
+            pen = r2 - sg * delta;
+            n64 = v3(W.axis == 0 ? sg : 0.0, W.axis == 1 ? sg : 0.0, W.axis == 2 ? sg : 0.0);
+        }
+
+        if (!real) {
+            P.fsx[k] = 0.0;
+            P.fsy[k] = 0.0;
+            P.fsz[k] = 0.0;
+            P.nx[k] = 0.0;
+            P.ny[k] = 0.0;
+            P.nz[k] = 0.0;
+            if (PREC == DEM_FP32_MIXED) {
+                P.fxf[k] = 0.f;
+                P.fyf[k] = 0.f;
+                P.fzf[k] = 0.f;
+                P.txf[k] = 0.f;
+                P.tyf[k] = 0.f;
+                P.tzf[k] = 0.f;
+            } else {
+                P.fx[k] = 0.0;
+                P.fy[k] = 0.0;
+                P.fz[k] = 0.0;
+                P.tx[k] = 0.0;
+                P.ty[k] = 0.0;
+                P.tz[k] = 0.0;
+            }
+        } else {
+            // ---- ScGeom inputs
+            const double R1d = wall ? r2 : r1;
+            const double R2d = r2;
+            V3<double> v1d = v3(0.0, 0.0, 0.0), w1d = v3(0.0, 0.0, 0.0);
+            if (!wall) {
+                v1d = v3(B.vx[sa], B.vy[sa], B.vz[sa]);
+                w1d = v3(B.wx[sa], B.wy[sa], B.wz[sa]);
+            }
+            V3<double> v2d = v3(B.vx[sb], B.vy[sb], B.vz[sb]);
+            const V3<double> w2d = v3(B.wx[sb], B.wy[sb], B.wz[sb]);
+            if (PERIODIC) {
+                // the image of #2 moves with the cell: (H - H_prev) c / dt
+                const double* D = S.dH;
+                const double sx = (D[0] * (double)cc[0] + D[1] * (double)cc[1]) + D[2] * (double)cc[2];
+                const double sy = (D[3] * (double)cc[0] + D[4] * (double)cc[1]) + D[5] * (double)cc[2];
+                const double sz = (D[6] * (double)cc[0] + D[7] * (double)cc[1]) + D[8] * (double)cc[2];
+                v2d = v3(v2d.x + sx / dt, v2d.y + sy / dt, v2d.z + sz / dt);
+            }
+            // relative translational velocity in double (difference of absolute values)
+            const V3<double> dv64 = v2d - v1d;
+
+            // ---- Ip2_FrictMat_FrictMat_FrictPhys: series springs k_i = E_i (2 R_i)
+            const Material M1 = a.mats[m1];
+            const Material M2 = a.mats[m2];
+            const R k1 = (R)M1.young * ((R)2 * (R)R1d), k2 = (R)M2.young * ((R)2 * (R)R2d);
+            const R kn = k1 * k2 / (k1 + k2);
+            const R q1 = (R)M1.young_poisson * ((R)2 * (R)R1d), q2 = (R)M2.young_poisson * ((R)2 * (R)R2d);
+            const R ks = q1 * q2 / (q1 + q2);
+            const R tanphi = (R)a.tanphi[m1 * a.nmat + m2];
+
+            const V3<R> n = cvt<R>(n64);
+            const R penr = (R)pen;
+            const R Rd1 = (R)R1d, Rd2 = (R)R2d;
+            const R dtr = (R)dt;
+
+            // ---- shear update (section 2.1.3): both rotation increments from
+            // the previous vector, then the sliding increment
+            const V3<double> fs_old64 = v3(P.fsx[k], P.fsy[k], P.fsz[k]);
+            const V3<R> fs_old = cvt<R>(fs_old64);
+            const V3<R> nprev = v3((R)P.nx[k], (R)P.ny[k], (R)P.nz[k]);
+            const V3<R> inc1 = cross(fs_old, cross(nprev, n));
+            const V3<R> w1 = cvt<R>(w1d), w2 = cvt<R>(w2d);
+            const R spin = (dtr / (R)2) * dot(n, w1 + w2);
+            const V3<R> inc2 = cross(fs_old, spin * n);
+            // v12 = alpha (v2 - v1) - (r2 w2 + r1 w1) x n, alpha = (r1 + r2)/l
+            const R alpha = wall ? (R)1 : (R)((r1 + r2) * inv_l);
+            const V3<R> rw = Rd2 * w2 + Rd1 * w1;
+            const V3<R> v12 = alpha * cvt<R>(dv64) - cross(rw, n);
+            const V3<R> vs = v12 - dot(n, v12) * n;
+            const V3<R> dfs = ((v3<R>((R)0, (R)0, (R)0) - inc1) - inc2) - (ks * dtr) * vs;
+            V3<double> fs64 = fs_old64 + cvt<double>(dfs);
+
+            // ---- Law2_ScGeom_FrictPhys_CundallStrack
+            const R fn_mag = kn * penr;
+            const R fmax = fn_mag * tanphi;
+            const double fs_norm = sqrt(dot(fs64, fs64));
+            if (fs_norm > (double)fmax) {
+                part.plast += (fs_norm - (double)fmax) * (double)fmax / (double)ks;
+                const double ratio = (double)fmax / fs_norm;
+                fs64 = ratio * fs64;
+            }
+            part.el += 0.5 * ((double)fn_mag * (double)fn_mag / (double)kn) + 0.5 * (dot(fs64, fs64) / (double)ks);
+            const V3<R> F = fn_mag * n + cvt<R>(fs64);
+            const V3<R> tau = cross(n, F);
+
+            P.fsx[k] = fs64.x;
+            P.fsy[k] = fs64.y;
+            P.fsz[k] = fs64.z;
+            P.nx[k] = (double)n.x;
+            P.ny[k] = (double)n.y;
+            P.nz[k] = (double)n.z;
+            if (PREC == DEM_FP32_MIXED) {
+                P.fxf[k] = (float)F.x;
+                P.fyf[k] = (float)F.y;
+                P.fzf[k] = (float)F.z;
+                P.txf[k] = (float)tau.x;
+                P.tyf[k] = (float)tau.y;
+                P.tzf[k] = (float)tau.z;
+            } else {
+                P.fx[k] = (double)F.x;
+                P.fy[k] = (double)F.y;
+                P.fz[k] = (double)F.z;
+                P.tx[k] = (double)tau.x;
+                P.ty[k] = (double)tau.y;
+                P.tz[k] = (double)tau.z;
+            }
+            if (wall)
+                part.sw = 1;
+            else
+                part.ss = 1;
+            unstable = pen > (wall ? r2 : (r1 < r2 ? r1 : r2));
+        }
+    }
+
+    // ---- block sums: integer counts by atomics (exact), energies by a
+    // fixed-order two-level sum (per-block partial, then the last block)
+    __shared__ double s_el[kMaxBlock / 64], s_pl[kMaxBlock / 64];
+    __shared__ unsigned long long s_ss[kMaxBlock / 64], s_sw[kMaxBlock / 64];
+    __shared__ int s_last;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    for (int off = 32; off > 0; off >>= 1) {
+        part.el += __shfl_down(part.el, off, 64);
+        part.plast += __shfl_down(part.plast, off, 64);
+        part.ss += __shfl_down(part.ss, off, 64);
+        part.sw += __shfl_down(part.sw, off, 64);
+    }
+    if (__any(unstable) && lane == 0) a.ctr->unstable = 1;
+    if (lane == 0) {
+        s_el[wave] = part.el;
+        s_pl[wave] = part.plast;
+        s_ss[wave] = part.ss;
+        s_sw[wave] = part.sw;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double el = 0.0, pl = 0.0;
+        unsigned long long ss = 0, sw = 0;
+        for (int w = 0; w < nwaves; ++w) {
+            el += s_el[w];
+            pl += s_pl[w];
+            ss += s_ss[w];
+            sw += s_sw[w];
+        }
+        if (ss) atomicAdd(&a.ctr->cur_ss, ss);
+        if (sw) atomicAdd(&a.ctr->cur_sw, sw);
+        s_last = 0;
+        if (a.track_energy) {
+            BlockPartial bp;
+            bp.e[0] = el;
+            bp.e[1] = pl;
+            bp.e[2] = 0.0;
+            bp.e[3] = 0.0;
+            a.part_contact[blockIdx.x] = bp;
+            __threadfence();
+            const unsigned prev = atomicAdd(&a.ctr->blocks_done_contact, 1u);
+            s_last = prev == gridDim.x - 1;
+        }
+    }
+    __syncthreads();
+    if (s_last) {
+        __threadfence();
+        // fixed assignment of partials to threads, then fixed-order wave and
+        // block combination: the result does not depend on block timing
+        double el = 0.0, pl = 0.0;
+        for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
+            el += a.part_contact[b].e[0];
+            pl += a.part_contact[b].e[1];
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            el += __shfl_down(el, off, 64);
+            pl += __shfl_down(pl, off, 64);
+        }
+        __syncthreads();
+        if (lane == 0) {
+            s_el[wave] = el;
+            s_pl[wave] = pl;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            el = 0.0;
+            pl = 0.0;
+            for (int w = 0; w < nwaves; ++w) {
+                el += s_el[w];
+                pl += s_pl[w];
+            }
+            a.ctr->e_el = el;
+            a.ctr->e_plast += pl;
+            a.ctr->blocks_done_contact = 0u;
+        }
+    }
+}
+
+template <int PREC, bool BATCHED, bool PERIODIC>
+void launch_t(const StepArgs* args, int grid, int block, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_contact<PREC, BATCHED, PERIODIC>), dim3(grid > 0 ? grid : 1), dim3(block), 0, st, args);
+}
+
+}  // namespace
+
+void launch_contact(const StepArgs* args, int grid, int precision, bool batched, bool periodic, int block,
+                    hipStream_t st)
+{
+    if (precision == DEM_FP32_MIXED) {
+        if (batched) launch_t<DEM_FP32_MIXED, true, false>(args, grid, block, st);
+        else if (periodic) launch_t<DEM_FP32_MIXED, false, true>(args, grid, block, st);
+        else launch_t<DEM_FP32_MIXED, false, false>(args, grid, block, st);
+    } else {
+        if (batched) launch_t<DEM_FP64, true, false>(args, grid, block, st);
+        else if (periodic) launch_t<DEM_FP64, false, true>(args, grid, block, st);
+        else launch_t<DEM_FP64, false, false>(args, grid, block, st);
+    }
+}
+
+}  // namespace dem

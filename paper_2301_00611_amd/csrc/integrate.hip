@@ -1,0 +1,366 @@
+// integrate.hip -- ForceContainer sum + NewtonIntegrator (section 2.1.5).
+//
+// One thread per body: the body adds the forces of its candidate pairs one by
+// one, in ascending partner id (its row order), so the sum is deterministic
+// and needs no atomics; then gravity (damped like any force, dampGravity),
+// Cundall damping eq. 2.9 per component with the on-step velocity estimate
+// v + a dt/2, the leapfrog update, the spherical rotation and, in a periodic
+// cell, the homoDeform velocity terms (class Cell).  Energies use the
+// mid-step velocities v-, w-.  The last block to finish closes the step:
+// energy totals (fixed-order sum of the block partials), the Verlet budget
+// (eq. 2.3-2.4: a broad-phase run is requested once some body may have moved
+// Delta L since the last one), step counters and the periodic cell update
+// F+ = (I + L dt) F.
+#include "dem_internal.hpp"
+
+namespace dem {
+
+namespace {
+
+constexpr int kMaxBlock = 1024;
+
+__device__ inline int logical_block(int nb)
+{
+    const int b = blockIdx.x;
+    const int xcd = b & 7, idx = b >> 3;
+    const int q = nb >> 3, r = nb & 7;
+    return xcd * q + (xcd < r ? xcd : r) + idx;
+}
+
+__device__ inline double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
+
+// Resultant contact force and torque on slot i, in row order.
+template <int PREC>
+__device__ inline void body_sum(const StepArgs& a, int i, double r, double* F, double* T)
+{
+    F[0] = F[1] = F[2] = 0.0;
+    T[0] = T[1] = T[2] = 0.0;
+    const int beg = a.rows.start[i], end = a.rows.start[i + 1];
+    for (int e = beg; e < end; ++e) {
+        const uint32_t u = a.rows.ent[e];
+        const uint32_t k = u & kPairMask;
+        if (k >= (uint32_t)a.npairs) continue;
+        double f0, f1, f2, t0, t1, t2;
+        if (PREC == DEM_FP32_MIXED) {
+            f0 = a.pr.fxf[k];
+            f1 = a.pr.fyf[k];
+            f2 = a.pr.fzf[k];
+            t0 = a.pr.txf[k];
+            t1 = a.pr.tyf[k];
+            t2 = a.pr.tzf[k];
+        } else {
+            f0 = a.pr.fx[k];
+            f1 = a.pr.fy[k];
+            f2 = a.pr.fz[k];
+            t0 = a.pr.tx[k];
+            t1 = a.pr.ty[k];
+            t2 = a.pr.tz[k];
+        }
+        if (u & kNegSign) {
+            F[0] += -f0;
+            F[1] += -f1;
+            F[2] += -f2;
+        } else {
+            F[0] += f0;
+            F[1] += f1;
+            F[2] += f2;
+        }
+        // both bodies of a pair feel -r_k (n x F) (lever arms r1 n and -r2 n)
+        T[0] += -r * t0;
+        T[1] += -r * t1;
+        T[2] += -r * t2;
+    }
+}
+
+__device__ inline void matvec(const double* M, double x, double y, double z, double* o)
+{
+    o[0] = (M[0] * x + M[1] * y) + M[2] * z;
+    o[1] = (M[3] * x + M[4] * y) + M[5] * z;
+    o[2] = (M[6] * x + M[7] * y) + M[8] * z;
+}
+
+struct IntPartial {
+    double kin, rot, grav, damp;
+};
+
+template <int PREC, bool BATCHED, bool PERIODIC>
+__global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restrict__ args)
+{
+    const StepArgs& a = *args;
+    if (a.ctr->stall) return;
+    const int i = logical_block(gridDim.x) * blockDim.x + threadIdx.x;
+    IntPartial part = {0.0, 0.0, 0.0, 0.0};
+    double vmax = 0.0;
+    bool bad = false;
+    if (i < a.nslots) {
+        const Bodies& B = a.bod;
+        const int s = BATCHED ? (int)B.scene[i] : 0;
+        const SceneParams& S = (BATCHED || PERIODIC) ? a.scenes[s] : a.scene0;
+        const double dt = S.dt;
+        const double lam = S.damping;
+        const double r = B.rad[i], m = B.mass[i];
+        const double I = 2.0 * m * r * r / 5.0;
+        const unsigned blocked = B.blocked[i];
+        double F[3], T[3];
+        body_sum<PREC>(a, i, r, F, T);
+
+        const double x0[3] = {B.x[i], B.y[i], B.z[i]};
+        const double v0[3] = {B.vx[i], B.vy[i], B.vz[i]};
+        double w[3] = {B.wx[i], B.wy[i], B.wz[i]};
+        double f[3], t[3];
+        for (int k = 0; k < 3; ++k) {
+            f[k] = F[k] + m * S.gravity[k];
+            t[k] = T[k];
+        }
+        part.kin = 0.5 * m * ((v0[0] * v0[0] + v0[1] * v0[1]) + v0[2] * v0[2]);
+        part.rot = 0.5 * I * ((w[0] * w[0] + w[1] * w[1]) + w[2] * w[2]);
+
+        double homo[3] = {0.0, 0.0, 0.0};
+        if (PERIODIC && S.homo_deform > 0) {
+            double dL[9], a1[3], a2[3];
+            for (int k = 0; k < 9; ++k) dL[k] = S.L[k] - S.Lprev[k];
+            matvec(dL, x0[0], x0[1], x0[2], a1);
+            matvec(S.L, v0[0], v0[1], v0[2], a2);
+            for (int k = 0; k < 3; ++k) homo[k] = a1[k] + (S.homo_deform == 2 ? a2[k] * dt : 0.0);
+        }
+        double v[3];
+        for (int k = 0; k < 3; ++k) {
+            if (blocked & (1u << k)) {
+                v[k] = v0[k];
+                continue;
+            }
+            part.grav += -m * S.gravity[k] * v0[k] * dt;
+            if (lam > 0.0) {
+                const double acc = f[k] / m;
+                const double df = -lam * sgn(f[k] * (v0[k] + acc * dt / 2.0)) * f[k];
+                part.damp += -df * v0[k] * dt;
+                f[k] += df;
+            }
+            v[k] = v0[k] + f[k] / m * dt + homo[k];
+        }
+        const double x1[3] = {x0[0] + v[0] * dt, x0[1] + v[1] * dt, x0[2] + v[2] * dt};
+
+        for (int k = 0; k < 3; ++k) {
+            if (blocked & (8u << k)) continue;
+            if (lam > 0.0 && S.damp_rot) {
+                const double acc = t[k] / I;
+                t[k] += -lam * sgn(t[k] * (w[k] + acc * dt / 2.0)) * t[k];
+            }
+            w[k] = w[k] + t[k] / I * dt;
+        }
+        double q[4] = {B.qw[i], B.qx[i], B.qy[i], B.qz[i]};
+        const double wn = sqrt((w[0] * w[0] + w[1] * w[1]) + w[2] * w[2]);
+        if (wn > 0.0) {
+            const double half = 0.5 * wn * dt;
+            const double sh = sin(half) / wn;
+            const double d0 = cos(half), d1 = w[0] * sh, d2 = w[1] * sh, d3 = w[2] * sh;
+            const double n0 = d0 * q[0] - d1 * q[1] - d2 * q[2] - d3 * q[3];
+            const double n1 = d0 * q[1] + d1 * q[0] + d2 * q[3] - d3 * q[2];
+            const double n2 = d0 * q[2] - d1 * q[3] + d2 * q[0] + d3 * q[1];
+            const double n3 = d0 * q[3] + d1 * q[2] - d2 * q[1] + d3 * q[0];
+            const double qn = sqrt(n0 * n0 + n1 * n1 + n2 * n2 + n3 * n3);
+            q[0] = n0 / qn;
+            q[1] = n1 / qn;
+            q[2] = n2 / qn;
+            q[3] = n3 / qn;
+            B.qw[i] = q[0];
+            B.qx[i] = q[1];
+            B.qy[i] = q[2];
+            B.qz[i] = q[3];
+        }
+        B.x[i] = x1[0];
+        B.y[i] = x1[1];
+        B.z[i] = x1[2];
+        B.vx[i] = v[0];
+        B.vy[i] = v[1];
+        B.vz[i] = v[2];
+        B.wx[i] = w[0];
+        B.wy[i] = w[1];
+        B.wz[i] = w[2];
+
+        // non-affine displacement of this step, for the Verlet budget
+        double u[3] = {v[0], v[1], v[2]};
+        if (PERIODIC) {
+            double Lx[3];
+            matvec(S.L, x0[0], x0[1], x0[2], Lx);
+            for (int k = 0; k < 3; ++k) u[k] -= Lx[k];
+        }
+        vmax = sqrt((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]) * dt;
+        bad = !(isfinite(x1[0]) && isfinite(x1[1]) && isfinite(x1[2]) && isfinite(v[0]) && isfinite(v[1]) &&
+                isfinite(v[2]));
+        if (bad) vmax = 0.0;
+    }
+
+    // ---- block reduction
+    __shared__ IntPartial s_p[kMaxBlock / 64];
+    __shared__ double s_v[kMaxBlock / 64];
+    __shared__ int s_last;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    for (int off = 32; off > 0; off >>= 1) {
+        part.kin += __shfl_down(part.kin, off, 64);
+        part.rot += __shfl_down(part.rot, off, 64);
+        part.grav += __shfl_down(part.grav, off, 64);
+        part.damp += __shfl_down(part.damp, off, 64);
+        const double o = __shfl_down(vmax, off, 64);
+        vmax = o > vmax ? o : vmax;
+    }
+    if (__any(bad) && lane == 0) a.ctr->nonfinite = 1;
+    if (lane == 0) {
+        s_p[wave] = part;
+        s_v[wave] = vmax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        IntPartial p = {0.0, 0.0, 0.0, 0.0};
+        double vm = 0.0;
+        for (int w = 0; w < nwaves; ++w) {
+            p.kin += s_p[w].kin;
+            p.rot += s_p[w].rot;
+            p.grav += s_p[w].grav;
+            p.damp += s_p[w].damp;
+            vm = s_v[w] > vm ? s_v[w] : vm;
+        }
+        // max of non-negative doubles: their bit patterns order the same way
+        atomicMax(&a.ctr->vmax_bits, (unsigned long long)__double_as_longlong(vm));
+        BlockPartial bp;
+        bp.e[0] = p.kin;
+        bp.e[1] = p.rot;
+        bp.e[2] = p.grav;
+        bp.e[3] = p.damp;
+        a.part_integrate[blockIdx.x] = bp;
+        __threadfence();
+        const unsigned prev = atomicAdd(&a.ctr->blocks_done_integrate, 1u);
+        s_last = prev == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+
+    // ---- last block: close the step
+    __threadfence();
+    IntPartial p = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
+        const BlockPartial bp = a.part_integrate[b];
+        p.kin += bp.e[0];
+        p.rot += bp.e[1];
+        p.grav += bp.e[2];
+        p.damp += bp.e[3];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        p.kin += __shfl_down(p.kin, off, 64);
+        p.rot += __shfl_down(p.rot, off, 64);
+        p.grav += __shfl_down(p.grav, off, 64);
+        p.damp += __shfl_down(p.damp, off, 64);
+    }
+    __syncthreads();
+    if (lane == 0) s_p[wave] = p;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    IntPartial tot = {0.0, 0.0, 0.0, 0.0};
+    for (int w = 0; w < nwaves; ++w) {
+        tot.kin += s_p[w].kin;
+        tot.rot += s_p[w].rot;
+        tot.grav += s_p[w].grav;
+        tot.damp += s_p[w].damp;
+    }
+    Counters* c = a.ctr;
+    if (a.track_energy) {
+        c->e_kin = tot.kin;
+        c->e_rot = tot.rot;
+        c->e_grav += tot.grav;
+        c->e_damp += tot.damp;
+    }
+    const double vstep = __longlong_as_double((long long)c->vmax_bits);
+    c->vmax_bits = 0ull;
+    c->verlet_acc += vstep + c->verlet_cell_step;
+    if (c->verlet_acc > c->verlet_limit) c->stall = 1;
+    c->steps_done += 1;
+    c->last_ss = c->cur_ss;
+    c->last_sw = c->cur_sw;
+    c->contact_steps += c->cur_ss + c->cur_sw;
+    c->cur_ss = 0ull;
+    c->cur_sw = 0ull;
+    c->blocks_done_integrate = 0u;
+
+    if (PERIODIC) {
+        // Cell: H+ = (I + L dt) H, trsf likewise; keep H - H_prev for the
+        // image velocity of the next step; L becomes L_prev
+        SceneParams* S = &a.scenes[0];
+        const double dt = S->dt;
+        double M[9], Hn[9], Tn[9];
+        for (int k = 0; k < 9; ++k) M[k] = ((k % 4 == 0) ? 1.0 : 0.0) + S->L[k] * dt;
+        for (int r = 0; r < 3; ++r)
+            for (int q = 0; q < 3; ++q) {
+                Hn[3 * r + q] = (M[3 * r + 0] * S->H[q] + M[3 * r + 1] * S->H[3 + q]) + M[3 * r + 2] * S->H[6 + q];
+                Tn[3 * r + q] =
+                    (M[3 * r + 0] * S->trsf[q] + M[3 * r + 1] * S->trsf[3 + q]) + M[3 * r + 2] * S->trsf[6 + q];
+            }
+        for (int k = 0; k < 9; ++k) {
+            S->dH[k] = Hn[k] - S->H[k];
+            S->H[k] = Hn[k];
+            S->trsf[k] = Tn[k];
+            S->Lprev[k] = S->L[k];
+        }
+        const double* A = S->H;
+        const double a0 = A[0], a1 = A[1], a2 = A[2], a3 = A[3], a4 = A[4], a5 = A[5], a6 = A[6], a7 = A[7],
+                     a8 = A[8];
+        const double C0 = a4 * a8 - a5 * a7, C1 = -(a3 * a8 - a5 * a6), C2 = a3 * a7 - a4 * a6;
+        const double det = a0 * C0 + a1 * C1 + a2 * C2;
+        S->Hinv[0] = C0 / det;
+        S->Hinv[1] = -(a1 * a8 - a2 * a7) / det;
+        S->Hinv[2] = (a1 * a5 - a2 * a4) / det;
+        S->Hinv[3] = C1 / det;
+        S->Hinv[4] = (a0 * a8 - a2 * a6) / det;
+        S->Hinv[5] = -(a0 * a5 - a2 * a3) / det;
+        S->Hinv[6] = C2 / det;
+        S->Hinv[7] = -(a0 * a7 - a1 * a6) / det;
+        S->Hinv[8] = (a0 * a4 - a1 * a3) / det;
+    }
+}
+
+// Resultant force/torque per slot (for reporting), same sum as the step.
+template <int PREC>
+__global__ void k_body_forces(StepArgs a, double* __restrict__ f3, double* __restrict__ t3)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.nslots) return;
+    double F[3], T[3];
+    body_sum<PREC>(a, i, a.bod.rad[i], F, T);
+    for (int k = 0; k < 3; ++k) {
+        f3[3 * i + k] = F[k];
+        t3[3 * i + k] = T[k];
+    }
+}
+
+template <int PREC, bool BATCHED, bool PERIODIC>
+void launch_t(const StepArgs* args, int grid, int block, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_integrate<PREC, BATCHED, PERIODIC>), dim3(grid > 0 ? grid : 1), dim3(block), 0, st, args);
+}
+
+}  // namespace
+
+void launch_integrate(const StepArgs* args, int grid, int precision, bool batched, bool periodic, int block,
+                      hipStream_t st)
+{
+    if (precision == DEM_FP32_MIXED) {
+        if (batched) launch_t<DEM_FP32_MIXED, true, false>(args, grid, block, st);
+        else if (periodic) launch_t<DEM_FP32_MIXED, false, true>(args, grid, block, st);
+        else launch_t<DEM_FP32_MIXED, false, false>(args, grid, block, st);
+    } else {
+        if (batched) launch_t<DEM_FP64, true, false>(args, grid, block, st);
+        else if (periodic) launch_t<DEM_FP64, false, true>(args, grid, block, st);
+        else launch_t<DEM_FP64, false, false>(args, grid, block, st);
+    }
+}
+
+void launch_body_forces(const StepArgs& a, int precision, double* f3, double* t3, hipStream_t st)
+{
+    if (a.nslots <= 0) return;
+    const int grid = (a.nslots + 255) / 256;
+    if (precision == DEM_FP32_MIXED)
+        hipLaunchKernelGGL(k_body_forces<DEM_FP32_MIXED>, dim3(grid), dim3(256), 0, st, a, f3, t3);
+    else
+        hipLaunchKernelGGL(k_body_forces<DEM_FP64>, dim3(grid), dim3(256), 0, st, a, f3, t3);
+}
+
+}  // namespace dem

@@ -1,0 +1,1869 @@
+// runtime.cpp -- host side of libdem_hip.so: scene/world management, device
+// buffers, the broad-phase run (host-orchestrated, a few small read-backs),
+// the stepping loop (HIP graphs of `chunk` steps that stop themselves when a
+// broad-phase run is needed), read-back and the extern "C" API of dem.h.
+//
+// A World holds one or more independent scenes in one set of arrays: bodies
+// of all scenes live in one structure-of-arrays arena and are advanced by
+// the same kernels; each body carries its scene index (batched mode only).
+// Internally every body (wall or sphere) of the world has a global index
+// (gid); each scene maps its own ids (0, 1, ... in insertion order) to gids.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "dem_internal.hpp"
+
+namespace dem {
+namespace {
+
+thread_local std::string g_err;
+
+struct Error {
+    dem_status code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(dem_status code, const std::string& msg) { throw Error{code, msg}; }
+
+void hip_check(hipError_t e, const char* what)
+{
+    if (e != hipSuccess) fail(DEM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+#define HIPC(x) ::dem::hip_check((x), #x)
+
+// Growable device allocation.
+struct DBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    void ensure(size_t need)
+    {
+        if (need <= bytes && p) return;
+        size_t nb = std::max<size_t>(need + need / 2, 256);
+        void* q = nullptr;
+        if (hipMalloc(&q, nb) != hipSuccess) fail(DEM_ENOMEM, "device allocation of " + std::to_string(nb) + " bytes failed");
+        if (p) (void)hipFree(p);
+        p = q;
+        bytes = nb;
+    }
+    // grow keeping the first `keep` bytes
+    void ensure_keep(size_t need, size_t keep, hipStream_t st)
+    {
+        if (need <= bytes && p) return;
+        size_t nb = std::max<size_t>(need + need / 2, 256);
+        void* q = nullptr;
+        if (hipMalloc(&q, nb) != hipSuccess) fail(DEM_ENOMEM, "device allocation failed");
+        if (p && keep) HIPC(hipMemcpyAsync(q, p, std::min(keep, bytes), hipMemcpyDeviceToDevice, st));
+        if (p) {
+            HIPC(hipStreamSynchronize(st));
+            (void)hipFree(p);
+        }
+        p = q;
+        bytes = nb;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+struct BodySet {
+    DBuf x, y, z, vx, vy, vz, wx, wy, wz, qw, qx, qy, qz, rad, mass, mat, blocked, id, scene, period;
+    void ensure(size_t n)
+    {
+        for (DBuf* b : {&x, &y, &z, &vx, &vy, &vz, &wx, &wy, &wz, &qw, &qx, &qy, &qz, &rad, &mass}) b->ensure(n * 8);
+        mat.ensure(n);
+        blocked.ensure(n);
+        id.ensure(n * 4);
+        scene.ensure(n * 2);
+        period.ensure(n * 4);
+    }
+    Bodies view() const
+    {
+        Bodies b;
+        b.x = x.as<double>();
+        b.y = y.as<double>();
+        b.z = z.as<double>();
+        b.vx = vx.as<double>();
+        b.vy = vy.as<double>();
+        b.vz = vz.as<double>();
+        b.wx = wx.as<double>();
+        b.wy = wy.as<double>();
+        b.wz = wz.as<double>();
+        b.qw = qw.as<double>();
+        b.qx = qx.as<double>();
+        b.qy = qy.as<double>();
+        b.qz = qz.as<double>();
+        b.rad = rad.as<double>();
+        b.mass = mass.as<double>();
+        b.mat = mat.as<uint8_t>();
+        b.blocked = blocked.as<uint8_t>();
+        b.id = id.as<int32_t>();
+        b.scene = scene.as<uint16_t>();
+        b.period = period.as<int32_t>();
+        return b;
+    }
+    void release()
+    {
+        for (DBuf* b : {&x, &y, &z, &vx, &vy, &vz, &wx, &wy, &wz, &qw, &qx, &qy, &qz, &rad, &mass, &mat, &blocked, &id,
+                        &scene, &period})
+            b->release();
+    }
+};
+
+struct PairSet {
+    DBuf a, b, cell, pid, fsx, fsy, fsz, nx, ny, nz, fx, fy, fz, tx, ty, tz, fxf, fyf, fzf, txf, tyf, tzf;
+    DBuf own_begin, own_count;  // by gid
+    size_t cap = 0;
+    void ensure(size_t n, bool fp32)
+    {
+        n = std::max<size_t>(n, 1);
+        for (DBuf* d : {&a, &b, &cell, &pid}) d->ensure(n * 4);
+        for (DBuf* d : {&fsx, &fsy, &fsz, &nx, &ny, &nz}) d->ensure(n * 8);
+        if (fp32) {
+            for (DBuf* d : {&fxf, &fyf, &fzf, &txf, &tyf, &tzf}) d->ensure(n * 4);
+        } else {
+            for (DBuf* d : {&fx, &fy, &fz, &tx, &ty, &tz}) d->ensure(n * 8);
+        }
+        cap = n;
+    }
+    Pairs view() const
+    {
+        Pairs p;
+        p.a = a.as<int32_t>();
+        p.b = b.as<int32_t>();
+        p.cell = cell.as<int32_t>();
+        p.pid = pid.as<int32_t>();
+        p.fsx = fsx.as<double>();
+        p.fsy = fsy.as<double>();
+        p.fsz = fsz.as<double>();
+        p.nx = nx.as<double>();
+        p.ny = ny.as<double>();
+        p.nz = nz.as<double>();
+        p.fx = fx.as<double>();
+        p.fy = fy.as<double>();
+        p.fz = fz.as<double>();
+        p.tx = tx.as<double>();
+        p.ty = ty.as<double>();
+        p.tz = tz.as<double>();
+        p.fxf = fxf.as<float>();
+        p.fyf = fyf.as<float>();
+        p.fzf = fzf.as<float>();
+        p.txf = txf.as<float>();
+        p.tyf = tyf.as<float>();
+        p.tzf = tzf.as<float>();
+        return p;
+    }
+    History history() const
+    {
+        History h;
+        h.own_begin = own_begin.as<int32_t>();
+        h.own_count = own_count.as<int32_t>();
+        h.pid = pid.as<int32_t>();
+        h.cell = cell.as<int32_t>();
+        h.fsx = fsx.as<double>();
+        h.fsy = fsy.as<double>();
+        h.fsz = fsz.as<double>();
+        h.nx = nx.as<double>();
+        h.ny = ny.as<double>();
+        h.nz = nz.as<double>();
+        return h;
+    }
+    void release()
+    {
+        for (DBuf* d : {&a, &b, &cell, &pid, &fsx, &fsy, &fsz, &nx, &ny, &nz, &fx, &fy, &fz, &tx, &ty, &tz, &fxf, &fyf,
+                        &fzf, &txf, &tyf, &tzf, &own_begin, &own_count})
+            d->release();
+        cap = 0;
+    }
+};
+
+struct HostMaterial {
+    double density, young, poisson, friction;
+};
+
+struct HostScene {
+    dem_params p;
+    std::vector<int32_t> gids;  // local id -> gid
+    int64_t n_spheres = 0, n_walls = 0;
+    int64_t iter = 0;
+    double time = 0.0;
+    double verlet = 0.0;        // Delta L in use
+};
+
+// Host copy of everything per gid (kept in step only when bodies are added
+// or the state is overwritten; the device holds the truth while stepping).
+struct HostBody {
+    int kind;  // 0 sphere, 1 wall
+    int scene;
+    int wall;  // wall index when kind == 1
+    double x[3], v[3], w[3], q[4];
+    double r, m;
+    int mat;
+    uint8_t blocked;
+};
+
+struct KernelTimer {
+    double total_ms = 0.0;
+    int64_t launches = 0;
+};
+
+struct World {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int precision = DEM_FP64;
+    bool periodic = false;
+    bool track_energy = false;
+    std::vector<HostScene> scenes;
+    std::vector<HostMaterial> mats;
+    std::vector<Wall> walls;           // global wall table (ordered by scene)
+    std::vector<int> wall_scene;
+    std::vector<HostBody> bodies;      // by gid (authoritative only while host_dirty)
+    bool host_dirty = false;           // bodies added / state set: upload before stepping
+    bool on_device = false;            // device arrays hold the current state
+    bool need_rebuild = true;
+    bool contacts_valid = false;
+
+    // device
+    BodySet bs[2];
+    int active = 0;
+    PairSet ps[2];
+    int pactive = 0;
+    int npairs = 0;
+    int nslots = 0;
+    int ngids_dev = 0;                 // number of gids the device arrays were built for
+    int old_ngids = 0;                 // gids covered by the active own arrays
+    DBuf slot_of_id, keys, vals, keys_alt, vals_alt, cell_start, cell_end, counts, row_start;
+    DBuf ent_slot, ent_pid, ent_cell, ent_own, own_scan, rows_ent, scan_tmp, radix_tmp;
+    DBuf d_scenes, d_walls, d_mats, d_tanphi, d_ctr, d_part_c, d_part_i, d_bounds, d_total, d_tmp3, d_args;
+    int grid_c = 1, grid_i = 1;        // step-kernel grids (contact sized with headroom)
+    std::vector<SceneParams> sp;       // host copy of the scene table
+    Counters* h_ctr = nullptr;         // pinned
+    int ncells = 0;
+    int morton_bits = 1, scene_bits = 0;
+    int64_t rebuilds = 0;
+    int64_t n_candidates = 0;
+    int block_contact = 256, block_integrate = 256;
+    int chunk = 32;
+    bool use_graph = true;
+
+    // graphs
+    struct GraphEntry {
+        hipGraphExec_t exec = nullptr;
+        std::vector<hipEvent_t> ev;
+    };
+    std::map<std::string, GraphEntry> graphs;
+
+    // timing
+    bool timing = false;
+    std::map<std::string, KernelTimer> timers;
+
+    ~World() { release(); }
+    void release()
+    {
+        for (auto& kv : graphs) {
+            if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+            for (auto e : kv.second.ev) (void)hipEventDestroy(e);
+        }
+        graphs.clear();
+        for (auto& b : bs) b.release();
+        for (auto& p : ps) p.release();
+        for (DBuf* d : {&slot_of_id, &keys, &vals, &keys_alt, &vals_alt, &cell_start, &cell_end, &counts, &row_start,
+                        &ent_slot, &ent_pid, &ent_cell, &ent_own, &own_scan, &rows_ent, &scan_tmp, &radix_tmp,
+                        &d_scenes, &d_walls, &d_mats, &d_tanphi, &d_ctr, &d_part_c, &d_part_i, &d_bounds, &d_total,
+                        &d_tmp3, &d_args})
+            d->release();
+        if (h_ctr) (void)hipHostFree(h_ctr);
+        h_ctr = nullptr;
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+        stream = nullptr;
+    }
+
+    bool batched() const { return scenes.size() > 1; }
+
+    void invalidate_graphs()
+    {
+        for (auto& kv : graphs) {
+            if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+            for (auto e : kv.second.ev) (void)hipEventDestroy(e);
+        }
+        graphs.clear();
+    }
+
+    // ------------------------------------------------------------ setup
+    void init(int nsc, const dem_params* p)
+    {
+        device = p[0].device;
+        HIPC(hipSetDevice(device));
+        if (p[0].stream) {
+            stream = static_cast<hipStream_t>(p[0].stream);
+        } else {
+            HIPC(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+            own_stream = true;
+        }
+        precision = p[0].precision;
+        periodic = p[0].periodic != 0;
+        track_energy = p[0].track_energy != 0;
+        scenes.resize(nsc);
+        for (int i = 0; i < nsc; ++i) scenes[i].p = p[i];
+        HIPC(hipHostMalloc(reinterpret_cast<void**>(&h_ctr), sizeof(Counters), hipHostMallocDefault));
+        std::memset(h_ctr, 0, sizeof(Counters));
+        d_ctr.ensure(sizeof(Counters));
+        HIPC(hipMemsetAsync(d_ctr.p, 0, sizeof(Counters), stream));
+        sp.resize(nsc);
+        for (int i = 0; i < nsc; ++i) {
+            SceneParams& s = sp[i];
+            std::memset(&s, 0, sizeof s);
+            const dem_params& q = p[i];
+            s.dt = q.dt;
+            for (int k = 0; k < 3; ++k) s.gravity[k] = q.gravity[k];
+            s.damping = q.damping;
+            s.damp_rot = q.damp_rot;
+            s.homo_deform = q.homo_deform;
+            s.periodic = q.periodic;
+            for (int k = 0; k < 9; ++k) {
+                s.H[k] = q.periodic ? q.hsize[k] : (k % 4 == 0 ? 1.0 : 0.0);
+                s.L[k] = q.periodic ? q.velgrad[k] : 0.0;
+                s.trsf[k] = (k % 4 == 0 ? 1.0 : 0.0);
+            }
+            if (q.periodic) invert(s.H, s.Hinv);
+        }
+        d_scenes.ensure(sizeof(SceneParams) * nsc);
+        HIPC(hipMemcpyAsync(d_scenes.p, sp.data(), sizeof(SceneParams) * nsc, hipMemcpyHostToDevice, stream));
+        HIPC(hipStreamSynchronize(stream));
+        if (const char* c = std::getenv("DEM_CHUNK")) chunk = std::max(1, std::atoi(c));
+        if (const char* g = std::getenv("DEM_NO_GRAPH")) use_graph = std::atoi(g) == 0;
+    }
+
+    static bool invert(const double* M, double* out)
+    {
+        const double a = M[0], b = M[1], c = M[2], d = M[3], e = M[4], f = M[5], g = M[6], h = M[7], i = M[8];
+        const double A = e * i - f * h, B = -(d * i - f * g), C = d * h - e * g;
+        const double det = a * A + b * B + c * C;
+        if (!(std::fabs(det) > 0.0)) return false;
+        out[0] = A / det;
+        out[1] = -(b * i - c * h) / det;
+        out[2] = (b * f - c * e) / det;
+        out[3] = B / det;
+        out[4] = (a * i - c * g) / det;
+        out[5] = -(a * f - c * d) / det;
+        out[6] = C / det;
+        out[7] = -(a * h - b * g) / det;
+        out[8] = (a * e - b * d) / det;
+        return true;
+    }
+
+    int add_material(double density, double young, double poisson, double friction)
+    {
+        if (!(density > 0.0) || !(young > 0.0) || !(poisson > -1.0 && poisson <= 0.5) ||
+            !(friction >= 0.0 && friction < 1.5707963267948966))
+            fail(DEM_EINVAL, "dem_add_material: need density > 0, young > 0, -1 < poisson <= 0.5, 0 <= friction < pi/2");
+        if (mats.size() >= 255) fail(DEM_EINVAL, "dem_add_material: at most 255 materials");
+        mats.push_back({density, young, poisson, friction});
+        upload_materials();
+        return (int)mats.size() - 1;
+    }
+
+    void upload_materials()
+    {
+        const int n = (int)mats.size();
+        std::vector<Material> m(n);
+        std::vector<double> tp((size_t)n * n);
+        for (int i = 0; i < n; ++i) {
+            m[i].young = mats[i].young;
+            m[i].young_poisson = mats[i].young * mats[i].poisson;
+            m[i].density = mats[i].density;
+            for (int j = 0; j < n; ++j)
+                tp[(size_t)i * n + j] = std::tan(mats[i].friction < mats[j].friction ? mats[i].friction : mats[j].friction);
+        }
+        d_mats.ensure(sizeof(Material) * std::max(n, 1));
+        d_tanphi.ensure(sizeof(double) * std::max(n * n, 1));
+        HIPC(hipMemcpyAsync(d_mats.p, m.data(), sizeof(Material) * n, hipMemcpyHostToDevice, stream));
+        HIPC(hipMemcpyAsync(d_tanphi.p, tp.data(), sizeof(double) * n * n, hipMemcpyHostToDevice, stream));
+        HIPC(hipStreamSynchronize(stream));
+        if (d_args.p) upload_args();
+    }
+
+    // Bring the host copy up to date with the device (before adding bodies).
+    void pull_bodies()
+    {
+        if (!on_device || host_dirty) return;
+        std::vector<double> buf((size_t)nslots);
+        std::vector<int32_t> ids((size_t)nslots);
+        const BodySet& B = bs[active];
+        HIPC(hipMemcpyAsync(ids.data(), B.id.p, 4 * (size_t)nslots, hipMemcpyDeviceToHost, stream));
+        HIPC(hipStreamSynchronize(stream));
+        auto pull = [&](const DBuf& d, auto setter) {
+            HIPC(hipMemcpyAsync(buf.data(), d.p, 8 * (size_t)nslots, hipMemcpyDeviceToHost, stream));
+            HIPC(hipStreamSynchronize(stream));
+            for (int i = 0; i < nslots; ++i) setter(bodies[ids[i]], buf[i]);
+        };
+        pull(B.x, [](HostBody& b, double v) { b.x[0] = v; });
+        pull(B.y, [](HostBody& b, double v) { b.x[1] = v; });
+        pull(B.z, [](HostBody& b, double v) { b.x[2] = v; });
+        pull(B.vx, [](HostBody& b, double v) { b.v[0] = v; });
+        pull(B.vy, [](HostBody& b, double v) { b.v[1] = v; });
+        pull(B.vz, [](HostBody& b, double v) { b.v[2] = v; });
+        pull(B.wx, [](HostBody& b, double v) { b.w[0] = v; });
+        pull(B.wy, [](HostBody& b, double v) { b.w[1] = v; });
+        pull(B.wz, [](HostBody& b, double v) { b.w[2] = v; });
+        pull(B.qw, [](HostBody& b, double v) { b.q[0] = v; });
+        pull(B.qx, [](HostBody& b, double v) { b.q[1] = v; });
+        pull(B.qy, [](HostBody& b, double v) { b.q[2] = v; });
+        pull(B.qz, [](HostBody& b, double v) { b.q[3] = v; });
+    }
+
+    int64_t add_spheres(int s, int64_t n, const double* pos3, const double* radius, const double* vel3,
+                        const double* angvel3, const int32_t* mat, int32_t default_mat, const uint8_t* blocked)
+    {
+        if (n < 0 || (n > 0 && (!pos3 || !radius))) fail(DEM_EINVAL, "dem_add_spheres: need pos3 and radius");
+        for (int64_t i = 0; i < n; ++i) {
+            const int mi = mat ? mat[i] : default_mat;
+            if (mi < 0 || mi >= (int)mats.size()) fail(DEM_EINVAL, "dem_add_spheres: unknown material");
+            if (!(radius[i] > 0.0) || !std::isfinite(radius[i])) fail(DEM_EINVAL, "dem_add_spheres: radius must be > 0");
+            for (int k = 0; k < 3; ++k)
+                if (!std::isfinite(pos3[3 * i + k])) fail(DEM_EINVAL, "dem_add_spheres: non-finite position");
+        }
+        if ((int64_t)bodies.size() + n > 0x7ffffff0LL) fail(DEM_EINVAL, "dem_add_spheres: too many bodies");
+        pull_bodies();
+        HostScene& S = scenes[s];
+        const int64_t first = (int64_t)S.gids.size();
+        for (int64_t i = 0; i < n; ++i) {
+            HostBody b;
+            std::memset(&b, 0, sizeof b);
+            b.kind = 0;
+            b.scene = s;
+            b.mat = mat ? mat[i] : default_mat;
+            b.r = radius[i];
+            for (int k = 0; k < 3; ++k) {
+                b.x[k] = pos3[3 * i + k];
+                b.v[k] = vel3 ? vel3[3 * i + k] : 0.0;
+                b.w[k] = angvel3 ? angvel3[3 * i + k] : 0.0;
+            }
+            b.q[0] = 1.0;
+            b.blocked = blocked ? (uint8_t)(blocked[i] & 63u) : 0;
+            const double rho = mats[b.mat].density;
+            const double r = b.r;
+            b.m = 4.0 / 3.0 * M_PI * r * r * r * rho;
+            S.gids.push_back((int32_t)bodies.size());
+            bodies.push_back(b);
+        }
+        S.n_spheres += n;
+        host_dirty = true;
+        need_rebuild = true;
+        return first;
+    }
+
+    int64_t add_wall(int s, int axis, double position, int sense, int mat)
+    {
+        if (axis < 0 || axis > 2 || sense < -1 || sense > 1 || !std::isfinite(position))
+            fail(DEM_EINVAL, "dem_add_wall: axis in 0..2, sense in -1..1, finite position");
+        if (mat < 0 || mat >= (int)mats.size()) fail(DEM_EINVAL, "dem_add_wall: unknown material");
+        if (scenes[s].p.periodic) fail(DEM_EINVAL, "dem_add_wall: walls are not supported in a periodic cell");
+        if (scenes[s].n_walls >= kMaxWallsPerScene) fail(DEM_EINVAL, "dem_add_wall: too many walls in one scene");
+        pull_bodies();
+        HostScene& S = scenes[s];
+        HostBody b;
+        std::memset(&b, 0, sizeof b);
+        b.kind = 1;
+        b.scene = s;
+        b.mat = mat;
+        b.q[0] = 1.0;
+        const int32_t gid = (int32_t)bodies.size();
+        Wall w;
+        w.axis = axis;
+        w.sense = sense;
+        w.mat = mat;
+        w.id = gid;
+        w.pos = position;
+        // keep the wall table grouped by scene
+        int at = 0;
+        while (at < (int)walls.size() && wall_scene[at] <= s) ++at;
+        walls.insert(walls.begin() + at, w);
+        wall_scene.insert(wall_scene.begin() + at, s);
+        b.wall = -1;
+        const int64_t local = (int64_t)S.gids.size();
+        S.gids.push_back(gid);
+        bodies.push_back(b);
+        for (int i = 0; i < (int)walls.size(); ++i) bodies[walls[i].id].wall = i;
+        S.n_walls += 1;
+        host_dirty = true;
+        need_rebuild = true;
+        return local;
+    }
+
+    double pwave_dt(int s) const
+    {
+        // radii and materials never change after insertion: the host copy is current for them
+        double best = INFINITY;
+        for (int32_t g : scenes[s].gids) {
+            const HostBody& b = bodies[g];
+            if (b.kind != 0) continue;
+            const HostMaterial& m = mats[b.mat];
+            const double dt = b.r / std::sqrt(m.young / m.density);
+            if (dt < best) best = dt;
+        }
+        return best;
+    }
+
+    // ------------------------------------------------------- uploading
+    void upload_bodies()
+    {
+        // sphere slots in gid order; the first broad-phase run sorts them
+        std::vector<int32_t> sph;
+        for (int32_t g = 0; g < (int32_t)bodies.size(); ++g)
+            if (bodies[g].kind == 0) sph.push_back(g);
+        nslots = (int)sph.size();
+        const size_t n = std::max<size_t>(nslots, 1);
+        for (auto& b : bs) b.ensure(n);
+        BodySet& B = bs[active];
+        std::vector<double> col(n);
+        auto push = [&](DBuf& d, auto get) {
+            for (int i = 0; i < nslots; ++i) col[i] = get(bodies[sph[i]]);
+            HIPC(hipMemcpyAsync(d.p, col.data(), 8 * (size_t)nslots, hipMemcpyHostToDevice, stream));
+            HIPC(hipStreamSynchronize(stream));
+        };
+        push(B.x, [](const HostBody& b) { return b.x[0]; });
+        push(B.y, [](const HostBody& b) { return b.x[1]; });
+        push(B.z, [](const HostBody& b) { return b.x[2]; });
+        push(B.vx, [](const HostBody& b) { return b.v[0]; });
+        push(B.vy, [](const HostBody& b) { return b.v[1]; });
+        push(B.vz, [](const HostBody& b) { return b.v[2]; });
+        push(B.wx, [](const HostBody& b) { return b.w[0]; });
+        push(B.wy, [](const HostBody& b) { return b.w[1]; });
+        push(B.wz, [](const HostBody& b) { return b.w[2]; });
+        push(B.qw, [](const HostBody& b) { return b.q[0]; });
+        push(B.qx, [](const HostBody& b) { return b.q[1]; });
+        push(B.qy, [](const HostBody& b) { return b.q[2]; });
+        push(B.qz, [](const HostBody& b) { return b.q[3]; });
+        push(B.rad, [](const HostBody& b) { return b.r; });
+        push(B.mass, [](const HostBody& b) { return b.m; });
+        std::vector<uint8_t> u8(n);
+        std::vector<int32_t> i32(n);
+        std::vector<uint16_t> u16(n);
+        for (int i = 0; i < nslots; ++i) u8[i] = (uint8_t)bodies[sph[i]].mat;
+        HIPC(hipMemcpyAsync(B.mat.p, u8.data(), (size_t)nslots, hipMemcpyHostToDevice, stream));
+        HIPC(hipStreamSynchronize(stream));
+        for (int i = 0; i < nslots; ++i) u8[i] = bodies[sph[i]].blocked;
+        HIPC(hipMemcpyAsync(B.blocked.p, u8.data(), (size_t)nslots, hipMemcpyHostToDevice, stream));
+        HIPC(hipStreamSynchronize(stream));
+        for (int i = 0; i < nslots; ++i) i32[i] = sph[i];
+        HIPC(hipMemcpyAsync(B.id.p, i32.data(), 4 * (size_t)nslots, hipMemcpyHostToDevice, stream));
+        for (int i = 0; i < nslots; ++i) u16[i] = (uint16_t)bodies[sph[i]].scene;
+        HIPC(hipMemcpyAsync(B.scene.p, u16.data(), 2 * (size_t)nslots, hipMemcpyHostToDevice, stream));
+        HIPC(hipStreamSynchronize(stream));
+        // gid -> slot
+        const int ng = (int)bodies.size();
+        slot_of_id.ensure(4 * (size_t)std::max(ng, 1));
+        std::vector<int32_t> sl((size_t)std::max(ng, 1), -1);
+        for (int i = 0; i < nslots; ++i) sl[sph[i]] = i;
+        HIPC(hipMemcpyAsync(slot_of_id.p, sl.data(), 4 * (size_t)ng, hipMemcpyHostToDevice, stream));
+        // walls, scene table wall ranges
+        d_walls.ensure(sizeof(Wall) * std::max<size_t>(walls.size(), 1));
+        if (!walls.empty())
+            HIPC(hipMemcpyAsync(d_walls.p, walls.data(), sizeof(Wall) * walls.size(), hipMemcpyHostToDevice, stream));
+        HIPC(hipStreamSynchronize(stream));
+        // wall ranges live in the device scene table (which the device also
+        // updates for a periodic cell): read, modify, write back
+        pull_scene_table();
+        for (size_t s = 0; s < scenes.size(); ++s) {
+            int b = 0, c = 0;
+            for (int i = 0; i < (int)walls.size(); ++i)
+                if (wall_scene[i] == (int)s) {
+                    if (!c) b = i;
+                    ++c;
+                }
+            sp[s].wall_begin = b;
+            sp[s].wall_count = c;
+        }
+        push_scene_table();
+        // the own arrays of the active pair set must cover every gid
+        for (auto& P : ps) {
+            P.own_begin.ensure_keep(4 * (size_t)std::max(ng, 1), 4 * (size_t)ngids_dev, stream);
+            P.own_count.ensure_keep(4 * (size_t)std::max(ng, 1), 4 * (size_t)ngids_dev, stream);
+        }
+        ngids_dev = ng;
+        host_dirty = false;
+        on_device = true;
+        need_rebuild = true;
+        invalidate_graphs();
+    }
+
+    void pull_scene_table()
+    {
+        HIPC(hipMemcpyAsync(sp.data(), d_scenes.p, sizeof(SceneParams) * sp.size(), hipMemcpyDeviceToHost, stream));
+        HIPC(hipStreamSynchronize(stream));
+    }
+    void push_scene_table()
+    {
+        HIPC(hipMemcpyAsync(d_scenes.p, sp.data(), sizeof(SceneParams) * sp.size(), hipMemcpyHostToDevice, stream));
+        HIPC(hipStreamSynchronize(stream));
+    }
+
+    // The step kernels read their arguments from device memory.
+    void upload_args()
+    {
+        const StepArgs a = step_args();
+        d_args.ensure(sizeof(StepArgs));
+        HIPC(hipMemcpyAsync(d_args.p, &a, sizeof(StepArgs), hipMemcpyHostToDevice, stream));
+        HIPC(hipStreamSynchronize(stream));
+    }
+
+    // ------------------------------------------------------- broad phase
+    void rebuild()
+    {
+        if (host_dirty) upload_bodies();
+        pull_scene_table();
+        const int nsc = (int)scenes.size();
+        // Delta L per scene (InsertionSortCollider.verletDist, negative = times the smallest radius)
+        std::vector<double> rmin(nsc, INFINITY), rmax(nsc, 0.0);
+        for (const HostBody& b : bodies)
+            if (b.kind == 0) {
+                rmin[b.scene] = std::min(rmin[b.scene], b.r);
+                rmax[b.scene] = std::max(rmax[b.scene], b.r);
+            }
+        double limit = INFINITY;
+        for (int s = 0; s < nsc; ++s) {
+            const double vd = scenes[s].p.verlet_dist;
+            const double dl = vd < 0.0 ? (std::isfinite(rmin[s]) ? -vd * rmin[s] : 0.0) : vd;
+            scenes[s].verlet = dl;
+            sp[s].verlet = dl;
+            if (std::isfinite(rmin[s])) limit = std::min(limit, dl);
+        }
+        // grid per scene
+        std::vector<double> bnd(6 * (size_t)nsc, 0.0);
+        if (!periodic && nslots > 0) {
+            d_bounds.ensure(sizeof(double) * 6 * nsc);
+            launch_bounds(bs[active].view(), nullptr, nslots, nsc, d_bounds.as<double>(), stream);
+            HIPC(hipGetLastError());
+            HIPC(hipMemcpyAsync(bnd.data(), d_bounds.p, sizeof(double) * 6 * nsc, hipMemcpyDeviceToHost, stream));
+            HIPC(hipStreamSynchronize(stream));
+        }
+        int cells = 0, maxdim = 1;
+        for (int s = 0; s < nsc; ++s) {
+            SceneParams& P = sp[s];
+            const double h0 = std::max(2.0 * rmax[s] + 2.0 * P.verlet, 1e-300) * (1.0 + 1e-9);
+            if (periodic) {
+                double Hinv[9];
+                if (!invert(P.H, Hinv)) fail(DEM_EPERIODIC, "singular periodic cell");
+                std::memcpy(P.Hinv, Hinv, sizeof Hinv);
+                for (int k = 0; k < 3; ++k) {
+                    const double rn = std::sqrt(Hinv[3 * k] * Hinv[3 * k] + Hinv[3 * k + 1] * Hinv[3 * k + 1] +
+                                                Hinv[3 * k + 2] * Hinv[3 * k + 2]);
+                    const double width = 1.0 / rn;  // distance between opposite faces
+                    int n = (int)std::floor(width / h0);
+                    if (n < 3)
+                        fail(DEM_EPERIODIC, "periodic cell narrower than 3 x (2 r_max + 2 Delta L) along an axis");
+                    n = std::min(n, 1 << 20);
+                    P.dims[k] = n;
+                    P.inv_h[k] = (double)n;
+                    P.origin[k] = 0.0;
+                }
+            } else {
+                const double lo[3] = {bnd[6 * s + 0], bnd[6 * s + 1], bnd[6 * s + 2]};
+                const double hi[3] = {bnd[6 * s + 3], bnd[6 * s + 4], bnd[6 * s + 5]};
+                double h = h0;
+                int64_t nscene = 0;
+                for (;;) {
+                    int64_t tot = 1;
+                    for (int k = 0; k < 3; ++k) {
+                        const double ext = hi[k] > lo[k] ? hi[k] - lo[k] : 0.0;
+                        int64_t n = (int64_t)std::floor(ext / h) + 1;
+                        P.dims[k] = (int)std::min<int64_t>(n, 1 << 20);
+                        tot *= P.dims[k];
+                    }
+                    nscene = tot;
+                    const int64_t ns = std::max<int64_t>(scenes[s].n_spheres, 1);
+                    if (tot <= 4 * ns + 4096 && P.dims[0] < (1 << 20) && P.dims[1] < (1 << 20) && P.dims[2] < (1 << 20)) break;
+                    h *= 1.25;
+                }
+                (void)nscene;
+                for (int k = 0; k < 3; ++k) {
+                    P.origin[k] = lo[k] - 1e-12 * std::fabs(lo[k]) - 1e-300;
+                    P.inv_h[k] = 1.0 / h;
+                }
+            }
+            P.cell_offset = cells;
+            cells += P.dims[0] * P.dims[1] * P.dims[2];
+            for (int k = 0; k < 3; ++k) maxdim = std::max(maxdim, P.dims[k]);
+            // mean-field share of the Verlet budget (periodic)
+            double lf = 0.0;
+            for (int k = 0; k < 9; ++k) lf += P.L[k] * P.L[k];
+            P.verlet_cell_rate = 0.5 * std::sqrt(lf) * (2.0 * rmax[s] + 4.0 * P.verlet);
+        }
+        ncells = std::max(cells, 1);
+        morton_bits = 1;
+        while ((1 << morton_bits) < maxdim) ++morton_bits;
+        scene_bits = 0;
+        if (nsc > 1)
+            while ((1 << scene_bits) < nsc) ++scene_bits;
+        if (3 * morton_bits + scene_bits > 64) fail(DEM_EINVAL, "grid too large for 64-bit cell keys");
+        push_scene_table();
+
+        Counters& C = *h_ctr;
+        int npairs_new = 0;
+        if (nslots > 0) {
+            GridArgs g;
+            g.bod = bs[active].view();
+            g.scenes = d_scenes.as<SceneParams>();
+            g.scene0 = sp[0];
+            g.nscenes = nsc;
+            g.nslots = nslots;
+            g.scene_bits = scene_bits;
+            g.morton_bits = morton_bits;
+            // keys, sort, permute into the other body set
+            keys.ensure(8 * (size_t)nslots);
+            vals.ensure(4 * (size_t)nslots);
+            keys_alt.ensure(8 * (size_t)nslots);
+            vals_alt.ensure(4 * (size_t)nslots);
+            radix_tmp.ensure(radix_temp_bytes(nslots));
+            launch_keys(g, keys.as<uint64_t>(), vals.as<uint32_t>(), stream);
+            bool in_alt = false;
+            radix_sort_pairs(keys.as<uint64_t>(), vals.as<uint32_t>(), keys_alt.as<uint64_t>(), vals_alt.as<uint32_t>(),
+                             nslots, 3 * morton_bits + scene_bits, radix_tmp.p, stream, &in_alt);
+            const uint64_t* skeys = in_alt ? keys_alt.as<uint64_t>() : keys.as<uint64_t>();
+            const uint32_t* order = in_alt ? vals_alt.as<uint32_t>() : vals.as<uint32_t>();
+            launch_permute(bs[active].view(), bs[1 - active].view(), order, nslots, batched(), periodic,
+                           slot_of_id.as<int32_t>(), stream);
+            active = 1 - active;
+            g.bod = bs[active].view();
+            // cells
+            cell_start.ensure(4 * (size_t)ncells);
+            cell_end.ensure(4 * (size_t)ncells);
+            launch_cells(g, skeys, cell_start.as<uint32_t>(), cell_end.as<uint32_t>(), ncells, stream);
+            // sweep: count, scan, fill
+            SweepArgs sw;
+            sw.g = g;
+            sw.cell_start = cell_start.as<uint32_t>();
+            sw.cell_end = cell_end.as<uint32_t>();
+            sw.walls = d_walls.as<Wall>();
+            counts.ensure(4 * ((size_t)nslots + 1));
+            row_start.ensure(4 * ((size_t)nslots + 1));
+            HIPC(hipMemsetAsync(counts.as<uint32_t>() + nslots, 0, 4, stream));
+            sw.count = counts.as<uint32_t>();
+            launch_sweep_count(sw, stream);
+            d_total.ensure(16);
+            scan_tmp.ensure(scan_temp_bytes(nslots + 1));
+            exclusive_scan_u32(counts.as<uint32_t>(), row_start.as<uint32_t>(), nslots + 1, scan_tmp.p,
+                               d_total.as<uint32_t>(), stream);
+            uint32_t nent = 0;
+            HIPC(hipMemcpyAsync(&nent, d_total.p, 4, hipMemcpyDeviceToHost, stream));
+            HIPC(hipStreamSynchronize(stream));
+            HIPC(hipGetLastError());
+            if (nent > 0x7ffffff0u) fail(DEM_ENOMEM, "too many candidate entries");
+            ent_slot.ensure(4 * ((size_t)nent + 1));
+            ent_pid.ensure(4 * ((size_t)nent + 1));
+            ent_cell.ensure(4 * ((size_t)nent + 1));
+            ent_own.ensure(4 * ((size_t)nent + 1));
+            own_scan.ensure(4 * ((size_t)nent + 1));
+            rows_ent.ensure(4 * ((size_t)nent + 1));
+            sw.row_start = row_start.as<int32_t>();
+            sw.ent_slot = ent_slot.as<int32_t>();
+            sw.ent_pid = ent_pid.as<int32_t>();
+            sw.ent_cell = ent_cell.as<int32_t>();
+            sw.ent_own = ent_own.as<uint32_t>();
+            sw.max_row = 0;
+            launch_sweep_fill(sw, stream);
+            HIPC(hipMemsetAsync(ent_own.as<uint32_t>() + nent, 0, 4, stream));
+            scan_tmp.ensure(scan_temp_bytes((int)nent + 1));
+            exclusive_scan_u32(ent_own.as<uint32_t>(), own_scan.as<uint32_t>(), (int)nent + 1, scan_tmp.p,
+                               d_total.as<uint32_t>(), stream);
+            uint32_t np = 0;
+            HIPC(hipMemcpyAsync(&np, d_total.p, 4, hipMemcpyDeviceToHost, stream));
+            HIPC(hipStreamSynchronize(stream));
+            HIPC(hipGetLastError());
+            npairs_new = (int)np;
+            n_candidates = np;
+            // new pair set
+            PairSet& NP = ps[1 - pactive];
+            PairSet& OP = ps[pactive];
+            NP.ensure(np, precision == DEM_FP32_MIXED);
+            const int ng = (int)bodies.size();
+            NP.own_begin.ensure(4 * (size_t)std::max(ng, 1));
+            NP.own_count.ensure(4 * (size_t)std::max(ng, 1));
+            HIPC(hipMemsetAsync(NP.own_begin.p, 0, 4 * (size_t)std::max(ng, 1), stream));
+            HIPC(hipMemsetAsync(NP.own_count.p, 0, 4 * (size_t)std::max(ng, 1), stream));
+            PairBuildArgs pb;
+            pb.bod = g.bod;
+            pb.row_start = row_start.as<int32_t>();
+            pb.ent_slot = ent_slot.as<int32_t>();
+            pb.ent_pid = ent_pid.as<int32_t>();
+            pb.ent_cell = ent_cell.as<int32_t>();
+            pb.own_scan = own_scan.as<uint32_t>();
+            pb.ent_own = ent_own.as<uint32_t>();
+            pb.rows.start = row_start.as<int32_t>();
+            pb.rows.ent = rows_ent.as<uint32_t>();
+            pb.pr = NP.view();
+            pb.hist_new = NP.history();
+            pb.hist_old = OP.history();
+            pb.nslots = nslots;
+            pb.nent = (int)nent;
+            pb.npairs = (int)np;
+            pb.has_old = (OP.cap > 0 && OP.own_begin.p && old_ngids > 0) ? 1 : 0;
+            launch_pair_build(pb, stream);
+            launch_carry_over(pb, stream, std::min(old_ngids, ng));
+            HIPC(hipGetLastError());
+            pactive = 1 - pactive;
+            old_ngids = ng;
+        } else {
+            npairs_new = 0;
+            n_candidates = 0;
+            row_start.ensure(8);
+            HIPC(hipMemsetAsync(row_start.p, 0, 8, stream));
+            old_ngids = (int)bodies.size();
+        }
+        npairs = npairs_new;
+        // step-kernel grids: the contact grid keeps 25 % headroom so that a
+        // captured graph survives the next runs; blocks past npairs exit
+        if ((int64_t)grid_c * block_contact < npairs || grid_c < 1)
+            grid_c = std::max((int)(((int64_t)npairs * 5 / 4 + block_contact - 1) / block_contact), 1);
+        grid_i = std::max((nslots + block_integrate - 1) / block_integrate, 1);
+        d_part_c.ensure(sizeof(BlockPartial) * (size_t)grid_c);
+        d_part_i.ensure(sizeof(BlockPartial) * (size_t)grid_i);
+        // counters: fresh Verlet budget
+        HIPC(hipMemcpyAsync(h_ctr, d_ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, stream));
+        HIPC(hipStreamSynchronize(stream));
+        C.verlet_acc = 0.0;
+        C.verlet_limit = 0.98 * (std::isfinite(limit) ? limit : 0.0);
+        double cell_step = 0.0;
+        for (int s = 0; s < nsc; ++s) cell_step = std::max(cell_step, sp[s].verlet_cell_rate * sp[s].dt);
+        C.verlet_cell_step = cell_step;
+        C.stall = 0;
+        C.blocks_done_contact = 0;
+        C.blocks_done_integrate = 0;
+        C.vmax_bits = 0;
+        C.cur_ss = C.cur_sw = 0;
+        HIPC(hipMemcpyAsync(d_ctr.p, h_ctr, sizeof(Counters), hipMemcpyHostToDevice, stream));
+        HIPC(hipStreamSynchronize(stream));
+        upload_args();
+        need_rebuild = false;
+        ++rebuilds;
+    }
+
+    // ------------------------------------------------------------ step
+    StepArgs step_args() const
+    {
+        StepArgs a;
+        a.bod = bs[active].view();
+        a.pr = ps[pactive].view();
+        a.rows.start = row_start.as<int32_t>();
+        a.rows.ent = rows_ent.as<uint32_t>();
+        a.walls = d_walls.as<Wall>();
+        a.mats = d_mats.as<Material>();
+        a.tanphi = d_tanphi.as<double>();
+        a.nmat = (int)mats.size();
+        a.scenes = d_scenes.as<SceneParams>();
+        a.scene0 = sp[0];
+        a.nscenes = (int)scenes.size();
+        a.nslots = nslots;
+        a.npairs = npairs;
+        a.ctr = d_ctr.as<Counters>();
+        a.part_contact = d_part_c.as<BlockPartial>();
+        a.part_integrate = d_part_i.as<BlockPartial>();
+        a.track_energy = track_energy ? 1 : 0;
+        return a;
+    }
+
+    void launch_step(hipEvent_t* ev)
+    {
+        const StepArgs* a = d_args.as<StepArgs>();
+        if (ev) HIPC(hipEventRecord(ev[0], stream));
+        launch_contact(a, grid_c, precision, batched(), periodic, block_contact, stream);
+        if (ev) HIPC(hipEventRecord(ev[1], stream));
+        launch_integrate(a, grid_i, precision, batched(), periodic, block_integrate, stream);
+        if (ev) HIPC(hipEventRecord(ev[2], stream));
+    }
+
+    std::string graph_key(int n) const
+    {
+        char buf[256];
+        std::snprintf(buf, sizeof buf, "%p/%d/%d/%d/%d/%d/%d", d_args.p, grid_c, grid_i, n, timing ? 1 : 0,
+                      block_contact, block_integrate);
+        return buf;
+    }
+
+    GraphEntry& get_graph(int n)
+    {
+        const std::string key = graph_key(n);
+        auto it = graphs.find(key);
+        if (it != graphs.end()) return it->second;
+        if (graphs.size() > 8) invalidate_graphs();
+        GraphEntry ge;
+        if (timing) {
+            ge.ev.resize(3 * (size_t)n);
+            for (auto& e : ge.ev) HIPC(hipEventCreate(&e));
+        }
+        hipGraph_t g;
+        HIPC(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        for (int i = 0; i < n; ++i) launch_step(timing ? &ge.ev[3 * (size_t)i] : nullptr);
+        HIPC(hipStreamEndCapture(stream, &g));
+        HIPC(hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0));
+        HIPC(hipGraphDestroy(g));
+        return graphs.emplace(key, std::move(ge)).first->second;
+    }
+
+    void read_counters()
+    {
+        HIPC(hipMemcpyAsync(h_ctr, d_ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, stream));
+        HIPC(hipStreamSynchronize(stream));
+    }
+
+    void add_time(const char* name, hipEvent_t a, hipEvent_t b)
+    {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, a, b) == hipSuccess) {
+            timers[name].total_ms += ms;
+            timers[name].launches += 1;
+        }
+    }
+
+    void step(int64_t nsteps)
+    {
+        if (nsteps < 0) fail(DEM_EINVAL, "dem_step: nsteps < 0");
+        HIPC(hipSetDevice(device));
+        if (timing) timers.clear();
+        if (host_dirty) upload_bodies();
+        if (nslots == 0 && walls.empty()) {
+            for (auto& S : scenes) {
+                S.iter += nsteps;
+                S.time += nsteps * S.p.dt;
+            }
+            return;
+        }
+        int64_t remaining = nsteps;
+        std::vector<hipEvent_t> direct_ev;
+        if (timing) {
+            direct_ev.resize(3);
+            for (auto& e : direct_ev) HIPC(hipEventCreate(&e));
+        }
+        hipEvent_t rb0 = nullptr, rb1 = nullptr;
+        if (timing) {
+            HIPC(hipEventCreate(&rb0));
+            HIPC(hipEventCreate(&rb1));
+        }
+        try {
+            while (remaining > 0) {
+                if (need_rebuild || h_ctr->stall) {
+                    if (timing) HIPC(hipEventRecord(rb0, stream));
+                    rebuild();
+                    if (timing) {
+                        HIPC(hipEventRecord(rb1, stream));
+                        HIPC(hipEventSynchronize(rb1));
+                        add_time("rebuild", rb0, rb1);
+                    }
+                }
+                h_ctr->steps_done = 0;
+                HIPC(hipMemsetAsync(reinterpret_cast<char*>(d_ctr.p) + offsetof(Counters, steps_done), 0, 4, stream));
+                const int n = (int)std::min<int64_t>(remaining, chunk);
+                GraphEntry* ge = nullptr;
+                if (use_graph && n == chunk) {
+                    ge = &get_graph(n);
+                    HIPC(hipGraphLaunch(ge->exec, stream));
+                } else {
+                    for (int i = 0; i < n; ++i) {
+                        launch_step(timing ? direct_ev.data() : nullptr);
+                        if (timing) {
+                            HIPC(hipEventSynchronize(direct_ev[2]));
+                            add_time("contact", direct_ev[0], direct_ev[1]);
+                            add_time("integrate", direct_ev[1], direct_ev[2]);
+                        }
+                    }
+                }
+                HIPC(hipGetLastError());
+                read_counters();
+                const int done = h_ctr->steps_done;
+                if (timing && ge) {
+                    for (int i = 0; i < done; ++i) {
+                        add_time("contact", ge->ev[3 * (size_t)i], ge->ev[3 * (size_t)i + 1]);
+                        add_time("integrate", ge->ev[3 * (size_t)i + 1], ge->ev[3 * (size_t)i + 2]);
+                    }
+                }
+                for (auto& S : scenes) {
+                    S.iter += done;
+                    S.time += done * S.p.dt;
+                }
+                remaining -= done;
+                contacts_valid = done > 0 || contacts_valid;
+                if (h_ctr->nonfinite) fail(DEM_ENONFINITE, "non-finite position or velocity after a step");
+                if (h_ctr->unstable) fail(DEM_EUNSTABLE, "an overlap exceeded a sphere radius (numerically exploding)");
+                if (done == 0 && !h_ctr->stall) fail(DEM_EDEVICE, "no step completed");
+            }
+        } catch (...) {
+            for (auto e : direct_ev) (void)hipEventDestroy(e);
+            if (rb0) (void)hipEventDestroy(rb0);
+            if (rb1) (void)hipEventDestroy(rb1);
+            throw;
+        }
+        for (auto e : direct_ev) (void)hipEventDestroy(e);
+        if (rb0) (void)hipEventDestroy(rb0);
+        if (rb1) (void)hipEventDestroy(rb1);
+    }
+
+    // ------------------------------------------------------- read-back
+    struct Snapshot {
+        std::vector<double> x, y, z, vx, vy, vz, wx, wy, wz, qw, qx, qy, qz;
+        std::vector<int32_t> id;
+        std::vector<int32_t> slot_of;  // gid -> slot
+    };
+
+    Snapshot snapshot()
+    {
+        Snapshot s;
+        const BodySet& B = bs[active];
+        const size_t n = (size_t)nslots;
+        auto get = [&](const DBuf& d, std::vector<double>& v) {
+            v.resize(n);
+            if (n) HIPC(hipMemcpyAsync(v.data(), d.p, 8 * n, hipMemcpyDeviceToHost, stream));
+        };
+        get(B.x, s.x);
+        get(B.y, s.y);
+        get(B.z, s.z);
+        get(B.vx, s.vx);
+        get(B.vy, s.vy);
+        get(B.vz, s.vz);
+        get(B.wx, s.wx);
+        get(B.wy, s.wy);
+        get(B.wz, s.wz);
+        get(B.qw, s.qw);
+        get(B.qx, s.qx);
+        get(B.qy, s.qy);
+        get(B.qz, s.qz);
+        s.id.resize(n);
+        if (n) HIPC(hipMemcpyAsync(s.id.data(), B.id.p, 4 * n, hipMemcpyDeviceToHost, stream));
+        HIPC(hipStreamSynchronize(stream));
+        s.slot_of.assign(bodies.size(), -1);
+        for (size_t i = 0; i < n; ++i) s.slot_of[s.id[i]] = (int32_t)i;
+        return s;
+    }
+
+    struct PairSnapshot {
+        std::vector<int32_t> a, b, cell;
+        std::vector<double> fsx, fsy, fsz, nx, ny, nz, fx, fy, fz;
+    };
+
+    PairSnapshot pair_snapshot()
+    {
+        PairSnapshot p;
+        const PairSet& P = ps[pactive];
+        const size_t n = (size_t)npairs;
+        auto gi = [&](const DBuf& d, std::vector<int32_t>& v) {
+            v.resize(n);
+            if (n) HIPC(hipMemcpyAsync(v.data(), d.p, 4 * n, hipMemcpyDeviceToHost, stream));
+        };
+        auto gd = [&](const DBuf& d, std::vector<double>& v) {
+            v.resize(n);
+            if (n) HIPC(hipMemcpyAsync(v.data(), d.p, 8 * n, hipMemcpyDeviceToHost, stream));
+        };
+        gi(P.a, p.a);
+        gi(P.b, p.b);
+        gi(P.cell, p.cell);
+        gd(P.fsx, p.fsx);
+        gd(P.fsy, p.fsy);
+        gd(P.fsz, p.fsz);
+        gd(P.nx, p.nx);
+        gd(P.ny, p.ny);
+        gd(P.nz, p.nz);
+        if (precision == DEM_FP32_MIXED) {
+            std::vector<float> f(n);
+            auto gf = [&](const DBuf& d, std::vector<double>& v) {
+                v.resize(n);
+                if (n) HIPC(hipMemcpyAsync(f.data(), d.p, 4 * n, hipMemcpyDeviceToHost, stream));
+                HIPC(hipStreamSynchronize(stream));
+                for (size_t i = 0; i < n; ++i) v[i] = f[i];
+            };
+            gf(P.fxf, p.fx);
+            gf(P.fyf, p.fy);
+            gf(P.fzf, p.fz);
+        } else {
+            gd(P.fx, p.fx);
+            gd(P.fy, p.fy);
+            gd(P.fz, p.fz);
+        }
+        HIPC(hipStreamSynchronize(stream));
+        return p;
+    }
+
+    void check_scene_id(int s, int64_t first, int64_t count) const
+    {
+        if (first < 0 || count < 0 || first + count > (int64_t)scenes[s].gids.size())
+            fail(DEM_ERANGE, "Body id out of range");
+    }
+
+    void get_state(int s, int64_t first, int64_t count, double* pos3, double* vel3, double* angvel3, double* ori4,
+                   double* force3, double* torque3)
+    {
+        check_scene_id(s, first, count);
+        const HostScene& S = scenes[s];
+        if (host_dirty || !on_device) {
+            for (int64_t i = 0; i < count; ++i) {
+                const HostBody& b = bodies[S.gids[first + i]];
+                for (int k = 0; k < 3; ++k) {
+                    if (pos3) pos3[3 * i + k] = b.kind ? (k == walls[b.wall].axis ? walls[b.wall].pos : 0.0) : b.x[k];
+                    if (vel3) vel3[3 * i + k] = b.v[k];
+                    if (angvel3) angvel3[3 * i + k] = b.w[k];
+                    if (force3) force3[3 * i + k] = 0.0;
+                    if (torque3) torque3[3 * i + k] = 0.0;
+                }
+                if (ori4)
+                    for (int k = 0; k < 4; ++k) ori4[4 * i + k] = b.q[k];
+            }
+            return;
+        }
+        Snapshot sn = snapshot();
+        std::vector<double> f, t;
+        std::vector<double> wallF(3 * walls.size(), 0.0);
+        if (force3 || torque3) {
+            f.assign(3 * (size_t)nslots, 0.0);
+            t.assign(3 * (size_t)nslots, 0.0);
+            if (nslots > 0 && contacts_valid) {
+                d_tmp3.ensure(sizeof(double) * 6 * (size_t)nslots);
+                StepArgs a = step_args();
+                launch_body_forces(a, precision, d_tmp3.as<double>(), d_tmp3.as<double>() + 3 * (size_t)nslots, stream);
+                HIPC(hipGetLastError());
+                HIPC(hipMemcpyAsync(f.data(), d_tmp3.p, 8 * 3 * (size_t)nslots, hipMemcpyDeviceToHost, stream));
+                HIPC(hipMemcpyAsync(t.data(), d_tmp3.as<double>() + 3 * (size_t)nslots, 8 * 3 * (size_t)nslots,
+                                    hipMemcpyDeviceToHost, stream));
+                HIPC(hipStreamSynchronize(stream));
+                // reaction on walls: minus the force on the sphere, in pair order
+                PairSnapshot p = pair_snapshot();
+                for (int k = 0; k < npairs; ++k)
+                    if (p.a[k] < 0) {
+                        const int w = -1 - p.a[k];
+                        wallF[3 * w + 0] += -p.fx[k];
+                        wallF[3 * w + 1] += -p.fy[k];
+                        wallF[3 * w + 2] += -p.fz[k];
+                    }
+            }
+        }
+        for (int64_t i = 0; i < count; ++i) {
+            const int32_t g = S.gids[first + i];
+            const HostBody& b = bodies[g];
+            if (b.kind == 1) {
+                const Wall& W = walls[b.wall];
+                for (int k = 0; k < 3; ++k) {
+                    if (pos3) pos3[3 * i + k] = k == W.axis ? W.pos : 0.0;
+                    if (vel3) vel3[3 * i + k] = 0.0;
+                    if (angvel3) angvel3[3 * i + k] = 0.0;
+                    if (force3) force3[3 * i + k] = wallF[3 * b.wall + k];
+                    if (torque3) torque3[3 * i + k] = 0.0;
+                }
+                if (ori4) {
+                    ori4[4 * i] = 1.0;
+                    ori4[4 * i + 1] = ori4[4 * i + 2] = ori4[4 * i + 3] = 0.0;
+                }
+                continue;
+            }
+            const int sl = sn.slot_of[g];
+            if (pos3) {
+                pos3[3 * i] = sn.x[sl];
+                pos3[3 * i + 1] = sn.y[sl];
+                pos3[3 * i + 2] = sn.z[sl];
+            }
+            if (vel3) {
+                vel3[3 * i] = sn.vx[sl];
+                vel3[3 * i + 1] = sn.vy[sl];
+                vel3[3 * i + 2] = sn.vz[sl];
+            }
+            if (angvel3) {
+                angvel3[3 * i] = sn.wx[sl];
+                angvel3[3 * i + 1] = sn.wy[sl];
+                angvel3[3 * i + 2] = sn.wz[sl];
+            }
+            if (ori4) {
+                ori4[4 * i] = sn.qw[sl];
+                ori4[4 * i + 1] = sn.qx[sl];
+                ori4[4 * i + 2] = sn.qy[sl];
+                ori4[4 * i + 3] = sn.qz[sl];
+            }
+            for (int k = 0; k < 3; ++k) {
+                if (force3) force3[3 * i + k] = f[3 * (size_t)sl + k];
+                if (torque3) torque3[3 * i + k] = t[3 * (size_t)sl + k];
+            }
+        }
+    }
+
+    void set_state(int s, const double* pos3, const double* vel3, const double* angvel3, const double* ori4)
+    {
+        pull_bodies();
+        const HostScene& S = scenes[s];
+        for (size_t i = 0; i < S.gids.size(); ++i) {
+            HostBody& b = bodies[S.gids[i]];
+            if (b.kind != 0) continue;
+            for (int k = 0; k < 3; ++k) {
+                if (pos3) b.x[k] = pos3[3 * i + k];
+                if (vel3) b.v[k] = vel3[3 * i + k];
+                if (angvel3) b.w[k] = angvel3[3 * i + k];
+            }
+            if (ori4)
+                for (int k = 0; k < 4; ++k) b.q[k] = ori4[4 * i + k];
+        }
+        host_dirty = true;
+        need_rebuild = true;
+    }
+
+    // local id of a gid within its scene
+    std::vector<int64_t> local_ids() const
+    {
+        std::vector<int64_t> loc(bodies.size(), -1);
+        for (const HostScene& S : scenes)
+            for (size_t i = 0; i < S.gids.size(); ++i) loc[S.gids[i]] = (int64_t)i;
+        return loc;
+    }
+
+    static void unpack_cell(int32_t p, int32_t* c)
+    {
+        const uint32_t u = (uint32_t)p;
+        c[0] = (int32_t)((u >> 20) & 1023u) - 512;
+        c[1] = (int32_t)((u >> 10) & 1023u) - 512;
+        c[2] = (int32_t)(u & 1023u) - 512;
+    }
+
+    std::vector<dem_contact> contacts(int s)
+    {
+        std::vector<dem_contact> out;
+        if (!contacts_valid || host_dirty || npairs == 0) return out;
+        Snapshot sn = snapshot();
+        PairSnapshot p = pair_snapshot();
+        const std::vector<int64_t> loc = local_ids();
+        for (int k = 0; k < npairs; ++k) {
+            const double nn = p.nx[k] * p.nx[k] + p.ny[k] * p.ny[k] + p.nz[k] * p.nz[k];
+            if (!(nn > 0.0)) continue;
+            const int sb = p.b[k];
+            const int32_t g2 = sn.id[sb];
+            const HostBody& B2 = bodies[g2];
+            if (B2.scene != s) continue;
+            dem_contact c;
+            std::memset(&c, 0, sizeof c);
+            const bool wall = p.a[k] < 0;
+            const HostBody* B1 = nullptr;
+            int32_t g1;
+            if (wall) {
+                g1 = walls[-1 - p.a[k]].id;
+            } else {
+                g1 = sn.id[p.a[k]];
+                B1 = &bodies[g1];
+            }
+            c.id1 = loc[g1];
+            c.id2 = loc[g2];
+            c.is_wall = wall ? 1 : 0;
+            unpack_cell(p.cell[k], c.cell);
+            c.normal[0] = p.nx[k];
+            c.normal[1] = p.ny[k];
+            c.normal[2] = p.nz[k];
+            c.fs[0] = p.fsx[k];
+            c.fs[1] = p.fsy[k];
+            c.fs[2] = p.fsz[k];
+            c.fn[0] = p.fx[k] - p.fsx[k];
+            c.fn[1] = p.fy[k] - p.fsy[k];
+            c.fn[2] = p.fz[k] - p.fsz[k];
+            const HostMaterial& M2 = mats[B2.mat];
+            const HostMaterial& M1 = wall ? mats[walls[-1 - p.a[k]].mat] : mats[B1->mat];
+            const double R1 = wall ? B2.r : B1->r, R2 = B2.r;
+            const double k1 = M1.young * (2.0 * R1), k2 = M2.young * (2.0 * R2);
+            c.kn = k1 * k2 / (k1 + k2);
+            const double q1 = (M1.young * M1.poisson) * (2.0 * R1), q2 = (M2.young * M2.poisson) * (2.0 * R2);
+            c.ks = q1 * q2 / (q1 + q2);
+            c.pen = std::sqrt(c.fn[0] * c.fn[0] + c.fn[1] * c.fn[1] + c.fn[2] * c.fn[2]) / c.kn;
+            const double dt = scenes[s].p.dt;
+            // positions of the step the contact was evaluated at: x - v dt
+            const double x2[3] = {sn.x[sb] - sn.vx[sb] * dt, sn.y[sb] - sn.vy[sb] * dt, sn.z[sb] - sn.vz[sb] * dt};
+            if (wall) {
+                for (int q = 0; q < 3; ++q) c.point[q] = x2[q] - (R2 - 0.5 * c.pen) * c.normal[q];
+            } else {
+                const int sa = p.a[k];
+                const double x1[3] = {sn.x[sa] - sn.vx[sa] * dt, sn.y[sa] - sn.vy[sa] * dt, sn.z[sa] - sn.vz[sa] * dt};
+                for (int q = 0; q < 3; ++q) c.point[q] = x1[q] + (R1 - 0.5 * c.pen) * c.normal[q];
+            }
+            out.push_back(c);
+        }
+        std::sort(out.begin(), out.end(), [](const dem_contact& a, const dem_contact& b) {
+            const int64_t alo = std::min(a.id1, a.id2), ahi = std::max(a.id1, a.id2);
+            const int64_t blo = std::min(b.id1, b.id2), bhi = std::max(b.id1, b.id2);
+            if (alo != blo) return alo < blo;
+            if (ahi != bhi) return ahi < bhi;
+            for (int q = 0; q < 3; ++q)
+                if (a.cell[q] != b.cell[q]) return a.cell[q] < b.cell[q];
+            return false;
+        });
+        return out;
+    }
+
+    void set_history(int s, int64_t n, const dem_history* in)
+    {
+        if (n < 0 || (n > 0 && !in)) fail(DEM_EINVAL, "dem_set_history: bad arguments");
+        if (host_dirty) upload_bodies();
+        const HostScene& S = scenes[s];
+        struct Rec {
+            int32_t owner, partner, cell;
+            double fs[3], n[3];
+        };
+        std::vector<Rec> recs;
+        recs.reserve((size_t)n);
+        for (int64_t i = 0; i < n; ++i) {
+            const dem_history& h = in[i];
+            if (h.id1 < 0 || h.id2 < 0 || h.id1 >= (int64_t)S.gids.size() || h.id2 >= (int64_t)S.gids.size() ||
+                h.id1 == h.id2)
+                fail(DEM_ERANGE, "dem_set_history: body id out of range");
+            int32_t g1 = S.gids[h.id1], g2 = S.gids[h.id2];
+            int32_t c[3] = {h.cell[0], h.cell[1], h.cell[2]};
+            const bool w1 = bodies[g1].kind == 1, w2 = bodies[g2].kind == 1;
+            if (w1 && w2) fail(DEM_EINVAL, "dem_set_history: wall-wall record");
+            Rec r;
+            if (w1 || w2) {
+                r.owner = w1 ? g2 : g1;
+                r.partner = w1 ? g1 : g2;
+                c[0] = c[1] = c[2] = 0;
+            } else if (g1 < g2) {
+                r.owner = g1;
+                r.partner = g2;
+            } else {
+                r.owner = g2;
+                r.partner = g1;
+                for (int q = 0; q < 3; ++q) c[q] = -c[q];
+            }
+            for (int q = 0; q < 3; ++q)
+                if (c[q] < -512 || c[q] > 511) fail(DEM_EINVAL, "dem_set_history: cell shift out of range");
+            r.cell = (int32_t)(((uint32_t)(c[0] + 512) << 20) | ((uint32_t)(c[1] + 512) << 10) | (uint32_t)(c[2] + 512));
+            for (int q = 0; q < 3; ++q) {
+                r.fs[q] = h.fs[q];
+                r.n[q] = h.nprev[q];
+            }
+            recs.push_back(r);
+        }
+        std::sort(recs.begin(), recs.end(), [](const Rec& a, const Rec& b) {
+            if (a.owner != b.owner) return a.owner < b.owner;
+            if (a.partner != b.partner) return a.partner < b.partner;
+            return (uint32_t)a.cell < (uint32_t)b.cell;
+        });
+        // keep the history of other scenes: merge with the current real contacts
+        std::vector<Rec> keep;
+        if (scenes.size() > 1 && contacts_valid && npairs > 0) {
+            Snapshot sn = snapshot();
+            PairSnapshot p = pair_snapshot();
+            for (int k = 0; k < npairs; ++k) {
+                const double nn = p.nx[k] * p.nx[k] + p.ny[k] * p.ny[k] + p.nz[k] * p.nz[k];
+                if (!(nn > 0.0)) continue;
+                const int32_t g2 = sn.id[p.b[k]];
+                if (bodies[g2].scene == s) continue;
+                Rec r;
+                if (p.a[k] < 0) {
+                    r.owner = g2;
+                    r.partner = walls[-1 - p.a[k]].id;
+                } else {
+                    r.owner = sn.id[p.a[k]];
+                    r.partner = g2;
+                }
+                r.cell = p.cell[k];
+                r.fs[0] = p.fsx[k];
+                r.fs[1] = p.fsy[k];
+                r.fs[2] = p.fsz[k];
+                r.n[0] = p.nx[k];
+                r.n[1] = p.ny[k];
+                r.n[2] = p.nz[k];
+                keep.push_back(r);
+            }
+        }
+        recs.insert(recs.end(), keep.begin(), keep.end());
+        std::sort(recs.begin(), recs.end(), [](const Rec& a, const Rec& b) {
+            if (a.owner != b.owner) return a.owner < b.owner;
+            if (a.partner != b.partner) return a.partner < b.partner;
+            return (uint32_t)a.cell < (uint32_t)b.cell;
+        });
+        const int ng = (int)bodies.size();
+        std::vector<int32_t> ob((size_t)std::max(ng, 1), 0), oc((size_t)std::max(ng, 1), 0);
+        for (size_t i = 0; i < recs.size(); ++i) {
+            if (oc[recs[i].owner] == 0) ob[recs[i].owner] = (int32_t)i;
+            oc[recs[i].owner] += 1;
+        }
+        const size_t m = recs.size();
+        PairSet& P = ps[pactive];
+        P.ensure(std::max<size_t>(m, (size_t)npairs), precision == DEM_FP32_MIXED);
+        P.own_begin.ensure(4 * (size_t)std::max(ng, 1));
+        P.own_count.ensure(4 * (size_t)std::max(ng, 1));
+        std::vector<int32_t> pid(m), cell(m);
+        std::vector<double> f[6];
+        for (auto& v : f) v.resize(m);
+        for (size_t i = 0; i < m; ++i) {
+            pid[i] = recs[i].partner;
+            cell[i] = recs[i].cell;
+            for (int q = 0; q < 3; ++q) {
+                f[q][i] = recs[i].fs[q];
+                f[3 + q][i] = recs[i].n[q];
+            }
+        }
+        HIPC(hipMemcpyAsync(P.own_begin.p, ob.data(), 4 * (size_t)ng, hipMemcpyHostToDevice, stream));
+        HIPC(hipMemcpyAsync(P.own_count.p, oc.data(), 4 * (size_t)ng, hipMemcpyHostToDevice, stream));
+        if (m) {
+            HIPC(hipMemcpyAsync(P.pid.p, pid.data(), 4 * m, hipMemcpyHostToDevice, stream));
+            HIPC(hipMemcpyAsync(P.cell.p, cell.data(), 4 * m, hipMemcpyHostToDevice, stream));
+            DBuf* dst[6] = {&P.fsx, &P.fsy, &P.fsz, &P.nx, &P.ny, &P.nz};
+            for (int q = 0; q < 6; ++q)
+                HIPC(hipMemcpyAsync(dst[q]->p, f[q].data(), 8 * m, hipMemcpyHostToDevice, stream));
+        }
+        HIPC(hipStreamSynchronize(stream));
+        old_ngids = ng;
+        npairs = 0;  // the active set now only holds history: nothing to report until the next step
+        contacts_valid = false;
+        need_rebuild = true;
+        invalidate_graphs();
+    }
+};
+
+}  // namespace
+}  // namespace dem
+
+// ======================================================================
+//                                C ABI
+// ======================================================================
+
+struct dem_scene {
+    dem::World* w;
+    int s;
+    bool owner;
+};
+struct dem_batch {
+    dem::World* w;
+    std::vector<dem_scene> views;
+};
+
+namespace {
+
+template <typename F>
+dem_status guarded(F&& f)
+{
+    try {
+        f();
+        dem::g_err.clear();
+        return DEM_OK;
+    } catch (const dem::Error& e) {
+        dem::g_err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        dem::g_err = "host allocation failed";
+        return DEM_ENOMEM;
+    } catch (const std::exception& e) {
+        dem::g_err = e.what();
+        return DEM_EINVAL;
+    }
+}
+
+void check_params(const dem_params* p)
+{
+    if (!p) dem::fail(DEM_EINVAL, "null params");
+    if (!(p->dt >= 0.0) || !std::isfinite(p->dt)) dem::fail(DEM_EINVAL, "dt must be >= 0 and finite");
+    if (!(p->damping >= 0.0 && p->damping < 1.0)) dem::fail(DEM_EINVAL, "damping must be in [0, 1)");
+    if (p->precision != DEM_FP64 && p->precision != DEM_FP32_MIXED) dem::fail(DEM_EINVAL, "unknown precision");
+    if (p->homo_deform < 0 || p->homo_deform > 2) dem::fail(DEM_EINVAL, "homo_deform must be 0, 1 or 2");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(p->gravity[k])) dem::fail(DEM_EINVAL, "gravity must be finite");
+    if (p->periodic) {
+        double inv[9];
+        if (!dem::World::invert(p->hsize, inv)) dem::fail(DEM_EINVAL, "singular cell matrix");
+    }
+}
+
+dem::World* world_of(dem_scene* s)
+{
+    if (!s || !s->w) dem::fail(DEM_EINVAL, "null scene");
+    HIPC(hipSetDevice(s->w->device));
+    return s->w;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t dem_abi_version(void) { return DEM_ABI_VERSION; }
+
+const char* dem_last_error(void) { return dem::g_err.c_str(); }
+
+void dem_params_default(dem_params* p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->damping = 0.2;
+    p->damp_rot = 1;
+    p->verlet_dist = -0.5;
+    p->precision = DEM_FP64;
+    p->homo_deform = 2;
+    for (int k = 0; k < 9; ++k) p->hsize[k] = (k % 4 == 0) ? 1.0 : 0.0;
+}
+
+dem_status dem_create(const dem_params* p, dem_scene** out)
+{
+    return guarded([&] {
+        check_params(p);
+        if (!out) dem::fail(DEM_EINVAL, "null out");
+        std::unique_ptr<dem::World> w(new dem::World());
+        w->init(1, p);
+        *out = new dem_scene{w.release(), 0, true};
+    });
+}
+
+dem_status dem_destroy(dem_scene* s)
+{
+    return guarded([&] {
+        if (!s) dem::fail(DEM_EINVAL, "null scene");
+        if (!s->owner) dem::fail(DEM_EINVAL, "dem_destroy: batch views are owned by the batch");
+        (void)hipSetDevice(s->w->device);
+        delete s->w;
+        delete s;
+    });
+}
+
+dem_status dem_add_material(dem_scene* s, double density, double young, double poisson, double friction_angle,
+                            int32_t* out_mat)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        const int m = w->add_material(density, young, poisson, friction_angle);
+        if (out_mat) *out_mat = m;
+    });
+}
+
+dem_status dem_add_spheres(dem_scene* s, int64_t n, const double* pos3, const double* radius, const double* vel3,
+                           const double* angvel3, const int32_t* mat, int32_t default_mat, const uint8_t* blocked,
+                           int64_t* out_first_id)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        const int64_t first = w->add_spheres(s->s, n, pos3, radius, vel3, angvel3, mat, default_mat, blocked);
+        if (out_first_id) *out_first_id = first;
+    });
+}
+
+dem_status dem_add_wall(dem_scene* s, int32_t axis, double position, int32_t sense, int32_t mat, int64_t* out_id)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        const int64_t id = w->add_wall(s->s, axis, position, sense, mat);
+        if (out_id) *out_id = id;
+    });
+}
+
+dem_status dem_pwave_dt(dem_scene* s, double* out)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        if (!out) dem::fail(DEM_EINVAL, "null out");
+        *out = w->pwave_dt(s->s);
+    });
+}
+
+dem_status dem_set_dt(dem_scene* s, double dt)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        if (!(dt > 0.0) || !std::isfinite(dt)) dem::fail(DEM_EINVAL, "dt must be > 0");
+        w->pull_scene_table();
+        w->scenes[s->s].p.dt = dt;
+        w->sp[s->s].dt = dt;
+        w->push_scene_table();
+        if (w->d_args.p) w->upload_args();
+    });
+}
+
+dem_status dem_set_velgrad(dem_scene* s, const double* velgrad9)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        if (!velgrad9) dem::fail(DEM_EINVAL, "null velgrad");
+        if (!w->scenes[s->s].p.periodic) dem::fail(DEM_EINVAL, "dem_set_velgrad: scene is not periodic");
+        w->pull_scene_table();
+        for (int k = 0; k < 9; ++k) {
+            w->scenes[s->s].p.velgrad[k] = velgrad9[k];
+            w->sp[s->s].L[k] = velgrad9[k];
+        }
+        w->push_scene_table();
+        if (w->d_args.p) w->upload_args();
+        w->need_rebuild = true;  // the Verlet budget of the mean field changes
+    });
+}
+
+dem_status dem_get_cell(dem_scene* s, double* hsize9, double* trsf9)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        w->pull_scene_table();
+        for (int k = 0; k < 9; ++k) {
+            if (hsize9) hsize9[k] = w->sp[s->s].H[k];
+            if (trsf9) trsf9[k] = w->sp[s->s].trsf[k];
+        }
+    });
+}
+
+dem_status dem_step(dem_scene* s, int64_t nsteps)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        if (!s->owner) dem::fail(DEM_EINVAL, "dem_step: step the batch, not one of its scenes");
+        for (const auto& S : w->scenes)
+            if (!(S.p.dt > 0.0)) dem::fail(DEM_EINVAL, "dem_step: dt is not set");
+        w->step(nsteps);
+    });
+}
+
+dem_status dem_get_state(dem_scene* s, int64_t first_id, int64_t count, double* pos3, double* vel3, double* angvel3,
+                         double* ori4, double* force3, double* torque3)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        w->get_state(s->s, first_id, count, pos3, vel3, angvel3, ori4, force3, torque3);
+    });
+}
+
+dem_status dem_get_state_device(dem_scene* s, int64_t first_id, int64_t count, double* pos3, double* vel3,
+                                double* angvel3, double* ori4)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        w->check_scene_id(s->s, first_id, count);
+        std::vector<double> p(pos3 ? 3 * count : 0), v(vel3 ? 3 * count : 0), a(angvel3 ? 3 * count : 0),
+            q(ori4 ? 4 * count : 0);
+        w->get_state(s->s, first_id, count, pos3 ? p.data() : nullptr, vel3 ? v.data() : nullptr,
+                     angvel3 ? a.data() : nullptr, ori4 ? q.data() : nullptr, nullptr, nullptr);
+        auto put = [&](double* dst, const std::vector<double>& src) {
+            if (dst && !src.empty())
+                HIPC(hipMemcpyAsync(dst, src.data(), 8 * src.size(), hipMemcpyHostToDevice, w->stream));
+        };
+        put(pos3, p);
+        put(vel3, v);
+        put(angvel3, a);
+        put(ori4, q);
+        HIPC(hipStreamSynchronize(w->stream));
+    });
+}
+
+dem_status dem_set_state(dem_scene* s, const double* pos3, const double* vel3, const double* angvel3,
+                         const double* ori4)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        w->set_state(s->s, pos3, vel3, angvel3, ori4);
+    });
+}
+
+dem_status dem_get_mass(dem_scene* s, double* mass, double* inertia)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        const auto& S = w->scenes[s->s];
+        for (size_t i = 0; i < S.gids.size(); ++i) {
+            const auto& b = w->bodies[S.gids[i]];
+            if (mass) mass[i] = b.kind ? 0.0 : b.m;
+            if (inertia) inertia[i] = b.kind ? 0.0 : 2.0 * b.m * b.r * b.r / 5.0;
+        }
+    });
+}
+
+dem_status dem_get_contacts(dem_scene* s, int64_t capacity, dem_contact* out, int64_t* out_count)
+{
+    dem_status rc = DEM_OK;
+    dem_status g = guarded([&] {
+        dem::World* w = world_of(s);
+        if (!out_count) dem::fail(DEM_EINVAL, "null out_count");
+        std::vector<dem_contact> c = w->contacts(s->s);
+        *out_count = (int64_t)c.size();
+        if (capacity < (int64_t)c.size()) {
+            rc = DEM_ECAPACITY;
+            return;
+        }
+        if (!c.empty()) {
+            if (!out) dem::fail(DEM_EINVAL, "null out");
+            std::memcpy(out, c.data(), sizeof(dem_contact) * c.size());
+        }
+    });
+    if (g == DEM_OK && rc != DEM_OK) dem::g_err = "dem_get_contacts: buffer too small";
+    return g != DEM_OK ? g : rc;
+}
+
+dem_status dem_get_history(dem_scene* s, int64_t capacity, dem_history* out, int64_t* out_count)
+{
+    dem_status rc = DEM_OK;
+    dem_status g = guarded([&] {
+        dem::World* w = world_of(s);
+        if (!out_count) dem::fail(DEM_EINVAL, "null out_count");
+        std::vector<dem_contact> c = w->contacts(s->s);
+        *out_count = (int64_t)c.size();
+        if (capacity < (int64_t)c.size()) {
+            rc = DEM_ECAPACITY;
+            return;
+        }
+        for (size_t i = 0; i < c.size(); ++i) {
+            dem_history h;
+            std::memset(&h, 0, sizeof h);
+            h.id1 = c[i].id1;
+            h.id2 = c[i].id2;
+            for (int q = 0; q < 3; ++q) {
+                h.cell[q] = c[i].cell[q];
+                h.fs[q] = c[i].fs[q];
+                h.nprev[q] = c[i].normal[q];
+            }
+            out[i] = h;
+        }
+    });
+    if (g == DEM_OK && rc != DEM_OK) dem::g_err = "dem_get_history: buffer too small";
+    return g != DEM_OK ? g : rc;
+}
+
+dem_status dem_set_history(dem_scene* s, int64_t n, const dem_history* in)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        w->set_history(s->s, n, in);
+    });
+}
+
+dem_status dem_get_energy(dem_scene* s, dem_energy* out)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        if (!out) dem::fail(DEM_EINVAL, "null out");
+        if (w->scenes.size() > 1) dem::fail(DEM_EINVAL, "dem_get_energy: energies are tracked per world, not per batch scene");
+        w->read_counters();
+        const dem::Counters& c = *w->h_ctr;
+        out->kinetic = c.e_kin;
+        out->kin_rot = c.e_rot;
+        out->elastic = c.e_el;
+        out->grav_work = c.e_grav;
+        out->damp_dissip = c.e_damp;
+        out->plastic_dissip = c.e_plast;
+        out->total = ((((c.e_kin + c.e_rot) + c.e_el) + c.e_grav) + c.e_damp) + c.e_plast;
+    });
+}
+
+static void fill_stats(dem::World* w, int s, dem_stats* out)
+{
+    w->read_counters();
+    const dem::Counters& c = *w->h_ctr;
+    std::memset(out, 0, sizeof *out);
+    int64_t nsph = 0, nw = 0;
+    if (s >= 0) {
+        out->iter = w->scenes[s].iter;
+        out->time = w->scenes[s].time;
+        nsph = w->scenes[s].n_spheres;
+        nw = w->scenes[s].n_walls;
+        out->verlet_dist = w->scenes[s].verlet;
+    } else {
+        out->iter = w->scenes[0].iter;
+        out->time = w->scenes[0].time;
+        for (const auto& S : w->scenes) {
+            nsph += S.n_spheres;
+            nw += S.n_walls;
+        }
+        out->verlet_dist = w->scenes[0].verlet;
+    }
+    out->n_spheres = nsph;
+    out->n_walls = nw;
+    out->n_contacts_ss = (int64_t)c.last_ss;
+    out->n_contacts_sw = (int64_t)c.last_sw;
+    out->n_candidates = w->n_candidates;
+    out->rebuilds = w->rebuilds;
+    out->contact_steps = (int64_t)c.contact_steps;
+    out->coordination = nsph ? 2.0 * (double)c.last_ss / (double)nsph : 0.0;
+}
+
+dem_status dem_get_stats(dem_scene* s, dem_stats* out)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        if (!out) dem::fail(DEM_EINVAL, "null out");
+        fill_stats(w, w->scenes.size() > 1 ? -1 : s->s, out);
+        if (w->scenes.size() > 1) {
+            out->iter = w->scenes[s->s].iter;
+            out->time = w->scenes[s->s].time;
+        }
+    });
+}
+
+dem_status dem_set_timing(dem_scene* s, int32_t on)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        w->timing = on != 0;
+        w->invalidate_graphs();
+    });
+}
+
+dem_status dem_get_timing(dem_scene* s, const char* name, double* avg_ms, int64_t* launches)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        if (!name) dem::fail(DEM_EINVAL, "null name");
+        auto it = w->timers.find(name);
+        const double tot = it == w->timers.end() ? 0.0 : it->second.total_ms;
+        const int64_t n = it == w->timers.end() ? 0 : it->second.launches;
+        if (avg_ms) *avg_ms = n ? tot / (double)n : 0.0;
+        if (launches) *launches = n;
+    });
+}
+
+dem_status dem_batch_create(int32_t n_scenes, const dem_params* per_scene, dem_batch** out)
+{
+    return guarded([&] {
+        if (n_scenes < 1 || n_scenes > 65535 || !per_scene || !out) dem::fail(DEM_EINVAL, "dem_batch_create: bad arguments");
+        for (int i = 0; i < n_scenes; ++i) {
+            check_params(&per_scene[i]);
+            if (per_scene[i].periodic) dem::fail(DEM_EINVAL, "dem_batch_create: periodic scenes cannot be batched");
+        }
+        std::unique_ptr<dem::World> w(new dem::World());
+        w->init(n_scenes, per_scene);
+        dem_batch* b = new dem_batch;
+        b->w = w.release();
+        b->views.resize(n_scenes);
+        for (int i = 0; i < n_scenes; ++i) b->views[i] = dem_scene{b->w, i, false};
+        *out = b;
+    });
+}
+
+dem_status dem_batch_scene(dem_batch* b, int32_t i, dem_scene** view)
+{
+    return guarded([&] {
+        if (!b || !view) dem::fail(DEM_EINVAL, "null argument");
+        if (i < 0 || i >= (int32_t)b->views.size()) dem::fail(DEM_ERANGE, "scene index out of range");
+        *view = &b->views[i];
+    });
+}
+
+dem_status dem_batch_step(dem_batch* b, int64_t nsteps)
+{
+    return guarded([&] {
+        if (!b) dem::fail(DEM_EINVAL, "null batch");
+        HIPC(hipSetDevice(b->w->device));
+        for (const auto& S : b->w->scenes)
+            if (!(S.p.dt > 0.0)) dem::fail(DEM_EINVAL, "dem_batch_step: dt is not set");
+        b->w->step(nsteps);
+    });
+}
+
+dem_status dem_batch_stats(dem_batch* b, dem_stats* out)
+{
+    return guarded([&] {
+        if (!b || !out) dem::fail(DEM_EINVAL, "null argument");
+        HIPC(hipSetDevice(b->w->device));
+        fill_stats(b->w, -1, out);
+    });
+}
+
+dem_status dem_batch_destroy(dem_batch* b)
+{
+    return guarded([&] {
+        if (!b) dem::fail(DEM_EINVAL, "null batch");
+        (void)hipSetDevice(b->w->device);
+        delete b->w;
+        delete b;
+    });
+}
+
+}  // extern "C"
