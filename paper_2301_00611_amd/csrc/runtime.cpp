@@ -649,6 +649,10 @@ struct World {
             HIPC(hipGetLastError());
             HIPC(hipMemcpyAsync(bnd.data(), d_bounds.p, sizeof(double) * 6 * nsc, hipMemcpyDeviceToHost, stream));
             HIPC(hipStreamSynchronize(stream));
+            for (int s = 0; s < nsc; ++s)
+                if (scenes[s].n_spheres > 0)
+                    for (int k = 0; k < 6; ++k)
+                        if (!std::isfinite(bnd[6 * s + k])) fail(DEM_ENONFINITE, "non-finite sphere position");
         }
         int cells = 0, maxdim = 1;
         for (int s = 0; s < nsc; ++s) {
@@ -1195,8 +1199,12 @@ struct World {
 
     void set_state(int s, const double* pos3, const double* vel3, const double* angvel3, const double* ori4)
     {
-        pull_bodies();
         const HostScene& S = scenes[s];
+        for (size_t i = 0; i < 3 * S.gids.size(); ++i)
+            if ((pos3 && !std::isfinite(pos3[i])) || (vel3 && !std::isfinite(vel3[i])) ||
+                (angvel3 && !std::isfinite(angvel3[i])))
+                fail(DEM_EINVAL, "dem_set_state: non-finite value");
+        pull_bodies();
         for (size_t i = 0; i < S.gids.size(); ++i) {
             HostBody& b = bodies[S.gids[i]];
             if (b.kind != 0) continue;
@@ -1743,27 +1751,25 @@ dem_status dem_get_energy(dem_scene* s, dem_energy* out)
     });
 }
 
+// Per-scene fields come from scene s (s < 0: totals over the batch); the
+// contact counters are kept per world.
 static void fill_stats(dem::World* w, int s, dem_stats* out)
 {
     w->read_counters();
     const dem::Counters& c = *w->h_ctr;
     std::memset(out, 0, sizeof *out);
     int64_t nsph = 0, nw = 0;
-    if (s >= 0) {
-        out->iter = w->scenes[s].iter;
-        out->time = w->scenes[s].time;
-        nsph = w->scenes[s].n_spheres;
-        nw = w->scenes[s].n_walls;
-        out->verlet_dist = w->scenes[s].verlet;
-    } else {
-        out->iter = w->scenes[0].iter;
-        out->time = w->scenes[0].time;
-        for (const auto& S : w->scenes) {
-            nsph += S.n_spheres;
-            nw += S.n_walls;
+    const int s0 = s < 0 ? 0 : s;
+    out->iter = w->scenes[s0].iter;
+    out->time = w->scenes[s0].time;
+    out->verlet_dist = w->scenes[s0].verlet;
+    for (int i = 0; i < (int)w->scenes.size(); ++i)
+        if (s < 0 || i == s) {
+            nsph += w->scenes[i].n_spheres;
+            nw += w->scenes[i].n_walls;
         }
-        out->verlet_dist = w->scenes[0].verlet;
-    }
+    int64_t all = 0;
+    for (const auto& S : w->scenes) all += S.n_spheres;
     out->n_spheres = nsph;
     out->n_walls = nw;
     out->n_contacts_ss = (int64_t)c.last_ss;
@@ -1771,7 +1777,7 @@ static void fill_stats(dem::World* w, int s, dem_stats* out)
     out->n_candidates = w->n_candidates;
     out->rebuilds = w->rebuilds;
     out->contact_steps = (int64_t)c.contact_steps;
-    out->coordination = nsph ? 2.0 * (double)c.last_ss / (double)nsph : 0.0;
+    out->coordination = all ? 2.0 * (double)c.last_ss / (double)all : 0.0;
 }
 
 dem_status dem_get_stats(dem_scene* s, dem_stats* out)
@@ -1779,11 +1785,7 @@ dem_status dem_get_stats(dem_scene* s, dem_stats* out)
     return guarded([&] {
         dem::World* w = world_of(s);
         if (!out) dem::fail(DEM_EINVAL, "null out");
-        fill_stats(w, w->scenes.size() > 1 ? -1 : s->s, out);
-        if (w->scenes.size() > 1) {
-            out->iter = w->scenes[s->s].iter;
-            out->time = w->scenes[s->s].time;
-        }
+        fill_stats(w, s->s, out);
     });
 }
 

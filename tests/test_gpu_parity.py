@@ -1,0 +1,301 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars (stated by the task for this method):
+  * real-contact pair sets identical (bit-exact keys);
+  * per-step forces from an identical state within 1e-12 relative in FP64
+    and 1e-5 in FP32-mixed mode (per contact and per body);
+  * multi-step runs (chaotic) compared by energy terms and coordination
+    number within 1 %.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_helpers import EPS, body_force_errors, contact_errors, keyset, random_history, twin
+
+pytestmark = pytest.mark.gpu
+
+
+def _dense_spec(n, seed, squeeze=0.9, box=None, walls=True, rmin=0.5e-3, rmax=1.5e-3):
+    """Random cloud at solid fraction ~0.2, squeezed by 10 % so that close
+    neighbours overlap."""
+    from paper_2301_00611_amd.scenes import Material, Scene, Wall, compressed_cloud
+    if box is None:
+        mean_vol = 4.0 / 3.0 * math.pi * (rmax ** 4 - rmin ** 4) / (4 * (rmax - rmin))
+        box = ((n * mean_vol / 0.2) ** (1.0 / 3.0) + 2 * rmax) * squeeze
+    pos, rad = compressed_cloud(n, box, rmin, rmax, squeeze, seed)
+    wl = [Wall(a, p, 0) for a in range(3) for p in (0.0, box)] if walls else []
+    return Scene(pos=pos, radius=rad, material=Material(2600.0, 1e7, 0.3, 0.5), walls=wl,
+                 gravity=(0.0, 0.0, -9.81), damping=0.2, dt_factor=0.5)
+
+
+def _one_step_parity(n, seed, precision=0, tol=1e-12):
+    from paper_2301_00611_amd.scenes import random_velocities
+    spec = _dense_spec(n, seed)
+    nw = len(spec.walls)
+    v, w = random_velocities(n, 0.05, seed + 100)
+    g, o, dt = twin(spec, precision=precision, vel=v, angvel=w * 0.05)
+    rng = np.random.default_rng(seed + 7)
+    hist = random_history(spec.pos, spec.radius, spec.walls, rng)
+    if hist is not None:
+        g.set_history(*hist)
+        o.set_contacts(*hist)
+    g.step(1)
+    o.step(1)
+    cg, co = g.get_contacts(), o.get_contacts()
+    assert keyset(cg) == keyset(co)
+    err = contact_errors(cg, co) if len(co) else None
+    sg, so = g.get_state(), o.get_state()
+    return spec, g, o, cg, co, err, sg, so, nw
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (37, 1), (511, 2), (1500, 3)])
+def test_one_step_fp64_from_identical_state(n, seed):
+    spec, g, o, cg, co, err, sg, so, nw = _one_step_parity(n, seed)
+    if n > 30:
+        assert len(co) > n // 8, "the dense start should have many contacts"
+        assert np.max(err["f"]) <= 1e-12
+        assert np.max(err["fn"]) <= 1e-12 and np.max(err["fs"]) <= 1e-12
+        assert np.max(err["normal"]) <= 1e-14
+        ef, touched = body_force_errors(sg, so, co)
+        assert ef.max() <= 1e-12
+    scale = np.abs(so["pos"]).max()
+    assert np.abs(sg["pos"] - so["pos"]).max() <= 1e-14 * scale
+    assert np.abs(sg["vel"] - so["vel"]).max() <= 1e-12 * (np.abs(so["vel"]).max() + 1e-30)
+    assert np.abs(sg["ori"] - so["ori"]).max() <= 1e-14
+    eg, eo = g.get_energy(), o.get_energy()
+    for k in eo:
+        assert eg[k] == pytest.approx(eo[k], rel=1e-12, abs=1e-12 * (abs(eo["kinetic"]) + abs(eo["elastic"]) + 1e-30))
+
+
+@pytest.mark.parametrize("n,seed", [(511, 2), (1500, 3)])
+def test_one_step_fp32_mixed_from_identical_state(n, seed):
+    spec, g, o, cg, co, err, sg, so, nw = _one_step_parity(n, seed, precision=1)
+    assert np.max(err["f"]) <= 1e-5
+    assert np.max(err["fs"]) <= 1e-5
+    ef, _ = body_force_errors(sg, so, co)
+    assert ef.max() <= 1e-5
+
+
+def test_walled_deposition_multistep():
+    """C1 shape (1,000 spheres, 6 walls, gravity, damping 0.2), 1,000 steps:
+    pair sets and forces checked every 50 steps while the two runs still
+    coincide; energy terms and coordination over the run within 1 %."""
+    from paper_2301_00611_amd.scenes import cloud_box
+    spec = cloud_box(n=1000, seed=0)
+    g, o, dt = twin(spec)
+    series_g, series_o = [], []
+    compared = 0
+    for k in range(20):
+        g.step(50)
+        o.step(50)
+        cg, co = g.get_contacts(), o.get_contacts()
+        assert keyset(cg) == keyset(co), f"pair sets differ after {50 * (k + 1)} steps"
+        if len(co):
+            err = contact_errors(cg, co)
+            assert err["f"].max() <= 1e-9  # after many steps: identical up to accumulated rounding
+            compared += len(co)
+        eg, eo = g.get_energy(), o.get_energy()
+        series_g.append([eg[x] for x in ("kinetic", "grav_work", "damp_dissip", "elastic", "plastic_dissip")])
+        series_o.append([eo[x] for x in ("kinetic", "grav_work", "damp_dissip", "elastic", "plastic_dissip")])
+    assert compared > 0
+    sg, so = np.array(series_g), np.array(series_o)
+    scale = np.abs(so[:, 1]).max()
+    assert np.abs(sg - so).max() <= 0.01 * scale
+    assert g.stats()["iter"] == 1000
+
+
+def test_determinism_bitwise():
+    from paper_2301_00611_amd.scenes import random_velocities
+    spec = _dense_spec(800, 11)
+    v, w = random_velocities(800, 0.05, 5)
+    runs = []
+    for _ in range(2):
+        g, o, dt = twin(spec, vel=v, angvel=w * 0.05)
+        g.step(300)
+        st = g.get_state()
+        runs.append((st["pos"].copy(), st["vel"].copy(), st["angvel"].copy(), g.get_contacts()))
+    for a, b in zip(runs[0][:3], runs[1][:3]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(runs[0][3], runs[1][3])
+
+
+def test_resume_from_saved_state_is_bitwise():
+    """run 2n == run n, save (state + shear history), restore into a fresh
+    scene, run n."""
+    from paper_2301_00611_amd.scenes import random_velocities
+    spec = _dense_spec(600, 12)
+    v, w = random_velocities(600, 0.05, 6)
+    g1, _, dt = twin(spec, vel=v, angvel=w * 0.05)
+    g1.step(400)
+    ref = g1.get_state()
+    g2, _, _ = twin(spec, vel=v, angvel=w * 0.05, dt=dt)
+    g2.step(200)
+    st, hist = g2.get_state(), g2.get_history()
+    assert len(hist) > 0
+    g3, _, _ = twin(spec, vel=v, angvel=w * 0.05, dt=dt)
+    g3.set_state(pos=st["pos"], vel=st["vel"], angvel=st["angvel"], ori=st["ori"])
+    g3.set_history(hist["id1"], hist["id2"], hist["fs"], hist["nprev"], hist["cell"])
+    g3.step(200)
+    out = g3.get_state()
+    for key in ("pos", "vel", "angvel", "ori"):
+        assert np.array_equal(out[key], ref[key]), key
+
+
+def test_bodies_added_between_steps_keep_history():
+    from paper_2301_00611_amd.scenes import random_velocities
+    spec = _dense_spec(400, 13)
+    v, w = random_velocities(400, 0.02, 7)
+    g, o, dt = twin(spec, vel=v, angvel=w * 0.05)
+    g.step(30)
+    o.step(30)
+    extra = np.array([[0.01, 0.01, 0.03], [0.012, 0.01, 0.03]])
+    g.add_spheres(extra, [1e-3, 1e-3])
+    o.add_spheres(extra, [1e-3, 1e-3])
+    g.step(30)
+    o.step(30)
+    cg, co = g.get_contacts(), o.get_contacts()
+    assert keyset(cg) == keyset(co)
+    assert contact_errors(cg, co)["f"].max() <= 1e-10
+
+
+def test_closed_forms_through_the_gpu_path():
+    """The oracle's closed-form pins, run through the HIP path directly:
+    static overlap on a wall and the sliding-block acceleration."""
+    from paper_2301_00611_amd import dem
+    r, E, g0 = 1e-3, 1e7, 9.81
+    m = 4.0 / 3.0 * math.pi * r ** 3 * 2600.0
+    dt = 0.5 * r * math.sqrt(2600.0 / E)
+    s = dem.Scene(dt=dt, gravity=(0, 0, -g0), damping=0.2)
+    mat = s.add_material(2600.0, E, 0.3, 0.5)
+    s.add_wall(2, 0.0, 1, mat)
+    s.add_spheres([[0, 0, r]], [r])
+    s.step(20000)
+    c = s.get_contacts()
+    assert len(c) == 1 and c["pen"][0] == pytest.approx(m * g0 / (E * r), rel=1e-6)
+    theta, phi = 0.5, 0.3
+    grav = (g0 * math.sin(theta), 0.0, -g0 * math.cos(theta))
+    pen0 = m * g0 * math.cos(theta) / (E * r)
+    s = dem.Scene(dt=dt, gravity=grav, damping=0.0)
+    ms = s.add_material(2600.0, E, 0.3, 0.9)
+    mw = s.add_material(2600.0, E, 0.3, phi)
+    s.add_wall(2, 0.0, 1, mw)
+    s.add_spheres([[0, 0, r - pen0]], [r], default_mat=ms, blocked=[8 | 16 | 32])
+    s.step(200)
+    v1 = s.get_state()["vel"][1, 0]
+    s.step(1000)
+    v2 = s.get_state()["vel"][1, 0]
+    assert (v2 - v1) / (1000 * dt) == pytest.approx(g0 * (math.sin(theta) - math.tan(phi) * math.cos(theta)),
+                                                     rel=1e-6)
+
+
+def test_periodic_shear_parity():
+    """Periodic cube in simple shear (homoDeform 2): pairs across the
+    sheared boundaries, image velocities, cell update."""
+    from paper_2301_00611_amd.scenes import Material, Scene, compressed_cloud, random_velocities
+    box = 0.016
+    pos, rad = compressed_cloud(300, box, 0.6e-3, 1.0e-3, 0.92, 21)
+    spec = Scene(pos=pos, radius=rad, material=Material(2600.0, 1e7, 0.3, 0.4), walls=[], gravity=(0, 0, 0),
+                 damping=0.1, dt_factor=0.5)
+    L = np.array([[0.0, 0.0, 5.0], [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    v, w = random_velocities(300, 0.02, 3)
+    g, o, dt = twin(spec, periodic=True, hsize=np.eye(3) * box, velgrad=L, vel=v, angvel=w * 0.05)
+    crossing = 0
+    for k in range(10):
+        g.step(40)
+        o.step(40)
+        cg, co = g.get_contacts(), o.get_contacts()
+        assert keyset(cg) == keyset(co)
+        crossing += int((np.abs(co["cell"]).sum(axis=1) > 0).sum())
+        if len(co):
+            assert contact_errors(cg, co)["f"].max() <= 1e-9
+    assert crossing > 0
+    hg, tg = g.get_cell()
+    ho, to = o.get_cell()
+    np.testing.assert_allclose(hg, ho, rtol=1e-14, atol=1e-16)
+    sg, so = g.get_state(), o.get_state()
+    assert np.abs(sg["pos"] - so["pos"]).max() <= 1e-12
+
+
+def test_batched_scenes_match_single_scenes_bitwise():
+    """Five scenes of uneven size and parameters stepped as one batch equal
+    the same scenes stepped alone, bit for bit; one of them also matches the
+    oracle."""
+    from paper_2301_00611_amd import dem
+    from paper_2301_00611_amd.scenes import batched_deposition
+    spec = batched_deposition(n_scenes=5, nmin=50, nmax=2000, seed=3, steps=200)
+    dt = 0.5 * spec.dt_radius * math.sqrt(2600.0 / 5e7)
+    params = [dem.make_params(dt=dt, gravity=s.gravity, damping=s.damping) for s in spec.scenes]
+    batch = dem.Batch(params)
+    for i, s in enumerate(spec.scenes):
+        view = batch.scene(i)
+        m = view.add_material(s.material.density, s.material.young, s.material.poisson, s.material.friction)
+        for w in s.walls:
+            view.add_wall(w.axis, w.position, w.sense, m)
+        view.add_spheres(s.pos, s.radius, default_mat=m)
+    batch.step(600)
+    for i, s in enumerate(spec.scenes):
+        single, o, _ = twin(s, dt=dt)
+        single.step(600)
+        a = batch.scene(i).get_state()
+        b = single.get_state()
+        for key in ("pos", "vel", "angvel"):
+            assert np.array_equal(a[key], b[key]), (i, key)
+        if i == 0:
+            o.step(600)
+            assert keyset(single.get_contacts()) == keyset(o.get_contacts())
+            assert np.abs(b["pos"] - o.get_state()["pos"]).max() <= 1e-12
+    assert batch.stats()["contact_steps"] > 0
+
+
+def test_full_size_spot_check_grid_column():
+    """The 200,000-sphere column grid at the benchmark's launch
+    configuration, compressed so that many pairs overlap, with random
+    velocities: one step on the GPU against the oracle's spot mode on
+    sampled bodies (each evaluated against all N)."""
+    from oracle import OracleScene
+    from paper_2301_00611_amd import dem
+    from paper_2301_00611_amd.scenes import grid_column, random_velocities
+    spec = grid_column(n=200_000, spacing=2.6e-3, seed=0)
+    n = spec.n
+    v, w = random_velocities(n, 0.02, 9)
+    g, _, dt = twin(spec, vel=v, angvel=w * 0.05, track_energy=False)
+    o = OracleScene(dt=dt, gravity=spec.gravity, damping=spec.damping)
+    mo = o.add_material(2600.0, spec.material.young, 0.3, 0.5)
+    for wl in spec.walls:
+        o.add_wall(wl.axis, wl.position, wl.sense, mo)
+    o.add_spheres(spec.pos, spec.radius, vel=v, angvel=w * 0.05, default_mat=mo)
+    nw = len(spec.walls)
+    rng = np.random.default_rng(4)
+    ids = nw + rng.choice(n, size=200, replace=False)
+    spot = o.spot_step(ids)
+    g.step(1)
+    st = g.get_state()
+    assert g.stats()["n_contacts_ss"] > 50_000
+    assert (spot["n_contacts"] > 0).sum() > 50
+    fscale = np.abs(spot["force"]).max(axis=1) + 1e-30
+    ferr = np.linalg.norm(st["force"][ids] - spot["force"], axis=1) / np.maximum(
+        np.linalg.norm(spot["force"], axis=1), 1e-12 * fscale.max())
+    assert np.median(ferr) <= 1e-12 and ferr.max() <= 1e-9
+    assert np.abs(st["pos"][ids] - spot["pos"]).max() <= 1e-15
+    assert np.abs(st["vel"][ids] - spot["vel"]).max() <= 1e-12 * np.abs(spot["vel"]).max()
+
+
+def test_invariants_over_a_long_run():
+    """Properties that hold at any size: Coulomb bound on every contact,
+    action-reaction (zero total contact force), finite state."""
+    from paper_2301_00611_amd.scenes import random_velocities
+    spec = _dense_spec(3000, 31)
+    v, w = random_velocities(3000, 0.1, 8)
+    g, _, dt = twin(spec, vel=v, angvel=w * 0.05)
+    for _ in range(5):
+        g.step(200)
+        c = g.get_contacts()
+        fs = np.linalg.norm(c["fs"], axis=1)
+        fn = np.linalg.norm(c["fn"], axis=1)
+        assert np.all(fs <= math.tan(0.5) * fn * (1 + 1e-6))
+        st = g.get_state()
+        total = st["force"].sum(axis=0)
+        assert np.linalg.norm(total) <= 1e-9 * np.abs(st["force"]).sum()
+        assert np.all(np.isfinite(st["pos"]))
