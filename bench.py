@@ -1,0 +1,253 @@
+#!/usr/bin/env python3
+"""Benchmark: one DEM timestep over spheres and walls on one MI355X.
+
+Workload (N=1): 200,000 spheres, radius U(0.5, 1.5) mm, jittered column grid
+(spacing 3.03 mm, 33 x 33 columns) falling onto a floor inside four side
+walls, E = 5e7 Pa, nu = 0.3, friction 0.5 rad, damping 0.2, gravity -9.81,
+dt = 0.5 x P-wave step, FP64.  A "step" is one pass of the whole path:
+broad phase when the Verlet budget is spent, contact kernel, ordered force
+sum + Newton.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra]
+
+Warm-up runs W steps on a throwaway scene of the same configuration; then a
+fresh scene is timed for exactly K steps from its initial state (default
+K = 10,000, the configuration's length).  Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+
+# Algorithmic bytes (what the method must move, FP64):
+#   integrate kernel, per body: read x, v, w, q, r, m (14 doubles) + material
+#   and blocked bytes = 114 B; write x, v, w, q (13 doubles) = 104 B.
+#   contact kernel: per body gathered once x, v, w, r = 80 B; per real
+#   contact ids 8 + shear force r/w 48 + previous normal r/w 48 = 104 B; per
+#   non-real candidate its ids, 8 B.
+INTEGRATE_BYTES_PER_BODY = 218
+CONTACT_BYTES_PER_BODY = 80
+CONTACT_BYTES_PER_REAL = 104
+CONTACT_BYTES_PER_CANDIDATE = 8
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the kernel's source changed since it was taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "traffic_grid_column_200k.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(rf"traffic_bytes_per_launch {kernel} (\d+) source_sha256_16 (\w+)", open(path).read())
+    if not m:
+        return None
+    csrc = os.path.join(ROOT, "paper_2301_00611_amd", "csrc")
+    src = kernel.replace("k_", "") + ".hip"
+    blob = open(os.path.join(csrc, src), "rb").read() + open(os.path.join(csrc, "dem_internal.hpp"), "rb").read()
+    if hashlib.sha256(blob).hexdigest()[:16] != m.group(2):
+        return None
+    return float(m.group(1))
+
+
+def build_scene(spec, precision=0, timing=False):
+    from paper_2301_00611_amd import dem
+    m = spec.material
+    s = dem.Scene(gravity=spec.gravity, damping=spec.damping, precision=precision)
+    mat = s.add_material(m.density, m.young, m.poisson, m.friction)
+    for w in spec.walls:
+        s.add_wall(w.axis, w.position, w.sense, mat)
+    s.add_spheres(spec.pos, spec.radius, default_mat=mat)
+    s.set_dt(spec.dt_factor * s.pwave_dt())
+    s.set_timing(timing)
+    return s
+
+
+def timed_run(spec, steps, warmup, precision=0, timing=False):
+    """Warm up on a throwaway scene, then time exactly `steps` steps of a
+    fresh scene from its initial state.  With timing=True every contact and
+    integrate launch is bracketed by HIP events (graph event nodes)."""
+    import torch
+    if warmup > 0:
+        w = build_scene(spec, precision, timing=timing)
+        w.step(warmup)
+        w.close()
+    s = build_scene(spec, precision, timing=timing)
+    s.step(0)
+    st0 = s.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st1 = s.stats()
+    kern = {}
+    for name in ("contact", "integrate", "rebuild"):
+        ms, n = s.get_timing(name)
+        kern[name] = {"avg_ms": ms, "launches": n}
+    s.close()
+    return {
+        "seconds": t1 - t0,
+        "contact_steps": st1["contact_steps"] - st0["contact_steps"],
+        "rebuilds": st1["rebuilds"] - st0["rebuilds"],
+        "candidates": st1["n_candidates"],
+        "contacts_last": st1["n_contacts_ss"] + st1["n_contacts_sw"],
+        "kernels": kern,
+    }
+
+
+def cpu_baseline(spec_full, budget_s=15.0):
+    """The FP64 oracle, single thread, on a bounded sample of the same
+    workload: the bottom 10,000 spheres of the same column (same generator,
+    same walls), stepped until about `budget_s` seconds of CPU time."""
+    from oracle import OracleScene
+    from paper_2301_00611_amd.scenes import grid_column
+    n_sample = 10_000
+    sp = grid_column(n=n_sample, seed=0)
+    dt = 0.5 * sp.radius.min() * math.sqrt(sp.material.density / sp.material.young)
+    o = OracleScene(dt=dt, gravity=sp.gravity, damping=sp.damping)
+    m = o.add_material(sp.material.density, sp.material.young, sp.material.poisson, sp.material.friction)
+    for w in sp.walls:
+        o.add_wall(w.axis, w.position, w.sense, m)
+    o.add_spheres(sp.pos, sp.radius, default_mat=m)
+    steps, contacts = 0, 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        o.step(1)
+        steps += 1
+        contacts += len(o.get_contacts())
+    t = time.perf_counter() - t0
+    per_step = t / steps
+    n_full = spec_full.n
+    return {
+        "value": contacts / t,
+        "unit": "contact-steps/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"bottom {n_sample} spheres of the same column (+5 walls), {steps} steps from the initial "
+                   f"state, {t:.1f} s; O(N^2) pairs: {per_step * 1e3:.1f} ms/step, "
+                   f"{n_sample * steps / t:.3g} body-steps/s, extrapolated {per_step * (n_full / n_sample) ** 2:.1f} "
+                   f"s/step at {n_full} spheres"),
+        "body_steps_per_s": n_sample * steps / t,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10_000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--no-extra", action="store_true", help="skip the FP32-mixed, batched and CPU legs")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU decomposition is a design note only)", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2301_00611_amd.scenes import grid_column
+    spec = grid_column(n=200_000, seed=0)
+    log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)
+    log(f"FP64 leg: {spec.n} spheres, {args.steps} steps")
+    r64 = timed_run(spec, args.steps, args.warmup, precision=0)
+    log(f"FP64 leg done in {r64['seconds']:.2f} s; kernel-timing pass")
+    # same workload again with HIP events around every contact / integrate
+    # launch: per-kernel durations for the roofline
+    rt = timed_run(spec, args.steps, 0, precision=0, timing=True)
+    secs = r64["seconds"]
+    value = r64["contact_steps"] / secs
+    kern = rt["kernels"]
+    # dominant kernel by total device time
+    tot = {k: v["avg_ms"] * v["launches"] for k, v in kern.items() if k != "rebuild"}
+    dom = max(tot, key=tot.get)
+    n = spec.n
+    if dom == "integrate":
+        alg_bytes = INTEGRATE_BYTES_PER_BODY * n
+    else:
+        c_real = r64["contact_steps"] / max(args.steps, 1)
+        cand = r64["candidates"]
+        alg_bytes = (CONTACT_BYTES_PER_BODY * n + CONTACT_BYTES_PER_REAL * c_real
+                     + CONTACT_BYTES_PER_CANDIDATE * max(cand - c_real, 0))
+    avg_s = kern[dom]["avg_ms"] * 1e-3
+    achieved = alg_bytes / avg_s / 1e9 if avg_s > 0 else 0.0
+    out = {
+        "metric": "contact-steps/s",
+        "value": value,
+        "unit": "contact-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": secs / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "grid_column deposition: 200,000 spheres r~U(0.5,1.5) mm, 0.1x0.1 m box with floor, "
+                               "E=5e7, nu=0.3, phi=0.5, damping 0.2, dt=0.5*P-wave",
+                   "n_spheres": n, "n_walls": len(spec.walls), "parallelism": "1 GPU"},
+        "body_steps_per_s": n * args.steps / secs,
+        "rebuilds": r64["rebuilds"],
+        "kernels_ms": {k: v["avg_ms"] for k, v in kern.items()},
+        "timing_pass_ms_per_step": rt["seconds"] / args.steps * 1e3,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic("k_" + dom),
+                     "algorithmic_bytes_per_launch": alg_bytes},
+    }
+    if not args.no_extra:
+        log("FP32-mixed leg")
+        r32 = timed_run(spec, args.steps, args.warmup, precision=1)
+        log("batched leg")
+        out["fp32_mixed"] = {"value": r32["contact_steps"] / r32["seconds"], "unit": "contact-steps/s",
+                             "ms_per_step": r32["seconds"] / args.steps * 1e3}
+        out["batched"] = batched_leg()
+    if not args.no_cpu and not args.no_extra:
+        log("CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(spec)
+    print(json.dumps(out), flush=True)
+
+
+def batched_leg(n_scenes=512, steps=2000):
+    """C4: 512 independent deposition scenes (log-uniform sizes 500..50,000,
+    per-scene friction and damping) stepped together; scenes.steps/s."""
+    import torch
+    from paper_2301_00611_amd import dem
+    from paper_2301_00611_amd.scenes import batched_deposition
+    spec = batched_deposition(n_scenes=n_scenes, steps=steps)
+    dt = 0.5 * spec.dt_radius * math.sqrt(2600.0 / 5e7)
+    params = [dem.make_params(dt=dt, gravity=s.gravity, damping=s.damping) for s in spec.scenes]
+    b = dem.Batch(params)
+    nbodies = 0
+    for i, s in enumerate(spec.scenes):
+        v = b.scene(i)
+        m = v.add_material(s.material.density, s.material.young, s.material.poisson, s.material.friction)
+        for w in s.walls:
+            v.add_wall(w.axis, w.position, w.sense, m)
+        v.add_spheres(s.pos, s.radius, default_mat=m)
+        nbodies += s.n
+    b.step(1)
+    c0 = b.stats()["contact_steps"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    st = b.stats()
+    st["contact_steps"] -= c0
+    b.close()
+    return {"value": n_scenes * steps / t, "unit": "scene-steps/s", "n_scenes": n_scenes, "n_spheres": nbodies,
+            "steps": steps, "seconds": t, "body_steps_per_s": nbodies * steps / t,
+            "contact_steps_per_s": st["contact_steps"] / t if st["contact_steps"] else 0.0}
+
+
+if __name__ == "__main__":
+    main()

@@ -130,6 +130,63 @@ __global__ void __launch_bounds__(kBlock) k_bounds(Bodies b, int nslots, int bat
     }
 }
 
+// Single scene: block maxima of the six ordered values, then one block
+// combines them (no contended atomics).
+__global__ void __launch_bounds__(kBlock) k_bounds_block(Bodies b, int nslots, unsigned long long* __restrict__ part)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long v[6] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
+    if (i < nslots) {
+        v[0] = ~ord_bits(b.x[i]);
+        v[1] = ~ord_bits(b.y[i]);
+        v[2] = ~ord_bits(b.z[i]);
+        v[3] = ord_bits(b.x[i]);
+        v[4] = ord_bits(b.y[i]);
+        v[5] = ord_bits(b.z[i]);
+    }
+    for (int k = 0; k < 6; ++k)
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long o = __shfl_xor(v[k], off, 64);
+            v[k] = o > v[k] ? o : v[k];
+        }
+    __shared__ unsigned long long s[kBlock / 64][6];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int k = 0; k < 6; ++k) s[wave][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        unsigned long long m = 0ull;
+        for (int w = 0; w < kBlock / 64; ++w) m = s[w][threadIdx.x] > m ? s[w][threadIdx.x] : m;
+        part[(long)blockIdx.x * 6 + threadIdx.x] = m;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_bounds_final(const unsigned long long* __restrict__ part, int nblk,
+                                                         unsigned long long* __restrict__ out)
+{
+    unsigned long long v[6] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+        for (int k = 0; k < 6; ++k) {
+            const unsigned long long o = part[(long)b * 6 + k];
+            v[k] = o > v[k] ? o : v[k];
+        }
+    for (int k = 0; k < 6; ++k)
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long o = __shfl_xor(v[k], off, 64);
+            v[k] = o > v[k] ? o : v[k];
+        }
+    __shared__ unsigned long long s[kBlock / 64][6];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int k = 0; k < 6; ++k) s[wave][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        unsigned long long m = 0ull;
+        for (int w = 0; w < kBlock / 64; ++w) m = s[w][threadIdx.x] > m ? s[w][threadIdx.x] : m;
+        out[threadIdx.x] = m;
+    }
+}
+
 __global__ void k_bounds_decode(unsigned long long* __restrict__ bits, double* __restrict__ out, int n6)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -189,6 +246,7 @@ __global__ void __launch_bounds__(kBlock) k_permute(Bodies src, Bodies dst, cons
     dst.id[i] = id;
     if (batched) dst.scene[i] = src.scene[o];
     if (periodic) dst.period[i] = src.period[o];
+    dst.disp[i] = 0.0;  // a fresh Verlet account after every broad-phase run
     slot_of_id[id] = i;
 }
 
@@ -425,20 +483,32 @@ __global__ void __launch_bounds__(kBlock) k_carry_over(PairBuildArgs a, int old_
     a.pr.nx[k] = nx;
     a.pr.ny[k] = ny;
     a.pr.nz[k] = nz;
+    // a carried normal is a unit vector: the pair touched at its last evaluation
+    a.pr.real[k] = (nx != 0.0 || ny != 0.0 || nz != 0.0) ? 1 : 0;
 }
 
 inline int nblocks(long n) { return (int)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
 
-void launch_bounds(const Bodies& b, const uint16_t* scene, int nslots, int nscenes, double* out6, hipStream_t st)
+size_t bounds_temp_bytes(int nslots) { return sizeof(unsigned long long) * 6 * (size_t)(nblocks(nslots) + 1); }
+
+void launch_bounds(const Bodies& b, int nslots, int nscenes, double* out6, void* temp, hipStream_t st)
 {
-    (void)scene;
-    // out6 doubles as the scratch for the ordered bits (same size)
+    // out6 doubles as the buffer of ordered bits (same size)
     unsigned long long* bits = reinterpret_cast<unsigned long long*>(out6);
     (void)hipMemsetAsync(bits, 0, sizeof(unsigned long long) * 6 * nscenes, st);
-    if (nslots > 0)
-        hipLaunchKernelGGL(k_bounds, dim3(nblocks(nslots)), dim3(kBlock), 0, st, b, nslots, nscenes > 1 ? 1 : 0, bits);
+    if (nslots > 0) {
+        if (nscenes == 1) {
+            unsigned long long* part = static_cast<unsigned long long*>(temp);
+            hipLaunchKernelGGL(k_bounds_block, dim3(nblocks(nslots)), dim3(kBlock), 0, st, b, nslots, part);
+            hipLaunchKernelGGL(k_bounds_final, dim3(1), dim3(kBlock), 0, st, part, nblocks(nslots), bits);
+        } else {
+            // bodies are grouped by scene after the first run, so nearly every
+            // wave is uniform and the atomics spread over the scenes
+            hipLaunchKernelGGL(k_bounds, dim3(nblocks(nslots)), dim3(kBlock), 0, st, b, nslots, 1, bits);
+        }
+    }
     hipLaunchKernelGGL(k_bounds_decode, dim3(nblocks(6 * nscenes)), dim3(kBlock), 0, st, bits, out6, 6 * nscenes);
 }
 

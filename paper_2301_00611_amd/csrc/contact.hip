@@ -96,13 +96,16 @@ struct ContactPartial {
 };
 
 template <int PREC, bool BATCHED, bool PERIODIC>
-__global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restrict__ args)
+__global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restrict__ args, int parity)
 {
     using R = typename std::conditional<PREC == DEM_FP32_MIXED, float, double>::type;
     // the arguments live in device memory so that a captured graph stays
     // valid across broad-phase runs (pair count and buffers change there)
     const StepArgs& a = *args;
-    if (a.ctr->stall) return;
+    // the previous step asked for a broad-phase run: this step does not run
+    if (a.ctr->stall[parity ^ 1]) return;
+    // this step's flag starts clear; the integrate kernel may raise it
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctr->stall[parity] = 0;
     const int k = logical_block(gridDim.x) * blockDim.x + threadIdx.x;
     ContactPartial part = {0.0, 0.0, 0ull, 0ull};
     bool unstable = false;
@@ -157,26 +160,15 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
         }
 
         if (!real) {
-            P.fsx[k] = 0.0;
-            P.fsy[k] = 0.0;
-            P.fsz[k] = 0.0;
-            P.nx[k] = 0.0;
-            P.ny[k] = 0.0;
-            P.nz[k] = 0.0;
-            if (PREC == DEM_FP32_MIXED) {
-                P.fxf[k] = 0.f;
-                P.fyf[k] = 0.f;
-                P.fzf[k] = 0.f;
-                P.txf[k] = 0.f;
-                P.tyf[k] = 0.f;
-                P.tzf[k] = 0.f;
-            } else {
-                P.fx[k] = 0.0;
-                P.fy[k] = 0.0;
-                P.fz[k] = 0.0;
-                P.tx[k] = 0.0;
-                P.ty[k] = 0.0;
-                P.tz[k] = 0.0;
+            // the contact is erased: drop its history (once), no force
+            if (P.real[k]) {
+                P.fsx[k] = 0.0;
+                P.fsy[k] = 0.0;
+                P.fsz[k] = 0.0;
+                P.nx[k] = 0.0;
+                P.ny[k] = 0.0;
+                P.nz[k] = 0.0;
+                P.real[k] = 0;
             }
         } else {
             // ---- ScGeom inputs
@@ -265,6 +257,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
                 P.ty[k] = (double)tau.y;
                 P.tz[k] = (double)tau.z;
             }
+            P.real[k] = 1;
             if (wall)
                 part.sw = 1;
             else
@@ -273,103 +266,73 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
         }
     }
 
-    // ---- block sums: integer counts by atomics (exact), energies by a
-    // fixed-order two-level sum (per-block partial, then the last block)
-    __shared__ double s_el[kMaxBlock / 64], s_pl[kMaxBlock / 64];
-    __shared__ unsigned long long s_ss[kMaxBlock / 64], s_sw[kMaxBlock / 64];
-    __shared__ int s_last;
+    // ---- block slot: counts always, energies when tracked (fixed-order
+    // wave and block combination, plain stores into this block's slot)
+    __shared__ ContactPartial s_p[kMaxBlock / 64];
+    __shared__ uint32_t s_bad[kMaxBlock / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const bool energy = a.track_energy != 0;
     for (int off = 32; off > 0; off >>= 1) {
-        part.el += __shfl_down(part.el, off, 64);
-        part.plast += __shfl_down(part.plast, off, 64);
+        if (energy) {
+            part.el += __shfl_down(part.el, off, 64);
+            part.plast += __shfl_down(part.plast, off, 64);
+        }
         part.ss += __shfl_down(part.ss, off, 64);
         part.sw += __shfl_down(part.sw, off, 64);
     }
-    if (__any(unstable) && lane == 0) a.ctr->unstable = 1;
+    const bool bad = __any(unstable);
     if (lane == 0) {
-        s_el[wave] = part.el;
-        s_pl[wave] = part.plast;
-        s_ss[wave] = part.ss;
-        s_sw[wave] = part.sw;
+        s_p[wave] = part;
+        s_bad[wave] = bad ? 1u : 0u;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         double el = 0.0, pl = 0.0;
         unsigned long long ss = 0, sw = 0;
+        uint32_t flags = 0;
         for (int w = 0; w < nwaves; ++w) {
-            el += s_el[w];
-            pl += s_pl[w];
-            ss += s_ss[w];
-            sw += s_sw[w];
+            el += s_p[w].el;
+            pl += s_p[w].plast;
+            ss += s_p[w].ss;
+            sw += s_p[w].sw;
+            flags |= s_bad[w];
         }
-        if (ss) atomicAdd(&a.ctr->cur_ss, ss);
-        if (sw) atomicAdd(&a.ctr->cur_sw, sw);
-        s_last = 0;
-        if (a.track_energy) {
-            BlockPartial bp;
-            bp.e[0] = el;
-            bp.e[1] = pl;
-            bp.e[2] = 0.0;
-            bp.e[3] = 0.0;
-            a.part_contact[blockIdx.x] = bp;
-            __threadfence();
-            const unsigned prev = atomicAdd(&a.ctr->blocks_done_contact, 1u);
-            s_last = prev == gridDim.x - 1;
+        ContactAcc& acc = a.acc_contact[blockIdx.x];
+        if (energy) {
+            acc.el = el;
+            acc.plast += pl;
         }
-    }
-    __syncthreads();
-    if (s_last) {
-        __threadfence();
-        // fixed assignment of partials to threads, then fixed-order wave and
-        // block combination: the result does not depend on block timing
-        double el = 0.0, pl = 0.0;
-        for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
-            el += a.part_contact[b].e[0];
-            pl += a.part_contact[b].e[1];
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-            el += __shfl_down(el, off, 64);
-            pl += __shfl_down(pl, off, 64);
-        }
-        __syncthreads();
-        if (lane == 0) {
-            s_el[wave] = el;
-            s_pl[wave] = pl;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            el = 0.0;
-            pl = 0.0;
-            for (int w = 0; w < nwaves; ++w) {
-                el += s_el[w];
-                pl += s_pl[w];
-            }
-            a.ctr->e_el = el;
-            a.ctr->e_plast += pl;
-            a.ctr->blocks_done_contact = 0u;
-        }
+        acc.ss = ss;
+        acc.sw = sw;
+        acc.ss_cum += ss;
+        acc.sw_cum += sw;
+        if (flags) a.ctr->unstable = 1;
     }
 }
 
 template <int PREC, bool BATCHED, bool PERIODIC>
-void launch_t(const StepArgs* args, int grid, int block, hipStream_t st)
+void launch_t(const StepArgs* args, int parity, int grid, int block, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
-    hipLaunchKernelGGL((k_contact<PREC, BATCHED, PERIODIC>), dim3(grid > 0 ? grid : 1), dim3(block), 0, st, args);
+    const dim3 g(grid > 0 ? grid : 1), b(block);
+    if (ev0)
+        hipExtLaunchKernelGGL((k_contact<PREC, BATCHED, PERIODIC>), g, b, 0, st, ev0, ev1, 0, args, parity);
+    else
+        hipLaunchKernelGGL((k_contact<PREC, BATCHED, PERIODIC>), g, b, 0, st, args, parity);
 }
 
 }  // namespace
 
-void launch_contact(const StepArgs* args, int grid, int precision, bool batched, bool periodic, int block,
-                    hipStream_t st)
+void launch_contact(const StepArgs* args, int parity, int grid, int precision, bool batched, bool periodic,
+                    int block, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (precision == DEM_FP32_MIXED) {
-        if (batched) launch_t<DEM_FP32_MIXED, true, false>(args, grid, block, st);
-        else if (periodic) launch_t<DEM_FP32_MIXED, false, true>(args, grid, block, st);
-        else launch_t<DEM_FP32_MIXED, false, false>(args, grid, block, st);
+        if (batched) launch_t<DEM_FP32_MIXED, true, false>(args, parity, grid, block, st, ev0, ev1);
+        else if (periodic) launch_t<DEM_FP32_MIXED, false, true>(args, parity, grid, block, st, ev0, ev1);
+        else launch_t<DEM_FP32_MIXED, false, false>(args, parity, grid, block, st, ev0, ev1);
     } else {
-        if (batched) launch_t<DEM_FP64, true, false>(args, grid, block, st);
-        else if (periodic) launch_t<DEM_FP64, false, true>(args, grid, block, st);
-        else launch_t<DEM_FP64, false, false>(args, grid, block, st);
+        if (batched) launch_t<DEM_FP64, true, false>(args, parity, grid, block, st, ev0, ev1);
+        else if (periodic) launch_t<DEM_FP64, false, true>(args, parity, grid, block, st, ev0, ev1);
+        else launch_t<DEM_FP64, false, false>(args, parity, grid, block, st, ev0, ev1);
     }
 }
 

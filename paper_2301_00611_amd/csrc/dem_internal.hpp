@@ -9,6 +9,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <cstdint>
 #include <type_traits>
 
@@ -69,11 +70,12 @@ struct Bodies {
     double *wx, *wy, *wz;
     double *qw, *qx, *qy, *qz;
     double *rad, *mass;
-    uint8_t *mat;
+    uint16_t *mat;            // material index
     uint8_t *blocked;
     int32_t *id;              // slot -> body id
     uint16_t *scene;          // slot -> scene (batched only)
     int32_t *period;          // periodic: packed integer period of the body at the last run
+    double *disp;             // non-affine displacement accumulated since the last broad-phase run
 };
 
 // Candidate pairs after a broad-phase run.
@@ -82,6 +84,7 @@ struct Pairs {
     int32_t *b;               // slot of #2
     int32_t *cell;            // packed image of #2 (periodic), 0 otherwise
     int32_t *pid;             // id of the non-owner partner (for history carry-over)
+    uint8_t *real;            // 1 when the pair touched at the last evaluation
     double *fsx, *fsy, *fsz;  // shear force on #2 (history)
     double *nx, *ny, *nz;     // normal of the last step; 0 for a non-real pair
     double *fx, *fy, *fz;     // total force on #2 of the last step
@@ -105,30 +108,32 @@ struct History {
     double *fsx, *fsy, *fsz, *nx, *ny, *nz;
 };
 
-// Device-side counters and accumulators (one struct in device memory).
+// Device-side flags and counters (one struct in device memory).  The hot
+// kernels use no atomics: flags are plain stores of 1, the step counter has
+// a single writer, and energies / contact counts go to per-block slots.
 struct Counters {
-    unsigned long long vmax_bits;   // this step: max over bodies of the non-affine displacement (double bits)
-    double verlet_acc;              // displacement bound accumulated since the last broad-phase run
-    double verlet_limit;            // a run is needed once verlet_acc exceeds this
-    double verlet_cell_step;        // mean-field term added every step (periodic)
-    int32_t stall;                  // 1: a broad-phase run is needed before the next step
-    int32_t steps_done;             // steps completed since the host last reset it
+    int32_t stall[2];               // by step parity: a broad-phase run is needed before the next step
+    int32_t steps_done;             // steps completed since the host last reset it (block 0 of integrate)
     int32_t nonfinite;              // a NaN/Inf position or velocity appeared
     int32_t unstable;               // an overlap exceeded a radius
-    unsigned int blocks_done_contact;
-    unsigned int blocks_done_integrate;
-    unsigned long long cur_ss, cur_sw;    // real contacts counted during this step
-    unsigned long long last_ss, last_sw;  // real contacts of the last completed step
-    unsigned long long contact_steps;     // sum over completed steps
-    double e_kin, e_rot, e_el, e_grav, e_damp, e_plast;
+    int32_t pad_;
+    double verlet_limit;            // per-body displacement budget (0.98 Delta L)
+    double verlet_cell_step;        // mean-field share of the budget used per step (periodic)
 };
 
-// Energy / count partials of one block.
-struct BlockPartial {
-    double e[4];                    // contact: el, plast, -, -   integrate: kin, rot, grav, damp
-    unsigned long long n[2];        // contact: ss, sw
-    double vmax;
-    double pad_;
+// Per-block slots of the contact kernel: the last step's values and the
+// running sums since the host last folded them (fixed block order).
+struct ContactAcc {
+    double el;                      // elastic energy of the block's contacts, last step
+    double plast;                   // plastic work, cumulative
+    unsigned long long ss, sw;      // real contacts of the last step
+    unsigned long long ss_cum, sw_cum;
+};
+
+// Per-block slots of the integrate kernel.
+struct IntAcc {
+    double kin, rot;                // last step
+    double grav, damp;              // cumulative
 };
 
 struct StepArgs {
@@ -145,8 +150,8 @@ struct StepArgs {
     int32_t nslots;
     int32_t npairs;
     Counters* ctr;
-    BlockPartial* part_contact;
-    BlockPartial* part_integrate;
+    ContactAcc* acc_contact;        // one slot per contact block
+    IntAcc* acc_integrate;          // one slot per integrate block
     int32_t track_energy;
 };
 
@@ -171,8 +176,8 @@ struct GridArgs {
     int32_t scene_bits;        // bits of the scene index in the key
     int32_t morton_bits;       // bits per axis
 };
-void launch_bounds(const Bodies& b, const uint16_t* scene, int nslots, int nscenes, double* out6,
-                   hipStream_t st);
+size_t bounds_temp_bytes(int nslots);
+void launch_bounds(const Bodies& b, int nslots, int nscenes, double* out6, void* temp, hipStream_t st);
 void launch_keys(const GridArgs& g, uint64_t* keys, uint32_t* vals, hipStream_t st);
 void launch_permute(const Bodies& src, const Bodies& dst, const uint32_t* order, int nslots, bool batched,
                     bool periodic, int32_t* slot_of_id, hipStream_t st);
@@ -214,12 +219,15 @@ void launch_pair_build(const PairBuildArgs& a, hipStream_t st);
 void launch_carry_over(const PairBuildArgs& a, hipStream_t st, int old_nbodies);
 
 // contact.hip
-void launch_contact(const StepArgs* args, int grid, int precision, bool batched, bool periodic, int block,
-                    hipStream_t st);
+// ev0/ev1 (optional): events stamped at the kernel's own start and end
+// (hipExtLaunchKernelGGL), used by the timing mode.
+void launch_contact(const StepArgs* args, int parity, int grid, int precision, bool batched, bool periodic,
+                    int block, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // integrate.hip
-void launch_integrate(const StepArgs* args, int grid, int precision, bool batched, bool periodic, int block,
-                      hipStream_t st);
+void launch_integrate(const StepArgs* args, int parity, int grid, int precision, bool batched, bool periodic,
+                      int block, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+void launch_cell_update(const StepArgs* args, int parity, hipStream_t st);
 void launch_body_forces(const StepArgs& a, int precision, double* f3, double* t3, hipStream_t st);
 
 

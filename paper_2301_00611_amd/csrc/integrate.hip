@@ -6,11 +6,11 @@
 // Cundall damping eq. 2.9 per component with the on-step velocity estimate
 // v + a dt/2, the leapfrog update, the spherical rotation and, in a periodic
 // cell, the homoDeform velocity terms (class Cell).  Energies use the
-// mid-step velocities v-, w-.  The last block to finish closes the step:
-// energy totals (fixed-order sum of the block partials), the Verlet budget
-// (eq. 2.3-2.4: a broad-phase run is requested once some body may have moved
-// Delta L since the last one), step counters and the periodic cell update
-// F+ = (I + L dt) F.
+// mid-step velocities v-, w-.  Each body also accumulates its non-affine
+// displacement since the last broad-phase run and raises the step's stall
+// flag once it exceeds the Verlet budget (eq. 2.3-2.4).  Energies go to the
+// block's own slot; a periodic cell is updated, F+ = (I + L dt) F, by a
+// one-block kernel after the step.
 #include "dem_internal.hpp"
 
 namespace dem {
@@ -39,7 +39,7 @@ __device__ inline void body_sum(const StepArgs& a, int i, double r, double* F, d
     for (int e = beg; e < end; ++e) {
         const uint32_t u = a.rows.ent[e];
         const uint32_t k = u & kPairMask;
-        if (k >= (uint32_t)a.npairs) continue;
+        if (k >= (uint32_t)a.npairs || !a.pr.real[k]) continue;
         double f0, f1, f2, t0, t1, t2;
         if (PREC == DEM_FP32_MIXED) {
             f0 = a.pr.fxf[k];
@@ -84,14 +84,18 @@ struct IntPartial {
 };
 
 template <int PREC, bool BATCHED, bool PERIODIC>
-__global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restrict__ args)
+__global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restrict__ args, int parity)
 {
     const StepArgs& a = *args;
-    if (a.ctr->stall) return;
+    if (a.ctr->stall[parity ^ 1]) {
+        // not run: keep every later step of this launch chain stopped too
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.ctr->stall[parity] = 1;
+        return;
+    }
     const int i = logical_block(gridDim.x) * blockDim.x + threadIdx.x;
     IntPartial part = {0.0, 0.0, 0.0, 0.0};
-    double vmax = 0.0;
     bool bad = false;
+    bool over = false;
     if (i < a.nslots) {
         const Bodies& B = a.bod;
         const int s = BATCHED ? (int)B.scene[i] : 0;
@@ -178,143 +182,89 @@ __global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restr
         B.wy[i] = w[1];
         B.wz[i] = w[2];
 
-        // non-affine displacement of this step, for the Verlet budget
+        // non-affine displacement of this step, added to the body's Verlet
+        // account (eq. 2.3); the cell's mean field uses its own share
         double u[3] = {v[0], v[1], v[2]};
         if (PERIODIC) {
             double Lx[3];
             matvec(S.L, x0[0], x0[1], x0[2], Lx);
             for (int k = 0; k < 3; ++k) u[k] -= Lx[k];
         }
-        vmax = sqrt((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]) * dt;
+        const double d = B.disp[i] + sqrt((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]) * dt + a.ctr->verlet_cell_step;
+        B.disp[i] = d;
+        over = d > a.ctr->verlet_limit;
         bad = !(isfinite(x1[0]) && isfinite(x1[1]) && isfinite(x1[2]) && isfinite(v[0]) && isfinite(v[1]) &&
                 isfinite(v[2]));
-        if (bad) vmax = 0.0;
     }
+    // eq. 2.4: some body may now have left its enlarged bound: the next step
+    // needs a broad-phase run (plain stores of the same value)
+    if (__any(over) && (threadIdx.x & 63) == 0) a.ctr->stall[parity] = 1;
+    if (__any(bad) && (threadIdx.x & 63) == 0) a.ctr->nonfinite = 1;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctr->steps_done += 1;
+    if (!a.track_energy) return;
 
-    // ---- block reduction
+    // ---- energies into this block's slot (fixed-order wave/block sums)
     __shared__ IntPartial s_p[kMaxBlock / 64];
-    __shared__ double s_v[kMaxBlock / 64];
-    __shared__ int s_last;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     for (int off = 32; off > 0; off >>= 1) {
         part.kin += __shfl_down(part.kin, off, 64);
         part.rot += __shfl_down(part.rot, off, 64);
         part.grav += __shfl_down(part.grav, off, 64);
         part.damp += __shfl_down(part.damp, off, 64);
-        const double o = __shfl_down(vmax, off, 64);
-        vmax = o > vmax ? o : vmax;
     }
-    if (__any(bad) && lane == 0) a.ctr->nonfinite = 1;
-    if (lane == 0) {
-        s_p[wave] = part;
-        s_v[wave] = vmax;
-    }
+    if (lane == 0) s_p[wave] = part;
     __syncthreads();
     if (threadIdx.x == 0) {
         IntPartial p = {0.0, 0.0, 0.0, 0.0};
-        double vm = 0.0;
         for (int w = 0; w < nwaves; ++w) {
             p.kin += s_p[w].kin;
             p.rot += s_p[w].rot;
             p.grav += s_p[w].grav;
             p.damp += s_p[w].damp;
-            vm = s_v[w] > vm ? s_v[w] : vm;
         }
-        // max of non-negative doubles: their bit patterns order the same way
-        atomicMax(&a.ctr->vmax_bits, (unsigned long long)__double_as_longlong(vm));
-        BlockPartial bp;
-        bp.e[0] = p.kin;
-        bp.e[1] = p.rot;
-        bp.e[2] = p.grav;
-        bp.e[3] = p.damp;
-        a.part_integrate[blockIdx.x] = bp;
-        __threadfence();
-        const unsigned prev = atomicAdd(&a.ctr->blocks_done_integrate, 1u);
-        s_last = prev == gridDim.x - 1;
+        IntAcc& acc = a.acc_integrate[blockIdx.x];
+        acc.kin = p.kin;
+        acc.rot = p.rot;
+        acc.grav += p.grav;
+        acc.damp += p.damp;
     }
-    __syncthreads();
-    if (!s_last) return;
+}
 
-    // ---- last block: close the step
-    __threadfence();
-    IntPartial p = {0.0, 0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
-        const BlockPartial bp = a.part_integrate[b];
-        p.kin += bp.e[0];
-        p.rot += bp.e[1];
-        p.grav += bp.e[2];
-        p.damp += bp.e[3];
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        p.kin += __shfl_down(p.kin, off, 64);
-        p.rot += __shfl_down(p.rot, off, 64);
-        p.grav += __shfl_down(p.grav, off, 64);
-        p.damp += __shfl_down(p.damp, off, 64);
-    }
-    __syncthreads();
-    if (lane == 0) s_p[wave] = p;
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    IntPartial tot = {0.0, 0.0, 0.0, 0.0};
-    for (int w = 0; w < nwaves; ++w) {
-        tot.kin += s_p[w].kin;
-        tot.rot += s_p[w].rot;
-        tot.grav += s_p[w].grav;
-        tot.damp += s_p[w].damp;
-    }
-    Counters* c = a.ctr;
-    if (a.track_energy) {
-        c->e_kin = tot.kin;
-        c->e_rot = tot.rot;
-        c->e_grav += tot.grav;
-        c->e_damp += tot.damp;
-    }
-    const double vstep = __longlong_as_double((long long)c->vmax_bits);
-    c->vmax_bits = 0ull;
-    c->verlet_acc += vstep + c->verlet_cell_step;
-    if (c->verlet_acc > c->verlet_limit) c->stall = 1;
-    c->steps_done += 1;
-    c->last_ss = c->cur_ss;
-    c->last_sw = c->cur_sw;
-    c->contact_steps += c->cur_ss + c->cur_sw;
-    c->cur_ss = 0ull;
-    c->cur_sw = 0ull;
-    c->blocks_done_integrate = 0u;
-
-    if (PERIODIC) {
-        // Cell: H+ = (I + L dt) H, trsf likewise; keep H - H_prev for the
-        // image velocity of the next step; L becomes L_prev
-        SceneParams* S = &a.scenes[0];
-        const double dt = S->dt;
-        double M[9], Hn[9], Tn[9];
-        for (int k = 0; k < 9; ++k) M[k] = ((k % 4 == 0) ? 1.0 : 0.0) + S->L[k] * dt;
-        for (int r = 0; r < 3; ++r)
-            for (int q = 0; q < 3; ++q) {
-                Hn[3 * r + q] = (M[3 * r + 0] * S->H[q] + M[3 * r + 1] * S->H[3 + q]) + M[3 * r + 2] * S->H[6 + q];
-                Tn[3 * r + q] =
-                    (M[3 * r + 0] * S->trsf[q] + M[3 * r + 1] * S->trsf[3 + q]) + M[3 * r + 2] * S->trsf[6 + q];
-            }
-        for (int k = 0; k < 9; ++k) {
-            S->dH[k] = Hn[k] - S->H[k];
-            S->H[k] = Hn[k];
-            S->trsf[k] = Tn[k];
-            S->Lprev[k] = S->L[k];
+// Periodic cell (section 2.1.6), once per step after the bodies: H+ =
+// (I + L dt) H and the same for trsf; H - H_prev is kept for the image
+// velocity of the next step's contacts; L becomes L_prev.
+__global__ void k_cell_update(const StepArgs* __restrict__ args, int parity)
+{
+    const StepArgs& a = *args;
+    if (a.ctr->stall[parity ^ 1] || threadIdx.x != 0) return;
+    SceneParams* S = &a.scenes[0];
+    const double dt = S->dt;
+    double M[9], Hn[9], Tn[9];
+    for (int k = 0; k < 9; ++k) M[k] = ((k % 4 == 0) ? 1.0 : 0.0) + S->L[k] * dt;
+    for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < 3; ++q) {
+            Hn[3 * r + q] = (M[3 * r + 0] * S->H[q] + M[3 * r + 1] * S->H[3 + q]) + M[3 * r + 2] * S->H[6 + q];
+            Tn[3 * r + q] = (M[3 * r + 0] * S->trsf[q] + M[3 * r + 1] * S->trsf[3 + q]) + M[3 * r + 2] * S->trsf[6 + q];
         }
-        const double* A = S->H;
-        const double a0 = A[0], a1 = A[1], a2 = A[2], a3 = A[3], a4 = A[4], a5 = A[5], a6 = A[6], a7 = A[7],
-                     a8 = A[8];
-        const double C0 = a4 * a8 - a5 * a7, C1 = -(a3 * a8 - a5 * a6), C2 = a3 * a7 - a4 * a6;
-        const double det = a0 * C0 + a1 * C1 + a2 * C2;
-        S->Hinv[0] = C0 / det;
-        S->Hinv[1] = -(a1 * a8 - a2 * a7) / det;
-        S->Hinv[2] = (a1 * a5 - a2 * a4) / det;
-        S->Hinv[3] = C1 / det;
-        S->Hinv[4] = (a0 * a8 - a2 * a6) / det;
-        S->Hinv[5] = -(a0 * a5 - a2 * a3) / det;
-        S->Hinv[6] = C2 / det;
-        S->Hinv[7] = -(a0 * a7 - a1 * a6) / det;
-        S->Hinv[8] = (a0 * a4 - a1 * a3) / det;
+    for (int k = 0; k < 9; ++k) {
+        S->dH[k] = Hn[k] - S->H[k];
+        S->H[k] = Hn[k];
+        S->trsf[k] = Tn[k];
+        S->Lprev[k] = S->L[k];
     }
+    const double* A = S->H;
+    const double a0 = A[0], a1 = A[1], a2 = A[2], a3 = A[3], a4 = A[4], a5 = A[5], a6 = A[6], a7 = A[7], a8 = A[8];
+    const double C0 = a4 * a8 - a5 * a7, C1 = -(a3 * a8 - a5 * a6), C2 = a3 * a7 - a4 * a6;
+    const double det = a0 * C0 + a1 * C1 + a2 * C2;
+    S->Hinv[0] = C0 / det;
+    S->Hinv[1] = -(a1 * a8 - a2 * a7) / det;
+    S->Hinv[2] = (a1 * a5 - a2 * a4) / det;
+    S->Hinv[3] = C1 / det;
+    S->Hinv[4] = (a0 * a8 - a2 * a6) / det;
+    S->Hinv[5] = -(a0 * a5 - a2 * a3) / det;
+    S->Hinv[6] = C2 / det;
+    S->Hinv[7] = -(a0 * a7 - a1 * a6) / det;
+    S->Hinv[8] = (a0 * a4 - a1 * a3) / det;
 }
 
 // Resultant force/torque per slot (for reporting), same sum as the step.
@@ -332,25 +282,34 @@ __global__ void k_body_forces(StepArgs a, double* __restrict__ f3, double* __res
 }
 
 template <int PREC, bool BATCHED, bool PERIODIC>
-void launch_t(const StepArgs* args, int grid, int block, hipStream_t st)
+void launch_t(const StepArgs* args, int parity, int grid, int block, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
-    hipLaunchKernelGGL((k_integrate<PREC, BATCHED, PERIODIC>), dim3(grid > 0 ? grid : 1), dim3(block), 0, st, args);
+    const dim3 g(grid > 0 ? grid : 1), b(block);
+    if (ev0)
+        hipExtLaunchKernelGGL((k_integrate<PREC, BATCHED, PERIODIC>), g, b, 0, st, ev0, ev1, 0, args, parity);
+    else
+        hipLaunchKernelGGL((k_integrate<PREC, BATCHED, PERIODIC>), g, b, 0, st, args, parity);
 }
 
 }  // namespace
 
-void launch_integrate(const StepArgs* args, int grid, int precision, bool batched, bool periodic, int block,
-                      hipStream_t st)
+void launch_integrate(const StepArgs* args, int parity, int grid, int precision, bool batched, bool periodic,
+                      int block, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (precision == DEM_FP32_MIXED) {
-        if (batched) launch_t<DEM_FP32_MIXED, true, false>(args, grid, block, st);
-        else if (periodic) launch_t<DEM_FP32_MIXED, false, true>(args, grid, block, st);
-        else launch_t<DEM_FP32_MIXED, false, false>(args, grid, block, st);
+        if (batched) launch_t<DEM_FP32_MIXED, true, false>(args, parity, grid, block, st, ev0, ev1);
+        else if (periodic) launch_t<DEM_FP32_MIXED, false, true>(args, parity, grid, block, st, ev0, ev1);
+        else launch_t<DEM_FP32_MIXED, false, false>(args, parity, grid, block, st, ev0, ev1);
     } else {
-        if (batched) launch_t<DEM_FP64, true, false>(args, grid, block, st);
-        else if (periodic) launch_t<DEM_FP64, false, true>(args, grid, block, st);
-        else launch_t<DEM_FP64, false, false>(args, grid, block, st);
+        if (batched) launch_t<DEM_FP64, true, false>(args, parity, grid, block, st, ev0, ev1);
+        else if (periodic) launch_t<DEM_FP64, false, true>(args, parity, grid, block, st, ev0, ev1);
+        else launch_t<DEM_FP64, false, false>(args, parity, grid, block, st, ev0, ev1);
     }
+}
+
+void launch_cell_update(const StepArgs* args, int parity, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cell_update, dim3(1), dim3(64), 0, st, args, parity);
 }
 
 void launch_body_forces(const StepArgs& a, int precision, double* f3, double* t3, hipStream_t st)

@@ -78,11 +78,11 @@ struct DBuf {
 };
 
 struct BodySet {
-    DBuf x, y, z, vx, vy, vz, wx, wy, wz, qw, qx, qy, qz, rad, mass, mat, blocked, id, scene, period;
+    DBuf x, y, z, vx, vy, vz, wx, wy, wz, qw, qx, qy, qz, rad, mass, mat, blocked, id, scene, period, disp;
     void ensure(size_t n)
     {
-        for (DBuf* b : {&x, &y, &z, &vx, &vy, &vz, &wx, &wy, &wz, &qw, &qx, &qy, &qz, &rad, &mass}) b->ensure(n * 8);
-        mat.ensure(n);
+        for (DBuf* b : {&x, &y, &z, &vx, &vy, &vz, &wx, &wy, &wz, &qw, &qx, &qy, &qz, &rad, &mass, &disp}) b->ensure(n * 8);
+        mat.ensure(n * 2);
         blocked.ensure(n);
         id.ensure(n * 4);
         scene.ensure(n * 2);
@@ -106,29 +106,31 @@ struct BodySet {
         b.qz = qz.as<double>();
         b.rad = rad.as<double>();
         b.mass = mass.as<double>();
-        b.mat = mat.as<uint8_t>();
+        b.mat = mat.as<uint16_t>();
         b.blocked = blocked.as<uint8_t>();
         b.id = id.as<int32_t>();
         b.scene = scene.as<uint16_t>();
         b.period = period.as<int32_t>();
+        b.disp = disp.as<double>();
         return b;
     }
     void release()
     {
         for (DBuf* b : {&x, &y, &z, &vx, &vy, &vz, &wx, &wy, &wz, &qw, &qx, &qy, &qz, &rad, &mass, &mat, &blocked, &id,
-                        &scene, &period})
+                        &scene, &period, &disp})
             b->release();
     }
 };
 
 struct PairSet {
-    DBuf a, b, cell, pid, fsx, fsy, fsz, nx, ny, nz, fx, fy, fz, tx, ty, tz, fxf, fyf, fzf, txf, tyf, tzf;
+    DBuf a, b, cell, pid, real, fsx, fsy, fsz, nx, ny, nz, fx, fy, fz, tx, ty, tz, fxf, fyf, fzf, txf, tyf, tzf;
     DBuf own_begin, own_count;  // by gid
     size_t cap = 0;
     void ensure(size_t n, bool fp32)
     {
         n = std::max<size_t>(n, 1);
         for (DBuf* d : {&a, &b, &cell, &pid}) d->ensure(n * 4);
+        real.ensure(n);
         for (DBuf* d : {&fsx, &fsy, &fsz, &nx, &ny, &nz}) d->ensure(n * 8);
         if (fp32) {
             for (DBuf* d : {&fxf, &fyf, &fzf, &txf, &tyf, &tzf}) d->ensure(n * 4);
@@ -144,6 +146,7 @@ struct PairSet {
         p.b = b.as<int32_t>();
         p.cell = cell.as<int32_t>();
         p.pid = pid.as<int32_t>();
+        p.real = real.as<uint8_t>();
         p.fsx = fsx.as<double>();
         p.fsy = fsy.as<double>();
         p.fsz = fsz.as<double>();
@@ -181,8 +184,8 @@ struct PairSet {
     }
     void release()
     {
-        for (DBuf* d : {&a, &b, &cell, &pid, &fsx, &fsy, &fsz, &nx, &ny, &nz, &fx, &fy, &fz, &tx, &ty, &tz, &fxf, &fyf,
-                        &fzf, &txf, &tyf, &tzf, &own_begin, &own_count})
+        for (DBuf* d : {&a, &b, &cell, &pid, &real, &fsx, &fsy, &fsz, &nx, &ny, &nz, &fx, &fy, &fz, &tx, &ty, &tz, &fxf,
+                        &fyf, &fzf, &txf, &tyf, &tzf, &own_begin, &own_count})
             d->release();
         cap = 0;
     }
@@ -248,6 +251,15 @@ struct World {
     DBuf ent_slot, ent_pid, ent_cell, ent_own, own_scan, rows_ent, scan_tmp, radix_tmp;
     DBuf d_scenes, d_walls, d_mats, d_tanphi, d_ctr, d_part_c, d_part_i, d_bounds, d_total, d_tmp3, d_args;
     int grid_c = 1, grid_i = 1;        // step-kernel grids (contact sized with headroom)
+    int acc_c_n = 0, acc_i_n = 0;      // slots currently in use in d_part_c / d_part_i
+    int next_parity = 0;               // parity of the next step (stall flags alternate)
+    // running sums folded from the per-block slots (fixed block order)
+    double base_plast = 0.0, base_grav = 0.0, base_damp = 0.0;
+    unsigned long long base_contact_steps = 0;
+    // last-step values kept across a fold until the next step runs
+    double last_el = 0.0, last_kin = 0.0, last_rot = 0.0;
+    unsigned long long last_ss = 0, last_sw = 0;
+    bool slots_fresh = true;           // no step has written the slots since the last fold
     std::vector<SceneParams> sp;       // host copy of the scene table
     Counters* h_ctr = nullptr;         // pinned
     int ncells = 0;
@@ -369,7 +381,7 @@ struct World {
         if (!(density > 0.0) || !(young > 0.0) || !(poisson > -1.0 && poisson <= 0.5) ||
             !(friction >= 0.0 && friction < 1.5707963267948966))
             fail(DEM_EINVAL, "dem_add_material: need density > 0, young > 0, -1 < poisson <= 0.5, 0 <= friction < pi/2");
-        if (mats.size() >= 255) fail(DEM_EINVAL, "dem_add_material: at most 255 materials");
+        if (mats.size() >= 1024) fail(DEM_EINVAL, "dem_add_material: at most 1024 materials");
         mats.push_back({density, young, poisson, friction});
         upload_materials();
         return (int)mats.size() - 1;
@@ -552,8 +564,9 @@ struct World {
         std::vector<uint8_t> u8(n);
         std::vector<int32_t> i32(n);
         std::vector<uint16_t> u16(n);
-        for (int i = 0; i < nslots; ++i) u8[i] = (uint8_t)bodies[sph[i]].mat;
-        HIPC(hipMemcpyAsync(B.mat.p, u8.data(), (size_t)nslots, hipMemcpyHostToDevice, stream));
+        std::vector<uint16_t> m16(n);
+        for (int i = 0; i < nslots; ++i) m16[i] = (uint16_t)bodies[sph[i]].mat;
+        HIPC(hipMemcpyAsync(B.mat.p, m16.data(), 2 * (size_t)nslots, hipMemcpyHostToDevice, stream));
         HIPC(hipStreamSynchronize(stream));
         for (int i = 0; i < nslots; ++i) u8[i] = bodies[sph[i]].blocked;
         HIPC(hipMemcpyAsync(B.blocked.p, u8.data(), (size_t)nslots, hipMemcpyHostToDevice, stream));
@@ -645,7 +658,8 @@ struct World {
         std::vector<double> bnd(6 * (size_t)nsc, 0.0);
         if (!periodic && nslots > 0) {
             d_bounds.ensure(sizeof(double) * 6 * nsc);
-            launch_bounds(bs[active].view(), nullptr, nslots, nsc, d_bounds.as<double>(), stream);
+            radix_tmp.ensure(std::max(radix_temp_bytes(nslots), bounds_temp_bytes(nslots)));
+            launch_bounds(bs[active].view(), nslots, nsc, d_bounds.as<double>(), radix_tmp.p, stream);
             HIPC(hipGetLastError());
             HIPC(hipMemcpyAsync(bnd.data(), d_bounds.p, sizeof(double) * 6 * nsc, hipMemcpyDeviceToHost, stream));
             HIPC(hipStreamSynchronize(stream));
@@ -731,7 +745,7 @@ struct World {
             vals.ensure(4 * (size_t)nslots);
             keys_alt.ensure(8 * (size_t)nslots);
             vals_alt.ensure(4 * (size_t)nslots);
-            radix_tmp.ensure(radix_temp_bytes(nslots));
+            radix_tmp.ensure(std::max(radix_temp_bytes(nslots), bounds_temp_bytes(nslots)));
             launch_keys(g, keys.as<uint64_t>(), vals.as<uint32_t>(), stream);
             bool in_alt = false;
             radix_sort_pairs(keys.as<uint64_t>(), vals.as<uint32_t>(), keys_alt.as<uint64_t>(), vals_alt.as<uint32_t>(),
@@ -828,31 +842,98 @@ struct World {
             old_ngids = (int)bodies.size();
         }
         npairs = npairs_new;
-        // step-kernel grids: the contact grid keeps 25 % headroom so that a
-        // captured graph survives the next runs; blocks past npairs exit
+        // fold the per-block slots before the grids change, then size them
+        fold_slots();
         if ((int64_t)grid_c * block_contact < npairs || grid_c < 1)
             grid_c = std::max((int)(((int64_t)npairs * 5 / 4 + block_contact - 1) / block_contact), 1);
         grid_i = std::max((nslots + block_integrate - 1) / block_integrate, 1);
-        d_part_c.ensure(sizeof(BlockPartial) * (size_t)grid_c);
-        d_part_i.ensure(sizeof(BlockPartial) * (size_t)grid_i);
-        // counters: fresh Verlet budget
+        d_part_c.ensure(sizeof(ContactAcc) * (size_t)grid_c);
+        d_part_i.ensure(sizeof(IntAcc) * (size_t)grid_i);
+        HIPC(hipMemsetAsync(d_part_c.p, 0, sizeof(ContactAcc) * (size_t)grid_c, stream));
+        HIPC(hipMemsetAsync(d_part_i.p, 0, sizeof(IntAcc) * (size_t)grid_i, stream));
+        acc_c_n = grid_c;
+        acc_i_n = grid_i;
+        // counters: fresh Verlet budget, flags clear, parity 0
         HIPC(hipMemcpyAsync(h_ctr, d_ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, stream));
         HIPC(hipStreamSynchronize(stream));
-        C.verlet_acc = 0.0;
         C.verlet_limit = 0.98 * (std::isfinite(limit) ? limit : 0.0);
         double cell_step = 0.0;
         for (int s = 0; s < nsc; ++s) cell_step = std::max(cell_step, sp[s].verlet_cell_rate * sp[s].dt);
         C.verlet_cell_step = cell_step;
-        C.stall = 0;
-        C.blocks_done_contact = 0;
-        C.blocks_done_integrate = 0;
-        C.vmax_bits = 0;
-        C.cur_ss = C.cur_sw = 0;
+        C.stall[0] = C.stall[1] = 0;
+        C.steps_done = 0;
+        next_parity = 0;
         HIPC(hipMemcpyAsync(d_ctr.p, h_ctr, sizeof(Counters), hipMemcpyHostToDevice, stream));
         HIPC(hipStreamSynchronize(stream));
         upload_args();
         need_rebuild = false;
         ++rebuilds;
+    }
+
+    // Sum the per-block slots in block order.  cum = true: add the running
+    // sums to the bases and clear the slots (before the grids change).
+    struct SlotSums {
+        double el = 0, plast = 0, kin = 0, rot = 0, grav = 0, damp = 0;
+        unsigned long long ss = 0, sw = 0, cum = 0;
+    };
+    SlotSums read_slots()
+    {
+        SlotSums t;
+        std::vector<ContactAcc> c((size_t)acc_c_n);
+        std::vector<IntAcc> i((size_t)acc_i_n);
+        if (acc_c_n) HIPC(hipMemcpyAsync(c.data(), d_part_c.p, sizeof(ContactAcc) * c.size(), hipMemcpyDeviceToHost, stream));
+        if (acc_i_n) HIPC(hipMemcpyAsync(i.data(), d_part_i.p, sizeof(IntAcc) * i.size(), hipMemcpyDeviceToHost, stream));
+        HIPC(hipStreamSynchronize(stream));
+        for (const ContactAcc& a : c) {
+            t.el += a.el;
+            t.plast += a.plast;
+            t.ss += a.ss;
+            t.sw += a.sw;
+            t.cum += a.ss_cum + a.sw_cum;
+        }
+        for (const IntAcc& a : i) {
+            t.kin += a.kin;
+            t.rot += a.rot;
+            t.grav += a.grav;
+            t.damp += a.damp;
+        }
+        return t;
+    }
+    void fold_slots()
+    {
+        if (!acc_c_n && !acc_i_n) return;
+        const SlotSums t = read_slots();
+        base_plast += t.plast;
+        base_grav += t.grav;
+        base_damp += t.damp;
+        base_contact_steps += t.cum;
+        if (!slots_fresh) {
+            last_el = t.el;
+            last_kin = t.kin;
+            last_rot = t.rot;
+            last_ss = t.ss;
+            last_sw = t.sw;
+        }
+        slots_fresh = true;
+    }
+    // Energies and contact counts as reported: bases + current slots.
+    void totals(dem_energy* e, unsigned long long* ss, unsigned long long* sw, unsigned long long* csteps)
+    {
+        const SlotSums t = read_slots();
+        const bool fresh = slots_fresh;
+        const double el = fresh ? last_el : t.el, kin = fresh ? last_kin : t.kin, rot = fresh ? last_rot : t.rot;
+        if (e) {
+            e->kinetic = kin;
+            e->kin_rot = rot;
+            e->elastic = el;
+            e->grav_work = base_grav + t.grav;
+            e->damp_dissip = base_damp + t.damp;
+            e->plastic_dissip = base_plast + t.plast;
+            e->total = ((((e->kinetic + e->kin_rot) + e->elastic) + e->grav_work) + e->damp_dissip) + e->plastic_dissip;
+        }
+        if (ss) *ss = fresh ? last_ss : t.ss;
+        if (sw) *sw = fresh ? last_sw : t.sw;
+        if (csteps) *csteps = base_contact_steps + t.cum;
     }
 
     // ------------------------------------------------------------ step
@@ -873,20 +954,22 @@ struct World {
         a.nslots = nslots;
         a.npairs = npairs;
         a.ctr = d_ctr.as<Counters>();
-        a.part_contact = d_part_c.as<BlockPartial>();
-        a.part_integrate = d_part_i.as<BlockPartial>();
+        a.acc_contact = d_part_c.as<ContactAcc>();
+        a.acc_integrate = d_part_i.as<IntAcc>();
         a.track_energy = track_energy ? 1 : 0;
         return a;
     }
 
-    void launch_step(hipEvent_t* ev)
+    // ev (timing mode): 4 events, stamped at the start and end of the
+    // contact and the integrate kernels by the dispatch packets themselves
+    void launch_step(int parity, hipEvent_t* ev)
     {
         const StepArgs* a = d_args.as<StepArgs>();
-        if (ev) HIPC(hipEventRecord(ev[0], stream));
-        launch_contact(a, grid_c, precision, batched(), periodic, block_contact, stream);
-        if (ev) HIPC(hipEventRecord(ev[1], stream));
-        launch_integrate(a, grid_i, precision, batched(), periodic, block_integrate, stream);
-        if (ev) HIPC(hipEventRecord(ev[2], stream));
+        launch_contact(a, parity, grid_c, precision, batched(), periodic, block_contact, stream, ev ? ev[0] : nullptr,
+                       ev ? ev[1] : nullptr);
+        launch_integrate(a, parity, grid_i, precision, batched(), periodic, block_integrate, stream,
+                         ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
+        if (periodic) launch_cell_update(a, parity, stream);
     }
 
     std::string graph_key(int n) const
@@ -904,13 +987,9 @@ struct World {
         if (it != graphs.end()) return it->second;
         if (graphs.size() > 8) invalidate_graphs();
         GraphEntry ge;
-        if (timing) {
-            ge.ev.resize(3 * (size_t)n);
-            for (auto& e : ge.ev) HIPC(hipEventCreate(&e));
-        }
         hipGraph_t g;
         HIPC(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-        for (int i = 0; i < n; ++i) launch_step(timing ? &ge.ev[3 * (size_t)i] : nullptr);
+        for (int i = 0; i < n; ++i) launch_step(i & 1, nullptr);
         HIPC(hipStreamEndCapture(stream, &g));
         HIPC(hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0));
         HIPC(hipGraphDestroy(g));
@@ -929,6 +1008,8 @@ struct World {
         if (hipEventElapsedTime(&ms, a, b) == hipSuccess) {
             timers[name].total_ms += ms;
             timers[name].launches += 1;
+        } else {
+            (void)hipGetLastError();  // do not leave the failed query as a sticky error
         }
     }
 
@@ -947,10 +1028,6 @@ struct World {
         }
         int64_t remaining = nsteps;
         std::vector<hipEvent_t> direct_ev;
-        if (timing) {
-            direct_ev.resize(3);
-            for (auto& e : direct_ev) HIPC(hipEventCreate(&e));
-        }
         hipEvent_t rb0 = nullptr, rb1 = nullptr;
         if (timing) {
             HIPC(hipEventCreate(&rb0));
@@ -958,7 +1035,7 @@ struct World {
         }
         try {
             while (remaining > 0) {
-                if (need_rebuild || h_ctr->stall) {
+                if (need_rebuild || h_ctr->stall[next_parity ^ 1]) {
                     if (timing) HIPC(hipEventRecord(rb0, stream));
                     rebuild();
                     if (timing) {
@@ -969,30 +1046,34 @@ struct World {
                 }
                 h_ctr->steps_done = 0;
                 HIPC(hipMemsetAsync(reinterpret_cast<char*>(d_ctr.p) + offsetof(Counters, steps_done), 0, 4, stream));
+                // graphs hold an even number of steps starting at parity 0
                 const int n = (int)std::min<int64_t>(remaining, chunk);
                 GraphEntry* ge = nullptr;
-                if (use_graph && n == chunk) {
+                const int par0 = next_parity;
+                // timing mode launches directly: kernel events come from the
+                // dispatch packets, which graph nodes do not expose here
+                if (use_graph && !timing && n == chunk && chunk % 2 == 0 && par0 == 0) {
                     ge = &get_graph(n);
                     HIPC(hipGraphLaunch(ge->exec, stream));
                 } else {
-                    for (int i = 0; i < n; ++i) {
-                        launch_step(timing ? direct_ev.data() : nullptr);
-                        if (timing) {
-                            HIPC(hipEventSynchronize(direct_ev[2]));
-                            add_time("contact", direct_ev[0], direct_ev[1]);
-                            add_time("integrate", direct_ev[1], direct_ev[2]);
-                        }
+                    if (timing && direct_ev.size() < 4 * (size_t)n) {
+                        const size_t old = direct_ev.size();
+                        direct_ev.resize(4 * (size_t)n);
+                        for (size_t q = old; q < direct_ev.size(); ++q) HIPC(hipEventCreate(&direct_ev[q]));
                     }
+                    for (int i = 0; i < n; ++i)
+                        launch_step((par0 + i) & 1, timing ? &direct_ev[4 * (size_t)i] : nullptr);
                 }
+                next_parity = (par0 + n) & 1;
                 HIPC(hipGetLastError());
                 read_counters();
                 const int done = h_ctr->steps_done;
-                if (timing && ge) {
+                if (done > 0) slots_fresh = false;
+                if (timing)
                     for (int i = 0; i < done; ++i) {
-                        add_time("contact", ge->ev[3 * (size_t)i], ge->ev[3 * (size_t)i + 1]);
-                        add_time("integrate", ge->ev[3 * (size_t)i + 1], ge->ev[3 * (size_t)i + 2]);
+                        add_time("contact", direct_ev[4 * (size_t)i], direct_ev[4 * (size_t)i + 1]);
+                        add_time("integrate", direct_ev[4 * (size_t)i + 2], direct_ev[4 * (size_t)i + 3]);
                     }
-                }
                 for (auto& S : scenes) {
                     S.iter += done;
                     S.time += done * S.p.dt;
@@ -1001,7 +1082,9 @@ struct World {
                 contacts_valid = done > 0 || contacts_valid;
                 if (h_ctr->nonfinite) fail(DEM_ENONFINITE, "non-finite position or velocity after a step");
                 if (h_ctr->unstable) fail(DEM_EUNSTABLE, "an overlap exceeded a sphere radius (numerically exploding)");
-                if (done == 0 && !h_ctr->stall) fail(DEM_EDEVICE, "no step completed");
+                const bool stalled = h_ctr->stall[next_parity ^ 1] != 0;
+                if (done == 0 && !stalled) fail(DEM_EDEVICE, "no step completed");
+                if (done < n && !stalled) fail(DEM_EDEVICE, "steps stopped without a broad-phase request");
             }
         } catch (...) {
             for (auto e : direct_ev) (void)hipEventDestroy(e);
@@ -1142,7 +1225,7 @@ struct World {
                 // reaction on walls: minus the force on the sphere, in pair order
                 PairSnapshot p = pair_snapshot();
                 for (int k = 0; k < npairs; ++k)
-                    if (p.a[k] < 0) {
+                    if (p.a[k] < 0 && (p.nx[k] != 0.0 || p.ny[k] != 0.0 || p.nz[k] != 0.0)) {
                         const int w = -1 - p.a[k];
                         wallF[3 * w + 0] += -p.fx[k];
                         wallF[3 * w + 1] += -p.fy[k];
@@ -1739,15 +1822,7 @@ dem_status dem_get_energy(dem_scene* s, dem_energy* out)
         dem::World* w = world_of(s);
         if (!out) dem::fail(DEM_EINVAL, "null out");
         if (w->scenes.size() > 1) dem::fail(DEM_EINVAL, "dem_get_energy: energies are tracked per world, not per batch scene");
-        w->read_counters();
-        const dem::Counters& c = *w->h_ctr;
-        out->kinetic = c.e_kin;
-        out->kin_rot = c.e_rot;
-        out->elastic = c.e_el;
-        out->grav_work = c.e_grav;
-        out->damp_dissip = c.e_damp;
-        out->plastic_dissip = c.e_plast;
-        out->total = ((((c.e_kin + c.e_rot) + c.e_el) + c.e_grav) + c.e_damp) + c.e_plast;
+        w->totals(out, nullptr, nullptr, nullptr);
     });
 }
 
@@ -1755,8 +1830,8 @@ dem_status dem_get_energy(dem_scene* s, dem_energy* out)
 // contact counters are kept per world.
 static void fill_stats(dem::World* w, int s, dem_stats* out)
 {
-    w->read_counters();
-    const dem::Counters& c = *w->h_ctr;
+    unsigned long long ss = 0, sw = 0, csteps = 0;
+    w->totals(nullptr, &ss, &sw, &csteps);
     std::memset(out, 0, sizeof *out);
     int64_t nsph = 0, nw = 0;
     const int s0 = s < 0 ? 0 : s;
@@ -1772,12 +1847,12 @@ static void fill_stats(dem::World* w, int s, dem_stats* out)
     for (const auto& S : w->scenes) all += S.n_spheres;
     out->n_spheres = nsph;
     out->n_walls = nw;
-    out->n_contacts_ss = (int64_t)c.last_ss;
-    out->n_contacts_sw = (int64_t)c.last_sw;
+    out->n_contacts_ss = (int64_t)ss;
+    out->n_contacts_sw = (int64_t)sw;
     out->n_candidates = w->n_candidates;
     out->rebuilds = w->rebuilds;
-    out->contact_steps = (int64_t)c.contact_steps;
-    out->coordination = all ? 2.0 * (double)c.last_ss / (double)all : 0.0;
+    out->contact_steps = (int64_t)csteps;
+    out->coordination = all ? 2.0 * (double)ss / (double)all : 0.0;
 }
 
 dem_status dem_get_stats(dem_scene* s, dem_stats* out)
