@@ -64,7 +64,8 @@ enum {
     DEM_EDEVICE = 6,      /* HIP runtime error; message holds the HIP error string */
     DEM_ENONFINITE = 7,   /* NaN/Inf in positions or velocities after a step */
     DEM_EPERIODIC = 8,    /* periodic cell too small for the spheres and Verlet distance */
-    DEM_EUNSTABLE = 9     /* overlap exceeded a sphere radius ("numerically exploding") */
+    DEM_EUNSTABLE = 9,    /* overlap exceeded a sphere radius ("numerically exploding") */
+    DEM_EBUSY = 10        /* an asynchronous step is in flight (dem_step_async) */
 };
 
 enum { DEM_FP64 = 0, DEM_FP32_MIXED = 1 };
@@ -132,6 +133,9 @@ typedef struct {
     int64_t contact_steps;   /* sum over steps of the real contacts */
     double coordination;     /* 2 C_ss / N_spheres (utils.avgNumInteractions) */
     double verlet_dist;      /* Delta L in use [m] */
+    double max_overlap_ratio; /* largest overlap / smaller radius at the last step; past 1
+                                 the run is exploding (class InsertionSortCollider,
+                                 periodic limitations) and dem_step fails */
 } dem_stats;
 
 int32_t dem_abi_version(void);
@@ -169,6 +173,13 @@ dem_status dem_get_cell(dem_scene* s, double* hsize9, double* trsf9);
 
 /* Advance nsteps steps (O.run(n, wait=True)); returns when they are done. */
 dem_status dem_step(dem_scene* s, int64_t nsteps);
+/* O.run(n) without waiting (section 2.2.1 running simulations): the steps
+ * run on a library thread; until dem_wait returns, every other call on this
+ * scene (or its batch) returns DEM_EBUSY.  dem_wait (O.wait) joins and
+ * returns the status (and message) the steps ended with; it returns DEM_OK
+ * at once when nothing is in flight.  dem_destroy waits first. */
+dem_status dem_step_async(dem_scene* s, int64_t nsteps);
+dem_status dem_wait(dem_scene* s);
 
 /* State of `count` bodies starting at id first_id, in id order, into HOST
  * buffers; any pointer may be NULL.  force3/torque3 are the resultants of
@@ -189,6 +200,13 @@ dem_status dem_get_mass(dem_scene* s, double* mass, double* inertia);
 
 /* Real contacts of the last step, sorted by (min id, max id, cell). */
 dem_status dem_get_contacts(dem_scene* s, int64_t capacity, dem_contact* out, int64_t* out_count);
+/* O.interactions[id1, id2] (class InteractionContainer): the real contact
+ * between two bodies, looked up symmetrically (id1, id2 in either order;
+ * cell3 = image of id2 seen from id1, NULL = (0,0,0)).  DEM_ERANGE for an
+ * id out of range, DEM_ENOENT when the pair is not in contact.  Reads the
+ * contact list back from the device: meant for inspection, not for loops. */
+dem_status dem_get_interaction(dem_scene* s, int64_t id1, int64_t id2, const int32_t* cell3,
+                               dem_contact* out);
 /* Shear history (all real contacts); dem_set_history replaces it and forces
  * a broad-phase run (the records are carried onto the new candidate list). */
 dem_status dem_get_history(dem_scene* s, int64_t capacity, dem_history* out, int64_t* out_count);

@@ -93,6 +93,7 @@ __device__ inline int logical_block(int nb)
 struct ContactPartial {
     double el, plast;
     unsigned long long ss, sw;
+    double ov;
 };
 
 template <int PREC, bool BATCHED, bool PERIODIC>
@@ -107,7 +108,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
     // this step's flag starts clear; the integrate kernel may raise it
     if (blockIdx.x == 0 && threadIdx.x == 0) a.ctr->stall[parity] = 0;
     const int k = logical_block(gridDim.x) * blockDim.x + threadIdx.x;
-    ContactPartial part = {0.0, 0.0, 0ull, 0ull};
+    ContactPartial part = {0.0, 0.0, 0ull, 0ull, 0.0};
     bool unstable = false;
     if (k < a.npairs) {
         const Bodies& B = a.bod;
@@ -262,7 +263,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
                 part.sw = 1;
             else
                 part.ss = 1;
-            unstable = pen > (wall ? r2 : (r1 < r2 ? r1 : r2));
+            const double rmin = wall ? r2 : (r1 < r2 ? r1 : r2);
+            unstable = pen > rmin;
+            part.ov = pen / rmin;
         }
     }
 
@@ -279,6 +282,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
         }
         part.ss += __shfl_down(part.ss, off, 64);
         part.sw += __shfl_down(part.sw, off, 64);
+        part.ov = fmax(part.ov, __shfl_down(part.ov, off, 64));
     }
     const bool bad = __any(unstable);
     if (lane == 0) {
@@ -287,7 +291,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double el = 0.0, pl = 0.0;
+        double el = 0.0, pl = 0.0, ov = 0.0;
         unsigned long long ss = 0, sw = 0;
         uint32_t flags = 0;
         for (int w = 0; w < nwaves; ++w) {
@@ -295,6 +299,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
             pl += s_p[w].plast;
             ss += s_p[w].ss;
             sw += s_p[w].sw;
+            ov = fmax(ov, s_p[w].ov);
             flags |= s_bad[w];
         }
         ContactAcc& acc = a.acc_contact[blockIdx.x];
@@ -306,6 +311,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
         acc.sw = sw;
         acc.ss_cum += ss;
         acc.sw_cum += sw;
+        acc.max_ov = ov;
         if (flags) a.ctr->unstable = 1;
     }
 }

@@ -128,6 +128,8 @@ struct ContactAcc {
     double plast;                   // plastic work, cumulative
     unsigned long long ss, sw;      // real contacts of the last step
     unsigned long long ss_cum, sw_cum;
+    double max_ov;                  // largest overlap / smaller radius, last step
+    double pad_;
 };
 
 // Per-block slots of the integrate kernel.

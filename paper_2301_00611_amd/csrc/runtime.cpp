@@ -9,6 +9,7 @@
 // Internally every body (wall or sphere) of the world has a global index
 // (gid); each scene maps its own ids (0, 1, ... in insertion order) to gids.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -16,6 +17,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "dem_internal.hpp"
@@ -222,6 +224,13 @@ struct KernelTimer {
 };
 
 struct World {
+    // asynchronous stepping: while `busy` is set every call but dem_wait is
+    // refused; the worker's outcome is handed to dem_wait
+    std::thread worker;
+    std::atomic<int> busy{0};
+    dem_status async_rc = DEM_OK;
+    std::string async_msg;
+
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -259,6 +268,7 @@ struct World {
     // last-step values kept across a fold until the next step runs
     double last_el = 0.0, last_kin = 0.0, last_rot = 0.0;
     unsigned long long last_ss = 0, last_sw = 0;
+    double last_maxov = 0.0;
     bool slots_fresh = true;           // no step has written the slots since the last fold
     std::vector<SceneParams> sp;       // host copy of the scene table
     Counters* h_ctr = nullptr;         // pinned
@@ -281,7 +291,11 @@ struct World {
     bool timing = false;
     std::map<std::string, KernelTimer> timers;
 
-    ~World() { release(); }
+    ~World()
+    {
+        if (worker.joinable()) worker.join();
+        release();
+    }
     void release()
     {
         for (auto& kv : graphs) {
@@ -656,7 +670,9 @@ struct World {
         }
         // grid per scene
         std::vector<double> bnd(6 * (size_t)nsc, 0.0);
-        if (!periodic && nslots > 0) {
+        // bounds: the grid of an aperiodic scene; in both cases the check
+        // that no position went non-finite before it is binned
+        if (nslots > 0) {
             d_bounds.ensure(sizeof(double) * 6 * nsc);
             radix_tmp.ensure(std::max(radix_temp_bytes(nslots), bounds_temp_bytes(nslots)));
             launch_bounds(bs[active].view(), nslots, nsc, d_bounds.as<double>(), radix_tmp.p, stream);
@@ -862,6 +878,8 @@ struct World {
         C.verlet_cell_step = cell_step;
         C.stall[0] = C.stall[1] = 0;
         C.steps_done = 0;
+        C.nonfinite = 0;  // positions are finite (checked above); an earlier
+        C.unstable = 0;   // failure was repaired with dem_set_state
         next_parity = 0;
         HIPC(hipMemcpyAsync(d_ctr.p, h_ctr, sizeof(Counters), hipMemcpyHostToDevice, stream));
         HIPC(hipStreamSynchronize(stream));
@@ -873,7 +891,7 @@ struct World {
     // Sum the per-block slots in block order.  cum = true: add the running
     // sums to the bases and clear the slots (before the grids change).
     struct SlotSums {
-        double el = 0, plast = 0, kin = 0, rot = 0, grav = 0, damp = 0;
+        double el = 0, plast = 0, kin = 0, rot = 0, grav = 0, damp = 0, maxov = 0;
         unsigned long long ss = 0, sw = 0, cum = 0;
     };
     SlotSums read_slots()
@@ -890,6 +908,7 @@ struct World {
             t.ss += a.ss;
             t.sw += a.sw;
             t.cum += a.ss_cum + a.sw_cum;
+            t.maxov = std::max(t.maxov, a.max_ov);
         }
         for (const IntAcc& a : i) {
             t.kin += a.kin;
@@ -913,11 +932,13 @@ struct World {
             last_rot = t.rot;
             last_ss = t.ss;
             last_sw = t.sw;
+            last_maxov = t.maxov;
         }
         slots_fresh = true;
     }
     // Energies and contact counts as reported: bases + current slots.
-    void totals(dem_energy* e, unsigned long long* ss, unsigned long long* sw, unsigned long long* csteps)
+    void totals(dem_energy* e, unsigned long long* ss, unsigned long long* sw, unsigned long long* csteps,
+                double* maxov = nullptr)
     {
         const SlotSums t = read_slots();
         const bool fresh = slots_fresh;
@@ -934,6 +955,7 @@ struct World {
         if (ss) *ss = fresh ? last_ss : t.ss;
         if (sw) *sw = fresh ? last_sw : t.sw;
         if (csteps) *csteps = base_contact_steps + t.cum;
+        if (maxov) *maxov = fresh ? last_maxov : t.maxov;
     }
 
     // ------------------------------------------------------------ step
@@ -1567,8 +1589,16 @@ void check_params(const dem_params* p)
 dem::World* world_of(dem_scene* s)
 {
     if (!s || !s->w) dem::fail(DEM_EINVAL, "null scene");
+    if (s->w->busy.load()) dem::fail(DEM_EBUSY, "an asynchronous step is in flight: call dem_wait first");
     HIPC(hipSetDevice(s->w->device));
     return s->w;
+}
+
+void check_steppable(dem_scene* s, dem::World* w)
+{
+    if (!s->owner) dem::fail(DEM_EINVAL, "dem_step: step the batch, not one of its scenes");
+    for (const auto& S : w->scenes)
+        if (!(S.p.dt > 0.0)) dem::fail(DEM_EINVAL, "dem_step: dt is not set");
 }
 
 }  // namespace
@@ -1607,6 +1637,7 @@ dem_status dem_destroy(dem_scene* s)
     return guarded([&] {
         if (!s) dem::fail(DEM_EINVAL, "null scene");
         if (!s->owner) dem::fail(DEM_EINVAL, "dem_destroy: batch views are owned by the batch");
+        if (s->w->worker.joinable()) s->w->worker.join();
         (void)hipSetDevice(s->w->device);
         delete s->w;
         delete s;
@@ -1698,10 +1729,74 @@ dem_status dem_step(dem_scene* s, int64_t nsteps)
 {
     return guarded([&] {
         dem::World* w = world_of(s);
-        if (!s->owner) dem::fail(DEM_EINVAL, "dem_step: step the batch, not one of its scenes");
-        for (const auto& S : w->scenes)
-            if (!(S.p.dt > 0.0)) dem::fail(DEM_EINVAL, "dem_step: dt is not set");
+        check_steppable(s, w);
         w->step(nsteps);
+    });
+}
+
+dem_status dem_step_async(dem_scene* s, int64_t nsteps)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        check_steppable(s, w);
+        if (nsteps < 0) dem::fail(DEM_EINVAL, "nsteps < 0");
+        if (w->worker.joinable()) w->worker.join();
+        w->async_rc = DEM_OK;
+        w->async_msg.clear();
+        w->busy.store(1);
+        w->worker = std::thread([w, nsteps] {
+            // the same guard as the synchronous call, on the worker thread;
+            // its message is moved to the thread that calls dem_wait
+            w->async_rc = guarded([&] {
+                HIPC(hipSetDevice(w->device));
+                w->step(nsteps);
+            });
+            w->async_msg = dem::g_err;
+        });
+    });
+}
+
+dem_status dem_wait(dem_scene* s)
+{
+    if (!s || !s->w) {
+        dem::g_err = "null scene";
+        return DEM_EINVAL;
+    }
+    dem::World* w = s->w;
+    if (w->worker.joinable()) w->worker.join();
+    const bool was_busy = w->busy.exchange(0) != 0;
+    if (!was_busy) {
+        dem::g_err.clear();
+        return DEM_OK;
+    }
+    dem::g_err = w->async_msg;
+    return w->async_rc;
+}
+
+dem_status dem_get_interaction(dem_scene* s, int64_t id1, int64_t id2, const int32_t* cell3, dem_contact* out)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        if (!out) dem::fail(DEM_EINVAL, "null out");
+        const int64_t nb = (int64_t)w->scenes[s->s].gids.size();
+        if (id1 < 0 || id2 < 0 || id1 >= nb || id2 >= nb) dem::fail(DEM_ERANGE, "body id out of range");
+        int32_t c[3] = {0, 0, 0};
+        if (cell3)
+            for (int q = 0; q < 3; ++q) c[q] = cell3[q];
+        // symmetric lookup: the record keeps #1 = lower id (wall first), and
+        // the image is that of #2 seen from #1
+        const std::vector<dem_contact> all = w->contacts(s->s);
+        for (const dem_contact& k : all) {
+            if (k.id1 == id1 && k.id2 == id2 && k.cell[0] == c[0] && k.cell[1] == c[1] && k.cell[2] == c[2]) {
+                *out = k;
+                return;
+            }
+            if (k.id1 == id2 && k.id2 == id1 && k.cell[0] == -c[0] && k.cell[1] == -c[1] && k.cell[2] == -c[2]) {
+                *out = k;
+                return;
+            }
+        }
+        dem::fail(DEM_ENOENT, "no real interaction between these bodies");
     });
 }
 
@@ -1831,7 +1926,8 @@ dem_status dem_get_energy(dem_scene* s, dem_energy* out)
 static void fill_stats(dem::World* w, int s, dem_stats* out)
 {
     unsigned long long ss = 0, sw = 0, csteps = 0;
-    w->totals(nullptr, &ss, &sw, &csteps);
+    double maxov = 0.0;
+    w->totals(nullptr, &ss, &sw, &csteps, &maxov);
     std::memset(out, 0, sizeof *out);
     int64_t nsph = 0, nw = 0;
     const int s0 = s < 0 ? 0 : s;
@@ -1853,6 +1949,7 @@ static void fill_stats(dem::World* w, int s, dem_stats* out)
     out->rebuilds = w->rebuilds;
     out->contact_steps = (int64_t)csteps;
     out->coordination = all ? 2.0 * (double)ss / (double)all : 0.0;
+    out->max_overlap_ratio = maxov;
 }
 
 dem_status dem_get_stats(dem_scene* s, dem_stats* out)

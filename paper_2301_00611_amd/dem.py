@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdem_hip.so")
 
 DEM_OK, DEM_EINVAL, DEM_ERANGE, DEM_ENOENT, DEM_ECAPACITY, DEM_ENOMEM, DEM_EDEVICE = range(7)
-DEM_ENONFINITE, DEM_EPERIODIC, DEM_EUNSTABLE = 7, 8, 9
+DEM_ENONFINITE, DEM_EPERIODIC, DEM_EUNSTABLE, DEM_EBUSY = 7, 8, 9, 10
 DEM_FP64, DEM_FP32_MIXED = 0, 1
 
 _DP = C.POINTER(C.c_double)
@@ -72,7 +72,7 @@ class dem_stats(C.Structure):
         ("iter", C.c_int64), ("time", C.c_double), ("n_spheres", C.c_int64), ("n_walls", C.c_int64),
         ("n_contacts_ss", C.c_int64), ("n_contacts_sw", C.c_int64), ("n_candidates", C.c_int64),
         ("rebuilds", C.c_int64), ("contact_steps", C.c_int64), ("coordination", C.c_double),
-        ("verlet_dist", C.c_double),
+        ("verlet_dist", C.c_double), ("max_overlap_ratio", C.c_double),
     ]
 
 
@@ -103,11 +103,14 @@ SIGNATURES = {
     "dem_set_velgrad": (C.c_int32, [C.c_void_p, _DP]),
     "dem_get_cell": (C.c_int32, [C.c_void_p, _DP, _DP]),
     "dem_step": (C.c_int32, [C.c_void_p, C.c_int64]),
+    "dem_step_async": (C.c_int32, [C.c_void_p, C.c_int64]),
+    "dem_wait": (C.c_int32, [C.c_void_p]),
     "dem_get_state": (C.c_int32, [C.c_void_p, C.c_int64, C.c_int64, _DP, _DP, _DP, _DP, _DP, _DP]),
     "dem_get_state_device": (C.c_int32, [C.c_void_p, C.c_int64, C.c_int64, _DP, _DP, _DP, _DP]),
     "dem_set_state": (C.c_int32, [C.c_void_p, _DP, _DP, _DP, _DP]),
     "dem_get_mass": (C.c_int32, [C.c_void_p, _DP, _DP]),
     "dem_get_contacts": (C.c_int32, [C.c_void_p, C.c_int64, C.POINTER(dem_contact), _I64P]),
+    "dem_get_interaction": (C.c_int32, [C.c_void_p, C.c_int64, C.c_int64, _I32P, C.POINTER(dem_contact)]),
     "dem_get_history": (C.c_int32, [C.c_void_p, C.c_int64, C.POINTER(dem_history), _I64P]),
     "dem_set_history": (C.c_int32, [C.c_void_p, C.c_int64, C.POINTER(dem_history)]),
     "dem_get_energy": (C.c_int32, [C.c_void_p, C.POINTER(dem_energy)]),
@@ -260,6 +263,12 @@ class Scene:
     def step(self, n=1):
         check(self.lib.dem_step(self.h, int(n)), "dem_step")
 
+    def step_async(self, n=1):
+        check(self.lib.dem_step_async(self.h, int(n)), "dem_step_async")
+
+    def wait(self):
+        check(self.lib.dem_wait(self.h), "dem_wait")
+
     # reading
     def stats(self):
         s = dem_stats()
@@ -308,6 +317,15 @@ class Scene:
         check(self.lib.dem_get_contacts(self.h, cnt.value, arr.ctypes.data_as(C.POINTER(dem_contact)),
                                         C.byref(cnt)), "dem_get_contacts")
         return arr[: cnt.value]
+
+    def get_interaction(self, id1, id2, cell=None):
+        """The real contact between id1 and id2 (either order) as a
+        CONTACT_DTYPE record; DemError with code DEM_ENOENT if none."""
+        out = np.zeros(1, dtype=CONTACT_DTYPE)
+        c = None if cell is None else np.ascontiguousarray(cell, dtype=np.int32).reshape(3)
+        check(self.lib.dem_get_interaction(self.h, int(id1), int(id2), _p(c, _I32P),
+                                           out.ctypes.data_as(C.POINTER(dem_contact))), "dem_get_interaction")
+        return out[0]
 
     def get_history(self):
         cnt = C.c_int64()

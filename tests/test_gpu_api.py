@@ -1,0 +1,172 @@
+"""The C ABI's documented behaviour on a GPU: error codes, asynchronous
+stepping, the symmetric interaction lookup and the statistics record.
+Every failure here is forced from the host (bad arguments, states the
+library must refuse); no kernel is made to fault."""
+import numpy as np
+import pytest
+
+from paper_2301_00611_amd import dem
+from paper_2301_00611_amd.scenes import cloud_box
+
+pytestmark = pytest.mark.gpu
+
+
+def _scene(**kw):
+    s = dem.Scene(gravity=(0.0, 0.0, -9.81), **kw)
+    m = s.add_material(2600.0, 1e7, 0.3, 0.5)
+    return s, m
+
+
+def _code(fn, *a, **kw):
+    with pytest.raises(dem.DemError) as e:
+        fn(*a, **kw)
+    return e.value.code
+
+
+def _settling_box(seed=3, n=200):
+    sc = cloud_box(n=n, box=0.016, seed=seed)
+    s = dem.Scene(gravity=sc.gravity, damping=sc.damping)
+    m = s.add_material(sc.material.density, sc.material.young, sc.material.poisson, sc.material.friction)
+    for w in sc.walls:
+        s.add_wall(w.axis, w.position, w.sense, m)
+    s.add_spheres(sc.pos, sc.radius, default_mat=m)
+    s.set_dt(sc.dt_factor * s.pwave_dt())
+    return s, sc
+
+
+def test_invalid_arguments():
+    s, m = _scene()
+    assert _code(s.add_spheres, np.zeros((1, 3)), np.zeros(1), default_mat=m) == dem.DEM_EINVAL   # r = 0
+    assert _code(s.add_spheres, np.zeros((1, 3)), np.ones(1), default_mat=7) == dem.DEM_EINVAL    # no such material
+    assert _code(s.add_wall, 3, 0.0, 0, m) == dem.DEM_EINVAL
+    assert _code(s.add_wall, 0, 0.0, 2, m) == dem.DEM_EINVAL
+    assert _code(s.add_material, -1.0, 1e7, 0.3, 0.5) == dem.DEM_EINVAL
+    assert _code(s.add_material, 2600.0, 1e7, 0.7, 0.5) == dem.DEM_EINVAL
+    assert _code(s.set_dt, 0.0) == dem.DEM_EINVAL
+    assert _code(s.set_velgrad, np.zeros(9)) == dem.DEM_EINVAL                                     # not periodic
+    s.add_spheres(np.array([[0.0, 0.0, 0.0]]), np.array([1e-3]), default_mat=m)
+    assert _code(s.step, 1) == dem.DEM_EINVAL                                                      # dt not set
+    assert _code(s.set_state, vel=np.full((1, 3), np.nan)) == dem.DEM_EINVAL
+    s.set_dt(1e-6)
+    s.step(3)
+    assert s.stats()["iter"] == 3
+    assert _code(s.step, -1) == dem.DEM_EINVAL
+    s.close()
+
+
+def test_range_and_capacity():
+    s, sc = _settling_box()
+    s.step(3000)
+    nb = s.num_bodies
+    assert _code(s.get_state, nb, 1) == dem.DEM_ERANGE
+    assert _code(s.get_state, -1, 1) == dem.DEM_ERANGE
+    lib = dem.load()
+    cnt = dem.C.c_int64()
+    rc = lib.dem_get_contacts(s.h, 0, None, dem.C.byref(cnt))
+    assert rc == dem.DEM_ECAPACITY and cnt.value == len(s.get_contacts()) > 0
+    assert _code(s.get_interaction, 0, nb) == dem.DEM_ERANGE
+    s.close()
+
+
+def test_interaction_lookup_is_symmetric():
+    s, sc = _settling_box()
+    s.step(3000)
+    c = s.get_contacts()
+    assert len(c) > 0
+    touching = {(int(a), int(b)) for a, b in zip(c["id1"], c["id2"])}
+    for rec in c[:20]:
+        a, b = int(rec["id1"]), int(rec["id2"])
+        fwd = s.get_interaction(a, b)
+        rev = s.get_interaction(b, a)
+        assert fwd.tobytes() == rev.tobytes() == rec.tobytes()
+    nw = len(sc.walls)
+    for i in range(nw, nw + 50):
+        j = i + 1
+        if (i, j) not in touching:
+            assert _code(s.get_interaction, i, j) == dem.DEM_ENOENT
+            break
+    s.close()
+
+
+def test_async_step_equals_sync_and_refuses_other_calls():
+    a, _ = _settling_box(seed=4)
+    b, _ = _settling_box(seed=4)
+    a.step(500)
+    b.step_async(500)
+    assert _code(b.stats) == dem.DEM_EBUSY
+    assert _code(b.step, 1) == dem.DEM_EBUSY
+    b.wait()
+    b.wait()  # nothing in flight: returns at once
+    sa, sb = a.get_state(), b.get_state()
+    for k in ("pos", "vel", "angvel", "ori", "force", "torque"):
+        assert np.array_equal(sa[k], sb[k]), k
+    assert a.stats()["iter"] == b.stats()["iter"] == 500
+    a.close()
+    b.close()
+
+
+def test_async_error_is_reported_by_wait():
+    s, m = _scene()
+    s.add_spheres(np.array([[0.0, 0.0, 0.0], [0.5e-3, 0.0, 0.0]]), np.array([1e-3, 1e-3]), default_mat=m)
+    s.set_dt(1e-7)
+    s.step_async(10)
+    assert _code(s.wait) == dem.DEM_EUNSTABLE
+    s.close()
+
+
+def test_unstable_overlap():
+    s, m = _scene()
+    # centres half a radius apart: overlap 1.5 r
+    s.add_spheres(np.array([[0.0, 0.0, 0.0], [0.5e-3, 0.0, 0.0]]), np.array([1e-3, 1e-3]), default_mat=m)
+    s.set_dt(1e-7)
+    assert _code(s.step, 5) == dem.DEM_EUNSTABLE
+    # the slot holds the last of the 5 steps; the pair has barely moved
+    assert s.stats()["max_overlap_ratio"] == pytest.approx(1.5, rel=1e-3)
+    # repaired by moving them apart; the scene keeps working
+    s.set_state(pos=np.array([[0.0, 0.0, 0.0], [1.99e-3, 0.0, 0.0]]), vel=np.zeros((2, 3)),
+                angvel=np.zeros((2, 3)))
+    s.step(5)
+    st = s.stats()
+    assert st["n_contacts_ss"] == 1 and 0.0 < st["max_overlap_ratio"] < 0.02
+    s.close()
+
+
+def test_nonfinite_state_then_repair():
+    s = dem.Scene(gravity=(0.0, 0.0, -1e308))
+    m = s.add_material(2600.0, 1e7, 0.3, 0.5)
+    s.add_spheres(np.array([[0.0, 0.0, 0.0], [0.1, 0.0, 0.0]]), np.array([1e-3, 1e-3]), default_mat=m)
+    s.set_dt(1.0)
+    assert _code(s.step, 10) == dem.DEM_ENONFINITE
+    assert _code(s.step, 10) == dem.DEM_ENONFINITE
+    s.set_state(pos=np.array([[0.0, 0.0, 0.0], [0.1, 0.0, 0.0]]), vel=np.zeros((2, 3)))
+    s.set_dt(1e-6)
+    s.step(1)
+    assert np.all(np.isfinite(s.get_state()["pos"]))
+    s.close()
+
+
+def test_periodic_cell_too_small():
+    h = np.diag([5e-3, 5e-3, 5e-3])
+    s = dem.Scene(periodic=True, hsize=h)
+    m = s.add_material(2600.0, 1e7, 0.3, 0.5)
+    assert _code(s.add_wall, 2, 0.0, 1, m) == dem.DEM_EINVAL  # walls are not allowed in a periodic cell
+    s.add_spheres(np.array([[1e-3, 1e-3, 1e-3]]), np.array([1e-3]), default_mat=m)
+    s.set_dt(1e-6)
+    assert _code(s.step, 1) == dem.DEM_EPERIODIC
+    s.close()
+
+
+def test_batch_views():
+    p = [dem.make_params(dt=1e-6, gravity=(0, 0, -9.81)) for _ in range(3)]
+    b = dem.Batch(p)
+    assert _code(b.scene, 3) == dem.DEM_ERANGE
+    v = b.scene(1)
+    m = v.add_material(2600.0, 1e7, 0.3, 0.5)
+    v.add_spheres(np.array([[0.0, 0.0, 0.01]]), np.array([1e-3]), default_mat=m)
+    assert _code(v.step, 1) == dem.DEM_EINVAL         # step the batch, not a view
+    assert _code(v.step_async, 1) == dem.DEM_EINVAL
+    lib = dem.load()
+    assert lib.dem_destroy(v.h) == dem.DEM_EINVAL      # views are owned by the batch
+    b.step(10)
+    assert b.stats()["iter"] == 10
+    b.close()
