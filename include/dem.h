@@ -213,6 +213,13 @@ dem_status dem_get_history(dem_scene* s, int64_t capacity, dem_history* out, int
 dem_status dem_set_history(dem_scene* s, int64_t n, const dem_history* in);
 
 dem_status dem_get_energy(dem_scene* s, dem_energy* out);
+/* utils.getStress (Love-Weber): sigma_ij = (1/V) sum over the real
+ * sphere-sphere contacts of the last step of f_i l_j, f the force on #2 and
+ * l the branch vector from #2 to #1 (negative under compression).  Wall
+ * contacts are left out.  volume <= 0 takes the periodic cell's volume
+ * (DEM_EINVAL for an aperiodic scene).  sigma9 is a host buffer of 9
+ * doubles, row-major. */
+dem_status dem_get_stress(dem_scene* s, double volume, double* sigma9);
 dem_status dem_get_stats(dem_scene* s, dem_stats* out);
 /* Average device duration [ms] of each kernel family over the last
  * dem_step call (names: "contact", "integrate", "rebuild"), measured with

@@ -954,6 +954,31 @@ int orc_get_energy(const orc_scene* s, double* out7)
     return ORC_OK;
 }
 
+/* utils.getStress (Love-Weber stress, utility reference of section 5):
+ * sigma_ij = (1/V) sum over the real contacts of f_i l_j, f the force on #2,
+ * l the branch vector from #2 to #1 (the negated detection vector), so that
+ * repulsion gives negative stress.  Wall contacts are left out. */
+int orc_get_stress(const orc_scene* s, double volume, double* sigma9)
+{
+    if (!s || !sigma9) return fail(ORC_EINVAL, "null argument");
+    double V = volume;
+    if (!(V > 0.0)) {
+        if (!s->p.periodic) return fail(ORC_EINVAL, "orc_get_stress: give the volume of an aperiodic scene");
+        const double* H = s->H;
+        V = fabs(H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
+                 H[2] * (H[3] * H[7] - H[4] * H[6]));
+    }
+    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (long k = 0; k < s->nc; ++k) {
+        const cont_t* ct = &s->c[k];
+        if (ct->is_wall) continue;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) acc[3 * i + j] += ct->f2[i] * (-ct->det_d[j]);
+    }
+    for (int q = 0; q < 9; ++q) sigma9[q] = acc[q] / V;
+    return ORC_OK;
+}
+
 int orc_get_cell(const orc_scene* s, double* hsize9, double* trsf9)
 {
     if (!s) return fail(ORC_EINVAL, "null scene");

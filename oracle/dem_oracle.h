@@ -107,6 +107,10 @@ int orc_set_contacts(orc_scene* s, long n, const long* id1, const long* id2,
 /* kinetic, kin_rot, elastic, grav_work, damp_dissip, plastic_dissip, total */
 int orc_get_energy(const orc_scene* s, double* out7);
 int orc_get_cell(const orc_scene* s, double* hsize9, double* trsf9);
+/* Love-Weber stress of the last step's sphere-sphere contacts (force on #2
+ * times the branch vector from #2 to #1, over V; V <= 0 takes the periodic
+ * cell's volume). */
+int orc_get_stress(const orc_scene* s, double volume, double* sigma9);
 
 /* Real pairs at the CURRENT positions (no step), by brute force. */
 int orc_detect_pairs(const orc_scene* s, long capacity, long* id1, long* id2,

@@ -92,6 +92,7 @@ def load_library(path: str | None = None):
         "orc_set_contacts": [C.c_void_p, C.c_long, _LP, _LP, _IP, _DP, _DP],
         "orc_get_energy": [C.c_void_p, _DP],
         "orc_get_cell": [C.c_void_p, _DP, _DP],
+        "orc_get_stress": [C.c_void_p, C.c_double, _DP],
         "orc_detect_pairs": [C.c_void_p, C.c_long, _LP, _LP, _IP, _LP],
         "orc_spot_step": [C.c_void_p, C.c_long, _LP, _DP, _DP, _DP, _DP, _DP, _DP, _LP],
     }
@@ -247,6 +248,11 @@ class OracleScene:
         out = np.zeros(7)
         self._check(self.lib.orc_get_energy(self._h, _ptr(out)), "get_energy")
         return dict(zip(ENERGY_KEYS, out.tolist()))
+
+    def get_stress(self, volume=0.0):
+        out = np.zeros(9)
+        self._check(self.lib.orc_get_stress(self._h, float(volume), _ptr(out)), "get_stress")
+        return out.reshape(3, 3)
 
     def get_cell(self):
         h, t = np.zeros(9), np.zeros(9)

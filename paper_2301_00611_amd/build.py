@@ -22,7 +22,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libdem_hip.so")
 ARCH = os.environ.get("DEM_OFFLOAD_ARCH", "gfx950")
 
-DEVICE_SOURCES = ["prim.hip", "broadphase.hip", "contact.hip", "integrate.hip"]
+DEVICE_SOURCES = ["prim.hip", "broadphase.hip", "contact.hip", "integrate.hip", "stress.hip"]
 HOST_SOURCES = ["runtime.cpp"]
 
 COMMON = ["-std=c++17", "-O3", "-fPIC", "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-Wall",

@@ -231,6 +231,10 @@ void launch_integrate(const StepArgs* args, int parity, int grid, int precision,
                       int block, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_cell_update(const StepArgs* args, int parity, hipStream_t st);
 void launch_body_forces(const StepArgs& a, int precision, double* f3, double* t3, hipStream_t st);
+// Love-Weber stress partial sums (9 doubles per block) of the last step's
+// real sphere-sphere contacts; `scene` selects a batch scene.
+int stress_blocks(int npairs);
+void launch_stress(const StepArgs& a, int precision, bool batched, int scene, double* part, hipStream_t st);
 
 
 }  // namespace dem

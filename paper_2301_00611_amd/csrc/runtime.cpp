@@ -1342,6 +1342,37 @@ struct World {
         c[2] = (int32_t)(u & 1023u) - 512;
     }
 
+    // Love-Weber stress of scene s: partial sums per block on the device,
+    // combined here in block order, divided by the volume (periodic: the
+    // cell's, else the caller's).
+    void stress(int s, double volume, double* out9)
+    {
+        double V = volume;
+        if (!(V > 0.0)) {
+            if (!scenes[s].p.periodic) fail(DEM_EINVAL, "dem_get_stress: give the volume of an aperiodic scene");
+            pull_scene_table();
+            const double* H = sp[s].H;
+            V = std::fabs(H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
+                          H[2] * (H[3] * H[7] - H[4] * H[6]));
+        }
+        if (!std::isfinite(V) || !(V > 0.0)) fail(DEM_EINVAL, "dem_get_stress: volume must be > 0");
+        double sum[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if (host_dirty) upload_bodies();
+        const int nb = (contacts_valid && npairs > 0) ? stress_blocks(npairs) : 0;
+        if (nb > 0) {
+            d_tmp3.ensure(sizeof(double) * 9 * (size_t)nb);
+            StepArgs a = step_args();
+            launch_stress(a, precision, scenes.size() > 1, s, d_tmp3.as<double>(), stream);
+            HIPC(hipGetLastError());
+            std::vector<double> part(9 * (size_t)nb);
+            HIPC(hipMemcpyAsync(part.data(), d_tmp3.p, sizeof(double) * part.size(), hipMemcpyDeviceToHost, stream));
+            HIPC(hipStreamSynchronize(stream));
+            for (int b = 0; b < nb; ++b)
+                for (int q = 0; q < 9; ++q) sum[q] += part[9 * (size_t)b + q];
+        }
+        for (int q = 0; q < 9; ++q) out9[q] = sum[q] / V;
+    }
+
     std::vector<dem_contact> contacts(int s)
     {
         std::vector<dem_contact> out;
@@ -1908,6 +1939,15 @@ dem_status dem_set_history(dem_scene* s, int64_t n, const dem_history* in)
     return guarded([&] {
         dem::World* w = world_of(s);
         w->set_history(s->s, n, in);
+    });
+}
+
+dem_status dem_get_stress(dem_scene* s, double volume, double* sigma9)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        if (!sigma9) dem::fail(DEM_EINVAL, "null out");
+        w->stress(s->s, volume, sigma9);
     });
 }
 

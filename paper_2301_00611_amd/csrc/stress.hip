@@ -1,0 +1,84 @@
+// stress.hip -- the Love-Weber stress of the contact network
+// (utils.getStress, section 5 utility reference): the sum over the real
+// sphere-sphere contacts of f (x) l, where f is the force on #2 and l the
+// branch vector from #2 to #1, so that repulsive contacts give negative
+// (compressive) stress.  Divided by the volume on the host.
+//
+// Run on demand, not in the step: it reads the pair records the last step
+// wrote.  The branch is rebuilt from the stored normal and overlap:
+// l = -(r1 + r2 - pen) n with pen = |F - Fs| / kn, the same quantities the
+// contact kernel used.  One partial sum of 9 doubles per block, combined in
+// a fixed order (waves, then blocks on the host): deterministic.
+#include "dem_internal.hpp"
+
+namespace dem {
+
+namespace {
+
+constexpr int kStressBlock = 256;
+
+template <int PREC, bool BATCHED>
+__global__ void __launch_bounds__(kStressBlock) k_stress(StepArgs a, int scene, double* __restrict__ part)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    double s[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const Pairs& P = a.pr;
+    if (k < a.npairs && P.real[k] && P.a[k] >= 0) {
+        const Bodies& B = a.bod;
+        const int sa = P.a[k], sb = P.b[k];
+        if (!BATCHED || (int)B.scene[sb] == scene) {
+            double F[3];
+            if (PREC == DEM_FP32_MIXED) {
+                F[0] = (double)P.fxf[k];
+                F[1] = (double)P.fyf[k];
+                F[2] = (double)P.fzf[k];
+            } else {
+                F[0] = P.fx[k];
+                F[1] = P.fy[k];
+                F[2] = P.fz[k];
+            }
+            const double n[3] = {P.nx[k], P.ny[k], P.nz[k]};
+            const double fn[3] = {F[0] - P.fsx[k], F[1] - P.fsy[k], F[2] - P.fsz[k]};
+            const double r1 = B.rad[sa], r2 = B.rad[sb];
+            const Material M1 = a.mats[B.mat[sa]], M2 = a.mats[B.mat[sb]];
+            const double k1 = M1.young * (2.0 * r1), k2 = M2.young * (2.0 * r2);
+            const double kn = k1 * k2 / (k1 + k2);
+            const double pen = sqrt(fn[0] * fn[0] + fn[1] * fn[1] + fn[2] * fn[2]) / kn;
+            const double lm = (r1 + r2) - pen;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) s[3 * i + j] = F[i] * (-lm * n[j]);
+        }
+    }
+    __shared__ double sh[kStressBlock / 64][9];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int q = 0; q < 9; ++q)
+        for (int off = 32; off > 0; off >>= 1) s[q] += __shfl_down(s[q], off, 64);
+    if (lane == 0)
+        for (int q = 0; q < 9; ++q) sh[wave][q] = s[q];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 9; ++q) {
+            double t = 0.0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w][q];
+            part[9 * (size_t)blockIdx.x + q] = t;
+        }
+}
+
+}  // namespace
+
+int stress_blocks(int npairs) { return npairs > 0 ? (npairs + kStressBlock - 1) / kStressBlock : 0; }
+
+void launch_stress(const StepArgs& a, int precision, bool batched, int scene, double* part, hipStream_t st)
+{
+    const int grid = stress_blocks(a.npairs);
+    if (grid == 0) return;
+    if (precision == DEM_FP32_MIXED) {
+        if (batched) hipLaunchKernelGGL((k_stress<DEM_FP32_MIXED, true>), dim3(grid), dim3(kStressBlock), 0, st, a, scene, part);
+        else hipLaunchKernelGGL((k_stress<DEM_FP32_MIXED, false>), dim3(grid), dim3(kStressBlock), 0, st, a, scene, part);
+    } else {
+        if (batched) hipLaunchKernelGGL((k_stress<DEM_FP64, true>), dim3(grid), dim3(kStressBlock), 0, st, a, scene, part);
+        else hipLaunchKernelGGL((k_stress<DEM_FP64, false>), dim3(grid), dim3(kStressBlock), 0, st, a, scene, part);
+    }
+}
+
+}  // namespace dem

@@ -114,6 +114,7 @@ SIGNATURES = {
     "dem_get_history": (C.c_int32, [C.c_void_p, C.c_int64, C.POINTER(dem_history), _I64P]),
     "dem_set_history": (C.c_int32, [C.c_void_p, C.c_int64, C.POINTER(dem_history)]),
     "dem_get_energy": (C.c_int32, [C.c_void_p, C.POINTER(dem_energy)]),
+    "dem_get_stress": (C.c_int32, [C.c_void_p, C.c_double, _DP]),
     "dem_get_stats": (C.c_int32, [C.c_void_p, C.POINTER(dem_stats)]),
     "dem_set_timing": (C.c_int32, [C.c_void_p, C.c_int32]),
     "dem_get_timing": (C.c_int32, [C.c_void_p, C.c_char_p, _DP, _I64P]),
@@ -354,6 +355,11 @@ class Scene:
         e = dem_energy()
         check(self.lib.dem_get_energy(self.h, C.byref(e)), "dem_get_energy")
         return {k: getattr(e, k) for k, _ in dem_energy._fields_}
+
+    def get_stress(self, volume=0.0):
+        out = np.zeros(9)
+        check(self.lib.dem_get_stress(self.h, float(volume), _p(out)), "dem_get_stress")
+        return out.reshape(3, 3)
 
     def set_timing(self, on=True):
         check(self.lib.dem_set_timing(self.h, 1 if on else 0), "dem_set_timing")

@@ -210,6 +210,8 @@ def test_periodic_shear_parity():
         crossing += int((np.abs(co["cell"]).sum(axis=1) > 0).sum())
         if len(co):
             assert contact_errors(cg, co)["f"].max() <= 1e-9
+            sg, so = g.get_stress(), o.get_stress()
+            assert np.abs(sg - so).max() <= 1e-9 * np.abs(so).max()
     assert crossing > 0
     hg, tg = g.get_cell()
     ho, to = o.get_cell()
@@ -299,3 +301,34 @@ def test_invariants_over_a_long_run():
         total = st["force"].sum(axis=0)
         assert np.linalg.norm(total) <= 1e-9 * np.abs(st["force"]).sum()
         assert np.all(np.isfinite(st["pos"]))
+
+
+def test_love_weber_stress_closed_form_and_oracle():
+    """dem_get_stress on the sheared lattice: the closed form
+    sigma_xx = -kn delta/a_y^2, sigma_yx = -fs/a_y^2 (others 0), and the
+    oracle's value from the same state and history."""
+    from lattice import sheared_lattice
+    from oracle import OracleScene
+    from paper_2301_00611_amd import dem
+    delta, fs, r = 2e-6, 1e-3, 1e-3
+    L = sheared_lattice(delta=delta, fs=fs, r=r)
+    g = dem.Scene(periodic=True, hsize=L["hsize"], damping=0.0)
+    g.add_material(2600.0, L["young"], 0.3, 0.5)
+    g.add_spheres(L["pos"], L["radius"])
+    g.set_dt(1e-8)
+    g.set_history(L["id1"], L["id2"], L["fs"], L["nprev"], cell=L["cell"])
+    o = OracleScene(dt=1e-8, periodic=True, hsize=L["hsize"])
+    o.add_material(2600.0, L["young"], 0.3, 0.5)
+    o.add_spheres(L["pos"], L["radius"])
+    o.set_contacts(L["id1"], L["id2"], L["fs"], L["nprev"], cell=L["cell"])
+    g.step(1)
+    o.step(1)
+    assert len(g.get_contacts()) == 125
+    sg, so = g.get_stress(), o.get_stress()
+    kn, ay = L["young"] * r, L["ay"]
+    expect = np.zeros((3, 3))
+    expect[0, 0] = -kn * delta / (ay * ay)
+    expect[1, 0] = -fs / (ay * ay)
+    scale = abs(expect[0, 0])
+    assert np.abs(sg - expect).max() <= 1e-9 * scale
+    assert np.abs(sg - so).max() <= 1e-12 * scale

@@ -37,6 +37,10 @@ MUTATIONS = {
     "rotation_angle_doubled": ("double half = 0.5 * wn * dt;", "double half = wn * dt;"),
     "overlap_dependent_branch": ("rw[k] = R2 * w2[k] + R1 * w1[k];",
                                  "rw[k] = (R2 - 0.5 * pen) * w2[k] + (R1 - 0.5 * pen) * w1[k];"),
+    "stress_transposed": ("acc[3 * i + j] += ct->f2[i] * (-ct->det_d[j]);",
+                          "acc[3 * i + j] += ct->f2[j] * (-ct->det_d[i]);"),
+    "stress_branch_sign": ("acc[3 * i + j] += ct->f2[i] * (-ct->det_d[j]);",
+                           "acc[3 * i + j] += ct->f2[i] * (ct->det_d[j]);"),
     "gravity_work_sign": ("en->grav += -b->m * s->p.gravity[k] * v0[k] * dt;",
                           "en->grav += b->m * s->p.gravity[k] * v0[k] * dt;"),
 }

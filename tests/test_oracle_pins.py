@@ -591,3 +591,39 @@ def test_periodic_pair_detection_through_images():
     id1, id2, cell = s.detect_pairs()
     assert len(id1) == 1
     assert tuple(cell[0]) == (-3, 0, 0)
+
+
+def _sheared_lattice(delta=2e-6, fs=1e-3, gap=0.2e-3, r=1e-3, n=5):
+    """The oracle on tests/lattice.py's sheared lattice (touching along x
+    only, preset shear force along y)."""
+    from lattice import sheared_lattice
+    L = sheared_lattice(delta=delta, fs=fs, gap=gap, r=r, n=n)
+    s = OracleScene(dt=1e-8, periodic=True, hsize=L["hsize"])
+    s.add_material(2600.0, L["young"], 0.3, 0.5)
+    s.add_spheres(L["pos"], L["radius"])
+    s.set_contacts(L["id1"], L["id2"], L["fs"], L["nprev"], cell=L["cell"])
+    # equal spheres, equal materials: kn = (E 2r)(E 2r)/(E 2r + E 2r) = E r
+    return s, L["ax"], L["ay"], L["young"] * r
+
+
+def test_love_weber_stress_of_a_sheared_lattice():
+    """utils.getStress on a lattice whose answer is a force per face area:
+    each x-contact carries kn*delta along x and fs along y, and each plane
+    of the lattice normal to x sees one contact per a_y*a_z, so
+    sigma_xx = -kn delta/(a_y a_z), sigma_yx = -fs/(a_y a_z) and every other
+    component is 0 (sign: negative under compression; row = force
+    component, column = branch component, so a transposed product shows up
+    in sigma_xy)."""
+    delta, fs = 2e-6, 1e-3
+    s, ax, ay, kn = _sheared_lattice(delta=delta, fs=fs)
+    s.step(1)
+    c = s.get_contacts()
+    assert len(c) == 125 and np.all(c["is_wall"] == 0)
+    sig = s.get_stress()
+    expect = np.zeros((3, 3))
+    expect[0, 0] = -kn * delta / (ay * ay)
+    expect[1, 0] = -fs / (ay * ay)
+    assert np.allclose(sig, expect, rtol=1e-9, atol=1e-9 * abs(expect[0, 0]))
+    # an explicit volume divides the same sum
+    V = 125 * ax * ay * ay
+    assert np.allclose(s.get_stress(volume=2 * V), expect / 2, rtol=1e-9, atol=1e-9 * abs(expect[0, 0]))
