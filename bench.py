@@ -218,6 +218,147 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def _periodic_scene(H, L, spec, pos, vel, angvel, precision, friction=None, track_energy=False):
+    from paper_2301_00611_amd import dem
+    m = spec.material
+    g = dem.Scene(periodic=True, hsize=H, velgrad=L, damping=spec.damping, gravity=spec.gravity,
+                  precision=precision, track_energy=track_energy)
+    mg = g.add_material(m.density, m.young, m.poisson, m.friction if friction is None else friction)
+    g.add_spheres(pos, spec.radius, vel=vel, angvel=angvel, default_mat=mg)
+    g.set_dt(spec.dt_factor * g.pwave_dt())
+    return g
+
+
+def prepare_periodic_compression(n=2_000_000, seed=0, target_pressure=1e3, tile=2, log=None):
+    """C3's unmeasured preparation: the lognormal lattice cloud of n/tile^3
+    spheres compressed frictionless (friction 0, same stiffness and
+    damping) to a jammed packing at about the target static mean pressure,
+    held 2000 more steps at rest, then replicated tile^3 times into a cell
+    tile times wider (the same periodic packing, n spheres).  Returns the spec
+    of the n-sphere workload and its prepared state (positions, velocities,
+    spins, cell)."""
+    import numpy as np
+    from paper_2301_00611_amd.prepare import jam_isotropic, mean_pressure, tile_periodic
+    from paper_2301_00611_amd.scenes import periodic_lognormal_gas
+    n0 = n // tile ** 3
+    spec0 = periodic_lognormal_gas(n=n0, seed=seed)
+    vs = float((4.0 / 3.0 * math.pi * spec0.radius ** 3).sum())
+    g = _periodic_scene(spec0.hsize, np.zeros((3, 3)), spec0, spec0.pos, None, None, 0, friction=0.0)
+    rec = jam_isotropic(g, spec0.dt_factor * g.pwave_dt(), vs, target_pressure, log=log)
+    g.step(2000)
+    rec["pressure_held"] = mean_pressure(g)
+    rec["coordination_held"] = g.stats()["coordination"]
+    st = g.get_state()
+    H, _ = g.get_cell()
+    g.close()
+    pos, rad, vel, ang, H2 = tile_periodic(st["pos"], spec0.radius, st["vel"], st["angvel"], H, (tile,) * 3)
+    spec = periodic_lognormal_gas(n=16, seed=seed)  # parameters of the workload
+    spec.pos, spec.radius = pos, rad
+    rec["prepared_spheres"] = n0
+    rec["tiling"] = [tile] * 3
+    rec["cell"] = H2
+    return spec, {"pos": pos, "vel": vel, "angvel": ang}, H2, rec
+
+
+def periodic_compression_leg(steps=5000, n=2_000_000, log=None):
+    """C3: FP64 vs FP32-mixed on the same prepared dense periodic packing
+    under isotropic compression at 0.01/s: throughput of each, kernel
+    durations, and the FP32-mixed error against FP64 from the identical
+    state (pair set, per-contact and per-body force) and over the run
+    (energy terms, coordination)."""
+    import numpy as np
+    import torch
+    log = log or (lambda m: None)
+    spec, st, H, rec = prepare_periodic_compression(n=n, log=log)
+    n = len(spec.radius)
+    L = spec.velgrad
+    out = {"workload": f"periodic isotropic compression: {n} spheres, lognormal r (median 1 mm, sigma 0.3), "
+                       f"E=1e8, nu=0.25, phi=0.3, damping 0.3, velGrad=-0.01 I, homoDeform 2, dt=0.5*P-wave; "
+                       f"from a packing prepared at {n // 8} spheres and tiled 2x2x2",
+           "preparation": {k: (v.tolist() if hasattr(v, "tolist") else v) for k, v in rec.items() if k != "cell0"},
+           "steps": steps}
+    # identical-state one-step comparison
+    one = {}
+    for prec in (0, 1):
+        g = _periodic_scene(H, L, spec, st["pos"], st["vel"], st["angvel"], prec)
+        g.step(1)
+        one[prec] = (g.get_contacts(), g.get_state())
+        g.close()
+    c64, c32 = one[0][0], one[1][0]
+    k64 = set(zip(c64["id1"].tolist(), c64["id2"].tolist(), map(tuple, c64["cell"].tolist())))
+    k32 = set(zip(c32["id1"].tolist(), c32["id2"].tolist(), map(tuple, c32["cell"].tolist())))
+    err = {"pair_set_differences": len(k64 ^ k32), "contacts": len(c64)}
+    if len(c64) and not (k64 ^ k32):
+        o64 = np.lexsort((c64["id2"], c64["id1"]))
+        o32 = np.lexsort((c32["id2"], c32["id1"]))
+        a, b = c64[o64], c32[o32]
+        scale = a["kn"] * 4 * np.finfo(float).eps * (2 * spec.radius.max())
+        fa, fb = a["fn"] + a["fs"], b["fn"] + b["fs"]
+        e = np.linalg.norm(fb - fa, axis=1) / (np.linalg.norm(fa, axis=1) + scale)
+        err["contact_force_rel_max"] = float(e.max())
+        err["contact_force_rel_p99"] = float(np.quantile(e, 0.99))
+        ssum = np.zeros(len(spec.radius))
+        mag = np.linalg.norm(fa, axis=1)
+        np.add.at(ssum, a["id1"], mag)
+        np.add.at(ssum, a["id2"], mag)
+        t = ssum > 0
+        eb = np.linalg.norm(one[1][1]["force"] - one[0][1]["force"], axis=1)[t] / ssum[t]
+        err["body_force_rel_max"] = float(eb.max())
+    out["fp32_vs_fp64_one_step"] = err
+    # timed runs, then the same runs with energy tracking for the statistics
+    for prec, name in ((0, "fp64"), (1, "fp32_mixed")):
+        g = _periodic_scene(H, L, spec, st["pos"], st["vel"], st["angvel"], prec)
+        g.step(0)
+        s0 = g.stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        s1 = g.stats()
+        g.set_timing(True)
+        g.step(500)
+        kern = {k: g.get_timing(k)[0] for k in ("contact", "integrate", "rebuild")}
+        st_t = g.stats()
+        g.close()
+        c_real = (s1["contact_steps"] - s0["contact_steps"]) / steps
+        r = {"value": (s1["contact_steps"] - s0["contact_steps"]) / el, "unit": "contact-steps/s",
+             "ms_per_step": el / steps * 1e3, "body_steps_per_s": n * steps / el, "rebuilds": s1["rebuilds"] - s0["rebuilds"],
+             "contacts_mean": c_real, "candidates": s1["n_candidates"], "coordination_end": s1["coordination"],
+             "kernels_ms": kern}
+        # interaction-kernel rooflines (algorithmic bytes per launch)
+        bpb, bpc = (80, 104) if prec == 0 else (52, 80)
+        cand = st_t["n_candidates"]
+        cb = bpb * n + bpc * c_real + 8 * max(cand - c_real, 0)
+        ib = (INTEGRATE_BYTES_PER_BODY + (0 if prec == 0 else 28)) * n
+        if kern["contact"] > 0:
+            r["contact_roofline"] = {"bytes": cb, "achieved_GBs": cb / (kern["contact"] * 1e-3) / 1e9,
+                                     "frac": cb / (kern["contact"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        if kern["integrate"] > 0:
+            r["integrate_roofline"] = {"bytes": ib, "achieved_GBs": ib / (kern["integrate"] * 1e-3) / 1e9,
+                                       "frac": ib / (kern["integrate"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        out[name] = r
+        log(f"periodic compression {name}: {r}")
+    stats = {}
+    for prec, name in ((0, "fp64"), (1, "fp32_mixed")):
+        g = _periodic_scene(H, L, spec, st["pos"], st["vel"], st["angvel"], prec, track_energy=True)
+        rows = []
+        for _ in range(steps // 500):
+            g.step(500)
+            e = g.get_energy()
+            rows.append([e["kinetic"], e["kin_rot"], e["elastic"], e["damp_dissip"], e["plastic_dissip"],
+                         g.stats()["coordination"]])
+        g.close()
+        stats[name] = np.array(rows)
+    a, b = stats["fp64"], stats["fp32_mixed"]
+    scale = np.abs(a[:, :5]).sum(axis=1, keepdims=True)
+    out["fp32_vs_fp64_run"] = {
+        "energy_terms_rel_to_total_max": float((np.abs(b[:, :5] - a[:, :5]) / scale).max()),
+        "coordination_rel_max": float((np.abs(b[:, 5] - a[:, 5]) / np.maximum(a[:, 5], 1e-30)).max()),
+        "windows": int(a.shape[0]), "window_steps": 500}
+    return out
+
+
 def batched_leg(n_scenes=512, steps=2000):
     """C4: 512 independent deposition scenes (log-uniform sizes 500..50,000,
     per-scene friction and damping) stepped together; scenes.steps/s."""

@@ -426,27 +426,34 @@ __global__ void __launch_bounds__(kBlock) k_pair_build(PairBuildArgs a)
         if (a.ent_own[e]) {
             const uint32_t k = a.own_scan[e];
             if (slot < 0) {
+                // a wall pair: the wall is #1 and has no row
                 a.pr.a[k] = slot;
                 a.pr.b[k] = i;
-                a.rows.ent[e] = k;
+                a.pr.e2[k] = e;
             } else {
                 a.pr.a[k] = i;
                 a.pr.b[k] = slot;
-                a.rows.ent[e] = k | kNegSign;
+                a.pr.e1[k] = e;
             }
             a.pr.cell[k] = a.ent_cell[e];
             a.pr.pid[k] = a.ent_pid[e];
         } else {
-            // the pair is owned by the partner: find this body in its row
-            const int32_t want = neg_cell(a.ent_cell[e]);
-            const int jb = a.row_start[slot], je = a.row_start[slot + 1];
-            uint32_t k = kPairMask;
-            for (int f = jb; f < je; ++f)
-                if (a.ent_pid[f] == myid && a.ent_cell[f] == want && a.ent_own[f]) {
-                    k = a.own_scan[f];
-                    break;
-                }
-            a.rows.ent[e] = k;
+            // the pair is owned by the partner: find this body in its row,
+            // which is sorted by (partner id, packed image as unsigned)
+            const uint32_t want = (uint32_t)neg_cell(a.ent_cell[e]);
+            int lo = a.row_start[slot], hi = a.row_start[slot + 1];
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                const int32_t pm = a.ent_pid[mid];
+                const uint32_t cm = (uint32_t)a.ent_cell[mid];
+                if (pm < myid || (pm == myid && cm < want))
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            if (lo < a.row_start[slot + 1] && a.ent_pid[lo] == myid && (uint32_t)a.ent_cell[lo] == want &&
+                a.ent_own[lo])
+                a.pr.e2[a.own_scan[lo]] = e;
         }
     }
     a.hist_new.own_begin[myid] = (int32_t)a.own_scan[beg];
@@ -572,6 +579,12 @@ void launch_pair_build(const PairBuildArgs& a, hipStream_t st)
 {
     if (a.nslots <= 0) return;
     hipLaunchKernelGGL(k_pair_build, dim3(nblocks(a.nslots)), dim3(kBlock), 0, st, a);
+}
+
+void launch_fill_u32(uint32_t* p, uint32_t v, int n, hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_u32, dim3(nblocks(n)), dim3(kBlock), 0, st, p, v, n);
 }
 
 void launch_carry_over(const PairBuildArgs& a, hipStream_t st, int old_nbodies)

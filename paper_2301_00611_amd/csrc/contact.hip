@@ -2,8 +2,9 @@
 // thread per candidate pair runs the exact contact test, the ScGeom update
 // (class ScGeom; section 2.1.3), Ip2_FrictMat_FrictMat_FrictPhys (section
 // 2.1.2) and Law2_ScGeom_FrictPhys_CundallStrack (section 2.1.4), and writes
-// the pair's shear history and its force on #2.  No scatter happens here:
-// each body sums its pairs later, in a fixed order (integrate.hip).
+// the pair's shear history and its force into the force records of the two
+// row entries of the pair (one per body).  No sum happens here: each body
+// adds its row's records later, in a fixed order (integrate.hip).
 //
 // FP64 mode computes everything in double.  FP32-mixed mode keeps the
 // contact test, the branch length and the overlap in double (they are
@@ -90,6 +91,42 @@ __device__ inline int logical_block(int nb)
     return xcd * q + (xcd < r ? xcd : r) + idx;
 }
 
+// A row entry's force record: the force on that body and n x F.
+template <int PREC, typename R>
+__device__ inline void put_slot(const Rows& rows, int e, V3<R> f, V3<R> t)
+{
+    if (e < 0) return;
+    if (PREC == DEM_FP32_MIXED) {
+        float* q = rows.slotf + (size_t)kSlotWords * e;
+        q[0] = (float)f.x;
+        q[1] = (float)f.y;
+        q[2] = (float)f.z;
+        q[3] = (float)t.x;
+        q[4] = (float)t.y;
+        q[5] = (float)t.z;
+    } else {
+        double* q = rows.slot + (size_t)kSlotWords * e;
+        q[0] = (double)f.x;
+        q[1] = (double)f.y;
+        q[2] = (double)f.z;
+        q[3] = (double)t.x;
+        q[4] = (double)t.y;
+        q[5] = (double)t.z;
+    }
+}
+template <int PREC>
+__device__ inline void clear_slot(const Rows& rows, int e)
+{
+    if (e < 0) return;
+    if (PREC == DEM_FP32_MIXED) {
+        float* q = rows.slotf + (size_t)kSlotWords * e;
+        for (int w = 0; w < kSlotWords; ++w) q[w] = 0.0f;
+    } else {
+        double* q = rows.slot + (size_t)kSlotWords * e;
+        for (int w = 0; w < kSlotWords; ++w) q[w] = 0.0;
+    }
+}
+
 struct ContactPartial {
     double el, plast;
     unsigned long long ss, sw;
@@ -170,6 +207,8 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
                 P.ny[k] = 0.0;
                 P.nz[k] = 0.0;
                 P.real[k] = 0;
+                clear_slot<PREC>(a.rows, P.e1[k]);
+                clear_slot<PREC>(a.rows, P.e2[k]);
             }
         } else {
             // ---- ScGeom inputs
@@ -243,21 +282,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
             P.nx[k] = (double)n.x;
             P.ny[k] = (double)n.y;
             P.nz[k] = (double)n.z;
-            if (PREC == DEM_FP32_MIXED) {
-                P.fxf[k] = (float)F.x;
-                P.fyf[k] = (float)F.y;
-                P.fzf[k] = (float)F.z;
-                P.txf[k] = (float)tau.x;
-                P.tyf[k] = (float)tau.y;
-                P.tzf[k] = (float)tau.z;
-            } else {
-                P.fx[k] = (double)F.x;
-                P.fy[k] = (double)F.y;
-                P.fz[k] = (double)F.z;
-                P.tx[k] = (double)tau.x;
-                P.ty[k] = (double)tau.y;
-                P.tz[k] = (double)tau.z;
-            }
+            // the force on #2 into #2's row entry, its negation into #1's
+            put_slot<PREC>(a.rows, P.e2[k], F, tau);
+            put_slot<PREC>(a.rows, P.e1[k], v3<R>((R)0, (R)0, (R)0) - F, tau);
             P.real[k] = 1;
             if (wall)
                 part.sw = 1;

@@ -87,16 +87,18 @@ struct Pairs {
     uint8_t *real;            // 1 when the pair touched at the last evaluation
     double *fsx, *fsy, *fsz;  // shear force on #2 (history)
     double *nx, *ny, *nz;     // normal of the last step; 0 for a non-real pair
-    double *fx, *fy, *fz;     // total force on #2 of the last step
-    double *tx, *ty, *tz;     // n x F of the last step (torque = -r_k * this)
-    float *fxf, *fyf, *fzf;   // FP32-mixed mode per-pair force
-    float *txf, *tyf, *tzf;
+    int32_t *e1, *e2;         // row entries of #1 (-1 for a wall) and #2, -1 if none
 };
 
-// Rows: for every slot, its candidate pairs sorted by partner id.
+// Rows: for every slot, its candidate pairs sorted by partner id.  Each row
+// entry owns one force record that the contact kernel fills for a real
+// pair (the force on this body and n x F) and clears when the pair stops
+// touching, so the per-body sum streams its row with no gather.
+constexpr int kSlotWords = 6;     // Fx, Fy, Fz, (n x F)x, y, z
 struct Rows {
     int32_t *start;           // nslots + 1
-    uint32_t *ent;            // pair index | kNegSign when the body is #1
+    double *slot;             // FP64: kSlotWords doubles per entry
+    float *slotf;             // FP32-mixed: kSlotWords floats per entry
 };
 
 // History of the previous candidate list, keyed by ids.
@@ -218,6 +220,7 @@ struct PairBuildArgs {
     int32_t has_old;
 };
 void launch_pair_build(const PairBuildArgs& a, hipStream_t st);
+void launch_fill_u32(uint32_t* p, uint32_t v, int n, hipStream_t st);
 void launch_carry_over(const PairBuildArgs& a, hipStream_t st, int old_nbodies);
 
 // contact.hip
@@ -234,6 +237,8 @@ void launch_body_forces(const StepArgs& a, int precision, double* f3, double* t3
 // Love-Weber stress partial sums (9 doubles per block) of the last step's
 // real sphere-sphere contacts; `scene` selects a batch scene.
 int stress_blocks(int npairs);
+// Force on #2 of every pair (3 doubles per pair), gathered from the row records.
+void launch_pair_forces(const StepArgs& a, int precision, double* f3, hipStream_t st);
 void launch_stress(const StepArgs& a, int precision, bool batched, int scene, double* part, hipStream_t st);
 
 

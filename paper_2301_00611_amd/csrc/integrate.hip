@@ -1,6 +1,6 @@
 // integrate.hip -- ForceContainer sum + NewtonIntegrator (section 2.1.5).
 //
-// One thread per body: the body adds the forces of its candidate pairs one by
+// One thread per body: the body adds the force records of its row one by
 // one, in ascending partner id (its row order), so the sum is deterministic
 // and needs no atomics; then gravity (damped like any force, dampGravity),
 // Cundall damping eq. 2.9 per component with the on-step velocity estimate
@@ -29,7 +29,8 @@ __device__ inline int logical_block(int nb)
 
 __device__ inline double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
 
-// Resultant contact force and torque on slot i, in row order.
+// Resultant contact force and torque on slot i: its row's force records in
+// row order (ascending partner id); a record is zero unless its pair is real.
 template <int PREC>
 __device__ inline void body_sum(const StepArgs& a, int i, double r, double* F, double* T)
 {
@@ -37,34 +38,27 @@ __device__ inline void body_sum(const StepArgs& a, int i, double r, double* F, d
     T[0] = T[1] = T[2] = 0.0;
     const int beg = a.rows.start[i], end = a.rows.start[i + 1];
     for (int e = beg; e < end; ++e) {
-        const uint32_t u = a.rows.ent[e];
-        const uint32_t k = u & kPairMask;
-        if (k >= (uint32_t)a.npairs || !a.pr.real[k]) continue;
         double f0, f1, f2, t0, t1, t2;
         if (PREC == DEM_FP32_MIXED) {
-            f0 = a.pr.fxf[k];
-            f1 = a.pr.fyf[k];
-            f2 = a.pr.fzf[k];
-            t0 = a.pr.txf[k];
-            t1 = a.pr.tyf[k];
-            t2 = a.pr.tzf[k];
+            const float* q = a.rows.slotf + (size_t)kSlotWords * e;
+            f0 = q[0];
+            f1 = q[1];
+            f2 = q[2];
+            t0 = q[3];
+            t1 = q[4];
+            t2 = q[5];
         } else {
-            f0 = a.pr.fx[k];
-            f1 = a.pr.fy[k];
-            f2 = a.pr.fz[k];
-            t0 = a.pr.tx[k];
-            t1 = a.pr.ty[k];
-            t2 = a.pr.tz[k];
+            const double* q = a.rows.slot + (size_t)kSlotWords * e;
+            f0 = q[0];
+            f1 = q[1];
+            f2 = q[2];
+            t0 = q[3];
+            t1 = q[4];
+            t2 = q[5];
         }
-        if (u & kNegSign) {
-            F[0] += -f0;
-            F[1] += -f1;
-            F[2] += -f2;
-        } else {
-            F[0] += f0;
-            F[1] += f1;
-            F[2] += f2;
-        }
+        F[0] += f0;
+        F[1] += f1;
+        F[2] += f2;
         // both bodies of a pair feel -r_k (n x F) (lever arms r1 n and -r2 n)
         T[0] += -r * t0;
         T[1] += -r * t1;

@@ -125,20 +125,15 @@ struct BodySet {
 };
 
 struct PairSet {
-    DBuf a, b, cell, pid, real, fsx, fsy, fsz, nx, ny, nz, fx, fy, fz, tx, ty, tz, fxf, fyf, fzf, txf, tyf, tzf;
+    DBuf a, b, cell, pid, real, fsx, fsy, fsz, nx, ny, nz, e1, e2;
     DBuf own_begin, own_count;  // by gid
     size_t cap = 0;
-    void ensure(size_t n, bool fp32)
+    void ensure(size_t n)
     {
         n = std::max<size_t>(n, 1);
-        for (DBuf* d : {&a, &b, &cell, &pid}) d->ensure(n * 4);
+        for (DBuf* d : {&a, &b, &cell, &pid, &e1, &e2}) d->ensure(n * 4);
         real.ensure(n);
         for (DBuf* d : {&fsx, &fsy, &fsz, &nx, &ny, &nz}) d->ensure(n * 8);
-        if (fp32) {
-            for (DBuf* d : {&fxf, &fyf, &fzf, &txf, &tyf, &tzf}) d->ensure(n * 4);
-        } else {
-            for (DBuf* d : {&fx, &fy, &fz, &tx, &ty, &tz}) d->ensure(n * 8);
-        }
         cap = n;
     }
     Pairs view() const
@@ -155,18 +150,8 @@ struct PairSet {
         p.nx = nx.as<double>();
         p.ny = ny.as<double>();
         p.nz = nz.as<double>();
-        p.fx = fx.as<double>();
-        p.fy = fy.as<double>();
-        p.fz = fz.as<double>();
-        p.tx = tx.as<double>();
-        p.ty = ty.as<double>();
-        p.tz = tz.as<double>();
-        p.fxf = fxf.as<float>();
-        p.fyf = fyf.as<float>();
-        p.fzf = fzf.as<float>();
-        p.txf = txf.as<float>();
-        p.tyf = tyf.as<float>();
-        p.tzf = tzf.as<float>();
+        p.e1 = e1.as<int32_t>();
+        p.e2 = e2.as<int32_t>();
         return p;
     }
     History history() const
@@ -186,8 +171,7 @@ struct PairSet {
     }
     void release()
     {
-        for (DBuf* d : {&a, &b, &cell, &pid, &real, &fsx, &fsy, &fsz, &nx, &ny, &nz, &fx, &fy, &fz, &tx, &ty, &tz, &fxf,
-                        &fyf, &fzf, &txf, &tyf, &tzf, &own_begin, &own_count})
+        for (DBuf* d : {&a, &b, &cell, &pid, &real, &fsx, &fsy, &fsz, &nx, &ny, &nz, &e1, &e2, &own_begin, &own_count})
             d->release();
         cap = 0;
     }
@@ -204,6 +188,7 @@ struct HostScene {
     int64_t iter = 0;
     double time = 0.0;
     double verlet = 0.0;        // Delta L in use
+    double rmax = 0.0;          // largest radius at the last broad-phase run
 };
 
 // Host copy of everything per gid (kept in step only when bodies are added
@@ -257,7 +242,7 @@ struct World {
     int ngids_dev = 0;                 // number of gids the device arrays were built for
     int old_ngids = 0;                 // gids covered by the active own arrays
     DBuf slot_of_id, keys, vals, keys_alt, vals_alt, cell_start, cell_end, counts, row_start;
-    DBuf ent_slot, ent_pid, ent_cell, ent_own, own_scan, rows_ent, scan_tmp, radix_tmp;
+    DBuf ent_slot, ent_pid, ent_cell, ent_own, own_scan, rows_slot, scan_tmp, radix_tmp;
     DBuf d_scenes, d_walls, d_mats, d_tanphi, d_ctr, d_part_c, d_part_i, d_bounds, d_total, d_tmp3, d_args;
     int grid_c = 1, grid_i = 1;        // step-kernel grids (contact sized with headroom)
     int acc_c_n = 0, acc_i_n = 0;      // slots currently in use in d_part_c / d_part_i
@@ -306,7 +291,7 @@ struct World {
         for (auto& b : bs) b.release();
         for (auto& p : ps) p.release();
         for (DBuf* d : {&slot_of_id, &keys, &vals, &keys_alt, &vals_alt, &cell_start, &cell_end, &counts, &row_start,
-                        &ent_slot, &ent_pid, &ent_cell, &ent_own, &own_scan, &rows_ent, &scan_tmp, &radix_tmp,
+                        &ent_slot, &ent_pid, &ent_cell, &ent_own, &own_scan, &rows_slot, &scan_tmp, &radix_tmp,
                         &d_scenes, &d_walls, &d_mats, &d_tanphi, &d_ctr, &d_part_c, &d_part_i, &d_bounds, &d_total,
                         &d_tmp3, &d_args})
             d->release();
@@ -735,6 +720,7 @@ struct World {
             double lf = 0.0;
             for (int k = 0; k < 9; ++k) lf += P.L[k] * P.L[k];
             P.verlet_cell_rate = 0.5 * std::sqrt(lf) * (2.0 * rmax[s] + 4.0 * P.verlet);
+            scenes[s].rmax = rmax[s];
         }
         ncells = std::max(cells, 1);
         morton_bits = 1;
@@ -801,7 +787,11 @@ struct World {
             ent_cell.ensure(4 * ((size_t)nent + 1));
             ent_own.ensure(4 * ((size_t)nent + 1));
             own_scan.ensure(4 * ((size_t)nent + 1));
-            rows_ent.ensure(4 * ((size_t)nent + 1));
+            // one force record per row entry, cleared: a record is non-zero
+            // only while its pair is real
+            const size_t rec = precision == DEM_FP32_MIXED ? sizeof(float) : sizeof(double);
+            rows_slot.ensure(rec * kSlotWords * ((size_t)nent + 1));
+            HIPC(hipMemsetAsync(rows_slot.p, 0, rec * kSlotWords * ((size_t)nent + 1), stream));
             sw.row_start = row_start.as<int32_t>();
             sw.ent_slot = ent_slot.as<int32_t>();
             sw.ent_pid = ent_pid.as<int32_t>();
@@ -822,7 +812,9 @@ struct World {
             // new pair set
             PairSet& NP = ps[1 - pactive];
             PairSet& OP = ps[pactive];
-            NP.ensure(np, precision == DEM_FP32_MIXED);
+            NP.ensure(np);
+            launch_fill_u32(NP.e1.as<uint32_t>(), 0xffffffffu, (int)np, stream);
+            launch_fill_u32(NP.e2.as<uint32_t>(), 0xffffffffu, (int)np, stream);
             const int ng = (int)bodies.size();
             NP.own_begin.ensure(4 * (size_t)std::max(ng, 1));
             NP.own_count.ensure(4 * (size_t)std::max(ng, 1));
@@ -837,7 +829,8 @@ struct World {
             pb.own_scan = own_scan.as<uint32_t>();
             pb.ent_own = ent_own.as<uint32_t>();
             pb.rows.start = row_start.as<int32_t>();
-            pb.rows.ent = rows_ent.as<uint32_t>();
+            pb.rows.slot = rows_slot.as<double>();
+            pb.rows.slotf = rows_slot.as<float>();
             pb.pr = NP.view();
             pb.hist_new = NP.history();
             pb.hist_old = OP.history();
@@ -886,6 +879,19 @@ struct World {
         upload_args();
         need_rebuild = false;
         ++rebuilds;
+    }
+
+    // Per-step mean-field share of the Verlet budget (periodic), written
+    // into the device counters between steps.
+    void update_cell_step()
+    {
+        if (need_rebuild || !d_ctr.p) return;  // the next run sets it
+        double cell_step = 0.0;
+        for (size_t s = 0; s < sp.size(); ++s) cell_step = std::max(cell_step, sp[s].verlet_cell_rate * sp[s].dt);
+        h_ctr->verlet_cell_step = cell_step;
+        HIPC(hipMemcpyAsync(reinterpret_cast<char*>(d_ctr.p) + offsetof(Counters, verlet_cell_step),
+                            &h_ctr->verlet_cell_step, sizeof(double), hipMemcpyHostToDevice, stream));
+        HIPC(hipStreamSynchronize(stream));
     }
 
     // Sum the per-block slots in block order.  cum = true: add the running
@@ -965,7 +971,8 @@ struct World {
         a.bod = bs[active].view();
         a.pr = ps[pactive].view();
         a.rows.start = row_start.as<int32_t>();
-        a.rows.ent = rows_ent.as<uint32_t>();
+        a.rows.slot = rows_slot.as<double>();
+        a.rows.slotf = rows_slot.as<float>();
         a.walls = d_walls.as<Wall>();
         a.mats = d_mats.as<Material>();
         a.tanphi = d_tanphi.as<double>();
@@ -1183,21 +1190,23 @@ struct World {
         gd(P.nx, p.nx);
         gd(P.ny, p.ny);
         gd(P.nz, p.nz);
-        if (precision == DEM_FP32_MIXED) {
-            std::vector<float> f(n);
-            auto gf = [&](const DBuf& d, std::vector<double>& v) {
-                v.resize(n);
-                if (n) HIPC(hipMemcpyAsync(f.data(), d.p, 4 * n, hipMemcpyDeviceToHost, stream));
-                HIPC(hipStreamSynchronize(stream));
-                for (size_t i = 0; i < n; ++i) v[i] = f[i];
-            };
-            gf(P.fxf, p.fx);
-            gf(P.fyf, p.fy);
-            gf(P.fzf, p.fz);
-        } else {
-            gd(P.fx, p.fx);
-            gd(P.fy, p.fy);
-            gd(P.fz, p.fz);
+        // force on #2 of every pair, gathered from #2's row record
+        p.fx.assign(n, 0.0);
+        p.fy.assign(n, 0.0);
+        p.fz.assign(n, 0.0);
+        if (n) {
+            d_tmp3.ensure(sizeof(double) * 3 * n);
+            StepArgs a = step_args();
+            launch_pair_forces(a, precision, d_tmp3.as<double>(), stream);
+            HIPC(hipGetLastError());
+            std::vector<double> f(3 * n);
+            HIPC(hipMemcpyAsync(f.data(), d_tmp3.p, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, stream));
+            HIPC(hipStreamSynchronize(stream));
+            for (size_t k = 0; k < n; ++k) {
+                p.fx[k] = f[3 * k];
+                p.fy[k] = f[3 * k + 1];
+                p.fz[k] = f[3 * k + 2];
+            }
         }
         HIPC(hipStreamSynchronize(stream));
         return p;
@@ -1532,7 +1541,7 @@ struct World {
         }
         const size_t m = recs.size();
         PairSet& P = ps[pactive];
-        P.ensure(std::max<size_t>(m, (size_t)npairs), precision == DEM_FP32_MIXED);
+        P.ensure(std::max<size_t>(m, (size_t)npairs));
         P.own_begin.ensure(4 * (size_t)std::max(ng, 1));
         P.own_count.ensure(4 * (size_t)std::max(ng, 1));
         std::vector<int32_t> pid(m), cell(m);
@@ -1724,6 +1733,7 @@ dem_status dem_set_dt(dem_scene* s, double dt)
         w->sp[s->s].dt = dt;
         w->push_scene_table();
         if (w->d_args.p) w->upload_args();
+        w->update_cell_step();
     });
 }
 
@@ -1738,9 +1748,14 @@ dem_status dem_set_velgrad(dem_scene* s, const double* velgrad9)
             w->scenes[s->s].p.velgrad[k] = velgrad9[k];
             w->sp[s->s].L[k] = velgrad9[k];
         }
+        // the mean field's share of the Verlet budget changes from the next
+        // step on; what the bodies' accounts hold stays valid
+        double lf = 0.0;
+        for (int k = 0; k < 9; ++k) lf += velgrad9[k] * velgrad9[k];
+        w->sp[s->s].verlet_cell_rate = 0.5 * std::sqrt(lf) * (2.0 * w->scenes[s->s].rmax + 4.0 * w->sp[s->s].verlet);
         w->push_scene_table();
         if (w->d_args.p) w->upload_args();
-        w->need_rebuild = true;  // the Verlet budget of the mean field changes
+        w->update_cell_step();
     });
 }
 

@@ -1,4 +1,6 @@
-// stress.hip -- the Love-Weber stress of the contact network
+// stress.hip -- reporting kernels: per-pair forces (read back by the
+// contact list and the wall reactions) and the Love-Weber stress of the
+// contact network
 // (utils.getStress, section 5 utility reference): the sum over the real
 // sphere-sphere contacts of f (x) l, where f is the force on #2 and l the
 // branch vector from #2 to #1, so that repulsive contacts give negative
@@ -17,6 +19,39 @@ namespace {
 
 constexpr int kStressBlock = 256;
 
+// Force on #2 of pair k: the record of #2's row entry.
+template <int PREC>
+__device__ inline void pair_force(const StepArgs& a, int k, double* F)
+{
+    const int e = a.pr.e2[k];
+    F[0] = F[1] = F[2] = 0.0;
+    if (e < 0) return;
+    if (PREC == DEM_FP32_MIXED) {
+        const float* q = a.rows.slotf + (size_t)kSlotWords * e;
+        F[0] = q[0];
+        F[1] = q[1];
+        F[2] = q[2];
+    } else {
+        const double* q = a.rows.slot + (size_t)kSlotWords * e;
+        F[0] = q[0];
+        F[1] = q[1];
+        F[2] = q[2];
+    }
+}
+
+// Per-pair force on #2 (3 doubles per pair) for reporting.
+template <int PREC>
+__global__ void __launch_bounds__(kStressBlock) k_pair_forces(StepArgs a, double* __restrict__ f3)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.npairs) return;
+    double F[3];
+    pair_force<PREC>(a, k, F);
+    f3[3 * (size_t)k + 0] = F[0];
+    f3[3 * (size_t)k + 1] = F[1];
+    f3[3 * (size_t)k + 2] = F[2];
+}
+
 template <int PREC, bool BATCHED>
 __global__ void __launch_bounds__(kStressBlock) k_stress(StepArgs a, int scene, double* __restrict__ part)
 {
@@ -28,15 +63,7 @@ __global__ void __launch_bounds__(kStressBlock) k_stress(StepArgs a, int scene, 
         const int sa = P.a[k], sb = P.b[k];
         if (!BATCHED || (int)B.scene[sb] == scene) {
             double F[3];
-            if (PREC == DEM_FP32_MIXED) {
-                F[0] = (double)P.fxf[k];
-                F[1] = (double)P.fyf[k];
-                F[2] = (double)P.fzf[k];
-            } else {
-                F[0] = P.fx[k];
-                F[1] = P.fy[k];
-                F[2] = P.fz[k];
-            }
+            pair_force<PREC>(a, k, F);
             const double n[3] = {P.nx[k], P.ny[k], P.nz[k]};
             const double fn[3] = {F[0] - P.fsx[k], F[1] - P.fsy[k], F[2] - P.fsz[k]};
             const double r1 = B.rad[sa], r2 = B.rad[sb];
@@ -65,6 +92,16 @@ __global__ void __launch_bounds__(kStressBlock) k_stress(StepArgs a, int scene, 
 }
 
 }  // namespace
+
+void launch_pair_forces(const StepArgs& a, int precision, double* f3, hipStream_t st)
+{
+    const int grid = stress_blocks(a.npairs);
+    if (grid == 0) return;
+    if (precision == DEM_FP32_MIXED)
+        hipLaunchKernelGGL(k_pair_forces<DEM_FP32_MIXED>, dim3(grid), dim3(kStressBlock), 0, st, a, f3);
+    else
+        hipLaunchKernelGGL(k_pair_forces<DEM_FP64>, dim3(grid), dim3(kStressBlock), 0, st, a, f3);
+}
 
 int stress_blocks(int npairs) { return npairs > 0 ? (npairs + kStressBlock - 1) / kStressBlock : 0; }
 

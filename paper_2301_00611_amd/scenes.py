@@ -18,6 +18,13 @@ benchmark configurations described in the design notes:
 * ``batched_deposition`` -- C4: 512 scenes, sphere count log-uniform in
   [500, 50000], r ~ U(0.8, 1.2) mm, friction ~ U(0.1, 0.7) rad,
   damping ~ U(0.05, 0.4), each a jittered column grid in its own box.
+* ``periodic_lognormal_gas`` -- C3's starting cloud: 2,000,000 spheres with
+  lognormal radii (median 1 mm, sigma_ln 0.3, truncated at +-3 sigma) on a
+  jittered cubic lattice in a periodic cube (periodic simple-shear and
+  triaxial tutorials, section 3.1.x), before its isotropic compression.
+* ``periodic_bidisperse_gas`` -- C5's starting cloud: 0.5 mm and 2.0 mm
+  spheres, equal total volume, large spheres and blocks of small ones at
+  randomly permuted nodes of one cubic lattice.
 """
 from __future__ import annotations
 
@@ -185,6 +192,85 @@ def batched_deposition(n_scenes: int = 512, nmin: int = 500, nmax: int = 50_000,
                             gravity=(0.0, 0.0, -9.81), damping=float(damping[s]), steps=steps,
                             name=f"batch_{s}"))
     return BatchSpec(scenes=scenes, dt_radius=rmin, steps=steps)
+
+
+def truncated_lognormal(rng: np.random.Generator, n: int, median: float, sigma: float, lo: float,
+                        hi: float) -> np.ndarray:
+    """Lognormal draws (median, sigma of the log) kept inside [lo, hi]:
+    out-of-range draws are redrawn."""
+    out = np.exp(rng.normal(math.log(median), sigma, size=n))
+    bad = (out < lo) | (out > hi)
+    while bad.any():
+        out[bad] = np.exp(rng.normal(math.log(median), sigma, size=int(bad.sum())))
+        bad = (out < lo) | (out > hi)
+    return out
+
+
+def periodic_lognormal_gas(n: int = 2_000_000, seed: int = 0, median: float = 1e-3, sigma: float = 0.3,
+                           young: float = 1e8, poisson: float = 0.25, friction: float = 0.3,
+                           damping: float = 0.3, strain_rate: float = 0.01, steps: int = 5000) -> Scene:
+    """C3's cloud: lognormal radii truncated to median * exp(+-3 sigma); the
+    k^3 >= n nodes of a cubic lattice of spacing 2 r_max (1 + 1e-3), filled
+    in node order, each centre jittered by U(-j, j) per axis with
+    j = (s - 2r)/2, so no two spheres overlap, also across the periodic
+    boundaries.  The cube side is k s.  The workload itself is an isotropic
+    compression at `strain_rate` (Cell.velGrad = -rate I, homoDeform 2),
+    started after a preparation to a dense state."""
+    rng = _rng(seed)
+    radius = truncated_lognormal(rng, n, median, sigma, median * math.exp(-3 * sigma), median * math.exp(3 * sigma))
+    s = 2.0 * radius.max() * (1.0 + 1e-3)
+    k = int(math.ceil(n ** (1.0 / 3.0) - 1e-9))
+    while k ** 3 < n:
+        k += 1
+    idx = np.arange(n)
+    nodes = (np.stack([idx % k, (idx // k) % k, idx // (k * k)], axis=1).astype(np.float64) + 0.5) * s
+    jit = (s - 2.0 * radius) / 2.0
+    pos = nodes + rng.uniform(-1.0, 1.0, size=(n, 3)) * jit[:, None]
+    sc = Scene(pos=pos, radius=radius, material=Material(2600.0, young, poisson, friction), walls=[],
+               gravity=(0.0, 0.0, 0.0), damping=damping, dt_factor=0.5, steps=steps, periodic=True,
+               hsize=np.eye(3) * (k * s), velgrad=-strain_rate * np.eye(3), name=f"periodic_lognormal_{n}")
+    return sc
+
+
+def periodic_bidisperse_gas(n: int = 8_000_000, seed: int = 0, r_small: float = 0.5e-3, r_large: float = 2.0e-3,
+                            young: float = 1e8, poisson: float = 0.3, friction: float = 0.5,
+                            damping: float = 0.1, shear_rate: float = 1.0, steps: int = 2000) -> Scene:
+    """C5's cloud: equal total volume of small and large spheres (so
+    n_large / n_small = (r_small / r_large)^3, 1/64 for a size ratio of 4).
+    A cubic lattice of spacing s = 2 r_large (1 + 1e-3) holds, at randomly
+    permuted nodes, either one large sphere or a block of q^3 small spheres
+    (q = r_large / r_small) on a sub-lattice of spacing s / q; small centres
+    are jittered by U(-j, j), j = (s/q - 2 r_small)/2, large ones sit on
+    their node.  No two spheres overlap, also across the periodic
+    boundaries.  Ids: large spheres first, then small ones in node order.
+    The workload is simple shear v_x = rate z (Cell.velGrad[0][2] = rate)."""
+    rng = _rng(seed)
+    q = int(round(r_large / r_small))
+    ratio = (r_small / r_large) ** 3
+    n_large = int(round(n * ratio / (1.0 + ratio)))
+    n_small = n - n_large
+    n_blocks = -(-n_small // q ** 3)
+    m = int(math.ceil((n_large + n_blocks) ** (1.0 / 3.0) - 1e-9))
+    while m ** 3 < n_large + n_blocks:
+        m += 1
+    s = 2.0 * r_large * (1.0 + 1e-3)
+    order = rng.permutation(m ** 3)
+    nodes_l, nodes_b = order[:n_large], np.sort(order[n_large:n_large + n_blocks])
+    grid = lambda i: (np.stack([i % m, (i // m) % m, i // (m * m)], axis=1).astype(np.float64) + 0.5) * s
+    pos_l = grid(nodes_l)
+    sub = s / q
+    o = np.arange(q ** 3)
+    offs = (np.stack([o % q, (o // q) % q, o // (q * q)], axis=1).astype(np.float64) + 0.5) * sub - 0.5 * s
+    pos_s = (grid(nodes_b)[:, None, :] + offs[None, :, :]).reshape(-1, 3)[:n_small]
+    jit = (sub - 2.0 * r_small) / 2.0
+    pos_s = pos_s + rng.uniform(-jit, jit, size=(n_small, 3))
+    pos = np.concatenate([pos_l, pos_s])
+    radius = np.concatenate([np.full(n_large, r_large), np.full(n_small, r_small)])
+    L = np.zeros((3, 3))
+    L[0, 2] = shear_rate
+    return Scene(pos=pos, radius=radius, material=Material(2600.0, young, poisson, friction), walls=[],
+                 gravity=(0.0, 0.0, 0.0), damping=damping, dt_factor=0.5, steps=steps, periodic=True,
+                 hsize=np.eye(3) * (m * s), velgrad=L, name=f"periodic_bidisperse_{n}")
 
 
 def random_velocities(n: int, scale: float, seed: int) -> tuple[np.ndarray, np.ndarray]:
