@@ -105,12 +105,13 @@ __global__ void __launch_bounds__(kBlock) k_bounds(Bodies b, int nslots, int bat
     const int s = valid && batched ? (int)b.scene[i] : 0;
     unsigned long long v[6];
     if (valid) {
-        v[0] = ~ord_bits(b.x[i]);
-        v[1] = ~ord_bits(b.y[i]);
-        v[2] = ~ord_bits(b.z[i]);
-        v[3] = ord_bits(b.x[i]);
-        v[4] = ord_bits(b.y[i]);
-        v[5] = ord_bits(b.z[i]);
+        const double4 p = b.xr[i];
+        v[0] = ~ord_bits(p.x);
+        v[1] = ~ord_bits(p.y);
+        v[2] = ~ord_bits(p.z);
+        v[3] = ord_bits(p.x);
+        v[4] = ord_bits(p.y);
+        v[5] = ord_bits(p.z);
     } else {
         for (int k = 0; k < 6; ++k) v[k] = 0ull;
     }
@@ -137,12 +138,13 @@ __global__ void __launch_bounds__(kBlock) k_bounds_block(Bodies b, int nslots, u
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long v[6] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
     if (i < nslots) {
-        v[0] = ~ord_bits(b.x[i]);
-        v[1] = ~ord_bits(b.y[i]);
-        v[2] = ~ord_bits(b.z[i]);
-        v[3] = ord_bits(b.x[i]);
-        v[4] = ord_bits(b.y[i]);
-        v[5] = ord_bits(b.z[i]);
+        const double4 p = b.xr[i];
+        v[0] = ~ord_bits(p.x);
+        v[1] = ~ord_bits(p.y);
+        v[2] = ~ord_bits(p.z);
+        v[3] = ord_bits(p.x);
+        v[4] = ord_bits(p.y);
+        v[5] = ord_bits(p.z);
     }
     for (int k = 0; k < 6; ++k)
         for (int off = 32; off > 0; off >>= 1) {
@@ -208,7 +210,8 @@ __global__ void __launch_bounds__(kBlock) k_keys(GridArgs g, uint64_t* __restric
     const int s = BATCHED ? (int)g.bod.scene[i] : 0;
     const SceneParams& P = (BATCHED || PERIODIC) ? g.scenes[s] : g.scene0;
     int c[3], per[3];
-    cell_of<PERIODIC>(P, g.bod.x[i], g.bod.y[i], g.bod.z[i], c, per);
+    const double4 p = g.bod.xr[i];
+    cell_of<PERIODIC>(P, p.x, p.y, p.z, c, per);
     uint64_t key = morton3(c[0], c[1], c[2]);
     if (BATCHED) key |= (uint64_t)s << (3 * g.morton_bits);
     keys[i] = key;
@@ -225,21 +228,10 @@ __global__ void __launch_bounds__(kBlock) k_permute(Bodies src, Bodies dst, cons
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nslots) return;
     const uint32_t o = order[i];
-    dst.x[i] = src.x[o];
-    dst.y[i] = src.y[o];
-    dst.z[i] = src.z[o];
-    dst.vx[i] = src.vx[o];
-    dst.vy[i] = src.vy[o];
-    dst.vz[i] = src.vz[o];
-    dst.wx[i] = src.wx[o];
-    dst.wy[i] = src.wy[o];
-    dst.wz[i] = src.wz[o];
-    dst.qw[i] = src.qw[o];
-    dst.qx[i] = src.qx[o];
-    dst.qy[i] = src.qy[o];
-    dst.qz[i] = src.qz[o];
-    dst.rad[i] = src.rad[o];
-    dst.mass[i] = src.mass[o];
+    dst.xr[i] = src.xr[o];
+    dst.vm[i] = src.vm[o];
+    dst.w[i] = src.w[o];
+    dst.q[i] = src.q[o];
     dst.mat[i] = src.mat[o];
     dst.blocked[i] = src.blocked[o];
     const int32_t id = src.id[o];
@@ -294,7 +286,8 @@ __device__ inline void for_each_candidate(const SweepArgs& a, int i, F&& f)
     const Bodies& B = g.bod;
     const int s = BATCHED ? (int)B.scene[i] : 0;
     const SceneParams& P = (BATCHED || PERIODIC) ? g.scenes[s] : g.scene0;
-    const double xi = B.x[i], yi = B.y[i], zi = B.z[i], ri = B.rad[i];
+    const double4 pi = B.xr[i];
+    const double xi = pi.x, yi = pi.y, zi = pi.z, ri = pi.w;
     const int32_t myid = B.id[i];
     const double reach = 2.0 * P.verlet;
     int c[3], per_i[3];
@@ -323,14 +316,16 @@ __device__ inline void for_each_candidate(const SweepArgs& a, int i, F&& f)
                 const uint32_t en = a.cell_end[lin];
                 for (uint32_t j = st; j < en; ++j) {
                     if ((int)j == i) continue;
-                    const double rj = B.rad[j];
+                    const double4 pj = B.xr[j];
+                    const double rj = pj.w;
                     const double sc = (ri + rj) + reach;
                     double ddx, ddy, ddz;
                     int32_t packed = kCellZero;
                     if (PERIODIC) {
-                        int pj[3];
-                        unpack_cell(B.period[j], pj);
-                        const int cc[3] = {per_i[0] - pj[0] + w[0], per_i[1] - pj[1] + w[1], per_i[2] - pj[2] + w[2]};
+                        int perj[3];
+                        unpack_cell(B.period[j], perj);
+                        const int cc[3] = {per_i[0] - perj[0] + w[0], per_i[1] - perj[1] + w[1],
+                                           per_i[2] - perj[2] + w[2]};
                         packed = pack_cell(cc[0], cc[1], cc[2]);
                         // evaluate from the lower id's side so that both bodies of
                         // a pair take the same decision
@@ -340,15 +335,15 @@ __device__ inline void for_each_candidate(const SweepArgs& a, int i, F&& f)
                         const double sx = (H[0] * (sg * cc[0]) + H[1] * (sg * cc[1])) + H[2] * (sg * cc[2]);
                         const double sy = (H[3] * (sg * cc[0]) + H[4] * (sg * cc[1])) + H[5] * (sg * cc[2]);
                         const double sz = (H[6] * (sg * cc[0]) + H[7] * (sg * cc[1])) + H[8] * (sg * cc[2]);
-                        const double ax = from_i ? xi : B.x[j], ay = from_i ? yi : B.y[j], az = from_i ? zi : B.z[j];
-                        const double bx = from_i ? B.x[j] : xi, by = from_i ? B.y[j] : yi, bz = from_i ? B.z[j] : zi;
+                        const double ax = from_i ? xi : pj.x, ay = from_i ? yi : pj.y, az = from_i ? zi : pj.z;
+                        const double bx = from_i ? pj.x : xi, by = from_i ? pj.y : yi, bz = from_i ? pj.z : zi;
                         ddx = (bx + sx) - ax;
                         ddy = (by + sy) - ay;
                         ddz = (bz + sz) - az;
                     } else {
-                        ddx = B.x[j] - xi;
-                        ddy = B.y[j] - yi;
-                        ddz = B.z[j] - zi;
+                        ddx = pj.x - xi;
+                        ddy = pj.y - yi;
+                        ddz = pj.z - zi;
                     }
                     const double dd = (ddx * ddx + ddy * ddy) + ddz * ddz;
                     if (dd < sc * sc) f((int32_t)j, B.id[j], packed);
@@ -429,11 +424,11 @@ __global__ void __launch_bounds__(kBlock) k_pair_build(PairBuildArgs a)
                 // a wall pair: the wall is #1 and has no row
                 a.pr.a[k] = slot;
                 a.pr.b[k] = i;
-                a.pr.e2[k] = e;
+                a.rows.ent[e] = k;
             } else {
                 a.pr.a[k] = i;
                 a.pr.b[k] = slot;
-                a.pr.e1[k] = e;
+                a.rows.ent[e] = k | kNegSign;
             }
             a.pr.cell[k] = a.ent_cell[e];
             a.pr.pid[k] = a.ent_pid[e];
@@ -451,9 +446,11 @@ __global__ void __launch_bounds__(kBlock) k_pair_build(PairBuildArgs a)
                 else
                     hi = mid;
             }
+            uint32_t k = kPairMask;
             if (lo < a.row_start[slot + 1] && a.ent_pid[lo] == myid && (uint32_t)a.ent_cell[lo] == want &&
                 a.ent_own[lo])
-                a.pr.e2[a.own_scan[lo]] = e;
+                k = a.own_scan[lo];
+            a.rows.ent[e] = k;
         }
     }
     a.hist_new.own_begin[myid] = (int32_t)a.own_scan[beg];

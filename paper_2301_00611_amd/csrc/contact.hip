@@ -2,9 +2,9 @@
 // thread per candidate pair runs the exact contact test, the ScGeom update
 // (class ScGeom; section 2.1.3), Ip2_FrictMat_FrictMat_FrictPhys (section
 // 2.1.2) and Law2_ScGeom_FrictPhys_CundallStrack (section 2.1.4), and writes
-// the pair's shear history and its force into the force records of the two
-// row entries of the pair (one per body).  No sum happens here: each body
-// adds its row's records later, in a fixed order (integrate.hip).
+// the pair's shear history and its force record (force on #2, n x F).  No
+// sum happens here: each body adds its pairs' records later, in a fixed
+// order (integrate.hip).
 //
 // FP64 mode computes everything in double.  FP32-mixed mode keeps the
 // contact test, the branch length and the overlap in double (they are
@@ -91,42 +91,6 @@ __device__ inline int logical_block(int nb)
     return xcd * q + (xcd < r ? xcd : r) + idx;
 }
 
-// A row entry's force record: the force on that body and n x F.
-template <int PREC, typename R>
-__device__ inline void put_slot(const Rows& rows, int e, V3<R> f, V3<R> t)
-{
-    if (e < 0) return;
-    if (PREC == DEM_FP32_MIXED) {
-        float* q = rows.slotf + (size_t)kSlotWords * e;
-        q[0] = (float)f.x;
-        q[1] = (float)f.y;
-        q[2] = (float)f.z;
-        q[3] = (float)t.x;
-        q[4] = (float)t.y;
-        q[5] = (float)t.z;
-    } else {
-        double* q = rows.slot + (size_t)kSlotWords * e;
-        q[0] = (double)f.x;
-        q[1] = (double)f.y;
-        q[2] = (double)f.z;
-        q[3] = (double)t.x;
-        q[4] = (double)t.y;
-        q[5] = (double)t.z;
-    }
-}
-template <int PREC>
-__device__ inline void clear_slot(const Rows& rows, int e)
-{
-    if (e < 0) return;
-    if (PREC == DEM_FP32_MIXED) {
-        float* q = rows.slotf + (size_t)kSlotWords * e;
-        for (int w = 0; w < kSlotWords; ++w) q[w] = 0.0f;
-    } else {
-        double* q = rows.slot + (size_t)kSlotWords * e;
-        for (int w = 0; w < kSlotWords; ++w) q[w] = 0.0;
-    }
-}
-
 struct ContactPartial {
     double el, plast;
     unsigned long long ss, sw;
@@ -156,17 +120,19 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
         const SceneParams& S = (BATCHED || PERIODIC) ? a.scenes[s] : a.scene0;
         const double dt = S.dt;
 
-        const double x2 = B.x[sb], y2 = B.y[sb], z2 = B.z[sb], r2 = B.rad[sb];
+        const double4 p2 = B.xr[sb];
+        const double x2 = p2.x, y2 = p2.y, z2 = p2.z, r2 = p2.w;
         const int m2 = B.mat[sb];
         const bool wall = sa < 0;
         double x1 = 0.0, y1 = 0.0, z1 = 0.0, r1 = 0.0;
         int m1;
         Wall W;
         if (!wall) {
-            x1 = B.x[sa];
-            y1 = B.y[sa];
-            z1 = B.z[sa];
-            r1 = B.rad[sa];
+            const double4 p1 = B.xr[sa];
+            x1 = p1.x;
+            y1 = p1.y;
+            z1 = p1.z;
+            r1 = p1.w;
             m1 = B.mat[sa];
         } else {
             W = a.walls[-1 - sa];
@@ -207,8 +173,6 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
                 P.ny[k] = 0.0;
                 P.nz[k] = 0.0;
                 P.real[k] = 0;
-                clear_slot<PREC>(a.rows, P.e1[k]);
-                clear_slot<PREC>(a.rows, P.e2[k]);
             }
         } else {
             // ---- ScGeom inputs
@@ -216,11 +180,13 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
             const double R2d = r2;
             V3<double> v1d = v3(0.0, 0.0, 0.0), w1d = v3(0.0, 0.0, 0.0);
             if (!wall) {
-                v1d = v3(B.vx[sa], B.vy[sa], B.vz[sa]);
-                w1d = v3(B.wx[sa], B.wy[sa], B.wz[sa]);
+                const double4 va = B.vm[sa], wa = B.w[sa];
+                v1d = v3(va.x, va.y, va.z);
+                w1d = v3(wa.x, wa.y, wa.z);
             }
-            V3<double> v2d = v3(B.vx[sb], B.vy[sb], B.vz[sb]);
-            const V3<double> w2d = v3(B.wx[sb], B.wy[sb], B.wz[sb]);
+            const double4 vb = B.vm[sb], wb = B.w[sb];
+            V3<double> v2d = v3(vb.x, vb.y, vb.z);
+            const V3<double> w2d = v3(wb.x, wb.y, wb.z);
             if (PERIODIC) {
                 // the image of #2 moves with the cell: (H - H_prev) c / dt
                 const double* D = S.dH;
@@ -282,9 +248,23 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
             P.nx[k] = (double)n.x;
             P.ny[k] = (double)n.y;
             P.nz[k] = (double)n.z;
-            // the force on #2 into #2's row entry, its negation into #1's
-            put_slot<PREC>(a.rows, P.e2[k], F, tau);
-            put_slot<PREC>(a.rows, P.e1[k], v3<R>((R)0, (R)0, (R)0) - F, tau);
+            if (PREC == DEM_FP32_MIXED) {
+                float* q = P.frecf + (size_t)kForceWords * k;
+                q[0] = (float)F.x;
+                q[1] = (float)F.y;
+                q[2] = (float)F.z;
+                q[3] = (float)tau.x;
+                q[4] = (float)tau.y;
+                q[5] = (float)tau.z;
+            } else {
+                double* q = P.frec + (size_t)kForceWords * k;
+                q[0] = (double)F.x;
+                q[1] = (double)F.y;
+                q[2] = (double)F.z;
+                q[3] = (double)tau.x;
+                q[4] = (double)tau.y;
+                q[5] = (double)tau.z;
+            }
             P.real[k] = 1;
             if (wall)
                 part.sw = 1;

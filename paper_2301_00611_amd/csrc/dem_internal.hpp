@@ -63,13 +63,14 @@ struct Material {
     double density;
 };
 
-// Body arrays of one buffer set.
+// Body arrays of one buffer set.  The per-body vectors are packed four
+// doubles wide (32 bytes, one aligned load), so that gathering a partner's
+// position and radius, or its velocity, touches one memory segment.
 struct Bodies {
-    double *x, *y, *z;
-    double *vx, *vy, *vz;
-    double *wx, *wy, *wz;
-    double *qw, *qx, *qy, *qz;
-    double *rad, *mass;
+    double4 *xr;              // x, y, z, radius
+    double4 *vm;              // vx, vy, vz, mass
+    double4 *w;               // wx, wy, wz, 0
+    double4 *q;               // qw, qx, qy, qz
     uint16_t *mat;            // material index
     uint8_t *blocked;
     int32_t *id;              // slot -> body id
@@ -87,18 +88,17 @@ struct Pairs {
     uint8_t *real;            // 1 when the pair touched at the last evaluation
     double *fsx, *fsy, *fsz;  // shear force on #2 (history)
     double *nx, *ny, *nz;     // normal of the last step; 0 for a non-real pair
-    int32_t *e1, *e2;         // row entries of #1 (-1 for a wall) and #2, -1 if none
+    // force on #2 and n x F of the last step, one record of kForceWords
+    // values per pair (one contiguous gather per real row entry)
+    double *frec;             // FP64 mode
+    float *frecf;             // FP32-mixed mode
 };
+constexpr int kForceWords = 6;
 
-// Rows: for every slot, its candidate pairs sorted by partner id.  Each row
-// entry owns one force record that the contact kernel fills for a real
-// pair (the force on this body and n x F) and clears when the pair stops
-// touching, so the per-body sum streams its row with no gather.
-constexpr int kSlotWords = 6;     // Fx, Fy, Fz, (n x F)x, y, z
+// Rows: for every slot, its candidate pairs sorted by partner id.
 struct Rows {
     int32_t *start;           // nslots + 1
-    double *slot;             // FP64: kSlotWords doubles per entry
-    float *slotf;             // FP32-mixed: kSlotWords floats per entry
+    uint32_t *ent;            // pair index | kNegSign when the body is #1
 };
 
 // History of the previous candidate list, keyed by ids.
@@ -237,7 +237,7 @@ void launch_body_forces(const StepArgs& a, int precision, double* f3, double* t3
 // Love-Weber stress partial sums (9 doubles per block) of the last step's
 // real sphere-sphere contacts; `scene` selects a batch scene.
 int stress_blocks(int npairs);
-// Force on #2 of every pair (3 doubles per pair), gathered from the row records.
+// Force on #2 of every pair (3 doubles per pair; 0 for a pair not touching).
 void launch_pair_forces(const StepArgs& a, int precision, double* f3, hipStream_t st);
 void launch_stress(const StepArgs& a, int precision, bool batched, int scene, double* part, hipStream_t st);
 

@@ -1,6 +1,6 @@
 // integrate.hip -- ForceContainer sum + NewtonIntegrator (section 2.1.5).
 //
-// One thread per body: the body adds the force records of its row one by
+// One thread per body: the body adds the forces of its candidate pairs one by
 // one, in ascending partner id (its row order), so the sum is deterministic
 // and needs no atomics; then gravity (damped like any force, dampGravity),
 // Cundall damping eq. 2.9 per component with the on-step velocity estimate
@@ -29,8 +29,9 @@ __device__ inline int logical_block(int nb)
 
 __device__ inline double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
 
-// Resultant contact force and torque on slot i: its row's force records in
-// row order (ascending partner id); a record is zero unless its pair is real.
+// Resultant contact force and torque on slot i, in row order (ascending
+// partner id): the force records of its real pairs, negated where the body
+// is #1.
 template <int PREC>
 __device__ inline void body_sum(const StepArgs& a, int i, double r, double* F, double* T)
 {
@@ -38,9 +39,12 @@ __device__ inline void body_sum(const StepArgs& a, int i, double r, double* F, d
     T[0] = T[1] = T[2] = 0.0;
     const int beg = a.rows.start[i], end = a.rows.start[i + 1];
     for (int e = beg; e < end; ++e) {
+        const uint32_t u = a.rows.ent[e];
+        const uint32_t k = u & kPairMask;
+        if (k >= (uint32_t)a.npairs || !a.pr.real[k]) continue;
         double f0, f1, f2, t0, t1, t2;
         if (PREC == DEM_FP32_MIXED) {
-            const float* q = a.rows.slotf + (size_t)kSlotWords * e;
+            const float* q = a.pr.frecf + (size_t)kForceWords * k;
             f0 = q[0];
             f1 = q[1];
             f2 = q[2];
@@ -48,7 +52,7 @@ __device__ inline void body_sum(const StepArgs& a, int i, double r, double* F, d
             t1 = q[4];
             t2 = q[5];
         } else {
-            const double* q = a.rows.slot + (size_t)kSlotWords * e;
+            const double* q = a.pr.frec + (size_t)kForceWords * k;
             f0 = q[0];
             f1 = q[1];
             f2 = q[2];
@@ -56,9 +60,15 @@ __device__ inline void body_sum(const StepArgs& a, int i, double r, double* F, d
             t1 = q[4];
             t2 = q[5];
         }
-        F[0] += f0;
-        F[1] += f1;
-        F[2] += f2;
+        if (u & kNegSign) {
+            F[0] += -f0;
+            F[1] += -f1;
+            F[2] += -f2;
+        } else {
+            F[0] += f0;
+            F[1] += f1;
+            F[2] += f2;
+        }
         // both bodies of a pair feel -r_k (n x F) (lever arms r1 n and -r2 n)
         T[0] += -r * t0;
         T[1] += -r * t1;
@@ -96,15 +106,16 @@ __global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restr
         const SceneParams& S = (BATCHED || PERIODIC) ? a.scenes[s] : a.scene0;
         const double dt = S.dt;
         const double lam = S.damping;
-        const double r = B.rad[i], m = B.mass[i];
+        const double4 xr0 = B.xr[i], vm0 = B.vm[i], w0 = B.w[i];
+        const double r = xr0.w, m = vm0.w;
         const double I = 2.0 * m * r * r / 5.0;
         const unsigned blocked = B.blocked[i];
         double F[3], T[3];
         body_sum<PREC>(a, i, r, F, T);
 
-        const double x0[3] = {B.x[i], B.y[i], B.z[i]};
-        const double v0[3] = {B.vx[i], B.vy[i], B.vz[i]};
-        double w[3] = {B.wx[i], B.wy[i], B.wz[i]};
+        const double x0[3] = {xr0.x, xr0.y, xr0.z};
+        const double v0[3] = {vm0.x, vm0.y, vm0.z};
+        double w[3] = {w0.x, w0.y, w0.z};
         double f[3], t[3];
         for (int k = 0; k < 3; ++k) {
             f[k] = F[k] + m * S.gravity[k];
@@ -146,9 +157,11 @@ __global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restr
             }
             w[k] = w[k] + t[k] / I * dt;
         }
-        double q[4] = {B.qw[i], B.qx[i], B.qy[i], B.qz[i]};
         const double wn = sqrt((w[0] * w[0] + w[1] * w[1]) + w[2] * w[2]);
         if (wn > 0.0) {
+            // the orientation only changes (and is only read) for a spinning body
+            const double4 q0 = B.q[i];
+            double q[4] = {q0.x, q0.y, q0.z, q0.w};
             const double half = 0.5 * wn * dt;
             const double sh = sin(half) / wn;
             const double d0 = cos(half), d1 = w[0] * sh, d2 = w[1] * sh, d3 = w[2] * sh;
@@ -161,20 +174,12 @@ __global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restr
             q[1] = n1 / qn;
             q[2] = n2 / qn;
             q[3] = n3 / qn;
-            B.qw[i] = q[0];
-            B.qx[i] = q[1];
-            B.qy[i] = q[2];
-            B.qz[i] = q[3];
+            B.q[i] = make_double4(q[0], q[1], q[2], q[3]);
         }
-        B.x[i] = x1[0];
-        B.y[i] = x1[1];
-        B.z[i] = x1[2];
-        B.vx[i] = v[0];
-        B.vy[i] = v[1];
-        B.vz[i] = v[2];
-        B.wx[i] = w[0];
-        B.wy[i] = w[1];
-        B.wz[i] = w[2];
+        B.xr[i] = make_double4(x1[0], x1[1], x1[2], r);
+        B.vm[i] = make_double4(v[0], v[1], v[2], m);
+        // an unchanged spin (no torque, or blocked) is not stored again
+        if (w[0] != w0.x || w[1] != w0.y || w[2] != w0.z) B.w[i] = make_double4(w[0], w[1], w[2], 0.0);
 
         // non-affine displacement of this step, added to the body's Verlet
         // account (eq. 2.3); the cell's mean field uses its own share
@@ -268,7 +273,7 @@ __global__ void k_body_forces(StepArgs a, double* __restrict__ f3, double* __res
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.nslots) return;
     double F[3], T[3];
-    body_sum<PREC>(a, i, a.bod.rad[i], F, T);
+    body_sum<PREC>(a, i, a.bod.xr[i].w, F, T);
     for (int k = 0; k < 3; ++k) {
         f3[3 * i + k] = F[k];
         t3[3 * i + k] = T[k];

@@ -80,10 +80,11 @@ struct DBuf {
 };
 
 struct BodySet {
-    DBuf x, y, z, vx, vy, vz, wx, wy, wz, qw, qx, qy, qz, rad, mass, mat, blocked, id, scene, period, disp;
+    DBuf xr, vm, w, q, mat, blocked, id, scene, period, disp;
     void ensure(size_t n)
     {
-        for (DBuf* b : {&x, &y, &z, &vx, &vy, &vz, &wx, &wy, &wz, &qw, &qx, &qy, &qz, &rad, &mass, &disp}) b->ensure(n * 8);
+        for (DBuf* b : {&xr, &vm, &w, &q}) b->ensure(n * sizeof(double4));
+        disp.ensure(n * 8);
         mat.ensure(n * 2);
         blocked.ensure(n);
         id.ensure(n * 4);
@@ -93,21 +94,10 @@ struct BodySet {
     Bodies view() const
     {
         Bodies b;
-        b.x = x.as<double>();
-        b.y = y.as<double>();
-        b.z = z.as<double>();
-        b.vx = vx.as<double>();
-        b.vy = vy.as<double>();
-        b.vz = vz.as<double>();
-        b.wx = wx.as<double>();
-        b.wy = wy.as<double>();
-        b.wz = wz.as<double>();
-        b.qw = qw.as<double>();
-        b.qx = qx.as<double>();
-        b.qy = qy.as<double>();
-        b.qz = qz.as<double>();
-        b.rad = rad.as<double>();
-        b.mass = mass.as<double>();
+        b.xr = xr.as<double4>();
+        b.vm = vm.as<double4>();
+        b.w = w.as<double4>();
+        b.q = q.as<double4>();
         b.mat = mat.as<uint16_t>();
         b.blocked = blocked.as<uint8_t>();
         b.id = id.as<int32_t>();
@@ -118,22 +108,21 @@ struct BodySet {
     }
     void release()
     {
-        for (DBuf* b : {&x, &y, &z, &vx, &vy, &vz, &wx, &wy, &wz, &qw, &qx, &qy, &qz, &rad, &mass, &mat, &blocked, &id,
-                        &scene, &period, &disp})
-            b->release();
+        for (DBuf* b : {&xr, &vm, &w, &q, &mat, &blocked, &id, &scene, &period, &disp}) b->release();
     }
 };
 
 struct PairSet {
-    DBuf a, b, cell, pid, real, fsx, fsy, fsz, nx, ny, nz, e1, e2;
+    DBuf a, b, cell, pid, real, fsx, fsy, fsz, nx, ny, nz, frec;
     DBuf own_begin, own_count;  // by gid
     size_t cap = 0;
-    void ensure(size_t n)
+    void ensure(size_t n, bool fp32)
     {
         n = std::max<size_t>(n, 1);
-        for (DBuf* d : {&a, &b, &cell, &pid, &e1, &e2}) d->ensure(n * 4);
+        for (DBuf* d : {&a, &b, &cell, &pid}) d->ensure(n * 4);
         real.ensure(n);
         for (DBuf* d : {&fsx, &fsy, &fsz, &nx, &ny, &nz}) d->ensure(n * 8);
+        frec.ensure(n * kForceWords * (fp32 ? sizeof(float) : sizeof(double)));
         cap = n;
     }
     Pairs view() const
@@ -150,8 +139,8 @@ struct PairSet {
         p.nx = nx.as<double>();
         p.ny = ny.as<double>();
         p.nz = nz.as<double>();
-        p.e1 = e1.as<int32_t>();
-        p.e2 = e2.as<int32_t>();
+        p.frec = frec.as<double>();
+        p.frecf = frec.as<float>();
         return p;
     }
     History history() const
@@ -171,7 +160,7 @@ struct PairSet {
     }
     void release()
     {
-        for (DBuf* d : {&a, &b, &cell, &pid, &real, &fsx, &fsy, &fsz, &nx, &ny, &nz, &e1, &e2, &own_begin, &own_count})
+        for (DBuf* d : {&a, &b, &cell, &pid, &real, &fsx, &fsy, &fsz, &nx, &ny, &nz, &frec, &own_begin, &own_count})
             d->release();
         cap = 0;
     }
@@ -242,7 +231,7 @@ struct World {
     int ngids_dev = 0;                 // number of gids the device arrays were built for
     int old_ngids = 0;                 // gids covered by the active own arrays
     DBuf slot_of_id, keys, vals, keys_alt, vals_alt, cell_start, cell_end, counts, row_start;
-    DBuf ent_slot, ent_pid, ent_cell, ent_own, own_scan, rows_slot, scan_tmp, radix_tmp;
+    DBuf ent_slot, ent_pid, ent_cell, ent_own, own_scan, rows_ent, scan_tmp, radix_tmp;
     DBuf d_scenes, d_walls, d_mats, d_tanphi, d_ctr, d_part_c, d_part_i, d_bounds, d_total, d_tmp3, d_args;
     int grid_c = 1, grid_i = 1;        // step-kernel grids (contact sized with headroom)
     int acc_c_n = 0, acc_i_n = 0;      // slots currently in use in d_part_c / d_part_i
@@ -291,7 +280,7 @@ struct World {
         for (auto& b : bs) b.release();
         for (auto& p : ps) p.release();
         for (DBuf* d : {&slot_of_id, &keys, &vals, &keys_alt, &vals_alt, &cell_start, &cell_end, &counts, &row_start,
-                        &ent_slot, &ent_pid, &ent_cell, &ent_own, &own_scan, &rows_slot, &scan_tmp, &radix_tmp,
+                        &ent_slot, &ent_pid, &ent_cell, &ent_own, &own_scan, &rows_ent, &scan_tmp, &radix_tmp,
                         &d_scenes, &d_walls, &d_mats, &d_tanphi, &d_ctr, &d_part_c, &d_part_i, &d_bounds, &d_total,
                         &d_tmp3, &d_args})
             d->release();
@@ -410,29 +399,24 @@ struct World {
     void pull_bodies()
     {
         if (!on_device || host_dirty) return;
-        std::vector<double> buf((size_t)nslots);
+        std::vector<double> buf(4 * (size_t)nslots);
         std::vector<int32_t> ids((size_t)nslots);
         const BodySet& B = bs[active];
         HIPC(hipMemcpyAsync(ids.data(), B.id.p, 4 * (size_t)nslots, hipMemcpyDeviceToHost, stream));
         HIPC(hipStreamSynchronize(stream));
-        auto pull = [&](const DBuf& d, auto setter) {
-            HIPC(hipMemcpyAsync(buf.data(), d.p, 8 * (size_t)nslots, hipMemcpyDeviceToHost, stream));
+        // packed 4-vectors: component c of slot i is buf[4 i + c]
+        auto pull = [&](const DBuf& d, double* (*field)(HostBody&), int ncomp) {
+            HIPC(hipMemcpyAsync(buf.data(), d.p, 32 * (size_t)nslots, hipMemcpyDeviceToHost, stream));
             HIPC(hipStreamSynchronize(stream));
-            for (int i = 0; i < nslots; ++i) setter(bodies[ids[i]], buf[i]);
+            for (int i = 0; i < nslots; ++i) {
+                double* dst = field(bodies[ids[i]]);
+                for (int c = 0; c < ncomp; ++c) dst[c] = buf[4 * (size_t)i + c];
+            }
         };
-        pull(B.x, [](HostBody& b, double v) { b.x[0] = v; });
-        pull(B.y, [](HostBody& b, double v) { b.x[1] = v; });
-        pull(B.z, [](HostBody& b, double v) { b.x[2] = v; });
-        pull(B.vx, [](HostBody& b, double v) { b.v[0] = v; });
-        pull(B.vy, [](HostBody& b, double v) { b.v[1] = v; });
-        pull(B.vz, [](HostBody& b, double v) { b.v[2] = v; });
-        pull(B.wx, [](HostBody& b, double v) { b.w[0] = v; });
-        pull(B.wy, [](HostBody& b, double v) { b.w[1] = v; });
-        pull(B.wz, [](HostBody& b, double v) { b.w[2] = v; });
-        pull(B.qw, [](HostBody& b, double v) { b.q[0] = v; });
-        pull(B.qx, [](HostBody& b, double v) { b.q[1] = v; });
-        pull(B.qy, [](HostBody& b, double v) { b.q[2] = v; });
-        pull(B.qz, [](HostBody& b, double v) { b.q[3] = v; });
+        pull(B.xr, [](HostBody& b) { return b.x; }, 3);
+        pull(B.vm, [](HostBody& b) { return b.v; }, 3);
+        pull(B.w, [](HostBody& b) { return b.w; }, 3);
+        pull(B.q, [](HostBody& b) { return b.q; }, 4);
     }
 
     int64_t add_spheres(int s, int64_t n, const double* pos3, const double* radius, const double* vel3,
@@ -539,27 +523,20 @@ struct World {
         const size_t n = std::max<size_t>(nslots, 1);
         for (auto& b : bs) b.ensure(n);
         BodySet& B = bs[active];
-        std::vector<double> col(n);
+        std::vector<double> col(4 * n);
+        // packed 4-vectors: component c of slot i goes to col[4 i + c]
         auto push = [&](DBuf& d, auto get) {
-            for (int i = 0; i < nslots; ++i) col[i] = get(bodies[sph[i]]);
-            HIPC(hipMemcpyAsync(d.p, col.data(), 8 * (size_t)nslots, hipMemcpyHostToDevice, stream));
+            for (int i = 0; i < nslots; ++i) {
+                const HostBody& b = bodies[sph[i]];
+                for (int c = 0; c < 4; ++c) col[4 * (size_t)i + c] = get(b, c);
+            }
+            HIPC(hipMemcpyAsync(d.p, col.data(), 32 * (size_t)nslots, hipMemcpyHostToDevice, stream));
             HIPC(hipStreamSynchronize(stream));
         };
-        push(B.x, [](const HostBody& b) { return b.x[0]; });
-        push(B.y, [](const HostBody& b) { return b.x[1]; });
-        push(B.z, [](const HostBody& b) { return b.x[2]; });
-        push(B.vx, [](const HostBody& b) { return b.v[0]; });
-        push(B.vy, [](const HostBody& b) { return b.v[1]; });
-        push(B.vz, [](const HostBody& b) { return b.v[2]; });
-        push(B.wx, [](const HostBody& b) { return b.w[0]; });
-        push(B.wy, [](const HostBody& b) { return b.w[1]; });
-        push(B.wz, [](const HostBody& b) { return b.w[2]; });
-        push(B.qw, [](const HostBody& b) { return b.q[0]; });
-        push(B.qx, [](const HostBody& b) { return b.q[1]; });
-        push(B.qy, [](const HostBody& b) { return b.q[2]; });
-        push(B.qz, [](const HostBody& b) { return b.q[3]; });
-        push(B.rad, [](const HostBody& b) { return b.r; });
-        push(B.mass, [](const HostBody& b) { return b.m; });
+        push(B.xr, [](const HostBody& b, int c) { return c < 3 ? b.x[c] : b.r; });
+        push(B.vm, [](const HostBody& b, int c) { return c < 3 ? b.v[c] : b.m; });
+        push(B.w, [](const HostBody& b, int c) { return c < 3 ? b.w[c] : 0.0; });
+        push(B.q, [](const HostBody& b, int c) { return b.q[c]; });
         std::vector<uint8_t> u8(n);
         std::vector<int32_t> i32(n);
         std::vector<uint16_t> u16(n);
@@ -787,11 +764,7 @@ struct World {
             ent_cell.ensure(4 * ((size_t)nent + 1));
             ent_own.ensure(4 * ((size_t)nent + 1));
             own_scan.ensure(4 * ((size_t)nent + 1));
-            // one force record per row entry, cleared: a record is non-zero
-            // only while its pair is real
-            const size_t rec = precision == DEM_FP32_MIXED ? sizeof(float) : sizeof(double);
-            rows_slot.ensure(rec * kSlotWords * ((size_t)nent + 1));
-            HIPC(hipMemsetAsync(rows_slot.p, 0, rec * kSlotWords * ((size_t)nent + 1), stream));
+            rows_ent.ensure(4 * ((size_t)nent + 1));
             sw.row_start = row_start.as<int32_t>();
             sw.ent_slot = ent_slot.as<int32_t>();
             sw.ent_pid = ent_pid.as<int32_t>();
@@ -812,9 +785,7 @@ struct World {
             // new pair set
             PairSet& NP = ps[1 - pactive];
             PairSet& OP = ps[pactive];
-            NP.ensure(np);
-            launch_fill_u32(NP.e1.as<uint32_t>(), 0xffffffffu, (int)np, stream);
-            launch_fill_u32(NP.e2.as<uint32_t>(), 0xffffffffu, (int)np, stream);
+            NP.ensure(np, precision == DEM_FP32_MIXED);
             const int ng = (int)bodies.size();
             NP.own_begin.ensure(4 * (size_t)std::max(ng, 1));
             NP.own_count.ensure(4 * (size_t)std::max(ng, 1));
@@ -829,8 +800,7 @@ struct World {
             pb.own_scan = own_scan.as<uint32_t>();
             pb.ent_own = ent_own.as<uint32_t>();
             pb.rows.start = row_start.as<int32_t>();
-            pb.rows.slot = rows_slot.as<double>();
-            pb.rows.slotf = rows_slot.as<float>();
+            pb.rows.ent = rows_ent.as<uint32_t>();
             pb.pr = NP.view();
             pb.hist_new = NP.history();
             pb.hist_old = OP.history();
@@ -971,8 +941,7 @@ struct World {
         a.bod = bs[active].view();
         a.pr = ps[pactive].view();
         a.rows.start = row_start.as<int32_t>();
-        a.rows.slot = rows_slot.as<double>();
-        a.rows.slotf = rows_slot.as<float>();
+        a.rows.ent = rows_ent.as<uint32_t>();
         a.walls = d_walls.as<Wall>();
         a.mats = d_mats.as<Material>();
         a.tanphi = d_tanphi.as<double>();
@@ -1138,23 +1107,26 @@ struct World {
         Snapshot s;
         const BodySet& B = bs[active];
         const size_t n = (size_t)nslots;
-        auto get = [&](const DBuf& d, std::vector<double>& v) {
-            v.resize(n);
-            if (n) HIPC(hipMemcpyAsync(v.data(), d.p, 8 * n, hipMemcpyDeviceToHost, stream));
+        std::vector<double> buf(4 * n);
+        // packed 4-vectors: split the components into the snapshot's columns
+        auto get = [&](const DBuf& d, std::vector<double>* cols[4]) {
+            for (int c = 0; c < 4; ++c)
+                if (cols[c]) cols[c]->resize(n);
+            if (!n) return;
+            HIPC(hipMemcpyAsync(buf.data(), d.p, 32 * n, hipMemcpyDeviceToHost, stream));
+            HIPC(hipStreamSynchronize(stream));
+            for (size_t i = 0; i < n; ++i)
+                for (int c = 0; c < 4; ++c)
+                    if (cols[c]) (*cols[c])[i] = buf[4 * i + c];
         };
-        get(B.x, s.x);
-        get(B.y, s.y);
-        get(B.z, s.z);
-        get(B.vx, s.vx);
-        get(B.vy, s.vy);
-        get(B.vz, s.vz);
-        get(B.wx, s.wx);
-        get(B.wy, s.wy);
-        get(B.wz, s.wz);
-        get(B.qw, s.qw);
-        get(B.qx, s.qx);
-        get(B.qy, s.qy);
-        get(B.qz, s.qz);
+        std::vector<double>* cx[4] = {&s.x, &s.y, &s.z, nullptr};
+        std::vector<double>* cv[4] = {&s.vx, &s.vy, &s.vz, nullptr};
+        std::vector<double>* cw[4] = {&s.wx, &s.wy, &s.wz, nullptr};
+        std::vector<double>* cq[4] = {&s.qw, &s.qx, &s.qy, &s.qz};
+        get(B.xr, cx);
+        get(B.vm, cv);
+        get(B.w, cw);
+        get(B.q, cq);
         s.id.resize(n);
         if (n) HIPC(hipMemcpyAsync(s.id.data(), B.id.p, 4 * n, hipMemcpyDeviceToHost, stream));
         HIPC(hipStreamSynchronize(stream));
@@ -1190,7 +1162,7 @@ struct World {
         gd(P.nx, p.nx);
         gd(P.ny, p.ny);
         gd(P.nz, p.nz);
-        // force on #2 of every pair, gathered from #2's row record
+        // force on #2 of every pair
         p.fx.assign(n, 0.0);
         p.fy.assign(n, 0.0);
         p.fz.assign(n, 0.0);
@@ -1541,7 +1513,7 @@ struct World {
         }
         const size_t m = recs.size();
         PairSet& P = ps[pactive];
-        P.ensure(std::max<size_t>(m, (size_t)npairs));
+        P.ensure(std::max<size_t>(m, (size_t)npairs), precision == DEM_FP32_MIXED);
         P.own_begin.ensure(4 * (size_t)std::max(ng, 1));
         P.own_count.ensure(4 * (size_t)std::max(ng, 1));
         std::vector<int32_t> pid(m), cell(m);

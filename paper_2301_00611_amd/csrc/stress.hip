@@ -19,20 +19,19 @@ namespace {
 
 constexpr int kStressBlock = 256;
 
-// Force on #2 of pair k: the record of #2's row entry.
+// Force on #2 of pair k (0 unless the pair touched at the last step).
 template <int PREC>
 __device__ inline void pair_force(const StepArgs& a, int k, double* F)
 {
-    const int e = a.pr.e2[k];
     F[0] = F[1] = F[2] = 0.0;
-    if (e < 0) return;
+    if (!a.pr.real[k]) return;
     if (PREC == DEM_FP32_MIXED) {
-        const float* q = a.rows.slotf + (size_t)kSlotWords * e;
+        const float* q = a.pr.frecf + (size_t)kForceWords * k;
         F[0] = q[0];
         F[1] = q[1];
         F[2] = q[2];
     } else {
-        const double* q = a.rows.slot + (size_t)kSlotWords * e;
+        const double* q = a.pr.frec + (size_t)kForceWords * k;
         F[0] = q[0];
         F[1] = q[1];
         F[2] = q[2];
@@ -66,7 +65,7 @@ __global__ void __launch_bounds__(kStressBlock) k_stress(StepArgs a, int scene, 
             pair_force<PREC>(a, k, F);
             const double n[3] = {P.nx[k], P.ny[k], P.nz[k]};
             const double fn[3] = {F[0] - P.fsx[k], F[1] - P.fsy[k], F[2] - P.fsz[k]};
-            const double r1 = B.rad[sa], r2 = B.rad[sb];
+            const double r1 = B.xr[sa].w, r2 = B.xr[sb].w;
             const Material M1 = a.mats[B.mat[sa]], M2 = a.mats[B.mat[sb]];
             const double k1 = M1.young * (2.0 * r1), k2 = M2.young * (2.0 * r2);
             const double kn = k1 * k2 / (k1 + k2);
