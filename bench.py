@@ -211,7 +211,9 @@ def main():
         log("batched leg")
         out["fp32_mixed"] = {"value": r32["contact_steps"] / r32["seconds"], "unit": "contact-steps/s",
                              "ms_per_step": r32["seconds"] / args.steps * 1e3}
-        out["batched"] = batched_leg()
+        out["batched"] = batched_leg(log=log)
+        log("periodic compression leg (FP64 vs FP32-mixed)")
+        out["periodic_compression"] = periodic_compression_leg(log=log)
     if not args.no_cpu and not args.no_extra:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(spec)
@@ -359,37 +361,77 @@ def periodic_compression_leg(steps=5000, n=2_000_000, log=None):
     return out
 
 
-def batched_leg(n_scenes=512, steps=2000):
-    """C4: 512 independent deposition scenes (log-uniform sizes 500..50,000,
-    per-scene friction and damping) stepped together; scenes.steps/s."""
-    import torch
+def _build_batch(spec, dt, precision=0):
     from paper_2301_00611_amd import dem
-    from paper_2301_00611_amd.scenes import batched_deposition
-    spec = batched_deposition(n_scenes=n_scenes, steps=steps)
-    dt = 0.5 * spec.dt_radius * math.sqrt(2600.0 / 5e7)
-    params = [dem.make_params(dt=dt, gravity=s.gravity, damping=s.damping) for s in spec.scenes]
+    params = [dem.make_params(dt=dt, gravity=s.gravity, damping=s.damping, precision=precision) for s in spec.scenes]
     b = dem.Batch(params)
-    nbodies = 0
     for i, s in enumerate(spec.scenes):
         v = b.scene(i)
         m = v.add_material(s.material.density, s.material.young, s.material.poisson, s.material.friction)
         for w in s.walls:
             v.add_wall(w.axis, w.position, w.sense, m)
         v.add_spheres(s.pos, s.radius, default_mat=m)
-        nbodies += s.n
+    return b
+
+
+def _time_batch(b, steps):
+    import torch
     b.step(1)
-    c0 = b.stats()["contact_steps"]
+    s0 = b.stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.step(steps)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
-    st = b.stats()
-    st["contact_steps"] -= c0
-    b.close()
-    return {"value": n_scenes * steps / t, "unit": "scene-steps/s", "n_scenes": n_scenes, "n_spheres": nbodies,
-            "steps": steps, "seconds": t, "body_steps_per_s": nbodies * steps / t,
-            "contact_steps_per_s": st["contact_steps"] / t if st["contact_steps"] else 0.0}
+    s1 = b.stats()
+    return t, s1["contact_steps"] - s0["contact_steps"]
+
+
+def batched_leg(n_scenes=512, steps=2000, sequential_steps=200, log=None):
+    """C4: 512 independent deposition scenes (log-uniform sizes 500..50,000,
+    per-scene friction and damping) stepped together, FP64 and FP32-mixed:
+    scene-steps/s with the default launch setting and with the autotuner's
+    (its probe steps are not timed), against the same scenes stepped one
+    after another as single FP64 scenes (`sequential_steps` steps each)."""
+    from paper_2301_00611_amd import dem
+    from paper_2301_00611_amd.scenes import batched_deposition
+    log = log or (lambda m: None)
+    spec = batched_deposition(n_scenes=n_scenes, steps=steps)
+    dt = 0.5 * spec.dt_radius * math.sqrt(2600.0 / 5e7)
+    nbodies = sum(s.n for s in spec.scenes)
+    out = {"unit": "scene-steps/s", "n_scenes": n_scenes, "n_spheres": nbodies, "steps": steps}
+    for prec, name in ((0, "fp64"), (1, "fp32_mixed")):
+        b = _build_batch(spec, dt, prec)
+        t_def, c_def = _time_batch(b, steps)
+        tune = b.autotune(probe_steps=100)
+        t_tun, c_tun = _time_batch(b, steps)
+        b.close()
+        out[name] = {"value": n_scenes * steps / t_tun, "seconds": t_tun, "body_steps_per_s": nbodies * steps / t_tun,
+                     "contact_steps_per_s": c_tun / t_tun, "default_setting_value": n_scenes * steps / t_def,
+                     "tuning": tune}
+        log(f"batched {name}: {out[name]}")
+    out["value"] = out["fp64"]["value"]
+    # the same scenes one after another through the single-scene FP64 path
+    import torch
+    t_seq = 0.0
+    for s in spec.scenes:
+        g = dem.Scene(gravity=s.gravity, damping=s.damping)
+        m = g.add_material(s.material.density, s.material.young, s.material.poisson, s.material.friction)
+        for w in s.walls:
+            g.add_wall(w.axis, w.position, w.sense, m)
+        g.add_spheres(s.pos, s.radius, default_mat=m)
+        g.set_dt(dt)
+        g.step(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(sequential_steps)
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t0
+        g.close()
+    out["sequential_fp64"] = {"value": n_scenes * sequential_steps / t_seq, "steps_per_scene": sequential_steps,
+                              "seconds": t_seq}
+    out["speedup_vs_sequential"] = out["value"] / out["sequential_fp64"]["value"]
+    return out
 
 
 if __name__ == "__main__":

@@ -138,6 +138,18 @@ typedef struct {
                                  periodic limitations) and dem_step fails */
 } dem_stats;
 
+/* Performance knobs; none of them changes any result (positions,
+ * velocities, forces and contacts are bit for bit the same whatever the
+ * setting; only the per-block energy partial sums regroup). */
+typedef struct {
+    int32_t block_contact;   /* threads per block of the contact kernel: 64..1024, multiple of 64 */
+    int32_t block_integrate; /* same for the integrate kernel */
+    int32_t chunk;           /* steps per captured HIP graph: even, 2..4096 */
+    int32_t pad;
+    double verlet_factor;    /* Delta L = factor x smallest radius, every scene (0 = keep verlet_dist) */
+    double ms_per_step;      /* wall time per step measured by the autotuner, 0 if never measured */
+} dem_tuning;
+
 int32_t dem_abi_version(void);
 const char* dem_last_error(void);
 /* Fill *p with the documentation's defaults (damping 0.2, verletDist -0.5,
@@ -227,6 +239,20 @@ dem_status dem_get_stats(dem_scene* s, dem_stats* out);
 dem_status dem_set_timing(dem_scene* s, int32_t on);
 dem_status dem_get_timing(dem_scene* s, const char* name, double* avg_ms, int64_t* launches);
 
+/* The autotuner (for the batched form above all, where scene sizes vary):
+ * dem_autotune looks the workload up in the text cache file `cache_path`
+ * (key: GPU architecture, precision, batched/periodic, log2 of the sphere
+ * and candidate counts, number of scenes) and applies the stored setting;
+ * without an entry it times `probe_steps` ordinary steps per candidate
+ * setting, trying block sizes 128..1024, chunks 16/32/64 and Verlet factors
+ * 0.25/0.5/1 one knob at a time, keeps the fastest and appends it to the
+ * cache (NULL or "" = no cache).  The probe steps advance the simulation
+ * like any other steps.  dem_set_tuning on a batch view is refused: use the
+ * batch calls. */
+dem_status dem_get_tuning(dem_scene* s, dem_tuning* out);
+dem_status dem_set_tuning(dem_scene* s, const dem_tuning* t);
+dem_status dem_autotune(dem_scene* s, int64_t probe_steps, const char* cache_path, dem_tuning* out);
+
 /* Batched scenes: n_scenes independent scenes advanced together by the same
  * kernels (one bodies arena, per-scene parameters).  per_scene[i].periodic
  * must be 0; precision, device and stream are taken from per_scene[0]. */
@@ -236,6 +262,8 @@ dem_status dem_batch_create(int32_t n_scenes, const dem_params* per_scene, dem_b
 dem_status dem_batch_scene(dem_batch* b, int32_t i, dem_scene** view);
 dem_status dem_batch_step(dem_batch* b, int64_t nsteps);
 dem_status dem_batch_stats(dem_batch* b, dem_stats* out);
+dem_status dem_batch_set_tuning(dem_batch* b, const dem_tuning* t);
+dem_status dem_batch_autotune(dem_batch* b, int64_t probe_steps, const char* cache_path, dem_tuning* out);
 dem_status dem_batch_destroy(dem_batch* b);
 
 #ifdef __cplusplus

@@ -38,41 +38,45 @@ __device__ inline void body_sum(const StepArgs& a, int i, double r, double* F, d
     F[0] = F[1] = F[2] = 0.0;
     T[0] = T[1] = T[2] = 0.0;
     const int beg = a.rows.start[i], end = a.rows.start[i + 1];
-    for (int e = beg; e < end; ++e) {
-        const uint32_t u = a.rows.ent[e];
-        const uint32_t k = u & kPairMask;
-        if (k >= (uint32_t)a.npairs || !a.pr.real[k]) continue;
-        double f0, f1, f2, t0, t1, t2;
-        if (PREC == DEM_FP32_MIXED) {
-            const float* q = a.pr.frecf + (size_t)kForceWords * k;
-            f0 = q[0];
-            f1 = q[1];
-            f2 = q[2];
-            t0 = q[3];
-            t1 = q[4];
-            t2 = q[5];
-        } else {
-            const double* q = a.pr.frec + (size_t)kForceWords * k;
-            f0 = q[0];
-            f1 = q[1];
-            f2 = q[2];
-            t0 = q[3];
-            t1 = q[4];
-            t2 = q[5];
+    // entries are taken four at a time so that their loads are in flight
+    // together; they are still added one by one in row order
+    constexpr int kB = 4;
+    for (int e0 = beg; e0 < end; e0 += kB) {
+        uint32_t u[kB];
+        bool use[kB];
+        for (int j = 0; j < kB; ++j) u[j] = (e0 + j < end) ? a.rows.ent[e0 + j] : kPairMask;
+        for (int j = 0; j < kB; ++j) {
+            const uint32_t k = u[j] & kPairMask;
+            use[j] = k < (uint32_t)a.npairs && a.pr.real[k];
         }
-        if (u & kNegSign) {
-            F[0] += -f0;
-            F[1] += -f1;
-            F[2] += -f2;
-        } else {
-            F[0] += f0;
-            F[1] += f1;
-            F[2] += f2;
+        double f[kB][kForceWords];
+        for (int j = 0; j < kB; ++j) {
+            const uint32_t k = u[j] & kPairMask;
+            if (!use[j]) continue;
+            if (PREC == DEM_FP32_MIXED) {
+                const float* q = a.pr.frecf + (size_t)kForceWords * k;
+                for (int c = 0; c < kForceWords; ++c) f[j][c] = q[c];
+            } else {
+                const double* q = a.pr.frec + (size_t)kForceWords * k;
+                for (int c = 0; c < kForceWords; ++c) f[j][c] = q[c];
+            }
         }
-        // both bodies of a pair feel -r_k (n x F) (lever arms r1 n and -r2 n)
-        T[0] += -r * t0;
-        T[1] += -r * t1;
-        T[2] += -r * t2;
+        for (int j = 0; j < kB; ++j) {
+            if (!use[j]) continue;
+            if (u[j] & kNegSign) {
+                F[0] += -f[j][0];
+                F[1] += -f[j][1];
+                F[2] += -f[j][2];
+            } else {
+                F[0] += f[j][0];
+                F[1] += f[j][1];
+                F[2] += f[j][2];
+            }
+            // both bodies of a pair feel -r_k (n x F) (lever arms r1 n and -r2 n)
+            T[0] += -r * f[j][3];
+            T[1] += -r * f[j][4];
+            T[2] += -r * f[j][5];
+        }
     }
 }
 

@@ -10,6 +10,9 @@
 // (gid); each scene maps its own ids (0, 1, ... in insertion order) to gids.
 #include <algorithm>
 #include <atomic>
+#include <chrono>
+#include <fstream>
+#include <sstream>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -252,6 +255,7 @@ struct World {
     int64_t n_candidates = 0;
     int block_contact = 256, block_integrate = 256;
     int chunk = 32;
+    double tuned_ms = 0.0;             // ms per step measured by the autotuner
     bool use_graph = true;
 
     // graphs
@@ -932,6 +936,145 @@ struct World {
         if (sw) *sw = fresh ? last_sw : t.sw;
         if (csteps) *csteps = base_contact_steps + t.cum;
         if (maxov) *maxov = fresh ? last_maxov : t.maxov;
+    }
+
+    // ------------------------------------------------------------ tuning
+    // Performance knobs that leave every result unchanged: the launch shape
+    // of the two step kernels, the number of steps per captured graph, and
+    // the Verlet distance (it changes which non-touching pairs are carried
+    // as candidates and how often the broad phase runs, never the real
+    // contacts or the order of a body's force sum).
+    dem_tuning tuning() const
+    {
+        dem_tuning t;
+        std::memset(&t, 0, sizeof t);
+        t.block_contact = block_contact;
+        t.block_integrate = block_integrate;
+        t.chunk = chunk;
+        const double vd = scenes.empty() ? -0.5 : scenes[0].p.verlet_dist;
+        t.verlet_factor = vd < 0.0 ? -vd : 0.0;
+        t.ms_per_step = tuned_ms;
+        return t;
+    }
+    void set_tuning(const dem_tuning& t)
+    {
+        auto ok_block = [](int b) { return b >= 64 && b <= 1024 && b % 64 == 0; };
+        if (!ok_block(t.block_contact) || !ok_block(t.block_integrate))
+            fail(DEM_EINVAL, "tuning: block sizes must be multiples of 64 in [64, 1024]");
+        if (t.chunk < 2 || t.chunk > 4096 || t.chunk % 2) fail(DEM_EINVAL, "tuning: chunk must be even, 2..4096");
+        if (!(t.verlet_factor >= 0.0) || !(t.verlet_factor <= 4.0))
+            fail(DEM_EINVAL, "tuning: verlet_factor must be in [0, 4] (0 keeps each scene's own verlet_dist)");
+        block_contact = t.block_contact;
+        block_integrate = t.block_integrate;
+        chunk = t.chunk;
+        if (t.verlet_factor > 0.0) {
+            for (auto& S : scenes) S.p.verlet_dist = -t.verlet_factor;
+            need_rebuild = true;
+        }
+        // the contact grid follows the block size at the next run
+        grid_c = 0;
+        need_rebuild = true;
+        invalidate_graphs();
+    }
+    // Wall-clock milliseconds per step over `steps` ordinary steps.
+    double probe(int64_t steps)
+    {
+        HIPC(hipStreamSynchronize(stream));
+        const auto t0 = std::chrono::steady_clock::now();
+        step(steps);
+        HIPC(hipStreamSynchronize(stream));
+        const auto t1 = std::chrono::steady_clock::now();
+        return std::chrono::duration<double, std::milli>(t1 - t0).count() / (double)std::max<int64_t>(steps, 1);
+    }
+    std::string tuning_key()
+    {
+        hipDeviceProp_t prop;
+        HIPC(hipGetDeviceProperties(&prop, device));
+        auto lg = [](int64_t v) {
+            int b = 0;
+            while ((int64_t)1 << b < v + 1) ++b;
+            return b;
+        };
+        std::ostringstream k;
+        k << prop.gcnArchName << "|p" << precision << "|b" << (batched() ? 1 : 0) << "|c" << (periodic ? 1 : 0) << "|n"
+          << lg(nslots) << "|k" << lg(n_candidates) << "|s" << scenes.size();
+        std::string key = k.str();
+        for (char& c : key)
+            if (c == ' ' || c == ':') c = '_';
+        return key;
+    }
+    // The autotuner: with a cache file that already holds this workload's
+    // key, apply its entry; otherwise try each knob in turn (coordinate
+    // descent from the current setting), each candidate timed over
+    // `probe_steps` ordinary steps, keep the fastest, and append it to the
+    // cache.  The probe steps advance the simulation like any others.
+    dem_tuning autotune(int64_t probe_steps, const char* cache_path)
+    {
+        if (probe_steps < 2) fail(DEM_EINVAL, "dem_autotune: probe_steps must be >= 2");
+        if (need_rebuild || host_dirty) step(1);  // build the candidate list the key refers to
+        const std::string key = tuning_key();
+        if (cache_path && *cache_path) {
+            std::ifstream in(cache_path);
+            std::string line;
+            while (std::getline(in, line)) {
+                std::istringstream ls(line);
+                std::string k;
+                dem_tuning t;
+                std::memset(&t, 0, sizeof t);
+                if (ls >> k >> t.block_contact >> t.block_integrate >> t.chunk >> t.verlet_factor >> t.ms_per_step &&
+                    k == key) {
+                    set_tuning(t);
+                    tuned_ms = t.ms_per_step;
+                    return tuning();
+                }
+            }
+        }
+        dem_tuning best = tuning();
+        probe(probe_steps);  // warm the current setting (graph capture, first broad phase)
+        best.ms_per_step = probe(probe_steps);
+        const int blocks[] = {128, 256, 512, 1024};
+        const int chunks[] = {16, 32, 64};
+        const double vfs[] = {0.25, 0.5, 1.0};
+        auto trial = [&](dem_tuning t) {
+            set_tuning(t);
+            probe(2);  // first run of the new setting: capture and broad phase
+            t.ms_per_step = probe(probe_steps);
+            if (t.ms_per_step < best.ms_per_step) best = t;
+        };
+        for (double v : vfs)
+            if (v != best.verlet_factor) {
+                dem_tuning t = best;
+                t.verlet_factor = v;
+                trial(t);
+            }
+        for (int b : blocks)
+            if (b != best.block_contact) {
+                dem_tuning t = best;
+                t.block_contact = b;
+                trial(t);
+            }
+        for (int b : blocks)
+            if (b != best.block_integrate) {
+                dem_tuning t = best;
+                t.block_integrate = b;
+                trial(t);
+            }
+        for (int c : chunks)
+            if (c != best.chunk) {
+                dem_tuning t = best;
+                t.chunk = c;
+                trial(t);
+            }
+        set_tuning(best);
+        tuned_ms = best.ms_per_step;
+        if (cache_path && *cache_path) {
+            std::ofstream out(cache_path, std::ios::app);
+            if (!out) fail(DEM_EINVAL, std::string("dem_autotune: cannot write ") + cache_path);
+            out.precision(9);
+            out << key << ' ' << best.block_contact << ' ' << best.block_integrate << ' ' << best.chunk << ' '
+                << best.verlet_factor << ' ' << best.ms_per_step << '\n';
+        }
+        return tuning();
     }
 
     // ------------------------------------------------------------ step
@@ -2010,6 +2153,35 @@ dem_status dem_get_timing(dem_scene* s, const char* name, double* avg_ms, int64_
     });
 }
 
+dem_status dem_get_tuning(dem_scene* s, dem_tuning* out)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        if (!out) dem::fail(DEM_EINVAL, "null out");
+        *out = w->tuning();
+    });
+}
+
+dem_status dem_set_tuning(dem_scene* s, const dem_tuning* t)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        if (!t) dem::fail(DEM_EINVAL, "null tuning");
+        if (!s->owner) dem::fail(DEM_EINVAL, "dem_set_tuning: tune the batch, not one of its scenes");
+        w->set_tuning(*t);
+    });
+}
+
+dem_status dem_autotune(dem_scene* s, int64_t probe_steps, const char* cache_path, dem_tuning* out)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        check_steppable(s, w);
+        const dem_tuning t = w->autotune(probe_steps, cache_path);
+        if (out) *out = t;
+    });
+}
+
 dem_status dem_batch_create(int32_t n_scenes, const dem_params* per_scene, dem_batch** out)
 {
     return guarded([&] {
@@ -2054,6 +2226,27 @@ dem_status dem_batch_stats(dem_batch* b, dem_stats* out)
         if (!b || !out) dem::fail(DEM_EINVAL, "null argument");
         HIPC(hipSetDevice(b->w->device));
         fill_stats(b->w, -1, out);
+    });
+}
+
+dem_status dem_batch_set_tuning(dem_batch* b, const dem_tuning* t)
+{
+    return guarded([&] {
+        if (!b || !t) dem::fail(DEM_EINVAL, "null argument");
+        HIPC(hipSetDevice(b->w->device));
+        b->w->set_tuning(*t);
+    });
+}
+
+dem_status dem_batch_autotune(dem_batch* b, int64_t probe_steps, const char* cache_path, dem_tuning* out)
+{
+    return guarded([&] {
+        if (!b) dem::fail(DEM_EINVAL, "null batch");
+        HIPC(hipSetDevice(b->w->device));
+        for (const auto& S : b->w->scenes)
+            if (!(S.p.dt > 0.0)) dem::fail(DEM_EINVAL, "dem_batch_autotune: dt is not set");
+        const dem_tuning t = b->w->autotune(probe_steps, cache_path);
+        if (out) *out = t;
     });
 }
 

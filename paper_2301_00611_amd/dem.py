@@ -76,6 +76,22 @@ class dem_stats(C.Structure):
     ]
 
 
+class dem_tuning(C.Structure):
+    _fields_ = [("block_contact", C.c_int32), ("block_integrate", C.c_int32), ("chunk", C.c_int32),
+                ("pad", C.c_int32), ("verlet_factor", C.c_double), ("ms_per_step", C.c_double)]
+
+
+def _tuning_dict(t):
+    return {k: getattr(t, k) for k, _ in dem_tuning._fields_ if k != "pad"}
+
+
+def _tuning_struct(d):
+    t = dem_tuning()
+    for k, v in d.items():
+        setattr(t, k, v)
+    return t
+
+
 CONTACT_DTYPE = np.dtype([
     ("id1", np.int64), ("id2", np.int64), ("cell", np.int32, 3), ("is_wall", np.int32),
     ("normal", np.float64, 3), ("pen", np.float64), ("point", np.float64, 3),
@@ -123,6 +139,11 @@ SIGNATURES = {
     "dem_batch_step": (C.c_int32, [C.c_void_p, C.c_int64]),
     "dem_batch_stats": (C.c_int32, [C.c_void_p, C.POINTER(dem_stats)]),
     "dem_batch_destroy": (C.c_int32, [C.c_void_p]),
+    "dem_get_tuning": (C.c_int32, [C.c_void_p, C.POINTER(dem_tuning)]),
+    "dem_set_tuning": (C.c_int32, [C.c_void_p, C.POINTER(dem_tuning)]),
+    "dem_autotune": (C.c_int32, [C.c_void_p, C.c_int64, C.c_char_p, C.POINTER(dem_tuning)]),
+    "dem_batch_set_tuning": (C.c_int32, [C.c_void_p, C.POINTER(dem_tuning)]),
+    "dem_batch_autotune": (C.c_int32, [C.c_void_p, C.c_int64, C.c_char_p, C.POINTER(dem_tuning)]),
 }
 
 _lib = None
@@ -361,6 +382,23 @@ class Scene:
         check(self.lib.dem_get_stress(self.h, float(volume), _p(out)), "dem_get_stress")
         return out.reshape(3, 3)
 
+    def get_tuning(self):
+        t = dem_tuning()
+        check(self.lib.dem_get_tuning(self.h, C.byref(t)), "dem_get_tuning")
+        return _tuning_dict(t)
+
+    def set_tuning(self, **kw):
+        cur = self.get_tuning()
+        cur.update(kw)
+        t = _tuning_struct(cur)
+        check(self.lib.dem_set_tuning(self.h, C.byref(t)), "dem_set_tuning")
+
+    def autotune(self, probe_steps=200, cache_path=None):
+        t = dem_tuning()
+        check(self.lib.dem_autotune(self.h, int(probe_steps), None if cache_path is None else cache_path.encode(),
+                                    C.byref(t)), "dem_autotune")
+        return _tuning_dict(t)
+
     def set_timing(self, on=True):
         check(self.lib.dem_set_timing(self.h, 1 if on else 0), "dem_set_timing")
 
@@ -393,6 +431,22 @@ class Batch:
         s = dem_stats()
         check(self.lib.dem_batch_stats(self.h, C.byref(s)), "dem_batch_stats")
         return {k: getattr(s, k) for k, _ in dem_stats._fields_}
+
+    def get_tuning(self):
+        return self.scene(0).get_tuning()
+
+    def set_tuning(self, **kw):
+        cur = self.get_tuning()
+        cur.update(kw)
+        t = _tuning_struct(cur)
+        check(self.lib.dem_batch_set_tuning(self.h, C.byref(t)), "dem_batch_set_tuning")
+
+    def autotune(self, probe_steps=200, cache_path=None):
+        t = dem_tuning()
+        check(self.lib.dem_batch_autotune(self.h, int(probe_steps),
+                                          None if cache_path is None else cache_path.encode(), C.byref(t)),
+              "dem_batch_autotune")
+        return _tuning_dict(t)
 
     def close(self):
         if self.h:
