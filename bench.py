@@ -150,15 +150,38 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32-mixed, batched and CPU legs")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default="column", choices=("column", "periodic_compression", "batched"),
+                    help="column: the headline line (default); the others run one extra leg alone")
+    ap.add_argument("--prepared-state", default=None,
+                    help="periodic_compression: .npz holding the prepared packing (written if missing)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain 256 MiB device copy three times (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(multi-GPU decomposition is a design note only)", file=sys.stderr)
         sys.exit(2)
+    log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)
+    if args.copy_calibration:
+        import torch
+        n = 256 * 1024 * 1024 // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": n * 8, "launches": 3}), flush=True)
+        return
+    if args.workload == "periodic_compression":
+        out = periodic_compression_leg(steps=args.steps, log=log, prepared_state=args.prepared_state)
+        print(json.dumps(out), flush=True)
+        return
+    if args.workload == "batched":
+        print(json.dumps(batched_leg(steps=args.steps, log=log)), flush=True)
+        return
 
     from paper_2301_00611_amd.scenes import grid_column
     spec = grid_column(n=200_000, seed=0)
-    log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)
     log(f"FP64 leg: {spec.n} spheres, {args.steps} steps")
     r64 = timed_run(spec, args.steps, args.warmup, precision=0)
     log(f"FP64 leg done in {r64['seconds']:.2f} s; kernel-timing pass")
@@ -262,7 +285,7 @@ def prepare_periodic_compression(n=2_000_000, seed=0, target_pressure=1e3, tile=
     return spec, {"pos": pos, "vel": vel, "angvel": ang}, H2, rec
 
 
-def periodic_compression_leg(steps=5000, n=2_000_000, log=None):
+def periodic_compression_leg(steps=5000, n=2_000_000, log=None, prepared_state=None):
     """C3: FP64 vs FP32-mixed on the same prepared dense periodic packing
     under isotropic compression at 0.01/s: throughput of each, kernel
     durations, and the FP32-mixed error against FP64 from the identical
@@ -271,7 +294,18 @@ def periodic_compression_leg(steps=5000, n=2_000_000, log=None):
     import numpy as np
     import torch
     log = log or (lambda m: None)
-    spec, st, H, rec = prepare_periodic_compression(n=n, log=log)
+    import numpy as np
+    if prepared_state and os.path.exists(prepared_state):
+        from paper_2301_00611_amd.scenes import periodic_lognormal_gas
+        d = np.load(prepared_state)
+        spec = periodic_lognormal_gas(n=16)
+        spec.pos, spec.radius = d["pos"], d["radius"]
+        st = {"pos": d["pos"], "vel": d["vel"], "angvel": d["angvel"]}
+        H, rec = d["H"], {"loaded_from": prepared_state}
+    else:
+        spec, st, H, rec = prepare_periodic_compression(n=n, log=log)
+        if prepared_state:
+            np.savez(prepared_state, pos=st["pos"], vel=st["vel"], angvel=st["angvel"], radius=spec.radius, H=H)
     n = len(spec.radius)
     L = spec.velgrad
     out = {"workload": f"periodic isotropic compression: {n} spheres, lognormal r (median 1 mm, sigma 0.3), "
@@ -345,8 +379,9 @@ def periodic_compression_leg(steps=5000, n=2_000_000, log=None):
     for prec, name in ((0, "fp64"), (1, "fp32_mixed")):
         g = _periodic_scene(H, L, spec, st["pos"], st["vel"], st["angvel"], prec, track_energy=True)
         rows = []
-        for _ in range(steps // 500):
-            g.step(500)
+        win = min(500, steps)
+        for _ in range(max(1, steps // win)):
+            g.step(win)
             e = g.get_energy()
             rows.append([e["kinetic"], e["kin_rot"], e["elastic"], e["damp_dissip"], e["plastic_dissip"],
                          g.stats()["coordination"]])
@@ -357,7 +392,7 @@ def periodic_compression_leg(steps=5000, n=2_000_000, log=None):
     out["fp32_vs_fp64_run"] = {
         "energy_terms_rel_to_total_max": float((np.abs(b[:, :5] - a[:, :5]) / scale).max()),
         "coordination_rel_max": float((np.abs(b[:, 5] - a[:, 5]) / np.maximum(a[:, 5], 1e-30)).max()),
-        "windows": int(a.shape[0]), "window_steps": 500}
+        "windows": int(a.shape[0]), "window_steps": min(500, steps)}
     return out
 
 
