@@ -465,30 +465,20 @@ __global__ void __launch_bounds__(kBlock) k_carry_over(PairBuildArgs a, int old_
     const int32_t owner = sa >= 0 ? a.bod.id[sa] : a.bod.id[sb];
     const int32_t partner = a.pr.pid[k];
     const int32_t cell = a.pr.cell[k];
-    double fx = 0.0, fy = 0.0, fz = 0.0, nx = 0.0, ny = 0.0, nz = 0.0;
+    HistRec h = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (a.has_old && owner < old_nbodies) {
         const int lo = a.hist_old.own_begin[owner];
         const int cnt = a.hist_old.own_count[owner];
         for (int q = lo; q < lo + cnt; ++q) {
             if (a.hist_old.pid[q] == partner && a.hist_old.cell[q] == cell) {
-                fx = a.hist_old.fsx[q];
-                fy = a.hist_old.fsy[q];
-                fz = a.hist_old.fsz[q];
-                nx = a.hist_old.nx[q];
-                ny = a.hist_old.ny[q];
-                nz = a.hist_old.nz[q];
+                h = a.hist_old.h[q];
                 break;
             }
         }
     }
-    a.pr.fsx[k] = fx;
-    a.pr.fsy[k] = fy;
-    a.pr.fsz[k] = fz;
-    a.pr.nx[k] = nx;
-    a.pr.ny[k] = ny;
-    a.pr.nz[k] = nz;
+    a.pr.h[k] = h;
     // a carried normal is a unit vector: the pair touched at its last evaluation
-    a.pr.real[k] = (nx != 0.0 || ny != 0.0 || nz != 0.0) ? 1 : 0;
+    a.pr.real[k] = (h.nx != 0.0 || h.ny != 0.0 || h.nz != 0.0) ? 1 : 0;
 }
 
 inline int nblocks(long n) { return (int)((n + kBlock - 1) / kBlock); }

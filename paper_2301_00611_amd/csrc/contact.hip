@@ -166,12 +166,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
         if (!real) {
             // the contact is erased: drop its history (once), no force
             if (P.real[k]) {
-                P.fsx[k] = 0.0;
-                P.fsy[k] = 0.0;
-                P.fsz[k] = 0.0;
-                P.nx[k] = 0.0;
-                P.ny[k] = 0.0;
-                P.nz[k] = 0.0;
+                P.h[k] = HistRec{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
                 P.real[k] = 0;
             }
         } else {
@@ -214,9 +209,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
 
             // ---- shear update (section 2.1.3): both rotation increments from
             // the previous vector, then the sliding increment
-            const V3<double> fs_old64 = v3(P.fsx[k], P.fsy[k], P.fsz[k]);
+            const HistRec hold = P.h[k];
+            const V3<double> fs_old64 = v3(hold.fsx, hold.fsy, hold.fsz);
             const V3<R> fs_old = cvt<R>(fs_old64);
-            const V3<R> nprev = v3((R)P.nx[k], (R)P.ny[k], (R)P.nz[k]);
+            const V3<R> nprev = v3((R)hold.nx, (R)hold.ny, (R)hold.nz);
             const V3<R> inc1 = cross(fs_old, cross(nprev, n));
             const V3<R> w1 = cvt<R>(w1d), w2 = cvt<R>(w2d);
             const R spin = (dtr / (R)2) * dot(n, w1 + w2);
@@ -242,12 +238,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
             const V3<R> F = fn_mag * n + cvt<R>(fs64);
             const V3<R> tau = cross(n, F);
 
-            P.fsx[k] = fs64.x;
-            P.fsy[k] = fs64.y;
-            P.fsz[k] = fs64.z;
-            P.nx[k] = (double)n.x;
-            P.ny[k] = (double)n.y;
-            P.nz[k] = (double)n.z;
+            P.h[k] = HistRec{fs64.x, fs64.y, fs64.z, 0.0, (double)n.x, (double)n.y, (double)n.z, 0.0};
             if (PREC == DEM_FP32_MIXED) {
                 float* q = P.frecf + (size_t)kForceWords * k;
                 q[0] = (float)F.x;

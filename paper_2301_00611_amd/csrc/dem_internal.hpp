@@ -79,6 +79,16 @@ struct Bodies {
     double *disp;             // non-affine displacement accumulated since the last broad-phase run
 };
 
+// A pair's history record (64 bytes, one aligned segment): the shear force
+// on #2 after the Coulomb cap and the normal of its last evaluation; a
+// zero normal marks a pair that did not touch.
+struct HistRec {
+    double fsx, fsy, fsz;
+    double pad0_;
+    double nx, ny, nz;
+    double pad1_;
+};
+
 // Candidate pairs after a broad-phase run.
 struct Pairs {
     int32_t *a;               // slot of #1, or -1 - wall index
@@ -86,8 +96,7 @@ struct Pairs {
     int32_t *cell;            // packed image of #2 (periodic), 0 otherwise
     int32_t *pid;             // id of the non-owner partner (for history carry-over)
     uint8_t *real;            // 1 when the pair touched at the last evaluation
-    double *fsx, *fsy, *fsz;  // shear force on #2 (history)
-    double *nx, *ny, *nz;     // normal of the last step; 0 for a non-real pair
+    HistRec *h;               // history
     // force on #2 and n x F of the last step, one record of kForceWords
     // values per pair (one contiguous gather per real row entry)
     double *frec;             // FP64 mode
@@ -107,7 +116,7 @@ struct History {
     int32_t *own_count;
     int32_t *pid;             // by pair: partner id
     int32_t *cell;
-    double *fsx, *fsy, *fsz, *nx, *ny, *nz;
+    const HistRec *h;
 };
 
 // Device-side flags and counters (one struct in device memory).  The hot

@@ -116,7 +116,7 @@ struct BodySet {
 };
 
 struct PairSet {
-    DBuf a, b, cell, pid, real, fsx, fsy, fsz, nx, ny, nz, frec;
+    DBuf a, b, cell, pid, real, hist, frec;
     DBuf own_begin, own_count;  // by gid
     size_t cap = 0;
     void ensure(size_t n, bool fp32)
@@ -124,7 +124,7 @@ struct PairSet {
         n = std::max<size_t>(n, 1);
         for (DBuf* d : {&a, &b, &cell, &pid}) d->ensure(n * 4);
         real.ensure(n);
-        for (DBuf* d : {&fsx, &fsy, &fsz, &nx, &ny, &nz}) d->ensure(n * 8);
+        hist.ensure(n * sizeof(HistRec));
         frec.ensure(n * kForceWords * (fp32 ? sizeof(float) : sizeof(double)));
         cap = n;
     }
@@ -136,12 +136,7 @@ struct PairSet {
         p.cell = cell.as<int32_t>();
         p.pid = pid.as<int32_t>();
         p.real = real.as<uint8_t>();
-        p.fsx = fsx.as<double>();
-        p.fsy = fsy.as<double>();
-        p.fsz = fsz.as<double>();
-        p.nx = nx.as<double>();
-        p.ny = ny.as<double>();
-        p.nz = nz.as<double>();
+        p.h = hist.as<HistRec>();
         p.frec = frec.as<double>();
         p.frecf = frec.as<float>();
         return p;
@@ -153,17 +148,12 @@ struct PairSet {
         h.own_count = own_count.as<int32_t>();
         h.pid = pid.as<int32_t>();
         h.cell = cell.as<int32_t>();
-        h.fsx = fsx.as<double>();
-        h.fsy = fsy.as<double>();
-        h.fsz = fsz.as<double>();
-        h.nx = nx.as<double>();
-        h.ny = ny.as<double>();
-        h.nz = nz.as<double>();
+        h.h = hist.as<HistRec>();
         return h;
     }
     void release()
     {
-        for (DBuf* d : {&a, &b, &cell, &pid, &real, &fsx, &fsy, &fsz, &nx, &ny, &nz, &frec, &own_begin, &own_count})
+        for (DBuf* d : {&a, &b, &cell, &pid, &real, &hist, &frec, &own_begin, &own_count})
             d->release();
         cap = 0;
     }
@@ -1299,12 +1289,20 @@ struct World {
         gi(P.a, p.a);
         gi(P.b, p.b);
         gi(P.cell, p.cell);
-        gd(P.fsx, p.fsx);
-        gd(P.fsy, p.fsy);
-        gd(P.fsz, p.fsz);
-        gd(P.nx, p.nx);
-        gd(P.ny, p.ny);
-        gd(P.nz, p.nz);
+        {
+            std::vector<HistRec> h(n);
+            if (n) HIPC(hipMemcpyAsync(h.data(), P.hist.p, sizeof(HistRec) * n, hipMemcpyDeviceToHost, stream));
+            HIPC(hipStreamSynchronize(stream));
+            for (auto* v : {&p.fsx, &p.fsy, &p.fsz, &p.nx, &p.ny, &p.nz}) v->resize(n);
+            for (size_t k = 0; k < n; ++k) {
+                p.fsx[k] = h[k].fsx;
+                p.fsy[k] = h[k].fsy;
+                p.fsz[k] = h[k].fsz;
+                p.nx[k] = h[k].nx;
+                p.ny[k] = h[k].ny;
+                p.nz[k] = h[k].nz;
+            }
+        }
         // force on #2 of every pair
         p.fx.assign(n, 0.0);
         p.fy.assign(n, 0.0);
@@ -1660,24 +1658,18 @@ struct World {
         P.own_begin.ensure(4 * (size_t)std::max(ng, 1));
         P.own_count.ensure(4 * (size_t)std::max(ng, 1));
         std::vector<int32_t> pid(m), cell(m);
-        std::vector<double> f[6];
-        for (auto& v : f) v.resize(m);
+        std::vector<HistRec> h(m);
         for (size_t i = 0; i < m; ++i) {
             pid[i] = recs[i].partner;
             cell[i] = recs[i].cell;
-            for (int q = 0; q < 3; ++q) {
-                f[q][i] = recs[i].fs[q];
-                f[3 + q][i] = recs[i].n[q];
-            }
+            h[i] = HistRec{recs[i].fs[0], recs[i].fs[1], recs[i].fs[2], 0.0, recs[i].n[0], recs[i].n[1], recs[i].n[2], 0.0};
         }
         HIPC(hipMemcpyAsync(P.own_begin.p, ob.data(), 4 * (size_t)ng, hipMemcpyHostToDevice, stream));
         HIPC(hipMemcpyAsync(P.own_count.p, oc.data(), 4 * (size_t)ng, hipMemcpyHostToDevice, stream));
         if (m) {
             HIPC(hipMemcpyAsync(P.pid.p, pid.data(), 4 * m, hipMemcpyHostToDevice, stream));
             HIPC(hipMemcpyAsync(P.cell.p, cell.data(), 4 * m, hipMemcpyHostToDevice, stream));
-            DBuf* dst[6] = {&P.fsx, &P.fsy, &P.fsz, &P.nx, &P.ny, &P.nz};
-            for (int q = 0; q < 6; ++q)
-                HIPC(hipMemcpyAsync(dst[q]->p, f[q].data(), 8 * m, hipMemcpyHostToDevice, stream));
+            HIPC(hipMemcpyAsync(P.hist.p, h.data(), sizeof(HistRec) * m, hipMemcpyHostToDevice, stream));
         }
         HIPC(hipStreamSynchronize(stream));
         old_ngids = ng;

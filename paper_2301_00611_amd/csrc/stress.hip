@@ -63,8 +63,9 @@ __global__ void __launch_bounds__(kStressBlock) k_stress(StepArgs a, int scene, 
         if (!BATCHED || (int)B.scene[sb] == scene) {
             double F[3];
             pair_force<PREC>(a, k, F);
-            const double n[3] = {P.nx[k], P.ny[k], P.nz[k]};
-            const double fn[3] = {F[0] - P.fsx[k], F[1] - P.fsy[k], F[2] - P.fsz[k]};
+            const HistRec h = P.h[k];
+            const double n[3] = {h.nx, h.ny, h.nz};
+            const double fn[3] = {F[0] - h.fsx, F[1] - h.fsy, F[2] - h.fsz};
             const double r1 = B.xr[sa].w, r2 = B.xr[sb].w;
             const Material M1 = a.mats[B.mat[sa]], M2 = a.mats[B.mat[sb]];
             const double k1 = M1.young * (2.0 * r1), k2 = M2.young * (2.0 * r2);
