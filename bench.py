@@ -150,7 +150,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32-mixed, batched and CPU legs")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="column", choices=("column", "periodic_compression", "batched"),
+    ap.add_argument("--workload", default="column",
+                    choices=("column", "periodic_compression", "periodic_shear", "batched"),
                     help="column: the headline line (default); the others run one extra leg alone")
     ap.add_argument("--prepared-state", default=None,
                     help="periodic_compression: .npz holding the prepared packing (written if missing)")
@@ -172,8 +173,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each_way": n * 8, "launches": 3}), flush=True)
         return
-    if args.workload == "periodic_compression":
-        out = periodic_compression_leg(steps=args.steps, log=log, prepared_state=args.prepared_state)
+    if args.workload in PERIODIC_WORKLOADS:
+        out = periodic_leg(args.workload, steps=args.steps, log=log, prepared_state=args.prepared_state)
         print(json.dumps(out), flush=True)
         return
     if args.workload == "batched":
@@ -236,7 +237,7 @@ def main():
                              "ms_per_step": r32["seconds"] / args.steps * 1e3}
         out["batched"] = batched_leg(log=log)
         log("periodic compression leg (FP64 vs FP32-mixed)")
-        out["periodic_compression"] = periodic_compression_leg(log=log)
+        out["periodic_compression"] = periodic_leg("periodic_compression", log=log)
     if not args.no_cpu and not args.no_extra:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(spec)
@@ -254,19 +255,35 @@ def _periodic_scene(H, L, spec, pos, vel, angvel, precision, friction=None, trac
     return g
 
 
-def prepare_periodic_compression(n=2_000_000, seed=0, target_pressure=1e3, tile=2, log=None):
-    """C3's unmeasured preparation: the lognormal lattice cloud of n/tile^3
-    spheres compressed frictionless (friction 0, same stiffness and
-    damping) to a jammed packing at about the target static mean pressure,
-    held 2000 more steps at rest, then replicated tile^3 times into a cell
-    tile times wider (the same periodic packing, n spheres).  Returns the spec
-    of the n-sphere workload and its prepared state (positions, velocities,
-    spins, cell)."""
+PERIODIC_WORKLOADS = {
+    # name: (generator, spheres, tiling of the prepared packing, description)
+    "periodic_compression": ("periodic_lognormal_gas", 2_000_000, 2,
+                             "periodic isotropic compression: {n} spheres, lognormal r (median 1 mm, sigma 0.3), "
+                             "E=1e8, nu=0.25, phi=0.3, damping 0.3, velGrad=-0.01 I, homoDeform 2, dt=0.5*P-wave"),
+    "periodic_shear": ("periodic_bidisperse_gas", 8_000_000, 2,
+                       "periodic simple shear: {n} spheres, r = 0.5 and 2.0 mm (equal volumes), E=1e8, nu=0.3, "
+                       "phi=0.5, damping 0.1, velGrad[0][2] = 1/s, homoDeform 2, dt=0.5*P-wave"),
+}
+
+
+def _workload_spec(name, n, seed=0):
+    from paper_2301_00611_amd import scenes
+    return getattr(scenes, PERIODIC_WORKLOADS[name][0])(n=n, seed=seed)
+
+
+def prepare_periodic(name, n, seed=0, target_pressure=1e3, log=None):
+    """Unmeasured preparation of a periodic workload: its lattice cloud of
+    n / tile^3 spheres compressed frictionless (friction 0, same stiffness
+    and damping) to a jammed packing whose relaxed mean pressure reaches the
+    target, held 2000 more steps at rest, then replicated tile^3 times into
+    a cell tile times wider (the same periodic packing, n spheres).  Returns
+    the spec of the n-sphere workload and its prepared state (positions,
+    velocities, spins, cell)."""
     import numpy as np
     from paper_2301_00611_amd.prepare import jam_isotropic, mean_pressure, tile_periodic
-    from paper_2301_00611_amd.scenes import periodic_lognormal_gas
+    tile = PERIODIC_WORKLOADS[name][2]
     n0 = n // tile ** 3
-    spec0 = periodic_lognormal_gas(n=n0, seed=seed)
+    spec0 = _workload_spec(name, n0, seed)
     vs = float((4.0 / 3.0 * math.pi * spec0.radius ** 3).sum())
     g = _periodic_scene(spec0.hsize, np.zeros((3, 3)), spec0, spec0.pos, None, None, 0, friction=0.0)
     rec = jam_isotropic(g, spec0.dt_factor * g.pwave_dt(), vs, target_pressure, log=log)
@@ -277,7 +294,7 @@ def prepare_periodic_compression(n=2_000_000, seed=0, target_pressure=1e3, tile=
     H, _ = g.get_cell()
     g.close()
     pos, rad, vel, ang, H2 = tile_periodic(st["pos"], spec0.radius, st["vel"], st["angvel"], H, (tile,) * 3)
-    spec = periodic_lognormal_gas(n=16, seed=seed)  # parameters of the workload
+    spec = _workload_spec(name, 16, seed)  # parameters of the workload
     spec.pos, spec.radius = pos, rad
     rec["prepared_spheres"] = n0
     rec["tiling"] = [tile] * 3
@@ -285,32 +302,31 @@ def prepare_periodic_compression(n=2_000_000, seed=0, target_pressure=1e3, tile=
     return spec, {"pos": pos, "vel": vel, "angvel": ang}, H2, rec
 
 
-def periodic_compression_leg(steps=5000, n=2_000_000, log=None, prepared_state=None):
-    """C3: FP64 vs FP32-mixed on the same prepared dense periodic packing
-    under isotropic compression at 0.01/s: throughput of each, kernel
-    durations, and the FP32-mixed error against FP64 from the identical
-    state (pair set, per-contact and per-body force) and over the run
-    (energy terms, coordination)."""
+def periodic_leg(name="periodic_compression", steps=5000, n=None, log=None, prepared_state=None):
+    """A dense periodic workload (C3: isotropic compression at 0.01/s; C5:
+    bidisperse simple shear at 1/s), FP64 vs FP32-mixed on the same prepared
+    packing: throughput of each, kernel durations, and the FP32-mixed error
+    against FP64 from the identical state (pair set, per-contact and
+    per-body force) and over the run (energy terms, coordination)."""
     import numpy as np
     import torch
     log = log or (lambda m: None)
-    import numpy as np
+    n = n or PERIODIC_WORKLOADS[name][1]
     if prepared_state and os.path.exists(prepared_state):
-        from paper_2301_00611_amd.scenes import periodic_lognormal_gas
         d = np.load(prepared_state)
-        spec = periodic_lognormal_gas(n=16)
+        spec = _workload_spec(name, 16)
         spec.pos, spec.radius = d["pos"], d["radius"]
         st = {"pos": d["pos"], "vel": d["vel"], "angvel": d["angvel"]}
         H, rec = d["H"], {"loaded_from": prepared_state}
     else:
-        spec, st, H, rec = prepare_periodic_compression(n=n, log=log)
+        spec, st, H, rec = prepare_periodic(name, n, log=log)
         if prepared_state:
             np.savez(prepared_state, pos=st["pos"], vel=st["vel"], angvel=st["angvel"], radius=spec.radius, H=H)
     n = len(spec.radius)
     L = spec.velgrad
-    out = {"workload": f"periodic isotropic compression: {n} spheres, lognormal r (median 1 mm, sigma 0.3), "
-                       f"E=1e8, nu=0.25, phi=0.3, damping 0.3, velGrad=-0.01 I, homoDeform 2, dt=0.5*P-wave; "
-                       f"from a packing prepared at {n // 8} spheres and tiled 2x2x2",
+    tile = PERIODIC_WORKLOADS[name][2]
+    out = {"workload": PERIODIC_WORKLOADS[name][3].format(n=n)
+           + f"; from a packing prepared at {n // tile ** 3} spheres and tiled {tile}x{tile}x{tile}",
            "preparation": {k: (v.tolist() if hasattr(v, "tolist") else v) for k, v in rec.items() if k != "cell0"},
            "steps": steps}
     # identical-state one-step comparison
@@ -374,7 +390,7 @@ def periodic_compression_leg(steps=5000, n=2_000_000, log=None, prepared_state=N
             r["integrate_roofline"] = {"bytes": ib, "achieved_GBs": ib / (kern["integrate"] * 1e-3) / 1e9,
                                        "frac": ib / (kern["integrate"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
         out[name] = r
-        log(f"periodic compression {name}: {r}")
+        log(f"{out['workload'][:30]} {name}: {r}")
     stats = {}
     for prec, name in ((0, "fp64"), (1, "fp32_mixed")):
         g = _periodic_scene(H, L, spec, st["pos"], st["vel"], st["angvel"], prec, track_energy=True)

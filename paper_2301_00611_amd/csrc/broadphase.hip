@@ -568,12 +568,6 @@ void launch_pair_build(const PairBuildArgs& a, hipStream_t st)
     hipLaunchKernelGGL(k_pair_build, dim3(nblocks(a.nslots)), dim3(kBlock), 0, st, a);
 }
 
-void launch_fill_u32(uint32_t* p, uint32_t v, int n, hipStream_t st)
-{
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_fill_u32, dim3(nblocks(n)), dim3(kBlock), 0, st, p, v, n);
-}
-
 void launch_carry_over(const PairBuildArgs& a, hipStream_t st, int old_nbodies)
 {
     if (a.npairs <= 0) return;

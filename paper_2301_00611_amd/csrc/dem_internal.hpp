@@ -229,7 +229,6 @@ struct PairBuildArgs {
     int32_t has_old;
 };
 void launch_pair_build(const PairBuildArgs& a, hipStream_t st);
-void launch_fill_u32(uint32_t* p, uint32_t v, int n, hipStream_t st);
 void launch_carry_over(const PairBuildArgs& a, hipStream_t st, int old_nbodies);
 
 // contact.hip

@@ -332,3 +332,30 @@ def test_love_weber_stress_closed_form_and_oracle():
     scale = abs(expect[0, 0])
     assert np.abs(sg - expect).max() <= 1e-9 * scale
     assert np.abs(sg - so).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-5)])
+def test_bidisperse_periodic_shear_one_step(precision, tol):
+    """The bidisperse shear workload's shape (radii 0.5 and 2.0 mm, equal
+    volumes, periodic simple shear) at a size the oracle steps in seconds:
+    the lattice squeezed by 0.2 % so neighbours overlap, random velocities,
+    one step from identical states; pair sets bit-exact, forces within the
+    precision's bar, then 10 more steps still identical pair sets."""
+    from paper_2301_00611_amd.scenes import periodic_bidisperse_gas, random_velocities
+    sc = periodic_bidisperse_gas(n=2000, seed=7)
+    squeeze = 0.998
+    sc.pos = sc.pos * squeeze
+    H = sc.hsize * squeeze
+    v, w = random_velocities(sc.n, 0.01, 8)
+    g, o, dt = twin(sc, precision=precision, periodic=True, hsize=H, velgrad=sc.velgrad, vel=v, angvel=w * 0.1)
+    g.step(1)
+    o.step(1)
+    cg, co = g.get_contacts(), o.get_contacts()
+    assert len(co) > 500
+    assert keyset(cg) == keyset(co)
+    assert contact_errors(cg, co)["f"].max() <= tol
+    ef, _ = body_force_errors(g.get_state(), o.get_state(), co)
+    assert ef.max() <= tol
+    g.step(10)
+    o.step(10)
+    assert keyset(g.get_contacts()) == keyset(o.get_contacts())
