@@ -72,7 +72,18 @@ def build_scene(spec, precision=0, timing=False):
     return s
 
 
-def timed_run(spec, steps, warmup, precision=0, timing=False):
+def autotune_for(spec, precision=0, warmup=100, probe_steps=300, cache=None):
+    """Autotuner on a throwaway scene of the workload (its probe steps are
+    not timed); returns the chosen setting.  With a cache file that holds
+    this workload, the stored setting is used without probing."""
+    w = build_scene(spec, precision)
+    w.step(warmup)
+    t = w.autotune(probe_steps=probe_steps, cache_path=cache)
+    w.close()
+    return {k: v for k, v in t.items() if k != "ms_per_step"}
+
+
+def timed_run(spec, steps, warmup, precision=0, timing=False, tuning=None):
     """Warm up on a throwaway scene, then time exactly `steps` steps of a
     fresh scene from its initial state.  With timing=True every contact and
     integrate launch is bracketed by HIP events (graph event nodes)."""
@@ -82,6 +93,8 @@ def timed_run(spec, steps, warmup, precision=0, timing=False):
         w.step(warmup)
         w.close()
     s = build_scene(spec, precision, timing=timing)
+    if tuning:
+        s.set_tuning(**tuning)
     s.step(0)
     st0 = s.stats()
     torch.cuda.synchronize()
@@ -155,6 +168,8 @@ def main():
                     help="column: the headline line (default); the others run one extra leg alone")
     ap.add_argument("--prepared-state", default=None,
                     help="periodic_compression: .npz holding the prepared packing (written if missing)")
+    ap.add_argument("--tuning-cache", default=None,
+                    help="autotuner cache file: reuse a stored setting for this workload, or store the one found")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB device copy three times (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -183,12 +198,14 @@ def main():
 
     from paper_2301_00611_amd.scenes import grid_column
     spec = grid_column(n=200_000, seed=0)
-    log(f"FP64 leg: {spec.n} spheres, {args.steps} steps")
-    r64 = timed_run(spec, args.steps, args.warmup, precision=0)
+    log("autotuning the step kernels' launch shape, graph length and Verlet distance")
+    tune = autotune_for(spec, 0, warmup=args.warmup, cache=args.tuning_cache)
+    log(f"FP64 leg: {spec.n} spheres, {args.steps} steps, setting {tune}")
+    r64 = timed_run(spec, args.steps, args.warmup, precision=0, tuning=tune)
     log(f"FP64 leg done in {r64['seconds']:.2f} s; kernel-timing pass")
     # same workload again with HIP events around every contact / integrate
     # launch: per-kernel durations for the roofline
-    rt = timed_run(spec, args.steps, 0, precision=0, timing=True)
+    rt = timed_run(spec, args.steps, 0, precision=0, timing=True, tuning=tune)
     secs = r64["seconds"]
     value = r64["contact_steps"] / secs
     kern = rt["kernels"]
@@ -223,6 +240,7 @@ def main():
                    "n_spheres": n, "n_walls": len(spec.walls), "parallelism": "1 GPU"},
         "body_steps_per_s": n * args.steps / secs,
         "rebuilds": r64["rebuilds"],
+        "tuning": tune,
         "kernels_ms": {k: v["avg_ms"] for k, v in kern.items()},
         "timing_pass_ms_per_step": rt["seconds"] / args.steps * 1e3,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -231,7 +249,8 @@ def main():
     }
     if not args.no_extra:
         log("FP32-mixed leg")
-        r32 = timed_run(spec, args.steps, args.warmup, precision=1)
+        r32 = timed_run(spec, args.steps, args.warmup, precision=1, tuning=autotune_for(spec, 1, warmup=args.warmup,
+                                                                                    cache=args.tuning_cache))
         log("batched leg")
         out["fp32_mixed"] = {"value": r32["contact_steps"] / r32["seconds"], "unit": "contact-steps/s",
                              "ms_per_step": r32["seconds"] / args.steps * 1e3}

@@ -292,9 +292,13 @@ __device__ inline void for_each_candidate(const SweepArgs& a, int i, F&& f)
     const double reach = 2.0 * P.verlet;
     int c[3], per_i[3];
     cell_of<PERIODIC>(P, xi, yi, zi, c, per_i);
-    for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
+    // cells within reach of this body's largest possible candidate distance
+    const double far = (ri + P.rmax) + reach;
+    int kk[3];
+    for (int q = 0; q < 3; ++q) kk[q] = max(1, (int)ceil(far / P.cellw[q]));
+    for (int dz = -kk[2]; dz <= kk[2]; ++dz)
+        for (int dy = -kk[1]; dy <= kk[1]; ++dy)
+            for (int dx = -kk[0]; dx <= kk[0]; ++dx) {
                 int n[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
                 int w[3] = {0, 0, 0};
                 bool skip = false;

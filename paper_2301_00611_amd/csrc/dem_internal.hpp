@@ -46,6 +46,8 @@ struct SceneParams {
     double Lprev[9];          // velGrad of the previous step
     double trsf[9];           // accumulated cell transformation
     double verlet_cell_rate;  // 1/2 |L|_F (2 r_max + 4 Delta L): Verlet budget used per unit time by the mean field
+    double rmax;              // largest radius of the scene at the run
+    double cellw[3];          // metric width of a grid cell along each axis (>= the cell size h)
 };
 
 struct Wall {

@@ -643,7 +643,12 @@ struct World {
         int cells = 0, maxdim = 1;
         for (int s = 0; s < nsc; ++s) {
             SceneParams& P = sp[s];
-            const double h0 = std::max(2.0 * rmax[s] + 2.0 * P.verlet, 1e-300) * (1.0 + 1e-9);
+            const double hmax = std::max(2.0 * rmax[s] + 2.0 * P.verlet, 1e-300) * (1.0 + 1e-9);
+            // cells of size h0 = 2 r_max + 2 Delta L: every body searches
+            // +-1 cell per axis (the sweep computes its reach per body from the
+            // cell widths, so a finer grid only needs a smaller h0 here)
+            const double h0 = hmax;
+            const int kmax = std::max(1, (int)std::ceil((2.0 * rmax[s] + 2.0 * P.verlet) / h0));
             if (periodic) {
                 double Hinv[9];
                 if (!invert(P.H, Hinv)) fail(DEM_EPERIODIC, "singular periodic cell");
@@ -652,13 +657,17 @@ struct World {
                     const double rn = std::sqrt(Hinv[3 * k] * Hinv[3 * k] + Hinv[3 * k + 1] * Hinv[3 * k + 1] +
                                                 Hinv[3 * k + 2] * Hinv[3 * k + 2]);
                     const double width = 1.0 / rn;  // distance between opposite faces
+                    // cells of at least h0; a finer grid must keep 2 k + 1 distinct
+                    // cells across the period, else the plain grid is used
                     int n = (int)std::floor(width / h0);
+                    if (n < 2 * kmax + 1) n = (int)std::floor(width / hmax);
                     if (n < 3)
                         fail(DEM_EPERIODIC, "periodic cell narrower than 3 x (2 r_max + 2 Delta L) along an axis");
                     n = std::min(n, 1 << 20);
                     P.dims[k] = n;
                     P.inv_h[k] = (double)n;
                     P.origin[k] = 0.0;
+                    P.cellw[k] = width / (double)n;
                 }
             } else {
                 const double lo[3] = {bnd[6 * s + 0], bnd[6 * s + 1], bnd[6 * s + 2]};
@@ -682,6 +691,7 @@ struct World {
                 for (int k = 0; k < 3; ++k) {
                     P.origin[k] = lo[k] - 1e-12 * std::fabs(lo[k]) - 1e-300;
                     P.inv_h[k] = 1.0 / h;
+                    P.cellw[k] = h;
                 }
             }
             P.cell_offset = cells;
@@ -692,6 +702,7 @@ struct World {
             for (int k = 0; k < 9; ++k) lf += P.L[k] * P.L[k];
             P.verlet_cell_rate = 0.5 * std::sqrt(lf) * (2.0 * rmax[s] + 4.0 * P.verlet);
             scenes[s].rmax = rmax[s];
+            P.rmax = rmax[s];
         }
         ncells = std::max(cells, 1);
         morton_bits = 1;

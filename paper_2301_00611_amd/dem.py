@@ -157,6 +157,13 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_2301_00611_amd.build`")
+    # PyTorch ships its own HIP runtime library; loading it first makes this
+    # library bind to the same one, so both share one HIP runtime in the
+    # process (a second runtime initialised later finds no device)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

@@ -228,3 +228,40 @@ def test_autotune_probes_then_reuses_its_cache(tmp_path):
     assert len(open(cache).read().splitlines()) == 1
     b.close()
     b2.close()
+
+
+def test_empty_and_wall_only_scenes():
+    s, m = _scene()
+    s.set_dt(1e-6)
+    s.step(5)  # no bodies at all
+    assert s.stats()["iter"] == 5 and s.stats()["n_spheres"] == 0
+    s.add_wall(2, 0.0, 1, m)
+    s.step(5)  # walls only: nothing moves, nothing touches
+    st = s.stats()
+    assert st["iter"] == 10 and st["n_walls"] == 1 and st["n_contacts_sw"] == 0
+    assert len(s.get_contacts()) == 0
+    s.close()
+
+
+def test_exact_touch_is_not_a_contact():
+    """The tie rule (reading R7 / R13): spheres exactly touching, |d| =
+    r1 + r2, and a sphere exactly touching a wall, |x - p| = r, are not in
+    contact; a hair closer they are.  Same decision as the oracle."""
+    from oracle import OracleScene
+    pos = np.array([[0.0, 0.0, 0.5], [1.0, 0.0, 0.5], [3.0, 0.0, 0.5], [np.nextafter(4.0, 0.0), 0.0, 0.5]])
+    rad = np.full(4, 0.5)
+    g = dem.Scene(gravity=(0.0, 0.0, 0.0), damping=0.0)
+    o = OracleScene(dt=1e-6, gravity=(0.0, 0.0, 0.0), damping=0.0)
+    mg = g.add_material(2600.0, 1e7, 0.3, 0.5)
+    mo = o.add_material(2600.0, 1e7, 0.3, 0.5)
+    g.add_wall(2, 0.0, 1, mg)   # id 0: spheres at z = 0.5 exactly touch it
+    o.add_wall(2, 0.0, 1, mo)
+    g.add_spheres(pos, rad, default_mat=mg)
+    o.add_spheres(pos, rad, default_mat=mo)
+    g.set_dt(1e-6)
+    g.step(1)
+    o.step(1)
+    kg = {(int(a), int(b)) for a, b in zip(g.get_contacts()["id1"], g.get_contacts()["id2"])}
+    ko = {(int(a), int(b)) for a, b in zip(o.get_contacts()["id1"], o.get_contacts()["id2"])}
+    assert kg == ko == {(3, 4)}
+    g.close()
