@@ -233,6 +233,69 @@ dem_status dem_get_energy(dem_scene* s, dem_energy* out);
  * doubles, row-major. */
 dem_status dem_get_stress(dem_scene* s, double volume, double* sigma9);
 dem_status dem_get_stats(dem_scene* s, dem_stats* out);
+
+/* utils.unbalancedForce (section 5 utility reference): the mean (use_max =
+ * 0) or largest (use_max = 1) magnitude of the resultant contact force over
+ * the dynamic spheres (not all six DOFs blocked; gravity is not part of
+ * it), divided by the mean |F_n + F_s| over the last step's real contacts
+ * (walls included).  *out is NaN when either set is empty.  Computed on the
+ * device with fixed-order sums. */
+dem_status dem_get_unbalanced_force(dem_scene* s, int32_t use_max, double* out);
+/* GlobalStiffnessTimeStepper (eqs. 2.12-2.14): safety x the smallest
+ * sqrt(2) sqrt(m / K_ii) over the dynamic spheres' unblocked DOFs, with the
+ * translational stiffness K_ii = sum over the body's contacts of
+ * (k_n - k_s) n_i^2 + k_s and the rotational one sum k_s r^2 (1 - n_i^2)
+ * against the inertia, from the last step's contacts; safety x the P-wave
+ * timestep when there is no contact.  safety in (0, 1]. */
+dem_status dem_stiffness_dt(dem_scene* s, double safety, double* out);
+/* Let the stiffness timestepper set dt before every step whose iteration
+ * count is a multiple of `interval` (timeStepUpdateInterval); interval 0
+ * turns it off.  Not available on batch views. */
+dem_status dem_set_stiffness_timestepper(dem_scene* s, double safety, int64_t interval);
+
+/* Stress/strain-controlled periodic cell (PeriTriaxController driven by the
+ * packing stiffness).  After every step that makes the iteration count a
+ * multiple of glob_update, the cell is steered from the last step's
+ * contacts: with the Love-Weber stress sigma, the normal springs' modulus
+ * M_i = (1/V) sum over sphere-sphere contacts of k_n (d_i n_i)^2 (d the
+ * centre distance vector) and T = glob_update dt, a stress axis (bit i of
+ * stress_mask set) gets the strain rate (1 - grow_damping)(goal_i -
+ * sigma_ii) / (M_i T) (the full rate towards the goal's sign while
+ * M_i = 0), a strain axis (strain = log of the cell transformation's
+ * diagonal, relative to the initial cell) the rate (goal_i - strain_i) / T;
+ * rates are capped at max_strain_rate and the velocity gradient becomes
+ * diag(rates).  The goal is reached when every stress axis is within
+ * max(abs_stress_tol, rel_stress_tol |goal_i|), every strain axis within
+ * 1e-6 and the unbalanced force is at most max_unbalanced; the cell then
+ * stops (zero velocity gradient) and, with stop_when_done, dem_step returns
+ * early (dem_get_stats gives the steps done).  Periodic scenes only. */
+typedef struct {
+    double goal[3];            /* stress [Pa] or strain [-] per axis */
+    int32_t stress_mask;       /* bit i: axis i is stress-controlled */
+    int32_t glob_update;       /* steps between updates, >= 1 (default 5) */
+    double max_strain_rate[3]; /* [1/s], > 0 (default 1) */
+    double grow_damping;       /* in [0, 1) (default 0.25) */
+    double max_unbalanced;     /* default 1e-4 */
+    double abs_stress_tol;     /* [Pa], default 1e3 */
+    double rel_stress_tol;     /* default 3e-5 */
+    int32_t stop_when_done;
+    int32_t pad;
+} dem_peri_triax;
+typedef struct {
+    double stress[3];          /* diagonal of the stress at the last update [Pa] */
+    double strain[3];          /* log of the transformation's diagonal */
+    double strain_rate[3];     /* the velocity gradient's diagonal now in use [1/s] */
+    double stiff[3];           /* M_i at the last update [Pa] */
+    double unbalanced;         /* at the last update */
+    int64_t updates;
+    int32_t done;              /* the goal was reached at the last update */
+    int32_t active;
+} dem_peri_triax_state;
+void dem_peri_triax_default(dem_peri_triax* c);
+/* c = NULL switches the controller off (the velocity gradient stays). */
+dem_status dem_set_peri_triax(dem_scene* s, const dem_peri_triax* c);
+dem_status dem_get_peri_triax(dem_scene* s, dem_peri_triax_state* out);
+
 /* Average device duration [ms] of each kernel family over the last
  * dem_step call (names: "contact", "integrate", "rebuild"), measured with
  * HIP events when timing is on. */

@@ -987,6 +987,25 @@ int orc_get_cell(const orc_scene* s, double* hsize9, double* trsf9)
     return ORC_OK;
 }
 
+/* O.dt = value: the next steps use it. */
+int orc_set_dt(orc_scene* s, double dt)
+{
+    if (!s) return fail(ORC_EINVAL, "null scene");
+    if (!(dt > 0.0) || !isfinite(dt)) return fail(ORC_EINVAL, "orc_set_dt: need a finite dt > 0");
+    s->p.dt = dt;
+    return ORC_OK;
+}
+
+/* Cell.velGrad = L between steps (a boundary controller's action): the next
+ * step sees the new L and, as Cell.prevVelGrad, the one of the last step. */
+int orc_set_velgrad(orc_scene* s, const double* velgrad9)
+{
+    if (!s || !velgrad9) return fail(ORC_EINVAL, "null argument");
+    if (!s->p.periodic) return fail(ORC_EINVAL, "orc_set_velgrad: the scene is not periodic");
+    memcpy(s->L, velgrad9, sizeof s->L);
+    return ORC_OK;
+}
+
 int orc_detect_pairs(const orc_scene* s, long capacity, long* id1, long* id2, int* cell3, long* out_count)
 {
     if (!s || !out_count) return fail(ORC_EINVAL, "null argument");

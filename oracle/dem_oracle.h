@@ -112,6 +112,9 @@ int orc_get_cell(const orc_scene* s, double* hsize9, double* trsf9);
  * cell's volume). */
 int orc_get_stress(const orc_scene* s, double volume, double* sigma9);
 
+/* O.dt and Cell.velGrad, changed between steps. */
+int orc_set_dt(orc_scene* s, double dt);
+int orc_set_velgrad(orc_scene* s, const double* velgrad9);
 /* Real pairs at the CURRENT positions (no step), by brute force. */
 int orc_detect_pairs(const orc_scene* s, long capacity, long* id1, long* id2,
                      int* cell3, long* out_count);

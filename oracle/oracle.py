@@ -95,6 +95,8 @@ def load_library(path: str | None = None):
         "orc_get_stress": [C.c_void_p, C.c_double, _DP],
         "orc_detect_pairs": [C.c_void_p, C.c_long, _LP, _LP, _IP, _LP],
         "orc_spot_step": [C.c_void_p, C.c_long, _LP, _DP, _DP, _DP, _DP, _DP, _DP, _LP],
+        "orc_set_dt": [C.c_void_p, C.c_double],
+        "orc_set_velgrad": [C.c_void_p, _DP],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -144,6 +146,13 @@ class OracleScene:
         self._h = self.lib.orc_create(C.byref(p))
         if not self._h:
             raise OracleError(self.lib.orc_last_error().decode())
+        # what the callers handed over, kept for the quantities computed in
+        # Python from the C oracle's outputs (oracle/controls.py)
+        self.dt = float(dt)
+        self.periodic = bool(periodic)
+        self.radius = []     # by id; 0 for a wall
+        self.blocked = []    # by id; a wall counts as fully blocked (63)
+        self.is_wall = []
 
     def close(self):
         if getattr(self, "_h", None):
@@ -179,12 +188,18 @@ class OracleScene:
         self._check(self.lib.orc_add_spheres(self._h, n, _ptr(pos), _ptr(radius), _ptr(vel), _ptr(angvel),
                                              _ptr(mat_a, _IP), int(default_mat), _ptr(blk, _UP), C.byref(first)),
                     "add_spheres")
+        self.radius.extend(radius.tolist())
+        self.blocked.extend([0] * n if blk is None else [int(b) & 63 for b in blk])
+        self.is_wall.extend([False] * n)
         return first.value
 
     def add_wall(self, axis, position, sense=0, mat=0):
         out = C.c_long()
         self._check(self.lib.orc_add_wall(self._h, int(axis), float(position), int(sense), int(mat), C.byref(out)),
                     "add_wall")
+        self.radius.append(0.0)
+        self.blocked.append(63)
+        self.is_wall.append(True)
         return out.value
 
     # -- stepping ---------------------------------------------------------
@@ -195,6 +210,14 @@ class OracleScene:
 
     def step(self, n=1):
         self._check(self.lib.orc_step(self._h, int(n)), "step")
+
+    def set_dt(self, dt):
+        self._check(self.lib.orc_set_dt(self._h, float(dt)), "set_dt")
+        self.dt = float(dt)
+
+    def set_velgrad(self, L):
+        L = _f64(L, (3, 3))
+        self._check(self.lib.orc_set_velgrad(self._h, _ptr(L)), "set_velgrad")
 
     # -- reading ----------------------------------------------------------
     @property

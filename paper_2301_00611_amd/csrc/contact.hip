@@ -49,7 +49,7 @@ struct SpherePairTest {
     bool real;
 };
 template <bool PERIODIC>
-__device__ __attribute__((noinline)) SpherePairTest sphere_pair_test(double x1, double y1, double z1, double x2,
+__device__ inline SpherePairTest sphere_pair_test(double x1, double y1, double z1, double x2,
                                                                       double y2, double z2, double r1, double r2,
                                                                       const double* H, int cx, int cy, int cz)
 {
@@ -112,32 +112,36 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
     ContactPartial part = {0.0, 0.0, 0ull, 0ull, 0.0};
     bool unstable = false;
     if (k < a.npairs) {
-        const Bodies& B = a.bod;
-        const Pairs& P = a.pr;
-        const int32_t sa = P.a[k];
-        const int32_t sb = P.b[k];
-        const int s = BATCHED ? (int)B.scene[sb] : 0;
-        const SceneParams& S = (BATCHED || PERIODIC) ? a.scenes[s] : a.scene0;
+        const gptr<const double4> xr = glb<const double4>(a.bod.xr);
+        const gptr<const double4> vm = glb<const double4>(a.bod.vm);
+        const gptr<const double4> wv = glb<const double4>(a.bod.w);
+        const gptr<const uint16_t> mat = glb<const uint16_t>(a.bod.mat);
+        const gptr<uint8_t> preal = glb(a.pr.real);
+        const gptr<HistRec> hist = glb(a.pr.h);
+        const int32_t sa = glb<const int32_t>(a.pr.a)[k];
+        const int32_t sb = glb<const int32_t>(a.pr.b)[k];
+        const int32_t pcell = PERIODIC ? glb<const int32_t>(a.pr.cell)[k] : 0;
+        const int s = BATCHED ? (int)glb<const uint16_t>(a.bod.scene)[sb] : 0;
+        // an unbatched scene (periodic included) reads the descriptor's own
+        // copy of its parameters: uniform, read-only here, so scalar loads
+        const SceneParams& S = BATCHED ? a.scenes[s] : a.scene0;
         const double dt = S.dt;
 
-        const double4 p2 = B.xr[sb];
-        const double x2 = p2.x, y2 = p2.y, z2 = p2.z, r2 = p2.w;
-        const int m2 = B.mat[sb];
+        // #1's loads are issued without a branch, together with #2's: a
+        // wall pair reads #2 in place of #1, a sphere pair reads wall 0 (the
+        // wall table always holds at least one entry); the unused values are
+        // then set aside
         const bool wall = sa < 0;
-        double x1 = 0.0, y1 = 0.0, z1 = 0.0, r1 = 0.0;
-        int m1;
-        Wall W;
-        if (!wall) {
-            const double4 p1 = B.xr[sa];
-            x1 = p1.x;
-            y1 = p1.y;
-            z1 = p1.z;
-            r1 = p1.w;
-            m1 = B.mat[sa];
-        } else {
-            W = a.walls[-1 - sa];
-            m1 = W.mat;
-        }
+        const int32_t s1 = wall ? sb : sa;
+        const double4 p2 = xr[sb];
+        const double4 p1 = xr[s1];
+        const int m2 = mat[sb];
+        const int m1s = mat[s1];
+        const Wall W = glb<const Wall>(a.walls)[wall ? -1 - sa : 0];
+        const double x2 = p2.x, y2 = p2.y, z2 = p2.z, r2 = p2.w;
+        const double x1 = wall ? 0.0 : p1.x, y1 = wall ? 0.0 : p1.y, z1 = wall ? 0.0 : p1.z;
+        const double r1 = wall ? 0.0 : p1.w;
+        const int m1 = wall ? W.mat : m1s;
 
         // ---- exact test, normal, overlap (always in double)
         bool real;
@@ -145,7 +149,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
         V3<double> n64;
         int cc[3] = {0, 0, 0};
         if (!wall) {
-            if (PERIODIC) unpack_cell(P.cell[k], cc);
+            if (PERIODIC) unpack_cell(pcell, cc);
             const SpherePairTest t =
                 sphere_pair_test<PERIODIC>(x1, y1, z1, x2, y2, z2, r1, r2, S.H, cc[0], cc[1], cc[2]);
             real = t.real;
@@ -165,21 +169,26 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
 
         if (!real) {
             // the contact is erased: drop its history (once), no force
-            if (P.real[k]) {
-                P.h[k] = HistRec{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-                P.real[k] = 0;
+            if (preal[k]) {
+                hist[k] = HistRec{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                preal[k] = 0;
             }
         } else {
+            // ---- every load of a touching pair, issued together: both
+            // bodies' velocities and spins, the history, the materials
+            const double4 va = vm[s1], wa = wv[s1];
+            const double4 vb = vm[sb], wb = wv[sb];
+            const HistRec hold = hist[k];
+            const Material M1 = glb<const Material>(a.mats)[m1];
+            const Material M2 = glb<const Material>(a.mats)[m2];
+            const double tanphi64 = glb<const double>(a.tanphi)[m1 * a.nmat + m2];
+
             // ---- ScGeom inputs
             const double R1d = wall ? r2 : r1;
             const double R2d = r2;
-            V3<double> v1d = v3(0.0, 0.0, 0.0), w1d = v3(0.0, 0.0, 0.0);
-            if (!wall) {
-                const double4 va = B.vm[sa], wa = B.w[sa];
-                v1d = v3(va.x, va.y, va.z);
-                w1d = v3(wa.x, wa.y, wa.z);
-            }
-            const double4 vb = B.vm[sb], wb = B.w[sb];
+            // a wall does not move
+            const V3<double> v1d = wall ? v3(0.0, 0.0, 0.0) : v3(va.x, va.y, va.z);
+            const V3<double> w1d = wall ? v3(0.0, 0.0, 0.0) : v3(wa.x, wa.y, wa.z);
             V3<double> v2d = v3(vb.x, vb.y, vb.z);
             const V3<double> w2d = v3(wb.x, wb.y, wb.z);
             if (PERIODIC) {
@@ -194,13 +203,11 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
             const V3<double> dv64 = v2d - v1d;
 
             // ---- Ip2_FrictMat_FrictMat_FrictPhys: series springs k_i = E_i (2 R_i)
-            const Material M1 = a.mats[m1];
-            const Material M2 = a.mats[m2];
             const R k1 = (R)M1.young * ((R)2 * (R)R1d), k2 = (R)M2.young * ((R)2 * (R)R2d);
             const R kn = k1 * k2 / (k1 + k2);
             const R q1 = (R)M1.young_poisson * ((R)2 * (R)R1d), q2 = (R)M2.young_poisson * ((R)2 * (R)R2d);
             const R ks = q1 * q2 / (q1 + q2);
-            const R tanphi = (R)a.tanphi[m1 * a.nmat + m2];
+            const R tanphi = (R)tanphi64;
 
             const V3<R> n = cvt<R>(n64);
             const R penr = (R)pen;
@@ -209,7 +216,6 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
 
             // ---- shear update (section 2.1.3): both rotation increments from
             // the previous vector, then the sliding increment
-            const HistRec hold = P.h[k];
             const V3<double> fs_old64 = v3(hold.fsx, hold.fsy, hold.fsz);
             const V3<R> fs_old = cvt<R>(fs_old64);
             const V3<R> nprev = v3((R)hold.nx, (R)hold.ny, (R)hold.nz);
@@ -238,25 +244,21 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
             const V3<R> F = fn_mag * n + cvt<R>(fs64);
             const V3<R> tau = cross(n, F);
 
-            P.h[k] = HistRec{fs64.x, fs64.y, fs64.z, 0.0, (double)n.x, (double)n.y, (double)n.z, 0.0};
+            hist[k] = HistRec{fs64.x, fs64.y, fs64.z, 0.0, (double)n.x, (double)n.y, (double)n.z, 0.0};
+            // the record as three pairs (a record starts on an 8-byte (FP32)
+            // or 16-byte (FP64) boundary of a 256-byte aligned array)
             if (PREC == DEM_FP32_MIXED) {
-                float* q = P.frecf + (size_t)kForceWords * k;
-                q[0] = (float)F.x;
-                q[1] = (float)F.y;
-                q[2] = (float)F.z;
-                q[3] = (float)tau.x;
-                q[4] = (float)tau.y;
-                q[5] = (float)tau.z;
+                const gptr<float2> q = glb(reinterpret_cast<float2*>(a.pr.frecf)) + 3 * (size_t)k;
+                q[0] = make_float2((float)F.x, (float)F.y);
+                q[1] = make_float2((float)F.z, (float)tau.x);
+                q[2] = make_float2((float)tau.y, (float)tau.z);
             } else {
-                double* q = P.frec + (size_t)kForceWords * k;
-                q[0] = (double)F.x;
-                q[1] = (double)F.y;
-                q[2] = (double)F.z;
-                q[3] = (double)tau.x;
-                q[4] = (double)tau.y;
-                q[5] = (double)tau.z;
+                const gptr<double2> q = glb(reinterpret_cast<double2*>(a.pr.frec)) + 3 * (size_t)k;
+                q[0] = make_double2((double)F.x, (double)F.y);
+                q[1] = make_double2((double)F.z, (double)tau.x);
+                q[2] = make_double2((double)tau.y, (double)tau.z);
             }
-            P.real[k] = 1;
+            preal[k] = 1;
             if (wall)
                 part.sw = 1;
             else

@@ -170,6 +170,25 @@ struct StepArgs {
     int32_t track_energy;
 };
 
+// Global-memory view of a buffer pointer.  The step kernels load their
+// pointers from a device descriptor, so the compiler cannot prove that they
+// address global memory and would emit flat loads and stores (64-bit
+// addresses, waits shared with LDS and scalar loads); the cast lets it emit
+// global ones.  Only meaningful in device code (the host pass, which checks
+// the kernels' source, sees plain pointers).
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+#else
+template <typename T>
+using gptr = T*;
+#endif
+template <typename T>
+__device__ inline gptr<T> glb(T* p)
+{
+    return (gptr<T>)p;
+}
+
 // ---------------------------------------------------------------- launchers
 // (defined in the .hip files; all asynchronous on `st`)
 
@@ -244,12 +263,21 @@ void launch_integrate(const StepArgs* args, int parity, int grid, int precision,
                       int block, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_cell_update(const StepArgs* args, int parity, hipStream_t st);
 void launch_body_forces(const StepArgs& a, int precision, double* f3, double* t3, hipStream_t st);
-// Love-Weber stress partial sums (9 doubles per block) of the last step's
-// real sphere-sphere contacts; `scene` selects a batch scene.
+// Sums over the last step's real contacts, kNetworkWords doubles per block
+// (stress.hip): Love-Weber stress (9), modulus of the normal springs per
+// axis (3), sum of |F| and count (2); `scene` selects a batch scene.
+constexpr int kNetworkWords = 14;
 int stress_blocks(int npairs);
 // Force on #2 of every pair (3 doubles per pair; 0 for a pair not touching).
 void launch_pair_forces(const StepArgs& a, int precision, double* f3, hipStream_t st);
-void launch_stress(const StepArgs& a, int precision, bool batched, int scene, double* part, hipStream_t st);
+void launch_network(const StepArgs& a, int precision, bool batched, int scene, double* part, hipStream_t st);
+// Sums over the bodies of one scene, kBodyWords doubles per block
+// (integrate.hip): sum and largest |resultant contact force| over the
+// dynamic spheres, their number, and the smallest stiffness-based critical
+// timestep (eqs. 2.12-2.14; +inf without contacts).
+constexpr int kBodyWords = 4;
+int body_blocks(int nslots);
+void launch_body_measures(const StepArgs& a, int precision, bool batched, int scene, double* part, hipStream_t st);
 
 
 }  // namespace dem

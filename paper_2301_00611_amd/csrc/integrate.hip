@@ -33,32 +33,46 @@ __device__ inline double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 
 // partner id): the force records of its real pairs, negated where the body
 // is #1.
 template <int PREC>
-__device__ inline void body_sum(const StepArgs& a, int i, double r, double* F, double* T)
+__device__ inline void body_sum(const StepArgs& a, int beg, int end, double r, double* F, double* T)
 {
     F[0] = F[1] = F[2] = 0.0;
     T[0] = T[1] = T[2] = 0.0;
-    const int beg = a.rows.start[i], end = a.rows.start[i + 1];
+    const gptr<const uint32_t> ent = glb<const uint32_t>(a.rows.ent);
+    const gptr<const uint8_t> real = glb<const uint8_t>(a.pr.real);
     // entries are taken four at a time so that their loads are in flight
-    // together; they are still added one by one in row order
+    // together (no branch between them: a position past the row's end reads
+    // the row's last entry again and is then ignored); they are still added
+    // one by one in row order
     constexpr int kB = 4;
     for (int e0 = beg; e0 < end; e0 += kB) {
         uint32_t u[kB];
         bool use[kB];
-        for (int j = 0; j < kB; ++j) u[j] = (e0 + j < end) ? a.rows.ent[e0 + j] : kPairMask;
+        for (int j = 0; j < kB; ++j) u[j] = ent[min(e0 + j, end - 1)];
         for (int j = 0; j < kB; ++j) {
             const uint32_t k = u[j] & kPairMask;
-            use[j] = k < (uint32_t)a.npairs && a.pr.real[k];
+            const bool flag = real[k < (uint32_t)a.npairs ? k : 0u] != 0;
+            use[j] = (e0 + j < end) && k < (uint32_t)a.npairs && flag;
         }
+        // a record is read as three pairs (it starts on an 8-byte (FP32) or
+        // 16-byte (FP64) boundary of a 256-byte aligned array)
         double f[kB][kForceWords];
         for (int j = 0; j < kB; ++j) {
             const uint32_t k = u[j] & kPairMask;
             if (!use[j]) continue;
             if (PREC == DEM_FP32_MIXED) {
-                const float* q = a.pr.frecf + (size_t)kForceWords * k;
-                for (int c = 0; c < kForceWords; ++c) f[j][c] = q[c];
+                const gptr<const float2> q = glb<const float2>(reinterpret_cast<const float2*>(a.pr.frecf)) + 3 * (size_t)k;
+                for (int c = 0; c < 3; ++c) {
+                    const float2 v = q[c];
+                    f[j][2 * c] = v.x;
+                    f[j][2 * c + 1] = v.y;
+                }
             } else {
-                const double* q = a.pr.frec + (size_t)kForceWords * k;
-                for (int c = 0; c < kForceWords; ++c) f[j][c] = q[c];
+                const gptr<const double2> q = glb<const double2>(reinterpret_cast<const double2*>(a.pr.frec)) + 3 * (size_t)k;
+                for (int c = 0; c < 3; ++c) {
+                    const double2 v = q[c];
+                    f[j][2 * c] = v.x;
+                    f[j][2 * c + 1] = v.y;
+                }
             }
         }
         for (int j = 0; j < kB; ++j) {
@@ -105,17 +119,23 @@ __global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restr
     bool bad = false;
     bool over = false;
     if (i < a.nslots) {
-        const Bodies& B = a.bod;
-        const int s = BATCHED ? (int)B.scene[i] : 0;
-        const SceneParams& S = (BATCHED || PERIODIC) ? a.scenes[s] : a.scene0;
+        const gptr<double4> bxr = glb(a.bod.xr), bvm = glb(a.bod.vm), bw = glb(a.bod.w), bq = glb(a.bod.q);
+        const gptr<double> bdisp = glb(a.bod.disp);
+        // the row bounds first: the row's loads wait for them, not for the
+        // body's own state, which is requested right after
+        const int beg = glb<const int32_t>(a.rows.start)[i], end = glb<const int32_t>(a.rows.start)[i + 1];
+        const int s = BATCHED ? (int)glb<const uint16_t>(a.bod.scene)[i] : 0;
+        // an unbatched scene (periodic included) reads the descriptor's own
+        // copy of its parameters: uniform, read-only here, so scalar loads
+        const SceneParams& S = BATCHED ? a.scenes[s] : a.scene0;
         const double dt = S.dt;
         const double lam = S.damping;
-        const double4 xr0 = B.xr[i], vm0 = B.vm[i], w0 = B.w[i];
+        const double4 xr0 = bxr[i], vm0 = bvm[i], w0 = bw[i];
         const double r = xr0.w, m = vm0.w;
         const double I = 2.0 * m * r * r / 5.0;
-        const unsigned blocked = B.blocked[i];
+        const unsigned blocked = glb<const uint8_t>(a.bod.blocked)[i];
         double F[3], T[3];
-        body_sum<PREC>(a, i, r, F, T);
+        body_sum<PREC>(a, beg, end, r, F, T);
 
         const double x0[3] = {xr0.x, xr0.y, xr0.z};
         const double v0[3] = {vm0.x, vm0.y, vm0.z};
@@ -164,7 +184,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restr
         const double wn = sqrt((w[0] * w[0] + w[1] * w[1]) + w[2] * w[2]);
         if (wn > 0.0) {
             // the orientation only changes (and is only read) for a spinning body
-            const double4 q0 = B.q[i];
+            const double4 q0 = bq[i];
             double q[4] = {q0.x, q0.y, q0.z, q0.w};
             const double half = 0.5 * wn * dt;
             const double sh = sin(half) / wn;
@@ -178,12 +198,12 @@ __global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restr
             q[1] = n1 / qn;
             q[2] = n2 / qn;
             q[3] = n3 / qn;
-            B.q[i] = make_double4(q[0], q[1], q[2], q[3]);
+            bq[i] = make_double4(q[0], q[1], q[2], q[3]);
         }
-        B.xr[i] = make_double4(x1[0], x1[1], x1[2], r);
-        B.vm[i] = make_double4(v[0], v[1], v[2], m);
+        bxr[i] = make_double4(x1[0], x1[1], x1[2], r);
+        bvm[i] = make_double4(v[0], v[1], v[2], m);
         // an unchanged spin (no torque, or blocked) is not stored again
-        if (w[0] != w0.x || w[1] != w0.y || w[2] != w0.z) B.w[i] = make_double4(w[0], w[1], w[2], 0.0);
+        if (w[0] != w0.x || w[1] != w0.y || w[2] != w0.z) bw[i] = make_double4(w[0], w[1], w[2], 0.0);
 
         // non-affine displacement of this step, added to the body's Verlet
         // account (eq. 2.3); the cell's mean field uses its own share
@@ -193,8 +213,8 @@ __global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restr
             matvec(S.L, x0[0], x0[1], x0[2], Lx);
             for (int k = 0; k < 3; ++k) u[k] -= Lx[k];
         }
-        const double d = B.disp[i] + sqrt((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]) * dt + a.ctr->verlet_cell_step;
-        B.disp[i] = d;
+        const double d = bdisp[i] + sqrt((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]) * dt + a.ctr->verlet_cell_step;
+        bdisp[i] = d;
         over = d > a.ctr->verlet_limit;
         bad = !(isfinite(x1[0]) && isfinite(x1[1]) && isfinite(x1[2]) && isfinite(v[0]) && isfinite(v[1]) &&
                 isfinite(v[2]));
@@ -236,7 +256,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restr
 // Periodic cell (section 2.1.6), once per step after the bodies: H+ =
 // (I + L dt) H and the same for trsf; H - H_prev is kept for the image
 // velocity of the next step's contacts; L becomes L_prev.
-__global__ void k_cell_update(const StepArgs* __restrict__ args, int parity)
+__global__ void k_cell_update(StepArgs* args, int parity)
 {
     const StepArgs& a = *args;
     if (a.ctr->stall[parity ^ 1] || threadIdx.x != 0) return;
@@ -268,6 +288,8 @@ __global__ void k_cell_update(const StepArgs* __restrict__ args, int parity)
     S->Hinv[6] = C2 / det;
     S->Hinv[7] = -(a0 * a7 - a1 * a6) / det;
     S->Hinv[8] = (a0 * a4 - a1 * a3) / det;
+    // the step kernels of an unbatched scene read the descriptor's copy
+    args->scene0 = *S;
 }
 
 // Resultant force/torque per slot (for reporting), same sum as the step.
@@ -277,10 +299,90 @@ __global__ void k_body_forces(StepArgs a, double* __restrict__ f3, double* __res
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.nslots) return;
     double F[3], T[3];
-    body_sum<PREC>(a, i, a.bod.xr[i].w, F, T);
+    body_sum<PREC>(a, a.rows.start[i], a.rows.start[i + 1], a.bod.xr[i].w, F, T);
     for (int k = 0; k < 3; ++k) {
         f3[3 * i + k] = F[k];
         t3[3 * i + k] = T[k];
+    }
+}
+
+// Per-body measures of one scene for the unbalanced force and the stiffness
+// timestepper (reporting, not in the step), kBodyWords doubles per block:
+// sum and largest |resultant contact force| over the dynamic spheres (not
+// all six DOFs blocked), their number, and the smallest critical timestep
+// sqrt(2) sqrt(m / K_ii) over their unblocked DOFs (eq. 2.12), with the
+// translational stiffness K_ii = sum of (k_n - k_s) n_i^2 + k_s over the
+// body's contacts (eq. 2.14) and the rotational one R_ii = sum of
+// k_s r^2 (1 - n_i^2) against the inertia (+inf without contacts).
+constexpr int kMeasureBlock = 256;
+
+template <int PREC, bool BATCHED>
+__global__ void __launch_bounds__(kMeasureBlock) k_body_measures(StepArgs a, int scene, double* __restrict__ part)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double fsum = 0.0, fmaxv = 0.0, cnt = 0.0, dtmin = INFINITY;
+    if (i < a.nslots && (!BATCHED || (int)a.bod.scene[i] == scene) && a.bod.blocked[i] != 63u) {
+        const unsigned blocked = a.bod.blocked[i];
+        const double4 xr = a.bod.xr[i];
+        const double r = xr.w, m = a.bod.vm[i].w;
+        const double I = 2.0 * m * r * r / 5.0;
+        const int beg = a.rows.start[i], end = a.rows.start[i + 1];
+        double F[3], T[3];
+        body_sum<PREC>(a, beg, end, r, F, T);
+        const double fa = sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]);
+        fsum = fa;
+        fmaxv = fa;
+        cnt = 1.0;
+        double K[3] = {0.0, 0.0, 0.0}, Rr[3] = {0.0, 0.0, 0.0};
+        for (int e = beg; e < end; ++e) {
+            const uint32_t k = a.rows.ent[e] & kPairMask;
+            if (!a.pr.real[k]) continue;
+            const HistRec h = a.pr.h[k];
+            const double n[3] = {h.nx, h.ny, h.nz};
+            const int sa = a.pr.a[k], sb = a.pr.b[k];
+            const bool wall = sa < 0;
+            const double r2 = a.bod.xr[sb].w;
+            const double r1 = wall ? r2 : a.bod.xr[sa].w;
+            const int m1 = wall ? a.walls[-1 - sa].mat : (int)a.bod.mat[sa];
+            const Material M1 = a.mats[m1], M2 = a.mats[a.bod.mat[sb]];
+            const double k1 = M1.young * (2.0 * r1), k2 = M2.young * (2.0 * r2);
+            const double kn = k1 * k2 / (k1 + k2);
+            const double q1 = M1.young_poisson * (2.0 * r1), q2 = M2.young_poisson * (2.0 * r2);
+            const double ks = q1 * q2 / (q1 + q2);
+            for (int c = 0; c < 3; ++c) {
+                K[c] += (kn - ks) * n[c] * n[c] + ks;
+                Rr[c] += ks * r * r * (1.0 - n[c] * n[c]);
+            }
+        }
+        for (int c = 0; c < 3; ++c) {
+            if (!(blocked & (1u << c)) && K[c] > 0.0) dtmin = fmin(dtmin, sqrt(2.0) * sqrt(m / K[c]));
+            if (!(blocked & (8u << c)) && Rr[c] > 0.0) dtmin = fmin(dtmin, sqrt(2.0) * sqrt(I / Rr[c]));
+        }
+    }
+    __shared__ double sh[kMeasureBlock / 64][kBodyWords];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int off = 32; off > 0; off >>= 1) {
+        fsum += __shfl_down(fsum, off, 64);
+        fmaxv = fmax(fmaxv, __shfl_down(fmaxv, off, 64));
+        cnt += __shfl_down(cnt, off, 64);
+        dtmin = fmin(dtmin, __shfl_down(dtmin, off, 64));
+    }
+    if (lane == 0) {
+        sh[wave][0] = fsum;
+        sh[wave][1] = fmaxv;
+        sh[wave][2] = cnt;
+        sh[wave][3] = dtmin;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t[kBodyWords] = {0.0, 0.0, 0.0, INFINITY};
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            t[0] += sh[w][0];
+            t[1] = fmax(t[1], sh[w][1]);
+            t[2] += sh[w][2];
+            t[3] = fmin(t[3], sh[w][3]);
+        }
+        for (int q = 0; q < kBodyWords; ++q) part[kBodyWords * (size_t)blockIdx.x + q] = t[q];
     }
 }
 
@@ -312,7 +414,23 @@ void launch_integrate(const StepArgs* args, int parity, int grid, int precision,
 
 void launch_cell_update(const StepArgs* args, int parity, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cell_update, dim3(1), dim3(64), 0, st, args, parity);
+    hipLaunchKernelGGL(k_cell_update, dim3(1), dim3(64), 0, st, const_cast<StepArgs*>(args), parity);
+}
+
+int body_blocks(int nslots) { return nslots > 0 ? (nslots + kMeasureBlock - 1) / kMeasureBlock : 0; }
+
+void launch_body_measures(const StepArgs& a, int precision, bool batched, int scene, double* part, hipStream_t st)
+{
+    const int grid = body_blocks(a.nslots);
+    if (grid == 0) return;
+    const dim3 g(grid), b(kMeasureBlock);
+    if (precision == DEM_FP32_MIXED) {
+        if (batched) hipLaunchKernelGGL((k_body_measures<DEM_FP32_MIXED, true>), g, b, 0, st, a, scene, part);
+        else hipLaunchKernelGGL((k_body_measures<DEM_FP32_MIXED, false>), g, b, 0, st, a, scene, part);
+    } else {
+        if (batched) hipLaunchKernelGGL((k_body_measures<DEM_FP64, true>), g, b, 0, st, a, scene, part);
+        else hipLaunchKernelGGL((k_body_measures<DEM_FP64, false>), g, b, 0, st, a, scene, part);
+    }
 }
 
 void launch_body_forces(const StepArgs& a, int precision, double* f3, double* t3, hipStream_t st)

@@ -171,6 +171,8 @@ struct HostScene {
     double time = 0.0;
     double verlet = 0.0;        // Delta L in use
     double rmax = 0.0;          // largest radius at the last broad-phase run
+    double r_lo = INFINITY;     // smallest and largest sphere radius (radii never change)
+    double r_hi = 0.0;
 };
 
 // Host copy of everything per gid (kept in step only when bodies are added
@@ -445,6 +447,8 @@ struct World {
             const double rho = mats[b.mat].density;
             const double r = b.r;
             b.m = 4.0 / 3.0 * M_PI * r * r * r * rho;
+            S.r_lo = std::min(S.r_lo, r);
+            S.r_hi = std::max(S.r_hi, r);
             S.gids.push_back((int32_t)bodies.size());
             bodies.push_back(b);
         }
@@ -597,6 +601,9 @@ struct World {
     // The step kernels read their arguments from device memory.
     void upload_args()
     {
+        // the descriptor carries a copy of scene 0's parameters, which the
+        // device advances for a periodic cell: start from the current ones
+        if (periodic && d_scenes.p) pull_scene_table();
         const StepArgs a = step_args();
         d_args.ensure(sizeof(StepArgs));
         HIPC(hipMemcpyAsync(d_args.p, &a, sizeof(StepArgs), hipMemcpyHostToDevice, stream));
@@ -607,15 +614,16 @@ struct World {
     void rebuild()
     {
         if (host_dirty) upload_bodies();
-        pull_scene_table();
+        // only a periodic cell is advanced on the device; otherwise the host
+        // table is the current one
+        if (periodic) pull_scene_table();
         const int nsc = (int)scenes.size();
         // Delta L per scene (InsertionSortCollider.verletDist, negative = times the smallest radius)
         std::vector<double> rmin(nsc, INFINITY), rmax(nsc, 0.0);
-        for (const HostBody& b : bodies)
-            if (b.kind == 0) {
-                rmin[b.scene] = std::min(rmin[b.scene], b.r);
-                rmax[b.scene] = std::max(rmax[b.scene], b.r);
-            }
+        for (int s = 0; s < nsc; ++s) {
+            rmin[s] = scenes[s].r_lo;
+            rmax[s] = scenes[s].r_hi;
+        }
         double limit = INFINITY;
         for (int s = 0; s < nsc; ++s) {
             const double vd = scenes[s].p.verlet_dist;
@@ -837,9 +845,8 @@ struct World {
         HIPC(hipMemsetAsync(d_part_i.p, 0, sizeof(IntAcc) * (size_t)grid_i, stream));
         acc_c_n = grid_c;
         acc_i_n = grid_i;
-        // counters: fresh Verlet budget, flags clear, parity 0
-        HIPC(hipMemcpyAsync(h_ctr, d_ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, stream));
-        HIPC(hipStreamSynchronize(stream));
+        // counters: fresh Verlet budget, flags clear, parity 0 (every field
+        // is rewritten, so the device copy is not read back first)
         C.verlet_limit = 0.98 * (std::isfinite(limit) ? limit : 0.0);
         double cell_step = 0.0;
         for (int s = 0; s < nsc; ++s) cell_step = std::max(cell_step, sp[s].verlet_cell_rate * sp[s].dt);
@@ -1155,11 +1162,38 @@ struct World {
         }
     }
 
+    // O.step x nsteps.  With the stiffness timestepper or the stress-
+    // controlled cell active, the steps run in segments that end where one
+    // of them acts: the timestepper before a step whose iteration count is a
+    // multiple of its interval, the controller after a step that makes the
+    // count a multiple of glob_update.
     void step(int64_t nsteps)
     {
         if (nsteps < 0) fail(DEM_EINVAL, "dem_step: nsteps < 0");
         HIPC(hipSetDevice(device));
         if (timing) timers.clear();
+        if (ts_interval <= 0 && !pt_active) {
+            run_steps(nsteps);
+            return;
+        }
+        HostScene& S = scenes[0];
+        int64_t left = nsteps;
+        while (left > 0) {
+            if (ts_interval > 0 && S.iter % ts_interval == 0) set_dt(0, stiffness_dt(0, ts_safety));
+            int64_t seg = left;
+            if (ts_interval > 0) seg = std::min(seg, ts_interval - S.iter % ts_interval);
+            if (pt_active) seg = std::min<int64_t>(seg, pt_cfg.glob_update - S.iter % pt_cfg.glob_update);
+            run_steps(seg);
+            left -= seg;
+            if (pt_active && S.iter % pt_cfg.glob_update == 0) {
+                peri_triax_update();
+                if (pt_st.done && pt_cfg.stop_when_done) break;
+            }
+        }
+    }
+
+    void run_steps(int64_t nsteps)
+    {
         if (host_dirty) upload_bodies();
         if (nslots == 0 && walls.empty()) {
             for (auto& S : scenes) {
@@ -1478,6 +1512,146 @@ struct World {
     // Love-Weber stress of scene s: partial sums per block on the device,
     // combined here in block order, divided by the volume (periodic: the
     // cell's, else the caller's).
+    // O.dt between steps
+    void set_dt(int s, double dt)
+    {
+        pull_scene_table();
+        scenes[s].p.dt = dt;
+        sp[s].dt = dt;
+        push_scene_table();
+        if (d_args.p) upload_args();
+        update_cell_step();
+    }
+    // Cell.velGrad between steps: the next step sees it, and the last
+    // step's one as the previous gradient
+    void set_velgrad(int s, const double* L9)
+    {
+        pull_scene_table();
+        for (int k = 0; k < 9; ++k) {
+            scenes[s].p.velgrad[k] = L9[k];
+            sp[s].L[k] = L9[k];
+        }
+        // the mean field's share of the Verlet budget changes from the next
+        // step on; what the bodies' accounts hold stays valid
+        double lf = 0.0;
+        for (int k = 0; k < 9; ++k) lf += L9[k] * L9[k];
+        sp[s].verlet_cell_rate = 0.5 * std::sqrt(lf) * (2.0 * scenes[s].rmax + 4.0 * sp[s].verlet);
+        push_scene_table();
+        if (d_args.p) upload_args();
+        update_cell_step();
+    }
+
+    // Device sums over the last step's contacts and bodies of scene s, in a
+    // fixed block order (the kernels reduce waves in a fixed order too).
+    struct Measures {
+        double sigma[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // times the volume
+        double modulus[3] = {0, 0, 0};                   // times the volume
+        double contact_force_sum = 0.0, contacts = 0.0;
+        double body_force_sum = 0.0, body_force_max = 0.0, bodies_dyn = 0.0;
+        double min_dt = INFINITY;
+    };
+    Measures measures(int s)
+    {
+        Measures m;
+        if (host_dirty) upload_bodies();
+        if (!contacts_valid || nslots == 0) return m;
+        const int np = npairs > 0 ? stress_blocks(npairs) : 0;
+        const int nb = body_blocks(nslots);
+        d_tmp3.ensure(sizeof(double) * ((size_t)kNetworkWords * np + (size_t)kBodyWords * nb));
+        double* part_p = d_tmp3.as<double>();
+        double* part_b = part_p + (size_t)kNetworkWords * np;
+        const StepArgs a = step_args();
+        const bool batched = scenes.size() > 1;
+        if (np > 0) launch_network(a, precision, batched, s, part_p, stream);
+        launch_body_measures(a, precision, batched, s, part_b, stream);
+        HIPC(hipGetLastError());
+        std::vector<double> hp((size_t)kNetworkWords * np), hb((size_t)kBodyWords * nb);
+        if (np > 0)
+            HIPC(hipMemcpyAsync(hp.data(), part_p, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, stream));
+        HIPC(hipMemcpyAsync(hb.data(), part_b, sizeof(double) * hb.size(), hipMemcpyDeviceToHost, stream));
+        HIPC(hipStreamSynchronize(stream));
+        for (int b = 0; b < np; ++b) {
+            const double* q = &hp[(size_t)kNetworkWords * b];
+            for (int k = 0; k < 9; ++k) m.sigma[k] += q[k];
+            for (int k = 0; k < 3; ++k) m.modulus[k] += q[9 + k];
+            m.contact_force_sum += q[12];
+            m.contacts += q[13];
+        }
+        for (int b = 0; b < nb; ++b) {
+            const double* q = &hb[(size_t)kBodyWords * b];
+            m.body_force_sum += q[0];
+            m.body_force_max = std::max(m.body_force_max, q[1]);
+            m.bodies_dyn += q[2];
+            m.min_dt = std::min(m.min_dt, q[3]);
+        }
+        return m;
+    }
+    static double unbalanced_of(const Measures& m, bool use_max)
+    {
+        if (!(m.contacts > 0.0) || !(m.bodies_dyn > 0.0)) return NAN;
+        const double mean_contact = m.contact_force_sum / m.contacts;
+        const double top = use_max ? m.body_force_max : m.body_force_sum / m.bodies_dyn;
+        return top / mean_contact;
+    }
+    double stiffness_dt(int s, double safety)
+    {
+        const Measures m = measures(s);
+        if (std::isinf(m.min_dt)) return safety * pwave_dt(s);
+        return safety * m.min_dt;
+    }
+
+    // ---- GlobalStiffnessTimeStepper and the stress-controlled cell, run
+    // between steps by step() (scene 0 of an unbatched world)
+    double ts_safety = 0.8;
+    int64_t ts_interval = 0;
+    bool pt_active = false;
+    dem_peri_triax pt_cfg{};
+    dem_peri_triax_state pt_st{};
+
+    static double cell_volume(const double* H)
+    {
+        return std::fabs(H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
+                         H[2] * (H[3] * H[7] - H[4] * H[6]));
+    }
+    void peri_triax_update()
+    {
+        const Measures m = measures(0);
+        pull_scene_table();
+        const SceneParams& P = sp[0];
+        const double V = cell_volume(P.H);
+        const double T = (double)pt_cfg.glob_update * P.dt;
+        double rates[3];
+        bool reached = true;
+        for (int i = 0; i < 3; ++i) {
+            pt_st.stress[i] = m.sigma[4 * i] / V;
+            pt_st.strain[i] = std::log(P.trsf[4 * i]);
+            pt_st.stiff[i] = m.modulus[i] / V;
+            double rate;
+            if (pt_cfg.stress_mask & (1 << i)) {
+                const double err = pt_cfg.goal[i] - pt_st.stress[i];
+                if (pt_st.stiff[i] > 0.0)
+                    rate = (1.0 - pt_cfg.grow_damping) * err / (pt_st.stiff[i] * T);
+                else
+                    rate = err != 0.0 ? std::copysign(pt_cfg.max_strain_rate[i], err) : 0.0;
+                if (std::fabs(err) > std::max(pt_cfg.abs_stress_tol, pt_cfg.rel_stress_tol * std::fabs(pt_cfg.goal[i])))
+                    reached = false;
+            } else {
+                const double err = pt_cfg.goal[i] - pt_st.strain[i];
+                rate = err / T;
+                if (std::fabs(err) > 1e-6) reached = false;
+            }
+            rates[i] = std::max(-pt_cfg.max_strain_rate[i], std::min(pt_cfg.max_strain_rate[i], rate));
+        }
+        pt_st.unbalanced = unbalanced_of(m, false);
+        if (!(pt_st.unbalanced <= pt_cfg.max_unbalanced)) reached = false;
+        pt_st.done = reached ? 1 : 0;
+        if (reached) rates[0] = rates[1] = rates[2] = 0.0;
+        for (int i = 0; i < 3; ++i) pt_st.strain_rate[i] = rates[i];
+        const double L[9] = {rates[0], 0.0, 0.0, 0.0, rates[1], 0.0, 0.0, 0.0, rates[2]};
+        set_velgrad(0, L);
+        pt_st.updates += 1;
+    }
+
     void stress(int s, double volume, double* out9)
     {
         double V = volume;
@@ -1493,15 +1667,15 @@ struct World {
         if (host_dirty) upload_bodies();
         const int nb = (contacts_valid && npairs > 0) ? stress_blocks(npairs) : 0;
         if (nb > 0) {
-            d_tmp3.ensure(sizeof(double) * 9 * (size_t)nb);
+            d_tmp3.ensure(sizeof(double) * kNetworkWords * (size_t)nb);
             StepArgs a = step_args();
-            launch_stress(a, precision, scenes.size() > 1, s, d_tmp3.as<double>(), stream);
+            launch_network(a, precision, scenes.size() > 1, s, d_tmp3.as<double>(), stream);
             HIPC(hipGetLastError());
-            std::vector<double> part(9 * (size_t)nb);
+            std::vector<double> part(kNetworkWords * (size_t)nb);
             HIPC(hipMemcpyAsync(part.data(), d_tmp3.p, sizeof(double) * part.size(), hipMemcpyDeviceToHost, stream));
             HIPC(hipStreamSynchronize(stream));
             for (int b = 0; b < nb; ++b)
-                for (int q = 0; q < 9; ++q) sum[q] += part[9 * (size_t)b + q];
+                for (int q = 0; q < 9; ++q) sum[q] += part[kNetworkWords * (size_t)b + q];
         }
         for (int q = 0; q < 9; ++q) out9[q] = sum[q] / V;
     }
@@ -1846,12 +2020,7 @@ dem_status dem_set_dt(dem_scene* s, double dt)
     return guarded([&] {
         dem::World* w = world_of(s);
         if (!(dt > 0.0) || !std::isfinite(dt)) dem::fail(DEM_EINVAL, "dt must be > 0");
-        w->pull_scene_table();
-        w->scenes[s->s].p.dt = dt;
-        w->sp[s->s].dt = dt;
-        w->push_scene_table();
-        if (w->d_args.p) w->upload_args();
-        w->update_cell_step();
+        w->set_dt(s->s, dt);
     });
 }
 
@@ -1861,19 +2030,9 @@ dem_status dem_set_velgrad(dem_scene* s, const double* velgrad9)
         dem::World* w = world_of(s);
         if (!velgrad9) dem::fail(DEM_EINVAL, "null velgrad");
         if (!w->scenes[s->s].p.periodic) dem::fail(DEM_EINVAL, "dem_set_velgrad: scene is not periodic");
-        w->pull_scene_table();
-        for (int k = 0; k < 9; ++k) {
-            w->scenes[s->s].p.velgrad[k] = velgrad9[k];
-            w->sp[s->s].L[k] = velgrad9[k];
-        }
-        // the mean field's share of the Verlet budget changes from the next
-        // step on; what the bodies' accounts hold stays valid
-        double lf = 0.0;
-        for (int k = 0; k < 9; ++k) lf += velgrad9[k] * velgrad9[k];
-        w->sp[s->s].verlet_cell_rate = 0.5 * std::sqrt(lf) * (2.0 * w->scenes[s->s].rmax + 4.0 * w->sp[s->s].verlet);
-        w->push_scene_table();
-        if (w->d_args.p) w->upload_args();
-        w->update_cell_step();
+        for (int k = 0; k < 9; ++k)
+            if (!std::isfinite(velgrad9[k])) dem::fail(DEM_EINVAL, "dem_set_velgrad: non-finite entry");
+        w->set_velgrad(s->s, velgrad9);
     });
 }
 
@@ -2123,6 +2282,89 @@ static void fill_stats(dem::World* w, int s, dem_stats* out)
     out->contact_steps = (int64_t)csteps;
     out->coordination = all ? 2.0 * (double)ss / (double)all : 0.0;
     out->max_overlap_ratio = maxov;
+}
+
+dem_status dem_get_unbalanced_force(dem_scene* s, int32_t use_max, double* out)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        if (!out) dem::fail(DEM_EINVAL, "null output");
+        *out = dem::World::unbalanced_of(w->measures(s->s), use_max != 0);
+    });
+}
+
+dem_status dem_stiffness_dt(dem_scene* s, double safety, double* out)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        if (!out) dem::fail(DEM_EINVAL, "null output");
+        if (!(safety > 0.0) || !(safety <= 1.0)) dem::fail(DEM_EINVAL, "dem_stiffness_dt: safety in (0, 1]");
+        *out = w->stiffness_dt(s->s, safety);
+    });
+}
+
+dem_status dem_set_stiffness_timestepper(dem_scene* s, double safety, int64_t interval)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        if (w->scenes.size() > 1) dem::fail(DEM_EINVAL, "dem_set_stiffness_timestepper: not available for batch scenes");
+        if (interval < 0) dem::fail(DEM_EINVAL, "dem_set_stiffness_timestepper: interval >= 0");
+        if (interval > 0 && (!(safety > 0.0) || !(safety <= 1.0)))
+            dem::fail(DEM_EINVAL, "dem_set_stiffness_timestepper: safety in (0, 1]");
+        w->ts_safety = safety;
+        w->ts_interval = interval;
+    });
+}
+
+void dem_peri_triax_default(dem_peri_triax* c)
+{
+    if (!c) return;
+    std::memset(c, 0, sizeof *c);
+    c->stress_mask = 7;
+    c->glob_update = 5;
+    for (int i = 0; i < 3; ++i) c->max_strain_rate[i] = 1.0;
+    c->grow_damping = 0.25;
+    c->max_unbalanced = 1e-4;
+    c->abs_stress_tol = 1e3;
+    c->rel_stress_tol = 3e-5;
+}
+
+dem_status dem_set_peri_triax(dem_scene* s, const dem_peri_triax* c)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        if (!c) {
+            w->pt_active = false;
+            w->pt_st.active = 0;
+            return;
+        }
+        if (!w->scenes[s->s].p.periodic || w->scenes.size() > 1)
+            dem::fail(DEM_EINVAL, "dem_set_peri_triax: needs an unbatched periodic scene");
+        if (c->glob_update < 1) dem::fail(DEM_EINVAL, "dem_set_peri_triax: glob_update >= 1");
+        if (c->stress_mask < 0 || c->stress_mask > 7) dem::fail(DEM_EINVAL, "dem_set_peri_triax: stress_mask in 0..7");
+        if (!(c->grow_damping >= 0.0 && c->grow_damping < 1.0)) dem::fail(DEM_EINVAL, "dem_set_peri_triax: grow_damping in [0, 1)");
+        for (int i = 0; i < 3; ++i) {
+            if (!(c->max_strain_rate[i] > 0.0) || !std::isfinite(c->max_strain_rate[i]))
+                dem::fail(DEM_EINVAL, "dem_set_peri_triax: max_strain_rate > 0");
+            if (!std::isfinite(c->goal[i])) dem::fail(DEM_EINVAL, "dem_set_peri_triax: non-finite goal");
+        }
+        if (!(c->abs_stress_tol >= 0.0) || !(c->rel_stress_tol >= 0.0) || std::isnan(c->max_unbalanced))
+            dem::fail(DEM_EINVAL, "dem_set_peri_triax: tolerances >= 0");
+        w->pt_cfg = *c;
+        w->pt_st = dem_peri_triax_state{};
+        w->pt_st.unbalanced = NAN;
+        w->pt_st.active = 1;
+        w->pt_active = true;
+    });
+}
+
+dem_status dem_get_peri_triax(dem_scene* s, dem_peri_triax_state* out)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        if (!out) dem::fail(DEM_EINVAL, "null output");
+        *out = w->pt_st;
+    });
 }
 
 dem_status dem_get_stats(dem_scene* s, dem_stats* out)

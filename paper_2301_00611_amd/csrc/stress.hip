@@ -1,6 +1,7 @@
 // stress.hip -- reporting kernels: per-pair forces (read back by the
-// contact list and the wall reactions) and the Love-Weber stress of the
-// contact network
+// contact list and the wall reactions) and the sums over the contact
+// network: the Love-Weber stress, the normal springs' modulus of the
+// stress-controlled cell and the mean contact force of the unbalanced force
 // (utils.getStress, section 5 utility reference): the sum over the real
 // sphere-sphere contacts of f (x) l, where f is the force on #2 and l the
 // branch vector from #2 to #1, so that repulsive contacts give negative
@@ -51,43 +52,57 @@ __global__ void __launch_bounds__(kStressBlock) k_pair_forces(StepArgs a, double
     f3[3 * (size_t)k + 2] = F[2];
 }
 
+// Per-block sums over the real contacts of one scene (kNetworkWords
+// doubles): the Love-Weber stress sum (9, sphere-sphere contacts), the
+// normal springs' modulus sum k_n (d_i n_i)^2 per axis (3, sphere-sphere;
+// d = (r1 + r2 - pen) n is the centre distance vector), the sum of |F| and
+// the number of contacts (walls included; unbalanced force).
 template <int PREC, bool BATCHED>
-__global__ void __launch_bounds__(kStressBlock) k_stress(StepArgs a, int scene, double* __restrict__ part)
+__global__ void __launch_bounds__(kStressBlock) k_network(StepArgs a, int scene, double* __restrict__ part)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    double s[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double s[kNetworkWords];
+    for (int q = 0; q < kNetworkWords; ++q) s[q] = 0.0;
     const Pairs& P = a.pr;
-    if (k < a.npairs && P.real[k] && P.a[k] >= 0) {
+    if (k < a.npairs && P.real[k]) {
         const Bodies& B = a.bod;
         const int sa = P.a[k], sb = P.b[k];
         if (!BATCHED || (int)B.scene[sb] == scene) {
             double F[3];
             pair_force<PREC>(a, k, F);
-            const HistRec h = P.h[k];
-            const double n[3] = {h.nx, h.ny, h.nz};
-            const double fn[3] = {F[0] - h.fsx, F[1] - h.fsy, F[2] - h.fsz};
-            const double r1 = B.xr[sa].w, r2 = B.xr[sb].w;
-            const Material M1 = a.mats[B.mat[sa]], M2 = a.mats[B.mat[sb]];
-            const double k1 = M1.young * (2.0 * r1), k2 = M2.young * (2.0 * r2);
-            const double kn = k1 * k2 / (k1 + k2);
-            const double pen = sqrt(fn[0] * fn[0] + fn[1] * fn[1] + fn[2] * fn[2]) / kn;
-            const double lm = (r1 + r2) - pen;
-            for (int i = 0; i < 3; ++i)
-                for (int j = 0; j < 3; ++j) s[3 * i + j] = F[i] * (-lm * n[j]);
+            s[12] = sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]);
+            s[13] = 1.0;
+            if (sa >= 0) {
+                const HistRec h = P.h[k];
+                const double n[3] = {h.nx, h.ny, h.nz};
+                const double fn[3] = {F[0] - h.fsx, F[1] - h.fsy, F[2] - h.fsz};
+                const double r1 = B.xr[sa].w, r2 = B.xr[sb].w;
+                const Material M1 = a.mats[B.mat[sa]], M2 = a.mats[B.mat[sb]];
+                const double k1 = M1.young * (2.0 * r1), k2 = M2.young * (2.0 * r2);
+                const double kn = k1 * k2 / (k1 + k2);
+                const double pen = sqrt(fn[0] * fn[0] + fn[1] * fn[1] + fn[2] * fn[2]) / kn;
+                const double lm = (r1 + r2) - pen;
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) s[3 * i + j] = F[i] * (-lm * n[j]);
+                for (int i = 0; i < 3; ++i) {
+                    const double dn = (lm * n[i]) * n[i];
+                    s[9 + i] = kn * dn * dn;
+                }
+            }
         }
     }
-    __shared__ double sh[kStressBlock / 64][9];
+    __shared__ double sh[kStressBlock / 64][kNetworkWords];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int q = 0; q < 9; ++q)
+    for (int q = 0; q < kNetworkWords; ++q)
         for (int off = 32; off > 0; off >>= 1) s[q] += __shfl_down(s[q], off, 64);
     if (lane == 0)
-        for (int q = 0; q < 9; ++q) sh[wave][q] = s[q];
+        for (int q = 0; q < kNetworkWords; ++q) sh[wave][q] = s[q];
     __syncthreads();
     if (threadIdx.x == 0)
-        for (int q = 0; q < 9; ++q) {
+        for (int q = 0; q < kNetworkWords; ++q) {
             double t = 0.0;
             for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w][q];
-            part[9 * (size_t)blockIdx.x + q] = t;
+            part[kNetworkWords * (size_t)blockIdx.x + q] = t;
         }
 }
 
@@ -105,16 +120,16 @@ void launch_pair_forces(const StepArgs& a, int precision, double* f3, hipStream_
 
 int stress_blocks(int npairs) { return npairs > 0 ? (npairs + kStressBlock - 1) / kStressBlock : 0; }
 
-void launch_stress(const StepArgs& a, int precision, bool batched, int scene, double* part, hipStream_t st)
+void launch_network(const StepArgs& a, int precision, bool batched, int scene, double* part, hipStream_t st)
 {
     const int grid = stress_blocks(a.npairs);
     if (grid == 0) return;
     if (precision == DEM_FP32_MIXED) {
-        if (batched) hipLaunchKernelGGL((k_stress<DEM_FP32_MIXED, true>), dim3(grid), dim3(kStressBlock), 0, st, a, scene, part);
-        else hipLaunchKernelGGL((k_stress<DEM_FP32_MIXED, false>), dim3(grid), dim3(kStressBlock), 0, st, a, scene, part);
+        if (batched) hipLaunchKernelGGL((k_network<DEM_FP32_MIXED, true>), dim3(grid), dim3(kStressBlock), 0, st, a, scene, part);
+        else hipLaunchKernelGGL((k_network<DEM_FP32_MIXED, false>), dim3(grid), dim3(kStressBlock), 0, st, a, scene, part);
     } else {
-        if (batched) hipLaunchKernelGGL((k_stress<DEM_FP64, true>), dim3(grid), dim3(kStressBlock), 0, st, a, scene, part);
-        else hipLaunchKernelGGL((k_stress<DEM_FP64, false>), dim3(grid), dim3(kStressBlock), 0, st, a, scene, part);
+        if (batched) hipLaunchKernelGGL((k_network<DEM_FP64, true>), dim3(grid), dim3(kStressBlock), 0, st, a, scene, part);
+        else hipLaunchKernelGGL((k_network<DEM_FP64, false>), dim3(grid), dim3(kStressBlock), 0, st, a, scene, part);
     }
 }
 

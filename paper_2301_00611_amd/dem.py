@@ -81,6 +81,19 @@ class dem_tuning(C.Structure):
                 ("pad", C.c_int32), ("verlet_factor", C.c_double), ("ms_per_step", C.c_double)]
 
 
+class dem_peri_triax(C.Structure):
+    _fields_ = [("goal", C.c_double * 3), ("stress_mask", C.c_int32), ("glob_update", C.c_int32),
+                ("max_strain_rate", C.c_double * 3), ("grow_damping", C.c_double),
+                ("max_unbalanced", C.c_double), ("abs_stress_tol", C.c_double), ("rel_stress_tol", C.c_double),
+                ("stop_when_done", C.c_int32), ("pad", C.c_int32)]
+
+
+class dem_peri_triax_state(C.Structure):
+    _fields_ = [("stress", C.c_double * 3), ("strain", C.c_double * 3), ("strain_rate", C.c_double * 3),
+                ("stiff", C.c_double * 3), ("unbalanced", C.c_double), ("updates", C.c_int64),
+                ("done", C.c_int32), ("active", C.c_int32)]
+
+
 def _tuning_dict(t):
     return {k: getattr(t, k) for k, _ in dem_tuning._fields_ if k != "pad"}
 
@@ -144,6 +157,12 @@ SIGNATURES = {
     "dem_autotune": (C.c_int32, [C.c_void_p, C.c_int64, C.c_char_p, C.POINTER(dem_tuning)]),
     "dem_batch_set_tuning": (C.c_int32, [C.c_void_p, C.POINTER(dem_tuning)]),
     "dem_batch_autotune": (C.c_int32, [C.c_void_p, C.c_int64, C.c_char_p, C.POINTER(dem_tuning)]),
+    "dem_get_unbalanced_force": (C.c_int32, [C.c_void_p, C.c_int32, _DP]),
+    "dem_stiffness_dt": (C.c_int32, [C.c_void_p, C.c_double, _DP]),
+    "dem_set_stiffness_timestepper": (C.c_int32, [C.c_void_p, C.c_double, C.c_int64]),
+    "dem_peri_triax_default": (None, [C.POINTER(dem_peri_triax)]),
+    "dem_set_peri_triax": (C.c_int32, [C.c_void_p, C.POINTER(dem_peri_triax)]),
+    "dem_get_peri_triax": (C.c_int32, [C.c_void_p, C.POINTER(dem_peri_triax_state)]),
 }
 
 _lib = None
@@ -388,6 +407,50 @@ class Scene:
         out = np.zeros(9)
         check(self.lib.dem_get_stress(self.h, float(volume), _p(out)), "dem_get_stress")
         return out.reshape(3, 3)
+
+    def unbalanced_force(self, use_max=False):
+        out = C.c_double()
+        check(self.lib.dem_get_unbalanced_force(self.h, 1 if use_max else 0, C.byref(out)), "dem_get_unbalanced_force")
+        return out.value
+
+    def stiffness_dt(self, safety=0.8):
+        out = C.c_double()
+        check(self.lib.dem_stiffness_dt(self.h, float(safety), C.byref(out)), "dem_stiffness_dt")
+        return out.value
+
+    def set_stiffness_timestepper(self, safety=0.8, interval=1):
+        check(self.lib.dem_set_stiffness_timestepper(self.h, float(safety), int(interval)),
+              "dem_set_stiffness_timestepper")
+
+    def set_peri_triax(self, goal=None, stress_mask=7, **kw):
+        """Switch the stress-controlled cell on (goal: 3 values) or off
+        (goal None).  Keywords: glob_update, max_strain_rate (3),
+        grow_damping, max_unbalanced, abs_stress_tol, rel_stress_tol,
+        stop_when_done."""
+        if goal is None:
+            check(self.lib.dem_set_peri_triax(self.h, None), "dem_set_peri_triax")
+            return
+        c = dem_peri_triax()
+        self.lib.dem_peri_triax_default(C.byref(c))
+        c.goal[:] = [float(g) for g in goal]
+        c.stress_mask = int(stress_mask)
+        for k, v in kw.items():
+            if k == "max_strain_rate":
+                c.max_strain_rate[:] = [float(x) for x in v]
+            elif k in ("glob_update", "stop_when_done"):
+                setattr(c, k, int(v))
+            else:
+                setattr(c, k, float(v))
+        check(self.lib.dem_set_peri_triax(self.h, C.byref(c)), "dem_set_peri_triax")
+
+    def get_peri_triax(self):
+        st = dem_peri_triax_state()
+        check(self.lib.dem_get_peri_triax(self.h, C.byref(st)), "dem_get_peri_triax")
+        out = {}
+        for k, _ in dem_peri_triax_state._fields_:
+            v = getattr(st, k)
+            out[k] = list(v) if hasattr(v, "__len__") else v
+        return out
 
     def get_tuning(self):
         t = dem_tuning()

@@ -1,0 +1,190 @@
+"""Parity of the GPU's unbalanced force, stiffness timestepper and
+stress/strain-controlled periodic cell (C ABI) with the oracle's versions
+(oracle/controls.py), plus the controller's closed form on a lattice.
+
+Bars: from an identical state the unbalanced force and the stiffness
+timestep agree to 1e-10 / 1e-12 relative (the body resultants are
+near-cancelling sums; the sums run in a different order); a controlled run
+of 100 steps keeps the cell, the controller's state and the positions within
+1e-9 relative of the oracle's.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_helpers import twin
+
+pytestmark = pytest.mark.gpu
+
+R = 2.0 ** -10
+E, NU, RHO = 1e7, 0.3, 1000.0
+
+
+def _dense(n, seed):
+    from test_gpu_parity import _dense_spec
+    return _dense_spec(n, seed)
+
+
+@pytest.mark.parametrize("n,seed", [(37, 1), (511, 2), (1500, 3)])
+def test_unbalanced_and_stiffness_dt_one_step(n, seed):
+    from oracle.controls import stiffness_dt, unbalanced_force
+    from paper_2301_00611_amd.scenes import random_velocities
+    spec = _dense(n, seed)
+    v, w = random_velocities(n, 0.05, seed + 100)
+    g, o, dt = twin(spec, vel=v, angvel=w * 0.05)
+    g.step(1)
+    o.step(1)
+    for use_max in (False, True):
+        ug, uo = g.unbalanced_force(use_max), unbalanced_force(o, use_max)
+        assert math.isfinite(uo)
+        assert ug == pytest.approx(uo, rel=1e-10)
+    for safety in (0.8, 0.3):
+        assert g.stiffness_dt(safety) == pytest.approx(stiffness_dt(o, safety), rel=1e-12)
+
+
+def test_unbalanced_nan_and_pwave_fallback_without_contacts():
+    from paper_2301_00611_amd import dem
+    g = dem.Scene(gravity=(0, 0, 0), damping=0.0)
+    m = g.add_material(RHO, E, NU, 0.5)
+    g.add_spheres(np.array([[0, 0, 0], [3 * R, 0, 0]], dtype=float), [R, R], default_mat=m)
+    g.set_dt(0.1 * g.pwave_dt())
+    assert math.isnan(g.unbalanced_force())      # before any step
+    assert g.stiffness_dt(0.7) == pytest.approx(0.7 * R * math.sqrt(RHO / E), rel=1e-15)
+    g.step(2)
+    assert math.isnan(g.unbalanced_force())
+    assert g.stiffness_dt(0.7) == pytest.approx(0.7 * R * math.sqrt(RHO / E), rel=1e-15)
+
+
+def test_stiffness_timestepper_run_parity():
+    """The timestepper every 4 steps over 40 steps of a dense walled cloud:
+    the same dt sequence and the same states as the oracle's."""
+    from oracle.controls import run_with_timestepper
+    spec = _dense(511, 2)
+    g, o, dt = twin(spec)
+    g.set_stiffness_timestepper(0.5, 4)
+    for k in range(10):
+        g.step(4)
+        run_with_timestepper(o, 4, safety=0.5, interval=4)
+    assert g.stats()["iter"] == 40
+    sg, so = g.get_state(), o.get_state()
+    scale = np.abs(so["pos"]).max()
+    assert np.abs(sg["pos"] - so["pos"]).max() <= 1e-12 * scale
+    # the next dt both would set
+    from oracle.controls import stiffness_dt
+    assert g.stiffness_dt(0.5) == pytest.approx(stiffness_dt(o, 0.5), rel=1e-12)
+    g.set_stiffness_timestepper(0.5, 0)      # off
+    g.step(3)
+    assert g.stats()["iter"] == 43
+
+
+def _lattice_twin(jitter=0.0, seed=0, k=5, delta_frac=0.01):
+    # k = 5: the GPU grid needs a cell at least 3 (2 r_max + 2 Delta L) wide
+    from oracle import OracleScene
+    from paper_2301_00611_amd import dem
+    delta = delta_frac * R
+    a = 2 * R - delta
+    grid = np.arange(k) * a
+    pos = np.array([[x, y, z] for z in grid for y in grid for x in grid]) + 0.5 * a
+    if jitter:
+        pos = pos + np.random.default_rng(seed).uniform(-jitter, jitter, pos.shape) * delta
+    H = np.eye(3) * (k * a)
+    g = dem.Scene(periodic=True, hsize=H, gravity=(0, 0, 0), damping=0.2)
+    mg = g.add_material(RHO, E, NU, 0.5)
+    g.add_spheres(pos, [R] * len(pos), default_mat=mg)
+    dt = 0.2 * g.pwave_dt()
+    g.set_dt(dt)
+    o = OracleScene(dt=dt, periodic=True, hsize=H, damping=0.2)
+    mo = o.add_material(RHO, E, NU, 0.5)
+    o.add_spheres(pos, [R] * len(pos), default_mat=mo)
+    return g, o, a, delta, dt
+
+
+def test_peri_triax_lattice_closed_form_on_the_gpu():
+    """Through the GPU path: at rest the lattice gives sigma_ii = -k_n delta
+    / a^2, M_i = k_n / a, and the first update's rate (1 - 0.25)(goal -
+    sigma)/(M 5 dt)."""
+    g, o, a, delta, dt = _lattice_twin()
+    kn = E * R
+    sig = -kn * delta / a ** 2
+    goal = 2.0 * sig
+    g.set_peri_triax((goal,) * 3, 7, glob_update=5, max_strain_rate=(1e3,) * 3)
+    g.step(5)
+    st = g.get_peri_triax()
+    assert st["updates"] == 1 and st["active"] == 1 and st["done"] == 0
+    for i in range(3):
+        assert st["stress"][i] == pytest.approx(sig, rel=1e-9)
+        assert st["stiff"][i] == pytest.approx(kn / a, rel=1e-9)
+        assert st["strain_rate"][i] == pytest.approx(0.75 * (goal - sig) / ((kn / a) * 5 * dt), rel=1e-9)
+
+
+@pytest.mark.parametrize("mask,goal_scale", [(7, (1.5, 1.5, 1.5)), (0b011, (1.3, 0.8, None))])
+def test_peri_triax_run_parity(mask, goal_scale):
+    """A jittered lattice under the controller for 100 steps (20 updates):
+    cell, controller state and positions as in the oracle; a strain axis
+    (goal -2e-3) when bit 2 is clear."""
+    from oracle.controls import PeriTriax
+    g, o, a, delta, dt = _lattice_twin(jitter=0.2, seed=4)
+    sig = -E * R * delta / a ** 2
+    goal = [sig * s if s is not None else -2e-3 for s in goal_scale]
+    kw = dict(glob_update=5, max_strain_rate=(50.0, 50.0, 50.0), grow_damping=0.3)
+    g.set_peri_triax(goal, mask, **kw)
+    c = PeriTriax(o, goal, mask, **kw)
+    g.step(100)
+    c.run(100)
+    st = g.get_peri_triax()
+    assert st["updates"] == c.updates == 20
+    for i in range(3):
+        assert st["stress"][i] == pytest.approx(c.stress[i], rel=1e-9)
+        assert st["stiff"][i] == pytest.approx(c.stiff[i], rel=1e-9)
+        assert st["strain"][i] == pytest.approx(c.strain[i], rel=1e-9, abs=1e-15)
+        assert st["strain_rate"][i] == pytest.approx(c.strain_rate[i], rel=1e-8, abs=1e-12)
+    assert st["unbalanced"] == pytest.approx(c.unbalanced, rel=1e-6)
+    hg, _ = g.get_cell()
+    ho, _ = o.get_cell()
+    assert np.abs(hg - ho).max() <= 1e-12 * np.abs(ho).max()
+    pg, po = g.get_state()["pos"], o.get_state()["pos"]
+    assert np.abs(pg - po).max() <= 1e-12 * np.abs(po).max()
+    assert any(abs(x) > 0 for x in st["strain"])     # the cell did move
+
+
+def test_peri_triax_stops_when_done():
+    """At the goal from the start: done at the first update, the cell stops
+    and dem_step returns after 5 of the 50 steps asked."""
+    g, o, a, delta, dt = _lattice_twin()
+    sig = -E * R * delta / a ** 2
+    g.set_peri_triax((sig,) * 3, 7, glob_update=5, stop_when_done=1)
+    g.step(50)
+    st = g.get_peri_triax()
+    assert st["done"] == 1 and st["updates"] == 1
+    assert g.stats()["iter"] == 5
+    assert st["strain_rate"] == [0.0, 0.0, 0.0]
+    g.set_peri_triax(None)
+    assert g.get_peri_triax()["active"] == 0
+    g.step(5)
+    assert g.stats()["iter"] == 10
+
+
+def test_control_call_errors():
+    from paper_2301_00611_amd import dem
+    g = dem.Scene(gravity=(0, 0, 0))
+    m = g.add_material(RHO, E, NU, 0.5)
+    g.add_spheres(np.zeros((1, 3)), [R], default_mat=m)
+    with pytest.raises(dem.DemError):
+        g.set_peri_triax((0.0, 0.0, 0.0), 7)            # not periodic
+    with pytest.raises(dem.DemError):
+        g.stiffness_dt(0.0)
+    with pytest.raises(dem.DemError):
+        g.set_stiffness_timestepper(1.5, 3)
+    with pytest.raises(dem.DemError):
+        g.set_stiffness_timestepper(0.5, -1)
+    p, o, a, delta, dt = _lattice_twin()
+    with pytest.raises(dem.DemError):
+        p.set_peri_triax((0.0, 0.0, 0.0), 7, glob_update=0)
+    with pytest.raises(dem.DemError):
+        p.set_peri_triax((0.0, 0.0, 0.0), 7, grow_damping=1.0)
+    with pytest.raises(dem.DemError):
+        p.set_peri_triax((0.0, 0.0, 0.0), 8)
+    b = dem.Batch([dem.make_params(dt=1e-6), dem.make_params(dt=1e-6)])
+    with pytest.raises(dem.DemError):
+        b.scene(0).set_stiffness_timestepper(0.5, 3)

@@ -1,0 +1,229 @@
+"""Pins of the oracle's unbalanced force, stiffness timestep and
+stress/strain-controlled periodic cell (oracle/controls.py) against closed
+forms.
+
+Each expected value is written out from the mechanics of the configuration
+(two or three touching spheres, a simple cubic lattice), not taken from the
+oracle: a dropped term, a wrong sign or a swapped operand in the oracle's
+formula fails one of them (the comment of each test names what it guards).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import OracleScene
+from oracle.controls import PeriTriax, run_with_timestepper, stiffness_dt, unbalanced_force
+
+R = 2.0 ** -10          # radius (exact in binary)
+E, NU, RHO = 1e7, 0.3, 1000.0
+
+
+def _scene(pos, blocked=None, periodic=False, hsize=None, dt=None):
+    s = OracleScene(dt=1.0 if dt is None else dt, periodic=periodic, hsize=hsize)
+    m = s.add_material(RHO, E, NU, 0.5)
+    s.add_spheres(np.asarray(pos, dtype=float), [R] * len(pos), default_mat=m, blocked=blocked)
+    if dt is None:
+        s.set_dt(0.2 * s.pwave_dt())
+    return s
+
+
+def _mass():
+    return 4.0 / 3.0 * math.pi * R ** 3 * RHO
+
+
+# --------------------------------------------------------- unbalanced force
+
+def test_unbalanced_two_spheres_is_one():
+    """Two touching spheres: each body's resultant is the contact force, so
+    mean and max ratios are exactly 1 (guards the pairing of numerator and
+    denominator)."""
+    s = _scene([[0, 0, 0], [1.5 * R, 0, 0]])
+    s.step(1)
+    assert unbalanced_force(s) == pytest.approx(1.0, rel=1e-15)
+    assert unbalanced_force(s, use_max=True) == pytest.approx(1.0, rel=1e-15)
+
+
+def test_unbalanced_three_collinear_spheres():
+    """Three equal spheres in a row with equal overlaps: the middle one's
+    forces cancel, the ends carry |F| each; mean over bodies 2|F|/3, mean
+    contact force |F| -> 2/3; max -> 1 (guards mean vs max and the body
+    average)."""
+    s = _scene([[0, 0, 0], [1.5 * R, 0, 0], [3.0 * R, 0, 0]])
+    s.step(1)
+    f = s.get_state()["force"]
+    assert np.linalg.norm(f[1]) == 0.0
+    assert unbalanced_force(s) == pytest.approx(2.0 / 3.0, rel=1e-14)
+    assert unbalanced_force(s, use_max=True) == pytest.approx(1.0, rel=1e-14)
+
+
+def test_unbalanced_skips_non_dynamic_bodies():
+    """The middle sphere fully blocked (all six DOFs) is not dynamic: only
+    the ends count, ratio 1 (guards the dynamic-body filter)."""
+    s = _scene([[0, 0, 0], [1.5 * R, 0, 0], [3.0 * R, 0, 0]], blocked=[0, 63, 0])
+    s.step(1)
+    assert unbalanced_force(s) == pytest.approx(1.0, rel=1e-14)
+
+
+def test_unbalanced_without_contacts_is_nan():
+    s = _scene([[0, 0, 0], [3.0 * R, 0, 0]])
+    s.step(1)
+    assert math.isnan(unbalanced_force(s))
+
+
+# ------------------------------------------------------- stiffness timestep
+
+def test_stiffness_dt_axial_contact():
+    """Two equal spheres touching along x: k_n = E r, k_s = E nu r (series
+    springs of E 2r each).  K_xx = k_n dominates (rotation: I / (k_s r^2) =
+    0.4 m / (E nu r) is larger), so dt = safety sqrt(2) sqrt(m / (E r))
+    (eq. 2.12 with eq. 2.14's normal term)."""
+    s = _scene([[0, 0, 0], [1.5 * R, 0, 0]])
+    s.step(1)
+    expected = 0.8 * math.sqrt(2.0) * math.sqrt(_mass() / (E * R))
+    assert stiffness_dt(s, 0.8) == pytest.approx(expected, rel=1e-13)
+
+
+def test_stiffness_dt_blocked_axis_leaves_the_rotation():
+    """The same pair with x translation blocked on both: K_yy = K_zz = k_s
+    (eq. 2.14's tangential term) and the rotations about y and z see
+    k_s r^2 against I = 2/5 m r^2, the stiffest of what is left:
+    dt = sqrt(2) sqrt(0.4 m / (E nu r)) (guards the blocked-DOF rule and the
+    rotational term)."""
+    s = _scene([[0, 0, 0], [1.5 * R, 0, 0]], blocked=[1, 1])
+    s.step(1)
+    expected = 0.5 * math.sqrt(2.0) * math.sqrt(0.4 * _mass() / (E * NU * R))
+    assert stiffness_dt(s, 0.5) == pytest.approx(expected, rel=1e-13)
+
+
+def test_stiffness_dt_diagonal_contact():
+    """Contact normal (1, 1, 0)/sqrt2: K_xx = K_yy = (k_n + k_s)/2 (the
+    n_i n_j weighting of eq. 2.14), K_zz = k_s; rotation about z sees the
+    full k_s r^2.  With nu = 0.3 the z rotation is the stiffest:
+    0.4 m / (E nu r) < 2 m / (E r (1 + nu)) (guards the n_i^2 weights)."""
+    c = 1.5 * R / math.sqrt(2.0)
+    s = _scene([[0, 0, 0], [c, c, 0]])
+    s.step(1)
+    m = _mass()
+    assert 0.4 * m / (E * NU * R) < 2.0 * m / (E * R * (1 + NU))
+    expected = 0.8 * math.sqrt(2.0) * math.sqrt(0.4 * m / (E * NU * R))
+    assert stiffness_dt(s, 0.8) == pytest.approx(expected, rel=1e-12)
+
+
+def test_stiffness_dt_without_contacts_is_pwave():
+    s = _scene([[0, 0, 0], [3.0 * R, 0, 0]])
+    s.step(1)
+    assert stiffness_dt(s, 0.7) == pytest.approx(0.7 * R * math.sqrt(RHO / E), rel=1e-15)
+
+
+def test_timestepper_sets_dt_every_interval():
+    """The timestepper acts before steps 0, interval, 2 interval, ...: before
+    the first step there is no contact (P-wave value); afterwards the
+    contact value."""
+    s = _scene([[0, 0, 0], [1.5 * R, 0, 0]])
+    run_with_timestepper(s, 1, safety=0.8, interval=3)
+    assert s.dt == pytest.approx(0.8 * R * math.sqrt(RHO / E), rel=1e-15)
+    run_with_timestepper(s, 3, safety=0.8, interval=3)
+    assert s.dt == pytest.approx(0.8 * math.sqrt(2.0) * math.sqrt(_mass() / (E * R)), rel=1e-12)
+
+
+# ------------------------------------------------- stress-controlled cell
+
+def _lattice(delta_frac=0.01, k=3):
+    """Simple cubic lattice, k^3 equal spheres, spacing a = 2r - delta, in a
+    periodic cube of side k a; every sphere touches its 6 neighbours with
+    overlap delta."""
+    delta = delta_frac * R
+    a = 2 * R - delta
+    g = np.arange(k) * a
+    pos = np.array([[x, y, z] for z in g for y in g for x in g]) + 0.5 * a
+    H = np.eye(3) * (k * a)
+    s = OracleScene(dt=1.0, periodic=True, hsize=H)
+    mat = s.add_material(RHO, E, NU, 0.5)
+    s.add_spheres(pos, [R] * len(pos), default_mat=mat)
+    s.set_dt(0.2 * s.pwave_dt())
+    return s, a, delta
+
+
+def test_lattice_stress_and_modulus_closed_form():
+    """At rest the lattice's stress is sigma_ii = -k_n delta / a^2 and the
+    normal springs' modulus M_i = k_n / a (k_n = E r): the first update's
+    rates are (1 - grow_damping)(goal - sigma)/(M T), T = 5 dt (guards the
+    rate law, the modulus and the update period)."""
+    s, a, delta = _lattice()
+    kn = E * R
+    sig = -kn * delta / a ** 2
+    goal = 2.0 * sig
+    c = PeriTriax(s, goal=(goal, goal, goal), stress_mask=7, glob_update=5, max_strain_rate=(1e3,) * 3)
+    c.run(5)
+    assert c.updates == 1
+    T = 5 * s.dt
+    for i in range(3):
+        assert c.stress[i] == pytest.approx(sig, rel=1e-9)
+        assert c.stiff[i] == pytest.approx(kn / a, rel=1e-9)
+        assert c.strain_rate[i] == pytest.approx(0.75 * (goal - sig) / ((kn / a) * T), rel=1e-9)
+        assert c.strain_rate[i] < 0.0   # more compression needed
+    h, _ = s.get_cell()
+    assert np.allclose(h, np.eye(3) * 3 * a, rtol=0, atol=0)   # nothing moved yet
+
+
+def test_rate_cap_and_strain_axis():
+    """The cap: a far goal runs at max_strain_rate.  A strain axis (bit
+    clear) gets (goal - strain)/T, the strain being log of the cell
+    transformation's diagonal (0 at start)."""
+    s, a, delta = _lattice()
+    kn = E * R
+    sig = -kn * delta / a ** 2
+    c = PeriTriax(s, goal=(100 * sig, 100 * sig, -1e-3), stress_mask=0b011, glob_update=5,
+                  max_strain_rate=(2.0, 3.0, 1e3))
+    c.run(5)
+    T = 5 * s.dt
+    assert c.strain_rate[0] == -2.0 and c.strain_rate[1] == -3.0
+    assert c.strain_rate[2] == pytest.approx(-1e-3 / T, rel=1e-12)
+    assert c.strain == [0.0, 0.0, 0.0]
+
+
+def test_controller_reaches_a_stress_goal_and_stops():
+    """Driven to a higher pressure the lattice ends within the tolerance,
+    with the cell stopped (zero velocity gradient) and the run cut short
+    (guards the sign of the correction: a wrong sign diverges)."""
+    s, a, delta = _lattice()
+    kn = E * R
+    goal = -1.5 * kn * delta / a ** 2
+    c = PeriTriax(s, goal=(goal,) * 3, stress_mask=7, glob_update=5, max_strain_rate=(1e3,) * 3,
+                  abs_stress_tol=1e-3 * abs(goal), max_unbalanced=1e-6)
+    steps = c.run(2000, stop_when_done=True)
+    assert c.done and steps < 2000
+    for i in range(3):
+        assert abs(c.stress[i] - goal) <= 1e-3 * abs(goal)
+        assert c.strain_rate[i] == 0.0
+        assert c.strain[i] < 0.0
+    s.step(3)
+    h0, _ = s.get_cell()
+    s.step(2)
+    assert np.array_equal(s.get_cell()[0], h0)
+
+
+def test_controller_done_at_once_when_at_goal():
+    s, a, delta = _lattice()
+    sig = -E * R * delta / a ** 2
+    c = PeriTriax(s, goal=(sig,) * 3, stress_mask=7, glob_update=5)
+    assert c.run(50, stop_when_done=True) == 5
+    assert c.done and c.updates == 1
+
+
+def test_modulus_of_a_diagonal_contact():
+    """One contact along (1, 1, 0)/sqrt2 at centre distance l: d_i n_i =
+    l n_i^2 = l/2 on x and y, 0 on z, so M = k_n l^2 / (4 V) on x and y
+    (guards the (d_i n_i)^2 weighting against d_i^2 or n_i^2 alone)."""
+    from oracle.controls import contact_modulus
+    c = 1.5 * R / math.sqrt(2.0)
+    L = 20 * R
+    s = _scene([[5 * R, 5 * R, 5 * R], [5 * R + c, 5 * R + c, 5 * R]], periodic=True, hsize=np.eye(3) * L)
+    s.step(1)
+    l = 1.5 * R
+    V = L ** 3
+    M = contact_modulus(s, V)
+    assert M[0] == pytest.approx(E * R * l * l / 4 / V, rel=1e-12)
+    assert M[1] == pytest.approx(E * R * l * l / 4 / V, rel=1e-12)
+    assert abs(M[2]) < 1e-20 * M[0]
