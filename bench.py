@@ -410,6 +410,7 @@ def periodic_leg(name="periodic_compression", steps=5000, n=None, log=None, prep
                                        "frac": ib / (kern["integrate"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
         out[name] = r
         log(f"{out['workload'][:30]} {name}: {r}")
+    out["controlled_cell"] = controlled_cell_run(H, spec, st, steps, log)
     stats = {}
     for prec, name in ((0, "fp64"), (1, "fp32_mixed")):
         g = _periodic_scene(H, L, spec, st["pos"], st["vel"], st["angvel"], prec, track_energy=True)
@@ -429,6 +430,46 @@ def periodic_leg(name="periodic_compression", steps=5000, n=None, log=None, prep
         "coordination_rel_max": float((np.abs(b[:, 5] - a[:, 5]) / np.maximum(a[:, 5], 1e-30)).max()),
         "windows": int(a.shape[0]), "window_steps": min(500, steps)}
     return out
+
+
+def controlled_cell_run(H, spec, st, steps, log=None):
+    """The stress-controlled cell on the prepared packing (FP64): goal an
+    isotropic stress of twice the packing's mean pressure, updates every 5
+    steps on the device; `steps` steps timed, then the same number without
+    the controller (zero velocity gradient) for the overhead."""
+    import numpy as np
+    import torch
+    from paper_2301_00611_amd.prepare import mean_pressure
+    res = {}
+    for on in (True, False):
+        g = _periodic_scene(H, np.zeros((3, 3)), spec, st["pos"], st["vel"], st["angvel"], 0)
+        g.step(1)
+        p0 = mean_pressure(g)
+        goal = -2.0 * max(p0, 1.0)
+        if on:
+            g.set_peri_triax((goal, goal, goal), 7, glob_update=5, max_strain_rate=(1.0, 1.0, 1.0), grow_damping=0.25)
+        s0 = g.stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        s1 = g.stats()
+        r = {"ms_per_step": el / steps * 1e3, "rebuilds": s1["rebuilds"] - s0["rebuilds"],
+             "value": (s1["contact_steps"] - s0["contact_steps"]) / el, "unit": "contact-steps/s"}
+        if on:
+            c = g.get_peri_triax()
+            r.update({"goal_pressure": -goal, "start_pressure": p0, "updates": c["updates"],
+                      "stress_end": c["stress"], "strain_end": c["strain"], "unbalanced_end": c["unbalanced"],
+                      "pressure_end": mean_pressure(g)})
+            res["controlled"] = r
+        else:
+            res["uncontrolled"] = r
+        g.close()
+    res["controller_overhead"] = res["controlled"]["ms_per_step"] / res["uncontrolled"]["ms_per_step"] - 1.0
+    if log:
+        log(f"controlled cell: {res}")
+    return res
 
 
 def _build_batch(spec, dt, precision=0):

@@ -106,8 +106,15 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
     const StepArgs& a = *args;
     // the previous step asked for a broad-phase run: this step does not run
     if (a.ctr->stall[parity ^ 1]) return;
-    // this step's flag starts clear; the integrate kernel may raise it
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctr->stall[parity] = 0;
+    // this step's flag starts clear; the integrate kernel may raise it.  The
+    // step ends an update period of the controlled cell when the iteration
+    // count after it is a multiple of the period (the later kernels of the
+    // step read the flag)
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.ctr->stall[parity] = 0;
+        const CtrlConfig& c = *a.ctrl;
+        a.ctr->measure = (c.active && (a.ctr->iter0 + a.ctr->steps_done + 1) % c.glob_update == 0) ? 1 : 0;
+    }
     const int k = logical_block(gridDim.x) * blockDim.x + threadIdx.x;
     ContactPartial part = {0.0, 0.0, 0ull, 0ull, 0.0};
     bool unstable = false;

@@ -127,12 +127,43 @@ struct History {
 struct Counters {
     int32_t stall[2];               // by step parity: a broad-phase run is needed before the next step
     int32_t steps_done;             // steps completed since the host last reset it (block 0 of integrate)
+    int32_t halt;                   // the controlled cell reached its goal: the launch chain stops
+    int64_t iter0;                  // the scene's iteration count when the host last reset steps_done
     int32_t nonfinite;              // a NaN/Inf position or velocity appeared
     int32_t unstable;               // an overlap exceeded a radius
-    int32_t pad_;
     double verlet_limit;            // per-body displacement budget (0.98 Delta L)
     double verlet_cell_step;        // mean-field share of the budget used per step (periodic)
+    int32_t measure;                // this step ends an update period of the controlled cell (set by contact)
+    int32_t pad_;
 };
+
+// The stress/strain-controlled periodic cell (PeriTriaxController driven by
+// the packing stiffness), run on the device after the steps that make the
+// iteration count a multiple of glob_update.
+struct CtrlConfig {
+    double goal[3];
+    int32_t stress_mask;
+    int32_t glob_update;
+    double max_rate[3];
+    double grow_damping;
+    double max_unbalanced;
+    double abs_tol;
+    double rel_tol;
+    int32_t stop_when_done;
+    int32_t active;
+};
+struct CtrlState {
+    double stress[3], strain[3], rate[3], stiff[3];
+    double unbalanced;
+    int64_t updates;
+    int32_t done;
+    int32_t pad_;
+};
+// The controlled cell's sums over contacts run in a fixed grid of
+// kCtrlGrid blocks (a grid-stride loop in a fixed order), so that their
+// partial sums stay few and a captured graph never depends on the pair
+// count; the sums over bodies come from the integrate kernel's own slots.
+constexpr int kCtrlGrid = 1024;
 
 // Per-block slots of the contact kernel: the last step's values and the
 // running sums since the host last folded them (fixed block order).
@@ -149,6 +180,8 @@ struct ContactAcc {
 struct IntAcc {
     double kin, rot;                // last step
     double grav, damp;              // cumulative
+    double fsum, fcnt;              // |resultant contact force| over dynamic spheres and their number,
+                                    // at the last step that ended an update period of the controlled cell
 };
 
 struct StepArgs {
@@ -168,6 +201,14 @@ struct StepArgs {
     ContactAcc* acc_contact;        // one slot per contact block
     IntAcc* acc_integrate;          // one slot per integrate block
     int32_t track_energy;
+    // stress/strain-controlled cell (periodic, unbatched): configuration,
+    // state, and the kCtrlGrid partial sums (kNetworkWords each) of its
+    // measuring kernel
+    const CtrlConfig* ctrl;
+    CtrlState* ctrl_state;
+    double* acc_ctrl;
+    int32_t nblocks_integrate;      // slots of acc_integrate written by the integrate kernel
+    int32_t pad2_;
 };
 
 // Global-memory view of a buffer pointer.  The step kernels load their
@@ -261,7 +302,15 @@ void launch_contact(const StepArgs* args, int parity, int grid, int precision, b
 // integrate.hip
 void launch_integrate(const StepArgs* args, int parity, int grid, int precision, bool batched, bool periodic,
                       int block, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// One block after the step: the periodic cell's update, then (when the
+// controlled cell is on and the step is one of its updates) the
+// controller, from the partial sums of the kernel below and of the
+// integrate kernel.
 void launch_cell_update(const StepArgs* args, int parity, hipStream_t st);
+// The controlled cell's sums over contacts (stress.hip), launched after
+// integrate on every step while the controller is on; it returns at once
+// except on update steps.
+void launch_ctrl_network(const StepArgs* args, int parity, int precision, hipStream_t st);
 void launch_body_forces(const StepArgs& a, int precision, double* f3, double* t3, hipStream_t st);
 // Sums over the last step's real contacts, kNetworkWords doubles per block
 // (stress.hip): Love-Weber stress (9), modulus of the normal springs per

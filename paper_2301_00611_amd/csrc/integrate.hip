@@ -102,7 +102,7 @@ __device__ inline void matvec(const double* M, double x, double y, double z, dou
 }
 
 struct IntPartial {
-    double kin, rot, grav, damp;
+    double kin, rot, grav, damp, fsum, fcnt;
 };
 
 template <int PREC, bool BATCHED, bool PERIODIC>
@@ -115,7 +115,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restr
         return;
     }
     const int i = logical_block(gridDim.x) * blockDim.x + threadIdx.x;
-    IntPartial part = {0.0, 0.0, 0.0, 0.0};
+    // this step ends an update period of the controlled cell: also sum the
+    // dynamic spheres' |resultant contact force| (unbalanced force)
+    const bool measure = a.ctr->measure != 0;
+    IntPartial part = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     bool bad = false;
     bool over = false;
     if (i < a.nslots) {
@@ -136,6 +139,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restr
         const unsigned blocked = glb<const uint8_t>(a.bod.blocked)[i];
         double F[3], T[3];
         body_sum<PREC>(a, beg, end, r, F, T);
+        if (measure && blocked != 63u) {
+            part.fsum = sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]);
+            part.fcnt = 1.0;
+        }
 
         const double x0[3] = {xr0.x, xr0.y, xr0.z};
         const double v0[3] = {vm0.x, vm0.y, vm0.z};
@@ -224,72 +231,177 @@ __global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restr
     if (__any(over) && (threadIdx.x & 63) == 0) a.ctr->stall[parity] = 1;
     if (__any(bad) && (threadIdx.x & 63) == 0) a.ctr->nonfinite = 1;
     if (blockIdx.x == 0 && threadIdx.x == 0) a.ctr->steps_done += 1;
-    if (!a.track_energy) return;
+    const bool energy = a.track_energy != 0;
+    if (!energy && !measure) return;
 
-    // ---- energies into this block's slot (fixed-order wave/block sums)
+    // ---- energies and the controlled cell's force sums into this block's
+    // slot (fixed-order wave/block sums)
     __shared__ IntPartial s_p[kMaxBlock / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     for (int off = 32; off > 0; off >>= 1) {
-        part.kin += __shfl_down(part.kin, off, 64);
-        part.rot += __shfl_down(part.rot, off, 64);
-        part.grav += __shfl_down(part.grav, off, 64);
-        part.damp += __shfl_down(part.damp, off, 64);
+        if (energy) {
+            part.kin += __shfl_down(part.kin, off, 64);
+            part.rot += __shfl_down(part.rot, off, 64);
+            part.grav += __shfl_down(part.grav, off, 64);
+            part.damp += __shfl_down(part.damp, off, 64);
+        }
+        if (measure) {
+            part.fsum += __shfl_down(part.fsum, off, 64);
+            part.fcnt += __shfl_down(part.fcnt, off, 64);
+        }
     }
     if (lane == 0) s_p[wave] = part;
     __syncthreads();
     if (threadIdx.x == 0) {
-        IntPartial p = {0.0, 0.0, 0.0, 0.0};
+        IntPartial p = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         for (int w = 0; w < nwaves; ++w) {
             p.kin += s_p[w].kin;
             p.rot += s_p[w].rot;
             p.grav += s_p[w].grav;
             p.damp += s_p[w].damp;
+            p.fsum += s_p[w].fsum;
+            p.fcnt += s_p[w].fcnt;
         }
         IntAcc& acc = a.acc_integrate[blockIdx.x];
-        acc.kin = p.kin;
-        acc.rot = p.rot;
-        acc.grav += p.grav;
-        acc.damp += p.damp;
+        if (energy) {
+            acc.kin = p.kin;
+            acc.rot = p.rot;
+            acc.grav += p.grav;
+            acc.damp += p.damp;
+        }
+        if (measure) {
+            acc.fsum = p.fsum;
+            acc.fcnt = p.fcnt;
+        }
     }
 }
 
 // Periodic cell (section 2.1.6), once per step after the bodies: H+ =
 // (I + L dt) H and the same for trsf; H - H_prev is kept for the image
-// velocity of the next step's contacts; L becomes L_prev.
-__global__ void k_cell_update(StepArgs* args, int parity)
+// velocity of the next step's contacts; L becomes L_prev.  Then, on the
+// steps that end an update period of the controlled cell, the controller
+// (PeriTriaxController driven by the packing stiffness) sets the velocity
+// gradient of the next steps from the partial sums of the contact sums
+// kernel (stress.hip) and of the integrate kernel's slots: per stress axis (1 - grow_damping)(goal - sigma_ii)/(M_i T),
+// M_i = (1/V) sum k_n (d_i n_i)^2 and T = glob_update dt (the full rate
+// towards the goal's sign while M_i = 0), per strain axis
+// (goal - log trsf_ii)/T, capped at max_rate; zero once the goal is reached
+// (every stress axis within max(abs_tol, rel_tol |goal|), every strain axis
+// within 1e-6, unbalanced force at most max_unbalanced), and with
+// stop_when_done the launch chain halts.  One block; the partial sums are
+// combined in a fixed order (a fixed range per thread, then a fixed tree).
+constexpr int kCellBlock = 256;
+
+__global__ void __launch_bounds__(kCellBlock) k_cell_update(StepArgs* args, int parity)
 {
     const StepArgs& a = *args;
-    if (a.ctr->stall[parity ^ 1] || threadIdx.x != 0) return;
+    if (a.ctr->stall[parity ^ 1]) return;
     SceneParams* S = &a.scenes[0];
-    const double dt = S->dt;
-    double M[9], Hn[9], Tn[9];
-    for (int k = 0; k < 9; ++k) M[k] = ((k % 4 == 0) ? 1.0 : 0.0) + S->L[k] * dt;
-    for (int r = 0; r < 3; ++r)
-        for (int q = 0; q < 3; ++q) {
-            Hn[3 * r + q] = (M[3 * r + 0] * S->H[q] + M[3 * r + 1] * S->H[3 + q]) + M[3 * r + 2] * S->H[6 + q];
-            Tn[3 * r + q] = (M[3 * r + 0] * S->trsf[q] + M[3 * r + 1] * S->trsf[3 + q]) + M[3 * r + 2] * S->trsf[6 + q];
+    if (threadIdx.x == 0) {
+        const double dt = S->dt;
+        double M[9], Hn[9], Tn[9];
+        for (int k = 0; k < 9; ++k) M[k] = ((k % 4 == 0) ? 1.0 : 0.0) + S->L[k] * dt;
+        for (int r = 0; r < 3; ++r)
+            for (int q = 0; q < 3; ++q) {
+                Hn[3 * r + q] = (M[3 * r + 0] * S->H[q] + M[3 * r + 1] * S->H[3 + q]) + M[3 * r + 2] * S->H[6 + q];
+                Tn[3 * r + q] =
+                    (M[3 * r + 0] * S->trsf[q] + M[3 * r + 1] * S->trsf[3 + q]) + M[3 * r + 2] * S->trsf[6 + q];
+            }
+        for (int k = 0; k < 9; ++k) {
+            S->dH[k] = Hn[k] - S->H[k];
+            S->H[k] = Hn[k];
+            S->trsf[k] = Tn[k];
+            S->Lprev[k] = S->L[k];
         }
-    for (int k = 0; k < 9; ++k) {
-        S->dH[k] = Hn[k] - S->H[k];
-        S->H[k] = Hn[k];
-        S->trsf[k] = Tn[k];
-        S->Lprev[k] = S->L[k];
+        const double* A = S->H;
+        const double a0 = A[0], a1 = A[1], a2 = A[2], a3 = A[3], a4 = A[4], a5 = A[5], a6 = A[6], a7 = A[7],
+                     a8 = A[8];
+        const double C0 = a4 * a8 - a5 * a7, C1 = -(a3 * a8 - a5 * a6), C2 = a3 * a7 - a4 * a6;
+        const double det = a0 * C0 + a1 * C1 + a2 * C2;
+        S->Hinv[0] = C0 / det;
+        S->Hinv[1] = -(a1 * a8 - a2 * a7) / det;
+        S->Hinv[2] = (a1 * a5 - a2 * a4) / det;
+        S->Hinv[3] = C1 / det;
+        S->Hinv[4] = (a0 * a8 - a2 * a6) / det;
+        S->Hinv[5] = -(a0 * a5 - a2 * a3) / det;
+        S->Hinv[6] = C2 / det;
+        S->Hinv[7] = -(a0 * a7 - a1 * a6) / det;
+        S->Hinv[8] = (a0 * a4 - a1 * a3) / det;
     }
-    const double* A = S->H;
-    const double a0 = A[0], a1 = A[1], a2 = A[2], a3 = A[3], a4 = A[4], a5 = A[5], a6 = A[6], a7 = A[7], a8 = A[8];
-    const double C0 = a4 * a8 - a5 * a7, C1 = -(a3 * a8 - a5 * a6), C2 = a3 * a7 - a4 * a6;
-    const double det = a0 * C0 + a1 * C1 + a2 * C2;
-    S->Hinv[0] = C0 / det;
-    S->Hinv[1] = -(a1 * a8 - a2 * a7) / det;
-    S->Hinv[2] = (a1 * a5 - a2 * a4) / det;
-    S->Hinv[3] = C1 / det;
-    S->Hinv[4] = (a0 * a8 - a2 * a6) / det;
-    S->Hinv[5] = -(a0 * a5 - a2 * a3) / det;
-    S->Hinv[6] = C2 / det;
-    S->Hinv[7] = -(a0 * a7 - a1 * a6) / det;
-    S->Hinv[8] = (a0 * a4 - a1 * a3) / det;
+    const CtrlConfig& c = *a.ctrl;
+    if (c.active && a.ctr->measure) {
+        // fixed-order sum of the partials: thread t takes the blocks t,
+        // t + blockDim, ... in order; then a fixed pairwise tree over threads
+        constexpr int W = kNetworkWords + 2;
+        double t[W];
+        for (int q = 0; q < W; ++q) t[q] = 0.0;
+        const double* pn = a.acc_ctrl;
+        for (int b = threadIdx.x; b < kCtrlGrid; b += blockDim.x)
+            for (int q = 0; q < kNetworkWords; ++q) t[q] += pn[(size_t)kNetworkWords * b + q];
+        for (int b = threadIdx.x; b < a.nblocks_integrate; b += blockDim.x) {
+            t[kNetworkWords] += a.acc_integrate[b].fsum;
+            t[kNetworkWords + 1] += a.acc_integrate[b].fcnt;
+        }
+        __shared__ double sh[kCellBlock][W];
+        for (int q = 0; q < W; ++q) sh[threadIdx.x][q] = t[q];
+        __syncthreads();
+        for (int half = kCellBlock / 2; half > 0; half >>= 1) {
+            if ((int)threadIdx.x < half)
+                for (int q = 0; q < W; ++q) sh[threadIdx.x][q] += sh[threadIdx.x + half][q];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const double* sum = sh[0];
+            CtrlState& st = *a.ctrl_state;
+            const double* H = S->H;
+            const double V = fabs(H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
+                                  H[2] * (H[3] * H[7] - H[4] * H[6]));
+            const double T = (double)c.glob_update * S->dt;
+            double rates[3];
+            bool reached = true;
+            for (int i = 0; i < 3; ++i) {
+                st.stress[i] = sum[4 * i] / V;
+                st.strain[i] = log(S->trsf[4 * i]);
+                st.stiff[i] = sum[9 + i] / V;
+                double rate;
+                if (c.stress_mask & (1 << i)) {
+                    const double err = c.goal[i] - st.stress[i];
+                    if (st.stiff[i] > 0.0)
+                        rate = (1.0 - c.grow_damping) * err / (st.stiff[i] * T);
+                    else
+                        rate = err != 0.0 ? copysign(c.max_rate[i], err) : 0.0;
+                    if (fabs(err) > fmax(c.abs_tol, c.rel_tol * fabs(c.goal[i]))) reached = false;
+                } else {
+                    const double err = c.goal[i] - st.strain[i];
+                    rate = err / T;
+                    if (fabs(err) > 1e-6) reached = false;
+                }
+                rates[i] = fmax(-c.max_rate[i], fmin(c.max_rate[i], rate));
+            }
+            const double ncont = sum[13], ndyn = sum[kNetworkWords + 1];
+            st.unbalanced = (ncont > 0.0 && ndyn > 0.0) ? (sum[kNetworkWords] / ndyn) / (sum[12] / ncont) : NAN;
+            if (!(st.unbalanced <= c.max_unbalanced)) reached = false;
+            st.done = reached ? 1 : 0;
+            if (reached) rates[0] = rates[1] = rates[2] = 0.0;
+            double lf = 0.0;
+            for (int k = 0; k < 9; ++k) S->L[k] = 0.0;
+            for (int i = 0; i < 3; ++i) {
+                st.rate[i] = rates[i];
+                S->L[4 * i] = rates[i];
+                lf += rates[i] * rates[i];
+            }
+            st.updates += 1;
+            // the mean field's share of the Verlet budget follows the new gradient
+            S->verlet_cell_rate = 0.5 * sqrt(lf) * (2.0 * S->rmax + 4.0 * S->verlet);
+            a.ctr->verlet_cell_step = S->verlet_cell_rate * S->dt;
+            if (reached && c.stop_when_done) {
+                a.ctr->halt = 1;
+                a.ctr->stall[parity] = 1;  // the remaining steps of the chain do not run
+            }
+        }
+    }
     // the step kernels of an unbatched scene read the descriptor's copy
-    args->scene0 = *S;
+    if (threadIdx.x == 0) args->scene0 = *S;
 }
 
 // Resultant force/torque per slot (for reporting), same sum as the step.
@@ -414,8 +526,9 @@ void launch_integrate(const StepArgs* args, int parity, int grid, int precision,
 
 void launch_cell_update(const StepArgs* args, int parity, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cell_update, dim3(1), dim3(64), 0, st, const_cast<StepArgs*>(args), parity);
+    hipLaunchKernelGGL(k_cell_update, dim3(1), dim3(kCellBlock), 0, st, const_cast<StepArgs*>(args), parity);
 }
+
 
 int body_blocks(int nslots) { return nslots > 0 ? (nslots + kMeasureBlock - 1) / kMeasureBlock : 0; }
 

@@ -228,6 +228,7 @@ struct World {
     DBuf slot_of_id, keys, vals, keys_alt, vals_alt, cell_start, cell_end, counts, row_start;
     DBuf ent_slot, ent_pid, ent_cell, ent_own, own_scan, rows_ent, scan_tmp, radix_tmp;
     DBuf d_scenes, d_walls, d_mats, d_tanphi, d_ctr, d_part_c, d_part_i, d_bounds, d_total, d_tmp3, d_args;
+    DBuf d_ctrl_cfg, d_ctrl_state, d_acc_ctrl;  // the controlled cell (device-resident)
     int grid_c = 1, grid_i = 1;        // step-kernel grids (contact sized with headroom)
     int acc_c_n = 0, acc_i_n = 0;      // slots currently in use in d_part_c / d_part_i
     int next_parity = 0;               // parity of the next step (stall flags alternate)
@@ -241,6 +242,13 @@ struct World {
     bool slots_fresh = true;           // no step has written the slots since the last fold
     std::vector<SceneParams> sp;       // host copy of the scene table
     Counters* h_ctr = nullptr;         // pinned
+    // pinned: what the host writes into the counters before a launch chain
+    // (steps_done = 0, halt = 0, iter0), the 16 bytes from steps_done on
+    struct ChunkStart {
+        int32_t steps_done, halt;
+        int64_t iter0;
+    };
+    ChunkStart* h_chunk = nullptr;
     int ncells = 0;
     int morton_bits = 1, scene_bits = 0;
     int64_t rebuilds = 0;
@@ -278,10 +286,12 @@ struct World {
         for (DBuf* d : {&slot_of_id, &keys, &vals, &keys_alt, &vals_alt, &cell_start, &cell_end, &counts, &row_start,
                         &ent_slot, &ent_pid, &ent_cell, &ent_own, &own_scan, &rows_ent, &scan_tmp, &radix_tmp,
                         &d_scenes, &d_walls, &d_mats, &d_tanphi, &d_ctr, &d_part_c, &d_part_i, &d_bounds, &d_total,
-                        &d_tmp3, &d_args})
+                        &d_tmp3, &d_args, &d_ctrl_cfg, &d_ctrl_state, &d_acc_ctrl})
             d->release();
         if (h_ctr) (void)hipHostFree(h_ctr);
         h_ctr = nullptr;
+        if (h_chunk) (void)hipHostFree(h_chunk);
+        h_chunk = nullptr;
         if (own_stream && stream) (void)hipStreamDestroy(stream);
         stream = nullptr;
     }
@@ -317,6 +327,15 @@ struct World {
         std::memset(h_ctr, 0, sizeof(Counters));
         d_ctr.ensure(sizeof(Counters));
         HIPC(hipMemsetAsync(d_ctr.p, 0, sizeof(Counters), stream));
+        static_assert(offsetof(Counters, halt) == offsetof(Counters, steps_done) + 4 &&
+                          offsetof(Counters, iter0) == offsetof(Counters, steps_done) + 8,
+                      "the chunk-start fields are contiguous");
+        HIPC(hipHostMalloc(reinterpret_cast<void**>(&h_chunk), sizeof(ChunkStart), hipHostMallocDefault));
+        std::memset(h_chunk, 0, sizeof(ChunkStart));
+        d_ctrl_cfg.ensure(sizeof(CtrlConfig));
+        d_ctrl_state.ensure(sizeof(CtrlState));
+        HIPC(hipMemsetAsync(d_ctrl_cfg.p, 0, sizeof(CtrlConfig), stream));
+        HIPC(hipMemsetAsync(d_ctrl_state.p, 0, sizeof(CtrlState), stream));
         sp.resize(nsc);
         for (int i = 0; i < nsc; ++i) {
             SceneParams& s = sp[i];
@@ -604,6 +623,7 @@ struct World {
         // the descriptor carries a copy of scene 0's parameters, which the
         // device advances for a periodic cell: start from the current ones
         if (periodic && d_scenes.p) pull_scene_table();
+        d_acc_ctrl.ensure(sizeof(double) * (size_t)kNetworkWords * kCtrlGrid);
         const StepArgs a = step_args();
         d_args.ensure(sizeof(StepArgs));
         HIPC(hipMemcpyAsync(d_args.p, &a, sizeof(StepArgs), hipMemcpyHostToDevice, stream));
@@ -853,6 +873,8 @@ struct World {
         C.verlet_cell_step = cell_step;
         C.stall[0] = C.stall[1] = 0;
         C.steps_done = 0;
+        C.halt = 0;
+        C.iter0 = scenes[0].iter;
         C.nonfinite = 0;  // positions are finite (checked above); an earlier
         C.unstable = 0;   // failure was repaired with dem_set_state
         next_parity = 0;
@@ -1106,6 +1128,10 @@ struct World {
         a.acc_contact = d_part_c.as<ContactAcc>();
         a.acc_integrate = d_part_i.as<IntAcc>();
         a.track_energy = track_energy ? 1 : 0;
+        a.ctrl = d_ctrl_cfg.as<CtrlConfig>();
+        a.ctrl_state = d_ctrl_state.as<CtrlState>();
+        a.acc_ctrl = d_acc_ctrl.as<double>();
+        a.nblocks_integrate = grid_i;
         return a;
     }
 
@@ -1118,14 +1144,15 @@ struct World {
                        ev ? ev[1] : nullptr);
         launch_integrate(a, parity, grid_i, precision, batched(), periodic, block_integrate, stream,
                          ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
+        if (periodic && pt_active) launch_ctrl_network(a, parity, precision, stream);
         if (periodic) launch_cell_update(a, parity, stream);
     }
 
     std::string graph_key(int n) const
     {
         char buf[256];
-        std::snprintf(buf, sizeof buf, "%p/%d/%d/%d/%d/%d/%d", d_args.p, grid_c, grid_i, n, timing ? 1 : 0,
-                      block_contact, block_integrate);
+        std::snprintf(buf, sizeof buf, "%p/%d/%d/%d/%d/%d/%d/%d", d_args.p, grid_c, grid_i, n, timing ? 1 : 0,
+                      block_contact, block_integrate, pt_active ? 1 : 0);
         return buf;
     }
 
@@ -1162,37 +1189,34 @@ struct World {
         }
     }
 
-    // O.step x nsteps.  With the stiffness timestepper or the stress-
-    // controlled cell active, the steps run in segments that end where one
-    // of them acts: the timestepper before a step whose iteration count is a
-    // multiple of its interval, the controller after a step that makes the
-    // count a multiple of glob_update.
+    // O.step x nsteps.  With the stiffness timestepper active the steps run
+    // in segments, and the timestepper sets dt before each step whose
+    // iteration count is a multiple of its interval.  The controlled cell
+    // runs on the device inside the steps; when it reaches its goal with
+    // stop_when_done the call returns early.
     void step(int64_t nsteps)
     {
         if (nsteps < 0) fail(DEM_EINVAL, "dem_step: nsteps < 0");
         HIPC(hipSetDevice(device));
         if (timing) timers.clear();
-        if (ts_interval <= 0 && !pt_active) {
+        if (ts_interval <= 0) {
             run_steps(nsteps);
             return;
         }
         HostScene& S = scenes[0];
         int64_t left = nsteps;
         while (left > 0) {
-            if (ts_interval > 0 && S.iter % ts_interval == 0) set_dt(0, stiffness_dt(0, ts_safety));
-            int64_t seg = left;
-            if (ts_interval > 0) seg = std::min(seg, ts_interval - S.iter % ts_interval);
-            if (pt_active) seg = std::min<int64_t>(seg, pt_cfg.glob_update - S.iter % pt_cfg.glob_update);
-            run_steps(seg);
-            left -= seg;
-            if (pt_active && S.iter % pt_cfg.glob_update == 0) {
-                peri_triax_update();
-                if (pt_st.done && pt_cfg.stop_when_done) break;
-            }
+            if (S.iter % ts_interval == 0) set_dt(0, stiffness_dt(0, ts_safety));
+            const int64_t seg = std::min(left, ts_interval - S.iter % ts_interval);
+            const int64_t before = S.iter;
+            const bool halted = run_steps(seg);
+            left -= S.iter - before;
+            if (halted) break;
         }
     }
 
-    void run_steps(int64_t nsteps)
+    // Returns true when the controlled cell halted the steps.
+    bool run_steps(int64_t nsteps)
     {
         if (host_dirty) upload_bodies();
         if (nslots == 0 && walls.empty()) {
@@ -1200,8 +1224,9 @@ struct World {
                 S.iter += nsteps;
                 S.time += nsteps * S.p.dt;
             }
-            return;
+            return false;
         }
+        bool halted = false;
         int64_t remaining = nsteps;
         std::vector<hipEvent_t> direct_ev;
         hipEvent_t rb0 = nullptr, rb1 = nullptr;
@@ -1221,7 +1246,11 @@ struct World {
                     }
                 }
                 h_ctr->steps_done = 0;
-                HIPC(hipMemsetAsync(reinterpret_cast<char*>(d_ctr.p) + offsetof(Counters, steps_done), 0, 4, stream));
+                h_chunk->steps_done = 0;
+                h_chunk->halt = 0;
+                h_chunk->iter0 = scenes[0].iter;
+                HIPC(hipMemcpyAsync(reinterpret_cast<char*>(d_ctr.p) + offsetof(Counters, steps_done), h_chunk,
+                                    sizeof(ChunkStart), hipMemcpyHostToDevice, stream));
                 // graphs hold an even number of steps starting at parity 0
                 const int n = (int)std::min<int64_t>(remaining, chunk);
                 GraphEntry* ge = nullptr;
@@ -1261,6 +1290,14 @@ struct World {
                 const bool stalled = h_ctr->stall[next_parity ^ 1] != 0;
                 if (done == 0 && !stalled) fail(DEM_EDEVICE, "no step completed");
                 if (done < n && !stalled) fail(DEM_EDEVICE, "steps stopped without a broad-phase request");
+                if (h_ctr->halt) {
+                    // the controlled cell reached its goal; the stall flags it
+                    // raised (with any broad-phase request of the same step)
+                    // are cleared by the broad-phase run the next call starts with
+                    halted = true;
+                    need_rebuild = true;
+                    break;
+                }
             }
         } catch (...) {
             for (auto e : direct_ev) (void)hipEventDestroy(e);
@@ -1271,6 +1308,7 @@ struct World {
         for (auto e : direct_ev) (void)hipEventDestroy(e);
         if (rb0) (void)hipEventDestroy(rb0);
         if (rb1) (void)hipEventDestroy(rb1);
+        return halted;
     }
 
     // ------------------------------------------------------- read-back
@@ -1605,51 +1643,56 @@ struct World {
     double ts_safety = 0.8;
     int64_t ts_interval = 0;
     bool pt_active = false;
-    dem_peri_triax pt_cfg{};
-    dem_peri_triax_state pt_st{};
 
-    static double cell_volume(const double* H)
+    void set_peri_triax(const dem_peri_triax* c)
     {
-        return std::fabs(H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
-                         H[2] * (H[3] * H[7] - H[4] * H[6]));
-    }
-    void peri_triax_update()
-    {
-        const Measures m = measures(0);
-        pull_scene_table();
-        const SceneParams& P = sp[0];
-        const double V = cell_volume(P.H);
-        const double T = (double)pt_cfg.glob_update * P.dt;
-        double rates[3];
-        bool reached = true;
-        for (int i = 0; i < 3; ++i) {
-            pt_st.stress[i] = m.sigma[4 * i] / V;
-            pt_st.strain[i] = std::log(P.trsf[4 * i]);
-            pt_st.stiff[i] = m.modulus[i] / V;
-            double rate;
-            if (pt_cfg.stress_mask & (1 << i)) {
-                const double err = pt_cfg.goal[i] - pt_st.stress[i];
-                if (pt_st.stiff[i] > 0.0)
-                    rate = (1.0 - pt_cfg.grow_damping) * err / (pt_st.stiff[i] * T);
-                else
-                    rate = err != 0.0 ? std::copysign(pt_cfg.max_strain_rate[i], err) : 0.0;
-                if (std::fabs(err) > std::max(pt_cfg.abs_stress_tol, pt_cfg.rel_stress_tol * std::fabs(pt_cfg.goal[i])))
-                    reached = false;
-            } else {
-                const double err = pt_cfg.goal[i] - pt_st.strain[i];
-                rate = err / T;
-                if (std::fabs(err) > 1e-6) reached = false;
+        CtrlConfig k;
+        std::memset(&k, 0, sizeof k);
+        if (c) {
+            for (int i = 0; i < 3; ++i) {
+                k.goal[i] = c->goal[i];
+                k.max_rate[i] = c->max_strain_rate[i];
             }
-            rates[i] = std::max(-pt_cfg.max_strain_rate[i], std::min(pt_cfg.max_strain_rate[i], rate));
+            k.stress_mask = c->stress_mask;
+            k.glob_update = c->glob_update;
+            k.grow_damping = c->grow_damping;
+            k.max_unbalanced = c->max_unbalanced;
+            k.abs_tol = c->abs_stress_tol;
+            k.rel_tol = c->rel_stress_tol;
+            k.stop_when_done = c->stop_when_done;
+            k.active = 1;
+        } else {
+            k.glob_update = 1;
         }
-        pt_st.unbalanced = unbalanced_of(m, false);
-        if (!(pt_st.unbalanced <= pt_cfg.max_unbalanced)) reached = false;
-        pt_st.done = reached ? 1 : 0;
-        if (reached) rates[0] = rates[1] = rates[2] = 0.0;
-        for (int i = 0; i < 3; ++i) pt_st.strain_rate[i] = rates[i];
-        const double L[9] = {rates[0], 0.0, 0.0, 0.0, rates[1], 0.0, 0.0, 0.0, rates[2]};
-        set_velgrad(0, L);
-        pt_st.updates += 1;
+        HIPC(hipMemcpyAsync(d_ctrl_cfg.p, &k, sizeof k, hipMemcpyHostToDevice, stream));
+        if (c) {
+            CtrlState st;
+            std::memset(&st, 0, sizeof st);
+            st.unbalanced = NAN;
+            HIPC(hipMemcpyAsync(d_ctrl_state.p, &st, sizeof st, hipMemcpyHostToDevice, stream));
+        }
+        HIPC(hipStreamSynchronize(stream));
+        pt_active = c != nullptr;
+        if (d_args.p) upload_args();
+    }
+    dem_peri_triax_state peri_triax_state()
+    {
+        CtrlState st;
+        HIPC(hipMemcpyAsync(&st, d_ctrl_state.p, sizeof st, hipMemcpyDeviceToHost, stream));
+        HIPC(hipStreamSynchronize(stream));
+        dem_peri_triax_state o;
+        std::memset(&o, 0, sizeof o);
+        for (int i = 0; i < 3; ++i) {
+            o.stress[i] = st.stress[i];
+            o.strain[i] = st.strain[i];
+            o.strain_rate[i] = st.rate[i];
+            o.stiff[i] = st.stiff[i];
+        }
+        o.unbalanced = st.unbalanced;
+        o.updates = st.updates;
+        o.done = st.done;
+        o.active = pt_active ? 1 : 0;
+        return o;
     }
 
     void stress(int s, double volume, double* out9)
@@ -2334,8 +2377,7 @@ dem_status dem_set_peri_triax(dem_scene* s, const dem_peri_triax* c)
     return guarded([&] {
         dem::World* w = world_of(s);
         if (!c) {
-            w->pt_active = false;
-            w->pt_st.active = 0;
+            w->set_peri_triax(nullptr);
             return;
         }
         if (!w->scenes[s->s].p.periodic || w->scenes.size() > 1)
@@ -2350,11 +2392,7 @@ dem_status dem_set_peri_triax(dem_scene* s, const dem_peri_triax* c)
         }
         if (!(c->abs_stress_tol >= 0.0) || !(c->rel_stress_tol >= 0.0) || std::isnan(c->max_unbalanced))
             dem::fail(DEM_EINVAL, "dem_set_peri_triax: tolerances >= 0");
-        w->pt_cfg = *c;
-        w->pt_st = dem_peri_triax_state{};
-        w->pt_st.unbalanced = NAN;
-        w->pt_st.active = 1;
-        w->pt_active = true;
+        w->set_peri_triax(c);
     });
 }
 
@@ -2363,7 +2401,7 @@ dem_status dem_get_peri_triax(dem_scene* s, dem_peri_triax_state* out)
     return guarded([&] {
         dem::World* w = world_of(s);
         if (!out) dem::fail(DEM_EINVAL, "null output");
-        *out = w->pt_st;
+        *out = w->peri_triax_state();
     });
 }
 

@@ -52,45 +52,46 @@ __global__ void __launch_bounds__(kStressBlock) k_pair_forces(StepArgs a, double
     f3[3 * (size_t)k + 2] = F[2];
 }
 
-// Per-block sums over the real contacts of one scene (kNetworkWords
-// doubles): the Love-Weber stress sum (9, sphere-sphere contacts), the
-// normal springs' modulus sum k_n (d_i n_i)^2 per axis (3, sphere-sphere;
-// d = (r1 + r2 - pen) n is the centre distance vector), the sum of |F| and
-// the number of contacts (walls included; unbalanced force).
+// The terms of pair k for the sums over the real contacts of one scene
+// (kNetworkWords doubles): the Love-Weber stress (9, sphere-sphere
+// contacts), the normal springs' modulus k_n (d_i n_i)^2 per axis (3,
+// sphere-sphere; d = (r1 + r2 - pen) n is the centre distance vector), |F|
+// and 1 (walls included; unbalanced force).  Zero for a pair not touching.
 template <int PREC, bool BATCHED>
-__global__ void __launch_bounds__(kStressBlock) k_network(StepArgs a, int scene, double* __restrict__ part)
+__device__ inline void network_terms(const StepArgs& a, int k, int scene, double* s)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    double s[kNetworkWords];
     for (int q = 0; q < kNetworkWords; ++q) s[q] = 0.0;
     const Pairs& P = a.pr;
-    if (k < a.npairs && P.real[k]) {
-        const Bodies& B = a.bod;
-        const int sa = P.a[k], sb = P.b[k];
-        if (!BATCHED || (int)B.scene[sb] == scene) {
-            double F[3];
-            pair_force<PREC>(a, k, F);
-            s[12] = sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]);
-            s[13] = 1.0;
-            if (sa >= 0) {
-                const HistRec h = P.h[k];
-                const double n[3] = {h.nx, h.ny, h.nz};
-                const double fn[3] = {F[0] - h.fsx, F[1] - h.fsy, F[2] - h.fsz};
-                const double r1 = B.xr[sa].w, r2 = B.xr[sb].w;
-                const Material M1 = a.mats[B.mat[sa]], M2 = a.mats[B.mat[sb]];
-                const double k1 = M1.young * (2.0 * r1), k2 = M2.young * (2.0 * r2);
-                const double kn = k1 * k2 / (k1 + k2);
-                const double pen = sqrt(fn[0] * fn[0] + fn[1] * fn[1] + fn[2] * fn[2]) / kn;
-                const double lm = (r1 + r2) - pen;
-                for (int i = 0; i < 3; ++i)
-                    for (int j = 0; j < 3; ++j) s[3 * i + j] = F[i] * (-lm * n[j]);
-                for (int i = 0; i < 3; ++i) {
-                    const double dn = (lm * n[i]) * n[i];
-                    s[9 + i] = kn * dn * dn;
-                }
-            }
-        }
+    if (k >= a.npairs || !P.real[k]) return;
+    const Bodies& B = a.bod;
+    const int sa = P.a[k], sb = P.b[k];
+    if (BATCHED && (int)B.scene[sb] != scene) return;
+    double F[3];
+    pair_force<PREC>(a, k, F);
+    s[12] = sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]);
+    s[13] = 1.0;
+    if (sa < 0) return;
+    const HistRec h = P.h[k];
+    const double n[3] = {h.nx, h.ny, h.nz};
+    const double fn[3] = {F[0] - h.fsx, F[1] - h.fsy, F[2] - h.fsz};
+    const double r1 = B.xr[sa].w, r2 = B.xr[sb].w;
+    const Material M1 = a.mats[B.mat[sa]], M2 = a.mats[B.mat[sb]];
+    const double k1 = M1.young * (2.0 * r1), k2 = M2.young * (2.0 * r2);
+    const double kn = k1 * k2 / (k1 + k2);
+    const double pen = sqrt(fn[0] * fn[0] + fn[1] * fn[1] + fn[2] * fn[2]) / kn;
+    const double lm = (r1 + r2) - pen;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) s[3 * i + j] = F[i] * (-lm * n[j]);
+    for (int i = 0; i < 3; ++i) {
+        const double dn = (lm * n[i]) * n[i];
+        s[9 + i] = kn * dn * dn;
     }
+}
+
+// Block sum of kNetworkWords terms in a fixed order (waves, then the
+// block's waves in order), written to part[blockIdx.x].
+__device__ inline void block_store_terms(double* s, double* __restrict__ part)
+{
     __shared__ double sh[kStressBlock / 64][kNetworkWords];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int q = 0; q < kNetworkWords; ++q)
@@ -106,6 +107,34 @@ __global__ void __launch_bounds__(kStressBlock) k_network(StepArgs a, int scene,
         }
 }
 
+// On demand (reports): one scene's sums, one partial per block.
+template <int PREC, bool BATCHED>
+__global__ void __launch_bounds__(kStressBlock) k_network(StepArgs a, int scene, double* __restrict__ part)
+{
+    double s[kNetworkWords];
+    network_terms<PREC, BATCHED>(a, blockIdx.x * blockDim.x + threadIdx.x, scene, s);
+    block_store_terms(s, part);
+}
+
+// In the step (controlled cell on): the same sums on the steps that end an
+// update period (flagged by the contact kernel), any other step returns at
+// once.  A fixed grid of kCtrlGrid blocks walks the pairs with a grid
+// stride, each thread in a fixed order, so the partials are few and the
+// captured graph does not depend on the pair count.
+template <int PREC>
+__global__ void __launch_bounds__(kStressBlock) k_ctrl_network(const StepArgs* __restrict__ args, int parity)
+{
+    const StepArgs& a = *args;
+    if (a.ctr->stall[parity ^ 1] || !a.ctr->measure) return;
+    double s[kNetworkWords], t[kNetworkWords];
+    for (int q = 0; q < kNetworkWords; ++q) s[q] = 0.0;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < a.npairs; k += gridDim.x * blockDim.x) {
+        network_terms<PREC, false>(a, k, 0, t);
+        for (int q = 0; q < kNetworkWords; ++q) s[q] += t[q];
+    }
+    block_store_terms(s, a.acc_ctrl);
+}
+
 }  // namespace
 
 void launch_pair_forces(const StepArgs& a, int precision, double* f3, hipStream_t st)
@@ -116,6 +145,14 @@ void launch_pair_forces(const StepArgs& a, int precision, double* f3, hipStream_
         hipLaunchKernelGGL(k_pair_forces<DEM_FP32_MIXED>, dim3(grid), dim3(kStressBlock), 0, st, a, f3);
     else
         hipLaunchKernelGGL(k_pair_forces<DEM_FP64>, dim3(grid), dim3(kStressBlock), 0, st, a, f3);
+}
+
+void launch_ctrl_network(const StepArgs* args, int parity, int precision, hipStream_t st)
+{
+    if (precision == DEM_FP32_MIXED)
+        hipLaunchKernelGGL(k_ctrl_network<DEM_FP32_MIXED>, dim3(kCtrlGrid), dim3(kStressBlock), 0, st, args, parity);
+    else
+        hipLaunchKernelGGL(k_ctrl_network<DEM_FP64>, dim3(kCtrlGrid), dim3(kStressBlock), 0, st, args, parity);
 }
 
 int stress_blocks(int npairs) { return npairs > 0 ? (npairs + kStressBlock - 1) / kStressBlock : 0; }

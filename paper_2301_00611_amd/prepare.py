@@ -1,11 +1,14 @@
-"""Preparation of dense periodic packings (the role PeriIsoCompressor plays
-in the documentation's periodic tutorials, section 3.1.x): a host-side
-controller that drives Cell.velGrad of a periodic scene from its
-Love-Weber stress until a target mean pressure is reached.
+"""Preparation of dense periodic packings (the role PeriIsoCompressor and
+PeriTriaxController play in the documentation's periodic tutorials).
 
-It only calls the C ABI (dem_set_velgrad, dem_step, dem_get_stress,
-dem_get_state, dem_set_state, dem_get_stats); every step runs in the HIP
-library.
+Two routes, both through the C ABI only (every step runs in the HIP
+library):
+  * compress_to_pressure: the library's stress-controlled cell
+    (dem_set_peri_triax) drives the cell to a target isotropic stress and
+    stops there;
+  * jam_isotropic: a host-side schedule of compressions, velocity resets
+    and relaxations (dem_set_velgrad, dem_step, dem_get_stress,
+    dem_set_state), which reaches a static jammed packing.
 """
 from __future__ import annotations
 
@@ -99,3 +102,42 @@ def jam_isotropic(scene, dt: float, solid_volume: float, target_pressure: float,
     return {"steps": steps, "cycles": cycles, "pressure": p, "coordination": st["coordination"],
             "solid_fraction": vs / abs(np.linalg.det(h)), "cell": h, "cell0": h0,
             "converged": p >= target_pressure, "seconds": time.perf_counter() - t0}
+
+
+def compress_to_pressure(scene, target_pressure: float, max_strain_rate: float = 30.0, grow_damping: float = 0.25,
+                         glob_update: int = 5, max_unbalanced: float = 0.05, stress_tol: float = 0.05,
+                         max_steps: int = 200_000, report_every: int = 2000, reset_fluctuations: bool = False,
+                         log=None) -> dict:
+    """Isotropic compression of a periodic scene by the stress-controlled
+    cell (PeriTriaxController): goal sigma_ii = -target_pressure on every
+    axis, reached when each is within stress_tol * target_pressure and the
+    unbalanced force is at most max_unbalanced; the cell then stops.  With
+    `reset_fluctuations`, the velocity fluctuations are reset (spheres follow the
+    cell's homogeneous field) every `report_every` steps, which lets a
+    loose packing settle into a static one sooner.  The controller is
+    switched off at the end.  Returns a record of the run."""
+    p = float(target_pressure)
+    scene.set_peri_triax((-p, -p, -p), 7, glob_update=glob_update, max_strain_rate=(max_strain_rate,) * 3,
+                         grow_damping=grow_damping, max_unbalanced=max_unbalanced, abs_stress_tol=stress_tol * p,
+                         rel_stress_tol=0.0, stop_when_done=1)
+    t0 = time.perf_counter()
+    it0 = scene.stats()["iter"]
+    st = scene.get_peri_triax()
+    while scene.stats()["iter"] - it0 < max_steps:
+        scene.step(min(report_every, max_steps - (scene.stats()["iter"] - it0)))
+        st = scene.get_peri_triax()
+        if log is not None:
+            log(f"controlled cell: step {scene.stats()['iter'] - it0}, stress {[round(x, 1) for x in st['stress']]}, "
+                f"unbalanced {st['unbalanced']:.3g}, strain {[round(x, 4) for x in st['strain']]}, "
+                f"Z {scene.stats()['coordination']:.3f}")
+        if st["done"]:
+            break
+        if reset_fluctuations:
+            r = st["strain_rate"]
+            quench(scene, np.diag(r))
+    scene.set_peri_triax(None)
+    stats = scene.stats()
+    return {"steps": stats["iter"] - it0, "converged": bool(st["done"]), "stress": st["stress"],
+            "strain": st["strain"], "unbalanced": st["unbalanced"], "updates": st["updates"],
+            "coordination": stats["coordination"], "seconds": time.perf_counter() - t0}
+
