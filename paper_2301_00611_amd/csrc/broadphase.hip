@@ -426,16 +426,16 @@ __global__ void __launch_bounds__(kBlock) k_pair_build(PairBuildArgs a)
             const uint32_t k = a.own_scan[e];
             if (slot < 0) {
                 // a wall pair: the wall is #1 and has no row
-                a.pr.a[k] = slot;
-                a.pr.b[k] = i;
+                a.ca[k] = slot;
+                a.cb[k] = i;
                 a.rows.ent[e] = k;
             } else {
-                a.pr.a[k] = i;
-                a.pr.b[k] = slot;
+                a.ca[k] = i;
+                a.cb[k] = slot;
                 a.rows.ent[e] = k | kNegSign;
             }
-            a.pr.cell[k] = a.ent_cell[e];
-            a.pr.pid[k] = a.ent_pid[e];
+            a.hist_new.cell[k] = a.ent_cell[e];
+            a.hist_new.pid[k] = a.ent_pid[e];
         } else {
             // the pair is owned by the partner: find this body in its row,
             // which is sorted by (partner id, packed image as unsigned)
@@ -461,28 +461,80 @@ __global__ void __launch_bounds__(kBlock) k_pair_build(PairBuildArgs a)
     a.hist_new.own_count[myid] = (int32_t)(a.own_scan[end] - a.own_scan[beg]);
 }
 
-__global__ void __launch_bounds__(kBlock) k_carry_over(PairBuildArgs a, int old_nbodies)
+// Per canonical pair: where its history sits in the previous list, and
+// whether that history says the pair touched (a carried normal is a unit
+// vector; a new pair starts with zero shear force and no normal).
+__global__ void __launch_bounds__(kBlock) k_carry_find(PairBuildArgs a, int old_nbodies)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.npairs) return;
-    const int32_t sa = a.pr.a[k], sb = a.pr.b[k];
+    if (k > a.npairs) return;
+    if (k == a.npairs) {
+        a.flag[k] = 0u;  // the scan's extra entry
+        return;
+    }
+    const int32_t sa = a.ca[k], sb = a.cb[k];
     const int32_t owner = sa >= 0 ? a.bod.id[sa] : a.bod.id[sb];
-    const int32_t partner = a.pr.pid[k];
-    const int32_t cell = a.pr.cell[k];
-    HistRec h = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const int32_t partner = a.hist_new.pid[k];
+    const int32_t cell = a.hist_new.cell[k];
+    int32_t found = -1;
     if (a.has_old && owner < old_nbodies) {
         const int lo = a.hist_old.own_begin[owner];
         const int cnt = a.hist_old.own_count[owner];
         for (int q = lo; q < lo + cnt; ++q) {
             if (a.hist_old.pid[q] == partner && a.hist_old.cell[q] == cell) {
-                h = a.hist_old.h[q];
+                found = a.hist_old.map[q];
                 break;
             }
         }
     }
-    a.pr.h[k] = h;
-    // a carried normal is a unit vector: the pair touched at its last evaluation
-    a.pr.real[k] = (h.nx != 0.0 || h.ny != 0.0 || h.nz != 0.0) ? 1 : 0;
+    bool touched = false;
+    if (found >= 0) {
+        const HistRec h = a.hist_old.h[found];
+        touched = h.nx != 0.0 || h.ny != 0.0 || h.nz != 0.0;
+    }
+    a.found[k] = found;
+    a.flag[k] = touched ? 1u : 0u;
+}
+
+// The stable partition, within each eighth [P_x, P_x+1) of the pairs
+// (P_x = x npairs / 8, the segment one XCD takes in the contact kernel):
+// touching pairs first, then the others, each group in canonical order; the
+// history moves with its pair, and the canonical -> final map is kept for
+// the next run.
+__device__ inline uint32_t segment_start(int x, int npairs) { return (uint32_t)(((int64_t)x * npairs) >> 3); }
+
+__global__ void __launch_bounds__(kBlock) k_partition(PairBuildArgs a)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.npairs) return;
+    int x = (int)(((int64_t)k * 8) / a.npairs);
+    if (x > 7) x = 7;
+    while (x < 7 && (uint32_t)k >= segment_start(x + 1, a.npairs)) ++x;
+    while (x > 0 && (uint32_t)k < segment_start(x, a.npairs)) --x;
+    const uint32_t p0 = segment_start(x, a.npairs), p1 = segment_start(x + 1, a.npairs);
+    const uint32_t s0 = a.flag_scan[p0];
+    const uint32_t ntouch = a.flag_scan[p1] - s0;
+    const uint32_t r = a.flag_scan[k] - s0;
+    const bool touched = a.flag[k] != 0u;
+    const uint32_t pos = p0 + (touched ? r : ntouch + (((uint32_t)k - p0) - r));
+    a.pr.a[pos] = a.ca[k];
+    a.pr.b[pos] = a.cb[k];
+    a.pr.cell[pos] = a.hist_new.cell[k];
+    a.pr.pid[pos] = a.hist_new.pid[k];
+    const int32_t f = a.found[k];
+    a.pr.h[pos] = f >= 0 ? a.hist_old.h[f] : HistRec{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    a.pr.real[pos] = touched ? 1 : 0;
+    a.hist_new.map[k] = (int32_t)pos;
+}
+
+// Row entries: canonical pair index -> partitioned index (the side bit kept).
+__global__ void __launch_bounds__(kBlock) k_remap_rows(PairBuildArgs a)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.nent) return;
+    const uint32_t u = a.rows.ent[e];
+    const uint32_t k = u & kPairMask;
+    if (k < (uint32_t)a.npairs) a.rows.ent[e] = (u & kNegSign) | (uint32_t)a.hist_new.map[k];
 }
 
 inline int nblocks(long n) { return (int)((n + kBlock - 1) / kBlock); }
@@ -572,10 +624,15 @@ void launch_pair_build(const PairBuildArgs& a, hipStream_t st)
     hipLaunchKernelGGL(k_pair_build, dim3(nblocks(a.nslots)), dim3(kBlock), 0, st, a);
 }
 
-void launch_carry_over(const PairBuildArgs& a, hipStream_t st, int old_nbodies)
+void launch_carry_find(const PairBuildArgs& a, hipStream_t st, int old_nbodies)
 {
-    if (a.npairs <= 0) return;
-    hipLaunchKernelGGL(k_carry_over, dim3(nblocks(a.npairs)), dim3(kBlock), 0, st, a, old_nbodies);
+    hipLaunchKernelGGL(k_carry_find, dim3(nblocks((long)a.npairs + 1)), dim3(kBlock), 0, st, a, old_nbodies);
+}
+
+void launch_partition(const PairBuildArgs& a, hipStream_t st)
+{
+    if (a.npairs > 0) hipLaunchKernelGGL(k_partition, dim3(nblocks(a.npairs)), dim3(kBlock), 0, st, a);
+    if (a.nent > 0) hipLaunchKernelGGL(k_remap_rows, dim3(nblocks(a.nent)), dim3(kBlock), 0, st, a);
 }
 
 }  // namespace dem

@@ -81,14 +81,18 @@ __device__ inline void unpack_cell(int32_t p, int* c)
     c[2] = (int)(u & 1023u) - 512;
 }
 
-__device__ inline int logical_block(int nb)
+// Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b & 7).  Each XCD takes one eighth of the pairs, a contiguous segment
+// [P_x, P_x+1) with P_x = x npairs / 8, so that neighbouring pairs share its
+// L2 and every XCD gets the same share whatever the grid's headroom (the
+// grid has at least ceil(ceil(npairs / 8) / blockDim) blocks per XCD).
+// Returns the pair of this thread, or -1.
+__device__ inline int xcd_pair(int npairs)
 {
-    // blocks are dispatched round-robin over the 8 XCDs; give each XCD a
-    // contiguous range of work so neighbouring pairs share its L2
-    const int b = blockIdx.x;
-    const int xcd = b & 7, idx = b >> 3;
-    const int q = nb >> 3, r = nb & 7;
-    return xcd * q + (xcd < r ? xcd : r) + idx;
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int64_t p0 = ((int64_t)xcd * npairs) >> 3, p1 = ((int64_t)(xcd + 1) * npairs) >> 3;
+    const int64_t k = p0 + (int64_t)j * blockDim.x + threadIdx.x;
+    return k < p1 ? (int)k : -1;
 }
 
 struct ContactPartial {
@@ -97,7 +101,14 @@ struct ContactPartial {
     double ov;
 };
 
-template <int PREC, bool BATCHED, bool PERIODIC>
+// MEASURE (periodic, unbatched; launched on the steps that end an update
+// period of the controlled cell only): the kernel also sums, per block, the
+// controller's contact terms: the Love-Weber stress (9, sphere pairs), the
+// normal springs' modulus k_n (d_i n_i)^2 (3, sphere pairs; d = l n the
+// centre distance vector) and |F| with a count (every touching pair), from
+// the force and normal as stored.  A separate instantiation, so that the
+// extra registers do not lower the occupancy of every other step.
+template <int PREC, bool BATCHED, bool PERIODIC, bool MEASURE = false>
 __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restrict__ args, int parity)
 {
     using R = typename std::conditional<PREC == DEM_FP32_MIXED, float, double>::type;
@@ -115,10 +126,12 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
         const CtrlConfig& c = *a.ctrl;
         a.ctr->measure = (c.active && (a.ctr->iter0 + a.ctr->steps_done + 1) % c.glob_update == 0) ? 1 : 0;
     }
-    const int k = logical_block(gridDim.x) * blockDim.x + threadIdx.x;
+    const int k = xcd_pair(a.npairs);
     ContactPartial part = {0.0, 0.0, 0ull, 0ull, 0.0};
     bool unstable = false;
-    if (k < a.npairs) {
+    double net[MEASURE ? kNetworkWords : 1];
+    for (int q = 0; q < (MEASURE ? kNetworkWords : 1); ++q) net[q] = 0.0;
+    if (k >= 0) {
         const gptr<const double4> xr = glb<const double4>(a.bod.xr);
         const gptr<const double4> vm = glb<const double4>(a.bod.vm);
         const gptr<const double4> wv = glb<const double4>(a.bod.w);
@@ -273,6 +286,21 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
             const double rmin = wall ? r2 : (r1 < r2 ? r1 : r2);
             unstable = pen > rmin;
             part.ov = pen / rmin;
+            if constexpr (MEASURE) {
+                const double f[3] = {(double)F.x, (double)F.y, (double)F.z};
+                const double nn[3] = {(double)n.x, (double)n.y, (double)n.z};
+                net[12] = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+                net[13] = 1.0;
+                if (!wall) {
+                    for (int i = 0; i < 3; ++i)
+                        for (int j = 0; j < 3; ++j) net[3 * i + j] = f[i] * (-l * nn[j]);
+                    const double knd = (double)kn;
+                    for (int i = 0; i < 3; ++i) {
+                        const double dn = (l * nn[i]) * nn[i];
+                        net[9 + i] = knd * dn * dn;
+                    }
+                }
+            }
         }
     }
 
@@ -321,23 +349,43 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
         acc.max_ov = ov;
         if (flags) a.ctr->unstable = 1;
     }
+    if constexpr (MEASURE) {
+        // the block's partial, one array per term (coalesced for the
+        // single-block reduction that follows the step)
+        __shared__ double s_net[kMaxBlock / 64][kNetworkWords];
+        for (int q = 0; q < kNetworkWords; ++q)
+            for (int off = 32; off > 0; off >>= 1) net[q] += __shfl_down(net[q], off, 64);
+        if (lane == 0)
+            for (int q = 0; q < kNetworkWords; ++q) s_net[wave][q] = net[q];
+        __syncthreads();
+        if (threadIdx.x < kNetworkWords) {
+            double t = 0.0;
+            for (int w = 0; w < nwaves; ++w) t += s_net[w][threadIdx.x];
+            a.acc_ctrl[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
+        }
+    }
 }
 
-template <int PREC, bool BATCHED, bool PERIODIC>
+template <int PREC, bool BATCHED, bool PERIODIC, bool MEASURE = false>
 void launch_t(const StepArgs* args, int parity, int grid, int block, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
     const dim3 g(grid > 0 ? grid : 1), b(block);
     if (ev0)
-        hipExtLaunchKernelGGL((k_contact<PREC, BATCHED, PERIODIC>), g, b, 0, st, ev0, ev1, 0, args, parity);
+        hipExtLaunchKernelGGL((k_contact<PREC, BATCHED, PERIODIC, MEASURE>), g, b, 0, st, ev0, ev1, 0, args, parity);
     else
-        hipLaunchKernelGGL((k_contact<PREC, BATCHED, PERIODIC>), g, b, 0, st, args, parity);
+        hipLaunchKernelGGL((k_contact<PREC, BATCHED, PERIODIC, MEASURE>), g, b, 0, st, args, parity);
 }
 
 }  // namespace
 
 void launch_contact(const StepArgs* args, int parity, int grid, int precision, bool batched, bool periodic,
-                    int block, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
+                    int block, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, bool measure)
 {
+    if (measure && periodic && !batched) {
+        if (precision == DEM_FP32_MIXED) launch_t<DEM_FP32_MIXED, false, true, true>(args, parity, grid, block, st, ev0, ev1);
+        else launch_t<DEM_FP64, false, true, true>(args, parity, grid, block, st, ev0, ev1);
+        return;
+    }
     if (precision == DEM_FP32_MIXED) {
         if (batched) launch_t<DEM_FP32_MIXED, true, false>(args, parity, grid, block, st, ev0, ev1);
         else if (periodic) launch_t<DEM_FP32_MIXED, false, true>(args, parity, grid, block, st, ev0, ev1);

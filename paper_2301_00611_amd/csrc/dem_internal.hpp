@@ -91,7 +91,10 @@ struct HistRec {
     double pad1_;
 };
 
-// Candidate pairs after a broad-phase run.
+// Candidate pairs after a broad-phase run, the pairs that touched at the
+// last evaluation first (a stable partition of the owner-sorted order), so
+// that the contact kernel's touching pairs, their history and force records
+// are dense in memory and its waves rarely mix the two paths.
 struct Pairs {
     int32_t *a;               // slot of #1, or -1 - wall index
     int32_t *b;               // slot of #2
@@ -112,13 +115,16 @@ struct Rows {
     uint32_t *ent;            // pair index | kNegSign when the body is #1
 };
 
-// History of the previous candidate list, keyed by ids.
+// History of the previous candidate list, keyed by ids: per owner id a
+// range of the owner-sorted ("canonical") order with each pair's partner id
+// and image, and where that pair sits in the partitioned arrays.
 struct History {
     int32_t *own_begin;       // by body id
     int32_t *own_count;
-    int32_t *pid;             // by pair: partner id
-    int32_t *cell;
-    const HistRec *h;
+    int32_t *pid;             // canonical: partner id
+    int32_t *cell;            // canonical: image
+    int32_t *map;             // canonical -> index of the pair in the partitioned arrays
+    const HistRec *h;         // partitioned order
 };
 
 // Device-side flags and counters (one struct in device memory).  The hot
@@ -159,11 +165,14 @@ struct CtrlState {
     int32_t done;
     int32_t pad_;
 };
-// The controlled cell's sums over contacts run in a fixed grid of
-// kCtrlGrid blocks (a grid-stride loop in a fixed order), so that their
-// partial sums stay few and a captured graph never depends on the pair
-// count; the sums over bodies come from the integrate kernel's own slots.
-constexpr int kCtrlGrid = 1024;
+// The controlled cell's sums come from the step kernels' own blocks on its
+// update steps: the contact kernel's measuring instantiation (kNetworkWords
+// per block in acc_ctrl, stored term-major: term q of block b at
+// q * nblocks_contact + b) and the integrate kernel's slots (IntAcc.fsum /
+// fcnt).  A first reduction level (kCtrlReduceGrid blocks, update steps
+// only) brings them to kCtrlReduceGrid partials in acc_ctrl2 for the
+// cell-update block.
+constexpr int kCtrlReduceGrid = 256;
 
 // Per-block slots of the contact kernel: the last step's values and the
 // running sums since the host last folded them (fixed block order).
@@ -202,13 +211,13 @@ struct StepArgs {
     IntAcc* acc_integrate;          // one slot per integrate block
     int32_t track_energy;
     // stress/strain-controlled cell (periodic, unbatched): configuration,
-    // state, and the kCtrlGrid partial sums (kNetworkWords each) of its
-    // measuring kernel
+    // state, and the contact kernel's per-block sums on update steps
     const CtrlConfig* ctrl;
     CtrlState* ctrl_state;
     double* acc_ctrl;
+    double* acc_ctrl2;              // kCtrlReduceGrid x (kNetworkWords + 2)
+    int32_t nblocks_contact;        // blocks of the contact kernel (its grid)
     int32_t nblocks_integrate;      // slots of acc_integrate written by the integrate kernel
-    int32_t pad2_;
 };
 
 // Global-memory view of a buffer pointer.  The step kernels load their
@@ -282,35 +291,45 @@ struct PairBuildArgs {
     const uint32_t* own_scan;  // exclusive scan of the owner flags
     const uint32_t* ent_own;
     Rows rows;
-    Pairs pr;
-    History hist_new;          // own ranges of the new list (by id)
+    Pairs pr;                  // the new list (partitioned order)
+    History hist_new;          // own ranges and canonical arrays of the new list
     History hist_old;          // previous list
+    int32_t* ca;               // canonical #1 / #2 slots (scratch)
+    int32_t* cb;
+    int32_t* found;            // canonical: index of the pair in the previous list's arrays, -1 if new
+    uint32_t* flag;            // canonical: 1 when the carried history says the pair touched (+1 entry, 0)
+    uint32_t* flag_scan;       // exclusive scan of flag; flag_scan[npairs] = number of touching pairs
     int32_t nslots;
     int32_t nent;
     int32_t npairs;
     int32_t has_old;
 };
+// canonical pair arrays and rows (pair_build), history lookup (carry_find),
+// then, after the host scans `flag`, the partition into the final arrays
+// and the rows' entries renumbered to it (partition)
 void launch_pair_build(const PairBuildArgs& a, hipStream_t st);
-void launch_carry_over(const PairBuildArgs& a, hipStream_t st, int old_nbodies);
+void launch_carry_find(const PairBuildArgs& a, hipStream_t st, int old_nbodies);
+void launch_partition(const PairBuildArgs& a, hipStream_t st);
 
 // contact.hip
 // ev0/ev1 (optional): events stamped at the kernel's own start and end
 // (hipExtLaunchKernelGGL), used by the timing mode.
+// measure: the step ends an update period of the controlled cell (periodic,
+// unbatched): the measuring instantiation runs (the host decides per step;
+// captured graphs are keyed by the period's phase at their first step)
 void launch_contact(const StepArgs* args, int parity, int grid, int precision, bool batched, bool periodic,
-                    int block, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                    int block, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                    bool measure = false);
 
 // integrate.hip
 void launch_integrate(const StepArgs* args, int parity, int grid, int precision, bool batched, bool periodic,
                       int block, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // One block after the step: the periodic cell's update, then (when the
 // controlled cell is on and the step is one of its updates) the
-// controller, from the partial sums of the kernel below and of the
-// integrate kernel.
+// controller, from the contact and integrate kernels' partial sums.
 void launch_cell_update(const StepArgs* args, int parity, hipStream_t st);
-// The controlled cell's sums over contacts (stress.hip), launched after
-// integrate on every step while the controller is on; it returns at once
-// except on update steps.
-void launch_ctrl_network(const StepArgs* args, int parity, int precision, hipStream_t st);
+// first reduction level of the controller's partial sums (update steps only)
+void launch_ctrl_reduce(const StepArgs* args, int parity, hipStream_t st);
 void launch_body_forces(const StepArgs& a, int precision, double* f3, double* t3, hipStream_t st);
 // Sums over the last step's real contacts, kNetworkWords doubles per block
 // (stress.hip): Love-Weber stress (9), modulus of the normal springs per

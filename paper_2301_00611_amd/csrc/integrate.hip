@@ -276,13 +276,51 @@ __global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restr
     }
 }
 
+// The controlled cell's first reduction level (update steps only): block g
+// of kCtrlReduceGrid sums, in a fixed order, a fixed contiguous share of the
+// contact kernel's per-block terms (term-major in acc_ctrl) and of the
+// integrate kernel's slots, into kCtrlWords values at acc_ctrl2[g].
+constexpr int kCtrlWords = kNetworkWords + 2;
+constexpr int kCtrlReduceBlock = 256;
+
+__global__ void __launch_bounds__(kCtrlReduceBlock) k_ctrl_reduce(const StepArgs* __restrict__ args, int parity)
+{
+    const StepArgs& a = *args;
+    if (a.ctr->stall[parity ^ 1] || !a.ctr->measure) return;
+    const int g = blockIdx.x, G = gridDim.x;
+    const int nb = a.nblocks_contact, ni = a.nblocks_integrate;
+    const int b0 = (int)(((int64_t)g * nb) / G), b1 = (int)(((int64_t)(g + 1) * nb) / G);
+    const int i0 = (int)(((int64_t)g * ni) / G), i1 = (int)(((int64_t)(g + 1) * ni) / G);
+    double t[kCtrlWords];
+    for (int q = 0; q < kCtrlWords; ++q) t[q] = 0.0;
+    for (int b = b0 + (int)threadIdx.x; b < b1; b += blockDim.x)
+        for (int q = 0; q < kNetworkWords; ++q) t[q] += a.acc_ctrl[(size_t)q * nb + b];
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += blockDim.x) {
+        t[kNetworkWords] += a.acc_integrate[i].fsum;
+        t[kNetworkWords + 1] += a.acc_integrate[i].fcnt;
+    }
+    __shared__ double sh[kCtrlReduceBlock / 64][kCtrlWords];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int q = 0; q < kCtrlWords; ++q)
+        for (int off = 32; off > 0; off >>= 1) t[q] += __shfl_down(t[q], off, 64);
+    if (lane == 0)
+        for (int q = 0; q < kCtrlWords; ++q) sh[wave][q] = t[q];
+    __syncthreads();
+    if (threadIdx.x < kCtrlWords) {
+        double v = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v += sh[w][threadIdx.x];
+        a.acc_ctrl2[(size_t)kCtrlWords * g + threadIdx.x] = v;
+    }
+}
+
 // Periodic cell (section 2.1.6), once per step after the bodies: H+ =
 // (I + L dt) H and the same for trsf; H - H_prev is kept for the image
 // velocity of the next step's contacts; L becomes L_prev.  Then, on the
 // steps that end an update period of the controlled cell, the controller
 // (PeriTriaxController driven by the packing stiffness) sets the velocity
-// gradient of the next steps from the partial sums of the contact sums
-// kernel (stress.hip) and of the integrate kernel's slots: per stress axis (1 - grow_damping)(goal - sigma_ii)/(M_i T),
+// gradient of the next steps from the partial sums of the contact kernel's
+// measuring instantiation and of the integrate kernel's slots (first reduced
+// by k_ctrl_reduce): per stress axis (1 - grow_damping)(goal - sigma_ii)/(M_i T),
 // M_i = (1/V) sum k_n (d_i n_i)^2 and T = glob_update dt (the full rate
 // towards the goal's sign while M_i = 0), per strain axis
 // (goal - log trsf_ii)/T, capped at max_rate; zero once the goal is reached
@@ -332,16 +370,11 @@ __global__ void __launch_bounds__(kCellBlock) k_cell_update(StepArgs* args, int 
     if (c.active && a.ctr->measure) {
         // fixed-order sum of the partials: thread t takes the blocks t,
         // t + blockDim, ... in order; then a fixed pairwise tree over threads
-        constexpr int W = kNetworkWords + 2;
+        constexpr int W = kCtrlWords;
         double t[W];
         for (int q = 0; q < W; ++q) t[q] = 0.0;
-        const double* pn = a.acc_ctrl;
-        for (int b = threadIdx.x; b < kCtrlGrid; b += blockDim.x)
-            for (int q = 0; q < kNetworkWords; ++q) t[q] += pn[(size_t)kNetworkWords * b + q];
-        for (int b = threadIdx.x; b < a.nblocks_integrate; b += blockDim.x) {
-            t[kNetworkWords] += a.acc_integrate[b].fsum;
-            t[kNetworkWords + 1] += a.acc_integrate[b].fcnt;
-        }
+        for (int g = threadIdx.x; g < kCtrlReduceGrid; g += blockDim.x)
+            for (int q = 0; q < W; ++q) t[q] += a.acc_ctrl2[(size_t)W * g + q];
         __shared__ double sh[kCellBlock][W];
         for (int q = 0; q < W; ++q) sh[threadIdx.x][q] = t[q];
         __syncthreads();
@@ -522,6 +555,11 @@ void launch_integrate(const StepArgs* args, int parity, int grid, int precision,
         else if (periodic) launch_t<DEM_FP64, false, true>(args, parity, grid, block, st, ev0, ev1);
         else launch_t<DEM_FP64, false, false>(args, parity, grid, block, st, ev0, ev1);
     }
+}
+
+void launch_ctrl_reduce(const StepArgs* args, int parity, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_ctrl_reduce, dim3(kCtrlReduceGrid), dim3(kCtrlReduceBlock), 0, st, args, parity);
 }
 
 void launch_cell_update(const StepArgs* args, int parity, hipStream_t st)

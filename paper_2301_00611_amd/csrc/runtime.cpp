@@ -116,13 +116,14 @@ struct BodySet {
 };
 
 struct PairSet {
-    DBuf a, b, cell, pid, real, hist, frec;
-    DBuf own_begin, own_count;  // by gid
+    DBuf a, b, cell, pid, real, hist, frec;     // partitioned order (touching pairs first)
+    DBuf hpid, hcell, hmap;                     // canonical (owner-sorted) order, for the next run's lookup
+    DBuf own_begin, own_count;  // by gid, into the canonical order
     size_t cap = 0;
     void ensure(size_t n, bool fp32)
     {
         n = std::max<size_t>(n, 1);
-        for (DBuf* d : {&a, &b, &cell, &pid}) d->ensure(n * 4);
+        for (DBuf* d : {&a, &b, &cell, &pid, &hpid, &hcell, &hmap}) d->ensure(n * 4);
         real.ensure(n);
         hist.ensure(n * sizeof(HistRec));
         frec.ensure(n * kForceWords * (fp32 ? sizeof(float) : sizeof(double)));
@@ -146,14 +147,15 @@ struct PairSet {
         History h;
         h.own_begin = own_begin.as<int32_t>();
         h.own_count = own_count.as<int32_t>();
-        h.pid = pid.as<int32_t>();
-        h.cell = cell.as<int32_t>();
+        h.pid = hpid.as<int32_t>();
+        h.cell = hcell.as<int32_t>();
+        h.map = hmap.as<int32_t>();
         h.h = hist.as<HistRec>();
         return h;
     }
     void release()
     {
-        for (DBuf* d : {&a, &b, &cell, &pid, &real, &hist, &frec, &own_begin, &own_count})
+        for (DBuf* d : {&a, &b, &cell, &pid, &real, &hist, &frec, &hpid, &hcell, &hmap, &own_begin, &own_count})
             d->release();
         cap = 0;
     }
@@ -228,7 +230,8 @@ struct World {
     DBuf slot_of_id, keys, vals, keys_alt, vals_alt, cell_start, cell_end, counts, row_start;
     DBuf ent_slot, ent_pid, ent_cell, ent_own, own_scan, rows_ent, scan_tmp, radix_tmp;
     DBuf d_scenes, d_walls, d_mats, d_tanphi, d_ctr, d_part_c, d_part_i, d_bounds, d_total, d_tmp3, d_args;
-    DBuf d_ctrl_cfg, d_ctrl_state, d_acc_ctrl;  // the controlled cell (device-resident)
+    DBuf d_ctrl_cfg, d_ctrl_state, d_acc_ctrl, d_acc_ctrl2;  // the controlled cell (device-resident)
+    DBuf pb_ca, pb_cb, pb_found, pb_flag, pb_scan;  // pair build scratch (canonical order)
     int grid_c = 1, grid_i = 1;        // step-kernel grids (contact sized with headroom)
     int acc_c_n = 0, acc_i_n = 0;      // slots currently in use in d_part_c / d_part_i
     int next_parity = 0;               // parity of the next step (stall flags alternate)
@@ -286,7 +289,8 @@ struct World {
         for (DBuf* d : {&slot_of_id, &keys, &vals, &keys_alt, &vals_alt, &cell_start, &cell_end, &counts, &row_start,
                         &ent_slot, &ent_pid, &ent_cell, &ent_own, &own_scan, &rows_ent, &scan_tmp, &radix_tmp,
                         &d_scenes, &d_walls, &d_mats, &d_tanphi, &d_ctr, &d_part_c, &d_part_i, &d_bounds, &d_total,
-                        &d_tmp3, &d_args, &d_ctrl_cfg, &d_ctrl_state, &d_acc_ctrl})
+                        &d_tmp3, &d_args, &d_ctrl_cfg, &d_ctrl_state, &d_acc_ctrl, &d_acc_ctrl2, &pb_ca, &pb_cb, &pb_found,
+                        &pb_flag, &pb_scan})
             d->release();
         if (h_ctr) (void)hipHostFree(h_ctr);
         h_ctr = nullptr;
@@ -623,7 +627,8 @@ struct World {
         // the descriptor carries a copy of scene 0's parameters, which the
         // device advances for a periodic cell: start from the current ones
         if (periodic && d_scenes.p) pull_scene_table();
-        d_acc_ctrl.ensure(sizeof(double) * (size_t)kNetworkWords * kCtrlGrid);
+        d_acc_ctrl.ensure(sizeof(double) * (size_t)kNetworkWords * std::max(grid_c, 1));
+        d_acc_ctrl2.ensure(sizeof(double) * (size_t)(kNetworkWords + 2) * kCtrlReduceGrid);
         const StepArgs a = step_args();
         d_args.ensure(sizeof(StepArgs));
         HIPC(hipMemcpyAsync(d_args.p, &a, sizeof(StepArgs), hipMemcpyHostToDevice, stream));
@@ -837,12 +842,26 @@ struct World {
             pb.pr = NP.view();
             pb.hist_new = NP.history();
             pb.hist_old = OP.history();
+            pb_ca.ensure(4 * ((size_t)np + 1));
+            pb_cb.ensure(4 * ((size_t)np + 1));
+            pb_found.ensure(4 * ((size_t)np + 1));
+            pb_flag.ensure(4 * ((size_t)np + 1));
+            pb_scan.ensure(4 * ((size_t)np + 1));
+            pb.ca = pb_ca.as<int32_t>();
+            pb.cb = pb_cb.as<int32_t>();
+            pb.found = pb_found.as<int32_t>();
+            pb.flag = pb_flag.as<uint32_t>();
+            pb.flag_scan = pb_scan.as<uint32_t>();
             pb.nslots = nslots;
             pb.nent = (int)nent;
             pb.npairs = (int)np;
             pb.has_old = (OP.cap > 0 && OP.own_begin.p && old_ngids > 0) ? 1 : 0;
             launch_pair_build(pb, stream);
-            launch_carry_over(pb, stream, std::min(old_ngids, ng));
+            launch_carry_find(pb, stream, std::min(old_ngids, ng));
+            // touching pairs first: ranks from a scan of the carried flags
+            scan_tmp.ensure(scan_temp_bytes((int)np + 1));
+            exclusive_scan_u32(pb.flag, pb.flag_scan, (int)np + 1, scan_tmp.p, d_total.as<uint32_t>(), stream);
+            launch_partition(pb, stream);
             HIPC(hipGetLastError());
             pactive = 1 - pactive;
             old_ngids = ng;
@@ -856,8 +875,11 @@ struct World {
         npairs = npairs_new;
         // fold the per-block slots before the grids change, then size them
         fold_slots();
-        if ((int64_t)grid_c * block_contact < npairs || grid_c < 1)
-            grid_c = std::max((int)(((int64_t)npairs * 5 / 4 + block_contact - 1) / block_contact), 1);
+        // the contact kernel gives each of the 8 XCDs one eighth of the
+        // pairs: at least ceil(ceil(npairs / 8) / block) blocks per XCD
+        const int per_xcd = (int)((((int64_t)npairs + 7) / 8 + block_contact - 1) / block_contact);
+        if ((int64_t)grid_c * block_contact < npairs || grid_c < 8 * per_xcd || grid_c < 1)
+            grid_c = std::max({(int)(((int64_t)npairs * 5 / 4 + block_contact - 1) / block_contact), 8 * per_xcd, 1});
         grid_i = std::max((nslots + block_integrate - 1) / block_integrate, 1);
         d_part_c.ensure(sizeof(ContactAcc) * (size_t)grid_c);
         d_part_i.ensure(sizeof(IntAcc) * (size_t)grid_i);
@@ -1131,41 +1153,50 @@ struct World {
         a.ctrl = d_ctrl_cfg.as<CtrlConfig>();
         a.ctrl_state = d_ctrl_state.as<CtrlState>();
         a.acc_ctrl = d_acc_ctrl.as<double>();
+        a.acc_ctrl2 = d_acc_ctrl2.as<double>();
+        a.nblocks_contact = grid_c;
         a.nblocks_integrate = grid_i;
         return a;
     }
 
     // ev (timing mode): 4 events, stamped at the start and end of the
     // contact and the integrate kernels by the dispatch packets themselves
-    void launch_step(int parity, hipEvent_t* ev)
+    // measure: the step ends an update period of the controlled cell (its
+    // contact sums kernel runs after integrate)
+    void launch_step(int parity, hipEvent_t* ev, bool measure)
     {
         const StepArgs* a = d_args.as<StepArgs>();
         launch_contact(a, parity, grid_c, precision, batched(), periodic, block_contact, stream, ev ? ev[0] : nullptr,
-                       ev ? ev[1] : nullptr);
+                       ev ? ev[1] : nullptr, periodic && pt_active && measure);
         launch_integrate(a, parity, grid_i, precision, batched(), periodic, block_integrate, stream,
                          ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
-        if (periodic && pt_active) launch_ctrl_network(a, parity, precision, stream);
+        if (periodic && pt_active && measure) launch_ctrl_reduce(a, parity, stream);
         if (periodic) launch_cell_update(a, parity, stream);
     }
+    // phase of the controlled cell's update period at a launch chain's first
+    // step; step i of the chain ends a period when (phase + i + 1) % period == 0
+    int ctrl_period() const { return pt_active ? std::max(pt_glob_update, 1) : 1; }
+    int ctrl_phase() const { return pt_active ? (int)(scenes[0].iter % ctrl_period()) : 0; }
+    bool measure_step(int phase, int i) const { return pt_active && (phase + i + 1) % ctrl_period() == 0; }
 
-    std::string graph_key(int n) const
+    std::string graph_key(int n, int phase) const
     {
         char buf[256];
-        std::snprintf(buf, sizeof buf, "%p/%d/%d/%d/%d/%d/%d/%d", d_args.p, grid_c, grid_i, n, timing ? 1 : 0,
-                      block_contact, block_integrate, pt_active ? 1 : 0);
+        std::snprintf(buf, sizeof buf, "%p/%d/%d/%d/%d/%d/%d/%d/%d/%d", d_args.p, grid_c, grid_i, n, timing ? 1 : 0,
+                      block_contact, block_integrate, pt_active ? 1 : 0, ctrl_period(), phase);
         return buf;
     }
 
-    GraphEntry& get_graph(int n)
+    GraphEntry& get_graph(int n, int phase)
     {
-        const std::string key = graph_key(n);
+        const std::string key = graph_key(n, phase);
         auto it = graphs.find(key);
         if (it != graphs.end()) return it->second;
-        if (graphs.size() > 8) invalidate_graphs();
+        if (graphs.size() > 16) invalidate_graphs();
         GraphEntry ge;
         hipGraph_t g;
         HIPC(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-        for (int i = 0; i < n; ++i) launch_step(i & 1, nullptr);
+        for (int i = 0; i < n; ++i) launch_step(i & 1, nullptr, measure_step(phase, i));
         HIPC(hipStreamEndCapture(stream, &g));
         HIPC(hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0));
         HIPC(hipGraphDestroy(g));
@@ -1258,7 +1289,7 @@ struct World {
                 // timing mode launches directly: kernel events come from the
                 // dispatch packets, which graph nodes do not expose here
                 if (use_graph && !timing && n == chunk && chunk % 2 == 0 && par0 == 0) {
-                    ge = &get_graph(n);
+                    ge = &get_graph(n, ctrl_phase());
                     HIPC(hipGraphLaunch(ge->exec, stream));
                 } else {
                     if (timing && direct_ev.size() < 4 * (size_t)n) {
@@ -1267,7 +1298,8 @@ struct World {
                         for (size_t q = old; q < direct_ev.size(); ++q) HIPC(hipEventCreate(&direct_ev[q]));
                     }
                     for (int i = 0; i < n; ++i)
-                        launch_step((par0 + i) & 1, timing ? &direct_ev[4 * (size_t)i] : nullptr);
+                        launch_step((par0 + i) & 1, timing ? &direct_ev[4 * (size_t)i] : nullptr,
+                                    measure_step(ctrl_phase(), i));
                 }
                 next_parity = (par0 + n) & 1;
                 HIPC(hipGetLastError());
@@ -1643,6 +1675,7 @@ struct World {
     double ts_safety = 0.8;
     int64_t ts_interval = 0;
     bool pt_active = false;
+    int pt_glob_update = 1;
 
     void set_peri_triax(const dem_peri_triax* c)
     {
@@ -1673,6 +1706,7 @@ struct World {
         }
         HIPC(hipStreamSynchronize(stream));
         pt_active = c != nullptr;
+        pt_glob_update = c ? c->glob_update : 1;
         if (d_args.p) upload_args();
     }
     dem_peri_triax_state peri_triax_state()
@@ -1894,9 +1928,12 @@ struct World {
         }
         HIPC(hipMemcpyAsync(P.own_begin.p, ob.data(), 4 * (size_t)ng, hipMemcpyHostToDevice, stream));
         HIPC(hipMemcpyAsync(P.own_count.p, oc.data(), 4 * (size_t)ng, hipMemcpyHostToDevice, stream));
+        std::vector<int32_t> ident(m);
+        for (size_t i = 0; i < m; ++i) ident[i] = (int32_t)i;
         if (m) {
-            HIPC(hipMemcpyAsync(P.pid.p, pid.data(), 4 * m, hipMemcpyHostToDevice, stream));
-            HIPC(hipMemcpyAsync(P.cell.p, cell.data(), 4 * m, hipMemcpyHostToDevice, stream));
+            HIPC(hipMemcpyAsync(P.hpid.p, pid.data(), 4 * m, hipMemcpyHostToDevice, stream));
+            HIPC(hipMemcpyAsync(P.hcell.p, cell.data(), 4 * m, hipMemcpyHostToDevice, stream));
+            HIPC(hipMemcpyAsync(P.hmap.p, ident.data(), 4 * m, hipMemcpyHostToDevice, stream));
             HIPC(hipMemcpyAsync(P.hist.p, h.data(), sizeof(HistRec) * m, hipMemcpyHostToDevice, stream));
         }
         HIPC(hipStreamSynchronize(stream));

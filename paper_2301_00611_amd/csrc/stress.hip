@@ -116,25 +116,6 @@ __global__ void __launch_bounds__(kStressBlock) k_network(StepArgs a, int scene,
     block_store_terms(s, part);
 }
 
-// In the step (controlled cell on): the same sums on the steps that end an
-// update period (flagged by the contact kernel), any other step returns at
-// once.  A fixed grid of kCtrlGrid blocks walks the pairs with a grid
-// stride, each thread in a fixed order, so the partials are few and the
-// captured graph does not depend on the pair count.
-template <int PREC>
-__global__ void __launch_bounds__(kStressBlock) k_ctrl_network(const StepArgs* __restrict__ args, int parity)
-{
-    const StepArgs& a = *args;
-    if (a.ctr->stall[parity ^ 1] || !a.ctr->measure) return;
-    double s[kNetworkWords], t[kNetworkWords];
-    for (int q = 0; q < kNetworkWords; ++q) s[q] = 0.0;
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < a.npairs; k += gridDim.x * blockDim.x) {
-        network_terms<PREC, false>(a, k, 0, t);
-        for (int q = 0; q < kNetworkWords; ++q) s[q] += t[q];
-    }
-    block_store_terms(s, a.acc_ctrl);
-}
-
 }  // namespace
 
 void launch_pair_forces(const StepArgs& a, int precision, double* f3, hipStream_t st)
@@ -145,14 +126,6 @@ void launch_pair_forces(const StepArgs& a, int precision, double* f3, hipStream_
         hipLaunchKernelGGL(k_pair_forces<DEM_FP32_MIXED>, dim3(grid), dim3(kStressBlock), 0, st, a, f3);
     else
         hipLaunchKernelGGL(k_pair_forces<DEM_FP64>, dim3(grid), dim3(kStressBlock), 0, st, a, f3);
-}
-
-void launch_ctrl_network(const StepArgs* args, int parity, int precision, hipStream_t st)
-{
-    if (precision == DEM_FP32_MIXED)
-        hipLaunchKernelGGL(k_ctrl_network<DEM_FP32_MIXED>, dim3(kCtrlGrid), dim3(kStressBlock), 0, st, args, parity);
-    else
-        hipLaunchKernelGGL(k_ctrl_network<DEM_FP64>, dim3(kCtrlGrid), dim3(kStressBlock), 0, st, args, parity);
 }
 
 int stress_blocks(int npairs) { return npairs > 0 ? (npairs + kStressBlock - 1) / kStressBlock : 0; }
