@@ -376,9 +376,15 @@ def periodic_leg(name="periodic_compression", steps=5000, n=None, log=None, prep
         eb = np.linalg.norm(one[1][1]["force"] - one[0][1]["force"], axis=1)[t] / ssum[t]
         err["body_force_rel_max"] = float(eb.max())
     out["fp32_vs_fp64_one_step"] = err
-    # timed runs, then the same runs with energy tracking for the statistics
+    # timed runs (the launch setting chosen by the autotuner on a copy of the
+    # same state, which it advances), then the same runs with energy
+    # tracking for the statistics
     for prec, name in ((0, "fp64"), (1, "fp32_mixed")):
         g = _periodic_scene(H, L, spec, st["pos"], st["vel"], st["angvel"], prec)
+        tune = g.autotune(probe_steps=200)
+        g.close()
+        g = _periodic_scene(H, L, spec, st["pos"], st["vel"], st["angvel"], prec)
+        g.set_tuning(**{k: v for k, v in tune.items() if k != "ms_per_step"})
         g.step(0)
         s0 = g.stats()
         torch.cuda.synchronize()
@@ -396,7 +402,7 @@ def periodic_leg(name="periodic_compression", steps=5000, n=None, log=None, prep
         r = {"value": (s1["contact_steps"] - s0["contact_steps"]) / el, "unit": "contact-steps/s",
              "ms_per_step": el / steps * 1e3, "body_steps_per_s": n * steps / el, "rebuilds": s1["rebuilds"] - s0["rebuilds"],
              "contacts_mean": c_real, "candidates": s1["n_candidates"], "coordination_end": s1["coordination"],
-             "kernels_ms": kern}
+             "kernels_ms": kern, "tuning": tune}
         # interaction-kernel rooflines (algorithmic bytes per launch)
         bpb, bpc = (80, 104) if prec == 0 else (52, 80)
         cand = st_t["n_candidates"]

@@ -229,7 +229,8 @@ __global__ void __launch_bounds__(kBlock) k_permute(Bodies src, Bodies dst, cons
     if (i >= nslots) return;
     const uint32_t o = order[i];
     dst.xr[i] = src.xr[o];
-    dst.vm[i] = src.vm[o];
+    const double4 v = src.vm[o];
+    dst.vm[i] = make_double4(v.x, v.y, v.z, 0.0);  // a fresh Verlet account after every broad-phase run
     dst.w[i] = src.w[o];
     dst.q[i] = src.q[o];
     dst.mat[i] = src.mat[o];
@@ -238,7 +239,6 @@ __global__ void __launch_bounds__(kBlock) k_permute(Bodies src, Bodies dst, cons
     dst.id[i] = id;
     if (batched) dst.scene[i] = src.scene[o];
     if (periodic) dst.period[i] = src.period[o];
-    dst.disp[i] = 0.0;  // a fresh Verlet account after every broad-phase run
     slot_of_id[id] = i;
 }
 

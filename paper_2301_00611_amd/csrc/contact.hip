@@ -129,8 +129,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
     const int k = xcd_pair(a.npairs);
     ContactPartial part = {0.0, 0.0, 0ull, 0ull, 0.0};
     bool unstable = false;
-    double net[MEASURE ? kNetworkWords : 1];
-    for (int q = 0; q < (MEASURE ? kNetworkWords : 1); ++q) net[q] = 0.0;
+    // the measuring instantiation keeps what its terms need (force and
+    // normal as stored, the branch length, k_n; zero for a pair not
+    // touching) and forms the terms one at a time at the end
+    double mf[3] = {0.0, 0.0, 0.0}, mn[3] = {0.0, 0.0, 0.0}, ml = 0.0, mkn = 0.0, mtouch = 0.0;
     if (k >= 0) {
         const gptr<const double4> xr = glb<const double4>(a.bod.xr);
         const gptr<const double4> vm = glb<const double4>(a.bod.vm);
@@ -287,18 +289,17 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
             unstable = pen > rmin;
             part.ov = pen / rmin;
             if constexpr (MEASURE) {
-                const double f[3] = {(double)F.x, (double)F.y, (double)F.z};
-                const double nn[3] = {(double)n.x, (double)n.y, (double)n.z};
-                net[12] = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
-                net[13] = 1.0;
+                mf[0] = (double)F.x;
+                mf[1] = (double)F.y;
+                mf[2] = (double)F.z;
+                mtouch = 1.0;
                 if (!wall) {
-                    for (int i = 0; i < 3; ++i)
-                        for (int j = 0; j < 3; ++j) net[3 * i + j] = f[i] * (-l * nn[j]);
-                    const double knd = (double)kn;
-                    for (int i = 0; i < 3; ++i) {
-                        const double dn = (l * nn[i]) * nn[i];
-                        net[9 + i] = knd * dn * dn;
-                    }
+                    // sphere pairs only enter the stress and modulus terms
+                    mn[0] = (double)n.x;
+                    mn[1] = (double)n.y;
+                    mn[2] = (double)n.z;
+                    ml = l;
+                    mkn = (double)kn;
                 }
             }
         }
@@ -351,12 +352,23 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
     }
     if constexpr (MEASURE) {
         // the block's partial, one array per term (coalesced for the
-        // single-block reduction that follows the step)
+        // reduction that follows the step): Love-Weber stress f_i (-l n_j)
+        // (9), modulus k_n (l n_i n_i)^2 (3), |F| and the count
         __shared__ double s_net[kMaxBlock / 64][kNetworkWords];
-        for (int q = 0; q < kNetworkWords; ++q)
-            for (int off = 32; off > 0; off >>= 1) net[q] += __shfl_down(net[q], off, 64);
-        if (lane == 0)
-            for (int q = 0; q < kNetworkWords; ++q) s_net[wave][q] = net[q];
+        for (int q = 0; q < kNetworkWords; ++q) {
+            double v;
+            if (q < 9)
+                v = mf[q / 3] * (-ml * mn[q % 3]);
+            else if (q < 12) {
+                const double dn = (ml * mn[q - 9]) * mn[q - 9];
+                v = mkn * dn * dn;
+            } else if (q == 12)
+                v = sqrt(mf[0] * mf[0] + mf[1] * mf[1] + mf[2] * mf[2]);
+            else
+                v = mtouch;
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+            if (lane == 0) s_net[wave][q] = v;
+        }
         __syncthreads();
         if (threadIdx.x < kNetworkWords) {
             double t = 0.0;

@@ -70,7 +70,8 @@ struct Material {
 // position and radius, or its velocity, touches one memory segment.
 struct Bodies {
     double4 *xr;              // x, y, z, radius
-    double4 *vm;              // vx, vy, vz, mass
+    double4 *vm;              // vx, vy, vz, and the Verlet account: non-affine displacement
+                              // accumulated since the last broad-phase run
     double4 *w;               // wx, wy, wz, 0
     double4 *q;               // qw, qx, qy, qz
     uint16_t *mat;            // material index
@@ -78,8 +79,17 @@ struct Bodies {
     int32_t *id;              // slot -> body id
     uint16_t *scene;          // slot -> scene (batched only)
     int32_t *period;          // periodic: packed integer period of the body at the last run
-    double *disp;             // non-affine displacement accumulated since the last broad-phase run
 };
+
+// A sphere's mass, m = 4/3 pi r^3 rho, computed where it is needed (it is
+// not stored: the fourth word of vm carries the Verlet account), in the
+// same order of operations and without contraction, as the host computes
+// it when the sphere is added.
+__device__ inline double sphere_mass(double r, double rho)
+{
+#pragma clang fp contract(off)
+    return 4.0 / 3.0 * 3.14159265358979323846 * r * r * r * rho;
+}
 
 // A pair's history record (64 bytes, one aligned segment): the shear force
 // on #2 after the Coulomb cap and the normal of its last evaluation; a

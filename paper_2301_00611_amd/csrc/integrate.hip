@@ -123,7 +123,6 @@ __global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restr
     bool over = false;
     if (i < a.nslots) {
         const gptr<double4> bxr = glb(a.bod.xr), bvm = glb(a.bod.vm), bw = glb(a.bod.w), bq = glb(a.bod.q);
-        const gptr<double> bdisp = glb(a.bod.disp);
         // the row bounds first: the row's loads wait for them, not for the
         // body's own state, which is requested right after
         const int beg = glb<const int32_t>(a.rows.start)[i], end = glb<const int32_t>(a.rows.start)[i + 1];
@@ -134,7 +133,8 @@ __global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restr
         const double dt = S.dt;
         const double lam = S.damping;
         const double4 xr0 = bxr[i], vm0 = bvm[i], w0 = bw[i];
-        const double r = xr0.w, m = vm0.w;
+        const double rho = glb<const Material>(a.mats)[glb<const uint16_t>(a.bod.mat)[i]].density;
+        const double r = xr0.w, m = sphere_mass(r, rho);
         const double I = 2.0 * m * r * r / 5.0;
         const unsigned blocked = glb<const uint8_t>(a.bod.blocked)[i];
         double F[3], T[3];
@@ -208,20 +208,19 @@ __global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restr
             bq[i] = make_double4(q[0], q[1], q[2], q[3]);
         }
         bxr[i] = make_double4(x1[0], x1[1], x1[2], r);
-        bvm[i] = make_double4(v[0], v[1], v[2], m);
-        // an unchanged spin (no torque, or blocked) is not stored again
-        if (w[0] != w0.x || w[1] != w0.y || w[2] != w0.z) bw[i] = make_double4(w[0], w[1], w[2], 0.0);
-
-        // non-affine displacement of this step, added to the body's Verlet
-        // account (eq. 2.3); the cell's mean field uses its own share
+        // the Verlet account (fourth word of vm): non-affine displacement of
+        // this step (eq. 2.3); the cell's mean field uses its own share
         double u[3] = {v[0], v[1], v[2]};
         if (PERIODIC) {
             double Lx[3];
             matvec(S.L, x0[0], x0[1], x0[2], Lx);
             for (int k = 0; k < 3; ++k) u[k] -= Lx[k];
         }
-        const double d = bdisp[i] + sqrt((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]) * dt + a.ctr->verlet_cell_step;
-        bdisp[i] = d;
+        const double d = vm0.w + sqrt((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]) * dt + a.ctr->verlet_cell_step;
+        bvm[i] = make_double4(v[0], v[1], v[2], d);
+        // an unchanged spin (no torque, or blocked) is not stored again
+        if (w[0] != w0.x || w[1] != w0.y || w[2] != w0.z) bw[i] = make_double4(w[0], w[1], w[2], 0.0);
+
         over = d > a.ctr->verlet_limit;
         bad = !(isfinite(x1[0]) && isfinite(x1[1]) && isfinite(x1[2]) && isfinite(v[0]) && isfinite(v[1]) &&
                 isfinite(v[2]));
@@ -469,7 +468,7 @@ __global__ void __launch_bounds__(kMeasureBlock) k_body_measures(StepArgs a, int
     if (i < a.nslots && (!BATCHED || (int)a.bod.scene[i] == scene) && a.bod.blocked[i] != 63u) {
         const unsigned blocked = a.bod.blocked[i];
         const double4 xr = a.bod.xr[i];
-        const double r = xr.w, m = a.bod.vm[i].w;
+        const double r = xr.w, m = sphere_mass(r, a.mats[a.bod.mat[i]].density);
         const double I = 2.0 * m * r * r / 5.0;
         const int beg = a.rows.start[i], end = a.rows.start[i + 1];
         double F[3], T[3];

@@ -83,11 +83,10 @@ struct DBuf {
 };
 
 struct BodySet {
-    DBuf xr, vm, w, q, mat, blocked, id, scene, period, disp;
+    DBuf xr, vm, w, q, mat, blocked, id, scene, period;
     void ensure(size_t n)
     {
         for (DBuf* b : {&xr, &vm, &w, &q}) b->ensure(n * sizeof(double4));
-        disp.ensure(n * 8);
         mat.ensure(n * 2);
         blocked.ensure(n);
         id.ensure(n * 4);
@@ -106,12 +105,11 @@ struct BodySet {
         b.id = id.as<int32_t>();
         b.scene = scene.as<uint16_t>();
         b.period = period.as<int32_t>();
-        b.disp = disp.as<double>();
         return b;
     }
     void release()
     {
-        for (DBuf* b : {&xr, &vm, &w, &q, &mat, &blocked, &id, &scene, &period, &disp}) b->release();
+        for (DBuf* b : {&xr, &vm, &w, &q, &mat, &blocked, &id, &scene, &period}) b->release();
     }
 };
 
@@ -555,7 +553,7 @@ struct World {
             HIPC(hipStreamSynchronize(stream));
         };
         push(B.xr, [](const HostBody& b, int c) { return c < 3 ? b.x[c] : b.r; });
-        push(B.vm, [](const HostBody& b, int c) { return c < 3 ? b.v[c] : b.m; });
+        push(B.vm, [](const HostBody& b, int c) { return c < 3 ? b.v[c] : 0.0; });  // fresh Verlet account
         push(B.w, [](const HostBody& b, int c) { return c < 3 ? b.w[c] : 0.0; });
         push(B.q, [](const HostBody& b, int c) { return b.q[c]; });
         std::vector<uint8_t> u8(n);
