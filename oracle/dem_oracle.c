@@ -45,9 +45,13 @@ typedef struct {
     double x[3], v[3], w[3], q[4]; /* q = (qw, qx, qy, qz) */
     double r, m, I;
     unsigned blocked;
-    /* wall */
+    /* boundary (is_wall): prim 0 = infinite axis-aligned plane (utils.wall),
+     * 1 = axis-aligned box [lo, hi] (Box), 2 = triangle fv[0..2] (Facet) */
+    int prim;
     int axis, sense;
     double wpos;
+    double lo[3], hi[3];
+    double fv[3][3];
     /* common */
     int mat;
     double F[3], T[3]; /* resultant of the last step's contacts */
@@ -63,7 +67,9 @@ typedef struct {
     /* geometry found by the detection pass */
     double det_d[3]; /* branch vector from #1 to (the image of) #2 */
     double det_dd;   /* its squared length */
-    double det_pen;  /* overlap of a wall contact */
+    double det_pen;  /* overlap of a boundary contact */
+    double det_n[3]; /* its normal (from the boundary towards the sphere) */
+    double det_R1;   /* the boundary's reference radius */
     /* results of the last evaluation */
     double n[3], pen, pt[3], fn[3], kn, ks;
     double f2[3];          /* total force on #2 */
@@ -384,6 +390,64 @@ static int sphere_pair(const orc_scene* s, const body_t* b1, const body_t* b2,
     return found;
 }
 
+static int add_boundary(orc_scene* s, int mat, long* out_id, body_t** out)
+{
+    if (mat < 0 || mat >= s->nmat) return fail(ORC_EINVAL, "unknown material");
+    if (s->p.periodic) return fail(ORC_EINVAL, "boundaries are not supported in a periodic cell");
+    int rc = grow_bodies(s, 1);
+    if (rc) return rc;
+    if (out_id) *out_id = s->nb;
+    body_t* b = &s->b[s->nb++];
+    memset(b, 0, sizeof *b);
+    b->is_wall = 1;
+    b->mat = mat;
+    b->q[0] = 1.0;
+    *out = b;
+    return ORC_OK;
+}
+
+/* Box: a fixed axis-aligned box with the given centre and half-sizes. */
+int orc_add_box(orc_scene* s, const double* center3, const double* half3, int mat, long* out_id)
+{
+    if (!s || !center3 || !half3) return fail(ORC_EINVAL, "orc_add_box: null argument");
+    for (int k = 0; k < 3; ++k)
+        if (!isfinite(center3[k]) || !(half3[k] > 0.0) || !isfinite(half3[k]))
+            return fail(ORC_EINVAL, "orc_add_box: finite centre and half-sizes > 0");
+    body_t* b;
+    int rc = add_boundary(s, mat, out_id, &b);
+    if (rc) return rc;
+    b->prim = 1;
+    for (int k = 0; k < 3; ++k) {
+        b->lo[k] = center3[k] - half3[k];
+        b->hi[k] = center3[k] + half3[k];
+    }
+    return ORC_OK;
+}
+
+/* Facet: a fixed triangle with vertices v0, v1, v2 (not collinear). */
+int orc_add_facet(orc_scene* s, const double* v0, const double* v1, const double* v2, int mat, long* out_id)
+{
+    if (!s || !v0 || !v1 || !v2) return fail(ORC_EINVAL, "orc_add_facet: null argument");
+    const double* v[3] = {v0, v1, v2};
+    for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k)
+            if (!isfinite(v[i][k])) return fail(ORC_EINVAL, "orc_add_facet: non-finite vertex");
+    double e1[3], e2[3], nn[3];
+    for (int k = 0; k < 3; ++k) {
+        e1[k] = v1[k] - v0[k];
+        e2[k] = v2[k] - v0[k];
+    }
+    cross3(e1, e2, nn);
+    if (!(dot3(nn, nn) > 0.0)) return fail(ORC_EINVAL, "orc_add_facet: degenerate triangle");
+    body_t* b;
+    int rc = add_boundary(s, mat, out_id, &b);
+    if (rc) return rc;
+    b->prim = 2;
+    for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) b->fv[i][k] = v[i][k];
+    return ORC_OK;
+}
+
 /* Wall.sense: -1 / +1 interact on that side only, 0 on both.  With sense 0
  * the normal follows the side the sphere centre is on (side of 0 = +). */
 static int wall_sign(const body_t* w, const body_t* sp)
@@ -403,6 +467,143 @@ static int wall_pair(const body_t* w, const body_t* sp, double* pen_out)
     if (!(fabs(delta) < sp->r)) return 0;
     int sg = wall_sign(w, sp);
     *pen_out = sp->r - (double)sg * delta;
+    return 1;
+}
+
+/* Closest point of segment [a, b] to x. */
+static void closest_on_segment(const double a[3], const double b[3], const double x[3], double out[3])
+{
+    double ab[3], ax[3];
+    for (int k = 0; k < 3; ++k) {
+        ab[k] = b[k] - a[k];
+        ax[k] = x[k] - a[k];
+    }
+    double t = dot3(ax, ab) / dot3(ab, ab);
+    if (t < 0.0) t = 0.0;
+    if (t > 1.0) t = 1.0;
+    for (int k = 0; k < 3; ++k) out[k] = a[k] + t * ab[k];
+}
+
+/* Closest point of the triangle to x: the projection on its plane when it
+ * falls inside (same side of all three edges), else the closest of the
+ * three edges' closest points. */
+static void closest_on_triangle(const double v[3][3], const double x[3], double out[3])
+{
+    double e1[3], e2[3], nn[3];
+    for (int k = 0; k < 3; ++k) {
+        e1[k] = v[1][k] - v[0][k];
+        e2[k] = v[2][k] - v[0][k];
+    }
+    cross3(e1, e2, nn);
+    double len = sqrt(dot3(nn, nn));
+    for (int k = 0; k < 3; ++k) nn[k] /= len;
+    double h = (x[0] - v[0][0]) * nn[0] + (x[1] - v[0][1]) * nn[1] + (x[2] - v[0][2]) * nn[2];
+    double p[3];
+    for (int k = 0; k < 3; ++k) p[k] = x[k] - h * nn[k];
+    int inside = 1;
+    for (int i = 0; i < 3; ++i) {
+        const double* a = v[i];
+        const double* b = v[(i + 1) % 3];
+        double ab[3], ap[3], c[3];
+        for (int k = 0; k < 3; ++k) {
+            ab[k] = b[k] - a[k];
+            ap[k] = p[k] - a[k];
+        }
+        cross3(ab, ap, c);
+        if (dot3(c, nn) < 0.0) inside = 0;
+    }
+    if (inside) {
+        memcpy(out, p, sizeof p);
+        return;
+    }
+    double best = INFINITY;
+    for (int i = 0; i < 3; ++i) {
+        double q[3], d[3];
+        closest_on_segment(v[i], v[(i + 1) % 3], x, q);
+        for (int k = 0; k < 3; ++k) d[k] = x[k] - q[k];
+        double dd = dot3(d, d);
+        if (dd < best) {
+            best = dd;
+            memcpy(out, q, sizeof q);
+        }
+    }
+}
+
+/* Contact of a sphere with a boundary, its normal (from the boundary
+ * towards the sphere centre), overlap and the boundary's reference radius:
+ *  - plane (Ig2_Wall_Sphere_ScGeom): as wall_pair, reference radius r;
+ *  - box (Ig2_Box_Sphere_ScGeom, the box seen as a virtual sphere of the
+ *    same radius, reference radius r): centre outside the box: the closest
+ *    point p of the box, touching iff |x - p| < r, n = (x - p)/|x - p|,
+ *    overlap r - |x - p|; centre inside: pushed out through the nearest face
+ *    (first in the order x-, x+, y-, y+, z-, z+ on a tie), overlap r + depth;
+ *  - facet (Ig2_Facet_Sphere_ScGeom, two-sided, reference radius 2r): the
+ *    closest point p of the triangle, touching iff |x - p| < r, n = (x - p)/
+ *    |x - p| (the face normal (v1 - v0) x (v2 - v0) when the centre lies on
+ *    the triangle), overlap r - |x - p|. */
+static int boundary_pair(const body_t* w, const body_t* sp, double n[3], double* pen, double* R1)
+{
+    n[0] = n[1] = n[2] = 0.0;
+    if (w->prim == 0) {
+        if (!wall_pair(w, sp, pen)) return 0;
+        n[w->axis] = (double)wall_sign(w, sp);
+        *R1 = sp->r;
+        return 1;
+    }
+    if (w->prim == 1) {
+        double p[3];
+        int inside = 1;
+        for (int k = 0; k < 3; ++k) {
+            p[k] = sp->x[k] < w->lo[k] ? w->lo[k] : (sp->x[k] > w->hi[k] ? w->hi[k] : sp->x[k]);
+            if (sp->x[k] < w->lo[k] || sp->x[k] > w->hi[k]) inside = 0;
+        }
+        *R1 = sp->r;
+        if (!inside) {
+            double d[3] = {sp->x[0] - p[0], sp->x[1] - p[1], sp->x[2] - p[2]};
+            double dist = sqrt(dot3(d, d));
+            if (!(dist < sp->r)) return 0;
+            for (int k = 0; k < 3; ++k) n[k] = d[k] / dist;
+            *pen = sp->r - dist;
+            return 1;
+        }
+        int ax = 0, sg = -1;
+        double depth = INFINITY;
+        for (int k = 0; k < 3; ++k) {
+            double dl = sp->x[k] - w->lo[k], dh = w->hi[k] - sp->x[k];
+            if (dl < depth) {
+                depth = dl;
+                ax = k;
+                sg = -1;
+            }
+            if (dh < depth) {
+                depth = dh;
+                ax = k;
+                sg = 1;
+            }
+        }
+        n[ax] = (double)sg;
+        *pen = sp->r + depth;
+        return 1;
+    }
+    double p[3] = {0.0, 0.0, 0.0};
+    closest_on_triangle(w->fv, sp->x, p);
+    double d[3] = {sp->x[0] - p[0], sp->x[1] - p[1], sp->x[2] - p[2]};
+    double dist = sqrt(dot3(d, d));
+    if (!(dist < sp->r)) return 0;
+    if (dist > 0.0) {
+        for (int k = 0; k < 3; ++k) n[k] = d[k] / dist;
+    } else {
+        double e1[3], e2[3];
+        for (int k = 0; k < 3; ++k) {
+            e1[k] = w->fv[1][k] - w->fv[0][k];
+            e2[k] = w->fv[2][k] - w->fv[0][k];
+        }
+        cross3(e1, e2, n);
+        double len = sqrt(dot3(n, n));
+        for (int k = 0; k < 3; ++k) n[k] /= len;
+    }
+    *pen = sp->r - dist;
+    *R1 = 2.0 * sp->r;
     return 1;
 }
 
@@ -461,13 +662,11 @@ static void eval_contact(const orc_scene* s, cont_t* ct, const double d[3], doub
          * granular ratcheting (ScGeom, Ig2_Sphere_Sphere_ScGeom) */
         alpha = (R1 + R2) / l;
     } else {
-        /* Ig2_Wall_Sphere_ScGeom: the wall is #1, its reference radius is the
-         * sphere's radius; the normal is the wall normal on the sphere side. */
-        int sg = wall_sign(b1, b2);
-        n[0] = n[1] = n[2] = 0.0;
-        n[b1->axis] = (double)sg;
+        /* a boundary (plane, box, facet) is #1; normal, overlap and its
+         * reference radius come from boundary_pair at detection */
+        memcpy(n, ct->det_n, sizeof n);
         pen = pen_wall;
-        R1 = b2->r;
+        R1 = ct->det_R1;
         R2 = b2->r;
         for (int k = 0; k < 3; ++k) pt[k] = b2->x[k] - (b2->r - 0.5 * pen) * n[k];
         alpha = 1.0;
@@ -584,11 +783,11 @@ static int detect_all(const orc_scene* s, const cont_t* old, long nold, cont_t**
             } else {
                 const body_t* w = bi->is_wall ? bi : bj;
                 const body_t* sp = bi->is_wall ? bj : bi;
-                if (!wall_pair(w, sp, &penw)) continue;
+                if (!boundary_pair(w, sp, ct.det_n, &penw, &ct.det_R1)) continue;
                 ct.is_wall = 1;
                 ct.id1 = bi->is_wall ? i : j;
                 ct.id2 = bi->is_wall ? j : i;
-                ct.n[w->axis] = (double)wall_sign(w, sp);
+                memcpy(ct.n, ct.det_n, sizeof ct.n);
             }
             memcpy(ct.det_d, d, sizeof d);
             ct.det_dd = dd;
@@ -838,6 +1037,16 @@ int orc_step(orc_scene* s, long nsteps)
 
 /* ---------------------------------------------------------------- access */
 
+/* Reported position of a body: a sphere's centre; a plane's coordinate on
+ * its axis (0 elsewhere); a box's centre; a facet's centroid. */
+static double boundary_position(const body_t* b, int k)
+{
+    if (!b->is_wall) return b->x[k];
+    if (b->prim == 0) return k == b->axis ? b->wpos : 0.0;
+    if (b->prim == 1) return 0.5 * (b->lo[k] + b->hi[k]);
+    return (b->fv[0][k] + b->fv[1][k] + b->fv[2][k]) / 3.0;
+}
+
 int orc_get_state(const orc_scene* s, double* pos3, double* vel3, double* angvel3,
                   double* ori4, double* force3, double* torque3)
 {
@@ -845,7 +1054,7 @@ int orc_get_state(const orc_scene* s, double* pos3, double* vel3, double* angvel
     for (long i = 0; i < s->nb; ++i) {
         const body_t* b = &s->b[i];
         for (int k = 0; k < 3; ++k) {
-            if (pos3) pos3[3 * i + k] = b->is_wall ? (k == b->axis ? b->wpos : 0.0) : b->x[k];
+            if (pos3) pos3[3 * i + k] = boundary_position(b, k);
             if (vel3) vel3[3 * i + k] = b->v[k];
             if (angvel3) angvel3[3 * i + k] = b->w[k];
             if (force3) force3[3 * i + k] = b->F[k];
@@ -1063,11 +1272,11 @@ int orc_spot_step(const orc_scene* s, long k, const long* ids, double* force3,
                 ct.id2 = ct.hi;
                 for (int a = 0; a < 3; ++a) ct.n[a] = d[a] / sqrt(dd);
             } else {
-                if (!wall_pair(bj, bi, &penw)) continue;
+                if (!boundary_pair(bj, bi, ct.det_n, &penw, &ct.det_R1)) continue;
                 ct.is_wall = 1;
                 ct.id1 = j;
                 ct.id2 = i;
-                ct.n[bj->axis] = (double)wall_sign(bj, bi);
+                memcpy(ct.n, ct.det_n, sizeof ct.n);
             }
             const cont_t* prev = find_contact(s->c, s->nc, ct.lo, ct.hi, ct.c);
             if (prev) {

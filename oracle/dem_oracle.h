@@ -78,6 +78,12 @@ int orc_add_spheres(orc_scene* s, long n, const double* pos3, const double* radi
 /* infinite plane normal to `axis` at coordinate `position`; sense -1/0/+1. */
 int orc_add_wall(orc_scene* s, int axis, double position, int sense, int mat, long* out_id);
 
+/* Fixed boundaries besides planes: an axis-aligned box (Box, centre and
+ * half-sizes, Ig2_Box_Sphere_ScGeom) and a triangle (Facet, vertices v0, v1,
+ * v2, two-sided, Ig2_Facet_Sphere_ScGeom with reference radius 2r).  Like a
+ * wall, a boundary is #1 of its contacts. */
+int orc_add_box(orc_scene* s, const double* center3, const double* half3, int mat, long* out_id);
+int orc_add_facet(orc_scene* s, const double* v0, const double* v1, const double* v2, int mat, long* out_id);
 /* utils.PWaveTimeStep: min over spheres of r*sqrt(rho/E). */
 int orc_pwave_dt(const orc_scene* s, double* out);
 int orc_step(orc_scene* s, long nsteps);
@@ -88,7 +94,8 @@ int orc_get_counters(const orc_scene* s, long* iter, double* time);
 
 /* All bodies in id order; any pointer may be NULL.  Forces/torques are the
  * resultants of the last step's contacts (gravity not included).  For a wall,
- * pos3[axis] holds its position and the rest is 0. */
+ * pos3[axis] holds its position and the rest is 0; a box reports its centre
+ * and a facet its centroid. */
 int orc_get_state(const orc_scene* s, double* pos3, double* vel3, double* angvel3,
                   double* ori4, double* force3, double* torque3);
 /* Mass and scalar inertia of every body (0 for walls). */

@@ -96,6 +96,8 @@ def load_library(path: str | None = None):
         "orc_detect_pairs": [C.c_void_p, C.c_long, _LP, _LP, _IP, _LP],
         "orc_spot_step": [C.c_void_p, C.c_long, _LP, _DP, _DP, _DP, _DP, _DP, _DP, _LP],
         "orc_set_dt": [C.c_void_p, C.c_double],
+        "orc_add_box": [C.c_void_p, _DP, _DP, C.c_int, _LP],
+        "orc_add_facet": [C.c_void_p, _DP, _DP, _DP, C.c_int, _LP],
         "orc_set_velgrad": [C.c_void_p, _DP],
     }
     for name, args in sigs.items():
@@ -197,6 +199,24 @@ class OracleScene:
         out = C.c_long()
         self._check(self.lib.orc_add_wall(self._h, int(axis), float(position), int(sense), int(mat), C.byref(out)),
                     "add_wall")
+        self.radius.append(0.0)
+        self.blocked.append(63)
+        self.is_wall.append(True)
+        return out.value
+
+    def add_box(self, center, half, mat=0):
+        out = C.c_long()
+        c, h = _f64(center, (3,)), _f64(half, (3,))
+        self._check(self.lib.orc_add_box(self._h, _ptr(c), _ptr(h), int(mat), C.byref(out)), "add_box")
+        self.radius.append(0.0)
+        self.blocked.append(63)
+        self.is_wall.append(True)
+        return out.value
+
+    def add_facet(self, v0, v1, v2, mat=0):
+        out = C.c_long()
+        a, b, c = _f64(v0, (3,)), _f64(v1, (3,)), _f64(v2, (3,))
+        self._check(self.lib.orc_add_facet(self._h, _ptr(a), _ptr(b), _ptr(c), int(mat), C.byref(out)), "add_facet")
         self.radius.append(0.0)
         self.blocked.append(63)
         self.is_wall.append(True)

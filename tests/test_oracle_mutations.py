@@ -32,7 +32,8 @@ MUTATIONS = {
                                         "double s1 = (m1->young) * (2.0 * R1);"),
     "friction_max_not_min": ("*tanphi = tan(m1->friction < m2->friction ? m1->friction : m2->friction);",
                              "*tanphi = tan(m1->friction > m2->friction ? m1->friction : m2->friction);"),
-    "wall_reference_radius": ("R1 = b2->r;\n        R2 = b2->r;", "R1 = 0.5 * b2->r;\n        R2 = b2->r;"),
+    "wall_reference_radius": ("n[w->axis] = (double)wall_sign(w, sp);\n        *R1 = sp->r;",
+                              "n[w->axis] = (double)wall_sign(w, sp);\n        *R1 = 0.5 * sp->r;"),
     "plastic_work_without_fmax": ("*e_plast += (fs_norm - fmax) * fmax / ks;", "*e_plast += (fs_norm - fmax) / ks;"),
     "rotation_angle_doubled": ("double half = 0.5 * wn * dt;", "double half = wn * dt;"),
     "overlap_dependent_branch": ("rw[k] = R2 * w2[k] + R1 * w1[k];",
