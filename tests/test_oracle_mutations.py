@@ -63,3 +63,32 @@ def test_pins_catch_mutation(name, tmp_path):
                        env=env, capture_output=True, text=True, cwd=ROOT, timeout=600)
     assert r.returncode != 0, f"no pin caught mutation {name}:\n{r.stdout[-2000:]}"
     assert "FAILED" in r.stdout
+
+
+# slips in the box and facet boundaries, caught by tests/test_oracle_boundaries.py
+BOUNDARY_MUTATIONS = {
+    "facet_reference_radius": ("*R1 = 2.0 * sp->r;", "*R1 = sp->r;"),
+    "box_inside_overlap": ("*pen = sp->r + depth;", "*pen = sp->r - depth;"),
+    "box_edge_as_two_planes": ("if (!(dist < sp->r)) return 0;\n            for (int k = 0; k < 3; ++k) n[k] = d[k] / dist;",
+                               "if (!(dist < sp->r * 1.5)) return 0;\n            for (int k = 0; k < 3; ++k) n[k] = d[k] / dist;"),
+    "facet_edge_clamp": ("if (t > 1.0) t = 1.0;", ""),
+    "facet_one_sided": ("if (dot3(c, nn) < 0.0) inside = 0;", "if (dot3(c, nn) > 0.0) inside = 0;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(BOUNDARY_MUTATIONS))
+def test_boundary_pins_catch_mutation(name, tmp_path):
+    before, after = BOUNDARY_MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(before) == 1, f"mutation anchor not found: {name}"
+    mutated = tmp_path / "dem_oracle_mutated.c"
+    mutated.write_text(src.replace(before, after))
+    lib = tmp_path / "libdem_oracle_mutated.so"
+    subprocess.run(["gcc", "-std=c99", "-D_DEFAULT_SOURCE", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+                    "-I", os.path.join(ROOT, "oracle"), "-o", str(lib), str(mutated), "-lm"], check=True)
+    env = dict(os.environ, DEM_ORACLE_LIB=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_boundaries.py")],
+                       env=env, capture_output=True, text=True, cwd=ROOT, timeout=600)
+    assert r.returncode != 0, f"no pin caught mutation {name}:\n{r.stdout[-2000:]}"
+    assert "FAILED" in r.stdout
