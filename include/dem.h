@@ -64,7 +64,8 @@ enum {
     DEM_EDEVICE = 6,      /* HIP runtime error; message holds the HIP error string */
     DEM_ENONFINITE = 7,   /* NaN/Inf in positions or velocities after a step */
     DEM_EPERIODIC = 8,    /* periodic cell too small for the spheres and Verlet distance */
-    DEM_EUNSTABLE = 9,    /* overlap exceeded a sphere radius ("numerically exploding") */
+    DEM_EUNSTABLE = 9,    /* overlap exceeded a sphere radius ("numerically exploding");
+                             a centre inside a box is not counted */
     DEM_EBUSY = 10        /* an asynchronous step is in flight (dem_step_async) */
 };
 
@@ -175,6 +176,24 @@ dem_status dem_add_spheres(dem_scene* s, int64_t n, const double* pos3, const do
  * (class Wall): the side(s) it interacts with.  Walls do not move. */
 dem_status dem_add_wall(dem_scene* s, int32_t axis, double position, int32_t sense, int32_t mat,
                         int64_t* out_id);
+/* Fixed boundaries besides planes; like a wall each is #1 of its contacts,
+ * takes an id in the same sequence and is not moved.
+ *  - dem_add_box: an axis-aligned box (class Box, Ig2_Box_Sphere_ScGeom)
+ *    with the given centre and half-sizes (> 0).  A sphere whose centre is
+ *    outside touches it when closer than r to the box: normal from the
+ *    closest point towards the centre, overlap r - distance; a centre inside
+ *    the box is pushed out through the nearest face (overlap r + depth).
+ *    Reference radius: the sphere's (a virtual sphere of the same radius).
+ *  - dem_add_facet: a triangle v0, v1, v2 (class Facet,
+ *    Ig2_Facet_Sphere_ScGeom), two-sided: normal from the closest point of
+ *    the triangle towards the centre (the face normal (v1 - v0) x (v2 - v0)
+ *    when the centre lies on it), overlap r - distance; reference radius
+ *    twice the sphere's.  A degenerate triangle is DEM_EINVAL.
+ * At most 64 boundaries (planes included) per scene; none in a periodic
+ * cell.  dem_get_state reports a box's centre and a facet's centroid. */
+dem_status dem_add_box(dem_scene* s, const double* center3, const double* half3, int32_t mat, int64_t* out_id);
+dem_status dem_add_facet(dem_scene* s, const double* v0, const double* v1, const double* v2, int32_t mat,
+                         int64_t* out_id);
 
 /* utils.PWaveTimeStep: min over spheres of r / sqrt(E / rho). */
 dem_status dem_pwave_dt(dem_scene* s, double* out);

@@ -356,9 +356,15 @@ __device__ inline void for_each_candidate(const SweepArgs& a, int i, F&& f)
     for (int k = 0; k < P.wall_count; ++k) {
         const int wi = P.wall_begin + k;
         const Wall W = a.walls[wi];
-        const double xa = W.axis == 0 ? xi : (W.axis == 1 ? yi : zi);
-        const double delta = xa - W.pos;
-        if (fabs(delta) < ri + reach) f(-1 - wi, W.id, kCellZero);
+        if (W.kind == kPlane) {
+            const double xa = W.axis == 0 ? xi : (W.axis == 1 ? yi : zi);
+            const double delta = xa - W.pos;
+            if (fabs(delta) < ri + reach) f(-1 - wi, W.id, kCellZero);
+        } else {
+            // box or facet: closer than r + 2 Delta L to the primitive
+            const double x[3] = {xi, yi, zi};
+            if (boundary_distance(W, x) < ri + reach) f(-1 - wi, W.id, kCellZero);
+        }
     }
 }
 

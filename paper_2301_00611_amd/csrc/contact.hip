@@ -108,7 +108,10 @@ struct ContactPartial {
 // centre distance vector) and |F| with a count (every touching pair), from
 // the force and normal as stored.  A separate instantiation, so that the
 // extra registers do not lower the occupancy of every other step.
-template <int PREC, bool BATCHED, bool PERIODIC, bool MEASURE = false>
+// PRIMS (aperiodic scenes holding a box or a facet): the geometry of those
+// boundaries is compiled in; without it the kernel keeps its registers for
+// spheres and planes.
+template <int PREC, bool BATCHED, bool PERIODIC, bool MEASURE = false, bool PRIMS = false>
 __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restrict__ args, int parity)
 {
     using R = typename std::conditional<PREC == DEM_FP32_MIXED, float, double>::type;
@@ -167,6 +170,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
 
         // ---- exact test, normal, overlap (always in double)
         bool real;
+        bool in_box = false;       // a centre inside a box: overlap r + depth by definition
         double pen, inv_l = 0.0, l = 0.0;
         V3<double> n64;
         int cc[3] = {0, 0, 0};
@@ -180,13 +184,61 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
             n64 = v3(t.dx * inv_l, t.dy * inv_l, t.dz * inv_l);
             pen = (r1 + r2) - l;
             if (pen < 0.0) pen = 0.0;
-        } else {
+        } else if (!PRIMS || W.kind == kPlane) {
             const double xa = W.axis == 0 ? x2 : (W.axis == 1 ? y2 : z2);
             const double delta = xa - W.pos;
             real = fabs(delta) < r2;
             const double sg = W.sense != 0 ? (double)W.sense : (delta >= 0.0 ? 1.0 : -1.0);
             pen = r2 - sg * delta;
             n64 = v3(W.axis == 0 ? sg : 0.0, W.axis == 1 ? sg : 0.0, W.axis == 2 ? sg : 0.0);
+        } else if constexpr (PRIMS) {
+            // box (Ig2_Box_Sphere_ScGeom) or facet (Ig2_Facet_Sphere_ScGeom,
+            // two-sided): normal from the closest point towards the centre
+            const double xs[3] = {x2, y2, z2};
+            double p[3];
+            bool inside = false;
+            if (W.kind == kBox)
+                box_closest(W, xs, p, &inside);
+            else
+                facet_closest(W, xs, p);
+            if (inside) {
+                // the centre is in the box: out through the nearest face (first
+                // of x-, x+, y-, y+, z-, z+ on a tie), overlap r + depth
+                int ax = 0;
+                double sgn = -1.0, depth = INFINITY;
+                for (int q = 0; q < 3; ++q) {
+                    const double dl = xs[q] - W.g[q], dh = W.g[3 + q] - xs[q];
+                    if (dl < depth) {
+                        depth = dl;
+                        ax = q;
+                        sgn = -1.0;
+                    }
+                    if (dh < depth) {
+                        depth = dh;
+                        ax = q;
+                        sgn = 1.0;
+                    }
+                }
+                real = true;
+                in_box = true;
+                pen = r2 + depth;
+                n64 = v3(ax == 0 ? sgn : 0.0, ax == 1 ? sgn : 0.0, ax == 2 ? sgn : 0.0);
+            } else {
+                const double d0 = xs[0] - p[0], d1 = xs[1] - p[1], d2 = xs[2] - p[2];
+                const double dist = sqrt((d0 * d0 + d1 * d1) + d2 * d2);
+                real = dist < r2;
+                pen = r2 - dist;
+                if (dist > 0.0) {
+                    n64 = v3(d0 / dist, d1 / dist, d2 / dist);
+                } else {
+                    // centre on the triangle: its face normal (v1 - v0) x (v2 - v0)
+                    const V3<double> e1 = v3(W.g[3] - W.g[0], W.g[4] - W.g[1], W.g[5] - W.g[2]);
+                    const V3<double> e2 = v3(W.g[6] - W.g[0], W.g[7] - W.g[1], W.g[8] - W.g[2]);
+                    const V3<double> fn = cross(e1, e2);
+                    const double len = sqrt(dot(fn, fn));
+                    n64 = v3(fn.x / len, fn.y / len, fn.z / len);
+                }
+            }
         }
 
         if (!real) {
@@ -205,8 +257,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
             const Material M2 = glb<const Material>(a.mats)[m2];
             const double tanphi64 = glb<const double>(a.tanphi)[m1 * a.nmat + m2];
 
-            // ---- ScGeom inputs
-            const double R1d = wall ? r2 : r1;
+            // ---- ScGeom inputs (a boundary's reference radius: the sphere's,
+            // twice the sphere's for a facet)
+            const double R1d = wall ? ((PRIMS && W.kind == kFacet) ? 2.0 * r2 : r2) : r1;
             const double R2d = r2;
             // a wall does not move
             const V3<double> v1d = wall ? v3(0.0, 0.0, 0.0) : v3(va.x, va.y, va.z);
@@ -286,7 +339,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
             else
                 part.ss = 1;
             const double rmin = wall ? r2 : (r1 < r2 ? r1 : r2);
-            unstable = pen > rmin;
+            unstable = pen > rmin && !in_box;
             part.ov = pen / rmin;
             if constexpr (MEASURE) {
                 mf[0] = (double)F.x;
@@ -378,21 +431,32 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
     }
 }
 
-template <int PREC, bool BATCHED, bool PERIODIC, bool MEASURE = false>
+template <int PREC, bool BATCHED, bool PERIODIC, bool MEASURE = false, bool PRIMS = false>
 void launch_t(const StepArgs* args, int parity, int grid, int block, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
     const dim3 g(grid > 0 ? grid : 1), b(block);
     if (ev0)
-        hipExtLaunchKernelGGL((k_contact<PREC, BATCHED, PERIODIC, MEASURE>), g, b, 0, st, ev0, ev1, 0, args, parity);
+        hipExtLaunchKernelGGL((k_contact<PREC, BATCHED, PERIODIC, MEASURE, PRIMS>), g, b, 0, st, ev0, ev1, 0, args,
+                              parity);
     else
-        hipLaunchKernelGGL((k_contact<PREC, BATCHED, PERIODIC, MEASURE>), g, b, 0, st, args, parity);
+        hipLaunchKernelGGL((k_contact<PREC, BATCHED, PERIODIC, MEASURE, PRIMS>), g, b, 0, st, args, parity);
 }
 
 }  // namespace
 
 void launch_contact(const StepArgs* args, int parity, int grid, int precision, bool batched, bool periodic,
-                    int block, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, bool measure)
+                    int block, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, bool measure, bool prims)
 {
+    if (prims && !periodic) {
+        if (precision == DEM_FP32_MIXED) {
+            if (batched) launch_t<DEM_FP32_MIXED, true, false, false, true>(args, parity, grid, block, st, ev0, ev1);
+            else launch_t<DEM_FP32_MIXED, false, false, false, true>(args, parity, grid, block, st, ev0, ev1);
+        } else {
+            if (batched) launch_t<DEM_FP64, true, false, false, true>(args, parity, grid, block, st, ev0, ev1);
+            else launch_t<DEM_FP64, false, false, false, true>(args, parity, grid, block, st, ev0, ev1);
+        }
+        return;
+    }
     if (measure && periodic && !batched) {
         if (precision == DEM_FP32_MIXED) launch_t<DEM_FP32_MIXED, false, true, true>(args, parity, grid, block, st, ev0, ev1);
         else launch_t<DEM_FP64, false, true, true>(args, parity, grid, block, st, ev0, ev1);

@@ -17,7 +17,7 @@
 
 namespace dem {
 
-constexpr int kMaxWallsPerScene = 16;
+constexpr int kMaxWallsPerScene = 64;   // fixed boundaries (planes, boxes, facets) per scene
 constexpr uint32_t kNegSign = 0x80000000u;  // row entry: body is #1, adds -F
 constexpr uint32_t kPairMask = 0x7fffffffu;
 
@@ -50,13 +50,106 @@ struct SceneParams {
     double cellw[3];          // metric width of a grid cell along each axis (>= the cell size h)
 };
 
+// A fixed boundary: an infinite axis-aligned plane (utils.wall: axis,
+// sense, pos), an axis-aligned box (Box: g = lo[3], hi[3]) or a triangle
+// (Facet: g = v0, v1, v2).  It is #1 of its contacts.
+enum BoundaryKind : int32_t { kPlane = 0, kBox = 1, kFacet = 2 };
 struct Wall {
     int32_t axis;
     int32_t sense;
     int32_t mat;
     int32_t id;
     double pos;
+    int32_t kind;
+    int32_t pad_;
+    double g[9];
 };
+
+// Closest point of a box or a triangle to x (device code of the broad phase
+// and the contact kernel).  Box: the clamp of x to [lo, hi]; `inside` when x
+// is in the box.  Triangle: the region test over vertices, edges and face
+// by the signs of the barycentric quantities (Ericson, Real-Time Collision
+// Detection, section 5.1.5).
+__device__ inline void box_closest(const Wall& W, const double* x, double* p, bool* inside)
+{
+    bool in = true;
+    for (int k = 0; k < 3; ++k) {
+        const double lo = W.g[k], hi = W.g[3 + k];
+        p[k] = x[k] < lo ? lo : (x[k] > hi ? hi : x[k]);
+        if (x[k] < lo || x[k] > hi) in = false;
+    }
+    *inside = in;
+}
+
+__device__ inline void facet_closest(const Wall& W, const double* x, double* p)
+{
+    const double* a = &W.g[0];
+    const double* b = &W.g[3];
+    const double* c = &W.g[6];
+    double ab[3], ac[3], ap[3];
+    for (int k = 0; k < 3; ++k) {
+        ab[k] = b[k] - a[k];
+        ac[k] = c[k] - a[k];
+        ap[k] = x[k] - a[k];
+    }
+    auto dot = [](const double* u, const double* v) { return (u[0] * v[0] + u[1] * v[1]) + u[2] * v[2]; };
+    const double d1 = dot(ab, ap), d2 = dot(ac, ap);
+    if (d1 <= 0.0 && d2 <= 0.0) {
+        for (int k = 0; k < 3; ++k) p[k] = a[k];
+        return;
+    }
+    double bp[3];
+    for (int k = 0; k < 3; ++k) bp[k] = x[k] - b[k];
+    const double d3 = dot(ab, bp), d4 = dot(ac, bp);
+    if (d3 >= 0.0 && d4 <= d3) {
+        for (int k = 0; k < 3; ++k) p[k] = b[k];
+        return;
+    }
+    const double vc = d1 * d4 - d3 * d2;
+    if (vc <= 0.0 && d1 >= 0.0 && d3 <= 0.0) {
+        const double t = d1 / (d1 - d3);
+        for (int k = 0; k < 3; ++k) p[k] = a[k] + t * ab[k];
+        return;
+    }
+    double cp[3];
+    for (int k = 0; k < 3; ++k) cp[k] = x[k] - c[k];
+    const double d5 = dot(ab, cp), d6 = dot(ac, cp);
+    if (d6 >= 0.0 && d5 <= d6) {
+        for (int k = 0; k < 3; ++k) p[k] = c[k];
+        return;
+    }
+    const double vb = d5 * d2 - d1 * d6;
+    if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) {
+        const double t = d2 / (d2 - d6);
+        for (int k = 0; k < 3; ++k) p[k] = a[k] + t * ac[k];
+        return;
+    }
+    const double va = d3 * d6 - d5 * d4;
+    if (va <= 0.0 && (d4 - d3) >= 0.0 && (d5 - d6) >= 0.0) {
+        const double t = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+        for (int k = 0; k < 3; ++k) p[k] = b[k] + t * (c[k] - b[k]);
+        return;
+    }
+    const double den = 1.0 / ((va + vb) + vc);
+    const double v = vb * den, w = vc * den;
+    for (int k = 0; k < 3; ++k) p[k] = (a[k] + ab[k] * v) + ac[k] * w;
+}
+
+// Distance from x to a box or triangle (0 inside a box): the broad phase's
+// candidate test against a boundary.
+__device__ inline double boundary_distance(const Wall& W, const double* x)
+{
+    double p[3];
+    if (W.kind == kBox) {
+        bool inside;
+        box_closest(W, x, p, &inside);
+        if (inside) return 0.0;
+    } else {
+        facet_closest(W, x, p);
+    }
+    const double d0 = x[0] - p[0], d1 = x[1] - p[1], d2 = x[2] - p[2];
+    return sqrt((d0 * d0 + d1 * d1) + d2 * d2);
+}
 
 // Material constants as the kernels need them.
 struct Material {
@@ -327,9 +420,11 @@ void launch_partition(const PairBuildArgs& a, hipStream_t st);
 // measure: the step ends an update period of the controlled cell (periodic,
 // unbatched): the measuring instantiation runs (the host decides per step;
 // captured graphs are keyed by the period's phase at their first step)
+// prims: the world holds a box or a facet (aperiodic): the instantiation
+// with their geometry runs
 void launch_contact(const StepArgs* args, int parity, int grid, int precision, bool batched, bool periodic,
                     int block, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
-                    bool measure = false);
+                    bool measure = false, bool prims = false);
 
 // integrate.hip
 void launch_integrate(const StepArgs* args, int parity, int grid, int precision, bool batched, bool periodic,

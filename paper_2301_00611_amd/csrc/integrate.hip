@@ -486,7 +486,7 @@ __global__ void __launch_bounds__(kMeasureBlock) k_body_measures(StepArgs a, int
             const int sa = a.pr.a[k], sb = a.pr.b[k];
             const bool wall = sa < 0;
             const double r2 = a.bod.xr[sb].w;
-            const double r1 = wall ? r2 : a.bod.xr[sa].w;
+            const double r1 = wall ? (a.walls[-1 - sa].kind == kFacet ? 2.0 * r2 : r2) : a.bod.xr[sa].w;
             const int m1 = wall ? a.walls[-1 - sa].mat : (int)a.bod.mat[sa];
             const Material M1 = a.mats[m1], M2 = a.mats[a.bod.mat[sb]];
             const double k1 = M1.young * (2.0 * r1), k2 = M2.young * (2.0 * r2);

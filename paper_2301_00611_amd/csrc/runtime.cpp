@@ -299,6 +299,13 @@ struct World {
     }
 
     bool batched() const { return scenes.size() > 1; }
+    // a box or a facet among the boundaries: the contact kernel with their geometry
+    bool has_prims() const
+    {
+        for (const Wall& w : walls)
+            if (w.kind != kPlane) return true;
+        return false;
+    }
 
     void invalidate_graphs()
     {
@@ -483,9 +490,52 @@ struct World {
     {
         if (axis < 0 || axis > 2 || sense < -1 || sense > 1 || !std::isfinite(position))
             fail(DEM_EINVAL, "dem_add_wall: axis in 0..2, sense in -1..1, finite position");
-        if (mat < 0 || mat >= (int)mats.size()) fail(DEM_EINVAL, "dem_add_wall: unknown material");
-        if (scenes[s].p.periodic) fail(DEM_EINVAL, "dem_add_wall: walls are not supported in a periodic cell");
-        if (scenes[s].n_walls >= kMaxWallsPerScene) fail(DEM_EINVAL, "dem_add_wall: too many walls in one scene");
+        Wall w;
+        std::memset(&w, 0, sizeof w);
+        w.kind = kPlane;
+        w.axis = axis;
+        w.sense = sense;
+        w.pos = position;
+        return add_boundary(s, w, mat, "dem_add_wall");
+    }
+    int64_t add_box(int s, const double* c3, const double* h3, int mat)
+    {
+        if (!c3 || !h3) fail(DEM_EINVAL, "dem_add_box: null argument");
+        Wall w;
+        std::memset(&w, 0, sizeof w);
+        w.kind = kBox;
+        for (int k = 0; k < 3; ++k) {
+            if (!std::isfinite(c3[k]) || !(h3[k] > 0.0) || !std::isfinite(h3[k]))
+                fail(DEM_EINVAL, "dem_add_box: finite centre and half-sizes > 0");
+            w.g[k] = c3[k] - h3[k];
+            w.g[3 + k] = c3[k] + h3[k];
+        }
+        return add_boundary(s, w, mat, "dem_add_box");
+    }
+    int64_t add_facet(int s, const double* v0, const double* v1, const double* v2, int mat)
+    {
+        if (!v0 || !v1 || !v2) fail(DEM_EINVAL, "dem_add_facet: null argument");
+        Wall w;
+        std::memset(&w, 0, sizeof w);
+        w.kind = kFacet;
+        const double* v[3] = {v0, v1, v2};
+        for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 3; ++k) {
+                if (!std::isfinite(v[i][k])) fail(DEM_EINVAL, "dem_add_facet: non-finite vertex");
+                w.g[3 * i + k] = v[i][k];
+            }
+        const double e1[3] = {v1[0] - v0[0], v1[1] - v0[1], v1[2] - v0[2]};
+        const double e2[3] = {v2[0] - v0[0], v2[1] - v0[1], v2[2] - v0[2]};
+        const double c[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        if (!((c[0] * c[0] + c[1] * c[1]) + c[2] * c[2] > 0.0)) fail(DEM_EINVAL, "dem_add_facet: degenerate triangle");
+        return add_boundary(s, w, mat, "dem_add_facet");
+    }
+    // A fixed boundary (plane, box, facet) of scene s.
+    int64_t add_boundary(int s, Wall w, int mat, const char* who)
+    {
+        if (mat < 0 || mat >= (int)mats.size()) fail(DEM_EINVAL, std::string(who) + ": unknown material");
+        if (scenes[s].p.periodic) fail(DEM_EINVAL, std::string(who) + ": boundaries are not supported in a periodic cell");
+        if (scenes[s].n_walls >= kMaxWallsPerScene) fail(DEM_EINVAL, std::string(who) + ": too many boundaries in one scene");
         pull_bodies();
         HostScene& S = scenes[s];
         HostBody b;
@@ -495,12 +545,8 @@ struct World {
         b.mat = mat;
         b.q[0] = 1.0;
         const int32_t gid = (int32_t)bodies.size();
-        Wall w;
-        w.axis = axis;
-        w.sense = sense;
         w.mat = mat;
         w.id = gid;
-        w.pos = position;
         // keep the wall table grouped by scene
         int at = 0;
         while (at < (int)walls.size() && wall_scene[at] <= s) ++at;
@@ -1165,7 +1211,7 @@ struct World {
     {
         const StepArgs* a = d_args.as<StepArgs>();
         launch_contact(a, parity, grid_c, precision, batched(), periodic, block_contact, stream, ev ? ev[0] : nullptr,
-                       ev ? ev[1] : nullptr, periodic && pt_active && measure);
+                       ev ? ev[1] : nullptr, periodic && pt_active && measure, has_prims());
         launch_integrate(a, parity, grid_i, precision, batched(), periodic, block_integrate, stream,
                          ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
         if (periodic && pt_active && measure) launch_ctrl_reduce(a, parity, stream);
@@ -1180,8 +1226,8 @@ struct World {
     std::string graph_key(int n, int phase) const
     {
         char buf[256];
-        std::snprintf(buf, sizeof buf, "%p/%d/%d/%d/%d/%d/%d/%d/%d/%d", d_args.p, grid_c, grid_i, n, timing ? 1 : 0,
-                      block_contact, block_integrate, pt_active ? 1 : 0, ctrl_period(), phase);
+        std::snprintf(buf, sizeof buf, "%p/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d", d_args.p, grid_c, grid_i, n, timing ? 1 : 0,
+                      block_contact, block_integrate, pt_active ? 1 : 0, ctrl_period(), phase, has_prims() ? 1 : 0);
         return buf;
     }
 
@@ -1444,6 +1490,15 @@ struct World {
             fail(DEM_ERANGE, "Body id out of range");
     }
 
+    // Reported position of a boundary: a plane's coordinate on its axis (0
+    // elsewhere), a box's centre, a facet's centroid.
+    static double boundary_position(const Wall& W, int k)
+    {
+        if (W.kind == kPlane) return k == W.axis ? W.pos : 0.0;
+        if (W.kind == kBox) return 0.5 * (W.g[k] + W.g[3 + k]);
+        return (W.g[k] + W.g[3 + k] + W.g[6 + k]) / 3.0;
+    }
+
     void get_state(int s, int64_t first, int64_t count, double* pos3, double* vel3, double* angvel3, double* ori4,
                    double* force3, double* torque3)
     {
@@ -1453,7 +1508,7 @@ struct World {
             for (int64_t i = 0; i < count; ++i) {
                 const HostBody& b = bodies[S.gids[first + i]];
                 for (int k = 0; k < 3; ++k) {
-                    if (pos3) pos3[3 * i + k] = b.kind ? (k == walls[b.wall].axis ? walls[b.wall].pos : 0.0) : b.x[k];
+                    if (pos3) pos3[3 * i + k] = b.kind ? boundary_position(walls[b.wall], k) : b.x[k];
                     if (vel3) vel3[3 * i + k] = b.v[k];
                     if (angvel3) angvel3[3 * i + k] = b.w[k];
                     if (force3) force3[3 * i + k] = 0.0;
@@ -1496,7 +1551,7 @@ struct World {
             if (b.kind == 1) {
                 const Wall& W = walls[b.wall];
                 for (int k = 0; k < 3; ++k) {
-                    if (pos3) pos3[3 * i + k] = k == W.axis ? W.pos : 0.0;
+                    if (pos3) pos3[3 * i + k] = boundary_position(W, k);
                     if (vel3) vel3[3 * i + k] = 0.0;
                     if (angvel3) angvel3[3 * i + k] = 0.0;
                     if (force3) force3[3 * i + k] = wallF[3 * b.wall + k];
@@ -1795,7 +1850,7 @@ struct World {
             c.fn[2] = p.fz[k] - p.fsz[k];
             const HostMaterial& M2 = mats[B2.mat];
             const HostMaterial& M1 = wall ? mats[walls[-1 - p.a[k]].mat] : mats[B1->mat];
-            const double R1 = wall ? B2.r : B1->r, R2 = B2.r;
+            const double R1 = wall ? (walls[-1 - p.a[k]].kind == kFacet ? 2.0 * B2.r : B2.r) : B1->r, R2 = B2.r;
             const double k1 = M1.young * (2.0 * R1), k2 = M2.young * (2.0 * R2);
             c.kn = k1 * k2 / (k1 + k2);
             const double q1 = (M1.young * M1.poisson) * (2.0 * R1), q2 = (M2.young * M2.poisson) * (2.0 * R2);
@@ -2080,6 +2135,25 @@ dem_status dem_add_wall(dem_scene* s, int32_t axis, double position, int32_t sen
     return guarded([&] {
         dem::World* w = world_of(s);
         const int64_t id = w->add_wall(s->s, axis, position, sense, mat);
+        if (out_id) *out_id = id;
+    });
+}
+
+dem_status dem_add_box(dem_scene* s, const double* center3, const double* half3, int32_t mat, int64_t* out_id)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        const int64_t id = w->add_box(s->s, center3, half3, mat);
+        if (out_id) *out_id = id;
+    });
+}
+
+dem_status dem_add_facet(dem_scene* s, const double* v0, const double* v1, const double* v2, int32_t mat,
+                         int64_t* out_id)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        const int64_t id = w->add_facet(s->s, v0, v1, v2, mat);
         if (out_id) *out_id = id;
     });
 }

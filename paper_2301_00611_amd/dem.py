@@ -157,6 +157,8 @@ SIGNATURES = {
     "dem_autotune": (C.c_int32, [C.c_void_p, C.c_int64, C.c_char_p, C.POINTER(dem_tuning)]),
     "dem_batch_set_tuning": (C.c_int32, [C.c_void_p, C.POINTER(dem_tuning)]),
     "dem_batch_autotune": (C.c_int32, [C.c_void_p, C.c_int64, C.c_char_p, C.POINTER(dem_tuning)]),
+    "dem_add_box": (C.c_int32, [C.c_void_p, _DP, _DP, C.c_int32, _I64P]),
+    "dem_add_facet": (C.c_int32, [C.c_void_p, _DP, _DP, _DP, C.c_int32, _I64P]),
     "dem_get_unbalanced_force": (C.c_int32, [C.c_void_p, C.c_int32, _DP]),
     "dem_stiffness_dt": (C.c_int32, [C.c_void_p, C.c_double, _DP]),
     "dem_set_stiffness_timestepper": (C.c_int32, [C.c_void_p, C.c_double, C.c_int64]),
@@ -211,6 +213,30 @@ def _f64(a, shape):
     if a is None:
         return None
     return np.ascontiguousarray(a, dtype=np.float64).reshape(shape)
+
+
+def facet_box_triangles(center, half, wall_mask=63):
+    """The triangles of geom.facetBox: each kept face of the box with the
+    given centre and half-sizes split along a diagonal into two triangles.
+    Face order x-, x+, y-, y+, z-, z+ (wall_mask bits 1, 2, 4, 8, 16, 32)."""
+    c = np.asarray(center, dtype=np.float64)
+    h = np.asarray(half, dtype=np.float64)
+    tris = []
+    for axis in range(3):
+        u, v = [a for a in range(3) if a != axis]
+        for side, bit in ((-1.0, 1 << (2 * axis)), (1.0, 1 << (2 * axis + 1))):
+            if not (wall_mask & bit):
+                continue
+            corners = []
+            for su, sv in ((-1, -1), (1, -1), (1, 1), (-1, 1)):
+                p = c.copy()
+                p[axis] += side * h[axis]
+                p[u] += su * h[u]
+                p[v] += sv * h[v]
+                corners.append(p)
+            tris.append((corners[0], corners[1], corners[2]))
+            tris.append((corners[0], corners[2], corners[3]))
+    return tris
 
 
 def make_params(dt=0.0, gravity=(0.0, 0.0, 0.0), damping=0.2, damp_rot=True, verlet_dist=-0.5,
@@ -289,6 +315,24 @@ class Scene:
         check(self.lib.dem_add_wall(self.h, int(axis), float(position), int(sense), int(mat), C.byref(out)),
               "dem_add_wall")
         return out.value
+
+    def add_box(self, center, half, mat=0):
+        c, h = _f64(center, (3,)), _f64(half, (3,))
+        out = C.c_int64()
+        check(self.lib.dem_add_box(self.h, _p(c), _p(h), int(mat), C.byref(out)), "dem_add_box")
+        return out.value
+
+    def add_facet(self, v0, v1, v2, mat=0):
+        a, b, c = _f64(v0, (3,)), _f64(v1, (3,)), _f64(v2, (3,))
+        out = C.c_int64()
+        check(self.lib.dem_add_facet(self.h, _p(a), _p(b), _p(c), int(mat), C.byref(out)), "dem_add_facet")
+        return out.value
+
+    def add_facet_box(self, center, half, mat=0, wall_mask=63):
+        """geom.facetBox: the faces of an axis-aligned box as two facets
+        each; wall_mask bits 1, 2, 4, 8, 16, 32 keep the x-, x+, y-, y+, z-,
+        z+ faces.  Returns the facets' ids."""
+        return [self.add_facet(*tri, mat=mat) for tri in facet_box_triangles(center, half, wall_mask)]
 
     def pwave_dt(self):
         out = C.c_double()

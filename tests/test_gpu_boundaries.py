@@ -1,0 +1,210 @@
+"""Parity of the GPU's box and facet boundaries (C ABI) with the oracle's
+(Ig2_Box_Sphere_ScGeom, Ig2_Facet_Sphere_ScGeom readings), and their closed
+forms through the GPU path.
+
+Bars as for the rest of the step: pair sets identical, forces within 1e-12
+(FP64) from an identical state; a 1,000-step deposition into a facet box
+with a box obstacle keeps identical pair sets at every check and its energy
+terms within 1 %.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_helpers import contact_errors, keyset
+
+pytestmark = pytest.mark.gpu
+
+R = 2.0 ** -10
+E, NU, RHO = 1e7, 0.3, 1000.0
+
+
+def _both(build, gravity=(0.0, 0.0, 0.0), damping=0.0, dt_factor=0.2, precision=0):
+    """The same boundaries and spheres in the GPU library and the oracle."""
+    from oracle import OracleScene
+    from paper_2301_00611_amd import dem
+    g = dem.Scene(gravity=gravity, damping=damping, precision=precision, track_energy=True)
+    mg = g.add_material(RHO, E, NU, 0.5)
+    o = OracleScene(dt=1.0, gravity=gravity, damping=damping)
+    mo = o.add_material(RHO, E, NU, 0.5)
+    build(g, mg, o, mo)
+    dt = dt_factor * g.pwave_dt()
+    g.set_dt(dt)
+    o.set_dt(dt)
+    return g, o
+
+
+def _container(g, mg, o, mo, side):
+    """A facet box open at the top (geom.facetBox, wallMask without z+) and a
+    box obstacle on its floor."""
+    from paper_2301_00611_amd.dem import facet_box_triangles
+    c = np.array([0.5 * side, 0.5 * side, 0.5 * side])
+    for tri in facet_box_triangles(c, [0.5 * side] * 3, wall_mask=31):
+        g.add_facet(*tri, mat=mg)
+        o.add_facet(*tri, mat=mo)
+    bc, bh = [0.5 * side, 0.5 * side, 0.1 * side], [0.15 * side, 0.1 * side, 0.1 * side]
+    g.add_box(bc, bh, mg)
+    o.add_box(bc, bh, mo)
+
+
+def _cloud(side, seed):
+    """Lattice nodes of spacing 2r filling the container (the outer ones r
+    from its faces), jittered by up to 0.2 r, radii U(0.85, 1.05) r: many
+    sphere-sphere and sphere-facet overlaps, none beyond the smaller radius;
+    nodes whose centre would be within 0.2 r of the box obstacle are left
+    out (a centre inside a box is an overlap beyond the radius)."""
+    rng = np.random.default_rng(seed)
+    k = int(round(side / (2 * R)))
+    g = (np.arange(k) + 0.5) * (side / k)
+    nodes = np.array([[x, y, z] for z in g for y in g for x in g])
+    pos = nodes + rng.uniform(-0.2, 0.2, nodes.shape) * R
+    bc, bh = np.array([0.5 * side, 0.5 * side, 0.1 * side]), np.array([0.15 * side, 0.1 * side, 0.1 * side])
+    far = np.any(np.abs(pos - bc) > bh + 0.2 * R, axis=1)
+    pos = pos[far]
+    rad = rng.uniform(0.85 * R, 1.05 * R, len(pos))
+    return pos, rad
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_one_step_against_boundaries(seed):
+    """Spheres scattered through a facet box with a box obstacle, many of
+    them crossing or touching facets, edges, corners and the box: one step
+    from random velocities."""
+    side = 24 * R
+    pos, rad = _cloud(side, seed)
+    n = len(pos)
+    vel = np.random.default_rng(seed + 5).normal(0.0, 0.05, (n, 3))
+
+    def build(g, mg, o, mo):
+        _container(g, mg, o, mo, side)
+        g.add_spheres(pos, rad, vel=vel, default_mat=mg)
+        o.add_spheres(pos, rad, vel=vel, default_mat=mo)
+
+    g, o = _both(build)
+    g.step(1)
+    o.step(1)
+    cg, co = g.get_contacts(), o.get_contacts()
+    assert keyset(cg) == keyset(co)
+    nb = int((co["is_wall"] == 1).sum())
+    assert nb > 40, "the cloud should touch the boundaries"
+    err = contact_errors(cg, co)
+    assert err["f"].max() <= 1e-12
+    assert err["normal"].max() <= 1e-13
+    sg, so = g.get_state(), o.get_state()
+    scale = np.abs(so["pos"]).max()
+    assert np.abs(sg["pos"] - so["pos"]).max() <= 1e-14 * scale
+    # boundary reactions: minus the sum of the forces on the touching spheres
+    assert np.allclose(sg["force"][:11], so["force"][:11], rtol=1e-10, atol=1e-12 * np.abs(so["force"]).max())
+
+
+def test_deposition_in_a_facet_box():
+    """500 spheres thrown into the open facet box onto the box obstacle,
+    damping 0.3, 1,000 steps: identical pair sets every 100 steps while the
+    runs coincide, energy terms within 1 % over the run."""
+    side = 30 * R
+    n = 500
+    rng = np.random.default_rng(7)
+    k = 8
+    grid = (np.arange(k) + 0.5) * (side / k)
+    nodes = np.array([[x, y, z] for z in grid for y in grid for x in grid])[:n]
+    rad = rng.uniform(0.8 * R, 1.2 * R, n)
+    pos = nodes + rng.uniform(-0.3, 0.3, (n, 3)) * R
+    pos[:, 2] += 0.2 * side
+    # 1,000 steps are about 3 ms of physical time: the spheres are thrown
+    # down at 4 m/s (about 12 r in that time) with a lateral spread, so that
+    # they reach the floor, the obstacle and the side facets
+    vel = rng.normal(0.0, 1.0, (n, 3))
+    vel[:, 2] -= 4.0
+
+    def build(g, mg, o, mo):
+        _container(g, mg, o, mo, side)
+        g.add_spheres(pos, rad, vel=vel, default_mat=mg)
+        o.add_spheres(pos, rad, vel=vel, default_mat=mo)
+
+    g, o = _both(build, gravity=(0.0, 0.0, -9.81), damping=0.3, dt_factor=0.3)
+    sg_, so_ = [], []
+    touched = 0
+    for step in range(10):
+        g.step(100)
+        o.step(100)
+        cg, co = g.get_contacts(), o.get_contacts()
+        assert keyset(cg) == keyset(co), f"pair sets differ after {100 * (step + 1)} steps"
+        touched += int((co["is_wall"] == 1).sum())
+        if len(co):
+            assert contact_errors(cg, co)["f"].max() <= 1e-8
+        eg, eo = g.get_energy(), o.get_energy()
+        sg_.append([eg[x] for x in ("kinetic", "grav_work", "damp_dissip", "elastic", "plastic_dissip")])
+        so_.append([eo[x] for x in ("kinetic", "grav_work", "damp_dissip", "elastic", "plastic_dissip")])
+    assert touched > 0
+    a, b = np.array(sg_), np.array(so_)
+    # each term within 1 % of the largest (the initial kinetic energy)
+    assert np.abs(a - b).max() <= 0.01 * np.abs(b).max()
+    assert b[-1, 2] > 0.0 and b[-1, 4] > 0.0       # damping and sliding did act
+
+
+@pytest.mark.parametrize("case", ["box_edge", "box_corner", "box_inside", "facet_vertex", "facet_face_below"])
+def test_boundary_closed_forms_on_the_gpu(case):
+    """A few of the oracle's closed-form cases through the GPU path: normal,
+    overlap and k_n (E r for a box, 4/3 E r for a facet)."""
+    half = np.array([4 * R, 3 * R, 2 * R])
+    L = 8 * R
+    tri = ([0.0, 0.0, 0.0], [L, 0.0, 0.0], [0.0, L, 0.0])
+    if case == "box_edge":
+        d = 0.6 * R
+        a = d / math.sqrt(2.0)
+        center, normal, pen, kn = [half[0] + a, 0.5 * R, half[2] + a], [1, 0, 1], R - d, E * R
+    elif case == "box_corner":
+        d = 0.8 * R
+        a = d / math.sqrt(3.0)
+        center, normal, pen, kn = [half[0] + a, half[1] + a, half[2] + a], [1, 1, 1], R - d, E * R
+    elif case == "box_inside":
+        center, normal, pen, kn = [0.0, 0.0, half[2] - 0.3 * R], [0, 0, 1], 1.3 * R, E * R
+    elif case == "facet_vertex":
+        a, b = 0.25 * R, 0.35 * R
+        center, normal, pen = [-a, -a, b], [-a, -a, b], R - math.sqrt(2 * a * a + b * b)
+        kn = (E * 4 * R) * (E * 2 * R) / (E * 6 * R)
+    else:
+        h = 0.4 * R
+        center, normal, pen = [L / 4, L / 4, -h], [0, 0, -1], R - h
+        kn = (E * 4 * R) * (E * 2 * R) / (E * 6 * R)
+
+    def build(g, mg, o, mo):
+        if case.startswith("box"):
+            g.add_box([0, 0, 0], half, mg)
+            o.add_box([0, 0, 0], half, mo)
+        else:
+            g.add_facet(*tri, mat=mg)
+            o.add_facet(*tri, mat=mo)
+        g.add_spheres(np.asarray([center], dtype=float), [R], default_mat=mg)
+        o.add_spheres(np.asarray([center], dtype=float), [R], default_mat=mo)
+
+    g, o = _both(build, dt_factor=0.1)
+    g.step(1)
+    c = g.get_contacts()
+    assert len(c) == 1 and c["is_wall"][0] == 1 and c["id1"][0] == 0
+    n = np.asarray(normal, dtype=float)
+    n /= np.linalg.norm(n)
+    assert np.allclose(c["normal"][0], n, rtol=0, atol=1e-13)
+    assert c["pen"][0] == pytest.approx(pen, rel=1e-10)
+    assert c["kn"][0] == pytest.approx(kn, rel=1e-14)
+
+
+def test_boundary_call_errors():
+    from paper_2301_00611_amd import dem
+    g = dem.Scene(gravity=(0, 0, 0))
+    m = g.add_material(RHO, E, NU, 0.5)
+    with pytest.raises(dem.DemError):
+        g.add_box([0, 0, 0], [1.0, 0.0, 1.0], m)
+    with pytest.raises(dem.DemError):
+        g.add_facet([0, 0, 0], [1, 1, 1], [2, 2, 2], m)
+    with pytest.raises(dem.DemError):
+        g.add_facet([0, 0, 0], [1, 0, 0], [0, 1, 0], 7)
+    p = dem.Scene(periodic=True, hsize=np.eye(3) * 0.1)
+    mp = p.add_material(RHO, E, NU, 0.5)
+    with pytest.raises(dem.DemError):
+        p.add_box([0, 0, 0], [1, 1, 1], mp)
+    ids = [g.add_facet(*t, mat=m) for t in dem.facet_box_triangles([0, 0, 0], [1, 1, 1], wall_mask=63)]
+    assert len(ids) == 12 and ids == list(range(12))
+    st = g.get_state()
+    assert np.allclose(st["pos"][0], [-1.0, 1.0 / 3.0, -1.0 / 3.0])
