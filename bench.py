@@ -66,6 +66,10 @@ def build_scene(spec, precision=0, timing=False):
     mat = s.add_material(m.density, m.young, m.poisson, m.friction)
     for w in spec.walls:
         s.add_wall(w.axis, w.position, w.sense, mat)
+    for c, h in spec.boxes:
+        s.add_box(c, h, mat)
+    for tri in spec.facets:
+        s.add_facet(*tri, mat=mat)
     s.add_spheres(spec.pos, spec.radius, default_mat=mat)
     s.set_dt(spec.dt_factor * s.pwave_dt())
     s.set_timing(timing)
@@ -164,7 +168,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32-mixed, batched and CPU legs")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="column",
-                    choices=("column", "periodic_compression", "periodic_shear", "batched"),
+                    choices=("column", "periodic_compression", "periodic_shear", "batched", "facet_column"),
                     help="column: the headline line (default); the others run one extra leg alone")
     ap.add_argument("--prepared-state", default=None,
                     help="periodic_compression: .npz holding the prepared packing (written if missing)")
@@ -194,6 +198,9 @@ def main():
         return
     if args.workload == "batched":
         print(json.dumps(batched_leg(steps=args.steps, log=log)), flush=True)
+        return
+    if args.workload == "facet_column":
+        print(json.dumps(facet_column_leg(args.steps, args.warmup, log=log, cache=args.tuning_cache)), flush=True)
         return
 
     from paper_2301_00611_amd.scenes import grid_column
@@ -255,12 +262,39 @@ def main():
         out["fp32_mixed"] = {"value": r32["contact_steps"] / r32["seconds"], "unit": "contact-steps/s",
                              "ms_per_step": r32["seconds"] / args.steps * 1e3}
         out["batched"] = batched_leg(log=log)
+        log("facet-box column leg")
+        out["facet_column"] = facet_column_leg(args.steps, args.warmup, log=log, cache=args.tuning_cache)
         log("periodic compression leg (FP64 vs FP32-mixed)")
         out["periodic_compression"] = periodic_leg("periodic_compression", log=log)
     if not args.no_cpu and not args.no_extra:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(spec)
     print(json.dumps(out), flush=True)
+
+
+def facet_column_leg(steps, warmup, log=None, cache=None):
+    """The 200,000-sphere column of the headline line in an open-topped
+    facet box (geom.facetBox, wallMask=31: 10 triangles) instead of its 5
+    planes: the contact kernel's box/facet instantiation and the broad
+    phase's closest-point tests at full size."""
+    from paper_2301_00611_amd.scenes import grid_column
+    spec = grid_column(n=200_000, seed=0, boundary="facets")
+    tune = autotune_for(spec, 0, warmup=warmup, cache=cache)
+    if log:
+        log(f"facet column: {spec.n} spheres, {len(spec.facets)} facets, {steps} steps, setting {tune}")
+    r = timed_run(spec, steps, warmup, precision=0, tuning=tune)
+    rt = timed_run(spec, steps, 0, precision=0, timing=True, tuning=tune)
+    return {
+        "workload": "grid_column deposition in an open facet box: 200,000 spheres r~U(0.5,1.5) mm, "
+                    "0.1x0.1 m footprint, 10 facets, E=5e7, nu=0.3, phi=0.5, damping 0.2, dt=0.5*P-wave",
+        "value": r["contact_steps"] / r["seconds"],
+        "unit": "contact-steps/s",
+        "ms_per_step": r["seconds"] / steps * 1e3,
+        "rebuilds": r["rebuilds"],
+        "tuning": tune,
+        "kernels_ms": {k: v["avg_ms"] for k, v in rt["kernels"].items()},
+        "contacts_last": r["contacts_last"],
+    }
 
 
 def _periodic_scene(H, L, spec, pos, vel, angvel, precision, friction=None, track_energy=False):

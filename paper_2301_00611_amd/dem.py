@@ -16,6 +16,8 @@ import os
 
 import numpy as np
 
+from .geom import aabb_walls, facet_box_triangles, packing_extrema  # noqa: F401  (re-exported)
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdem_hip.so")
 
@@ -215,30 +217,6 @@ def _f64(a, shape):
     return np.ascontiguousarray(a, dtype=np.float64).reshape(shape)
 
 
-def facet_box_triangles(center, half, wall_mask=63):
-    """The triangles of geom.facetBox: each kept face of the box with the
-    given centre and half-sizes split along a diagonal into two triangles.
-    Face order x-, x+, y-, y+, z-, z+ (wall_mask bits 1, 2, 4, 8, 16, 32)."""
-    c = np.asarray(center, dtype=np.float64)
-    h = np.asarray(half, dtype=np.float64)
-    tris = []
-    for axis in range(3):
-        u, v = [a for a in range(3) if a != axis]
-        for side, bit in ((-1.0, 1 << (2 * axis)), (1.0, 1 << (2 * axis + 1))):
-            if not (wall_mask & bit):
-                continue
-            corners = []
-            for su, sv in ((-1, -1), (1, -1), (1, 1), (-1, 1)):
-                p = c.copy()
-                p[axis] += side * h[axis]
-                p[u] += su * h[u]
-                p[v] += sv * h[v]
-                corners.append(p)
-            tris.append((corners[0], corners[1], corners[2]))
-            tris.append((corners[0], corners[2], corners[3]))
-    return tris
-
-
 def make_params(dt=0.0, gravity=(0.0, 0.0, 0.0), damping=0.2, damp_rot=True, verlet_dist=-0.5,
                 precision=DEM_FP64, periodic=False, hsize=None, velgrad=None, homo_deform=2,
                 track_energy=False, device=0, stream=None):
@@ -333,6 +311,12 @@ class Scene:
         each; wall_mask bits 1, 2, 4, 8, 16, 32 keep the x-, x+, y-, y+, z-,
         z+ faces.  Returns the facets' ids."""
         return [self.add_facet(*tri, mat=mat) for tri in facet_box_triangles(center, half, wall_mask)]
+
+    def add_aabb_walls(self, extrema, mat=0, thickness=None, oversize_factor=1.5):
+        """utils.aabbWalls: six boxes wrapping the packing whose bounding box
+        is extrema = (lo, hi) (see geom.aabb_walls for the placement), in the
+        order min x, max x, min y, max y, min z, max z.  Returns their ids."""
+        return [self.add_box(c, h, mat) for c, h in aabb_walls(extrema, thickness, oversize_factor)]
 
     def pwave_dt(self):
         out = C.c_double()

@@ -56,6 +56,8 @@ class Scene:
     radius: np.ndarray              # (n,) float64 [m]
     material: Material
     walls: list = field(default_factory=list)
+    boxes: list = field(default_factory=list)     # (centre, half-sizes) pairs, added after the walls
+    facets: list = field(default_factory=list)    # (v0, v1, v2) triples, added after the boxes
     vel: np.ndarray | None = None   # (n, 3)
     angvel: np.ndarray | None = None
     gravity: tuple = (0.0, 0.0, -9.81)
@@ -66,6 +68,11 @@ class Scene:
     hsize: np.ndarray | None = None
     velgrad: np.ndarray | None = None
     name: str = ""
+
+    @property
+    def n_boundaries(self) -> int:
+        """Walls, boxes and facets: the ids before the first sphere."""
+        return len(self.walls) + len(self.boxes) + len(self.facets)
 
     @property
     def n(self) -> int:
@@ -133,8 +140,12 @@ def cloud_box(n: int = 1000, box: float = 0.030, rmin: float = 0.9e-3, rmax: flo
 
 def grid_column(n: int = 200_000, width: float = 0.1, spacing: float = 3.03e-3,
                 rmin: float = 0.5e-3, rmax: float = 1.5e-3, seed: int = 0, young: float = 5e7,
-                steps: int = 10_000, side_walls: bool = True) -> Scene:
+                steps: int = 10_000, side_walls: bool = True, boundary: str = "walls") -> Scene:
     """C2: jittered column grid above a floor (z = 0) inside 4 side walls.
+
+    boundary="facets" puts the same column in an open-topped facet box
+    (geom.facetBox with wallMask=31, 10 triangles) over [0, width]^2 x
+    [0, top + r_max] instead of the 5 planes.
 
     Node (i, j, k) sits at ((i + 1/2) s, (j + 1/2) s, (k + 1/2) s), filled
     layer by layer (x fastest), and each centre is jittered by U(-j, j) per
@@ -151,12 +162,20 @@ def grid_column(n: int = 200_000, width: float = 0.1, spacing: float = 3.03e-3,
     nodes = (np.stack([ix, iy, iz], axis=1).astype(np.float64) + 0.5) * spacing
     jit = (spacing - 2.0 * radius) / 2.0
     pos = nodes + rng.uniform(-1.0, 1.0, size=(n, 3)) * jit[:, None]
-    walls = [Wall(2, 0.0, 1)]
+    walls, facets = [Wall(2, 0.0, 1)], []
     if side_walls:
         walls += [Wall(0, 0.0, 0), Wall(0, width, 0), Wall(1, 0.0, 0), Wall(1, width, 0)]
-    return Scene(pos=pos, radius=radius, material=Material(2600.0, young, 0.3, 0.5), walls=walls,
+    if boundary == "facets":
+        from .geom import facet_box_triangles
+        height = float((pos[:, 2] + radius).max()) + rmax
+        walls = []
+        facets = facet_box_triangles((0.5 * width, 0.5 * width, 0.5 * height), (0.5 * width, 0.5 * width, 0.5 * height),
+                                     wall_mask=31)
+    elif boundary != "walls":
+        raise ValueError("grid_column: boundary is 'walls' or 'facets'")
+    return Scene(pos=pos, radius=radius, material=Material(2600.0, young, 0.3, 0.5), walls=walls, facets=facets,
                  gravity=(0.0, 0.0, -9.81), damping=0.2, dt_factor=0.5, steps=steps,
-                 name=f"grid_column_{n}")
+                 name=f"grid_column_{n}" + ("_facets" if facets else ""))
 
 
 @dataclass

@@ -18,6 +18,10 @@ def twin(spec, precision=0, track_energy=True, periodic=False, hsize=None, velgr
     mg = g.add_material(m.density, m.young, m.poisson, m.friction)
     for w in spec.walls:
         g.add_wall(w.axis, w.position, w.sense, mg)
+    for c, h in getattr(spec, "boxes", []):
+        g.add_box(c, h, mg)
+    for tri in getattr(spec, "facets", []):
+        g.add_facet(*tri, mat=mg)
     g.add_spheres(spec.pos, spec.radius, vel=vel, angvel=angvel, default_mat=mg)
     if dt is None:
         dt = spec.dt_factor * g.pwave_dt()
@@ -27,6 +31,10 @@ def twin(spec, precision=0, track_energy=True, periodic=False, hsize=None, velgr
     mo = o.add_material(m.density, m.young, m.poisson, m.friction)
     for w in spec.walls:
         o.add_wall(w.axis, w.position, w.sense, mo)
+    for c, h in getattr(spec, "boxes", []):
+        o.add_box(c, h, mo)
+    for tri in getattr(spec, "facets", []):
+        o.add_facet(*tri, mat=mo)
     o.add_spheres(spec.pos, spec.radius, vel=vel, angvel=angvel, default_mat=mo)
     assert spec.dt_factor * o.pwave_dt() == spec.dt_factor * g.pwave_dt()
     return g, o, dt

@@ -208,3 +208,76 @@ def test_boundary_call_errors():
     assert len(ids) == 12 and ids == list(range(12))
     st = g.get_state()
     assert np.allclose(st["pos"][0], [-1.0, 1.0 / 3.0, -1.0 / 3.0])
+
+
+def test_aabb_walls_one_step():
+    """A jittered lattice pressed into utils.aabbWalls boxes (their inner
+    faces 0.3 r inside the packing's bounding box): one step from random
+    velocities, pair sets identical, forces within 1e-12."""
+    from paper_2301_00611_amd.geom import aabb_walls, packing_extrema
+    rng = np.random.default_rng(11)
+    k = 9
+    grid = (np.arange(k) + 0.5) * 2.2 * R
+    pos = np.array([[x, y, z] for z in grid for y in grid for x in grid])
+    pos += rng.uniform(-0.05, 0.05, pos.shape) * R
+    rad = rng.uniform(0.95 * R, 1.05 * R, len(pos))
+    lo, hi = packing_extrema(pos, rad)
+    walls = aabb_walls((lo + 0.3 * R, hi - 0.3 * R))
+    vel = rng.normal(0.0, 0.05, pos.shape)
+
+    def build(g, mg, o, mo):
+        ids = g.add_aabb_walls((lo + 0.3 * R, hi - 0.3 * R), mg)
+        assert ids == list(range(6))
+        for c, h in walls:
+            o.add_box(c, h, mo)
+        g.add_spheres(pos, rad, vel=vel, default_mat=mg)
+        o.add_spheres(pos, rad, vel=vel, default_mat=mo)
+
+    g, o = _both(build)
+    g.step(1)
+    o.step(1)
+    cg, co = g.get_contacts(), o.get_contacts()
+    assert keyset(cg) == keyset(co)
+    assert int((co["is_wall"] == 1).sum()) >= 6 * k * k - 12 * k      # most outer spheres touch a wall
+    err = contact_errors(cg, co)
+    assert err["f"].max() <= 1e-12
+    sg, so = g.get_state(), o.get_state()
+    assert np.abs(sg["pos"] - so["pos"]).max() <= 1e-14 * np.abs(so["pos"]).max()
+
+
+def test_full_size_spot_check_facet_column():
+    """The benchmark's 200,000-sphere column in an open facet box,
+    compressed so that many pairs overlap and the lowest and outermost
+    spheres cross the facets, with random velocities: one step on the GPU
+    against the oracle's spot mode on sampled bodies (half of them next to
+    a facet), each evaluated against all N and every facet."""
+    from oracle import OracleScene
+    from paper_2301_00611_amd.scenes import grid_column, random_velocities
+    from gpu_helpers import twin
+    spec = grid_column(n=200_000, spacing=2.6e-3, seed=0, boundary="facets")
+    n, nb = spec.n, spec.n_boundaries
+    assert nb == 10 and not spec.walls
+    v, w = random_velocities(n, 0.02, 9)
+    g, _, dt = twin(spec, vel=v, angvel=w * 0.05, track_energy=False)
+    o = OracleScene(dt=dt, gravity=spec.gravity, damping=spec.damping)
+    mo = o.add_material(2600.0, spec.material.young, 0.3, 0.5)
+    for tri in spec.facets:
+        o.add_facet(*tri, mat=mo)
+    o.add_spheres(spec.pos, spec.radius, vel=v, angvel=w * 0.05, default_mat=mo)
+    rng = np.random.default_rng(5)
+    near = np.flatnonzero((spec.pos[:, 0] < spec.radius) | (spec.pos[:, 1] < spec.radius)
+                          | (spec.pos[:, 2] < spec.radius))
+    ids = nb + np.concatenate([rng.choice(near, size=100, replace=False),
+                               rng.choice(n, size=100, replace=False)])
+    spot = o.spot_step(ids)
+    g.step(1)
+    st = g.get_state()
+    stats = g.stats()
+    assert stats["n_contacts_ss"] > 50_000 and stats["n_contacts_sw"] > 1000
+    assert (spot["n_contacts"] > 0).sum() > 100
+    fscale = np.abs(spot["force"]).max(axis=1) + 1e-30
+    ferr = np.linalg.norm(st["force"][ids] - spot["force"], axis=1) / np.maximum(
+        np.linalg.norm(spot["force"], axis=1), 1e-12 * fscale.max())
+    assert np.median(ferr) <= 1e-12 and ferr.max() <= 1e-9
+    assert np.abs(st["pos"][ids] - spot["pos"]).max() <= 1e-15
+    assert np.abs(st["vel"][ids] - spot["vel"]).max() <= 1e-12 * np.abs(spot["vel"]).max()
