@@ -281,3 +281,72 @@ def test_full_size_spot_check_facet_column():
     assert np.median(ferr) <= 1e-12 and ferr.max() <= 1e-9
     assert np.abs(st["pos"][ids] - spot["pos"]).max() <= 1e-15
     assert np.abs(st["vel"][ids] - spot["vel"]).max() <= 1e-12 * np.abs(spot["vel"]).max()
+
+
+def _thrown_into_facet_box(n, seed, side):
+    rng = np.random.default_rng(seed)
+    k = int(math.ceil(n ** (1.0 / 3.0)))
+    grid = (np.arange(k) + 0.5) * (side / k)
+    nodes = np.array([[x, y, z] for z in grid for y in grid for x in grid])[:n]
+    rad = rng.uniform(0.8, 1.0, n) * min(R, 0.45 * side / k)
+    pos = nodes + rng.uniform(-0.05, 0.05, (n, 3)) * R
+    pos[:, 2] += 0.2 * side
+    vel = rng.normal(0.0, 1.0, (n, 3))
+    vel[:, 2] -= 4.0
+    return pos, rad, vel
+
+
+def test_batched_boundaries_match_single_scenes_bitwise():
+    """Three scenes of different sizes, each thrown into its own facet box
+    with a box obstacle, stepped as one batch equal the same scenes stepped
+    alone, bit for bit, after 600 steps (the batched box/facet
+    instantiation)."""
+    from paper_2301_00611_amd import dem
+    sides = [24 * R, 30 * R, 20 * R]
+    sizes = [300, 500, 150]
+    specs = [_thrown_into_facet_box(n, 20 + i, sd) for i, (n, sd) in enumerate(zip(sizes, sides))]
+    probe = dem.Scene(gravity=(0, 0, -9.81))
+    pm = probe.add_material(RHO, E, NU, 0.5)
+    probe.add_spheres(np.zeros((1, 3)), [R], default_mat=pm)
+    dt = 0.3 * probe.pwave_dt()
+    params = [dem.make_params(dt=dt, gravity=(0.0, 0.0, -9.81), damping=0.3) for _ in specs]
+    batch = dem.Batch(params)
+    singles = []
+    for i, ((pos, rad, vel), side) in enumerate(zip(specs, sides)):
+        for g in (batch.scene(i), dem.Scene(gravity=(0.0, 0.0, -9.81), damping=0.3)):
+            m = g.add_material(RHO, E, NU, 0.5)
+            g.add_facet_box([0.5 * side] * 3, [0.5 * side] * 3, m, wall_mask=31)
+            g.add_box([0.5 * side, 0.5 * side, 0.1 * side], [0.15 * side, 0.1 * side, 0.1 * side], m)
+            g.add_spheres(pos, rad, vel=vel, default_mat=m)
+        singles.append(g)
+        g.set_dt(dt)
+    batch.step(600)
+    touched = 0
+    for i, single in enumerate(singles):
+        single.step(600)
+        a, b = batch.scene(i).get_state(), single.get_state()
+        for key in ("pos", "vel", "angvel"):
+            assert np.array_equal(a[key], b[key]), (i, key)
+        touched += int((single.get_contacts()["is_wall"] == 1).sum())
+    assert touched > 0
+
+
+def test_boundaries_fp32_mixed_one_step():
+    """The one-step cloud of the FP64 test in FP32-mixed mode: identical
+    pair sets (the predicate is FP64 in both modes), forces within 1e-5."""
+    side = 24 * R
+    pos, rad = _cloud(side, 0)
+    vel = np.random.default_rng(5).normal(0.0, 0.05, (len(pos), 3))
+
+    def build(g, mg, o, mo):
+        _container(g, mg, o, mo, side)
+        g.add_spheres(pos, rad, vel=vel, default_mat=mg)
+        o.add_spheres(pos, rad, vel=vel, default_mat=mo)
+
+    g, o = _both(build, precision=1)
+    g.step(1)
+    o.step(1)
+    cg, co = g.get_contacts(), o.get_contacts()
+    assert keyset(cg) == keyset(co)
+    assert int((co["is_wall"] == 1).sum()) > 40
+    assert contact_errors(cg, co)["f"].max() <= 1e-5
