@@ -35,8 +35,13 @@ static int fail(int code, const char* msg)
 
 /* ------------------------------------------------------------------ types */
 
+/* kind 0: FrictMat (density, young, poisson, friction); kind 1: ViscElMat
+ * given by contact time and restitution coefficients (tc, en, et), with the
+ * class's default young and poisson used only by the P-wave step. */
 typedef struct {
     double density, young, poisson, friction;
+    int kind;
+    double tc, en, et;
 } mat_t;
 
 typedef struct {
@@ -72,6 +77,7 @@ typedef struct {
     double det_R1;   /* the boundary's reference radius */
     /* results of the last evaluation */
     double n[3], pen, pt[3], fn[3], kn, ks;
+    double fs_out[3];      /* shear force on #2 as reported: fs plus the shear dashpot's force */
     double f2[3];          /* total force on #2 */
     double t1[3], t2[3];   /* torques on #1 and #2 */
 } cont_t;
@@ -87,7 +93,7 @@ struct orc_scene {
     double H[9], Hprev[9], L[9], Lprev[9], trsf[9];
     long iter;
     double time;
-    double e_kin, e_rot, e_el, e_grav, e_damp, e_plast;
+    double e_kin, e_rot, e_el, e_grav, e_damp, e_plast, e_visc;
 };
 
 /* ------------------------------------------------------------ small math */
@@ -225,12 +231,30 @@ int orc_add_material(orc_scene* s, double density, double young, double poisson,
         s->mats = m;
         s->matcap = cap;
     }
+    memset(&s->mats[s->nmat], 0, sizeof s->mats[s->nmat]);
     s->mats[s->nmat].density = density;
     s->mats[s->nmat].young = young;
     s->mats[s->nmat].poisson = poisson;
     s->mats[s->nmat].friction = friction_angle;
     if (out_mat) *out_mat = s->nmat;
     s->nmat++;
+    return ORC_OK;
+}
+
+int orc_add_viscel_material(orc_scene* s, double density, double tc, double en, double et,
+                            double friction_angle, int* out_mat)
+{
+    if (!s) return fail(ORC_EINVAL, "null scene");
+    if (!(tc > 0.0) || !(en > 0.0 && en <= 1.0) || !(et > 0.0 && et <= 1.0))
+        return fail(ORC_EINVAL, "orc_add_viscel_material: tc > 0 and restitution coefficients in (0, 1]");
+    int id;
+    int rc = orc_add_material(s, density, 1e9, 0.25, friction_angle, &id);
+    if (rc) return rc;
+    s->mats[id].kind = 1;
+    s->mats[id].tc = tc;
+    s->mats[id].en = en;
+    s->mats[id].et = et;
+    if (out_mat) *out_mat = id;
     return ORC_OK;
 }
 
@@ -611,6 +635,26 @@ static int boundary_pair(const body_t* w, const body_t* sp, double n[3], double*
 
 static const body_t* body(const orc_scene* s, long id) { return &s->b[id]; }
 
+/* The friction angle of a pair is the smaller of the two materials' (both
+ * laws). */
+static double pair_tanphi(const mat_t* m1, const mat_t* m2)
+{
+    return tan(m1->friction < m2->friction ? m1->friction : m2->friction);
+}
+
+/* Coulomb slider of both laws: a shear force above fmax is brought back to
+ * it, adding the slip's plastic work (|Fs_trial| - Fmax)/ks at force Fmax to
+ * *e_plast; returns 1 when it slid. */
+static int coulomb_cap(double fs[3], double fmax, double ks, double* e_plast)
+{
+    double fs_norm = sqrt(dot3(fs, fs));
+    if (!(fs_norm > fmax)) return 0;
+    *e_plast += (fs_norm - fmax) * fmax / ks;
+    double ratio = fmax / fs_norm;
+    for (int k = 0; k < 3; ++k) fs[k] = fs[k] * ratio;
+    return 1;
+}
+
 /* Ip2_FrictMat_FrictMat_FrictPhys: k = (E1 D1)(E2 D2) / (E1 D1 + E2 D2) with
  * D = 2*refR; the shear stiffness uses E*nu in place of E; the friction
  * angle is the smaller of the two (section 2.1.2, class reference). */
@@ -623,7 +667,31 @@ static void frict_phys(const mat_t* m1, const mat_t* m2, double R1, double R2,
     double s1 = (m1->young * m1->poisson) * (2.0 * R1);
     double s2 = (m2->young * m2->poisson) * (2.0 * R2);
     *ks = s1 * s2 / (s1 + s2);
-    *tanphi = tan(m1->friction < m2->friction ? m1->friction : m2->friction);
+    *tanphi = pair_tanphi(m1, m2);
+}
+
+/* Ip2_ViscElMat_ViscElMat_ViscElPhys from contact time and restitution
+ * coefficients (Pournin's formulation): the pair takes the means of the two
+ * materials' tc, en and et, and m is the reduced mass m1 m2/(m1 + m2) (the
+ * sphere's own mass against a boundary, which does not move); then
+ * (getViscoelasticFromSpheresInteraction with that m)
+ *   kn = m (pi^2 + ln^2 en)/tc^2,        cn = -2 m ln(en)/tc,
+ *   ks = 2/7 m (pi^2 + ln^2 et)/tc^2,    cs = -2/7 m ln(et)/tc,
+ * the values for which a two-body collision lasts tc with normal
+ * restitution en.  The friction angle is the smaller of the two. */
+static void viscel_phys(const mat_t* m1, const mat_t* m2, const body_t* b1, const body_t* b2,
+                        double* kn, double* cn, double* ks, double* cs, double* tanphi)
+{
+    const double pi = 3.14159265358979323846;
+    double m = b1->is_wall ? b2->m : b1->m * b2->m / (b1->m + b2->m);
+    double tc = 0.5 * (m1->tc + m2->tc);
+    double len = log(0.5 * (m1->en + m2->en));
+    double let = log(0.5 * (m1->et + m2->et));
+    *kn = m * (pi * pi + len * len) / (tc * tc);
+    *cn = -2.0 * m * len / tc;
+    *ks = 2.0 / 7.0 * m * (pi * pi + let * let) / (tc * tc);
+    *cs = -2.0 / 7.0 * m * let / tc;
+    *tanphi = pair_tanphi(m1, m2);
 }
 
 /* Evaluate one real contact: ScGeom update (normal, overlap, contact point,
@@ -631,10 +699,10 @@ static void frict_phys(const mat_t* m1, const mat_t* m2, double R1, double R2,
  * `d` and `dd` are the branch vector from #1 to (the image of) #2 and its
  * squared length, for sphere-sphere contacts; `pen_wall` is the overlap for
  * a wall.  ct->fs / ct->nprev hold the history on entry and are updated.
- * Adds this contact's elastic energy and plastic dissipation to *e_el /
- * *e_plast. */
+ * Adds this contact's elastic energy, plastic dissipation and (visco-elastic
+ * law) the work of its dashpots over the step to *e_el / *e_plast / *e_visc. */
 static void eval_contact(const orc_scene* s, cont_t* ct, const double d[3], double dd,
-                         double pen_wall, double* e_el, double* e_plast)
+                         double pen_wall, double* e_el, double* e_plast, double* e_visc)
 {
     const double dt = s->p.dt;
     const body_t* b1 = body(s, ct->id1);
@@ -681,8 +749,12 @@ static void eval_contact(const orc_scene* s, cont_t* ct, const double d[3], doub
         for (int k = 0; k < 3; ++k) v2[k] += sv[k] / dt;
     }
 
-    double kn, ks, tanphi;
-    frict_phys(m1, m2, R1, R2, &kn, &ks, &tanphi);
+    const int viscel = m1->kind == 1;   /* the scene's materials are all of one kind */
+    double kn, ks, tanphi, cn = 0.0, cs = 0.0;
+    if (viscel)
+        viscel_phys(m1, m2, b1, b2, &kn, &cn, &ks, &cs, &tanphi);
+    else
+        frict_phys(m1, m2, R1, R2, &kn, &ks, &tanphi);
 
     /* Shear update, section 2.1.3 "Shear deformation": the previous shear
      * vector is carried by the rotation of the contact plane (n_prev -> n)
@@ -710,27 +782,43 @@ static void eval_contact(const orc_scene* s, cont_t* ct, const double d[3], doub
     double fs[3];
     for (int k = 0; k < 3; ++k) fs[k] = ((fs_old[k] - inc1[k]) - inc2[k]) - ks * dt * vs[k];
 
-    /* Law2_ScGeom_FrictPhys_CundallStrack: repulsive normal force kn*pen on
-     * #2, shear force capped at |Fn| tan(phi). */
-    double fn_mag = kn * pen;
-    double fn[3];
-    for (int k = 0; k < 3; ++k) fn[k] = fn_mag * n[k];
-    double fmax = fn_mag * tanphi;
-    double fs_norm = sqrt(dot3(fs, fs));
-    if (fs_norm > fmax) {
-        /* plastic work of the slip (|Fs_trial| - Fmax)/ks at force Fmax */
-        *e_plast += (fs_norm - fmax) * fmax / ks;
-        double ratio = fmax / fs_norm;
-        for (int k = 0; k < 3; ++k) fs[k] = fs[k] * ratio;
+    double fn_mag, fn[3], fsv[3] = {0.0, 0.0, 0.0};
+    if (!viscel) {
+        /* Law2_ScGeom_FrictPhys_CundallStrack: repulsive normal force kn*pen
+         * on #2, shear force capped at |Fn| tan(phi). */
+        fn_mag = kn * pen;
+        double fmax = fn_mag * tanphi;
+        coulomb_cap(fs, fmax, ks, e_plast);
+        *e_el += 0.5 * (fn_mag * fn_mag / kn) + 0.5 * (dot3(fs, fs) / ks);
+    } else {
+        /* Law2_ScGeom_ViscElPhys_Basic: along the normal a spring kn and a
+         * dashpot cn in parallel, the dashpot on the overlap's rate of change
+         * -(v2 - v1).n (no tension cut-off: the closed forms of kn and cn
+         * assume none); tangentially a spring (the shear force carried and
+         * incremented as above) and a dashpot cs on the sliding velocity in
+         * parallel, in series with a slider: when the spring's force exceeds
+         * tan(phi) times the compressive normal force it is brought back to
+         * that bound and the shear dashpot carries nothing. */
+        double dv[3];
+        for (int k = 0; k < 3; ++k) dv[k] = v2[k] - v1[k];
+        double un = dot3(n, dv);
+        fn_mag = kn * pen - cn * un;
+        double fmax = (fn_mag > 0.0 ? fn_mag : 0.0) * tanphi;
+        int slide = coulomb_cap(fs, fmax, ks, e_plast);
+        if (!slide)
+            for (int k = 0; k < 3; ++k) fsv[k] = -cs * vs[k];
+        /* dashpot work over the step: cn un^2 dt + cs |vs|^2 dt (sticking) */
+        *e_visc += (cn * un * un + (slide ? 0.0 : cs * dot3(vs, vs))) * dt;
+        *e_el += 0.5 * (kn * pen * pen) + 0.5 * (dot3(fs, fs) / ks);
     }
-    *e_el += 0.5 * (fn_mag * fn_mag / kn) + 0.5 * (dot3(fs, fs) / ks);
+    for (int k = 0; k < 3; ++k) fn[k] = fn_mag * n[k];
 
     /* total force on #2; torques with branch vectors from the radii
      * (Law2_ScGeom_FrictPhys_CundallStrack.sphericalBodies = true):
      * T1 = (r1 n) x (-F), T2 = (-r2 n) x F. */
     double f2[3], br1[3], br2[3], mf[3];
     for (int k = 0; k < 3; ++k) {
-        f2[k] = fn[k] + fs[k];
+        f2[k] = fn[k] + (fs[k] + fsv[k]);
         mf[k] = -f2[k];
         br1[k] = R1 * n[k];
         br2[k] = -R2 * n[k];
@@ -740,6 +828,7 @@ static void eval_contact(const orc_scene* s, cont_t* ct, const double d[3], doub
     if (ct->is_wall) ct->t1[0] = ct->t1[1] = ct->t1[2] = 0.0;
 
     memcpy(ct->fs, fs, sizeof fs);
+    for (int k = 0; k < 3; ++k) ct->fs_out[k] = fs[k] + fsv[k];
     memcpy(ct->nprev, n, sizeof n);
     memcpy(ct->n, n, sizeof n);
     memcpy(ct->pt, pt, sizeof pt);
@@ -981,13 +1070,14 @@ static int step_one(orc_scene* s)
     s->c = nc;
     s->nc = nn;
     s->ccap = nn;
-    double e_el = 0.0, e_plast = 0.0;
+    double e_el = 0.0, e_plast = 0.0, e_visc = 0.0;
     for (long k = 0; k < s->nc; ++k) {
         cont_t* ct = &s->c[k];
-        eval_contact(s, ct, ct->det_d, ct->det_dd, ct->det_pen, &e_el, &e_plast);
+        eval_contact(s, ct, ct->det_d, ct->det_dd, ct->det_pen, &e_el, &e_plast, &e_visc);
     }
     s->e_el = e_el;
     s->e_plast += e_plast;
+    s->e_visc += e_visc;
 
     rc = sum_forces(s);
     if (rc) return rc;
@@ -1025,9 +1115,25 @@ static int step_one(orc_scene* s)
     return ORC_OK;
 }
 
+/* The contact laws pair materials of one kind (FrictMat with FrictMat,
+ * ViscElMat with ViscElMat): a scene that mixes them has no law for some
+ * pairs and is refused. */
+static int check_material_kinds(const orc_scene* s)
+{
+    int kind = -1;
+    for (long i = 0; i < s->nb; ++i) {
+        int k = s->mats[s->b[i].mat].kind;
+        if (kind >= 0 && k != kind) return fail(ORC_EINVAL, "bodies of elastic and visco-elastic materials in one scene");
+        kind = k;
+    }
+    return ORC_OK;
+}
+
 int orc_step(orc_scene* s, long nsteps)
 {
     if (!s || nsteps < 0) return fail(ORC_EINVAL, "orc_step: bad arguments");
+    int rc0 = check_material_kinds(s);
+    if (rc0) return rc0;
     for (long i = 0; i < nsteps; ++i) {
         int rc = step_one(s);
         if (rc) return rc;
@@ -1110,7 +1216,7 @@ int orc_get_contacts(const orc_scene* s, long capacity, orc_contact* out, long* 
         o->pen = ct->pen;
         memcpy(o->point, ct->pt, sizeof o->point);
         memcpy(o->fn, ct->fn, sizeof o->fn);
-        memcpy(o->fs, ct->fs, sizeof o->fs);
+        memcpy(o->fs, ct->fs_out, sizeof o->fs);
         o->kn = ct->kn;
         o->ks = ct->ks;
     }
@@ -1150,16 +1256,17 @@ int orc_set_contacts(orc_scene* s, long n, const long* id1, const long* id2,
     return ORC_OK;
 }
 
-int orc_get_energy(const orc_scene* s, double* out7)
+int orc_get_energy(const orc_scene* s, double* out8)
 {
-    if (!s || !out7) return fail(ORC_EINVAL, "null argument");
-    out7[0] = s->e_kin;
-    out7[1] = s->e_rot;
-    out7[2] = s->e_el;
-    out7[3] = s->e_grav;
-    out7[4] = s->e_damp;
-    out7[5] = s->e_plast;
-    out7[6] = ((((s->e_kin + s->e_rot) + s->e_el) + s->e_grav) + s->e_damp) + s->e_plast;
+    if (!s || !out8) return fail(ORC_EINVAL, "null argument");
+    out8[0] = s->e_kin;
+    out8[1] = s->e_rot;
+    out8[2] = s->e_el;
+    out8[3] = s->e_grav;
+    out8[4] = s->e_damp;
+    out8[5] = s->e_plast;
+    out8[6] = (((((s->e_kin + s->e_rot) + s->e_el) + s->e_grav) + s->e_damp) + s->e_plast) + s->e_visc;
+    out8[7] = s->e_visc;
     return ORC_OK;
 }
 
@@ -1244,6 +1351,8 @@ int orc_spot_step(const orc_scene* s, long k, const long* ids, double* force3,
                   double* ori4, long* n_contacts)
 {
     if (!s || k < 0 || (k > 0 && !ids)) return fail(ORC_EINVAL, "orc_spot_step: bad arguments");
+    int rc0 = check_material_kinds(s);
+    if (rc0) return rc0;
     double Hinv[9];
     if (s->p.periodic && !matinv(s->H, Hinv)) return fail(ORC_EPERIODIC, "singular cell");
     for (long q = 0; q < k; ++q) {
@@ -1252,7 +1361,7 @@ int orc_spot_step(const orc_scene* s, long k, const long* ids, double* force3,
         const body_t* bi = &s->b[i];
         double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
         long cnt = 0;
-        double e_dummy = 0.0, p_dummy = 0.0;
+        double e_dummy = 0.0, p_dummy = 0.0, v_dummy = 0.0;
         /* partners in ascending id order, as in the full step */
         for (long j = 0; j < s->nb; ++j) {
             if (j == i) continue;
@@ -1285,7 +1394,7 @@ int orc_spot_step(const orc_scene* s, long k, const long* ids, double* force3,
             } else {
                 memcpy(ct.nprev, ct.n, sizeof ct.nprev);
             }
-            eval_contact(s, &ct, d, dd, penw, &e_dummy, &p_dummy);
+            eval_contact(s, &ct, d, dd, penw, &e_dummy, &p_dummy, &v_dummy);
             for (int a = 0; a < 3; ++a) {
                 if (ct.id2 == i) {
                     F[a] += ct.f2[a];

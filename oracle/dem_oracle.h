@@ -70,6 +70,13 @@ void orc_destroy(orc_scene* s);
 /* FrictMat: density [kg/m3], young [Pa], poisson [-], frictionAngle [rad]. */
 int orc_add_material(orc_scene* s, double density, double young, double poisson,
                      double friction_angle, int* out_mat);
+/* ViscElMat given by contact time tc [s], normal and tangential restitution
+ * coefficients en, et in (0, 1], frictionAngle [rad] (Law2_ScGeom_ViscElPhys_Basic,
+ * Ip2_ViscElMat_ViscElMat_ViscElPhys); young and poisson take the class's
+ * defaults (1e9, 0.25), used only by the P-wave step.  A scene's bodies must
+ * all use materials of one kind (orc_step fails with ORC_EINVAL otherwise). */
+int orc_add_viscel_material(orc_scene* s, double density, double tc, double en, double et,
+                            double friction_angle, int* out_mat);
 /* n spheres; vel3 / angvel3 / mat / blocked may be NULL.  blocked bits:
  * 1,2,4 = x,y,z translation, 8,16,32 = x,y,z rotation (State.blockedDOFs). */
 int orc_add_spheres(orc_scene* s, long n, const double* pos3, const double* radius,
@@ -111,8 +118,9 @@ int orc_get_contacts(const orc_scene* s, long capacity, orc_contact* out, long* 
 int orc_set_contacts(orc_scene* s, long n, const long* id1, const long* id2,
                      const int* cell3, const double* fs3, const double* nprev3);
 
-/* kinetic, kin_rot, elastic, grav_work, damp_dissip, plastic_dissip, total */
-int orc_get_energy(const orc_scene* s, double* out7);
+/* kinetic, kin_rot, elastic, grav_work, damp_dissip, plastic_dissip, total,
+ * visc_dissip (cumulative dashpot work of the visco-elastic law; in total) */
+int orc_get_energy(const orc_scene* s, double* out8);
 int orc_get_cell(const orc_scene* s, double* hsize9, double* trsf9);
 /* Love-Weber stress of the last step's sphere-sphere contacts (force on #2
  * times the branch vector from #2 to #1, over V; V <= 0 takes the periodic

@@ -55,7 +55,7 @@ CONTACT_DTYPE = np.dtype([
 ])
 assert CONTACT_DTYPE.itemsize == C.sizeof(OrcContact)
 
-ENERGY_KEYS = ("kinetic", "kin_rot", "elastic", "grav_work", "damp_dissip", "plastic_dissip", "total")
+ENERGY_KEYS = ("kinetic", "kin_rot", "elastic", "grav_work", "damp_dissip", "plastic_dissip", "total", "visc_dissip")
 
 
 class OracleError(RuntimeError):
@@ -80,6 +80,7 @@ def load_library(path: str | None = None):
     lib.orc_last_error.restype = C.c_char_p
     sigs = {
         "orc_add_material": [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, _IP],
+        "orc_add_viscel_material": [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, _IP],
         "orc_add_spheres": [C.c_void_p, C.c_long, _DP, _DP, _DP, _DP, _IP, C.c_int, _UP, _LP],
         "orc_add_wall": [C.c_void_p, C.c_int, C.c_double, C.c_int, C.c_int, _LP],
         "orc_pwave_dt": [C.c_void_p, _DP],
@@ -176,6 +177,14 @@ class OracleScene:
         out = C.c_int()
         self._check(self.lib.orc_add_material(self._h, density, young, poisson, friction_angle, C.byref(out)),
                     "add_material")
+        return out.value
+
+    def add_viscel_material(self, density, tc, en, et, friction_angle):
+        """ViscElMat from contact time and restitution coefficients
+        (Law2_ScGeom_ViscElPhys_Basic)."""
+        out = C.c_int()
+        self._check(self.lib.orc_add_viscel_material(self._h, density, tc, en, et, friction_angle, C.byref(out)),
+                    "add_viscel_material")
         return out.value
 
     def add_spheres(self, pos, radius, vel=None, angvel=None, mat=None, default_mat=0, blocked=None):
@@ -288,7 +297,7 @@ class OracleScene:
                                               _ptr(fs), _ptr(nprev)), "set_contacts")
 
     def get_energy(self):
-        out = np.zeros(7)
+        out = np.zeros(8)
         self._check(self.lib.orc_get_energy(self._h, _ptr(out)), "get_energy")
         return dict(zip(ENERGY_KEYS, out.tolist()))
 

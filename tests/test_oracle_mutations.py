@@ -30,8 +30,8 @@ MUTATIONS = {
     "inertia_rounding": ("b->I = 2.0 * b->m * r * r / 5.0;", "b->I = 0.4 * b->m * r * r;"),
     "shear_stiffness_without_poisson": ("double s1 = (m1->young * m1->poisson) * (2.0 * R1);",
                                         "double s1 = (m1->young) * (2.0 * R1);"),
-    "friction_max_not_min": ("*tanphi = tan(m1->friction < m2->friction ? m1->friction : m2->friction);",
-                             "*tanphi = tan(m1->friction > m2->friction ? m1->friction : m2->friction);"),
+    "friction_max_not_min": ("return tan(m1->friction < m2->friction ? m1->friction : m2->friction);",
+                             "return tan(m1->friction > m2->friction ? m1->friction : m2->friction);"),
     "wall_reference_radius": ("n[w->axis] = (double)wall_sign(w, sp);\n        *R1 = sp->r;",
                               "n[w->axis] = (double)wall_sign(w, sp);\n        *R1 = 0.5 * sp->r;"),
     "plastic_work_without_fmax": ("*e_plast += (fs_norm - fmax) * fmax / ks;", "*e_plast += (fs_norm - fmax) / ks;"),
@@ -89,6 +89,40 @@ def test_boundary_pins_catch_mutation(name, tmp_path):
     env = dict(os.environ, DEM_ORACLE_LIB=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_boundaries.py")],
+                       env=env, capture_output=True, text=True, cwd=ROOT, timeout=600)
+    assert r.returncode != 0, f"no pin caught mutation {name}:\n{r.stdout[-2000:]}"
+    assert "FAILED" in r.stdout
+
+
+# slips in the visco-elastic law, caught by tests/test_oracle_viscel.py
+VISCEL_MUTATIONS = {
+    "viscel_sphere_mass_not_reduced": ("double m = b1->is_wall ? b2->m : b1->m * b2->m / (b1->m + b2->m);",
+                                       "double m = b2->m;"),
+    "viscel_tangential_without_two_sevenths": ("*ks = 2.0 / 7.0 * m * (pi * pi + let * let) / (tc * tc);",
+                                               "*ks = m * (pi * pi + let * let) / (tc * tc);"),
+    "viscel_normal_dashpot_sign": ("fn_mag = kn * pen - cn * un;", "fn_mag = kn * pen + cn * un;"),
+    "viscel_dashpot_work_halved": ("*e_visc += (cn * un * un", "*e_visc += (0.5 * cn * un * un"),
+    "viscel_shear_dashpot_dropped": ("fsv[k] = -cs * vs[k];", "fsv[k] = 0.0 * vs[k];"),
+    "viscel_tension_cut_off": ("double fmax = (fn_mag > 0.0 ? fn_mag : 0.0) * tanphi;",
+                               "if (fn_mag < 0.0) fn_mag = 0.0;\n        double fmax = fn_mag * tanphi;"),
+    "viscel_restitution_product": ("double len = log(0.5 * (m1->en + m2->en));",
+                                   "double len = log(m1->en * m2->en);"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(VISCEL_MUTATIONS))
+def test_viscel_pins_catch_mutation(name, tmp_path):
+    before, after = VISCEL_MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(before) == 1, f"mutation anchor not found: {name}"
+    mutated = tmp_path / "dem_oracle_mutated.c"
+    mutated.write_text(src.replace(before, after))
+    lib = tmp_path / "libdem_oracle_mutated.so"
+    subprocess.run(["gcc", "-std=c99", "-D_DEFAULT_SOURCE", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+                    "-I", os.path.join(ROOT, "oracle"), "-o", str(lib), str(mutated), "-lm"], check=True)
+    env = dict(os.environ, DEM_ORACLE_LIB=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_viscel.py")],
                        env=env, capture_output=True, text=True, cwd=ROOT, timeout=600)
     assert r.returncode != 0, f"no pin caught mutation {name}:\n{r.stdout[-2000:]}"
     assert "FAILED" in r.stdout
