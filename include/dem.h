@@ -120,7 +120,8 @@ typedef struct {
     double grav_work;      /* cumulative work of gravity, negated */
     double damp_dissip;    /* cumulative energy removed by eq. 2.9 */
     double plastic_dissip; /* cumulative Coulomb slip work */
-    double total;          /* sum of the above */
+    double total;          /* sum of the above and visc_dissip */
+    double visc_dissip;    /* cumulative work of the visco-elastic law's dashpots */
 } dem_energy;
 
 typedef struct {
@@ -164,6 +165,20 @@ dem_status dem_destroy(dem_scene* s);
  * poisson in (-1, 0.5], friction_angle in [0, pi/2) [rad]. */
 dem_status dem_add_material(dem_scene* s, double density, double young, double poisson,
                             double friction_angle, int32_t* out_mat);
+/* ViscElMat (class ViscElMat; Ip2_ViscElMat_ViscElMat_ViscElPhys and
+ * Law2_ScGeom_ViscElPhys_Basic): density > 0, contact time tc > 0 [s],
+ * normal and tangential restitution coefficients en, et in (0, 1],
+ * friction_angle as above.  A pair takes the means of the two materials'
+ * tc, en, et and its reduced mass m (the sphere's own against a boundary):
+ * kn = m (pi^2 + ln^2 en)/tc^2, cn = -2 m ln(en)/tc, ks = 2/7 m (pi^2 +
+ * ln^2 et)/tc^2, cs = -2/7 m ln(et)/tc (the analytic two-sphere solution of
+ * getViscoelasticFromSpheresInteraction).  young and poisson take the class
+ * defaults 1e9 and 0.25, used only by dem_pwave_dt.  The bodies of one scene
+ * must all use materials of one kind (dem_step fails with DEM_EINVAL
+ * otherwise); the stiffness timestep, its timestepper and the controlled cell
+ * are refused (DEM_EINVAL) while visco-elastic materials exist. */
+dem_status dem_add_viscel_material(dem_scene* s, double density, double tc, double en, double et,
+                                   double friction_angle, int32_t* out_mat);
 /* Append n spheres (ids out_first_id .. +n-1).  pos3 [n*3], radius [n] are
  * required; vel3, angvel3 [n*3], mat [n], blocked [n] may be NULL (zero /
  * default_mat / none).  blocked bits 1,2,4 = x,y,z translation, 8,16,32 =

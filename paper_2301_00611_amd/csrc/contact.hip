@@ -99,6 +99,7 @@ struct ContactPartial {
     double el, plast;
     unsigned long long ss, sw;
     double ov;
+    double visc;
 };
 
 // MEASURE (periodic, unbatched; launched on the steps that end an update
@@ -111,7 +112,9 @@ struct ContactPartial {
 // PRIMS (aperiodic scenes holding a box or a facet): the geometry of those
 // boundaries is compiled in; without it the kernel keeps its registers for
 // spheres and planes.
-template <int PREC, bool BATCHED, bool PERIODIC, bool MEASURE = false, bool PRIMS = false>
+// VISCEL (a world with visco-elastic materials): pairs of ViscElMat take
+// Law2_ScGeom_ViscElPhys_Basic, the others the linear law.
+template <int PREC, bool BATCHED, bool PERIODIC, bool MEASURE = false, bool PRIMS = false, bool VISCEL = false>
 __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restrict__ args, int parity)
 {
     using R = typename std::conditional<PREC == DEM_FP32_MIXED, float, double>::type;
@@ -130,7 +133,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
         a.ctr->measure = (c.active && (a.ctr->iter0 + a.ctr->steps_done + 1) % c.glob_update == 0) ? 1 : 0;
     }
     const int k = xcd_pair(a.npairs);
-    ContactPartial part = {0.0, 0.0, 0ull, 0ull, 0.0};
+    ContactPartial part = {0.0, 0.0, 0ull, 0ull, 0.0, 0.0};
     bool unstable = false;
     // the measuring instantiation keeps what its terms need (force and
     // normal as stored, the branch length, k_n; zero for a pair not
@@ -277,11 +280,31 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
             // relative translational velocity in double (difference of absolute values)
             const V3<double> dv64 = v2d - v1d;
 
-            // ---- Ip2_FrictMat_FrictMat_FrictPhys: series springs k_i = E_i (2 R_i)
-            const R k1 = (R)M1.young * ((R)2 * (R)R1d), k2 = (R)M2.young * ((R)2 * (R)R2d);
-            const R kn = k1 * k2 / (k1 + k2);
-            const R q1 = (R)M1.young_poisson * ((R)2 * (R)R1d), q2 = (R)M2.young_poisson * ((R)2 * (R)R2d);
-            const R ks = q1 * q2 / (q1 + q2);
+            // ---- contact stiffnesses (and the visco-elastic dashpots)
+            R kn, ks;
+            double kn64 = 0.0, cn64 = 0.0, cs64 = 0.0;
+            const bool ve = VISCEL && M2.viscel != 0;
+            if (ve) {
+                // Ip2_ViscElMat_ViscElMat_ViscElPhys: the pair's constants
+                // scaled by the reduced mass (the sphere's against a boundary)
+                const double m2m = sphere_mass(r2, M2.density);
+                const double m1m = wall ? 1.0 : sphere_mass(r1, M1.density);
+                const double mr = wall ? m2m : m1m * m2m / (m1m + m2m);
+                const ViscElPair P = glb<const ViscElPair>(a.ve)[m1 * a.nmat + m2];
+                const double pi2 = 3.14159265358979323846 * 3.14159265358979323846;
+                const double tc2 = P.tc * P.tc;
+                kn64 = mr * (pi2 + P.len * P.len) / tc2;
+                kn = (R)kn64;
+                cn64 = -2.0 * mr * P.len / P.tc;
+                ks = (R)(2.0 / 7.0 * mr * (pi2 + P.let * P.let) / tc2);
+                cs64 = -2.0 / 7.0 * mr * P.let / P.tc;
+            } else {
+                // Ip2_FrictMat_FrictMat_FrictPhys: series springs k_i = E_i (2 R_i)
+                const R k1 = (R)M1.young * ((R)2 * (R)R1d), k2 = (R)M2.young * ((R)2 * (R)R2d);
+                kn = k1 * k2 / (k1 + k2);
+                const R q1 = (R)M1.young_poisson * ((R)2 * (R)R1d), q2 = (R)M2.young_poisson * ((R)2 * (R)R2d);
+                ks = q1 * q2 / (q1 + q2);
+            }
             const R tanphi = (R)tanphi64;
 
             const V3<R> n = cvt<R>(n64);
@@ -306,20 +329,45 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
             const V3<R> dfs = ((v3<R>((R)0, (R)0, (R)0) - inc1) - inc2) - (ks * dtr) * vs;
             V3<double> fs64 = fs_old64 + cvt<double>(dfs);
 
-            // ---- Law2_ScGeom_FrictPhys_CundallStrack
-            const R fn_mag = kn * penr;
-            const R fmax = fn_mag * tanphi;
+            // ---- Law2_ScGeom_FrictPhys_CundallStrack; Law2_ScGeom_ViscElPhys_Basic
+            // adds a normal dashpot on the overlap's rate -(v2 - v1).n (no
+            // tension cut-off) and a shear dashpot that carries nothing while
+            // the slider slides, the slider bounding the spring's part by
+            // tan(phi) times the compressive normal force
+            R fn_mag;
+            double un = 0.0;
+            if (ve) {
+                // spring and dashpot in FP64 in both modes: near the end of a
+                // contact they cancel, and k_n rounded to FP32 would leave its
+                // rounding error against a small difference
+                un = (n64.x * dv64.x + n64.y * dv64.y) + n64.z * dv64.z;
+                fn_mag = (R)(kn64 * pen - cn64 * un);
+            } else {
+                fn_mag = kn * penr;
+            }
+            const R fmax = (ve && fn_mag < (R)0 ? (R)0 : fn_mag) * tanphi;
             const double fs_norm = sqrt(dot(fs64, fs64));
-            if (fs_norm > (double)fmax) {
+            const bool slide = fs_norm > (double)fmax;
+            if (slide) {
                 part.plast += (fs_norm - (double)fmax) * (double)fmax / (double)ks;
                 const double ratio = (double)fmax / fs_norm;
                 fs64 = ratio * fs64;
             }
-            part.el += 0.5 * ((double)fn_mag * (double)fn_mag / (double)kn) + 0.5 * (dot(fs64, fs64) / (double)ks);
-            const V3<R> F = fn_mag * n + cvt<R>(fs64);
+            V3<R> fsr = cvt<R>(fs64);
+            if (ve) {
+                const V3<double> vs64 = cvt<double>(vs);
+                const double vss = dot(vs64, vs64);
+                if (!slide) fsr = cvt<R>(fs64 + (-cs64) * vs64);
+                part.visc += ((cn64 * un) * un + (slide ? 0.0 : cs64 * vss)) * dt;
+                part.el += 0.5 * ((kn64 * pen) * pen) + 0.5 * (dot(fs64, fs64) / (double)ks);
+            } else {
+                part.el += 0.5 * ((double)fn_mag * (double)fn_mag / (double)kn) + 0.5 * (dot(fs64, fs64) / (double)ks);
+            }
+            const V3<R> F = fn_mag * n + fsr;
             const V3<R> tau = cross(n, F);
 
-            hist[k] = HistRec{fs64.x, fs64.y, fs64.z, 0.0, (double)n.x, (double)n.y, (double)n.z, 0.0};
+            hist[k] = HistRec{fs64.x, fs64.y, fs64.z, ve ? pen : 0.0, (double)n.x, (double)n.y, (double)n.z,
+                              ve ? (double)fn_mag : 0.0};
             // the record as three pairs (a record starts on an 8-byte (FP32)
             // or 16-byte (FP64) boundary of a 256-byte aligned array)
             if (PREC == DEM_FP32_MIXED) {
@@ -368,6 +416,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
         if (energy) {
             part.el += __shfl_down(part.el, off, 64);
             part.plast += __shfl_down(part.plast, off, 64);
+            if (VISCEL) part.visc += __shfl_down(part.visc, off, 64);
         }
         part.ss += __shfl_down(part.ss, off, 64);
         part.sw += __shfl_down(part.sw, off, 64);
@@ -380,12 +429,13 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double el = 0.0, pl = 0.0, ov = 0.0;
+        double el = 0.0, pl = 0.0, ov = 0.0, vi = 0.0;
         unsigned long long ss = 0, sw = 0;
         uint32_t flags = 0;
         for (int w = 0; w < nwaves; ++w) {
             el += s_p[w].el;
             pl += s_p[w].plast;
+            if (VISCEL) vi += s_p[w].visc;
             ss += s_p[w].ss;
             sw += s_p[w].sw;
             ov = fmax(ov, s_p[w].ov);
@@ -395,6 +445,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
         if (energy) {
             acc.el = el;
             acc.plast += pl;
+            if (VISCEL) acc.visc += vi;
         }
         acc.ss = ss;
         acc.sw = sw;
@@ -431,22 +482,43 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
     }
 }
 
-template <int PREC, bool BATCHED, bool PERIODIC, bool MEASURE = false, bool PRIMS = false>
+template <int PREC, bool BATCHED, bool PERIODIC, bool MEASURE = false, bool PRIMS = false, bool VISCEL = false>
 void launch_t(const StepArgs* args, int parity, int grid, int block, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
     const dim3 g(grid > 0 ? grid : 1), b(block);
     if (ev0)
-        hipExtLaunchKernelGGL((k_contact<PREC, BATCHED, PERIODIC, MEASURE, PRIMS>), g, b, 0, st, ev0, ev1, 0, args,
-                              parity);
+        hipExtLaunchKernelGGL((k_contact<PREC, BATCHED, PERIODIC, MEASURE, PRIMS, VISCEL>), g, b, 0, st, ev0, ev1, 0,
+                              args, parity);
     else
-        hipLaunchKernelGGL((k_contact<PREC, BATCHED, PERIODIC, MEASURE, PRIMS>), g, b, 0, st, args, parity);
+        hipLaunchKernelGGL((k_contact<PREC, BATCHED, PERIODIC, MEASURE, PRIMS, VISCEL>), g, b, 0, st, args, parity);
+}
+
+// the visco-elastic instantiation of a scene kind: boundaries of every kind
+// when aperiodic
+template <int PREC>
+void launch_viscel(const StepArgs* args, int parity, int grid, int block, hipStream_t st, hipEvent_t ev0,
+                   hipEvent_t ev1, bool batched, bool periodic)
+{
+    if (periodic)
+        launch_t<PREC, false, true, false, false, true>(args, parity, grid, block, st, ev0, ev1);
+    else if (batched)
+        launch_t<PREC, true, false, false, true, true>(args, parity, grid, block, st, ev0, ev1);
+    else
+        launch_t<PREC, false, false, false, true, true>(args, parity, grid, block, st, ev0, ev1);
 }
 
 }  // namespace
 
 void launch_contact(const StepArgs* args, int parity, int grid, int precision, bool batched, bool periodic,
-                    int block, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, bool measure, bool prims)
+                    int block, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, bool measure, bool prims, bool viscel)
 {
+    if (viscel) {
+        if (precision == DEM_FP32_MIXED)
+            launch_viscel<DEM_FP32_MIXED>(args, parity, grid, block, st, ev0, ev1, batched, periodic);
+        else
+            launch_viscel<DEM_FP64>(args, parity, grid, block, st, ev0, ev1, batched, periodic);
+        return;
+    }
     if (prims && !periodic) {
         if (precision == DEM_FP32_MIXED) {
             if (batched) launch_t<DEM_FP32_MIXED, true, false, false, true>(args, parity, grid, block, st, ev0, ev1);

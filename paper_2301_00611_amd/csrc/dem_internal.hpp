@@ -156,6 +156,18 @@ struct Material {
     double young;
     double young_poisson;     // E * nu
     double density;
+    int32_t viscel;           // 1: ViscElMat (visco-elastic law), 0: FrictMat
+    int32_t pad_;
+};
+
+// Pair constants of the visco-elastic law (Ip2_ViscElMat_ViscElMat_ViscElPhys
+// from contact time and restitution coefficients): the means of the two
+// materials' tc, and ln of the means of their en and et.  The coefficients
+// follow per contact from the reduced mass m:
+//   kn = m (pi^2 + len^2)/tc^2, cn = -2 m len/tc,
+//   ks = 2/7 m (pi^2 + let^2)/tc^2, cs = -2/7 m let/tc.
+struct ViscElPair {
+    double tc, len, let, pad_;
 };
 
 // Body arrays of one buffer set.  The per-body vectors are packed four
@@ -188,10 +200,10 @@ __device__ inline double sphere_mass(double r, double rho)
 // on #2 after the Coulomb cap and the normal of its last evaluation; a
 // zero normal marks a pair that did not touch.
 struct HistRec {
-    double fsx, fsy, fsz;
-    double pad0_;
+    double fsx, fsy, fsz;     // shear force (the spring's part under the visco-elastic law)
+    double pen;               // visco-elastic law: overlap of the last evaluation (report only), else 0
     double nx, ny, nz;
-    double pad1_;
+    double fn;                // visco-elastic law: signed normal force k_n pen - c_n u_n (report only), else 0
 };
 
 // Candidate pairs after a broad-phase run, the pairs that touched at the
@@ -285,7 +297,7 @@ struct ContactAcc {
     unsigned long long ss, sw;      // real contacts of the last step
     unsigned long long ss_cum, sw_cum;
     double max_ov;                  // largest overlap / smaller radius, last step
-    double pad_;
+    double visc;                    // dashpot work of the visco-elastic law, cumulative
 };
 
 // Per-block slots of the integrate kernel.
@@ -303,6 +315,7 @@ struct StepArgs {
     const Wall* walls;
     const Material* mats;
     const double* tanphi;           // nmat x nmat, tan(min(phi1, phi2))
+    const ViscElPair* ve;           // nmat x nmat, visco-elastic pair constants
     int32_t nmat;
     SceneParams* scenes;            // device table (the last integrate block updates a periodic cell)
     SceneParams scene0;             // copy of scene 0 for unbatched kernels
@@ -421,10 +434,11 @@ void launch_partition(const PairBuildArgs& a, hipStream_t st);
 // unbatched): the measuring instantiation runs (the host decides per step;
 // captured graphs are keyed by the period's phase at their first step)
 // prims: the world holds a box or a facet (aperiodic): the instantiation
-// with their geometry runs
+// with their geometry runs; viscel: the world holds visco-elastic materials
+// (their instantiation, which takes every boundary kind, runs)
 void launch_contact(const StepArgs* args, int parity, int grid, int precision, bool batched, bool periodic,
                     int block, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
-                    bool measure = false, bool prims = false);
+                    bool measure = false, bool prims = false, bool viscel = false);
 
 // integrate.hip
 void launch_integrate(const StepArgs* args, int parity, int grid, int precision, bool batched, bool periodic,

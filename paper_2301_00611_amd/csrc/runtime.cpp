@@ -159,8 +159,13 @@ struct PairSet {
     }
 };
 
+// kind 0: FrictMat; kind 1: ViscElMat given by contact time and restitution
+// coefficients (young and poisson then hold the class's defaults, used only by
+// the P-wave step)
 struct HostMaterial {
     double density, young, poisson, friction;
+    int kind = 0;
+    double tc = 0.0, en = 0.0, et = 0.0;
 };
 
 struct HostScene {
@@ -227,6 +232,7 @@ struct World {
     int old_ngids = 0;                 // gids covered by the active own arrays
     DBuf slot_of_id, keys, vals, keys_alt, vals_alt, cell_start, cell_end, counts, row_start;
     DBuf ent_slot, ent_pid, ent_cell, ent_own, own_scan, rows_ent, scan_tmp, radix_tmp;
+    DBuf d_ve;
     DBuf d_scenes, d_walls, d_mats, d_tanphi, d_ctr, d_part_c, d_part_i, d_bounds, d_total, d_tmp3, d_args;
     DBuf d_ctrl_cfg, d_ctrl_state, d_acc_ctrl, d_acc_ctrl2;  // the controlled cell (device-resident)
     DBuf pb_ca, pb_cb, pb_found, pb_flag, pb_scan;  // pair build scratch (canonical order)
@@ -234,7 +240,7 @@ struct World {
     int acc_c_n = 0, acc_i_n = 0;      // slots currently in use in d_part_c / d_part_i
     int next_parity = 0;               // parity of the next step (stall flags alternate)
     // running sums folded from the per-block slots (fixed block order)
-    double base_plast = 0.0, base_grav = 0.0, base_damp = 0.0;
+    double base_plast = 0.0, base_grav = 0.0, base_damp = 0.0, base_visc = 0.0;
     unsigned long long base_contact_steps = 0;
     // last-step values kept across a fold until the next step runs
     double last_el = 0.0, last_kin = 0.0, last_rot = 0.0;
@@ -394,9 +400,47 @@ struct World {
             !(friction >= 0.0 && friction < 1.5707963267948966))
             fail(DEM_EINVAL, "dem_add_material: need density > 0, young > 0, -1 < poisson <= 0.5, 0 <= friction < pi/2");
         if (mats.size() >= 1024) fail(DEM_EINVAL, "dem_add_material: at most 1024 materials");
-        mats.push_back({density, young, poisson, friction});
+        HostMaterial m;
+        m.density = density;
+        m.young = young;
+        m.poisson = poisson;
+        m.friction = friction;
+        mats.push_back(m);
         upload_materials();
         return (int)mats.size() - 1;
+    }
+    int add_viscel_material(double density, double tc, double en, double et, double friction)
+    {
+        if (!(tc > 0.0) || !std::isfinite(tc) || !(en > 0.0 && en <= 1.0) || !(et > 0.0 && et <= 1.0))
+            fail(DEM_EINVAL, "dem_add_viscel_material: need tc > 0 and restitution coefficients in (0, 1]");
+        const int id = add_material(density, 1e9, 0.25, friction);
+        mats[id].kind = 1;
+        mats[id].tc = tc;
+        mats[id].en = en;
+        mats[id].et = et;
+        upload_materials();
+        return id;
+    }
+    bool has_viscel() const
+    {
+        for (const HostMaterial& m : mats)
+            if (m.kind == 1) return true;
+        return false;
+    }
+    // The laws pair materials of one kind: a scene whose bodies mix FrictMat
+    // and ViscElMat has no law for some pairs and is refused at its next step.
+    bool kinds_checked = false;
+    void check_material_kinds()
+    {
+        if (kinds_checked || !has_viscel()) return;
+        std::vector<int> kind(scenes.size(), -1);
+        for (const HostBody& b : bodies) {
+            const int k = mats[b.mat].kind;
+            int& sk = kind[b.scene];
+            if (sk >= 0 && sk != k) fail(DEM_EINVAL, "dem_step: bodies of elastic and visco-elastic materials in one scene");
+            sk = k;
+        }
+        kinds_checked = true;
     }
 
     void upload_materials()
@@ -404,17 +448,31 @@ struct World {
         const int n = (int)mats.size();
         std::vector<Material> m(n);
         std::vector<double> tp((size_t)n * n);
+        std::vector<ViscElPair> ve((size_t)n * n);
         for (int i = 0; i < n; ++i) {
+            std::memset(&m[i], 0, sizeof m[i]);
             m[i].young = mats[i].young;
             m[i].young_poisson = mats[i].young * mats[i].poisson;
             m[i].density = mats[i].density;
-            for (int j = 0; j < n; ++j)
+            m[i].viscel = mats[i].kind == 1 ? 1 : 0;
+            for (int j = 0; j < n; ++j) {
                 tp[(size_t)i * n + j] = std::tan(mats[i].friction < mats[j].friction ? mats[i].friction : mats[j].friction);
+                // the pair's tc and restitution coefficients: the means of the two materials'
+                ViscElPair& P = ve[(size_t)i * n + j];
+                std::memset(&P, 0, sizeof P);
+                if (mats[i].kind == 1 && mats[j].kind == 1) {
+                    P.tc = 0.5 * (mats[i].tc + mats[j].tc);
+                    P.len = std::log(0.5 * (mats[i].en + mats[j].en));
+                    P.let = std::log(0.5 * (mats[i].et + mats[j].et));
+                }
+            }
         }
         d_mats.ensure(sizeof(Material) * std::max(n, 1));
         d_tanphi.ensure(sizeof(double) * std::max(n * n, 1));
+        d_ve.ensure(sizeof(ViscElPair) * std::max(n * n, 1));
         HIPC(hipMemcpyAsync(d_mats.p, m.data(), sizeof(Material) * n, hipMemcpyHostToDevice, stream));
         HIPC(hipMemcpyAsync(d_tanphi.p, tp.data(), sizeof(double) * n * n, hipMemcpyHostToDevice, stream));
+        HIPC(hipMemcpyAsync(d_ve.p, ve.data(), sizeof(ViscElPair) * n * n, hipMemcpyHostToDevice, stream));
         HIPC(hipStreamSynchronize(stream));
         if (d_args.p) upload_args();
     }
@@ -447,6 +505,7 @@ struct World {
                         const double* angvel3, const int32_t* mat, int32_t default_mat, const uint8_t* blocked)
     {
         if (n < 0 || (n > 0 && (!pos3 || !radius))) fail(DEM_EINVAL, "dem_add_spheres: need pos3 and radius");
+        kinds_checked = false;
         for (int64_t i = 0; i < n; ++i) {
             const int mi = mat ? mat[i] : default_mat;
             if (mi < 0 || mi >= (int)mats.size()) fail(DEM_EINVAL, "dem_add_spheres: unknown material");
@@ -558,6 +617,7 @@ struct World {
         bodies.push_back(b);
         for (int i = 0; i < (int)walls.size(); ++i) bodies[walls[i].id].wall = i;
         S.n_walls += 1;
+        kinds_checked = false;
         host_dirty = true;
         need_rebuild = true;
         return local;
@@ -967,7 +1027,7 @@ struct World {
     // Sum the per-block slots in block order.  cum = true: add the running
     // sums to the bases and clear the slots (before the grids change).
     struct SlotSums {
-        double el = 0, plast = 0, kin = 0, rot = 0, grav = 0, damp = 0, maxov = 0;
+        double el = 0, plast = 0, kin = 0, rot = 0, grav = 0, damp = 0, maxov = 0, visc = 0;
         unsigned long long ss = 0, sw = 0, cum = 0;
     };
     SlotSums read_slots()
@@ -981,6 +1041,7 @@ struct World {
         for (const ContactAcc& a : c) {
             t.el += a.el;
             t.plast += a.plast;
+            t.visc += a.visc;
             t.ss += a.ss;
             t.sw += a.sw;
             t.cum += a.ss_cum + a.sw_cum;
@@ -999,6 +1060,7 @@ struct World {
         if (!acc_c_n && !acc_i_n) return;
         const SlotSums t = read_slots();
         base_plast += t.plast;
+        base_visc += t.visc;
         base_grav += t.grav;
         base_damp += t.damp;
         base_contact_steps += t.cum;
@@ -1026,7 +1088,9 @@ struct World {
             e->grav_work = base_grav + t.grav;
             e->damp_dissip = base_damp + t.damp;
             e->plastic_dissip = base_plast + t.plast;
-            e->total = ((((e->kinetic + e->kin_rot) + e->elastic) + e->grav_work) + e->damp_dissip) + e->plastic_dissip;
+            e->visc_dissip = base_visc + t.visc;
+            e->total = (((((e->kinetic + e->kin_rot) + e->elastic) + e->grav_work) + e->damp_dissip) + e->plastic_dissip) +
+                       e->visc_dissip;
         }
         if (ss) *ss = fresh ? last_ss : t.ss;
         if (sw) *sw = fresh ? last_sw : t.sw;
@@ -1184,6 +1248,7 @@ struct World {
         a.walls = d_walls.as<Wall>();
         a.mats = d_mats.as<Material>();
         a.tanphi = d_tanphi.as<double>();
+        a.ve = d_ve.as<ViscElPair>();
         a.nmat = (int)mats.size();
         a.scenes = d_scenes.as<SceneParams>();
         a.scene0 = sp[0];
@@ -1211,7 +1276,7 @@ struct World {
     {
         const StepArgs* a = d_args.as<StepArgs>();
         launch_contact(a, parity, grid_c, precision, batched(), periodic, block_contact, stream, ev ? ev[0] : nullptr,
-                       ev ? ev[1] : nullptr, periodic && pt_active && measure, has_prims());
+                       ev ? ev[1] : nullptr, periodic && pt_active && measure, has_prims(), has_viscel());
         launch_integrate(a, parity, grid_i, precision, batched(), periodic, block_integrate, stream,
                          ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
         if (periodic && pt_active && measure) launch_ctrl_reduce(a, parity, stream);
@@ -1226,8 +1291,9 @@ struct World {
     std::string graph_key(int n, int phase) const
     {
         char buf[256];
-        std::snprintf(buf, sizeof buf, "%p/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d", d_args.p, grid_c, grid_i, n, timing ? 1 : 0,
-                      block_contact, block_integrate, pt_active ? 1 : 0, ctrl_period(), phase, has_prims() ? 1 : 0);
+        std::snprintf(buf, sizeof buf, "%p/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d/%d", d_args.p, grid_c, grid_i, n,
+                      timing ? 1 : 0, block_contact, block_integrate, pt_active ? 1 : 0, ctrl_period(), phase,
+                      has_prims() ? 1 : 0, has_viscel() ? 1 : 0);
         return buf;
     }
 
@@ -1273,6 +1339,10 @@ struct World {
     {
         if (nsteps < 0) fail(DEM_EINVAL, "dem_step: nsteps < 0");
         HIPC(hipSetDevice(device));
+        check_material_kinds();
+        if ((pt_active || ts_interval > 0) && has_viscel())
+            fail(DEM_EINVAL, "dem_step: the stiffness timestepper and the controlled cell are not available with "
+                             "visco-elastic materials");
         if (timing) timers.clear();
         if (ts_interval <= 0) {
             run_steps(nsteps);
@@ -1430,6 +1500,7 @@ struct World {
     struct PairSnapshot {
         std::vector<int32_t> a, b, cell;
         std::vector<double> fsx, fsy, fsz, nx, ny, nz, fx, fy, fz;
+        std::vector<double> pen, fn;   // the visco-elastic law's report words of the history
     };
 
     PairSnapshot pair_snapshot()
@@ -1452,8 +1523,10 @@ struct World {
             std::vector<HistRec> h(n);
             if (n) HIPC(hipMemcpyAsync(h.data(), P.hist.p, sizeof(HistRec) * n, hipMemcpyDeviceToHost, stream));
             HIPC(hipStreamSynchronize(stream));
-            for (auto* v : {&p.fsx, &p.fsy, &p.fsz, &p.nx, &p.ny, &p.nz}) v->resize(n);
+            for (auto* v : {&p.fsx, &p.fsy, &p.fsz, &p.nx, &p.ny, &p.nz, &p.pen, &p.fn}) v->resize(n);
             for (size_t k = 0; k < n; ++k) {
+                p.pen[k] = h[k].pen;
+                p.fn[k] = h[k].fn;
                 p.fsx[k] = h[k].fsx;
                 p.fsy[k] = h[k].fsy;
                 p.fsz[k] = h[k].fsz;
@@ -1718,6 +1791,7 @@ struct World {
     }
     double stiffness_dt(int s, double safety)
     {
+        if (has_viscel()) fail(DEM_EINVAL, "dem_stiffness_dt: not available with visco-elastic materials");
         const Measures m = measures(s);
         if (std::isinf(m.min_dt)) return safety * pwave_dt(s);
         return safety * m.min_dt;
@@ -1851,11 +1925,28 @@ struct World {
             const HostMaterial& M2 = mats[B2.mat];
             const HostMaterial& M1 = wall ? mats[walls[-1 - p.a[k]].mat] : mats[B1->mat];
             const double R1 = wall ? (walls[-1 - p.a[k]].kind == kFacet ? 2.0 * B2.r : B2.r) : B1->r, R2 = B2.r;
-            const double k1 = M1.young * (2.0 * R1), k2 = M2.young * (2.0 * R2);
-            c.kn = k1 * k2 / (k1 + k2);
-            const double q1 = (M1.young * M1.poisson) * (2.0 * R1), q2 = (M2.young * M2.poisson) * (2.0 * R2);
-            c.ks = q1 * q2 / (q1 + q2);
-            c.pen = std::sqrt(c.fn[0] * c.fn[0] + c.fn[1] * c.fn[1] + c.fn[2] * c.fn[2]) / c.kn;
+            if (M2.kind == 1) {
+                // visco-elastic law: the kernel left the overlap and the signed
+                // normal force in the history record; the shear force reported
+                // is the total (spring and dashpot) less the normal force
+                const double mr = wall ? B2.m : B1->m * B2.m / (B1->m + B2.m);
+                const double tc = 0.5 * (M1.tc + M2.tc);
+                const double len = std::log(0.5 * (M1.en + M2.en)), let = std::log(0.5 * (M1.et + M2.et));
+                const double pi2 = 3.14159265358979323846 * 3.14159265358979323846;
+                c.kn = mr * (pi2 + len * len) / (tc * tc);
+                c.ks = 2.0 / 7.0 * mr * (pi2 + let * let) / (tc * tc);
+                c.pen = p.pen[k];
+                for (int q = 0; q < 3; ++q) c.fn[q] = p.fn[k] * c.normal[q];
+                c.fs[0] = p.fx[k] - c.fn[0];
+                c.fs[1] = p.fy[k] - c.fn[1];
+                c.fs[2] = p.fz[k] - c.fn[2];
+            } else {
+                const double k1 = M1.young * (2.0 * R1), k2 = M2.young * (2.0 * R2);
+                c.kn = k1 * k2 / (k1 + k2);
+                const double q1 = (M1.young * M1.poisson) * (2.0 * R1), q2 = (M2.young * M2.poisson) * (2.0 * R2);
+                c.ks = q1 * q2 / (q1 + q2);
+                c.pen = std::sqrt(c.fn[0] * c.fn[0] + c.fn[1] * c.fn[1] + c.fn[2] * c.fn[2]) / c.kn;
+            }
             const double dt = scenes[s].p.dt;
             // positions of the step the contact was evaluated at: x - v dt
             const double x2[3] = {sn.x[sb] - sn.vx[sb] * dt, sn.y[sb] - sn.vy[sb] * dt, sn.z[sb] - sn.vz[sb] * dt};
@@ -2115,6 +2206,16 @@ dem_status dem_add_material(dem_scene* s, double density, double young, double p
     return guarded([&] {
         dem::World* w = world_of(s);
         const int m = w->add_material(density, young, poisson, friction_angle);
+        if (out_mat) *out_mat = m;
+    });
+}
+
+dem_status dem_add_viscel_material(dem_scene* s, double density, double tc, double en, double et,
+                                   double friction_angle, int32_t* out_mat)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        const int m = w->add_viscel_material(density, tc, en, et, friction_angle);
         if (out_mat) *out_mat = m;
     });
 }
@@ -2463,6 +2564,8 @@ dem_status dem_set_stiffness_timestepper(dem_scene* s, double safety, int64_t in
         if (interval < 0) dem::fail(DEM_EINVAL, "dem_set_stiffness_timestepper: interval >= 0");
         if (interval > 0 && (!(safety > 0.0) || !(safety <= 1.0)))
             dem::fail(DEM_EINVAL, "dem_set_stiffness_timestepper: safety in (0, 1]");
+        if (interval > 0 && w->has_viscel())
+            dem::fail(DEM_EINVAL, "dem_set_stiffness_timestepper: not available with visco-elastic materials");
         w->ts_safety = safety;
         w->ts_interval = interval;
     });
@@ -2489,6 +2592,7 @@ dem_status dem_set_peri_triax(dem_scene* s, const dem_peri_triax* c)
             w->set_peri_triax(nullptr);
             return;
         }
+        if (w->has_viscel()) dem::fail(DEM_EINVAL, "dem_set_peri_triax: not available with visco-elastic materials");
         if (!w->scenes[s->s].p.periodic || w->scenes.size() > 1)
             dem::fail(DEM_EINVAL, "dem_set_peri_triax: needs an unbatched periodic scene");
         if (c->glob_update < 1) dem::fail(DEM_EINVAL, "dem_set_peri_triax: glob_update >= 1");

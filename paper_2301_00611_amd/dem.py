@@ -66,7 +66,8 @@ class dem_history(C.Structure):
 
 class dem_energy(C.Structure):
     _fields_ = [(k, C.c_double) for k in
-                ("kinetic", "kin_rot", "elastic", "grav_work", "damp_dissip", "plastic_dissip", "total")]
+                ("kinetic", "kin_rot", "elastic", "grav_work", "damp_dissip", "plastic_dissip", "total",
+                 "visc_dissip")]
 
 
 class dem_stats(C.Structure):
@@ -127,6 +128,8 @@ SIGNATURES = {
     "dem_create": (C.c_int32, [C.POINTER(dem_params), C.POINTER(C.c_void_p)]),
     "dem_destroy": (C.c_int32, [C.c_void_p]),
     "dem_add_material": (C.c_int32, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, _I32P]),
+    "dem_add_viscel_material": (C.c_int32, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
+                                            _I32P]),
     "dem_add_spheres": (C.c_int32, [C.c_void_p, C.c_int64, _DP, _DP, _DP, _DP, _I32P, C.c_int32, _U8P, _I64P]),
     "dem_add_wall": (C.c_int32, [C.c_void_p, C.c_int32, C.c_double, C.c_int32, C.c_int32, _I64P]),
     "dem_pwave_dt": (C.c_int32, [C.c_void_p, _DP]),
@@ -275,6 +278,14 @@ class Scene:
         m = C.c_int32()
         check(self.lib.dem_add_material(self.h, density, young, poisson, friction_angle, C.byref(m)),
               "dem_add_material")
+        return m.value
+
+    def add_viscel_material(self, density, tc, en, et, friction_angle):
+        """ViscElMat from contact time and restitution coefficients
+        (Law2_ScGeom_ViscElPhys_Basic)."""
+        m = C.c_int32()
+        check(self.lib.dem_add_viscel_material(self.h, density, tc, en, et, friction_angle, C.byref(m)),
+              "dem_add_viscel_material")
         return m.value
 
     def add_spheres(self, pos, radius, vel=None, angvel=None, mat=None, default_mat=0, blocked=None):

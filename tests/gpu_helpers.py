@@ -7,15 +7,20 @@ EPS = np.finfo(float).eps
 
 
 def twin(spec, precision=0, track_energy=True, periodic=False, hsize=None, velgrad=None, dt=None,
-         vel=None, angvel=None, verlet_dist=-0.5):
-    """Build (gpu, oracle, dt) from a scenes.Scene-like spec."""
+         vel=None, angvel=None, verlet_dist=-0.5, viscel=None):
+    """Build (gpu, oracle, dt) from a scenes.Scene-like spec.  viscel =
+    (tc, en, et): a ViscElMat of the spec's density and friction angle in
+    place of its FrictMat (dt must then be given)."""
     from oracle import OracleScene
     from paper_2301_00611_amd import dem
 
     m = spec.material
     g = dem.Scene(gravity=spec.gravity, damping=spec.damping, track_energy=track_energy, precision=precision,
                   periodic=periodic, hsize=hsize, velgrad=velgrad, verlet_dist=verlet_dist)
-    mg = g.add_material(m.density, m.young, m.poisson, m.friction)
+    if viscel is None:
+        mg = g.add_material(m.density, m.young, m.poisson, m.friction)
+    else:
+        mg = g.add_viscel_material(m.density, *viscel, m.friction)
     for w in spec.walls:
         g.add_wall(w.axis, w.position, w.sense, mg)
     for c, h in getattr(spec, "boxes", []):
@@ -28,7 +33,10 @@ def twin(spec, precision=0, track_energy=True, periodic=False, hsize=None, velgr
     g.set_dt(dt)
     o = OracleScene(dt=dt, gravity=spec.gravity, damping=spec.damping, periodic=periodic, hsize=hsize,
                     velgrad=velgrad)
-    mo = o.add_material(m.density, m.young, m.poisson, m.friction)
+    if viscel is None:
+        mo = o.add_material(m.density, m.young, m.poisson, m.friction)
+    else:
+        mo = o.add_viscel_material(m.density, *viscel, m.friction)
     for w in spec.walls:
         o.add_wall(w.axis, w.position, w.sense, mo)
     for c, h in getattr(spec, "boxes", []):

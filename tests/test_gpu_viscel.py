@@ -1,0 +1,238 @@
+"""Parity of the GPU's visco-elastic law (Law2_ScGeom_ViscElPhys_Basic with
+ViscElMat from contact time and restitution coefficients, C ABI) with the
+oracle's, and its collision closed forms through the GPU path.
+
+Bars as for the linear law: pair sets identical and forces within 1e-12
+(FP64) / 1e-5 (FP32-mixed) from an identical state; multi-step runs keep
+identical pair sets while they coincide and energy terms within 1 %.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_helpers import body_force_errors, contact_errors, keyset, random_history, twin
+
+pytestmark = pytest.mark.gpu
+
+TC, EN, ET = 1e-4, 0.5, 0.7
+
+
+def _dense(n, seed):
+    from test_gpu_parity import _dense_spec
+    return _dense_spec(n, seed)
+
+
+def _one_step(n, seed, precision=0):
+    from paper_2301_00611_amd.scenes import random_velocities
+    spec = _dense(n, seed)
+    v, w = random_velocities(n, 0.05, seed + 100)
+    g, o, dt = twin(spec, precision=precision, vel=v, angvel=w * 0.05, viscel=(TC, EN, ET), dt=TC / 100)
+    rng = np.random.default_rng(seed + 7)
+    hist = random_history(spec.pos, spec.radius, spec.walls, rng)
+    if hist is not None:
+        g.set_history(*hist)
+        o.set_contacts(*hist)
+    g.step(1)
+    o.step(1)
+    cg, co = g.get_contacts(), o.get_contacts()
+    assert keyset(cg) == keyset(co)
+    return g, o, cg, co
+
+
+@pytest.mark.parametrize("n,seed", [(37, 1), (511, 2), (1500, 3)])
+def test_one_step_fp64_from_identical_state(n, seed):
+    g, o, cg, co = _one_step(n, seed)
+    assert len(co) > n // 8
+    err = contact_errors(cg, co)
+    assert np.max(err["f"]) <= 1e-12
+    assert np.max(err["fn"]) <= 1e-12
+    a = cg[np.lexsort((cg["id2"], cg["id1"]))]
+    b = co[np.lexsort((co["id2"], co["id1"]))]
+    for key in ("pen", "kn", "ks"):
+        assert np.allclose(a[key], b[key], rtol=1e-12, atol=0), key
+    # the library reports the shear force (spring and dashpot) as the stored
+    # total force less the normal force: that FP64 subtraction adds a few
+    # ulps of |F_n| to it
+    dfs = np.linalg.norm(a["fs"] - b["fs"], axis=1)
+    bound = 1e-12 * np.linalg.norm(b["fs"], axis=1) + 8 * np.finfo(float).eps * np.linalg.norm(b["fn"], axis=1)
+    assert np.all(dfs <= bound)
+    sg, so = g.get_state(), o.get_state()
+    ef, _ = body_force_errors(sg, so, co)
+    assert ef.max() <= 1e-12
+    assert np.abs(sg["pos"] - so["pos"]).max() <= 1e-14 * np.abs(so["pos"]).max()
+    eg, eo = g.get_energy(), o.get_energy()
+    assert eo["visc_dissip"] > 0.0
+    for k in eo:
+        assert eg[k] == pytest.approx(eo[k], rel=1e-11, abs=1e-12 * (abs(eo["kinetic"]) + abs(eo["elastic"]) + 1e-30)), k
+
+
+def test_one_step_fp32_mixed():
+    g, o, cg, co = _one_step(1500, 3, precision=1)
+    err = contact_errors(cg, co)
+    assert np.max(err["f"]) <= 1e-5
+    ef, _ = body_force_errors(g.get_state(), o.get_state(), co)
+    assert ef.max() <= 1e-5
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-5)])
+def test_periodic_shear_one_step(precision, tol):
+    """The periodic instantiation on the bidisperse shear workload's shape
+    (lattice squeezed by 0.2 % so that neighbours overlap, also across the
+    cell's faces; simple shear, so images move): one step, then 10 more
+    with identical pair sets."""
+    from paper_2301_00611_amd.scenes import periodic_bidisperse_gas, random_velocities
+    sc = periodic_bidisperse_gas(n=2000, seed=7)
+    squeeze = 0.998
+    sc.pos = sc.pos * squeeze
+    H = sc.hsize * squeeze
+    v, w = random_velocities(sc.n, 0.01, 8)
+    g, o, dt = twin(sc, precision=precision, periodic=True, hsize=H, velgrad=sc.velgrad, vel=v, angvel=w * 0.1,
+                    viscel=(TC, EN, ET), dt=TC / 100)
+    g.step(1)
+    o.step(1)
+    cg, co = g.get_contacts(), o.get_contacts()
+    assert len(co) > 500 and int((np.abs(co["cell"]).sum(axis=1) > 0).sum()) > 10
+    assert keyset(cg) == keyset(co)
+    assert contact_errors(cg, co)["f"].max() <= tol
+    ef, _ = body_force_errors(g.get_state(), o.get_state(), co)
+    assert ef.max() <= tol
+    g.step(10)
+    o.step(10)
+    assert keyset(g.get_contacts()) == keyset(o.get_contacts())
+
+
+def test_multistep_relaxation():
+    """A dense walled cloud relaxing under gravity for 1,000 steps (10 t_c):
+    identical pair sets at every check, energy terms (dashpot work included)
+    within 1 %."""
+    from paper_2301_00611_amd.scenes import random_velocities
+    spec = _dense(511, 2)
+    v, w = random_velocities(511, 0.05, 5)
+    g, o, dt = twin(spec, vel=v, angvel=w * 0.05, viscel=(TC, EN, ET), dt=TC / 100)
+    a, b = [], []
+    keys = ("kinetic", "elastic", "grav_work", "damp_dissip", "plastic_dissip", "visc_dissip")
+    for k in range(10):
+        g.step(100)
+        o.step(100)
+        assert keyset(g.get_contacts()) == keyset(o.get_contacts()), f"pair sets differ after {100 * (k + 1)} steps"
+        eg, eo = g.get_energy(), o.get_energy()
+        a.append([eg[x] for x in keys])
+        b.append([eo[x] for x in keys])
+    a, b = np.array(a), np.array(b)
+    assert b[-1, 5] > 0.0
+    assert np.abs(a - b).max() <= 0.01 * np.abs(b).max()
+
+
+def test_head_on_collision_closed_form_on_the_gpu():
+    """Two equal spheres approaching at 2v: contact duration t_c and
+    relative velocity -e_n times the incoming one (the closed form the
+    coefficients are built on), through the GPU path."""
+    from paper_2301_00611_amd import dem
+    R = 2.0 ** -10
+    steps_per_tc = 1000
+    dt = TC / steps_per_tc
+    g = dem.Scene(gravity=(0.0, 0.0, 0.0), damping=0.0)
+    m = g.add_viscel_material(2600.0, TC, EN, ET, 0.3)
+    v = 0.05
+    g.add_spheres(np.array([[0.0, 0.0, 0.0], [2 * R * (1 + 1e-4), 0.0, 0.0]]), [R, R],
+                  vel=np.array([[v, 0.0, 0.0], [-v, 0.0, 0.0]]), default_mat=m)
+    g.set_dt(dt)
+    start = end = None
+    for i in range(3 * steps_per_tc):
+        g.step(1)
+        n = g.stats()["n_contacts_ss"]
+        if n and start is None:
+            start = i
+        if start is not None and not n:
+            end = i
+            break
+    assert start is not None and end is not None
+    assert (end - start) * dt == pytest.approx(TC, abs=3 * dt)
+    vel = g.get_state()["vel"]
+    assert (vel[1, 0] - vel[0, 0]) / (2 * v) == pytest.approx(EN, rel=5e-3)
+
+
+def test_batched_viscel_scenes_match_single_scenes_bitwise():
+    """Three visco-elastic scenes with different materials and sizes, each
+    with walls, stepped as one batch equal the same scenes alone."""
+    from paper_2301_00611_amd import dem
+    from paper_2301_00611_amd.scenes import random_velocities
+    specs = [_dense(n, 10 + i) for i, n in enumerate((200, 500, 80))]
+    mats = [(TC, 0.5, 0.7), (2 * TC, 0.8, 0.4), (TC, 0.3, 0.9)]
+    dt = TC / 100
+    params = [dem.make_params(dt=dt, gravity=s.gravity, damping=s.damping) for s in specs]
+    batch = dem.Batch(params)
+    singles = []
+    for i, (s, vm) in enumerate(zip(specs, mats)):
+        v, w = random_velocities(s.n, 0.05, 30 + i)
+        for g in (batch.scene(i), dem.Scene(gravity=s.gravity, damping=s.damping)):
+            m = g.add_viscel_material(s.material.density, *vm, s.material.friction)
+            for wl in s.walls:
+                g.add_wall(wl.axis, wl.position, wl.sense, m)
+            g.add_spheres(s.pos, s.radius, vel=v, angvel=w * 0.05, default_mat=m)
+        g.set_dt(dt)
+        singles.append(g)
+    batch.step(300)
+    for i, single in enumerate(singles):
+        single.step(300)
+        a, b = batch.scene(i).get_state(), single.get_state()
+        for key in ("pos", "vel", "angvel"):
+            assert np.array_equal(a[key], b[key]), (i, key)
+    assert batch.stats()["contact_steps"] > 0
+
+
+def test_viscel_in_a_facet_box_one_step():
+    """The visco-elastic instantiation with facets and a box: one step of a
+    pressed lattice against the oracle."""
+    from oracle import OracleScene
+    from paper_2301_00611_amd import dem
+    R = 2.0 ** -10
+    rng = np.random.default_rng(3)
+    side = 16 * R
+    k = 8
+    grid = (np.arange(k) + 0.5) * (side / k)
+    pos = np.array([[x, y, z] for z in grid for y in grid for x in grid]) + rng.uniform(-0.1, 0.1, (k ** 3, 3)) * R
+    rad = rng.uniform(0.95, 1.1, k ** 3) * R
+    vel = rng.normal(0.0, 0.05, pos.shape)
+    g = dem.Scene(gravity=(0, 0, -9.81), damping=0.1, track_energy=True)
+    o = OracleScene(dt=1.0, gravity=(0, 0, -9.81), damping=0.1)
+    mg = g.add_viscel_material(2600.0, TC, EN, ET, 0.4)
+    mo = o.add_viscel_material(2600.0, TC, EN, ET, 0.4)
+    for tri in dem.facet_box_triangles([0.5 * side] * 3, [0.5 * side] * 3, wall_mask=63):
+        g.add_facet(*tri, mat=mg)
+        o.add_facet(*tri, mat=mo)
+    g.add_spheres(pos, rad, vel=vel, default_mat=mg)
+    o.add_spheres(pos, rad, vel=vel, default_mat=mo)
+    g.set_dt(TC / 100)
+    o.set_dt(TC / 100)
+    g.step(1)
+    o.step(1)
+    cg, co = g.get_contacts(), o.get_contacts()
+    assert keyset(cg) == keyset(co)
+    assert int((co["is_wall"] == 1).sum()) > 100
+    assert np.max(contact_errors(cg, co)["f"]) <= 1e-12
+
+
+def test_viscel_call_errors():
+    from paper_2301_00611_amd import dem
+    g = dem.Scene(gravity=(0, 0, 0))
+    with pytest.raises(dem.DemError):
+        g.add_viscel_material(2600.0, 0.0, 0.5, 0.5, 0.3)
+    with pytest.raises(dem.DemError):
+        g.add_viscel_material(2600.0, TC, 1.5, 0.5, 0.3)
+    a = g.add_material(2600.0, 1e7, 0.3, 0.5)
+    b = g.add_viscel_material(2600.0, TC, 0.5, 0.5, 0.3)
+    R = 1e-3
+    g.add_spheres(np.array([[0.0, 0.0, 0.0], [3 * R, 0.0, 0.0]]), [R, R], mat=[a, b])
+    g.set_dt(1e-6)
+    with pytest.raises(dem.DemError):
+        g.step(1)
+    with pytest.raises(dem.DemError):
+        g.stiffness_dt(0.5)
+    with pytest.raises(dem.DemError):
+        g.set_stiffness_timestepper(0.5, 10)
+    p = dem.Scene(periodic=True, hsize=np.eye(3) * 0.05)
+    p.add_viscel_material(2600.0, TC, 0.5, 0.5, 0.3)
+    with pytest.raises(dem.DemError):
+        p.set_peri_triax((0.0, 0.0, 0.0), 7)
