@@ -59,11 +59,17 @@ def profiled_traffic(kernel):
     return float(m.group(1))
 
 
-def build_scene(spec, precision=0, timing=False):
+def build_scene(spec, precision=0, timing=False, viscel=None):
+    """The GPU scene of a spec; viscel = (tc, en, et, dt): a ViscElMat of the
+    spec's density and friction angle in place of its FrictMat, stepped at
+    the given dt."""
     from paper_2301_00611_amd import dem
     m = spec.material
     s = dem.Scene(gravity=spec.gravity, damping=spec.damping, precision=precision)
-    mat = s.add_material(m.density, m.young, m.poisson, m.friction)
+    if viscel is None:
+        mat = s.add_material(m.density, m.young, m.poisson, m.friction)
+    else:
+        mat = s.add_viscel_material(m.density, viscel[0], viscel[1], viscel[2], m.friction)
     for w in spec.walls:
         s.add_wall(w.axis, w.position, w.sense, mat)
     for c, h in spec.boxes:
@@ -71,32 +77,32 @@ def build_scene(spec, precision=0, timing=False):
     for tri in spec.facets:
         s.add_facet(*tri, mat=mat)
     s.add_spheres(spec.pos, spec.radius, default_mat=mat)
-    s.set_dt(spec.dt_factor * s.pwave_dt())
+    s.set_dt(spec.dt_factor * s.pwave_dt() if viscel is None else viscel[3])
     s.set_timing(timing)
     return s
 
 
-def autotune_for(spec, precision=0, warmup=100, probe_steps=300, cache=None):
+def autotune_for(spec, precision=0, warmup=100, probe_steps=300, cache=None, viscel=None):
     """Autotuner on a throwaway scene of the workload (its probe steps are
     not timed); returns the chosen setting.  With a cache file that holds
     this workload, the stored setting is used without probing."""
-    w = build_scene(spec, precision)
+    w = build_scene(spec, precision, viscel=viscel)
     w.step(warmup)
     t = w.autotune(probe_steps=probe_steps, cache_path=cache)
     w.close()
     return {k: v for k, v in t.items() if k != "ms_per_step"}
 
 
-def timed_run(spec, steps, warmup, precision=0, timing=False, tuning=None):
+def timed_run(spec, steps, warmup, precision=0, timing=False, tuning=None, viscel=None):
     """Warm up on a throwaway scene, then time exactly `steps` steps of a
     fresh scene from its initial state.  With timing=True every contact and
     integrate launch is bracketed by HIP events (graph event nodes)."""
     import torch
     if warmup > 0:
-        w = build_scene(spec, precision, timing=timing)
+        w = build_scene(spec, precision, timing=timing, viscel=viscel)
         w.step(warmup)
         w.close()
-    s = build_scene(spec, precision, timing=timing)
+    s = build_scene(spec, precision, timing=timing, viscel=viscel)
     if tuning:
         s.set_tuning(**tuning)
     s.step(0)
@@ -168,7 +174,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32-mixed, batched and CPU legs")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="column",
-                    choices=("column", "periodic_compression", "periodic_shear", "batched", "facet_column"),
+                    choices=("column", "periodic_compression", "periodic_shear", "batched", "facet_column",
+                             "viscel_column"),
                     help="column: the headline line (default); the others run one extra leg alone")
     ap.add_argument("--prepared-state", default=None,
                     help="periodic_compression: .npz holding the prepared packing (written if missing)")
@@ -201,6 +208,9 @@ def main():
         return
     if args.workload == "facet_column":
         print(json.dumps(facet_column_leg(args.steps, args.warmup, log=log, cache=args.tuning_cache)), flush=True)
+        return
+    if args.workload == "viscel_column":
+        print(json.dumps(viscel_column_leg(args.steps, args.warmup, log=log, cache=args.tuning_cache)), flush=True)
         return
 
     from paper_2301_00611_amd.scenes import grid_column
@@ -264,12 +274,45 @@ def main():
         out["batched"] = batched_leg(log=log)
         log("facet-box column leg")
         out["facet_column"] = facet_column_leg(args.steps, args.warmup, log=log, cache=args.tuning_cache)
+        log("visco-elastic column leg")
+        out["viscel_column"] = viscel_column_leg(args.steps, args.warmup, log=log, cache=args.tuning_cache)
         log("periodic compression leg (FP64 vs FP32-mixed)")
         out["periodic_compression"] = periodic_leg("periodic_compression", log=log)
     if not args.no_cpu and not args.no_extra:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(spec)
     print(json.dumps(out), flush=True)
+
+
+def viscel_column_leg(steps, warmup, log=None, cache=None):
+    """The 200,000-sphere column of the headline line with the visco-elastic
+    law (ViscElMat, e_n = e_t = 0.5) in place of the linear one, at the same
+    dt; t_c = pi sqrt(m_eff / k_n) of the linear law for two 1 mm spheres
+    (3.28e-5 s, about 18 steps per collision)."""
+    import math
+    from paper_2301_00611_amd.scenes import grid_column
+    spec = grid_column(n=200_000, seed=0)
+    m = spec.material
+    mass = 4.0 / 3.0 * math.pi * 1e-3 ** 3 * m.density
+    tc = math.pi * math.sqrt(0.5 * mass / (m.young * 1e-3))
+    dt = spec.dt_factor * float(spec.radius.min()) * math.sqrt(m.density / m.young)
+    ve = (tc, 0.5, 0.5, dt)
+    tune = autotune_for(spec, 0, warmup=warmup, cache=cache, viscel=ve)
+    if log:
+        log(f"visco-elastic column: {spec.n} spheres, tc {tc:.3e} s, dt {dt:.3e} s, {steps} steps, setting {tune}")
+    r = timed_run(spec, steps, warmup, precision=0, tuning=tune, viscel=ve)
+    rt = timed_run(spec, steps, 0, precision=0, timing=True, tuning=tune, viscel=ve)
+    return {
+        "workload": "grid_column deposition with the visco-elastic law: 200,000 spheres r~U(0.5,1.5) mm, "
+                    f"tc={tc:.3e} s, en=et=0.5, phi=0.5, damping 0.2, dt={dt:.3e} s (the linear column's)",
+        "value": r["contact_steps"] / r["seconds"],
+        "unit": "contact-steps/s",
+        "ms_per_step": r["seconds"] / steps * 1e3,
+        "rebuilds": r["rebuilds"],
+        "tuning": tune,
+        "kernels_ms": {k: v["avg_ms"] for k, v in rt["kernels"].items()},
+        "contacts_last": r["contacts_last"],
+    }
 
 
 def facet_column_leg(steps, warmup, log=None, cache=None):
