@@ -121,8 +121,19 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
     // the arguments live in device memory so that a captured graph stays
     // valid across broad-phase runs (pair count and buffers change there)
     const StepArgs& a = *args;
+    // the previous step's stall flag is read first and tested only after this
+    // thread's pair ids are requested (in bounds; nothing is stored before
+    // the test), so that its latency overlaps theirs
+    const int32_t stalled = a.ctr->stall[parity ^ 1];
+    const int k = xcd_pair(a.npairs);
+    int32_t sa = 0, sb = 0, pcell = 0;
+    if (k >= 0) {
+        sa = glb<const int32_t>(a.pr.a)[k];
+        sb = glb<const int32_t>(a.pr.b)[k];
+        if (PERIODIC) pcell = glb<const int32_t>(a.pr.cell)[k];
+    }
     // the previous step asked for a broad-phase run: this step does not run
-    if (a.ctr->stall[parity ^ 1]) return;
+    if (stalled) return;
     // this step's flag starts clear; the integrate kernel may raise it.  The
     // step ends an update period of the controlled cell when the iteration
     // count after it is a multiple of the period (the later kernels of the
@@ -132,7 +143,6 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
         const CtrlConfig& c = *a.ctrl;
         a.ctr->measure = (c.active && (a.ctr->iter0 + a.ctr->steps_done + 1) % c.glob_update == 0) ? 1 : 0;
     }
-    const int k = xcd_pair(a.npairs);
     ContactPartial part = {0.0, 0.0, 0ull, 0ull, 0.0, 0.0};
     bool unstable = false;
     // the measuring instantiation keeps what its terms need (force and
@@ -146,9 +156,6 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
         const gptr<const uint16_t> mat = glb<const uint16_t>(a.bod.mat);
         const gptr<uint8_t> preal = glb(a.pr.real);
         const gptr<HistRec> hist = glb(a.pr.h);
-        const int32_t sa = glb<const int32_t>(a.pr.a)[k];
-        const int32_t sb = glb<const int32_t>(a.pr.b)[k];
-        const int32_t pcell = PERIODIC ? glb<const int32_t>(a.pr.cell)[k] : 0;
         const int s = BATCHED ? (int)glb<const uint16_t>(a.bod.scene)[sb] : 0;
         // an unbatched scene (periodic included) reads the descriptor's own
         // copy of its parameters: uniform, read-only here, so scalar loads

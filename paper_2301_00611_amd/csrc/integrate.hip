@@ -109,34 +109,48 @@ template <int PREC, bool BATCHED, bool PERIODIC>
 __global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restrict__ args, int parity)
 {
     const StepArgs& a = *args;
-    if (a.ctr->stall[parity ^ 1]) {
+    const int i = logical_block(gridDim.x) * blockDim.x + threadIdx.x;
+    const bool live = i < a.nslots;
+    const gptr<double4> bxr = glb(a.bod.xr), bvm = glb(a.bod.vm), bw = glb(a.bod.w), bq = glb(a.bod.q);
+    // the previous step's stall flag is read first and tested only after the
+    // body's loads are issued (they are in bounds, and nothing is stored
+    // before the test), so that its latency overlaps theirs; the row bounds
+    // before the body state: the row's loads wait for them
+    const int32_t stalled = a.ctr->stall[parity ^ 1];
+    int beg = 0, end = 0;
+    double4 xr0 = make_double4(0.0, 0.0, 0.0, 0.0), vm0 = xr0, w0 = xr0;
+    uint16_t mi = 0;
+    uint8_t blocked = 0;
+    if (live) {
+        beg = glb<const int32_t>(a.rows.start)[i];
+        end = glb<const int32_t>(a.rows.start)[i + 1];
+        xr0 = bxr[i];
+        vm0 = bvm[i];
+        w0 = bw[i];
+        mi = glb<const uint16_t>(a.bod.mat)[i];
+        blocked = glb<const uint8_t>(a.bod.blocked)[i];
+    }
+    if (stalled) {
         // not run: keep every later step of this launch chain stopped too
         if (blockIdx.x == 0 && threadIdx.x == 0) a.ctr->stall[parity] = 1;
         return;
     }
-    const int i = logical_block(gridDim.x) * blockDim.x + threadIdx.x;
     // this step ends an update period of the controlled cell: also sum the
     // dynamic spheres' |resultant contact force| (unbalanced force)
     const bool measure = a.ctr->measure != 0;
     IntPartial part = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     bool bad = false;
     bool over = false;
-    if (i < a.nslots) {
-        const gptr<double4> bxr = glb(a.bod.xr), bvm = glb(a.bod.vm), bw = glb(a.bod.w), bq = glb(a.bod.q);
-        // the row bounds first: the row's loads wait for them, not for the
-        // body's own state, which is requested right after
-        const int beg = glb<const int32_t>(a.rows.start)[i], end = glb<const int32_t>(a.rows.start)[i + 1];
+    if (live) {
         const int s = BATCHED ? (int)glb<const uint16_t>(a.bod.scene)[i] : 0;
         // an unbatched scene (periodic included) reads the descriptor's own
         // copy of its parameters: uniform, read-only here, so scalar loads
         const SceneParams& S = BATCHED ? a.scenes[s] : a.scene0;
         const double dt = S.dt;
         const double lam = S.damping;
-        const double4 xr0 = bxr[i], vm0 = bvm[i], w0 = bw[i];
-        const double rho = glb<const Material>(a.mats)[glb<const uint16_t>(a.bod.mat)[i]].density;
+        const double rho = glb<const Material>(a.mats)[mi].density;
         const double r = xr0.w, m = sphere_mass(r, rho);
         const double I = 2.0 * m * r * r / 5.0;
-        const unsigned blocked = glb<const uint8_t>(a.bod.blocked)[i];
         double F[3], T[3];
         body_sum<PREC>(a, beg, end, r, F, T);
         if (measure && blocked != 63u) {
