@@ -151,6 +151,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restr
         const double rho = glb<const Material>(a.mats)[mi].density;
         const double r = xr0.w, m = sphere_mass(r, rho);
         const double I = 2.0 * m * r * r / 5.0;
+        // FP64 division costs about ten FP64 instructions: the step divides
+        // by m and by I once and multiplies after that
+        const double inv_m = 1.0 / m, inv_I = 1.0 / I;
         double F[3], T[3];
         body_sum<PREC>(a, beg, end, r, F, T);
         if (measure && blocked != 63u) {
@@ -185,26 +188,27 @@ __global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restr
             }
             part.grav += -m * S.gravity[k] * v0[k] * dt;
             if (lam > 0.0) {
-                const double acc = f[k] / m;
+                const double acc = f[k] * inv_m;
                 const double df = -lam * sgn(f[k] * (v0[k] + acc * dt / 2.0)) * f[k];
                 part.damp += -df * v0[k] * dt;
                 f[k] += df;
             }
-            v[k] = v0[k] + f[k] / m * dt + homo[k];
+            v[k] = v0[k] + f[k] * inv_m * dt + homo[k];
         }
         const double x1[3] = {x0[0] + v[0] * dt, x0[1] + v[1] * dt, x0[2] + v[2] * dt};
 
         for (int k = 0; k < 3; ++k) {
             if (blocked & (8u << k)) continue;
             if (lam > 0.0 && S.damp_rot) {
-                const double acc = t[k] / I;
+                const double acc = t[k] * inv_I;
                 t[k] += -lam * sgn(t[k] * (w[k] + acc * dt / 2.0)) * t[k];
             }
-            w[k] = w[k] + t[k] / I * dt;
+            w[k] = w[k] + t[k] * inv_I * dt;
         }
-        const double wn = sqrt((w[0] * w[0] + w[1] * w[1]) + w[2] * w[2]);
-        if (wn > 0.0) {
+        const double ww = (w[0] * w[0] + w[1] * w[1]) + w[2] * w[2];
+        if (ww > 0.0) {
             // the orientation only changes (and is only read) for a spinning body
+            const double wn = sqrt(ww);
             const double4 q0 = bq[i];
             double q[4] = {q0.x, q0.y, q0.z, q0.w};
             const double half = 0.5 * wn * dt;
@@ -214,11 +218,11 @@ __global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restr
             const double n1 = d0 * q[1] + d1 * q[0] + d2 * q[3] - d3 * q[2];
             const double n2 = d0 * q[2] - d1 * q[3] + d2 * q[0] + d3 * q[1];
             const double n3 = d0 * q[3] + d1 * q[2] - d2 * q[1] + d3 * q[0];
-            const double qn = sqrt(n0 * n0 + n1 * n1 + n2 * n2 + n3 * n3);
-            q[0] = n0 / qn;
-            q[1] = n1 / qn;
-            q[2] = n2 / qn;
-            q[3] = n3 / qn;
+            const double inv_qn = 1.0 / sqrt(n0 * n0 + n1 * n1 + n2 * n2 + n3 * n3);
+            q[0] = n0 * inv_qn;
+            q[1] = n1 * inv_qn;
+            q[2] = n2 * inv_qn;
+            q[3] = n3 * inv_qn;
             bq[i] = make_double4(q[0], q[1], q[2], q[3]);
         }
         bxr[i] = make_double4(x1[0], x1[1], x1[2], r);
