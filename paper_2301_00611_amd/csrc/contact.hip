@@ -122,15 +122,17 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
     // valid across broad-phase runs (pair count and buffers change there)
     const StepArgs& a = *args;
     // the previous step's stall flag is read first and tested only after this
-    // thread's pair ids are requested (in bounds; nothing is stored before
-    // the test), so that its latency overlaps theirs
+    // thread's pair ids and its touched flag are requested (in bounds;
+    // nothing is stored before the test), so that its latency overlaps theirs
     const int32_t stalled = a.ctr->stall[parity ^ 1];
     const int k = xcd_pair(a.npairs);
     int32_t sa = 0, sb = 0, pcell = 0;
+    uint8_t was_real = 0;
     if (k >= 0) {
         sa = glb<const int32_t>(a.pr.a)[k];
         sb = glb<const int32_t>(a.pr.b)[k];
         if (PERIODIC) pcell = glb<const int32_t>(a.pr.cell)[k];
+        was_real = glb<const uint8_t>(a.pr.real)[k];
     }
     // the previous step asked for a broad-phase run: this step does not run
     if (stalled) return;
@@ -253,7 +255,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
 
         if (!real) {
             // the contact is erased: drop its history (once), no force
-            if (preal[k]) {
+            if (was_real) {
                 hist[k] = HistRec{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
                 preal[k] = 0;
             }
@@ -388,7 +390,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
                 q[1] = make_double2((double)F.z, (double)tau.x);
                 q[2] = make_double2((double)tau.y, (double)tau.z);
             }
-            preal[k] = 1;
+            if (!was_real) preal[k] = 1;
             if (wall)
                 part.sw = 1;
             else
