@@ -190,6 +190,87 @@ class PeriTriax:
         return done_steps
 
 
+class PeriIsoCompressor:
+    """Isotropic compression of a periodic cell through a series of mean
+    stresses (PeriIsoCompressor with keepProportions): after every
+    global_update_int-th step the mean stress sigma_m = tr(sigma)/3 and the
+    mean normal-spring modulus M_m = (M_1 + M_2 + M_3)/3 (contact_modulus)
+    give one strain rate for all three axes,
+        (1 - grow_damping)(goal - sigma_m)/(M_m T),  T = global_update_int dt,
+    or +-max_strain_rate towards the goal while M_m = 0, capped at
+    max_strain_rate (the law of the stress-controlled cell above, applied to
+    the mean).  A stress counts as reached when |goal - sigma_m| <=
+    max(abs_stress_tol, rel_stress_tol |goal|) and the unbalanced force is at
+    most max_unbalanced; then the next stress of the series becomes the goal
+    (its rate is set in the same update), and after the last one the cell
+    stops (done)."""
+
+    def __init__(self, sc, stresses, global_update_int=20, max_strain_rate=1.0, grow_damping=0.25,
+                 max_unbalanced=1e-4, abs_stress_tol=1e3, rel_stress_tol=3e-5):
+        self.sc = sc
+        self.stresses = [float(x) for x in stresses]
+        if not self.stresses:
+            raise ValueError("PeriIsoCompressor: empty stress series")
+        self.global_update_int = int(global_update_int)
+        self.max_rate = float(max_strain_rate)
+        self.grow_damping = float(grow_damping)
+        self.max_unbalanced = float(max_unbalanced)
+        self.abs_tol = float(abs_stress_tol)
+        self.rel_tol = float(rel_stress_tol)
+        self.state = 0
+        self.sigma = 0.0
+        self.stiff = 0.0
+        self.strain_rate = 0.0
+        self.unbalanced = float("nan")
+        self.updates = 0
+        self.done = False
+
+    def _rate(self, goal):
+        err = goal - self.sigma
+        T = self.global_update_int * self.sc.dt
+        if self.stiff > 0.0:
+            rate = (1.0 - self.grow_damping) * err / (self.stiff * T)
+        else:
+            rate = math.copysign(self.max_rate, err) if err != 0.0 else 0.0
+        return max(-self.max_rate, min(self.max_rate, rate))
+
+    def _reached(self, goal):
+        return (abs(goal - self.sigma) <= max(self.abs_tol, self.rel_tol * abs(goal))
+                and self.unbalanced <= self.max_unbalanced)
+
+    def update(self):
+        sc = self.sc
+        H, _trsf = sc.get_cell()
+        V = abs(float(np.linalg.det(H)))
+        sigma = sc.get_stress(V)
+        M = contact_modulus(sc, V)
+        self.sigma = (float(sigma[0, 0]) + float(sigma[1, 1]) + float(sigma[2, 2])) / 3.0
+        self.stiff = (M[0] + M[1] + M[2]) / 3.0
+        self.unbalanced = unbalanced_force(sc)
+        reached = self._reached(self.stresses[self.state])
+        if reached and self.state + 1 < len(self.stresses):
+            self.state += 1
+            reached = False
+        self.done = reached
+        self.strain_rate = 0.0 if reached else self._rate(self.stresses[self.state])
+        sc.set_velgrad(np.eye(3) * self.strain_rate)
+        self.updates += 1
+
+    def run(self, nsteps, stop_when_done=False):
+        """Step one at a time, updating after every global_update_int-th
+        step; returns the number of steps run."""
+        done_steps = 0
+        for _ in range(int(nsteps)):
+            self.sc.step(1)
+            done_steps += 1
+            it, _t = self.sc.counters()
+            if it % self.global_update_int == 0:
+                self.update()
+                if self.done and stop_when_done:
+                    break
+        return done_steps
+
+
 def run_with_timestepper(sc, nsteps, safety=0.8, interval=1):
     """Step with the stiffness timestepper: before every step whose
     iteration count is a multiple of `interval`, dt = stiffness_dt."""

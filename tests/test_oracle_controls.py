@@ -227,3 +227,95 @@ def test_modulus_of_a_diagonal_contact():
     assert M[0] == pytest.approx(E * R * l * l / 4 / V, rel=1e-12)
     assert M[1] == pytest.approx(E * R * l * l / 4 / V, rel=1e-12)
     assert abs(M[2]) < 1e-20 * M[0]
+
+
+# ------------------------------------------- isotropic stress-series compressor
+
+def _aniso_lattice(deltas=(0.01, 0.02, 0.03), k=3):
+    """Simple cubic lattice with a different overlap along each axis:
+    spacing a_i = 2r - delta_i, so sigma_ii = -k_n delta_i / (a_j a_k)."""
+    d = np.array(deltas) * R
+    a = 2 * R - d
+    g = [np.arange(k) * a[i] + 0.5 * a[i] for i in range(3)]
+    pos = np.array([[x, y, z] for z in g[2] for y in g[1] for x in g[0]])
+    H = np.diag(k * a)
+    s = OracleScene(dt=1.0, periodic=True, hsize=H)
+    mat = s.add_material(RHO, E, NU, 0.5)
+    s.add_spheres(pos, [R] * len(pos), default_mat=mat)
+    s.set_dt(0.2 * s.pwave_dt())
+    return s, a, d
+
+
+def test_iso_mean_stress_and_single_rate_closed_form():
+    """Different overlaps per axis: the compressor sees the mean stress
+    (sigma_xx + sigma_yy + sigma_zz)/3 with sigma_ii = -k_n delta_i/(a_j a_k),
+    the mean modulus (k_n/3)(a_x/(a_y a_z) + a_y/(a_x a_z) + a_z/(a_x a_y))
+    and sets one rate (1 - 0.25)(goal - sigma_m)/(M_m T) on all three axes
+    (guards the mean against a per-axis law)."""
+    from oracle.controls import PeriIsoCompressor
+    s, a, d = _aniso_lattice()
+    kn = E * R
+    sig = [-kn * d[i] / (a[(i + 1) % 3] * a[(i + 2) % 3]) for i in range(3)]
+    sm = sum(sig) / 3.0
+    Mm = kn / 3.0 * sum(a[i] / (a[(i + 1) % 3] * a[(i + 2) % 3]) for i in range(3))
+    c = PeriIsoCompressor(s, [2.0 * sm], global_update_int=5, max_strain_rate=1e3)
+    c.run(5)
+    assert c.updates == 1 and c.state == 0 and not c.done
+    assert c.sigma == pytest.approx(sm, rel=1e-9)
+    assert c.stiff == pytest.approx(Mm, rel=1e-9)
+    T = 5 * s.dt
+    assert c.strain_rate == pytest.approx(0.75 * (2.0 * sm - sm) / (Mm * T), rel=1e-9)
+    L = s.get_cell()[0]
+    c.run(5)
+    H = s.get_cell()[0]
+    # one rate on every axis: the cell keeps its proportions
+    assert H[0, 0] / H[1, 1] == pytest.approx(L[0, 0] / L[1, 1], rel=1e-14)
+    assert H[1, 1] / H[2, 2] == pytest.approx(L[1, 1] / L[2, 2], rel=1e-14)
+
+
+def test_iso_series_reaches_each_stress_in_turn():
+    """Two stresses, 1.5 and 2 times the lattice's: the compressor holds the
+    first until it is within tolerance, moves on, ends within tolerance of
+    the second with the cell stopped and the run cut short."""
+    from oracle.controls import PeriIsoCompressor
+    s, a, delta = _lattice()
+    kn = E * R
+    sig0 = -kn * delta / a ** 2
+    tol = 1e-3 * abs(sig0)
+    c = PeriIsoCompressor(s, [1.5 * sig0, 2.0 * sig0], global_update_int=5, max_strain_rate=1e3,
+                          abs_stress_tol=tol, rel_stress_tol=0.0, max_unbalanced=1e-6)
+    switched_at = None
+    for _ in range(1000):
+        before = c.state
+        c.run(5)
+        if before == 0 and c.state == 1:
+            switched_at = c.sigma
+        if c.done:
+            break
+    assert switched_at is not None and abs(switched_at - 1.5 * sig0) <= tol
+    assert c.done and c.state == 1 and abs(c.sigma - 2.0 * sig0) <= tol
+    assert c.strain_rate == 0.0
+    h0 = s.get_cell()[0]
+    s.step(5)
+    assert np.array_equal(s.get_cell()[0], h0)
+
+
+def test_iso_unbalanced_force_gates_the_series():
+    """At the goal from the start but with a jittered lattice (unbalanced
+    force of order one): not reached while max_unbalanced is below it,
+    reached at the first update once it is above."""
+    from oracle.controls import PeriIsoCompressor, unbalanced_force
+    s, a, delta = _lattice()
+    rng = np.random.default_rng(2)
+    st = s.get_state()
+    s.set_state(pos=st["pos"] + rng.uniform(-0.2, 0.2, st["pos"].shape) * delta)
+    s.step(1)
+    ub = unbalanced_force(s)
+    H = s.get_cell()[0]
+    sm = float(np.trace(s.get_stress(abs(np.linalg.det(H))))) / 3.0
+    c = PeriIsoCompressor(s, [sm], global_update_int=1, max_unbalanced=0.5 * ub, abs_stress_tol=1e6)
+    c.update()
+    assert not c.done and c.state == 0
+    c2 = PeriIsoCompressor(s, [sm], global_update_int=1, max_unbalanced=10 * ub, abs_stress_tol=1e6)
+    c2.update()
+    assert c2.done and c2.strain_rate == 0.0
