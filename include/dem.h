@@ -325,10 +325,57 @@ typedef struct {
     int32_t done;              /* the goal was reached at the last update */
     int32_t active;
 } dem_peri_triax_state;
+
+/* PeriIsoCompressor with keepProportions (class PeriIsoCompressor: stresses,
+ * globalUpdateInt, maxUnbalanced, state, sigma, currUnbalanced): the cell is
+ * compressed or dilated isotropically until the mean stress tr(sigma)/3
+ * reaches stresses[0], then stresses[1], ... .  The law is the controlled
+ * cell's (dem_set_peri_triax) applied to the mean: every global_update-th
+ * step one strain rate (1 - grow_damping)(goal - sigma_m)/(M_m T) for all
+ * three axes, M_m the mean of the normal springs' modulus per axis, T =
+ * global_update dt, +-max_strain_rate while M_m = 0, capped at
+ * max_strain_rate.  A stress is reached when |goal - sigma_m| <=
+ * max(abs_stress_tol, rel_stress_tol |goal|) and the unbalanced force is at
+ * most max_unbalanced; the next stress is then driven to from the same
+ * update; after the last one the cell stops, and with stop_when_done
+ * dem_step returns there (the doneHook's usual pause).  It replaces the
+ * controlled cell of dem_set_peri_triax (one controller per scene). */
+#define DEM_MAX_STRESS_SERIES 8
+typedef struct {
+    int32_t n_stresses;           /* 1 .. DEM_MAX_STRESS_SERIES */
+    int32_t global_update;        /* globalUpdateInt, >= 1 (default 20) */
+    double stresses[DEM_MAX_STRESS_SERIES]; /* [Pa], negative in compression */
+    double max_strain_rate;       /* > 0 [1/s] (default 1) */
+    double grow_damping;          /* [0, 1) (default 0.25) */
+    double max_unbalanced;        /* maxUnbalanced (default 1e-4) */
+    double abs_stress_tol;        /* [Pa] (default 1e3) */
+    double rel_stress_tol;        /* (default 3e-5) */
+    int32_t stop_when_done;
+    int32_t pad_;
+} dem_peri_iso;                   /* 136 bytes */
+
+typedef struct {
+    int32_t state;                /* index of the stress being driven to */
+    int32_t done;                 /* 1 once the last stress is reached */
+    double sigma;                 /* mean stress at the last update [Pa] */
+    double stiff;                 /* mean normal-spring modulus at the last update [Pa] */
+    double strain_rate;           /* the rate set on each axis [1/s] */
+    double unbalanced;            /* currUnbalanced (NaN before the first update) */
+    int64_t updates;
+    int32_t active;               /* 1 while this compressor is the scene's controller */
+    int32_t pad_;
+} dem_peri_iso_state;             /* 56 bytes */
+
 void dem_peri_triax_default(dem_peri_triax* c);
 /* c = NULL switches the controller off (the velocity gradient stays). */
 dem_status dem_set_peri_triax(dem_scene* s, const dem_peri_triax* c);
 dem_status dem_get_peri_triax(dem_scene* s, dem_peri_triax_state* out);
+/* The isotropic compressor; NULL switches the scene's controller off.  Same
+ * scene requirements and refusals as dem_set_peri_triax; DEM_EINVAL for an
+ * empty or too long series or a non-finite stress. */
+void dem_peri_iso_default(dem_peri_iso* c);
+dem_status dem_set_peri_iso(dem_scene* s, const dem_peri_iso* c);
+dem_status dem_get_peri_iso(dem_scene* s, dem_peri_iso_state* out);
 
 /* Average device duration [ms] of each kernel family over the last
  * dem_step call (names: "contact", "integrate", "rebuild"), measured with

@@ -261,6 +261,10 @@ struct Counters {
 // The stress/strain-controlled periodic cell (PeriTriaxController driven by
 // the packing stiffness), run on the device after the steps that make the
 // iteration count a multiple of glob_update.
+// iso: the isotropic compressor (PeriIsoCompressor with keepProportions):
+// the goals are series[0 .. n_series), one after another, controlled on the
+// mean stress with one rate for all axes; stress_mask and goal are unused.
+constexpr int kMaxStressSeries = 8;
 struct CtrlConfig {
     double goal[3];
     int32_t stress_mask;
@@ -272,13 +276,16 @@ struct CtrlConfig {
     double rel_tol;
     int32_t stop_when_done;
     int32_t active;
+    int32_t iso;
+    int32_t n_series;
+    double series[kMaxStressSeries];
 };
 struct CtrlState {
     double stress[3], strain[3], rate[3], stiff[3];
     double unbalanced;
     int64_t updates;
     int32_t done;
-    int32_t pad_;
+    int32_t series_index;     // iso: the goal being driven to
 };
 // The controlled cell's sums come from the step kernels' own blocks on its
 // update steps: the contact kernel's measuring instantiation (kNetworkWords

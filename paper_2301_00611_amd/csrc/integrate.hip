@@ -409,10 +409,39 @@ __global__ void __launch_bounds__(kCellBlock) k_cell_update(StepArgs* args, int 
             const double T = (double)c.glob_update * S->dt;
             double rates[3];
             bool reached = true;
+            const double ncont = sum[13], ndyn = sum[kNetworkWords + 1];
+            st.unbalanced = (ncont > 0.0 && ndyn > 0.0) ? (sum[kNetworkWords] / ndyn) / (sum[12] / ncont) : NAN;
             for (int i = 0; i < 3; ++i) {
                 st.stress[i] = sum[4 * i] / V;
                 st.strain[i] = log(S->trsf[4 * i]);
                 st.stiff[i] = sum[9 + i] / V;
+            }
+            if (c.iso) {
+                // the isotropic compressor: mean stress and mean modulus, one
+                // rate; a reached stress (balanced packing) hands over to the
+                // next of the series in the same update
+                const double sm = (st.stress[0] + st.stress[1] + st.stress[2]) / 3.0;
+                const double Mm = (st.stiff[0] + st.stiff[1] + st.stiff[2]) / 3.0;
+                double goal = c.series[st.series_index];
+                auto at_goal = [&](double g) {
+                    return fabs(g - sm) <= fmax(c.abs_tol, c.rel_tol * fabs(g)) && st.unbalanced <= c.max_unbalanced;
+                };
+                reached = at_goal(goal);
+                if (reached && st.series_index + 1 < c.n_series) {
+                    st.series_index += 1;
+                    goal = c.series[st.series_index];
+                    reached = false;
+                }
+                const double err = goal - sm;
+                double rate;
+                if (Mm > 0.0)
+                    rate = (1.0 - c.grow_damping) * err / (Mm * T);
+                else
+                    rate = err != 0.0 ? copysign(c.max_rate[0], err) : 0.0;
+                rate = fmax(-c.max_rate[0], fmin(c.max_rate[0], rate));
+                rates[0] = rates[1] = rates[2] = rate;
+            }
+            for (int i = 0; i < 3 && !c.iso; ++i) {
                 double rate;
                 if (c.stress_mask & (1 << i)) {
                     const double err = c.goal[i] - st.stress[i];
@@ -428,9 +457,7 @@ __global__ void __launch_bounds__(kCellBlock) k_cell_update(StepArgs* args, int 
                 }
                 rates[i] = fmax(-c.max_rate[i], fmin(c.max_rate[i], rate));
             }
-            const double ncont = sum[13], ndyn = sum[kNetworkWords + 1];
-            st.unbalanced = (ncont > 0.0 && ndyn > 0.0) ? (sum[kNetworkWords] / ndyn) / (sum[12] / ncont) : NAN;
-            if (!(st.unbalanced <= c.max_unbalanced)) reached = false;
+            if (!c.iso && !(st.unbalanced <= c.max_unbalanced)) reached = false;
             st.done = reached ? 1 : 0;
             if (reached) rates[0] = rates[1] = rates[2] = 0.0;
             double lf = 0.0;

@@ -1802,6 +1802,7 @@ struct World {
     double ts_safety = 0.8;
     int64_t ts_interval = 0;
     bool pt_active = false;
+    bool pt_iso = false;        // the active controller is the isotropic compressor
     int pt_glob_update = 1;
 
     void set_peri_triax(const dem_peri_triax* c)
@@ -1833,9 +1834,60 @@ struct World {
         }
         HIPC(hipStreamSynchronize(stream));
         pt_active = c != nullptr;
+        pt_iso = false;
         pt_glob_update = c ? c->glob_update : 1;
         if (d_args.p) upload_args();
     }
+    // The isotropic compressor through a stress series: the same device
+    // controller in its iso mode.
+    void set_peri_iso(const dem_peri_iso* c)
+    {
+        CtrlConfig k;
+        std::memset(&k, 0, sizeof k);
+        k.iso = 1;
+        k.stress_mask = 7;
+        k.n_series = c->n_stresses;
+        for (int j = 0; j < c->n_stresses; ++j) k.series[j] = c->stresses[j];
+        for (int i = 0; i < 3; ++i) {
+            k.goal[i] = c->stresses[0];
+            k.max_rate[i] = c->max_strain_rate;
+        }
+        k.glob_update = c->global_update;
+        k.grow_damping = c->grow_damping;
+        k.max_unbalanced = c->max_unbalanced;
+        k.abs_tol = c->abs_stress_tol;
+        k.rel_tol = c->rel_stress_tol;
+        k.stop_when_done = c->stop_when_done;
+        k.active = 1;
+        HIPC(hipMemcpyAsync(d_ctrl_cfg.p, &k, sizeof k, hipMemcpyHostToDevice, stream));
+        CtrlState st;
+        std::memset(&st, 0, sizeof st);
+        st.unbalanced = NAN;
+        HIPC(hipMemcpyAsync(d_ctrl_state.p, &st, sizeof st, hipMemcpyHostToDevice, stream));
+        HIPC(hipStreamSynchronize(stream));
+        pt_active = true;
+        pt_iso = true;
+        pt_glob_update = c->global_update;
+        if (d_args.p) upload_args();
+    }
+    dem_peri_iso_state peri_iso_state()
+    {
+        CtrlState st;
+        HIPC(hipMemcpyAsync(&st, d_ctrl_state.p, sizeof st, hipMemcpyDeviceToHost, stream));
+        HIPC(hipStreamSynchronize(stream));
+        dem_peri_iso_state o;
+        std::memset(&o, 0, sizeof o);
+        o.state = st.series_index;
+        o.done = st.done;
+        o.sigma = (st.stress[0] + st.stress[1] + st.stress[2]) / 3.0;
+        o.stiff = (st.stiff[0] + st.stiff[1] + st.stiff[2]) / 3.0;
+        o.strain_rate = st.rate[0];
+        o.unbalanced = st.unbalanced;
+        o.updates = st.updates;
+        o.active = (pt_active && pt_iso) ? 1 : 0;
+        return o;
+    }
+
     dem_peri_triax_state peri_triax_state()
     {
         CtrlState st;
@@ -1852,7 +1904,7 @@ struct World {
         o.unbalanced = st.unbalanced;
         o.updates = st.updates;
         o.done = st.done;
-        o.active = pt_active ? 1 : 0;
+        o.active = (pt_active && !pt_iso) ? 1 : 0;
         return o;
     }
 
@@ -2582,6 +2634,52 @@ void dem_peri_triax_default(dem_peri_triax* c)
     c->max_unbalanced = 1e-4;
     c->abs_stress_tol = 1e3;
     c->rel_stress_tol = 3e-5;
+}
+
+void dem_peri_iso_default(dem_peri_iso* c)
+{
+    if (!c) return;
+    std::memset(c, 0, sizeof *c);
+    c->global_update = 20;
+    c->max_strain_rate = 1.0;
+    c->grow_damping = 0.25;
+    c->max_unbalanced = 1e-4;
+    c->abs_stress_tol = 1e3;
+    c->rel_stress_tol = 3e-5;
+}
+
+dem_status dem_set_peri_iso(dem_scene* s, const dem_peri_iso* c)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        if (!c) {
+            w->set_peri_triax(nullptr);
+            return;
+        }
+        if (w->has_viscel()) dem::fail(DEM_EINVAL, "dem_set_peri_iso: not available with visco-elastic materials");
+        if (!w->scenes[s->s].p.periodic || w->scenes.size() > 1)
+            dem::fail(DEM_EINVAL, "dem_set_peri_iso: needs an unbatched periodic scene");
+        if (c->n_stresses < 1 || c->n_stresses > DEM_MAX_STRESS_SERIES)
+            dem::fail(DEM_EINVAL, "dem_set_peri_iso: 1 to 8 stresses");
+        for (int j = 0; j < c->n_stresses; ++j)
+            if (!std::isfinite(c->stresses[j])) dem::fail(DEM_EINVAL, "dem_set_peri_iso: non-finite stress");
+        if (c->global_update < 1) dem::fail(DEM_EINVAL, "dem_set_peri_iso: global_update >= 1");
+        if (!(c->grow_damping >= 0.0 && c->grow_damping < 1.0)) dem::fail(DEM_EINVAL, "dem_set_peri_iso: grow_damping in [0, 1)");
+        if (!(c->max_strain_rate > 0.0) || !std::isfinite(c->max_strain_rate))
+            dem::fail(DEM_EINVAL, "dem_set_peri_iso: max_strain_rate > 0");
+        if (!(c->abs_stress_tol >= 0.0) || !(c->rel_stress_tol >= 0.0) || std::isnan(c->max_unbalanced))
+            dem::fail(DEM_EINVAL, "dem_set_peri_iso: tolerances >= 0");
+        w->set_peri_iso(c);
+    });
+}
+
+dem_status dem_get_peri_iso(dem_scene* s, dem_peri_iso_state* out)
+{
+    return guarded([&] {
+        dem::World* w = world_of(s);
+        if (!out) dem::fail(DEM_EINVAL, "null output");
+        *out = w->peri_iso_state();
+    });
 }
 
 dem_status dem_set_peri_triax(dem_scene* s, const dem_peri_triax* c)

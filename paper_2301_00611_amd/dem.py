@@ -97,6 +97,19 @@ class dem_peri_triax_state(C.Structure):
                 ("done", C.c_int32), ("active", C.c_int32)]
 
 
+class dem_peri_iso(C.Structure):
+    _fields_ = [("n_stresses", C.c_int32), ("global_update", C.c_int32), ("stresses", C.c_double * 8),
+                ("max_strain_rate", C.c_double), ("grow_damping", C.c_double), ("max_unbalanced", C.c_double),
+                ("abs_stress_tol", C.c_double), ("rel_stress_tol", C.c_double), ("stop_when_done", C.c_int32),
+                ("pad_", C.c_int32)]
+
+
+class dem_peri_iso_state(C.Structure):
+    _fields_ = [("state", C.c_int32), ("done", C.c_int32), ("sigma", C.c_double), ("stiff", C.c_double),
+                ("strain_rate", C.c_double), ("unbalanced", C.c_double), ("updates", C.c_int64),
+                ("active", C.c_int32), ("pad_", C.c_int32)]
+
+
 def _tuning_dict(t):
     return {k: getattr(t, k) for k, _ in dem_tuning._fields_ if k != "pad"}
 
@@ -170,6 +183,9 @@ SIGNATURES = {
     "dem_peri_triax_default": (None, [C.POINTER(dem_peri_triax)]),
     "dem_set_peri_triax": (C.c_int32, [C.c_void_p, C.POINTER(dem_peri_triax)]),
     "dem_get_peri_triax": (C.c_int32, [C.c_void_p, C.POINTER(dem_peri_triax_state)]),
+    "dem_peri_iso_default": (None, [C.POINTER(dem_peri_iso)]),
+    "dem_set_peri_iso": (C.c_int32, [C.c_void_p, C.POINTER(dem_peri_iso)]),
+    "dem_get_peri_iso": (C.c_int32, [C.c_void_p, C.POINTER(dem_peri_iso_state)]),
 }
 
 _lib = None
@@ -481,6 +497,29 @@ class Scene:
             else:
                 setattr(c, k, float(v))
         check(self.lib.dem_set_peri_triax(self.h, C.byref(c)), "dem_set_peri_triax")
+
+    def set_peri_iso(self, stresses=None, **kw):
+        """PeriIsoCompressor (keepProportions): drive the mean stress to each
+        of `stresses` in turn (None switches the controller off).  Keywords:
+        global_update, max_strain_rate, grow_damping, max_unbalanced,
+        abs_stress_tol, rel_stress_tol, stop_when_done."""
+        if stresses is None:
+            check(self.lib.dem_set_peri_iso(self.h, None), "dem_set_peri_iso")
+            return
+        c = dem_peri_iso()
+        self.lib.dem_peri_iso_default(C.byref(c))
+        st = [float(x) for x in stresses]
+        c.n_stresses = len(st)
+        for j, x in enumerate(st[:8]):
+            c.stresses[j] = x
+        for k, v in kw.items():
+            setattr(c, k, int(v) if k in ("global_update", "stop_when_done") else float(v))
+        check(self.lib.dem_set_peri_iso(self.h, C.byref(c)), "dem_set_peri_iso")
+
+    def get_peri_iso(self):
+        st = dem_peri_iso_state()
+        check(self.lib.dem_get_peri_iso(self.h, C.byref(st)), "dem_get_peri_iso")
+        return {k: getattr(st, k) for k, _ in dem_peri_iso_state._fields_ if k != "pad_"}
 
     def get_peri_triax(self):
         st = dem_peri_triax_state()

@@ -58,6 +58,11 @@ LAYOUT_PROBE = r"""
 int main(void) {
   printf("dem_params %zu\ndem_contact %zu\ndem_history %zu\ndem_energy %zu\ndem_stats %zu\n",
          sizeof(dem_params), sizeof(dem_contact), sizeof(dem_history), sizeof(dem_energy), sizeof(dem_stats));
+  printf("dem_peri_triax %zu\ndem_peri_triax_state %zu\ndem_peri_iso %zu\ndem_peri_iso_state %zu\n",
+         sizeof(dem_peri_triax), sizeof(dem_peri_triax_state), sizeof(dem_peri_iso), sizeof(dem_peri_iso_state));
+  P(dem_energy, visc_dissip); P(dem_peri_iso, stresses); P(dem_peri_iso, max_strain_rate);
+  P(dem_peri_iso, stop_when_done); P(dem_peri_iso_state, sigma); P(dem_peri_iso_state, updates);
+  P(dem_peri_iso_state, active);
   P(dem_params, verlet_dist); P(dem_params, precision); P(dem_params, hsize); P(dem_params, homo_deform);
   P(dem_params, stream); P(dem_contact, normal); P(dem_contact, kn); P(dem_history, fs); P(dem_stats, coordination);
   return 0;
@@ -77,6 +82,8 @@ def test_struct_layouts_match_header(tmp_path):
     assert int(lines["dem_history"]) == ctypes.sizeof(dem.dem_history)
     assert int(lines["dem_energy"]) == ctypes.sizeof(dem.dem_energy)
     assert int(lines["dem_stats"]) == ctypes.sizeof(dem.dem_stats)
+    for name in ("dem_peri_triax", "dem_peri_triax_state", "dem_peri_iso", "dem_peri_iso_state"):
+        assert int(lines[name]) == ctypes.sizeof(getattr(dem, name)), name
     for key, val in lines.items():
         if "." in key:
             cls, field = key.split(".")

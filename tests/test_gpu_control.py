@@ -188,3 +188,100 @@ def test_control_call_errors():
     b = dem.Batch([dem.make_params(dt=1e-6), dem.make_params(dt=1e-6)])
     with pytest.raises(dem.DemError):
         b.scene(0).set_stiffness_timestepper(0.5, 3)
+
+
+def _aniso_twin(deltas=(0.01, 0.02, 0.03), k=5, jitter=0.0, seed=0):
+    """Simple cubic lattice with spacing a_i = 2r - delta_i per axis (a
+    different overlap along each axis), GPU and oracle."""
+    from oracle import OracleScene
+    from paper_2301_00611_amd import dem
+    d = np.array(deltas) * R
+    a = 2 * R - d
+    g = [np.arange(k) * a[i] + 0.5 * a[i] for i in range(3)]
+    pos = np.array([[x, y, z] for z in g[2] for y in g[1] for x in g[0]])
+    if jitter:
+        pos = pos + np.random.default_rng(seed).uniform(-jitter, jitter, pos.shape) * d.min()
+    H = np.diag(k * a)
+    gs = dem.Scene(periodic=True, hsize=H, gravity=(0, 0, 0), damping=0.2)
+    mg = gs.add_material(RHO, E, NU, 0.5)
+    gs.add_spheres(pos, [R] * len(pos), default_mat=mg)
+    dt = 0.2 * gs.pwave_dt()
+    gs.set_dt(dt)
+    o = OracleScene(dt=dt, periodic=True, hsize=H, damping=0.2)
+    mo = o.add_material(RHO, E, NU, 0.5)
+    o.add_spheres(pos, [R] * len(pos), default_mat=mo)
+    return gs, o, a, d, dt
+
+
+def test_peri_iso_closed_form_on_the_gpu():
+    """Through the GPU path: mean stress (sum of -k_n delta_i/(a_j a_k))/3,
+    mean modulus, and one rate 0.75 (goal - sigma_m)/(M_m 5 dt) on every
+    axis at the first update."""
+    g, o, a, d, dt = _aniso_twin()
+    kn = E * R
+    sig = [-kn * d[i] / (a[(i + 1) % 3] * a[(i + 2) % 3]) for i in range(3)]
+    sm = sum(sig) / 3.0
+    Mm = kn / 3.0 * sum(a[i] / (a[(i + 1) % 3] * a[(i + 2) % 3]) for i in range(3))
+    g.set_peri_iso([2.0 * sm], global_update=5, max_strain_rate=1e3)
+    g.step(5)
+    st = g.get_peri_iso()
+    assert st["active"] == 1 and st["updates"] == 1 and st["state"] == 0 and st["done"] == 0
+    assert st["sigma"] == pytest.approx(sm, rel=1e-9)
+    assert st["stiff"] == pytest.approx(Mm, rel=1e-9)
+    assert st["strain_rate"] == pytest.approx(0.75 * sm / (Mm * 5 * dt), rel=1e-9)
+    assert g.get_peri_triax()["active"] == 0
+    h0 = g.get_cell()[0]
+    g.step(5)
+    h1 = g.get_cell()[0]
+    for i, j in ((0, 1), (1, 2)):
+        assert h1[i, i] / h1[j, j] == pytest.approx(h0[i, i] / h0[j, j], rel=1e-14)
+
+
+def test_peri_iso_run_parity():
+    """A jittered anisotropic lattice through a two-stress series for 200
+    steps (40 updates): series position, mean stress, modulus, rate and the
+    cell as in the oracle."""
+    from oracle.controls import PeriIsoCompressor
+    g, o, a, d, dt = _aniso_twin(jitter=0.2, seed=3)
+    kn = E * R
+    sm0 = -kn * d.mean() / (2 * R) ** 2
+    series = [1.2 * sm0, 1.5 * sm0]
+    kw = dict(global_update=5, max_strain_rate=50.0, grow_damping=0.3, abs_stress_tol=0.02 * abs(sm0),
+              rel_stress_tol=0.0, max_unbalanced=0.5)
+    g.set_peri_iso(series, **kw)
+    c = PeriIsoCompressor(o, series, global_update_int=5, max_strain_rate=50.0, grow_damping=0.3,
+                          abs_stress_tol=0.02 * abs(sm0), rel_stress_tol=0.0, max_unbalanced=0.5)
+    g.step(200)
+    c.run(200)
+    st = g.get_peri_iso()
+    assert st["updates"] == c.updates == 40
+    assert st["state"] == c.state and st["done"] == int(c.done)
+    assert st["sigma"] == pytest.approx(c.sigma, rel=1e-9)
+    assert st["stiff"] == pytest.approx(c.stiff, rel=1e-9)
+    assert st["strain_rate"] == pytest.approx(c.strain_rate, rel=1e-8, abs=1e-12)
+    hg, _ = g.get_cell()
+    ho, _ = o.get_cell()
+    assert np.abs(hg - ho).max() <= 1e-12 * np.abs(ho).max()
+    assert not np.allclose(hg, np.diag(5 * a))      # the cell did move
+
+
+def test_peri_iso_stops_when_done_and_errors():
+    from paper_2301_00611_amd import dem
+    g, o, a, d, dt = _lattice_twin()
+    sig = -E * R * d / a ** 2
+    g.set_peri_iso([sig], global_update=5, stop_when_done=1)
+    g.step(50)
+    st = g.get_peri_iso()
+    assert st["done"] == 1 and st["updates"] == 1 and g.stats()["iter"] == 5
+    g.set_peri_iso(None)
+    assert g.get_peri_iso()["active"] == 0
+    with pytest.raises(dem.DemError):
+        g.set_peri_iso([])
+    with pytest.raises(dem.DemError):
+        g.set_peri_iso([sig] * 9)
+    with pytest.raises(dem.DemError):
+        g.set_peri_iso([float("nan")])
+    w = dem.Scene(gravity=(0, 0, 0))
+    w.add_material(RHO, E, NU, 0.5)
+    with pytest.raises(dem.DemError):
+        w.set_peri_iso([sig])
