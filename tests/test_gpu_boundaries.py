@@ -350,3 +350,83 @@ def test_boundaries_fp32_mixed_one_step():
     assert keyset(cg) == keyset(co)
     assert int((co["is_wall"] == 1).sum()) > 40
     assert contact_errors(cg, co)["f"].max() <= 1e-5
+
+
+def _scatter_near(rng, sample, n, existing, r, tries=200):
+    """n sphere centres from sample(), each at least 1.3 r from every centre
+    already placed (sphere overlaps stay below 0.7 r)."""
+    out = []
+    for _ in range(n):
+        for _ in range(tries):
+            p = sample()
+            if all(np.linalg.norm(p - q) >= 1.3 * r for q in existing + out):
+                out.append(p)
+                break
+    return out
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_random_triangles_and_boxes_one_step(seed):
+    """Arbitrarily oriented triangles and boxes of random shape, each on its
+    own cell of a coarse grid, with spheres scattered over their face, edge,
+    vertex and (for boxes) inside regions: one step, pair sets identical,
+    normals within 1e-13, forces within 1e-12."""
+    rng = np.random.default_rng(100 + seed)
+    cell = 16 * R
+    tris, boxes, centres = [], [], []
+    for c in range(27):
+        base = (np.array([c % 3, (c // 3) % 3, c // 9], dtype=float) + 0.5) * cell
+        if c % 3 == 2:
+            half = rng.uniform(1.0, 3.0, 3) * R
+            boxes.append((base, half))
+
+            def sample(base=base, half=half):
+                u = rng.uniform(-1.0, 1.0, 3) * (half + 0.9 * R)
+                return base + u
+        else:
+            q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+            pts = rng.uniform(-3.0, 3.0, (3, 2)) * R
+            v = [base + q[:, 0] * p[0] + q[:, 1] * p[1] for p in pts]
+            if np.linalg.norm(np.cross(v[1] - v[0], v[2] - v[0])) < 2 * R * R:
+                continue
+            tris.append(tuple(v))
+            nrm = q[:, 2]
+
+            def sample(v=v, nrm=nrm):
+                a, b = rng.uniform(-0.4, 1.2, 2)
+                p = v[0] + a * (v[1] - v[0]) + b * (v[2] - v[0])
+                return p + rng.uniform(-0.9, 0.9) * R * nrm
+        centres += _scatter_near(rng, sample, 8, centres, R)
+    pos = np.array(centres)
+    rad = rng.uniform(0.95, 1.0, len(pos)) * R
+    vel = rng.normal(0.0, 0.05, pos.shape)
+
+    def build(g, mg, o, mo):
+        for c, h in boxes:
+            g.add_box(c, h, mg)
+            o.add_box(c, h, mo)
+        for t in tris:
+            g.add_facet(*t, mat=mg)
+            o.add_facet(*t, mat=mo)
+        g.add_spheres(pos, rad, vel=vel, default_mat=mg)
+        o.add_spheres(pos, rad, vel=vel, default_mat=mo)
+
+    g, o = _both(build, gravity=(0.0, 0.0, -9.81), damping=0.1)
+    g.step(1)
+    o.step(1)
+    cg, co = g.get_contacts(), o.get_contacts()
+    assert keyset(cg) == keyset(co)
+    assert int((co["is_wall"] == 1).sum()) > 60
+    err = contact_errors(cg, co)
+    assert err["f"].max() <= 1e-12
+    # a boundary normal (x - p)/|x - p| from a closest point p computed in a
+    # different order carries the rounding of x and p over |x - p|: its
+    # error bound grows as the centre nears the triangle or the box
+    cs = co[np.lexsort((co["id2"], co["id1"]))]
+    nb = len(boxes) + len(tris)
+    r2 = rad[cs["id2"] - nb]
+    dist = np.where(cs["is_wall"] == 1, r2 - cs["pen"], np.inf)
+    bound = 1e-13 + 16 * np.finfo(float).eps * np.abs(pos).max() / np.maximum(dist, 1e-300)
+    assert np.all(err["normal"] <= bound)
+    sg, so = g.get_state(), o.get_state()
+    assert np.abs(sg["pos"] - so["pos"]).max() <= 1e-14 * np.abs(so["pos"]).max()
