@@ -91,7 +91,10 @@ typedef struct {
     void* stream;         /* hipStream_t to run on, or NULL for a library-owned stream */
 } dem_params;
 
-/* One real contact. */
+/* One real contact.  Under the visco-elastic law fn holds the spring and
+ * the normal dashpot (k_n pen - c_n u_n) n, fs the spring's and the shear
+ * dashpot's force, and kn, ks the pair's visco-elastic stiffnesses; the shear
+ * history (dem_history) holds the spring's part only. */
 typedef struct {
     int64_t id1, id2;
     int32_t cell[3];
