@@ -296,7 +296,8 @@ def _thrown_into_facet_box(n, seed, side):
     return pos, rad, vel
 
 
-def test_batched_boundaries_match_single_scenes_bitwise():
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_boundaries_match_single_scenes_bitwise(precision):
     """Three scenes of different sizes, each thrown into its own facet box
     with a box obstacle, stepped as one batch equal the same scenes stepped
     alone, bit for bit, after 600 steps (the batched box/facet
@@ -309,11 +310,11 @@ def test_batched_boundaries_match_single_scenes_bitwise():
     pm = probe.add_material(RHO, E, NU, 0.5)
     probe.add_spheres(np.zeros((1, 3)), [R], default_mat=pm)
     dt = 0.3 * probe.pwave_dt()
-    params = [dem.make_params(dt=dt, gravity=(0.0, 0.0, -9.81), damping=0.3) for _ in specs]
+    params = [dem.make_params(dt=dt, gravity=(0.0, 0.0, -9.81), damping=0.3, precision=precision) for _ in specs]
     batch = dem.Batch(params)
     singles = []
     for i, ((pos, rad, vel), side) in enumerate(zip(specs, sides)):
-        for g in (batch.scene(i), dem.Scene(gravity=(0.0, 0.0, -9.81), damping=0.3)):
+        for g in (batch.scene(i), dem.Scene(gravity=(0.0, 0.0, -9.81), damping=0.3, precision=precision)):
             m = g.add_material(RHO, E, NU, 0.5)
             g.add_facet_box([0.5 * side] * 3, [0.5 * side] * 3, m, wall_mask=31)
             g.add_box([0.5 * side, 0.5 * side, 0.1 * side], [0.15 * side, 0.1 * side, 0.1 * side], m)

@@ -153,7 +153,8 @@ def test_head_on_collision_closed_form_on_the_gpu():
     assert (vel[1, 0] - vel[0, 0]) / (2 * v) == pytest.approx(EN, rel=5e-3)
 
 
-def test_batched_viscel_scenes_match_single_scenes_bitwise():
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_viscel_scenes_match_single_scenes_bitwise(precision):
     """Three visco-elastic scenes with different materials and sizes, each
     with walls, stepped as one batch equal the same scenes alone."""
     from paper_2301_00611_amd import dem
@@ -161,12 +162,12 @@ def test_batched_viscel_scenes_match_single_scenes_bitwise():
     specs = [_dense(n, 10 + i) for i, n in enumerate((200, 500, 80))]
     mats = [(TC, 0.5, 0.7), (2 * TC, 0.8, 0.4), (TC, 0.3, 0.9)]
     dt = TC / 100
-    params = [dem.make_params(dt=dt, gravity=s.gravity, damping=s.damping) for s in specs]
+    params = [dem.make_params(dt=dt, gravity=s.gravity, damping=s.damping, precision=precision) for s in specs]
     batch = dem.Batch(params)
     singles = []
     for i, (s, vm) in enumerate(zip(specs, mats)):
         v, w = random_velocities(s.n, 0.05, 30 + i)
-        for g in (batch.scene(i), dem.Scene(gravity=s.gravity, damping=s.damping)):
+        for g in (batch.scene(i), dem.Scene(gravity=s.gravity, damping=s.damping, precision=precision)):
             m = g.add_viscel_material(s.material.density, *vm, s.material.friction)
             for wl in s.walls:
                 g.add_wall(wl.axis, wl.position, wl.sense, m)
