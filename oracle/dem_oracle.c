@@ -673,7 +673,8 @@ static void frict_phys(const mat_t* m1, const mat_t* m2, double R1, double R2,
 /* Ip2_ViscElMat_ViscElMat_ViscElPhys from contact time and restitution
  * coefficients (Pournin's formulation): the pair takes the means of the two
  * materials' tc, en and et, and m is the reduced mass m1 m2/(m1 + m2) (the
- * sphere's own mass against a boundary, which does not move); then
+ * other sphere's own mass against a body that cannot move: a boundary or a
+ * sphere with all six DOFs blocked); then
  * (getViscoelasticFromSpheresInteraction with that m)
  *   kn = m (pi^2 + ln^2 en)/tc^2,        cn = -2 m ln(en)/tc,
  *   ks = 2/7 m (pi^2 + ln^2 et)/tc^2,    cs = -2/7 m ln(et)/tc,
@@ -683,7 +684,12 @@ static void viscel_phys(const mat_t* m1, const mat_t* m2, const body_t* b1, cons
                         double* kn, double* cn, double* ks, double* cs, double* tanphi)
 {
     const double pi = 3.14159265358979323846;
-    double m = b1->is_wall ? b2->m : b1->m * b2->m / (b1->m + b2->m);
+    /* a body that cannot move (a boundary, or a sphere with all six DOFs
+     * blocked) leaves the other's own mass */
+    const int fixed1 = b1->is_wall || b1->blocked == 63u, fixed2 = !b2->is_wall && b2->blocked == 63u;
+    double m = b1->m * b2->m / (b1->m + b2->m);
+    if (fixed1 && !fixed2) m = b2->m;
+    if (fixed2 && !fixed1) m = b1->m;
     double tc = 0.5 * (m1->tc + m2->tc);
     double len = log(0.5 * (m1->en + m2->en));
     double let = log(0.5 * (m1->et + m2->et));

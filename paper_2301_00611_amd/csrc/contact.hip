@@ -295,10 +295,16 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
             const bool ve = VISCEL && M2.viscel != 0;
             if (ve) {
                 // Ip2_ViscElMat_ViscElMat_ViscElPhys: the pair's constants
-                // scaled by the reduced mass (the sphere's against a boundary)
+                // scaled by the reduced mass; a body that cannot move (a
+                // boundary, or a sphere with all six DOFs blocked) leaves the
+                // other's own mass
+                const gptr<const uint8_t> blk = glb<const uint8_t>(a.bod.blocked);
+                const bool fixed1 = wall || blk[s1] == 63u, fixed2 = blk[sb] == 63u;
                 const double m2m = sphere_mass(r2, M2.density);
-                const double m1m = wall ? 1.0 : sphere_mass(r1, M1.density);
-                const double mr = wall ? m2m : m1m * m2m / (m1m + m2m);
+                const double m1m = wall ? 0.0 : sphere_mass(r1, M1.density);
+                double mr = m1m * m2m / (m1m + m2m);
+                if (fixed1 && !fixed2) mr = m2m;
+                if (fixed2 && !fixed1) mr = m1m;
                 const ViscElPair P = glb<const ViscElPair>(a.ve)[m1 * a.nmat + m2];
                 const double pi2 = 3.14159265358979323846 * 3.14159265358979323846;
                 const double tc2 = P.tc * P.tc;

@@ -1981,7 +1981,11 @@ struct World {
                 // visco-elastic law: the kernel left the overlap and the signed
                 // normal force in the history record; the shear force reported
                 // is the total (spring and dashpot) less the normal force
-                const double mr = wall ? B2.m : B1->m * B2.m / (B1->m + B2.m);
+                const bool fixed1 = wall || B1->blocked == 63u, fixed2 = B2.blocked == 63u;
+                const double m1 = wall ? 0.0 : B1->m;
+                double mr = m1 * B2.m / (m1 + B2.m);
+                if (fixed1 && !fixed2) mr = B2.m;
+                if (fixed2 && !fixed1) mr = m1;
                 const double tc = 0.5 * (M1.tc + M2.tc);
                 const double len = std::log(0.5 * (M1.en + M2.en)), let = std::log(0.5 * (M1.et + M2.et));
                 const double pi2 = 3.14159265358979323846 * 3.14159265358979323846;

@@ -237,3 +237,46 @@ def test_viscel_call_errors():
     p.add_viscel_material(2600.0, TC, 0.5, 0.5, 0.3)
     with pytest.raises(dem.DemError):
         p.set_peri_triax((0.0, 0.0, 0.0), 7)
+
+
+@pytest.mark.parametrize("fixed", [0, 1])
+def test_collision_with_a_fixed_sphere_on_the_gpu(fixed):
+    """A sphere hitting a sphere with all six DOFs blocked, through the GPU
+    path: t_c and e_n with the moving sphere's own mass, and the reported
+    k_n equal to the oracle's at the first contact step."""
+    from oracle import OracleScene
+    from paper_2301_00611_amd import dem
+    R = 2.0 ** -10
+    steps_per_tc = 1000
+    dt = TC / steps_per_tc
+    v = 0.05
+    pos = np.array([[0.0, 0.0, 0.0], [2 * R * (1 + 1e-4), 0.0, 0.0]])
+    moving = 1 - fixed
+    vel = np.zeros((2, 3))
+    vel[moving, 0] = v if moving == 0 else -v
+    blocked = [0, 0]
+    blocked[fixed] = 63
+    g = dem.Scene(gravity=(0.0, 0.0, 0.0), damping=0.0)
+    mg = g.add_viscel_material(2600.0, TC, EN, ET, 0.3)
+    g.add_spheres(pos, [R, R], vel=vel, default_mat=mg, blocked=blocked)
+    g.set_dt(dt)
+    o = OracleScene(dt=dt, gravity=(0.0, 0.0, 0.0), damping=0.0)
+    mo = o.add_viscel_material(2600.0, TC, EN, ET, 0.3)
+    o.add_spheres(pos, [R, R], vel=vel, default_mat=mo, blocked=blocked)
+    start = end = None
+    for i in range(3 * steps_per_tc):
+        g.step(1)
+        n = g.stats()["n_contacts_ss"]
+        if n and start is None:
+            start = i
+            for _ in range(i + 1):
+                o.step(1)
+            assert g.get_contacts()["kn"][0] == pytest.approx(o.get_contacts()["kn"][0], rel=1e-14)
+        if start is not None and not n:
+            end = i
+            break
+    assert start is not None and end is not None
+    assert (end - start) * dt == pytest.approx(TC, abs=3 * dt)
+    st = g.get_state()
+    assert -st["vel"][moving, 0] / vel[moving, 0] == pytest.approx(EN, rel=5e-3)
+    assert np.array_equal(st["pos"][fixed], pos[fixed])

@@ -96,8 +96,8 @@ def test_boundary_pins_catch_mutation(name, tmp_path):
 
 # slips in the visco-elastic law, caught by tests/test_oracle_viscel.py
 VISCEL_MUTATIONS = {
-    "viscel_sphere_mass_not_reduced": ("double m = b1->is_wall ? b2->m : b1->m * b2->m / (b1->m + b2->m);",
-                                       "double m = b2->m;"),
+    "viscel_sphere_mass_not_reduced": ("double m = b1->m * b2->m / (b1->m + b2->m);", "double m = b2->m;"),
+    "viscel_fixed_sphere_mass": ("if (fixed2 && !fixed1) m = b1->m;", ""),
     "viscel_tangential_without_two_sevenths": ("*ks = 2.0 / 7.0 * m * (pi * pi + let * let) / (tc * tc);",
                                                "*ks = m * (pi * pi + let * let) / (tc * tc);"),
     "viscel_normal_dashpot_sign": ("fn_mag = kn * pen - cn * un;", "fn_mag = kn * pen + cn * un;"),

@@ -87,6 +87,29 @@ def test_unequal_spheres_use_the_reduced_mass():
     assert abs(m1 * vel[0, 0] + m2 * vel[1, 0] - (m1 - m2) * v) <= 1e-13 * m2 * v
 
 
+@pytest.mark.parametrize("fixed", [0, 1])
+def test_collision_with_a_fixed_sphere_uses_the_moving_mass(fixed):
+    """A sphere hitting a sphere with all six DOFs blocked (as #1 or as #2
+    of the pair): t_c and e_n with the moving sphere's own mass (the fixed
+    one acts as a boundary); the fixed sphere does not move."""
+    v, en = 0.05, 0.5
+    s = OracleScene(dt=TC / STEPS_PER_TC, gravity=(0.0, 0.0, 0.0), damping=0.0)
+    m = s.add_viscel_material(RHO, TC, en, 1.0, 0.3)
+    pos = np.array([[0.0, 0.0, 0.0], [2 * R * (1 + 1e-3), 0.0, 0.0]])
+    moving = 1 - fixed
+    vel = np.zeros((2, 3))
+    vel[moving, 0] = v if moving == 0 else -v
+    blocked = [0, 0]
+    blocked[fixed] = 63
+    s.add_spheres(pos, [R, R], vel=vel, default_mat=m, blocked=blocked)
+    start, end = _run_collision(s, 3 * STEPS_PER_TC)
+    dt = TC / STEPS_PER_TC
+    assert (end - start) * dt == pytest.approx(TC, abs=3 * dt)
+    st = s.get_state()
+    assert -st["vel"][moving, 0] / vel[moving, 0] == pytest.approx(en, rel=3e-3)
+    assert np.array_equal(st["pos"][fixed], pos[fixed])
+
+
 def _wall_bounce(en, et, vn, vt, friction=1.5):
     s = OracleScene(dt=TC / STEPS_PER_TC, gravity=(0.0, 0.0, 0.0), damping=0.0)
     m = s.add_viscel_material(RHO, TC, en, et, friction)
