@@ -132,7 +132,7 @@ def test_head_on_collision_closed_form_on_the_gpu():
     R = 2.0 ** -10
     steps_per_tc = 1000
     dt = TC / steps_per_tc
-    g = dem.Scene(gravity=(0.0, 0.0, 0.0), damping=0.0)
+    g = dem.Scene(gravity=(0.0, 0.0, 0.0), damping=0.0, track_energy=True)
     m = g.add_viscel_material(2600.0, TC, EN, ET, 0.3)
     v = 0.05
     g.add_spheres(np.array([[0.0, 0.0, 0.0], [2 * R * (1 + 1e-4), 0.0, 0.0]]), [R, R],
@@ -151,6 +151,9 @@ def test_head_on_collision_closed_form_on_the_gpu():
     assert (end - start) * dt == pytest.approx(TC, abs=3 * dt)
     vel = g.get_state()["vel"]
     assert (vel[1, 0] - vel[0, 0]) / (2 * v) == pytest.approx(EN, rel=5e-3)
+    # the dashpots took (1 - e_n^2) of the initial kinetic energy
+    e0 = 2 * 0.5 * (4.0 / 3.0 * math.pi * R ** 3 * 2600.0) * v * v
+    assert g.get_energy()["visc_dissip"] / e0 == pytest.approx(1 - EN ** 2, rel=1e-2)
 
 
 @pytest.mark.parametrize("precision", [0, 1])

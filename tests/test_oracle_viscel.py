@@ -129,6 +129,16 @@ def test_wall_bounce_uses_the_sphere_mass():
     assert s.get_state()["vel"][1, 2] / vn == pytest.approx(en, rel=3e-3)
 
 
+def test_wall_bounce_energy_balance():
+    """A sphere bouncing on a wall with e_n = 0.4: the dashpot work is
+    (1 - e_n^2) of the incoming kinetic energy (the wall takes none)."""
+    vn, en = 0.1, 0.4
+    s = _wall_bounce(en, 1.0, vn, 0.0)
+    _run_collision(s, 3 * STEPS_PER_TC)
+    e0 = 0.5 * _mass(R) * vn * vn
+    assert s.get_energy()["visc_dissip"] / e0 == pytest.approx(1 - en * en, rel=5e-3)
+
+
 @pytest.mark.parametrize("et", [0.9, 0.5])
 def test_oblique_sticking_impact_tangential_closed_form(et):
     """Oblique impact on a wall with e_n = 1 (no normal dashpot, so the
