@@ -1044,8 +1044,11 @@ static void newton_body(const orc_scene* s, body_t* b, const double F_in[3], con
     for (int k = 0; k < 3; ++k) {
         if (b->blocked & (8u << k)) continue;
         if (lam > 0.0 && s->p.damp_rot) {
+            /* the torque's share of the damping work, on the mid-step spin w-
+             * as for the force (the rotational counterpart of nonviscDamp) */
             double a = t[k] / b->I;
             double dtq = -lam * sgn(t[k] * (b->w[k] + a * dt / 2.0)) * t[k];
+            en->damp += -dtq * b->w[k] * dt;
             t[k] += dtq;
         }
         b->w[k] = b->w[k] + t[k] / b->I * dt;

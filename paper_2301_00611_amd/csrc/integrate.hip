@@ -200,8 +200,11 @@ __global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restr
         for (int k = 0; k < 3; ++k) {
             if (blocked & (8u << k)) continue;
             if (lam > 0.0 && S.damp_rot) {
+                // the torque's share of the damping work uses the mid-step spin
                 const double acc = t[k] * inv_I;
-                t[k] += -lam * sgn(t[k] * (w[k] + acc * dt / 2.0)) * t[k];
+                const double dtq = -lam * sgn(t[k] * (w[k] + acc * dt / 2.0)) * t[k];
+                part.damp += -dtq * w[k] * dt;
+                t[k] += dtq;
             }
             w[k] = w[k] + t[k] * inv_I * dt;
         }

@@ -22,6 +22,8 @@ MUTATIONS = {
     "torque_branch_of_2": ("cross3(br2, f2, ct->t2);", "cross3(br1, f2, ct->t2);"),
     "normal_force_sign": ("fn[k] = fn_mag * n[k];", "fn[k] = -fn_mag * n[k];"),
     "damping_without_half_step": ("(v0[k] + a * dt / 2.0)", "(v0[k])"),
+    "rotdamp_without_half_step": ("(b->w[k] + a * dt / 2.0)", "(b->w[k])"),
+    "rotdamp_work_dropped": ("en->damp += -dtq * b->w[k] * dt;", ""),
     "damping_excludes_gravity": ("f[k] = F_in[k] + b->m * s->p.gravity[k];", "f[k] = F_in[k];"),
     "elastic_energy_factor": ("*e_el += 0.5 * (fn_mag * fn_mag / kn)", "*e_el += 1.0 * (fn_mag * fn_mag / kn)"),
     "no_image_velocity": ("for (int k = 0; k < 3; ++k) v2[k] += sv[k] / dt;", ""),
