@@ -1,18 +1,24 @@
 #!/usr/bin/env python3
-"""Benchmark: one DEM timestep over spheres and walls on one MI355X.
+"""Benchmark: the DEM timestep over a dense periodic packing on one MI355X.
 
-Workload (N=1): 200,000 spheres, radius U(0.5, 1.5) mm, jittered column grid
-(spacing 3.03 mm, 33 x 33 columns) falling onto a floor inside four side
-walls, E = 5e7 Pa, nu = 0.3, friction 0.5 rad, damping 0.2, gravity -9.81,
-dt = 0.5 x P-wave step, FP64.  A "step" is one pass of the whole path:
-broad phase when the Verlet budget is spent, contact kernel, ordered force
-sum + Newton.
+Headline (N=1), the largest configuration that fits one GPU: 8,000,000
+spheres, bidisperse radii 0.5 and 2.0 mm (equal volumes), periodic simple
+shear at 1/s (Cell.velGrad[0][2] = 1, homoDeform 2), E = 1e8 Pa, nu = 0.3,
+friction 0.5 rad, damping 0.1, dt = 0.5 x P-wave step, FP64, from a dense
+packing prepared at a mean stress of 1 kPa (not timed).  A "step" is one
+pass of the whole path: a broad-phase run when the Verlet budget is spent,
+the contact kernel, the ordered force sum + Newton, the cell update.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra] [--workload NAME]
 
-Warm-up runs W steps on a throwaway scene of the same configuration; then a
-fresh scene is timed for exactly K steps from its initial state (default
-K = 10,000, the configuration's length).  Prints ONE JSON line.
+W untimed steps run on the timed scene itself, then one broad-phase run
+brings the pair list up to date, then exactly K steps are timed (inputs
+resident in HBM, no host<->device copies in the timed region but the
+per-chunk 64-byte counter read-back).  A second pass of the same scene with
+per-kernel HIP events gives the kernel durations for the roofline and the
+broad phase's cost per run and run rate, reported beside the timed rate as
+an amortised term.  FP32-mixed runs beside it on the same prepared packing.
+Prints ONE JSON line.
 """
 from __future__ import annotations
 
@@ -20,6 +26,7 @@ import argparse
 import json
 import math
 import os
+import statistics
 import sys
 import time
 
@@ -28,33 +35,41 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 
-# Algorithmic bytes (what the method must move, FP64):
+# Algorithmic bytes (what the method must move):
+#   contact kernel: per body gathered once x, v, w, r = 80 B (FP32-mixed: x
+#   in FP64, v, w, r in FP32 = 52 B); per real contact ids 8 + shear force
+#   r/w 48 + previous normal r/w 48 = 104 B (FP32-mixed: normal in FP32,
+#   80 B); per non-real candidate its ids, 8 B.
 #   integrate kernel, per body: read x, v, w, q, r, m (14 doubles) + material
 #   and blocked bytes = 114 B; write x, v, w, q (13 doubles) = 104 B.
-#   contact kernel: per body gathered once x, v, w, r = 80 B; per real
-#   contact ids 8 + shear force r/w 48 + previous normal r/w 48 = 104 B; per
-#   non-real candidate its ids, 8 B.
+CONTACT_BYTES = {0: (80, 104, 8), 1: (52, 80, 8)}
 INTEGRATE_BYTES_PER_BODY = 218
-CONTACT_BYTES_PER_BODY = 80
-CONTACT_BYTES_PER_REAL = 104
-CONTACT_BYTES_PER_CANDIDATE = 8
 
 
-def profiled_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when the kernel's source changed since it was taken."""
+def contact_algorithmic_bytes(precision, n_bodies, contacts, candidates):
+    b_body, b_real, b_cand = CONTACT_BYTES[precision]
+    return b_body * n_bodies + b_real * contacts + b_cand * max(candidates - contacts, 0)
+
+
+def kernel_source_hash(kernel):
     import hashlib
-    import re
-    path = os.path.join(ROOT, "profiles", "traffic_grid_column_200k.md")
-    if not os.path.exists(path):
-        return None
-    m = re.search(rf"traffic_bytes_per_launch {kernel} (\d+) source_sha256_16 (\w+)", open(path).read())
-    if not m:
-        return None
     csrc = os.path.join(ROOT, "paper_2301_00611_amd", "csrc")
     src = kernel.replace("k_", "") + ".hip"
     blob = open(os.path.join(csrc, src), "rb").read() + open(os.path.join(csrc, "dem_internal.hpp"), "rb").read()
-    if hashlib.sha256(blob).hexdigest()[:16] != m.group(2):
+    return hashlib.sha256(blob).hexdigest()[:16]
+
+
+def profiled_traffic(kernel, profile, precision=0):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 counter
+    summary (profiles/<profile>.md), or None when the kernel's source
+    changed since the counters were taken."""
+    import re
+    path = os.path.join(ROOT, "profiles", profile + ".md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(rf"traffic_bytes_per_launch {kernel} precision {precision} (\d+) source_sha256_16 (\w+)",
+                  open(path).read())
+    if not m or m.group(2) != kernel_source_hash(kernel):
         return None
     return float(m.group(1))
 
@@ -95,8 +110,9 @@ def autotune_for(spec, precision=0, warmup=100, probe_steps=300, cache=None, vis
 
 def timed_run(spec, steps, warmup, precision=0, timing=False, tuning=None, viscel=None):
     """Warm up on a throwaway scene, then time exactly `steps` steps of a
-    fresh scene from its initial state.  With timing=True every contact and
-    integrate launch is bracketed by HIP events (graph event nodes)."""
+    fresh scene from its initial state (its pair list built before the
+    timed region).  With timing=True every contact and integrate launch is
+    bracketed by HIP events."""
     import torch
     if warmup > 0:
         w = build_scene(spec, precision, timing=timing, viscel=viscel)
@@ -105,7 +121,7 @@ def timed_run(spec, steps, warmup, precision=0, timing=False, tuning=None, visce
     s = build_scene(spec, precision, timing=timing, viscel=viscel)
     if tuning:
         s.set_tuning(**tuning)
-    s.step(0)
+    s.step(0)  # the initial broad-phase run, outside the timed region
     st0 = s.stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -128,59 +144,351 @@ def timed_run(spec, steps, warmup, precision=0, timing=False, tuning=None, visce
     }
 
 
-def cpu_baseline(spec_full, budget_s=15.0):
-    """The FP64 oracle, single thread, on a bounded sample of the same
-    workload: the bottom layer of the same column (its first 33 x 33 spheres,
-    the layer that meets the floor, with the same 5 walls), stepped from the
-    initial state for about `budget_s` seconds."""
-    from oracle import OracleScene
-    cols = int(math.floor(0.1 / 3.03e-3))
-    n_sample = min(cols * cols, spec_full.n)
-    pos, rad = spec_full.pos[:n_sample], spec_full.radius[:n_sample]
-    m = spec_full.material
-    dt = spec_full.dt_factor * spec_full.radius.min() * math.sqrt(m.density / m.young)
-    o = OracleScene(dt=dt, gravity=spec_full.gravity, damping=spec_full.damping)
-    mo = o.add_material(m.density, m.young, m.poisson, m.friction)
-    for w in spec_full.walls:
-        o.add_wall(w.axis, w.position, w.sense, mo)
-    o.add_spheres(pos, rad, default_mat=mo)
-    steps, contacts = 0, 0
+# ------------------------------------------------------------------ periodic
+
+def _periodic_scene(H, L, spec, pos, vel, angvel, precision, friction=None, track_energy=False):
+    from paper_2301_00611_amd import dem
+    m = spec.material
+    g = dem.Scene(periodic=True, hsize=H, velgrad=L, damping=spec.damping, gravity=spec.gravity,
+                  precision=precision, track_energy=track_energy)
+    mg = g.add_material(m.density, m.young, m.poisson, m.friction if friction is None else friction)
+    g.add_spheres(pos, spec.radius, vel=vel, angvel=angvel, default_mat=mg)
+    g.set_dt(spec.dt_factor * g.pwave_dt())
+    return g
+
+
+PERIODIC_WORKLOADS = {
+    # name: (generator, spheres, tiling of the prepared packing, description)
+    "periodic_shear": ("periodic_bidisperse_gas", 8_000_000, 4,
+                       "periodic simple shear: {n} spheres, r = 0.5 and 2.0 mm (equal volumes), E=1e8, nu=0.3, "
+                       "phi=0.5, damping 0.1, velGrad[0][2] = 1/s, homoDeform 2, dt=0.5*P-wave"),
+    "periodic_compression": ("periodic_lognormal_gas", 2_000_000, 4,
+                             "periodic isotropic compression: {n} spheres, lognormal r (median 1 mm, sigma 0.3), "
+                             "E=1e8, nu=0.25, phi=0.3, damping 0.3, velGrad=-0.01 I, homoDeform 2, dt=0.5*P-wave"),
+}
+
+
+def _workload_spec(name, n, seed=0):
+    from paper_2301_00611_amd import scenes
+    return getattr(scenes, PERIODIC_WORKLOADS[name][0])(n=n, seed=seed)
+
+
+def prepare_periodic(name, n, seed=0, target_pressure=1e3, log=None):
+    """Unmeasured preparation of a periodic workload: its lattice cloud of
+    n / tile^3 spheres compressed frictionless (friction 0, same stiffness
+    and damping) by a schedule of compressions and velocity resets to a
+    jammed packing, settled at a mean stress of -target_pressure by the
+    library's isotropic compressor, then replicated tile^3 times into a cell
+    tile times wider (the same periodic packing, n spheres).  Returns the
+    spec of the n-sphere workload and its prepared state (positions,
+    velocities, spins, cell)."""
+    import numpy as np
+    from paper_2301_00611_amd.prepare import jam_isotropic, mean_pressure, settle_iso, tile_periodic
+    tile = PERIODIC_WORKLOADS[name][2]
+    n0 = n // tile ** 3
+    spec0 = _workload_spec(name, n0, seed)
+    vs = float((4.0 / 3.0 * math.pi * spec0.radius ** 3).sum())
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        o.step(10)
-        steps += 10
-        contacts += len(o.get_contacts())  # sampled every 10th step
-    t = time.perf_counter() - t0
-    per_step = t / steps
-    n_full = spec_full.n
+    g = _periodic_scene(spec0.hsize, np.zeros((3, 3)), spec0, spec0.pos, None, None, 0, friction=0.0)
+    rec = jam_isotropic(g, spec0.dt_factor * g.pwave_dt(), vs, target_pressure, log=log)
+    rec["settle"] = settle_iso(g, target_pressure, log=log)
+    g.step(1)
+    rec["pressure_settled"] = mean_pressure(g)
+    rec["coordination_settled"] = g.stats()["coordination"]
+    st = g.get_state()
+    H, _ = g.get_cell()
+    rec["solid_fraction"] = vs / abs(np.linalg.det(H))
+    g.close()
+    pos, rad, vel, ang, H2 = tile_periodic(st["pos"], spec0.radius, st["vel"], st["angvel"], H, (tile,) * 3)
+    spec = _workload_spec(name, 16, seed)  # parameters of the workload
+    spec.pos, spec.radius = pos, rad
+    rec["prepared_spheres"] = n0
+    rec["tiling"] = [tile] * 3
+    rec["cell"] = H2
+    rec["seconds"] = time.perf_counter() - t0
+    return spec, {"pos": pos, "vel": vel, "angvel": ang}, H2, rec
+
+
+def _fp32_vs_fp64_one_step(spec, st, H, L):
+    """FP32-mixed against FP64 from the identical prepared state: pair-set
+    differences, per-contact and per-body force errors."""
+    import numpy as np
+    one = {}
+    for prec in (0, 1):
+        g = _periodic_scene(H, L, spec, st["pos"], st["vel"], st["angvel"], prec)
+        g.step(1)
+        one[prec] = (g.get_contacts(), g.get_state())
+        g.close()
+    c64, c32 = one[0][0], one[1][0]
+    k64 = set(zip(c64["id1"].tolist(), c64["id2"].tolist(), map(tuple, c64["cell"].tolist())))
+    k32 = set(zip(c32["id1"].tolist(), c32["id2"].tolist(), map(tuple, c32["cell"].tolist())))
+    err = {"pair_set_differences": len(k64 ^ k32), "contacts": len(c64)}
+    if len(c64) and not (k64 ^ k32):
+        o64 = np.lexsort((c64["id2"], c64["id1"]))
+        o32 = np.lexsort((c32["id2"], c32["id1"]))
+        a, b = c64[o64], c32[o32]
+        scale = a["kn"] * 4 * np.finfo(float).eps * (2 * spec.radius.max())
+        fa, fb = a["fn"] + a["fs"], b["fn"] + b["fs"]
+        e = np.linalg.norm(fb - fa, axis=1) / (np.linalg.norm(fa, axis=1) + scale)
+        err["contact_force_rel_max"] = float(e.max())
+        err["contact_force_rel_p99"] = float(np.quantile(e, 0.99))
+        ssum = np.zeros(len(spec.radius))
+        mag = np.linalg.norm(fa, axis=1)
+        np.add.at(ssum, a["id1"], mag)
+        np.add.at(ssum, a["id2"], mag)
+        t = ssum > 0
+        eb = np.linalg.norm(one[1][1]["force"] - one[0][1]["force"], axis=1)[t] / ssum[t]
+        err["body_force_rel_max"] = float(eb.max())
+    return err
+
+
+def dense_run(spec, st, H, L, precision, steps, warmup, timing_steps=1000, probe_steps=100, log=None):
+    """One precision on the prepared packing: the autotuner's setting (found
+    on a copy of the state, which it advances), then `warmup` untimed steps
+    and exactly `steps` timed steps on a fresh scene, then `timing_steps`
+    more with kernel events (per-kernel durations, broad-phase runs)."""
+    import torch
+    n = len(spec.radius)
+    g = _periodic_scene(H, L, spec, st["pos"], st["vel"], st["angvel"], precision)
+    tune = g.autotune(probe_steps=probe_steps)
+    g.close()
+    tuning = {k: v for k, v in tune.items() if k != "ms_per_step"}
+    g = _periodic_scene(H, L, spec, st["pos"], st["vel"], st["angvel"], precision)
+    g.set_tuning(**tuning)
+    if warmup > 0:
+        g.step(warmup)
+    g.step(0)  # a pending broad-phase run happens here, outside the timed region
+    s0 = g.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    s1 = g.stats()
+    g.set_timing(True)
+    g.step(timing_steps)
+    kern = {k: g.get_timing(k) for k in ("contact", "integrate", "rebuild")}
+    s2 = g.stats()
+    g.close()
+    c_timed = (s1["contact_steps"] - s0["contact_steps"]) / steps
+    c_timing = (s2["contact_steps"] - s1["contact_steps"]) / timing_steps
+    # the broad phase: measured cost per run and runs per step over the
+    # timing pass (amortised term, beside the timed rate)
+    runs = kern["rebuild"][1]
+    rb_ms = kern["rebuild"][0]
+    r = {"value": (s1["contact_steps"] - s0["contact_steps"]) / el, "unit": "contact-steps/s",
+         "ms_per_step": el / steps * 1e3, "body_steps_per_s": n * steps / el,
+         "rebuilds_timed": s1["rebuilds"] - s0["rebuilds"], "contacts_per_step": c_timed,
+         "candidates": s2["n_candidates"], "coordination": s2["coordination"],
+         "kernels_ms": {k: v[0] for k, v in kern.items()},
+         "kernel_launches": {k: v[1] for k, v in kern.items()},
+         "broad_phase": {"ms_per_run": rb_ms, "runs": runs, "steps": timing_steps,
+                         "amortised_ms_per_step": rb_ms * runs / timing_steps},
+         "tuning": tune}
+    r["ms_per_step_with_amortised_broad_phase"] = r["ms_per_step"] + r["broad_phase"]["amortised_ms_per_step"]
+    r["value_with_amortised_broad_phase"] = c_timed / (r["ms_per_step_with_amortised_broad_phase"] * 1e-3)
+    rl = {}
+    if kern["contact"][0] > 0:
+        cb = contact_algorithmic_bytes(precision, n, c_timing, s2["n_candidates"])
+        a = cb / (kern["contact"][0] * 1e-3) / 1e9
+        rl["contact"] = {"bytes": cb, "achieved_GBs": a, "frac": a / HBM_PEAK_GBS}
+    if kern["integrate"][0] > 0:
+        ib = INTEGRATE_BYTES_PER_BODY * n
+        a = ib / (kern["integrate"][0] * 1e-3) / 1e9
+        rl["integrate"] = {"bytes": ib, "achieved_GBs": a, "frac": a / HBM_PEAK_GBS}
+    r["rooflines"] = rl
+    if log:
+        log(f"{'FP64' if precision == 0 else 'FP32-mixed'}: {r}")
+    return r
+
+
+def periodic_leg(name="periodic_compression", steps=2000, warmup=20, n=None, log=None, prepared=None,
+                 with_controller=True, with_stats=True):
+    """A dense periodic workload (C3: isotropic compression at 0.01/s; C5:
+    bidisperse simple shear at 1/s), FP64 vs FP32-mixed on the same prepared
+    packing: throughput of each, kernel durations and rooflines, and the
+    FP32-mixed error against FP64 from the identical state (pair set,
+    per-contact and per-body force) and over the run (energy terms,
+    coordination)."""
+    import numpy as np
+    log = log or (lambda m: None)
+    n = n or PERIODIC_WORKLOADS[name][1]
+    if prepared is None:
+        prepared = prepare_periodic(name, n, log=log)
+    spec, st, H, rec = prepared
+    n = len(spec.radius)
+    L = spec.velgrad
+    tile = PERIODIC_WORKLOADS[name][2]
+    out = {"workload": PERIODIC_WORKLOADS[name][3].format(n=n)
+           + f"; from a packing prepared at {n // tile ** 3} spheres and tiled {tile}x{tile}x{tile}",
+           "preparation": _jsonable(rec), "steps": steps}
+    out["fp32_vs_fp64_one_step"] = _fp32_vs_fp64_one_step(spec, st, H, L)
+    for prec, key in ((0, "fp64"), (1, "fp32_mixed")):
+        out[key] = dense_run(spec, st, H, L, prec, steps, warmup, log=log)
+    if with_controller:
+        out["controlled_cell"] = controlled_cell_run(H, spec, st, min(steps, 1000), log)
+    if with_stats:
+        stats = {}
+        for prec, key in ((0, "fp64"), (1, "fp32_mixed")):
+            g = _periodic_scene(H, L, spec, st["pos"], st["vel"], st["angvel"], prec, track_energy=True)
+            rows = []
+            win = min(500, steps)
+            for _ in range(max(1, steps // win)):
+                g.step(win)
+                e = g.get_energy()
+                rows.append([e["kinetic"], e["kin_rot"], e["elastic"], e["damp_dissip"], e["plastic_dissip"],
+                             g.stats()["coordination"]])
+            g.close()
+            stats[key] = np.array(rows)
+        a, b = stats["fp64"], stats["fp32_mixed"]
+        scale = np.abs(a[:, :5]).sum(axis=1, keepdims=True)
+        out["fp32_vs_fp64_run"] = {
+            "energy_terms_rel_to_total_max": float((np.abs(b[:, :5] - a[:, :5]) / scale).max()),
+            "coordination_rel_max": float((np.abs(b[:, 5] - a[:, 5]) / np.maximum(a[:, 5], 1e-30)).max()),
+            "windows": int(a.shape[0]), "window_steps": min(500, steps)}
+    return out
+
+
+def _jsonable(d):
+    out = {}
+    for k, v in d.items():
+        if isinstance(v, dict):
+            out[k] = _jsonable(v)
+        elif hasattr(v, "tolist"):
+            out[k] = v.tolist()
+        elif k != "cell0":
+            out[k] = v
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(budget_s=5.0, repeats=3, n=4096):
+    """The FP64 oracle, one thread, on a bounded sample of the headline
+    workload: a periodic cell of the same bidisperse mix (radii 0.5 and 2.0
+    mm, equal volumes, same material, damping and shear rate) with n
+    spheres, the generator's lattice squeezed by 0.2 % so that neighbours
+    overlap (a dense state built without the GPU), stepped for about
+    `budget_s` seconds, `repeats` times from the same state; the median
+    rate is reported.  Its pair detection is brute force over all pairs and
+    27 images, O(N^2)."""
+    import numpy as np
+    from oracle import OracleScene
+    from paper_2301_00611_amd.scenes import periodic_bidisperse_gas
+    sc = periodic_bidisperse_gas(n=n, seed=0)
+    squeeze = 0.998
+    m = sc.material
+    rates, body_rates, per_step = [], [], []
+    for _ in range(repeats):
+        o = OracleScene(dt=1.0, periodic=True, hsize=sc.hsize * squeeze, velgrad=sc.velgrad,
+                        damping=sc.damping, gravity=sc.gravity)
+        o.add_material(m.density, m.young, m.poisson, m.friction)
+        o.add_spheres(sc.pos * squeeze, sc.radius)
+        dt = sc.dt_factor * o.pwave_dt()
+        o = OracleScene(dt=dt, periodic=True, hsize=sc.hsize * squeeze, velgrad=sc.velgrad,
+                        damping=sc.damping, gravity=sc.gravity)
+        mo = o.add_material(m.density, m.young, m.poisson, m.friction)
+        o.add_spheres(sc.pos * squeeze, sc.radius, default_mat=mo)
+        steps, contacts = 0, 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget_s or steps == 0:
+            o.step(1)
+            steps += 1
+            contacts += len(o.get_contacts())
+        t = time.perf_counter() - t0
+        rates.append(contacts / t)
+        body_rates.append(n * steps / t)
+        per_step.append(t / steps)
     return {
-        "value": contacts * 10 / t,
+        "value": statistics.median(rates),
         "unit": "contact-steps/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"bottom layer of the same column ({n_sample} spheres + {len(spec_full.walls)} walls), "
-                   f"{steps} steps from the initial state in {t:.1f} s, real contacts counted every 10th step; "
-                   f"O(N^2) pairs: {per_step * 1e3:.2f} ms/step, {n_sample * steps / t:.3g} body-steps/s; "
-                   f"extrapolated {per_step * (n_full / n_sample) ** 2:.1f} s/step at {n_full} spheres"),
-        "body_steps_per_s": n_sample * steps / t,
+        "cpu_model": cpu_model(),
+        "sample": (f"periodic cell of the headline's bidisperse mix, {n} spheres (lattice squeezed 0.2 %), "
+                   f"stepped ~{budget_s:.0f} s from the same state {repeats} times, median; O(N^2) pairs over "
+                   f"27 images: {statistics.median(per_step) * 1e3:.0f} ms/step, "
+                   f"{len(o.get_contacts())} contacts at the end"),
+        "body_steps_per_s": statistics.median(body_rates),
+        "repeats": rates,
     }
+
+
+def headline(args, log):
+    """The N=1 line: C5 at FP64 (value), FP32-mixed beside it, the roofline
+    of the dominant kernel, the CPU oracle baseline."""
+    name = "periodic_shear"
+    n = PERIODIC_WORKLOADS[name][1]
+    log(f"preparing the {n}-sphere bidisperse packing (not timed)")
+    prepared = prepare_periodic(name, n, log=log)
+    spec, st, H, rec = prepared
+    L = spec.velgrad
+    log(f"prepared in {rec['seconds']:.1f} s: {_jsonable(rec)}")
+    r64 = dense_run(spec, st, H, L, 0, args.steps, args.warmup, log=log)
+    kern = r64["kernels_ms"]
+    dom = max(("contact", "integrate"), key=lambda k: kern[k])
+    rl = r64["rooflines"][dom]
+    tile = PERIODIC_WORKLOADS[name][2]
+    out = {
+        "metric": "contact-steps/s",
+        "value": r64["value"],
+        "unit": "contact-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": PERIODIC_WORKLOADS[name][3].format(n=len(spec.radius))
+                   + f"; dense packing prepared at 1 kPa ({n // tile ** 3} spheres, tiled {tile}x{tile}x{tile})",
+                   "n_spheres": len(spec.radius), "parallelism": "1 GPU"},
+        "roofline": {"bound": "hbm", "kernel": "k_" + dom, "achieved": rl["achieved_GBs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": rl["frac"],
+                     "traffic": profiled_traffic("k_" + dom, "traffic_periodic_shear_8m"),
+                     "algorithmic_bytes_per_launch": rl["bytes"]},
+        "body_steps_per_s": r64["body_steps_per_s"],
+        "contacts_per_step": r64["contacts_per_step"],
+        "coordination": r64["coordination"],
+        "candidates": r64["candidates"],
+        "kernels_ms": kern,
+        "rooflines": r64["rooflines"],
+        "broad_phase": r64["broad_phase"],
+        "ms_per_step_with_amortised_broad_phase": r64["ms_per_step_with_amortised_broad_phase"],
+        "value_with_amortised_broad_phase": r64["value_with_amortised_broad_phase"],
+        "tuning": r64["tuning"],
+        "preparation": _jsonable(rec),
+    }
+    log("FP32-mixed on the same packing")
+    r32 = dense_run(spec, st, H, L, 1, args.steps, args.warmup, log=log)
+    out["fp32_mixed"] = r32
+    out["fp32_vs_fp64_one_step"] = _fp32_vs_fp64_one_step(spec, st, H, L)
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10_000)
-    ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--no-extra", action="store_true", help="skip the FP32-mixed, batched and CPU legs")
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-extra", action="store_true", help="skip the other workloads' legs")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="column",
-                    choices=("column", "periodic_compression", "periodic_shear", "batched", "facet_column",
-                             "viscel_column"),
-                    help="column: the headline line (default); the others run one extra leg alone")
-    ap.add_argument("--prepared-state", default=None,
-                    help="periodic_compression: .npz holding the prepared packing (written if missing)")
+    ap.add_argument("--workload", default="headline",
+                    choices=("headline", "column", "periodic_compression", "periodic_shear", "batched",
+                             "facet_column", "viscel_column"),
+                    help="headline: the N=1 line (default); the others run one leg alone")
     ap.add_argument("--tuning-cache", default=None,
-                    help="autotuner cache file: reuse a stored setting for this workload, or store the one found")
+                    help="autotuner cache file for the column legs: reuse a stored setting, or store the one found")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB device copy three times (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -200,11 +508,15 @@ def main():
         print(json.dumps({"copy_bytes_each_way": n * 8, "launches": 3}), flush=True)
         return
     if args.workload in PERIODIC_WORKLOADS:
-        out = periodic_leg(args.workload, steps=args.steps, log=log, prepared_state=args.prepared_state)
+        out = periodic_leg(args.workload, steps=args.steps, warmup=args.warmup, log=log,
+                           with_controller=not args.no_extra, with_stats=not args.no_extra)
         print(json.dumps(out), flush=True)
         return
     if args.workload == "batched":
         print(json.dumps(batched_leg(steps=args.steps, log=log)), flush=True)
+        return
+    if args.workload == "column":
+        print(json.dumps(column_leg(args.steps, args.warmup, log=log, cache=args.tuning_cache)), flush=True)
         return
     if args.workload == "facet_column":
         print(json.dumps(facet_column_leg(args.steps, args.warmup, log=log, cache=args.tuning_cache)), flush=True)
@@ -213,75 +525,46 @@ def main():
         print(json.dumps(viscel_column_leg(args.steps, args.warmup, log=log, cache=args.tuning_cache)), flush=True)
         return
 
+    out = headline(args, log)
+    if not args.no_extra:
+        log("periodic compression leg (2 M spheres at 1 kPa, FP64 vs FP32-mixed)")
+        out["periodic_compression"] = periodic_leg("periodic_compression", steps=1000, warmup=20, log=log,
+                                                   with_stats=False)
+        log("column leg (200,000 spheres, deposition)")
+        out["column"] = column_leg(2000, 20, log=log)
+        log("batched leg")
+        out["batched"] = batched_leg(steps=1000, log=log)
+        log("facet-box column leg")
+        out["facet_column"] = facet_column_leg(2000, 20, log=log)
+        log("visco-elastic column leg")
+        out["viscel_column"] = viscel_column_leg(2000, 20, log=log)
+    if not args.no_cpu:
+        log("CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+def column_leg(steps, warmup, log=None, cache=None):
+    """The 200,000-sphere deposition column (C2) in FP64 and FP32-mixed:
+    `steps` steps from the initial state (few contacts: the bottom layer on
+    the floor), the integrate kernel's roofline."""
     from paper_2301_00611_amd.scenes import grid_column
     spec = grid_column(n=200_000, seed=0)
-    log("autotuning the step kernels' launch shape, graph length and Verlet distance")
-    tune = autotune_for(spec, 0, warmup=args.warmup, cache=args.tuning_cache)
-    log(f"FP64 leg: {spec.n} spheres, {args.steps} steps, setting {tune}")
-    r64 = timed_run(spec, args.steps, args.warmup, precision=0, tuning=tune)
-    log(f"FP64 leg done in {r64['seconds']:.2f} s; kernel-timing pass")
-    # same workload again with HIP events around every contact / integrate
-    # launch: per-kernel durations for the roofline
-    rt = timed_run(spec, args.steps, 0, precision=0, timing=True, tuning=tune)
-    secs = r64["seconds"]
-    value = r64["contact_steps"] / secs
-    kern = rt["kernels"]
-    # dominant kernel by total device time
-    tot = {k: v["avg_ms"] * v["launches"] for k, v in kern.items() if k != "rebuild"}
-    dom = max(tot, key=tot.get)
-    n = spec.n
-    if dom == "integrate":
-        alg_bytes = INTEGRATE_BYTES_PER_BODY * n
-    else:
-        c_real = r64["contact_steps"] / max(args.steps, 1)
-        cand = r64["candidates"]
-        alg_bytes = (CONTACT_BYTES_PER_BODY * n + CONTACT_BYTES_PER_REAL * c_real
-                     + CONTACT_BYTES_PER_CANDIDATE * max(cand - c_real, 0))
-    avg_s = kern[dom]["avg_ms"] * 1e-3
-    achieved = alg_bytes / avg_s / 1e9 if avg_s > 0 else 0.0
-    out = {
-        "metric": "contact-steps/s",
-        "value": value,
-        "unit": "contact-steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": secs / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "grid_column deposition: 200,000 spheres r~U(0.5,1.5) mm, 0.1x0.1 m box with floor, "
-                               "E=5e7, nu=0.3, phi=0.5, damping 0.2, dt=0.5*P-wave",
-                   "n_spheres": n, "n_walls": len(spec.walls), "parallelism": "1 GPU"},
-        "body_steps_per_s": n * args.steps / secs,
-        "rebuilds": r64["rebuilds"],
-        "tuning": tune,
-        "kernels_ms": {k: v["avg_ms"] for k, v in kern.items()},
-        "timing_pass_ms_per_step": rt["seconds"] / args.steps * 1e3,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic("k_" + dom),
-                     "algorithmic_bytes_per_launch": alg_bytes},
-    }
-    if not args.no_extra:
-        log("FP32-mixed leg")
-        r32 = timed_run(spec, args.steps, args.warmup, precision=1, tuning=autotune_for(spec, 1, warmup=args.warmup,
-                                                                                    cache=args.tuning_cache))
-        log("batched leg")
-        out["fp32_mixed"] = {"value": r32["contact_steps"] / r32["seconds"], "unit": "contact-steps/s",
-                             "ms_per_step": r32["seconds"] / args.steps * 1e3}
-        out["batched"] = batched_leg(log=log)
-        log("facet-box column leg")
-        out["facet_column"] = facet_column_leg(args.steps, args.warmup, log=log, cache=args.tuning_cache)
-        log("visco-elastic column leg")
-        out["viscel_column"] = viscel_column_leg(args.steps, args.warmup, log=log, cache=args.tuning_cache)
-        log("periodic compression leg (FP64 vs FP32-mixed)")
-        out["periodic_compression"] = periodic_leg("periodic_compression", log=log)
-    if not args.no_cpu and not args.no_extra:
-        log("CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(spec)
-    print(json.dumps(out), flush=True)
+    out = {"workload": "grid_column deposition: 200,000 spheres r~U(0.5,1.5) mm, 0.1x0.1 m box with floor, "
+                       "E=5e7, nu=0.3, phi=0.5, damping 0.2, dt=0.5*P-wave", "steps": steps}
+    for prec, key in ((0, "fp64"), (1, "fp32_mixed")):
+        tune = autotune_for(spec, prec, warmup=warmup, cache=cache)
+        r = timed_run(spec, steps, warmup, precision=prec, tuning=tune)
+        rt = timed_run(spec, steps, 0, precision=prec, timing=True, tuning=tune)
+        kern = {k: v["avg_ms"] for k, v in rt["kernels"].items()}
+        ib = INTEGRATE_BYTES_PER_BODY * spec.n
+        out[key] = {"value": r["contact_steps"] / r["seconds"], "unit": "contact-steps/s",
+                    "ms_per_step": r["seconds"] / steps * 1e3, "body_steps_per_s": spec.n * steps / r["seconds"],
+                    "rebuilds": r["rebuilds"], "tuning": tune, "kernels_ms": kern,
+                    "integrate_roofline": {"bytes": ib, "frac": ib / (kern["integrate"] * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+        if log:
+            log(f"column {key}: {out[key]}")
+    return out
 
 
 def viscel_column_leg(steps, warmup, log=None, cache=None):
@@ -338,181 +621,6 @@ def facet_column_leg(steps, warmup, log=None, cache=None):
         "kernels_ms": {k: v["avg_ms"] for k, v in rt["kernels"].items()},
         "contacts_last": r["contacts_last"],
     }
-
-
-def _periodic_scene(H, L, spec, pos, vel, angvel, precision, friction=None, track_energy=False):
-    from paper_2301_00611_amd import dem
-    m = spec.material
-    g = dem.Scene(periodic=True, hsize=H, velgrad=L, damping=spec.damping, gravity=spec.gravity,
-                  precision=precision, track_energy=track_energy)
-    mg = g.add_material(m.density, m.young, m.poisson, m.friction if friction is None else friction)
-    g.add_spheres(pos, spec.radius, vel=vel, angvel=angvel, default_mat=mg)
-    g.set_dt(spec.dt_factor * g.pwave_dt())
-    return g
-
-
-PERIODIC_WORKLOADS = {
-    # name: (generator, spheres, tiling of the prepared packing, description)
-    "periodic_compression": ("periodic_lognormal_gas", 2_000_000, 2,
-                             "periodic isotropic compression: {n} spheres, lognormal r (median 1 mm, sigma 0.3), "
-                             "E=1e8, nu=0.25, phi=0.3, damping 0.3, velGrad=-0.01 I, homoDeform 2, dt=0.5*P-wave"),
-    "periodic_shear": ("periodic_bidisperse_gas", 8_000_000, 2,
-                       "periodic simple shear: {n} spheres, r = 0.5 and 2.0 mm (equal volumes), E=1e8, nu=0.3, "
-                       "phi=0.5, damping 0.1, velGrad[0][2] = 1/s, homoDeform 2, dt=0.5*P-wave"),
-}
-
-
-def _workload_spec(name, n, seed=0):
-    from paper_2301_00611_amd import scenes
-    return getattr(scenes, PERIODIC_WORKLOADS[name][0])(n=n, seed=seed)
-
-
-def prepare_periodic(name, n, seed=0, target_pressure=1e3, log=None):
-    """Unmeasured preparation of a periodic workload: its lattice cloud of
-    n / tile^3 spheres compressed frictionless (friction 0, same stiffness
-    and damping) to a jammed packing whose relaxed mean pressure reaches the
-    target, held 2000 more steps at rest, then replicated tile^3 times into
-    a cell tile times wider (the same periodic packing, n spheres).  Returns
-    the spec of the n-sphere workload and its prepared state (positions,
-    velocities, spins, cell)."""
-    import numpy as np
-    from paper_2301_00611_amd.prepare import jam_isotropic, mean_pressure, tile_periodic
-    tile = PERIODIC_WORKLOADS[name][2]
-    n0 = n // tile ** 3
-    spec0 = _workload_spec(name, n0, seed)
-    vs = float((4.0 / 3.0 * math.pi * spec0.radius ** 3).sum())
-    g = _periodic_scene(spec0.hsize, np.zeros((3, 3)), spec0, spec0.pos, None, None, 0, friction=0.0)
-    rec = jam_isotropic(g, spec0.dt_factor * g.pwave_dt(), vs, target_pressure, log=log)
-    g.step(2000)
-    rec["pressure_held"] = mean_pressure(g)
-    rec["coordination_held"] = g.stats()["coordination"]
-    st = g.get_state()
-    H, _ = g.get_cell()
-    g.close()
-    pos, rad, vel, ang, H2 = tile_periodic(st["pos"], spec0.radius, st["vel"], st["angvel"], H, (tile,) * 3)
-    spec = _workload_spec(name, 16, seed)  # parameters of the workload
-    spec.pos, spec.radius = pos, rad
-    rec["prepared_spheres"] = n0
-    rec["tiling"] = [tile] * 3
-    rec["cell"] = H2
-    return spec, {"pos": pos, "vel": vel, "angvel": ang}, H2, rec
-
-
-def periodic_leg(name="periodic_compression", steps=5000, n=None, log=None, prepared_state=None):
-    """A dense periodic workload (C3: isotropic compression at 0.01/s; C5:
-    bidisperse simple shear at 1/s), FP64 vs FP32-mixed on the same prepared
-    packing: throughput of each, kernel durations, and the FP32-mixed error
-    against FP64 from the identical state (pair set, per-contact and
-    per-body force) and over the run (energy terms, coordination)."""
-    import numpy as np
-    import torch
-    log = log or (lambda m: None)
-    n = n or PERIODIC_WORKLOADS[name][1]
-    if prepared_state and os.path.exists(prepared_state):
-        d = np.load(prepared_state)
-        spec = _workload_spec(name, 16)
-        spec.pos, spec.radius = d["pos"], d["radius"]
-        st = {"pos": d["pos"], "vel": d["vel"], "angvel": d["angvel"]}
-        H, rec = d["H"], {"loaded_from": prepared_state}
-    else:
-        spec, st, H, rec = prepare_periodic(name, n, log=log)
-        if prepared_state:
-            np.savez(prepared_state, pos=st["pos"], vel=st["vel"], angvel=st["angvel"], radius=spec.radius, H=H)
-    n = len(spec.radius)
-    L = spec.velgrad
-    tile = PERIODIC_WORKLOADS[name][2]
-    out = {"workload": PERIODIC_WORKLOADS[name][3].format(n=n)
-           + f"; from a packing prepared at {n // tile ** 3} spheres and tiled {tile}x{tile}x{tile}",
-           "preparation": {k: (v.tolist() if hasattr(v, "tolist") else v) for k, v in rec.items() if k != "cell0"},
-           "steps": steps}
-    # identical-state one-step comparison
-    one = {}
-    for prec in (0, 1):
-        g = _periodic_scene(H, L, spec, st["pos"], st["vel"], st["angvel"], prec)
-        g.step(1)
-        one[prec] = (g.get_contacts(), g.get_state())
-        g.close()
-    c64, c32 = one[0][0], one[1][0]
-    k64 = set(zip(c64["id1"].tolist(), c64["id2"].tolist(), map(tuple, c64["cell"].tolist())))
-    k32 = set(zip(c32["id1"].tolist(), c32["id2"].tolist(), map(tuple, c32["cell"].tolist())))
-    err = {"pair_set_differences": len(k64 ^ k32), "contacts": len(c64)}
-    if len(c64) and not (k64 ^ k32):
-        o64 = np.lexsort((c64["id2"], c64["id1"]))
-        o32 = np.lexsort((c32["id2"], c32["id1"]))
-        a, b = c64[o64], c32[o32]
-        scale = a["kn"] * 4 * np.finfo(float).eps * (2 * spec.radius.max())
-        fa, fb = a["fn"] + a["fs"], b["fn"] + b["fs"]
-        e = np.linalg.norm(fb - fa, axis=1) / (np.linalg.norm(fa, axis=1) + scale)
-        err["contact_force_rel_max"] = float(e.max())
-        err["contact_force_rel_p99"] = float(np.quantile(e, 0.99))
-        ssum = np.zeros(len(spec.radius))
-        mag = np.linalg.norm(fa, axis=1)
-        np.add.at(ssum, a["id1"], mag)
-        np.add.at(ssum, a["id2"], mag)
-        t = ssum > 0
-        eb = np.linalg.norm(one[1][1]["force"] - one[0][1]["force"], axis=1)[t] / ssum[t]
-        err["body_force_rel_max"] = float(eb.max())
-    out["fp32_vs_fp64_one_step"] = err
-    # timed runs (the launch setting chosen by the autotuner on a copy of the
-    # same state, which it advances), then the same runs with energy
-    # tracking for the statistics
-    for prec, name in ((0, "fp64"), (1, "fp32_mixed")):
-        g = _periodic_scene(H, L, spec, st["pos"], st["vel"], st["angvel"], prec)
-        tune = g.autotune(probe_steps=200)
-        g.close()
-        g = _periodic_scene(H, L, spec, st["pos"], st["vel"], st["angvel"], prec)
-        g.set_tuning(**{k: v for k, v in tune.items() if k != "ms_per_step"})
-        g.step(0)
-        s0 = g.stats()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        g.step(steps)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        s1 = g.stats()
-        g.set_timing(True)
-        g.step(500)
-        kern = {k: g.get_timing(k)[0] for k in ("contact", "integrate", "rebuild")}
-        st_t = g.stats()
-        g.close()
-        c_real = (s1["contact_steps"] - s0["contact_steps"]) / steps
-        r = {"value": (s1["contact_steps"] - s0["contact_steps"]) / el, "unit": "contact-steps/s",
-             "ms_per_step": el / steps * 1e3, "body_steps_per_s": n * steps / el, "rebuilds": s1["rebuilds"] - s0["rebuilds"],
-             "contacts_mean": c_real, "candidates": s1["n_candidates"], "coordination_end": s1["coordination"],
-             "kernels_ms": kern, "tuning": tune}
-        # interaction-kernel rooflines (algorithmic bytes per launch)
-        bpb, bpc = (80, 104) if prec == 0 else (52, 80)
-        cand = st_t["n_candidates"]
-        cb = bpb * n + bpc * c_real + 8 * max(cand - c_real, 0)
-        ib = (INTEGRATE_BYTES_PER_BODY + (0 if prec == 0 else 28)) * n
-        if kern["contact"] > 0:
-            r["contact_roofline"] = {"bytes": cb, "achieved_GBs": cb / (kern["contact"] * 1e-3) / 1e9,
-                                     "frac": cb / (kern["contact"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
-        if kern["integrate"] > 0:
-            r["integrate_roofline"] = {"bytes": ib, "achieved_GBs": ib / (kern["integrate"] * 1e-3) / 1e9,
-                                       "frac": ib / (kern["integrate"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
-        out[name] = r
-        log(f"{out['workload'][:30]} {name}: {r}")
-    out["controlled_cell"] = controlled_cell_run(H, spec, st, steps, log)
-    stats = {}
-    for prec, name in ((0, "fp64"), (1, "fp32_mixed")):
-        g = _periodic_scene(H, L, spec, st["pos"], st["vel"], st["angvel"], prec, track_energy=True)
-        rows = []
-        win = min(500, steps)
-        for _ in range(max(1, steps // win)):
-            g.step(win)
-            e = g.get_energy()
-            rows.append([e["kinetic"], e["kin_rot"], e["elastic"], e["damp_dissip"], e["plastic_dissip"],
-                         g.stats()["coordination"]])
-        g.close()
-        stats[name] = np.array(rows)
-    a, b = stats["fp64"], stats["fp32_mixed"]
-    scale = np.abs(a[:, :5]).sum(axis=1, keepdims=True)
-    out["fp32_vs_fp64_run"] = {
-        "energy_terms_rel_to_total_max": float((np.abs(b[:, :5] - a[:, :5]) / scale).max()),
-        "coordination_rel_max": float((np.abs(b[:, 5] - a[:, 5]) / np.maximum(a[:, 5], 1e-30)).max()),
-        "windows": int(a.shape[0]), "window_steps": min(500, steps)}
-    return out
 
 
 def controlled_cell_run(H, spec, st, steps, log=None):

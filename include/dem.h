@@ -220,7 +220,10 @@ dem_status dem_set_dt(dem_scene* s, double dt);
 dem_status dem_set_velgrad(dem_scene* s, const double* velgrad9);
 dem_status dem_get_cell(dem_scene* s, double* hsize9, double* trsf9);
 
-/* Advance nsteps steps (O.run(n, wait=True)); returns when they are done. */
+/* Advance nsteps steps (O.run(n, wait=True)); returns when they are done.
+ * nsteps = 0 advances nothing but runs a pending broad phase (after bodies
+ * were added or moved, or when the last step asked for one), so that the
+ * next step starts from an up-to-date candidate list. */
 dem_status dem_step(dem_scene* s, int64_t nsteps);
 /* O.run(n) without waiting (section 2.2.1 running simulations): the steps
  * run on a library thread; until dem_wait returns, every other call on this

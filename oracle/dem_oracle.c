@@ -1357,7 +1357,7 @@ int orc_detect_pairs(const orc_scene* s, long capacity, long* id1, long* id2, in
  * full step, restricted to the contacts of the sampled bodies. */
 int orc_spot_step(const orc_scene* s, long k, const long* ids, double* force3,
                   double* torque3, double* pos3, double* vel3, double* angvel3,
-                  double* ori4, long* n_contacts)
+                  double* ori4, long* n_contacts, double* fmag_sum)
 {
     if (!s || k < 0 || (k > 0 && !ids)) return fail(ORC_EINVAL, "orc_spot_step: bad arguments");
     int rc0 = check_material_kinds(s);
@@ -1369,6 +1369,7 @@ int orc_spot_step(const orc_scene* s, long k, const long* ids, double* force3,
         if (i < 0 || i >= s->nb || s->b[i].is_wall) return fail(ORC_ERANGE, "orc_spot_step: not a sphere id");
         const body_t* bi = &s->b[i];
         double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
+        double fsum = 0.0;
         long cnt = 0;
         double e_dummy = 0.0, p_dummy = 0.0, v_dummy = 0.0;
         /* partners in ascending id order, as in the full step */
@@ -1413,6 +1414,7 @@ int orc_spot_step(const orc_scene* s, long k, const long* ids, double* force3,
                     T[a] += ct.t1[a];
                 }
             }
+            fsum += sqrt(dot3(ct.f2, ct.f2));
             cnt++;
         }
         body_t tmp = *bi;
@@ -1428,6 +1430,7 @@ int orc_spot_step(const orc_scene* s, long k, const long* ids, double* force3,
         if (ori4)
             for (int a = 0; a < 4; ++a) ori4[4 * q + a] = tmp.q[a];
         if (n_contacts) n_contacts[q] = cnt;
+        if (fmag_sum) fmag_sum[q] = fsum;
     }
     return ORC_OK;
 }

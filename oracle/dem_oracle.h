@@ -138,10 +138,11 @@ int orc_detect_pairs(const orc_scene* s, long capacity, long* id1, long* id2,
  * against all bodies (O(k*N)) from the current state and shear history, and
  * return what one step would give for those bodies: resultant force/torque
  * and the integrated state.  Nothing in the scene changes.  n_contacts gets
- * the number of real contacts of each sampled body. */
+ * the number of real contacts of each sampled body, fmag_sum the sum of
+ * their force magnitudes (the scale of a near-cancelling resultant). */
 int orc_spot_step(const orc_scene* s, long k, const long* ids, double* force3,
                   double* torque3, double* pos3, double* vel3, double* angvel3,
-                  double* ori4, long* n_contacts);
+                  double* ori4, long* n_contacts, double* fmag_sum);
 
 const char* orc_last_error(void);
 

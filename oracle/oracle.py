@@ -95,7 +95,7 @@ def load_library(path: str | None = None):
         "orc_get_cell": [C.c_void_p, _DP, _DP],
         "orc_get_stress": [C.c_void_p, C.c_double, _DP],
         "orc_detect_pairs": [C.c_void_p, C.c_long, _LP, _LP, _IP, _LP],
-        "orc_spot_step": [C.c_void_p, C.c_long, _LP, _DP, _DP, _DP, _DP, _DP, _DP, _LP],
+        "orc_spot_step": [C.c_void_p, C.c_long, _LP, _DP, _DP, _DP, _DP, _DP, _DP, _LP, _DP],
         "orc_set_dt": [C.c_void_p, C.c_double],
         "orc_add_box": [C.c_void_p, _DP, _DP, C.c_int, _LP],
         "orc_add_facet": [C.c_void_p, _DP, _DP, _DP, C.c_int, _LP],
@@ -330,7 +330,9 @@ class OracleScene:
         out = {key: np.zeros((k, 3)) for key in ("force", "torque", "pos", "vel", "angvel")}
         out["ori"] = np.zeros((k, 4))
         out["n_contacts"] = np.zeros(k, dtype=np.int64)
+        out["fmag_sum"] = np.zeros(k)
         self._check(self.lib.orc_spot_step(self._h, k, _ptr(ids, _LP), _ptr(out["force"]), _ptr(out["torque"]),
                                            _ptr(out["pos"]), _ptr(out["vel"]), _ptr(out["angvel"]),
-                                           _ptr(out["ori"]), _ptr(out["n_contacts"], _LP)), "spot_step")
+                                           _ptr(out["ori"]), _ptr(out["n_contacts"], _LP),
+                                           _ptr(out["fmag_sum"])), "spot_step")
         return out

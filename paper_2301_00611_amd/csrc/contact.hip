@@ -2,9 +2,10 @@
 // thread per candidate pair runs the exact contact test, the ScGeom update
 // (class ScGeom; section 2.1.3), Ip2_FrictMat_FrictMat_FrictPhys (section
 // 2.1.2) and Law2_ScGeom_FrictPhys_CundallStrack (section 2.1.4), and writes
-// the pair's shear history and its force record (force on #2, n x F).  No
-// sum happens here: each body adds its pairs' records later, in a fixed
-// order (integrate.hip).
+// the pair's history record (shear force, normal, overlap, normal force),
+// plus a force record (force on #2, n x F) in FP32-mixed mode and under the
+// visco-elastic law.  No sum happens here: each body adds its pairs' forces
+// later, in a fixed order (integrate.hip).
 //
 // FP64 mode computes everything in double.  FP32-mixed mode keeps the
 // contact test, the branch length and the overlap in double (they are
@@ -381,16 +382,16 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
             const V3<R> F = fn_mag * n + fsr;
             const V3<R> tau = cross(n, F);
 
-            hist[k] = HistRec{fs64.x, fs64.y, fs64.z, ve ? pen : 0.0, (double)n.x, (double)n.y, (double)n.z,
-                              ve ? (double)fn_mag : 0.0};
-            // the record as three pairs (a record starts on an 8-byte (FP32)
-            // or 16-byte (FP64) boundary of a 256-byte aligned array)
+            hist[k] = HistRec{fs64.x, fs64.y, fs64.z, pen, (double)n.x, (double)n.y, (double)n.z, (double)fn_mag};
+            // the force record as three pairs (a record starts on an 8-byte
+            // (FP32) or 16-byte (FP64) boundary of a 256-byte aligned array);
+            // the FP64 linear law's integrate kernel reads the history instead
             if (PREC == DEM_FP32_MIXED) {
                 const gptr<float2> q = glb(reinterpret_cast<float2*>(a.pr.frecf)) + 3 * (size_t)k;
                 q[0] = make_float2((float)F.x, (float)F.y);
                 q[1] = make_float2((float)F.z, (float)tau.x);
                 q[2] = make_float2((float)tau.y, (float)tau.z);
-            } else {
+            } else if (VISCEL) {
                 const gptr<double2> q = glb(reinterpret_cast<double2*>(a.pr.frec)) + 3 * (size_t)k;
                 q[0] = make_double2((double)F.x, (double)F.y);
                 q[1] = make_double2((double)F.z, (double)tau.x);

@@ -197,13 +197,16 @@ __device__ inline double sphere_mass(double r, double rho)
 }
 
 // A pair's history record (64 bytes, one aligned segment): the shear force
-// on #2 after the Coulomb cap and the normal of its last evaluation; a
-// zero normal marks a pair that did not touch.
+// on #2 after the Coulomb cap, the normal, the overlap and the normal force
+// of its last evaluation; a zero normal marks a pair that did not touch.
+// Under the linear law in FP64 the record is also the pair's force record:
+// the force on #2 is fn n + Fs and its torque term n x (fn n + Fs), so no
+// separate force record is written (one 64-byte segment per gather).
 struct HistRec {
     double fsx, fsy, fsz;     // shear force (the spring's part under the visco-elastic law)
-    double pen;               // visco-elastic law: overlap of the last evaluation (report only), else 0
+    double pen;               // overlap of the last evaluation
     double nx, ny, nz;
-    double fn;                // visco-elastic law: signed normal force k_n pen - c_n u_n (report only), else 0
+    double fn;                // signed normal force on #2 along n: k_n pen (linear law), k_n pen - c_n u_n (visco-elastic)
 };
 
 // Candidate pairs after a broad-phase run, the pairs that touched at the
@@ -218,11 +221,18 @@ struct Pairs {
     uint8_t *real;            // 1 when the pair touched at the last evaluation
     HistRec *h;               // history
     // force on #2 and n x F of the last step, one record of kForceWords
-    // values per pair (one contiguous gather per real row entry)
-    double *frec;             // FP64 mode
+    // values per pair (one contiguous gather per real row entry); written
+    // only where the history record is not enough (see uses_force_records)
+    double *frec;             // FP64 mode (visco-elastic law)
     float *frecf;             // FP32-mixed mode
 };
 constexpr int kForceWords = 6;
+
+// Where the integrate kernel and the reports take a pair's force from: a
+// force record (FP32-mixed: 24 bytes, smaller than the history record;
+// the visco-elastic law: its shear dashpot is not in the history), or the
+// history record itself (FP64 linear law).
+inline bool uses_force_records(int precision, bool viscel) { return precision == DEM_FP32_MIXED || viscel; }
 
 // Rows: for every slot, its candidate pairs sorted by partner id.
 struct Rows {
@@ -341,6 +351,8 @@ struct StepArgs {
     double* acc_ctrl2;              // kCtrlReduceGrid x (kNetworkWords + 2)
     int32_t nblocks_contact;        // blocks of the contact kernel (its grid)
     int32_t nblocks_integrate;      // slots of acc_integrate written by the integrate kernel
+    int32_t use_frec;               // forces come from the force records (uses_force_records), else the history
+    int32_t pad_;
 };
 
 // Global-memory view of a buffer pointer.  The step kernels load their
@@ -448,8 +460,9 @@ void launch_contact(const StepArgs* args, int parity, int grid, int precision, b
                     bool measure = false, bool prims = false, bool viscel = false);
 
 // integrate.hip
+// frec: uses_force_records(precision, world has visco-elastic materials)
 void launch_integrate(const StepArgs* args, int parity, int grid, int precision, bool batched, bool periodic,
-                      int block, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                      bool frec, int block, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // One block after the step: the periodic cell's update, then (when the
 // controlled cell is on and the step is one of its updates) the
 // controller, from the contact and integrate kernels' partial sums.

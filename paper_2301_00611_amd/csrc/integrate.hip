@@ -30,9 +30,10 @@ __device__ inline int logical_block(int nb)
 __device__ inline double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
 
 // Resultant contact force and torque on slot i, in row order (ascending
-// partner id): the force records of its real pairs, negated where the body
-// is #1.
-template <int PREC>
+// partner id): the forces of its real pairs, negated where the body is #1.
+// FREC: from the force records (F on #2, n x F); otherwise from the history
+// records (FP64 linear law): F = fn n + Fs, n x F.
+template <int PREC, bool FREC>
 __device__ inline void body_sum(const StepArgs& a, int beg, int end, double r, double* F, double* T)
 {
     F[0] = F[1] = F[2] = 0.0;
@@ -59,7 +60,18 @@ __device__ inline void body_sum(const StepArgs& a, int beg, int end, double r, d
         for (int j = 0; j < kB; ++j) {
             const uint32_t k = u[j] & kPairMask;
             if (!use[j]) continue;
-            if (PREC == DEM_FP32_MIXED) {
+            if (!FREC) {
+                // the history record, one 64-byte segment read as two halves
+                const gptr<const double4> h = glb<const double4>(reinterpret_cast<const double4*>(a.pr.h)) + 2 * (size_t)k;
+                const double4 h0 = h[0], h1 = h[1];
+                const double fx = h1.w * h1.x + h0.x, fy = h1.w * h1.y + h0.y, fz = h1.w * h1.z + h0.z;
+                f[j][0] = fx;
+                f[j][1] = fy;
+                f[j][2] = fz;
+                f[j][3] = h1.y * fz - h1.z * fy;
+                f[j][4] = h1.z * fx - h1.x * fz;
+                f[j][5] = h1.x * fy - h1.y * fx;
+            } else if (PREC == DEM_FP32_MIXED) {
                 const gptr<const float2> q = glb<const float2>(reinterpret_cast<const float2*>(a.pr.frecf)) + 3 * (size_t)k;
                 for (int c = 0; c < 3; ++c) {
                     const float2 v = q[c];
@@ -105,7 +117,7 @@ struct IntPartial {
     double kin, rot, grav, damp, fsum, fcnt;
 };
 
-template <int PREC, bool BATCHED, bool PERIODIC>
+template <int PREC, bool BATCHED, bool PERIODIC, bool FREC>
 __global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restrict__ args, int parity)
 {
     const StepArgs& a = *args;
@@ -155,7 +167,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restr
         // by m and by I once and multiplies after that
         const double inv_m = 1.0 / m, inv_I = 1.0 / I;
         double F[3], T[3];
-        body_sum<PREC>(a, beg, end, r, F, T);
+        body_sum<PREC, FREC>(a, beg, end, r, F, T);
         if (measure && blocked != 63u) {
             part.fsum = sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]);
             part.fcnt = 1.0;
@@ -485,13 +497,13 @@ __global__ void __launch_bounds__(kCellBlock) k_cell_update(StepArgs* args, int 
 }
 
 // Resultant force/torque per slot (for reporting), same sum as the step.
-template <int PREC>
+template <int PREC, bool FREC>
 __global__ void k_body_forces(StepArgs a, double* __restrict__ f3, double* __restrict__ t3)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.nslots) return;
     double F[3], T[3];
-    body_sum<PREC>(a, a.rows.start[i], a.rows.start[i + 1], a.bod.xr[i].w, F, T);
+    body_sum<PREC, FREC>(a, a.rows.start[i], a.rows.start[i + 1], a.bod.xr[i].w, F, T);
     for (int k = 0; k < 3; ++k) {
         f3[3 * i + k] = F[k];
         t3[3 * i + k] = T[k];
@@ -508,7 +520,7 @@ __global__ void k_body_forces(StepArgs a, double* __restrict__ f3, double* __res
 // k_s r^2 (1 - n_i^2) against the inertia (+inf without contacts).
 constexpr int kMeasureBlock = 256;
 
-template <int PREC, bool BATCHED>
+template <int PREC, bool BATCHED, bool FREC>
 __global__ void __launch_bounds__(kMeasureBlock) k_body_measures(StepArgs a, int scene, double* __restrict__ part)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -520,7 +532,7 @@ __global__ void __launch_bounds__(kMeasureBlock) k_body_measures(StepArgs a, int
         const double I = 2.0 * m * r * r / 5.0;
         const int beg = a.rows.start[i], end = a.rows.start[i + 1];
         double F[3], T[3];
-        body_sum<PREC>(a, beg, end, r, F, T);
+        body_sum<PREC, FREC>(a, beg, end, r, F, T);
         const double fa = sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]);
         fsum = fa;
         fmaxv = fa;
@@ -578,30 +590,37 @@ __global__ void __launch_bounds__(kMeasureBlock) k_body_measures(StepArgs a, int
     }
 }
 
-template <int PREC, bool BATCHED, bool PERIODIC>
+template <int PREC, bool BATCHED, bool PERIODIC, bool FREC>
 void launch_t(const StepArgs* args, int parity, int grid, int block, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
     const dim3 g(grid > 0 ? grid : 1), b(block);
     if (ev0)
-        hipExtLaunchKernelGGL((k_integrate<PREC, BATCHED, PERIODIC>), g, b, 0, st, ev0, ev1, 0, args, parity);
+        hipExtLaunchKernelGGL((k_integrate<PREC, BATCHED, PERIODIC, FREC>), g, b, 0, st, ev0, ev1, 0, args, parity);
     else
-        hipLaunchKernelGGL((k_integrate<PREC, BATCHED, PERIODIC>), g, b, 0, st, args, parity);
+        hipLaunchKernelGGL((k_integrate<PREC, BATCHED, PERIODIC, FREC>), g, b, 0, st, args, parity);
+}
+
+template <int PREC, bool FREC>
+void launch_kind(const StepArgs* args, int parity, int grid, bool batched, bool periodic, int block, hipStream_t st,
+                 hipEvent_t ev0, hipEvent_t ev1)
+{
+    if (batched) launch_t<PREC, true, false, FREC>(args, parity, grid, block, st, ev0, ev1);
+    else if (periodic) launch_t<PREC, false, true, FREC>(args, parity, grid, block, st, ev0, ev1);
+    else launch_t<PREC, false, false, FREC>(args, parity, grid, block, st, ev0, ev1);
 }
 
 }  // namespace
 
 void launch_integrate(const StepArgs* args, int parity, int grid, int precision, bool batched, bool periodic,
-                      int block, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
+                      bool frec, int block, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
-    if (precision == DEM_FP32_MIXED) {
-        if (batched) launch_t<DEM_FP32_MIXED, true, false>(args, parity, grid, block, st, ev0, ev1);
-        else if (periodic) launch_t<DEM_FP32_MIXED, false, true>(args, parity, grid, block, st, ev0, ev1);
-        else launch_t<DEM_FP32_MIXED, false, false>(args, parity, grid, block, st, ev0, ev1);
-    } else {
-        if (batched) launch_t<DEM_FP64, true, false>(args, parity, grid, block, st, ev0, ev1);
-        else if (periodic) launch_t<DEM_FP64, false, true>(args, parity, grid, block, st, ev0, ev1);
-        else launch_t<DEM_FP64, false, false>(args, parity, grid, block, st, ev0, ev1);
-    }
+    // FP32-mixed always has its force records
+    if (precision == DEM_FP32_MIXED)
+        launch_kind<DEM_FP32_MIXED, true>(args, parity, grid, batched, periodic, block, st, ev0, ev1);
+    else if (frec)
+        launch_kind<DEM_FP64, true>(args, parity, grid, batched, periodic, block, st, ev0, ev1);
+    else
+        launch_kind<DEM_FP64, false>(args, parity, grid, batched, periodic, block, st, ev0, ev1);
 }
 
 void launch_ctrl_reduce(const StepArgs* args, int parity, hipStream_t st)
@@ -623,11 +642,14 @@ void launch_body_measures(const StepArgs& a, int precision, bool batched, int sc
     if (grid == 0) return;
     const dim3 g(grid), b(kMeasureBlock);
     if (precision == DEM_FP32_MIXED) {
-        if (batched) hipLaunchKernelGGL((k_body_measures<DEM_FP32_MIXED, true>), g, b, 0, st, a, scene, part);
-        else hipLaunchKernelGGL((k_body_measures<DEM_FP32_MIXED, false>), g, b, 0, st, a, scene, part);
+        if (batched) hipLaunchKernelGGL((k_body_measures<DEM_FP32_MIXED, true, true>), g, b, 0, st, a, scene, part);
+        else hipLaunchKernelGGL((k_body_measures<DEM_FP32_MIXED, false, true>), g, b, 0, st, a, scene, part);
+    } else if (a.use_frec) {
+        if (batched) hipLaunchKernelGGL((k_body_measures<DEM_FP64, true, true>), g, b, 0, st, a, scene, part);
+        else hipLaunchKernelGGL((k_body_measures<DEM_FP64, false, true>), g, b, 0, st, a, scene, part);
     } else {
-        if (batched) hipLaunchKernelGGL((k_body_measures<DEM_FP64, true>), g, b, 0, st, a, scene, part);
-        else hipLaunchKernelGGL((k_body_measures<DEM_FP64, false>), g, b, 0, st, a, scene, part);
+        if (batched) hipLaunchKernelGGL((k_body_measures<DEM_FP64, true, false>), g, b, 0, st, a, scene, part);
+        else hipLaunchKernelGGL((k_body_measures<DEM_FP64, false, false>), g, b, 0, st, a, scene, part);
     }
 }
 
@@ -636,9 +658,11 @@ void launch_body_forces(const StepArgs& a, int precision, double* f3, double* t3
     if (a.nslots <= 0) return;
     const int grid = (a.nslots + 255) / 256;
     if (precision == DEM_FP32_MIXED)
-        hipLaunchKernelGGL(k_body_forces<DEM_FP32_MIXED>, dim3(grid), dim3(256), 0, st, a, f3, t3);
+        hipLaunchKernelGGL((k_body_forces<DEM_FP32_MIXED, true>), dim3(grid), dim3(256), 0, st, a, f3, t3);
+    else if (a.use_frec)
+        hipLaunchKernelGGL((k_body_forces<DEM_FP64, true>), dim3(grid), dim3(256), 0, st, a, f3, t3);
     else
-        hipLaunchKernelGGL(k_body_forces<DEM_FP64>, dim3(grid), dim3(256), 0, st, a, f3, t3);
+        hipLaunchKernelGGL((k_body_forces<DEM_FP64, false>), dim3(grid), dim3(256), 0, st, a, f3, t3);
 }
 
 }  // namespace dem

@@ -1265,6 +1265,8 @@ struct World {
         a.acc_ctrl2 = d_acc_ctrl2.as<double>();
         a.nblocks_contact = grid_c;
         a.nblocks_integrate = grid_i;
+        a.use_frec = uses_force_records(precision, has_viscel()) ? 1 : 0;
+        a.pad_ = 0;
         return a;
     }
 
@@ -1277,8 +1279,8 @@ struct World {
         const StepArgs* a = d_args.as<StepArgs>();
         launch_contact(a, parity, grid_c, precision, batched(), periodic, block_contact, stream, ev ? ev[0] : nullptr,
                        ev ? ev[1] : nullptr, periodic && pt_active && measure, has_prims(), has_viscel());
-        launch_integrate(a, parity, grid_i, precision, batched(), periodic, block_integrate, stream,
-                         ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
+        launch_integrate(a, parity, grid_i, precision, batched(), periodic, uses_force_records(precision, has_viscel()),
+                         block_integrate, stream, ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
         if (periodic && pt_active && measure) launch_ctrl_reduce(a, parity, stream);
         if (periodic) launch_cell_update(a, parity, stream);
     }
@@ -1364,6 +1366,11 @@ struct World {
     bool run_steps(int64_t nsteps)
     {
         if (host_dirty) upload_bodies();
+        // no step: only bring the pair list up to date (a pending broad-phase run)
+        if (nsteps == 0) {
+            if ((nslots > 0 || !walls.empty()) && (need_rebuild || h_ctr->stall[next_parity ^ 1])) rebuild();
+            return false;
+        }
         if (nslots == 0 && walls.empty()) {
             for (auto& S : scenes) {
                 S.iter += nsteps;
@@ -1500,7 +1507,7 @@ struct World {
     struct PairSnapshot {
         std::vector<int32_t> a, b, cell;
         std::vector<double> fsx, fsy, fsz, nx, ny, nz, fx, fy, fz;
-        std::vector<double> pen, fn;   // the visco-elastic law's report words of the history
+        std::vector<double> pen, fn;   // overlap and normal force of the last evaluation
     };
 
     PairSnapshot pair_snapshot()
@@ -1968,12 +1975,14 @@ struct World {
             c.normal[0] = p.nx[k];
             c.normal[1] = p.ny[k];
             c.normal[2] = p.nz[k];
+            // the kernel's own overlap and normal force (history record); the
+            // shear force is the stored spring (linear law) or the total less
+            // the normal force (visco-elastic law, whose dashpot is not stored)
+            c.pen = p.pen[k];
+            for (int q = 0; q < 3; ++q) c.fn[q] = p.fn[k] * c.normal[q];
             c.fs[0] = p.fsx[k];
             c.fs[1] = p.fsy[k];
             c.fs[2] = p.fsz[k];
-            c.fn[0] = p.fx[k] - p.fsx[k];
-            c.fn[1] = p.fy[k] - p.fsy[k];
-            c.fn[2] = p.fz[k] - p.fsz[k];
             const HostMaterial& M2 = mats[B2.mat];
             const HostMaterial& M1 = wall ? mats[walls[-1 - p.a[k]].mat] : mats[B1->mat];
             const double R1 = wall ? (walls[-1 - p.a[k]].kind == kFacet ? 2.0 * B2.r : B2.r) : B1->r, R2 = B2.r;
@@ -1991,8 +2000,6 @@ struct World {
                 const double pi2 = 3.14159265358979323846 * 3.14159265358979323846;
                 c.kn = mr * (pi2 + len * len) / (tc * tc);
                 c.ks = 2.0 / 7.0 * mr * (pi2 + let * let) / (tc * tc);
-                c.pen = p.pen[k];
-                for (int q = 0; q < 3; ++q) c.fn[q] = p.fn[k] * c.normal[q];
                 c.fs[0] = p.fx[k] - c.fn[0];
                 c.fs[1] = p.fy[k] - c.fn[1];
                 c.fs[2] = p.fz[k] - c.fn[2];
@@ -2001,7 +2008,6 @@ struct World {
                 c.kn = k1 * k2 / (k1 + k2);
                 const double q1 = (M1.young * M1.poisson) * (2.0 * R1), q2 = (M2.young * M2.poisson) * (2.0 * R2);
                 c.ks = q1 * q2 / (q1 + q2);
-                c.pen = std::sqrt(c.fn[0] * c.fn[0] + c.fn[1] * c.fn[1] + c.fn[2] * c.fn[2]) / c.kn;
             }
             const double dt = scenes[s].p.dt;
             // positions of the step the contact was evaluated at: x - v dt

@@ -20,13 +20,19 @@ namespace {
 
 constexpr int kStressBlock = 256;
 
-// Force on #2 of pair k (0 unless the pair touched at the last step).
+// Force on #2 of pair k (0 unless the pair touched at the last step): from
+// its force record, or (FP64 linear law) its history record, fn n + Fs.
 template <int PREC>
 __device__ inline void pair_force(const StepArgs& a, int k, double* F)
 {
     F[0] = F[1] = F[2] = 0.0;
     if (!a.pr.real[k]) return;
-    if (PREC == DEM_FP32_MIXED) {
+    if (!a.use_frec) {
+        const HistRec h = a.pr.h[k];
+        F[0] = h.fn * h.nx + h.fsx;
+        F[1] = h.fn * h.ny + h.fsy;
+        F[2] = h.fn * h.nz + h.fsz;
+    } else if (PREC == DEM_FP32_MIXED) {
         const float* q = a.pr.frecf + (size_t)kForceWords * k;
         F[0] = q[0];
         F[1] = q[1];

@@ -8,7 +8,10 @@ library):
     stops there;
   * jam_isotropic: a host-side schedule of compressions, velocity resets
     and relaxations (dem_set_velgrad, dem_step, dem_get_stress,
-    dem_set_state), which reaches a static jammed packing.
+    dem_set_state), which reaches a static jammed packing;
+  * settle_iso: the library's isotropic compressor (dem_set_peri_iso)
+    holding a near-jammed packing at a mean stress until its unbalanced
+    force is small.
 """
 from __future__ import annotations
 
@@ -141,3 +144,36 @@ def compress_to_pressure(scene, target_pressure: float, max_strain_rate: float =
             "strain": st["strain"], "unbalanced": st["unbalanced"], "updates": st["updates"],
             "coordination": stats["coordination"], "seconds": time.perf_counter() - t0}
 
+
+
+def settle_iso(scene, target_pressure: float, max_unbalanced: float = 0.02, stress_tol: float = 0.02,
+               max_steps: int = 100_000, report_every: int = 5000, max_strain_rate: float = 1.0,
+               log=None) -> dict:
+    """The isotropic compressor (PeriIsoCompressor, keepProportions) driving
+    the mean stress of a periodic scene to -target_pressure and holding it
+    until the unbalanced force is at most max_unbalanced (the compressor's
+    own goal test); the cell then stops.  Meant for a packing that is
+    already near jamming (from jam_isotropic): from a gas the stiffness-based
+    rate only keeps up the kinetic pressure and the packing densifies
+    slowly.  Returns a record of the run."""
+    p = float(target_pressure)
+    scene.set_peri_iso([-p], global_update=5, max_strain_rate=max_strain_rate, grow_damping=0.25,
+                       max_unbalanced=max_unbalanced, abs_stress_tol=stress_tol * p, rel_stress_tol=0.0,
+                       stop_when_done=1)
+    t0 = time.perf_counter()
+    it0 = scene.stats()["iter"]
+    st = scene.get_peri_iso()
+    while scene.stats()["iter"] - it0 < max_steps:
+        scene.step(min(report_every, max_steps - (scene.stats()["iter"] - it0)))
+        st = scene.get_peri_iso()
+        if log is not None:
+            log(f"isotropic compressor: step {scene.stats()['iter'] - it0}, mean stress {st['sigma']:.4g}, "
+                f"unbalanced {st['unbalanced']:.3g}, Z {scene.stats()['coordination']:.3f}")
+        if st["done"]:
+            break
+    scene.set_peri_iso(None)
+    scene.set_velgrad(np.zeros((3, 3)))
+    stats = scene.stats()
+    return {"steps": stats["iter"] - it0, "converged": bool(st["done"]), "mean_stress": st["sigma"],
+            "unbalanced": st["unbalanced"], "updates": st["updates"], "coordination": stats["coordination"],
+            "seconds": time.perf_counter() - t0}

@@ -69,6 +69,8 @@ def contact_errors(cg, co):
     out["f"] = np.linalg.norm(total_g - total_o, axis=1) / (np.linalg.norm(total_o, axis=1) + scale)
     out["normal"] = np.linalg.norm(cg["normal"] - co["normal"], axis=1)
     out["pen"] = np.abs(cg["pen"] - co["pen"]) / (np.abs(co["pen"]) + 4 * EPS * 2.5e-3)
+    # contact point, relative to its distance from the origin plus the radius scale
+    out["point"] = np.linalg.norm(cg["point"] - co["point"], axis=1) / (np.linalg.norm(co["point"], axis=1) + 1e-3)
     return out
 
 

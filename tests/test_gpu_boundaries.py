@@ -275,10 +275,13 @@ def test_full_size_spot_check_facet_column():
     stats = g.stats()
     assert stats["n_contacts_ss"] > 50_000 and stats["n_contacts_sw"] > 1000
     assert (spot["n_contacts"] > 0).sum() > 100
-    fscale = np.abs(spot["force"]).max(axis=1) + 1e-30
-    ferr = np.linalg.norm(st["force"][ids] - spot["force"], axis=1) / np.maximum(
-        np.linalg.norm(spot["force"], axis=1), 1e-12 * fscale.max())
-    assert np.median(ferr) <= 1e-12 and ferr.max() <= 1e-9
+    # per body: the resultant's error against the sum of its contact
+    # forces' magnitudes (plus the overlap's rounding, kn 4 eps (r1 + r2) per contact)
+    touched = spot["n_contacts"] > 0
+    scale = spot["fmag_sum"] + spot["n_contacts"] * spec.material.young * 1.5e-3 * 4 * np.finfo(float).eps * 3e-3
+    ferr = np.linalg.norm(st["force"][ids] - spot["force"], axis=1)
+    assert np.all(st["force"][ids][~touched] == 0.0)
+    assert (ferr[touched] / scale[touched]).max() <= 1e-12
     assert np.abs(st["pos"][ids] - spot["pos"]).max() <= 1e-15
     assert np.abs(st["vel"][ids] - spot["vel"]).max() <= 1e-12 * np.abs(spot["vel"]).max()
 
