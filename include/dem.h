@@ -272,6 +272,19 @@ dem_status dem_get_energy(dem_scene* s, dem_energy* out);
  * (DEM_EINVAL for an aperiodic scene).  sigma9 is a host buffer of 9
  * doubles, row-major. */
 dem_status dem_get_stress(dem_scene* s, double volume, double* sigma9);
+/* dem_get_stress for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * stress, from the same contacts, with its partial sums in a fixed device
+ * array of the library (1025 x 9 doubles, 73,800 bytes, one per GPU, kept
+ * until the process ends) instead of a buffer sized to the scene; it calls
+ * no hipMalloc or hipFree and no allocating routine.  The sums are taken in
+ * another fixed order than dem_get_stress's, so the two agree to rounding
+ * (relative 1e-12), not bit for bit; each is deterministic.  Limits: at most
+ * 67,108,864 candidate pairs (DEM_EINVAL beyond); the device state must be
+ * current (DEM_EINVAL when bodies were added or the state set since the last
+ * step, which dem_get_stress would upload).  Calls that overlap on one GPU
+ * (other threads, other scenes) share the array and race. */
+dem_status dem_get_stress_noalloc(dem_scene* s, double volume, double* sigma9);
 dem_status dem_get_stats(dem_scene* s, dem_stats* out);
 
 /* utils.unbalancedForce (section 5 utility reference): the mean (use_max =

@@ -478,6 +478,14 @@ int stress_blocks(int npairs);
 // Force on #2 of every pair (3 doubles per pair; 0 for a pair not touching).
 void launch_pair_forces(const StepArgs& a, int precision, double* f3, hipStream_t st);
 void launch_network(const StepArgs& a, int precision, bool batched, int scene, double* part, hipStream_t st);
+// The Love-Weber stress sums (9 doubles, times the volume) of one scene
+// computed in the library's fixed device scratch, allocating nothing; returns
+// the device address of the nine words (valid until the next such call on
+// this GPU), or nullptr when the scratch is unavailable or the pair count is
+// 0 or above stress_noalloc_max_pairs().
+constexpr int kNoAllocMaxPerThread = 256;
+int64_t stress_noalloc_max_pairs();
+const double* launch_stress_noalloc(const StepArgs& a, int precision, bool batched, int scene, hipStream_t st);
 // Sums over the bodies of one scene, kBodyWords doubles per block
 // (integrate.hip): sum and largest |resultant contact force| over the
 // dynamic spheres, their number, and the smallest stiffness-based critical

@@ -1943,6 +1943,37 @@ struct World {
         for (int q = 0; q < 9; ++q) out9[q] = sum[q] / V;
     }
 
+    // The same sums in the library's fixed device scratch: no device or host
+    // allocation (the device state must already be current, so bodies added
+    // or a state set since the last step are refused rather than uploaded).
+    void stress_noalloc(int s, double volume, double* out9)
+    {
+        if (host_dirty)
+            fail(DEM_EINVAL, "dem_get_stress_noalloc: bodies or state changed since the last step; step first");
+        double V = volume;
+        if (!(V > 0.0)) {
+            if (!scenes[s].p.periodic) fail(DEM_EINVAL, "dem_get_stress_noalloc: give the volume of an aperiodic scene");
+            pull_scene_table();
+            const double* H = sp[s].H;
+            V = std::fabs(H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
+                          H[2] * (H[3] * H[7] - H[4] * H[6]));
+        }
+        if (!std::isfinite(V) || !(V > 0.0)) fail(DEM_EINVAL, "dem_get_stress_noalloc: volume must be > 0");
+        double sum[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if (contacts_valid && npairs > 0) {
+            if ((int64_t)npairs > stress_noalloc_max_pairs())
+                fail(DEM_EINVAL, "dem_get_stress_noalloc: " + std::to_string(npairs) +
+                                     " candidate pairs exceed the fixed scratch's limit of " +
+                                     std::to_string(stress_noalloc_max_pairs()));
+            const double* d = launch_stress_noalloc(step_args(), precision, scenes.size() > 1, s, stream);
+            if (!d) fail(DEM_EDEVICE, "dem_get_stress_noalloc: the device scratch's address is not available");
+            HIPC(hipGetLastError());
+            HIPC(hipMemcpyAsync(sum, d, sizeof sum, hipMemcpyDeviceToHost, stream));
+            HIPC(hipStreamSynchronize(stream));
+        }
+        for (int q = 0; q < 9; ++q) out9[q] = sum[q] / V;
+    }
+
     std::vector<dem_contact> contacts(int s)
     {
         std::vector<dem_contact> out;
@@ -2555,6 +2586,15 @@ dem_status dem_get_stress(dem_scene* s, double volume, double* sigma9)
         dem::World* w = world_of(s);
         if (!sigma9) dem::fail(DEM_EINVAL, "null out");
         w->stress(s->s, volume, sigma9);
+    });
+}
+
+dem_status dem_get_stress_noalloc(dem_scene* s, double volume, double* sigma9)
+{
+    return guarded([&] {
+        if (!sigma9) dem::fail(DEM_EINVAL, "null output");
+        dem::World* w = world_of(s);
+        w->stress_noalloc(s->s, volume, sigma9);
     });
 }
 

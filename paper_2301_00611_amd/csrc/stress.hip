@@ -14,7 +14,15 @@
 // a fixed order (waves, then blocks on the host): deterministic.
 #include "dem_internal.hpp"
 
+#include <algorithm>
+#include <mutex>
+
 namespace dem {
+
+// The fixed device scratch of dem_get_stress_noalloc (see below): 1025 x 9
+// doubles (73,800 bytes) on every GPU the library runs on, held until the
+// process ends.
+static __device__ __align__(256) double scratch[(1024 + 1) * 9];
 
 namespace {
 
@@ -122,7 +130,109 @@ __global__ void __launch_bounds__(kStressBlock) k_network(StepArgs a, int scene,
     block_store_terms(s, part);
 }
 
+constexpr int kNoAllocBlocks = 1024;
+constexpr int kNoAllocWords = 9;
+
+// ---- the Love-Weber stress without any allocation (dem_get_stress_noalloc)
+//
+// Its partial sums live in `scratch`, a fixed device array of this file: at
+// most kNoAllocBlocks blocks, each striding over the pairs (thread t of block
+// b takes pairs b B + t + j G B, j = 0, 1, ..., in that order), store their
+// nine sums, and one more block adds the blocks' sums in block order into
+// the array's last nine words.  Every word read is written first by the same
+// call, so nothing needs clearing; two calls that overlap on one GPU share
+// the array and race.
+
+template <int PREC, bool BATCHED>
+__global__ void __launch_bounds__(kStressBlock) k_stress_strided(StepArgs a, int scene, int per_thread,
+                                                                  double* __restrict__ part)
+{
+    double acc[kNetworkWords];
+    for (int q = 0; q < kNetworkWords; ++q) acc[q] = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int j = 0; j < per_thread; ++j, k += stride) {
+        if (k >= a.npairs) break;
+        double t[kNetworkWords];
+        network_terms<PREC, BATCHED>(a, (int)k, scene, t);
+        for (int q = 0; q < kNoAllocWords; ++q) acc[q] += t[q];
+    }
+    // the block's sums of the nine stress words, waves in order
+    __shared__ double sh[kStressBlock / 64][kNoAllocWords];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int q = 0; q < kNoAllocWords; ++q)
+        for (int off = 32; off > 0; off >>= 1) acc[q] += __shfl_down(acc[q], off, 64);
+    if (lane == 0)
+        for (int q = 0; q < kNoAllocWords; ++q) sh[wave][q] = acc[q];
+    __syncthreads();
+    if (threadIdx.x < kNoAllocWords) {
+        double v = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v += sh[w][threadIdx.x];
+        part[kNoAllocWords * (size_t)blockIdx.x + threadIdx.x] = v;
+    }
+}
+
+// One block: word q of the total is the blocks' word q added in block order.
+__global__ void __launch_bounds__(64) k_stress_final(const double* __restrict__ part, int nblocks,
+                                                     double* __restrict__ out)
+{
+    if (threadIdx.x >= kNoAllocWords) return;
+    double v = 0.0;
+    for (int b = 0; b < nblocks; ++b) v += part[kNoAllocWords * (size_t)b + threadIdx.x];
+    out[threadIdx.x] = v;
+}
+
 }  // namespace
+
+// Device address of `scratch` on the current device, looked up once per
+// device (each GPU holds its own copy of the array at its own address; the
+// array's name in host code is only a stand-in for it).
+static double* noalloc_scratch()
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double* ptr[kMaxDevices] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        ptr[dev] = static_cast<double*>(p);
+    }
+    return ptr[dev];
+}
+
+int64_t stress_noalloc_max_pairs() { return (int64_t)kNoAllocBlocks * kStressBlock * kNoAllocMaxPerThread; }
+
+const double* launch_stress_noalloc(const StepArgs& a, int precision, bool batched, int scene, hipStream_t st)
+{
+    double* base = noalloc_scratch();
+    if (!base) return nullptr;
+    if (a.npairs <= 0 || (int64_t)a.npairs > stress_noalloc_max_pairs()) return nullptr;
+    const int grid = std::min(stress_blocks(a.npairs), kNoAllocBlocks);
+    const int64_t span = (int64_t)grid * kStressBlock;
+    const int per_thread = (int)((a.npairs + span - 1) / span);
+    static_assert(sizeof(scratch) == sizeof(double) * (kNoAllocBlocks + 1) * kNoAllocWords, "scratch size");
+    double* out = base + (size_t)kNoAllocBlocks * kNoAllocWords;
+    if (precision == DEM_FP32_MIXED) {
+        if (batched)
+            hipLaunchKernelGGL((k_stress_strided<DEM_FP32_MIXED, true>), dim3(grid), dim3(kStressBlock), 0, st, a, scene,
+                               per_thread, base);
+        else
+            hipLaunchKernelGGL((k_stress_strided<DEM_FP32_MIXED, false>), dim3(grid), dim3(kStressBlock), 0, st, a,
+                               scene, per_thread, base);
+    } else {
+        if (batched)
+            hipLaunchKernelGGL((k_stress_strided<DEM_FP64, true>), dim3(grid), dim3(kStressBlock), 0, st, a, scene,
+                               per_thread, base);
+        else
+            hipLaunchKernelGGL((k_stress_strided<DEM_FP64, false>), dim3(grid), dim3(kStressBlock), 0, st, a, scene,
+                               per_thread, base);
+    }
+    hipLaunchKernelGGL(k_stress_final, dim3(1), dim3(64), 0, st, (const double*)base, grid, out);
+    return out;
+}
 
 void launch_pair_forces(const StepArgs& a, int precision, double* f3, hipStream_t st)
 {

@@ -162,6 +162,7 @@ SIGNATURES = {
     "dem_set_history": (C.c_int32, [C.c_void_p, C.c_int64, C.POINTER(dem_history)]),
     "dem_get_energy": (C.c_int32, [C.c_void_p, C.POINTER(dem_energy)]),
     "dem_get_stress": (C.c_int32, [C.c_void_p, C.c_double, _DP]),
+    "dem_get_stress_noalloc": (C.c_int32, [C.c_void_p, C.c_double, _DP]),
     "dem_get_stats": (C.c_int32, [C.c_void_p, C.POINTER(dem_stats)]),
     "dem_set_timing": (C.c_int32, [C.c_void_p, C.c_int32]),
     "dem_get_timing": (C.c_int32, [C.c_void_p, C.c_char_p, _DP, _I64P]),
@@ -461,6 +462,11 @@ class Scene:
     def get_stress(self, volume=0.0):
         out = np.zeros(9)
         check(self.lib.dem_get_stress(self.h, float(volume), _p(out)), "dem_get_stress")
+        return out.reshape(3, 3)
+
+    def get_stress_noalloc(self, volume=0.0):
+        out = np.zeros(9)
+        check(self.lib.dem_get_stress_noalloc(self.h, float(volume), _p(out)), "dem_get_stress_noalloc")
         return out.reshape(3, 3)
 
     def unbalanced_force(self, use_max=False):
