@@ -69,14 +69,30 @@ __device__ inline int32_t neg_cell(int32_t p)
     return pack_cell(-c[0], -c[1], -c[2]);
 }
 
-// Cell of a body and, in a periodic cell, its integer period.
+// One level of a scene's grid (level 1 exists only when r_split > 0).
+struct Level {
+    const double* origin;
+    const double* inv_h;
+    const double* cellw;
+    const int32_t* dims;
+    int32_t offset;
+};
+__device__ inline Level level_of(const SceneParams& P, int lv)
+{
+    return lv == 0 ? Level{P.origin, P.inv_h, P.cellw, P.dims, P.cell_offset}
+                   : Level{P.origin2, P.inv_h2, P.cellw2, P.dims2, P.cell_offset2};
+}
+// the level a sphere of radius r is binned on
+__device__ inline int level_of_radius(const SceneParams& P, double r) { return (P.r_split > 0.0 && r > P.r_split) ? 1 : 0; }
+
+// Cell of a body on one level and, in a periodic cell, its integer period.
 template <bool PERIODIC>
-__device__ inline void cell_of(const SceneParams& P, double x, double y, double z, int* c, int* per)
+__device__ inline void cell_of(const SceneParams& P, const Level& V, double x, double y, double z, int* c, int* per)
 {
     if (!PERIODIC) {
-        c[0] = clampi((int)floor((x - P.origin[0]) * P.inv_h[0]), 0, P.dims[0] - 1);
-        c[1] = clampi((int)floor((y - P.origin[1]) * P.inv_h[1]), 0, P.dims[1] - 1);
-        c[2] = clampi((int)floor((z - P.origin[2]) * P.inv_h[2]), 0, P.dims[2] - 1);
+        c[0] = clampi((int)floor((x - V.origin[0]) * V.inv_h[0]), 0, V.dims[0] - 1);
+        c[1] = clampi((int)floor((y - V.origin[1]) * V.inv_h[1]), 0, V.dims[1] - 1);
+        c[2] = clampi((int)floor((z - V.origin[2]) * V.inv_h[2]), 0, V.dims[2] - 1);
         per[0] = per[1] = per[2] = 0;
         return;
     }
@@ -85,7 +101,7 @@ __device__ inline void cell_of(const SceneParams& P, double x, double y, double 
     for (int k = 0; k < 3; ++k) {
         double p = floor(f[k]);
         per[k] = (int)p;
-        c[k] = clampi((int)floor((f[k] - p) * P.inv_h[k]), 0, P.dims[k] - 1);
+        c[k] = clampi((int)floor((f[k] - p) * V.inv_h[k]), 0, V.dims[k] - 1);
     }
 }
 
@@ -211,12 +227,20 @@ __global__ void __launch_bounds__(kBlock) k_keys(GridArgs g, uint64_t* __restric
     const SceneParams& P = (BATCHED || PERIODIC) ? g.scenes[s] : g.scene0;
     int c[3], per[3];
     const double4 p = g.bod.xr[i];
-    cell_of<PERIODIC>(P, p.x, p.y, p.z, c, per);
+    cell_of<PERIODIC>(P, level_of(P, 0), p.x, p.y, p.z, c, per);
+    // key: scene | Morton code of the level-0 cell (every sphere)
     uint64_t key = morton3(c[0], c[1], c[2]);
     if (BATCHED) key |= (uint64_t)s << (3 * g.morton_bits);
     keys[i] = key;
     vals[i] = (uint32_t)i;
-    if (PERIODIC) g.bod.period[i] = pack_cell(per[0], per[1], per[2]);
+    if (PERIODIC) {
+        // a period is packed in 10 bits per axis: farther than 512 periods
+        // from the origin it would wrap, so the run is refused instead
+        bool out = false;
+        for (int k = 0; k < 3; ++k) out = out || per[k] < -512 || per[k] > 511;
+        if (out) *g.period_range = 1;
+        g.bod.period[i] = pack_cell(per[0], per[1], per[2]);
+    }
 }
 
 // ----------------------------------------------------------------- permute
@@ -244,15 +268,16 @@ __global__ void __launch_bounds__(kBlock) k_permute(Bodies src, Bodies dst, cons
 
 // ------------------------------------------------------------------- cells
 
-__device__ inline int cell_linear(const GridArgs& g, uint64_t key, const SceneParams** Pout)
+template <int LV>
+__device__ inline int cell_linear(const GridArgs& g, uint64_t key)
 {
-    const uint64_t mmask = (g.morton_bits * 3 >= 64) ? ~0ull : ((1ull << (3 * g.morton_bits)) - 1ull);
+    const uint64_t mmask = (3 * g.morton_bits >= 64) ? ~0ull : ((1ull << (3 * g.morton_bits)) - 1ull);
     const int s = g.nscenes > 1 ? (int)(key >> (3 * g.morton_bits)) : 0;
     const SceneParams& P = g.nscenes > 1 ? g.scenes[s] : g.scene0;
-    *Pout = &P;
+    const Level V = level_of(P, LV);
     const uint64_t m = key & mmask;
     const int cx = (int)compact3(m), cy = (int)compact3(m >> 1), cz = (int)compact3(m >> 2);
-    return P.cell_offset + cx + P.dims[0] * (cy + P.dims[1] * cz);
+    return V.offset + cx + V.dims[0] * (cy + V.dims[1] * cz);
 }
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int n)
@@ -268,11 +293,56 @@ __global__ void __launch_bounds__(kBlock) k_cells(GridArgs g, const uint64_t* __
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.nslots) return;
     const uint64_t k = keys[i];
-    const SceneParams* P;
-    const int lin = cell_linear(g, k, &P);
+    const int lin = cell_linear<0>(g, k);
     if (lin < 0 || lin >= ncells) return;
     if (i == 0 || keys[i - 1] != k) cell_start[lin] = (uint32_t)i;
     if (i == g.nslots - 1 || keys[i + 1] != k) cell_end[lin] = (uint32_t)(i + 1);
+}
+
+// ---------------------------------------------------- level 1 (two levels)
+
+// flag[i] = 1 for a sphere above its scene's r_split
+template <bool BATCHED>
+__global__ void __launch_bounds__(kBlock) k_large_flags(GridArgs g, uint32_t* __restrict__ flag)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.nslots) return;
+    const int s = BATCHED ? (int)g.bod.scene[i] : 0;
+    const SceneParams& P = BATCHED ? g.scenes[s] : g.scene0;
+    flag[i] = level_of_radius(P, g.bod.xr[i].w) == 1 ? 1u : 0u;
+}
+
+// the coarse-cell key and slot of each large sphere, at its scanned position
+template <bool BATCHED, bool PERIODIC>
+__global__ void __launch_bounds__(kBlock) k_large_keys(GridArgs g, const uint32_t* __restrict__ scan,
+                                                       uint64_t* __restrict__ keys2, uint32_t* __restrict__ vals2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.nslots) return;
+    const uint32_t q = scan[i];
+    if (scan[i + 1] == q) return;  // not a large sphere
+    const int s = BATCHED ? (int)g.bod.scene[i] : 0;
+    const SceneParams& P = (BATCHED || PERIODIC) ? g.scenes[s] : g.scene0;
+    const double4 p = g.bod.xr[i];
+    int c[3], per[3];
+    cell_of<PERIODIC>(P, level_of(P, 1), p.x, p.y, p.z, c, per);
+    uint64_t key = morton3(c[0], c[1], c[2]);
+    if (BATCHED) key |= (uint64_t)s << (3 * g.morton_bits);
+    keys2[q] = key;
+    vals2[q] = (uint32_t)i;
+}
+
+__global__ void __launch_bounds__(kBlock) k_cells_large(GridArgs g, const uint64_t* __restrict__ keys2, int n,
+                                                        uint32_t* __restrict__ cell_start,
+                                                        uint32_t* __restrict__ cell_end, int ncells)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const uint64_t k = keys2[q];
+    const int lin = cell_linear<1>(g, k);
+    if (lin < 0 || lin >= ncells) return;
+    if (q == 0 || keys2[q - 1] != k) cell_start[lin] = (uint32_t)q;
+    if (q == n - 1 || keys2[q + 1] != k) cell_end[lin] = (uint32_t)(q + 1);
 }
 
 // ------------------------------------------------------------------- sweep
@@ -290,12 +360,19 @@ __device__ inline void for_each_candidate(const SweepArgs& a, int i, F&& f)
     const double xi = pi.x, yi = pi.y, zi = pi.z, ri = pi.w;
     const int32_t myid = B.id[i];
     const double reach = 2.0 * P.verlet;
+    // level 0 holds every sphere; with two levels a sphere takes its
+    // partners up to r_split there and the larger ones from level 1
+    const bool two = P.r_split > 0.0;
+    const int nlev = two ? 2 : 1;
+    for (int lv = 0; lv < nlev; ++lv) {
+    const Level V = level_of(P, lv);
     int c[3], per_i[3];
-    cell_of<PERIODIC>(P, xi, yi, zi, c, per_i);
-    // cells within reach of this body's largest possible candidate distance
-    const double far = (ri + P.rmax) + reach;
+    cell_of<PERIODIC>(P, V, xi, yi, zi, c, per_i);
+    // cells of this level within reach of this body's largest possible
+    // candidate distance on it (the largest radius it takes there)
+    const double far = (ri + (lv == 0 && two ? P.r_split : P.rmax)) + reach;
     int kk[3];
-    for (int q = 0; q < 3; ++q) kk[q] = max(1, (int)ceil(far / P.cellw[q]));
+    for (int q = 0; q < 3; ++q) kk[q] = max(1, (int)ceil(far / V.cellw[q]));
     for (int dz = -kk[2]; dz <= kk[2]; ++dz)
         for (int dy = -kk[1]; dy <= kk[1]; ++dy)
             for (int dx = -kk[0]; dx <= kk[0]; ++dx) {
@@ -305,23 +382,25 @@ __device__ inline void for_each_candidate(const SweepArgs& a, int i, F&& f)
                 for (int k = 0; k < 3; ++k) {
                     if (n[k] < 0) {
                         if (!PERIODIC) skip = true;
-                        n[k] += P.dims[k];
+                        n[k] += V.dims[k];
                         w[k] = -1;
-                    } else if (n[k] >= P.dims[k]) {
+                    } else if (n[k] >= V.dims[k]) {
                         if (!PERIODIC) skip = true;
-                        n[k] -= P.dims[k];
+                        n[k] -= V.dims[k];
                         w[k] = 1;
                     }
                 }
                 if (skip) continue;
-                const int lin = P.cell_offset + n[0] + P.dims[0] * (n[1] + P.dims[1] * n[2]);
+                const int lin = V.offset + n[0] + V.dims[0] * (n[1] + V.dims[1] * n[2]);
                 const uint32_t st = a.cell_start[lin];
                 if (st == kEmpty) continue;
                 const uint32_t en = a.cell_end[lin];
-                for (uint32_t j = st; j < en; ++j) {
+                for (uint32_t q = st; q < en; ++q) {
+                    const uint32_t j = lv == 0 ? q : g.large_slot[q];
                     if ((int)j == i) continue;
                     const double4 pj = B.xr[j];
                     const double rj = pj.w;
+                    if (lv == 0 && two && rj > P.r_split) continue;  // found on level 1
                     const double sc = (ri + rj) + reach;
                     double ddx, ddy, ddz;
                     int32_t packed = kCellZero;
@@ -353,6 +432,7 @@ __device__ inline void for_each_candidate(const SweepArgs& a, int i, F&& f)
                     if (dd < sc * sc) f((int32_t)j, B.id[j], packed);
                 }
             }
+    }
     for (int k = 0; k < P.wall_count; ++k) {
         const int wi = P.wall_begin + k;
         const Wall W = a.walls[wi];
@@ -368,103 +448,133 @@ __device__ inline void for_each_candidate(const SweepArgs& a, int i, F&& f)
     }
 }
 
-template <bool BATCHED, bool PERIODIC>
+// The sweeps run in two passes when a scene has two levels: the spheres of
+// level 0 first (LARGE = false; a large sphere's lane returns at once), then
+// the large ones through their index array (LARGE = true), so that a wave
+// holds sweeps of one kind (a large sphere searches many more cells).
+template <bool BATCHED, bool LARGE>
+__device__ inline int sweep_body(const SweepArgs& a)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (LARGE) return t < a.nlarge ? (int)a.g.large_slot[t] : -1;
+    if (t >= a.g.nslots) return -1;
+    if (a.nlarge > 0) {
+        const int s = BATCHED ? (int)a.g.bod.scene[t] : 0;
+        const SceneParams& P = BATCHED ? a.g.scenes[s] : a.g.scene0;
+        if (level_of_radius(P, a.g.bod.xr[t].w) == 1) return -1;
+    }
+    return t;
+}
+
+template <bool BATCHED, bool PERIODIC, bool LARGE>
 __global__ void __launch_bounds__(kBlock) k_sweep_count(SweepArgs a)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.g.nslots) return;
+    const int i = sweep_body<BATCHED, LARGE>(a);
+    if (i < 0) return;
     uint32_t n = 0;
     for_each_candidate<BATCHED, PERIODIC>(a, i, [&](int32_t, int32_t, int32_t) { ++n; });
     a.count[i] = n;
 }
 
-template <bool BATCHED, bool PERIODIC>
+template <bool BATCHED, bool PERIODIC, bool LARGE>
 __global__ void __launch_bounds__(kBlock) k_sweep_fill(SweepArgs a)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.g.nslots) return;
+    const int i = sweep_body<BATCHED, LARGE>(a);
+    if (i < 0) return;
     const int beg = a.row_start[i];
     const int cap = a.row_start[i + 1] - beg;
-    const int32_t myid = a.g.bod.id[i];
     int n = 0;
     for_each_candidate<BATCHED, PERIODIC>(a, i, [&](int32_t slot, int32_t pid, int32_t cell) {
         if (n < cap) {
-            a.ent_slot[beg + n] = slot;
-            a.ent_pid[beg + n] = pid;
-            a.ent_cell[beg + n] = cell;
+            a.raw_slot[beg + n] = slot;
+            a.raw_pid[beg + n] = pid;
+            a.raw_cell[beg + n] = cell;
+            a.ent_body[beg + n] = i;
         }
         ++n;
     });
-    // sort the row by (partner id, image): this fixes the order of the force sum
-    for (int p = 1; p < cap; ++p) {
-        const int32_t ks = a.ent_slot[beg + p], kp = a.ent_pid[beg + p], kc = a.ent_cell[beg + p];
-        int q = p - 1;
-        while (q >= 0) {
-            const int32_t qp = a.ent_pid[beg + q];
-            const int32_t qc = a.ent_cell[beg + q];
-            if (qp < kp || (qp == kp && (uint32_t)qc <= (uint32_t)kc)) break;
-            a.ent_slot[beg + q + 1] = a.ent_slot[beg + q];
-            a.ent_pid[beg + q + 1] = qp;
-            a.ent_cell[beg + q + 1] = qc;
-            --q;
-        }
-        a.ent_slot[beg + q + 1] = ks;
-        a.ent_pid[beg + q + 1] = kp;
-        a.ent_cell[beg + q + 1] = kc;
+}
+
+// One thread per entry: its place in its row sorted by (partner id, image
+// as unsigned; ties by the order found, which cannot happen for distinct
+// candidates) is the number of the row's entries before it in that order.
+// Rows are short except those of the largest spheres, whose entries are
+// then spread over many threads; this order fixes the order of the force sum.
+__global__ void __launch_bounds__(kBlock) k_row_rank(SweepArgs a)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.nent) return;
+    const int i = a.ent_body[e];
+    const int beg = a.row_start[i], end = a.row_start[i + 1];
+    const int32_t pid = a.raw_pid[e];
+    const uint32_t cell = (uint32_t)a.raw_cell[e];
+    int rank = 0;
+    for (int f = beg; f < end; ++f) {
+        const int32_t pf = a.raw_pid[f];
+        const uint32_t cf = (uint32_t)a.raw_cell[f];
+        rank += (pf < pid || (pf == pid && (cf < cell || (cf == cell && f < e)))) ? 1 : 0;
     }
-    for (int p = 0; p < cap; ++p) {
-        const int32_t slot = a.ent_slot[beg + p];
-        a.ent_own[beg + p] = (slot < 0 || myid < a.ent_pid[beg + p]) ? 1u : 0u;
-    }
+    const int dst = beg + rank;
+    const int32_t slot = a.raw_slot[e];
+    a.ent_slot[dst] = slot;
+    a.ent_pid[dst] = pid;
+    a.ent_cell[dst] = (int32_t)cell;
+    a.ent_own[dst] = (slot < 0 || a.g.bod.id[i] < pid) ? 1u : 0u;
 }
 
 // -------------------------------------------------------- pairs and history
 
+// One thread per row entry: an owning entry writes its pair (canonical
+// index = the scan of the owner flags) and its row entry; the other finds
+// its pair by binary search in the partner's sorted row.  The first entry of
+// a row also writes the body's range of owned pairs.
 __global__ void __launch_bounds__(kBlock) k_pair_build(PairBuildArgs a)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.nslots) return;
-    const int beg = a.row_start[i], end = a.row_start[i + 1];
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.nent) return;
+    const int i = a.ent_body[e];
     const int32_t myid = a.bod.id[i];
-    for (int e = beg; e < end; ++e) {
-        const int32_t slot = a.ent_slot[e];
-        if (a.ent_own[e]) {
-            const uint32_t k = a.own_scan[e];
-            if (slot < 0) {
-                // a wall pair: the wall is #1 and has no row
-                a.ca[k] = slot;
-                a.cb[k] = i;
-                a.rows.ent[e] = k;
-            } else {
-                a.ca[k] = i;
-                a.cb[k] = slot;
-                a.rows.ent[e] = k | kNegSign;
-            }
-            a.hist_new.cell[k] = a.ent_cell[e];
-            a.hist_new.pid[k] = a.ent_pid[e];
-        } else {
-            // the pair is owned by the partner: find this body in its row,
-            // which is sorted by (partner id, packed image as unsigned)
-            const uint32_t want = (uint32_t)neg_cell(a.ent_cell[e]);
-            int lo = a.row_start[slot], hi = a.row_start[slot + 1];
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                const int32_t pm = a.ent_pid[mid];
-                const uint32_t cm = (uint32_t)a.ent_cell[mid];
-                if (pm < myid || (pm == myid && cm < want))
-                    lo = mid + 1;
-                else
-                    hi = mid;
-            }
-            uint32_t k = kPairMask;
-            if (lo < a.row_start[slot + 1] && a.ent_pid[lo] == myid && (uint32_t)a.ent_cell[lo] == want &&
-                a.ent_own[lo])
-                k = a.own_scan[lo];
+    const int32_t slot = a.ent_slot[e];
+    if (a.ent_own[e]) {
+        const uint32_t k = a.own_scan[e];
+        if (slot < 0) {
+            // a wall pair: the wall is #1 and has no row
+            a.ca[k] = slot;
+            a.cb[k] = i;
             a.rows.ent[e] = k;
+        } else {
+            a.ca[k] = i;
+            a.cb[k] = slot;
+            a.rows.ent[e] = k | kNegSign;
         }
+        a.hist_new.cell[k] = a.ent_cell[e];
+        a.hist_new.pid[k] = a.ent_pid[e];
+    } else {
+        // the pair is owned by the partner: find this body in its row,
+        // which is sorted by (partner id, packed image as unsigned)
+        const uint32_t want = (uint32_t)neg_cell(a.ent_cell[e]);
+        int lo = a.row_start[slot], hi = a.row_start[slot + 1];
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            const int32_t pm = a.ent_pid[mid];
+            const uint32_t cm = (uint32_t)a.ent_cell[mid];
+            if (pm < myid || (pm == myid && cm < want))
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        uint32_t k = kPairMask;
+        if (lo < a.row_start[slot + 1] && a.ent_pid[lo] == myid && (uint32_t)a.ent_cell[lo] == want &&
+            a.ent_own[lo])
+            k = a.own_scan[lo];
+        a.rows.ent[e] = k;
     }
-    a.hist_new.own_begin[myid] = (int32_t)a.own_scan[beg];
-    a.hist_new.own_count[myid] = (int32_t)(a.own_scan[end] - a.own_scan[beg]);
+    const int beg = a.row_start[i];
+    if (e == beg) {
+        const int end = a.row_start[i + 1];
+        a.hist_new.own_begin[myid] = (int32_t)a.own_scan[beg];
+        a.hist_new.own_count[myid] = (int32_t)(a.own_scan[end] - a.own_scan[beg]);
+    }
 }
 
 // Per canonical pair: where its history sits in the previous list, and
@@ -600,34 +710,67 @@ void launch_cells(const GridArgs& g, const uint64_t* sorted_keys, uint32_t* cell
                            cell_end, ncells);
 }
 
+void launch_large_flags(const GridArgs& g, uint32_t* flag, hipStream_t st)
+{
+    if (g.nslots <= 0) return;
+    if (g.nscenes > 1)
+        hipLaunchKernelGGL((k_large_flags<true>), dim3(nblocks(g.nslots)), dim3(kBlock), 0, st, g, flag);
+    else
+        hipLaunchKernelGGL((k_large_flags<false>), dim3(nblocks(g.nslots)), dim3(kBlock), 0, st, g, flag);
+}
+
+void launch_large_keys(const GridArgs& g, const uint32_t* scan, uint64_t* keys2, uint32_t* vals2, hipStream_t st)
+{
+    if (g.nslots <= 0) return;
+    dim3 grid(nblocks(g.nslots)), blk(kBlock);
+    if (g.nscenes > 1)
+        hipLaunchKernelGGL((k_large_keys<true, false>), grid, blk, 0, st, g, scan, keys2, vals2);
+    else if (g.scene0.periodic)
+        hipLaunchKernelGGL((k_large_keys<false, true>), grid, blk, 0, st, g, scan, keys2, vals2);
+    else
+        hipLaunchKernelGGL((k_large_keys<false, false>), grid, blk, 0, st, g, scan, keys2, vals2);
+}
+
+void launch_cells_large(const GridArgs& g, const uint64_t* sorted_keys2, int nlarge, uint32_t* cell_start,
+                        uint32_t* cell_end, int ncells, hipStream_t st)
+{
+    if (nlarge > 0)
+        hipLaunchKernelGGL(k_cells_large, dim3(nblocks(nlarge)), dim3(kBlock), 0, st, g, sorted_keys2, nlarge,
+                           cell_start, cell_end, ncells);
+}
+
+#define DEM_SWEEP_LAUNCH(KERNEL, A, ST)                                                                          \
+    do {                                                                                                      \
+        const dim3 blk(kBlock), g0(nblocks((A).g.nslots)), g1(nblocks((A).nlarge > 0 ? (A).nlarge : 1));     \
+        if ((A).g.nscenes > 1) {                                                                              \
+            hipLaunchKernelGGL((KERNEL<true, false, false>), g0, blk, 0, ST, A);                              \
+            if ((A).nlarge > 0) hipLaunchKernelGGL((KERNEL<true, false, true>), g1, blk, 0, ST, A);           \
+        } else if ((A).g.scene0.periodic) {                                                                   \
+            hipLaunchKernelGGL((KERNEL<false, true, false>), g0, blk, 0, ST, A);                              \
+            if ((A).nlarge > 0) hipLaunchKernelGGL((KERNEL<false, true, true>), g1, blk, 0, ST, A);           \
+        } else {                                                                                              \
+            hipLaunchKernelGGL((KERNEL<false, false, false>), g0, blk, 0, ST, A);                             \
+            if ((A).nlarge > 0) hipLaunchKernelGGL((KERNEL<false, false, true>), g1, blk, 0, ST, A);          \
+        }                                                                                                     \
+    } while (0)
+
 void launch_sweep_count(const SweepArgs& a, hipStream_t st)
 {
     if (a.g.nslots <= 0) return;
-    dim3 grid(nblocks(a.g.nslots)), blk(kBlock);
-    if (a.g.nscenes > 1)
-        hipLaunchKernelGGL((k_sweep_count<true, false>), grid, blk, 0, st, a);
-    else if (a.g.scene0.periodic)
-        hipLaunchKernelGGL((k_sweep_count<false, true>), grid, blk, 0, st, a);
-    else
-        hipLaunchKernelGGL((k_sweep_count<false, false>), grid, blk, 0, st, a);
+    DEM_SWEEP_LAUNCH(k_sweep_count, a, st);
 }
 
 void launch_sweep_fill(const SweepArgs& a, hipStream_t st)
 {
     if (a.g.nslots <= 0) return;
-    dim3 grid(nblocks(a.g.nslots)), blk(kBlock);
-    if (a.g.nscenes > 1)
-        hipLaunchKernelGGL((k_sweep_fill<true, false>), grid, blk, 0, st, a);
-    else if (a.g.scene0.periodic)
-        hipLaunchKernelGGL((k_sweep_fill<false, true>), grid, blk, 0, st, a);
-    else
-        hipLaunchKernelGGL((k_sweep_fill<false, false>), grid, blk, 0, st, a);
+    DEM_SWEEP_LAUNCH(k_sweep_fill, a, st);
+    if (a.nent > 0) hipLaunchKernelGGL(k_row_rank, dim3(nblocks(a.nent)), dim3(kBlock), 0, st, a);
 }
 
 void launch_pair_build(const PairBuildArgs& a, hipStream_t st)
 {
-    if (a.nslots <= 0) return;
-    hipLaunchKernelGGL(k_pair_build, dim3(nblocks(a.nslots)), dim3(kBlock), 0, st, a);
+    if (a.nent <= 0) return;
+    hipLaunchKernelGGL(k_pair_build, dim3(nblocks(a.nent)), dim3(kBlock), 0, st, a);
 }
 
 void launch_carry_find(const PairBuildArgs& a, hipStream_t st, int old_nbodies)

@@ -48,6 +48,19 @@ struct SceneParams {
     double verlet_cell_rate;  // 1/2 |L|_F (2 r_max + 4 Delta L): Verlet budget used per unit time by the mean field
     double rmax;              // largest radius of the scene at the run
     double cellw[3];          // metric width of a grid cell along each axis (>= the cell size h)
+    // Two-level grid for wide size ratios: every sphere is binned on the
+    // grid above (level 0, cells >= 2 r_split + 2 Delta L; this also fixes
+    // the bodies' memory order), and the spheres of radius > r_split also on
+    // a coarse grid of their own (level 1, cells >= 2 r_max + 2 Delta L,
+    // an index array of their slots).  A sphere finds its partners of radius
+    // <= r_split on level 0 and the larger ones on level 1.  r_split = 0: one
+    // level (cells >= 2 r_max + 2 Delta L).
+    double r_split;
+    double origin2[3];
+    double inv_h2[3];
+    double cellw2[3];
+    int32_t dims2[3];
+    int32_t cell_offset2;
 };
 
 // A fixed boundary: an infinite axis-aligned plane (utils.wall: axis,
@@ -394,6 +407,8 @@ struct GridArgs {
     int32_t nslots;
     int32_t scene_bits;        // bits of the scene index in the key
     int32_t morton_bits;       // bits per axis
+    int32_t* period_range;     // set to 1 by k_keys when a body's period is outside [-512, 511]
+    const uint32_t* large_slot;  // level 1: slots of the spheres above r_split, in coarse-cell order (or null)
 };
 size_t bounds_temp_bytes(int nslots);
 void launch_bounds(const Bodies& b, int nslots, int nscenes, double* out6, void* temp, hipStream_t st);
@@ -402,6 +417,14 @@ void launch_permute(const Bodies& src, const Bodies& dst, const uint32_t* order,
                     bool periodic, int32_t* slot_of_id, hipStream_t st);
 void launch_cells(const GridArgs& g, const uint64_t* sorted_keys, uint32_t* cell_start, uint32_t* cell_end,
                   int ncells, hipStream_t st);
+// Level 1 of a two-level grid: flags of the spheres above their scene's
+// r_split (then scanned by the caller), their coarse-cell keys and slots at
+// the scanned positions, and (after sorting those) the level's cell ranges
+// into the sorted index array.
+void launch_large_flags(const GridArgs& g, uint32_t* flag, hipStream_t st);
+void launch_large_keys(const GridArgs& g, const uint32_t* scan, uint64_t* keys2, uint32_t* vals2, hipStream_t st);
+void launch_cells_large(const GridArgs& g, const uint64_t* sorted_keys2, int nlarge, uint32_t* cell_start,
+                        uint32_t* cell_end, int ncells, hipStream_t st);
 struct SweepArgs {
     GridArgs g;
     const uint32_t* cell_start;
@@ -409,14 +432,23 @@ struct SweepArgs {
     const Wall* walls;
     uint32_t* count;           // per slot
     const int32_t* row_start;  // fill pass
-    int32_t* ent_slot;         // fill pass: partner slot or -1 - wall
-    int32_t* ent_pid;          // partner id
-    int32_t* ent_cell;         // packed image shift of the partner
+    // the fill pass writes each row's entries in the order found (raw_*, and
+    // the row of every entry), the rank pass sorts each row by (partner id,
+    // image) into ent_* and marks the entries that own their pair
+    int32_t* raw_slot;         // partner slot or -1 - wall
+    int32_t* raw_pid;          // partner id
+    int32_t* raw_cell;         // packed image shift of the partner
+    int32_t* ent_body;         // slot whose row holds the entry
+    int32_t* ent_slot;
+    int32_t* ent_pid;
+    int32_t* ent_cell;
     uint32_t* ent_own;         // 1 when this entry owns the pair
     int32_t max_row;
+    int32_t nent;
+    int32_t nlarge;            // spheres on level 1 (their sweeps run as a pass of their own)
 };
 void launch_sweep_count(const SweepArgs& a, hipStream_t st);
-void launch_sweep_fill(const SweepArgs& a, hipStream_t st);
+void launch_sweep_fill(const SweepArgs& a, hipStream_t st);  // fill, then the rank pass
 struct PairBuildArgs {
     Bodies bod;
     const int32_t* row_start;
@@ -425,6 +457,7 @@ struct PairBuildArgs {
     const int32_t* ent_cell;
     const uint32_t* own_scan;  // exclusive scan of the owner flags
     const uint32_t* ent_own;
+    const int32_t* ent_body;   // slot whose row holds the entry
     Rows rows;
     Pairs pr;                  // the new list (partitioned order)
     History hist_new;          // own ranges and canonical arrays of the new list

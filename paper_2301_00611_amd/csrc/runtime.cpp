@@ -178,6 +178,10 @@ struct HostScene {
     double rmax = 0.0;          // largest radius at the last broad-phase run
     double r_lo = INFINITY;     // smallest and largest sphere radius (radii never change)
     double r_hi = 0.0;
+    // two-level grid: radii above r_split go on the coarse level (0 = one
+    // level), n_large of them
+    double r_split = 0.0;
+    int64_t n_large = 0;
 };
 
 // Host copy of everything per gid (kept in step only when bodies are added
@@ -257,6 +261,9 @@ struct World {
     };
     ChunkStart* h_chunk = nullptr;
     int ncells = 0;
+    DBuf d_flag;                       // broad phase: a body's period out of the packed range
+    DBuf lflag, lscan, keys2, vals2, keys2_alt, vals2_alt;  // level 1 of a two-level grid
+    DBuf raw_slot, raw_pid, raw_cell, ent_body;              // row entries in the order found, and their rows
     int morton_bits = 1, scene_bits = 0;
     int64_t rebuilds = 0;
     int64_t n_candidates = 0;
@@ -294,7 +301,8 @@ struct World {
                         &ent_slot, &ent_pid, &ent_cell, &ent_own, &own_scan, &rows_ent, &scan_tmp, &radix_tmp,
                         &d_scenes, &d_walls, &d_mats, &d_tanphi, &d_ctr, &d_part_c, &d_part_i, &d_bounds, &d_total,
                         &d_tmp3, &d_args, &d_ctrl_cfg, &d_ctrl_state, &d_acc_ctrl, &d_acc_ctrl2, &pb_ca, &pb_cb, &pb_found,
-                        &pb_flag, &pb_scan})
+                        &pb_flag, &pb_scan, &d_flag, &lflag, &lscan, &keys2, &vals2, &keys2_alt, &vals2_alt, &raw_slot, &raw_pid,
+                        &raw_cell, &ent_body})
             d->release();
         if (h_ctr) (void)hipHostFree(h_ctr);
         h_ctr = nullptr;
@@ -540,9 +548,31 @@ struct World {
             bodies.push_back(b);
         }
         S.n_spheres += n;
+        split_levels(s);
         host_dirty = true;
         need_rebuild = true;
         return first;
+    }
+
+    // Size ratio above 2.5: two grid levels, split at the largest radius not
+    // above half the largest (small spheres then search cells sized for
+    // themselves, and the large ones search both levels); else one level.
+    void split_levels(int s)
+    {
+        HostScene& S = scenes[s];
+        S.r_split = 0.0;
+        S.n_large = 0;
+        if (!(S.r_hi > 2.5 * S.r_lo)) return;
+        double rs = 0.0;
+        for (int32_t g : S.gids) {
+            const HostBody& b = bodies[g];
+            if (b.kind == 0 && b.r <= 0.5 * S.r_hi) rs = std::max(rs, b.r);
+        }
+        int64_t nl = 0;
+        for (int32_t g : S.gids)
+            if (bodies[g].kind == 0 && bodies[g].r > rs) ++nl;
+        S.r_split = rs;
+        S.n_large = nl;
     }
 
     int64_t add_wall(int s, int axis, double position, int sense, int mat)
@@ -780,60 +810,94 @@ struct World {
         int cells = 0, maxdim = 1;
         for (int s = 0; s < nsc; ++s) {
             SceneParams& P = sp[s];
-            const double hmax = std::max(2.0 * rmax[s] + 2.0 * P.verlet, 1e-300) * (1.0 + 1e-9);
-            // cells of size h0 = 2 r_max + 2 Delta L: every body searches
-            // +-1 cell per axis (the sweep computes its reach per body from the
-            // cell widths, so a finer grid only needs a smaller h0 here)
-            const double h0 = hmax;
-            const int kmax = std::max(1, (int)std::ceil((2.0 * rmax[s] + 2.0 * P.verlet) / h0));
+            const double dl2 = 2.0 * P.verlet;
+            // the plain cell: 2 r_max + 2 Delta L; every body searches +-1 cell
+            const double hmax = std::max(2.0 * rmax[s] + dl2, 1e-300) * (1.0 + 1e-9);
+            double rs = scenes[s].r_split;
+            double Hinv[9];
             if (periodic) {
-                double Hinv[9];
                 if (!invert(P.H, Hinv)) fail(DEM_EPERIODIC, "singular periodic cell");
                 std::memcpy(P.Hinv, Hinv, sizeof Hinv);
+            }
+            // Periodic level: cells of at least h across each period; the
+            // largest body of the scene reaches `far` (its largest candidate
+            // distance on this level), which must stay within 2 k + 1 distinct
+            // cells so that no image is visited twice.
+            auto periodic_level = [&](double h, double far, int32_t* dims, double* inv_h, double* origin,
+                                      double* cellw) -> bool {
                 for (int k = 0; k < 3; ++k) {
                     const double rn = std::sqrt(Hinv[3 * k] * Hinv[3 * k] + Hinv[3 * k + 1] * Hinv[3 * k + 1] +
                                                 Hinv[3 * k + 2] * Hinv[3 * k + 2]);
                     const double width = 1.0 / rn;  // distance between opposite faces
-                    // cells of at least h0; a finer grid must keep 2 k + 1 distinct
-                    // cells across the period, else the plain grid is used
-                    int n = (int)std::floor(width / h0);
-                    if (n < 2 * kmax + 1) n = (int)std::floor(width / hmax);
-                    if (n < 3)
-                        fail(DEM_EPERIODIC, "periodic cell narrower than 3 x (2 r_max + 2 Delta L) along an axis");
-                    n = std::min(n, 1 << 20);
-                    P.dims[k] = n;
-                    P.inv_h[k] = (double)n;
-                    P.origin[k] = 0.0;
-                    P.cellw[k] = width / (double)n;
+                    int n = (int)std::min(std::floor(width / h), (double)(1 << 20));
+                    if (n < 3) return false;
+                    const int kk = std::max(1, (int)std::ceil(far / (width / (double)n)));
+                    if (n < 2 * kk + 1) return false;
+                    dims[k] = n;
+                    inv_h[k] = (double)n;
+                    origin[k] = 0.0;
+                    cellw[k] = width / (double)n;
                 }
-            } else {
+                return true;
+            };
+            // Aperiodic level: the bounding box in cells of at least h, the
+            // cell grown until the level's table holds at most 4 cells per body
+            auto box_level = [&](double h, int64_t nbodies, int32_t* dims, double* inv_h, double* origin,
+                                 double* cellw) {
                 const double lo[3] = {bnd[6 * s + 0], bnd[6 * s + 1], bnd[6 * s + 2]};
                 const double hi[3] = {bnd[6 * s + 3], bnd[6 * s + 4], bnd[6 * s + 5]};
-                double h = h0;
-                int64_t nscene = 0;
                 for (;;) {
                     int64_t tot = 1;
                     for (int k = 0; k < 3; ++k) {
                         const double ext = hi[k] > lo[k] ? hi[k] - lo[k] : 0.0;
                         int64_t n = (int64_t)std::floor(ext / h) + 1;
-                        P.dims[k] = (int)std::min<int64_t>(n, 1 << 20);
-                        tot *= P.dims[k];
+                        dims[k] = (int)std::min<int64_t>(n, 1 << 20);
+                        tot *= dims[k];
                     }
-                    nscene = tot;
-                    const int64_t ns = std::max<int64_t>(scenes[s].n_spheres, 1);
-                    if (tot <= 4 * ns + 4096 && P.dims[0] < (1 << 20) && P.dims[1] < (1 << 20) && P.dims[2] < (1 << 20)) break;
+                    const int64_t nb = std::max<int64_t>(nbodies, 1);
+                    if (tot <= 4 * nb + 4096 && dims[0] < (1 << 20) && dims[1] < (1 << 20) && dims[2] < (1 << 20)) break;
                     h *= 1.25;
                 }
-                (void)nscene;
                 for (int k = 0; k < 3; ++k) {
-                    P.origin[k] = lo[k] - 1e-12 * std::fabs(lo[k]) - 1e-300;
-                    P.inv_h[k] = 1.0 / h;
-                    P.cellw[k] = h;
+                    origin[k] = lo[k] - 1e-12 * std::fabs(lo[k]) - 1e-300;
+                    inv_h[k] = 1.0 / h;
+                    cellw[k] = h;
+                }
+            };
+            for (int k = 0; k < 3; ++k) {
+                P.dims2[k] = 1;
+                P.inv_h2[k] = 1.0;
+                P.origin2[k] = 0.0;
+                P.cellw2[k] = hmax;
+            }
+            if (rs > 0.0) {
+                // level 0 (radii <= r_split) and level 1 (the others)
+                const double h0 = (2.0 * rs + dl2) * (1.0 + 1e-9);
+                bool ok;
+                if (periodic) {
+                    ok = periodic_level(h0, (rmax[s] + rs) + dl2, P.dims, P.inv_h, P.origin, P.cellw) &&
+                         periodic_level(hmax, 2.0 * rmax[s] + dl2, P.dims2, P.inv_h2, P.origin2, P.cellw2);
+                } else {
+                    box_level(h0, scenes[s].n_spheres - scenes[s].n_large, P.dims, P.inv_h, P.origin, P.cellw);
+                    box_level(hmax, scenes[s].n_large, P.dims2, P.inv_h2, P.origin2, P.cellw2);
+                    ok = true;
+                }
+                if (!ok) rs = 0.0;  // the cell is too small for the fine level: one level
+            }
+            if (rs == 0.0) {
+                if (periodic) {
+                    if (!periodic_level(hmax, 2.0 * rmax[s] + dl2, P.dims, P.inv_h, P.origin, P.cellw))
+                        fail(DEM_EPERIODIC, "periodic cell narrower than 3 x (2 r_max + 2 Delta L) along an axis");
+                } else {
+                    box_level(hmax, scenes[s].n_spheres, P.dims, P.inv_h, P.origin, P.cellw);
                 }
             }
+            P.r_split = rs;
             P.cell_offset = cells;
             cells += P.dims[0] * P.dims[1] * P.dims[2];
-            for (int k = 0; k < 3; ++k) maxdim = std::max(maxdim, P.dims[k]);
+            P.cell_offset2 = cells;
+            if (rs > 0.0) cells += P.dims2[0] * P.dims2[1] * P.dims2[2];
+            for (int k = 0; k < 3; ++k) maxdim = std::max({maxdim, P.dims[k], rs > 0.0 ? P.dims2[k] : 1});
             // mean-field share of the Verlet budget (periodic)
             double lf = 0.0;
             for (int k = 0; k < 9; ++k) lf += P.L[k] * P.L[k];
@@ -847,7 +911,11 @@ struct World {
         scene_bits = 0;
         if (nsc > 1)
             while ((1 << scene_bits) < nsc) ++scene_bits;
+        // key: scene bits | 3 x morton_bits (either level's cell)
         if (3 * morton_bits + scene_bits > 64) fail(DEM_EINVAL, "grid too large for 64-bit cell keys");
+        int64_t nlarge = 0;
+        for (int s = 0; s < nsc; ++s)
+            if (sp[s].r_split > 0.0) nlarge += scenes[s].n_large;
         push_scene_table();
 
         Counters& C = *h_ctr;
@@ -867,7 +935,18 @@ struct World {
             keys_alt.ensure(8 * (size_t)nslots);
             vals_alt.ensure(4 * (size_t)nslots);
             radix_tmp.ensure(std::max(radix_temp_bytes(nslots), bounds_temp_bytes(nslots)));
+            d_flag.ensure(4);
+            g.period_range = d_flag.as<int32_t>();
+            HIPC(hipMemsetAsync(d_flag.p, 0, 4, stream));
             launch_keys(g, keys.as<uint64_t>(), vals.as<uint32_t>(), stream);
+            if (periodic) {
+                int32_t far = 0;
+                HIPC(hipMemcpyAsync(&far, d_flag.p, 4, hipMemcpyDeviceToHost, stream));
+                HIPC(hipStreamSynchronize(stream));
+                if (far)
+                    fail(DEM_EPERIODIC, "a sphere is more than 511 periods from the periodic cell's origin; "
+                                        "bring the positions back into the cell (dem_set_state)");
+            }
             bool in_alt = false;
             radix_sort_pairs(keys.as<uint64_t>(), vals.as<uint32_t>(), keys_alt.as<uint64_t>(), vals_alt.as<uint32_t>(),
                              nslots, 3 * morton_bits + scene_bits, radix_tmp.p, stream, &in_alt);
@@ -881,9 +960,36 @@ struct World {
             cell_start.ensure(4 * (size_t)ncells);
             cell_end.ensure(4 * (size_t)ncells);
             launch_cells(g, skeys, cell_start.as<uint32_t>(), cell_end.as<uint32_t>(), ncells, stream);
+            g.large_slot = nullptr;
+            if (nlarge > 0) {
+                // level 1: the spheres above r_split, their slots sorted by
+                // coarse cell (the bodies stay in level-0 order)
+                lflag.ensure(4 * ((size_t)nslots + 1));
+                lscan.ensure(4 * ((size_t)nslots + 1));
+                keys2.ensure(8 * (size_t)nlarge);
+                vals2.ensure(4 * (size_t)nlarge);
+                keys2_alt.ensure(8 * (size_t)nlarge);
+                vals2_alt.ensure(4 * (size_t)nlarge);
+                scan_tmp.ensure(scan_temp_bytes(nslots + 1));
+                d_total.ensure(16);
+                launch_large_flags(g, lflag.as<uint32_t>(), stream);
+                HIPC(hipMemsetAsync(lflag.as<uint32_t>() + nslots, 0, 4, stream));
+                exclusive_scan_u32(lflag.as<uint32_t>(), lscan.as<uint32_t>(), nslots + 1, scan_tmp.p,
+                                   d_total.as<uint32_t>(), stream);
+                launch_large_keys(g, lscan.as<uint32_t>(), keys2.as<uint64_t>(), vals2.as<uint32_t>(), stream);
+                bool alt2 = false;
+                radix_sort_pairs(keys2.as<uint64_t>(), vals2.as<uint32_t>(), keys2_alt.as<uint64_t>(),
+                                 vals2_alt.as<uint32_t>(), (int)nlarge, 3 * morton_bits + scene_bits, radix_tmp.p,
+                                 stream, &alt2);
+                const uint64_t* sk2 = alt2 ? keys2_alt.as<uint64_t>() : keys2.as<uint64_t>();
+                launch_cells_large(g, sk2, (int)nlarge, cell_start.as<uint32_t>(), cell_end.as<uint32_t>(), ncells,
+                                   stream);
+                g.large_slot = alt2 ? vals2_alt.as<uint32_t>() : vals2.as<uint32_t>();
+            }
             // sweep: count, scan, fill
-            SweepArgs sw;
+            SweepArgs sw{};
             sw.g = g;
+            sw.nlarge = (int)nlarge;
             sw.cell_start = cell_start.as<uint32_t>();
             sw.cell_end = cell_end.as<uint32_t>();
             sw.walls = d_walls.as<Wall>();
@@ -907,7 +1013,16 @@ struct World {
             ent_own.ensure(4 * ((size_t)nent + 1));
             own_scan.ensure(4 * ((size_t)nent + 1));
             rows_ent.ensure(4 * ((size_t)nent + 1));
+            raw_slot.ensure(4 * ((size_t)nent + 1));
+            raw_pid.ensure(4 * ((size_t)nent + 1));
+            raw_cell.ensure(4 * ((size_t)nent + 1));
+            ent_body.ensure(4 * ((size_t)nent + 1));
             sw.row_start = row_start.as<int32_t>();
+            sw.raw_slot = raw_slot.as<int32_t>();
+            sw.raw_pid = raw_pid.as<int32_t>();
+            sw.raw_cell = raw_cell.as<int32_t>();
+            sw.ent_body = ent_body.as<int32_t>();
+            sw.nent = (int)nent;
             sw.ent_slot = ent_slot.as<int32_t>();
             sw.ent_pid = ent_pid.as<int32_t>();
             sw.ent_cell = ent_cell.as<int32_t>();
@@ -941,6 +1056,7 @@ struct World {
             pb.ent_cell = ent_cell.as<int32_t>();
             pb.own_scan = own_scan.as<uint32_t>();
             pb.ent_own = ent_own.as<uint32_t>();
+            pb.ent_body = ent_body.as<int32_t>();
             pb.rows.start = row_start.as<int32_t>();
             pb.rows.ent = rows_ent.as<uint32_t>();
             pb.pr = NP.view();
@@ -1368,7 +1484,28 @@ struct World {
         if (host_dirty) upload_bodies();
         // no step: only bring the pair list up to date (a pending broad-phase run)
         if (nsteps == 0) {
-            if ((nslots > 0 || !walls.empty()) && (need_rebuild || h_ctr->stall[next_parity ^ 1])) rebuild();
+            if ((nslots > 0 || !walls.empty()) && (need_rebuild || h_ctr->stall[next_parity ^ 1])) {
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                if (timing) {
+                    HIPC(hipEventCreate(&e0));
+                    HIPC(hipEventCreate(&e1));
+                    HIPC(hipEventRecord(e0, stream));
+                }
+                try {
+                    rebuild();
+                    if (timing) {
+                        HIPC(hipEventRecord(e1, stream));
+                        HIPC(hipEventSynchronize(e1));
+                        add_time("rebuild", e0, e1);
+                    }
+                } catch (...) {
+                    if (e0) (void)hipEventDestroy(e0);
+                    if (e1) (void)hipEventDestroy(e1);
+                    throw;
+                }
+                if (e0) (void)hipEventDestroy(e0);
+                if (e1) (void)hipEventDestroy(e1);
+            }
             return false;
         }
         if (nslots == 0 && walls.empty()) {

@@ -156,6 +156,25 @@ def test_periodic_cell_too_small():
     s.close()
 
 
+def test_sphere_beyond_the_packed_period_range():
+    """Periods are packed in 10 bits per axis: a sphere more than 511
+    periods from the origin is refused (DEM_EPERIODIC) instead of wrapping
+    silently; brought back into the cell, the scene steps again."""
+    L = 0.02
+    s = dem.Scene(periodic=True, hsize=np.eye(3) * L, gravity=(0, 0, 0))
+    m = s.add_material(2600.0, 1e7, 0.3, 0.5)
+    pos = np.array([[0.005, 0.005, 0.005], [0.015, 0.015, 0.015]])
+    far = pos.copy()
+    far[1, 0] += 600 * L
+    s.add_spheres(far, np.array([1e-3, 1e-3]), default_mat=m)
+    s.set_dt(1e-6)
+    assert _code(s.step, 1) == dem.DEM_EPERIODIC
+    s.set_state(pos=pos)
+    s.step(2)
+    assert s.stats()["iter"] == 2
+    s.close()
+
+
 def test_batch_views():
     p = [dem.make_params(dt=1e-6, gravity=(0, 0, -9.81)) for _ in range(3)]
     b = dem.Batch(p)

@@ -61,15 +61,14 @@ def _periodic_history(pos, radius, box, ids, rng):
     return lo, hi, cell, fs, nprev
 
 
-def _periodic_full_size(spec, squeeze, ids, vel_scale, seed):
+def _periodic_full_size(spec, pos, H, ids, vel_scale, seed):
     """GPU scenes (FP64, FP32-mixed) and the oracle's spot step on `ids`
-    from the same squeezed state and history; returns the per-precision
-    GPU states after one step, the spot result and the GPU stats."""
+    from the same dense state (positions pos in the cube H) and history;
+    returns the per-precision GPU states and stats after one step, the spot
+    result and the step."""
     from oracle import OracleScene
     from paper_2301_00611_amd import dem
     from paper_2301_00611_amd.scenes import random_velocities
-    pos = spec.pos * squeeze
-    H = spec.hsize * squeeze
     box = float(H[0, 0])
     assert np.allclose(H, np.eye(3) * box) and pos.min() >= 0.0 and pos.max() < box
     n = len(spec.radius)
@@ -136,26 +135,32 @@ def test_bidisperse_shear_8m_spot():
     rng = np.random.default_rng(31)
     large = np.nonzero(spec.radius > 1e-3)[0]
     ids = np.concatenate([rng.choice(n, size=16, replace=False), rng.choice(large, size=8, replace=False)])
-    out, spot, dt = _periodic_full_size(spec, 0.998, ids, 0.01, 32)
+    out, spot, dt = _periodic_full_size(spec, spec.pos * 0.998, spec.hsize * 0.998, ids, 0.01, 32)
     st, stats = out[0]
     assert stats["n_contacts_ss"] > 10_000_000
     _check_spot(out, spot, ids, spec, dt, spec.material.young * 2.0e-3)
 
 
 def test_lognormal_compression_2m_spot():
-    """2,000,000 lognormal spheres (the compression workload's generator;
-    lattice spacing squeezed to 3.0 mm, so pairs with r1 + r2 > 3 mm
-    overlap and no overlap exceeds a radius), velGrad = -0.01 I: 24 random
-    spheres and 24 of the largest against the oracle's spot mode."""
+    """2,000,000 spheres with the compression workload's lognormal radii
+    (0.41 to 2.46 mm) on its generator's cubic lattice, with the spacing
+    brought down to 3.0 mm and a jitter of +-0.05 mm per axis: pairs with
+    r1 + r2 above ~3 mm overlap, and no overlap can exceed the smaller
+    radius.  velGrad = -0.01 I; 24 random spheres and 24 of the largest
+    against the oracle's spot mode."""
     from paper_2301_00611_amd.scenes import periodic_lognormal_gas
     spec = periodic_lognormal_gas(n=2_000_000, seed=0)
-    spacing = float(spec.hsize[0, 0]) / math.ceil(2_000_000 ** (1 / 3) - 1e-9)
-    squeeze = 3.0e-3 / spacing
     n = len(spec.radius)
+    k = math.ceil(n ** (1 / 3) - 1e-9)
+    a = 3.0e-3
+    idx = np.arange(n)
+    nodes = np.stack([idx % k, (idx // k) % k, idx // (k * k)], axis=1).astype(np.float64) + 0.5
+    pos = nodes * a + np.random.default_rng(40).uniform(-5e-5, 5e-5, size=(n, 3))
+    H = np.eye(3) * (k * a)
     rng = np.random.default_rng(41)
     big = np.argsort(spec.radius)[-20_000:]
     ids = np.concatenate([rng.choice(n, size=24, replace=False), rng.choice(big, size=24, replace=False)])
-    out, spot, dt = _periodic_full_size(spec, squeeze, ids, 0.01, 42)
+    out, spot, dt = _periodic_full_size(spec, pos, H, ids, 0.01, 42)
     st, stats = out[0]
     assert stats["n_contacts_ss"] > 100_000
     _check_spot(out, spot, ids, spec, dt, spec.material.young * 2 * spec.radius.max())
