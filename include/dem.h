@@ -407,11 +407,14 @@ dem_status dem_get_timing(dem_scene* s, const char* name, double* avg_ms, int64_
  * (key: GPU architecture, precision, batched/periodic, log2 of the sphere
  * and candidate counts, number of scenes) and applies the stored setting;
  * without an entry it times `probe_steps` ordinary steps per candidate
- * setting, trying block sizes 128..1024, chunks 16/32/64 and Verlet factors
- * 0.25/0.5/1 one knob at a time, keeps the fastest and appends it to the
- * cache (NULL or "" = no cache).  The probe steps advance the simulation
- * like any other steps.  dem_set_tuning on a batch view is refused: use the
- * batch calls. */
+ * setting, trying Verlet factors 0.05/0.1/0.25/0.5/1, block sizes
+ * 128..1024 and chunks 16/32/64 one knob at a time, keeps the fastest and
+ * appends it to the cache (NULL or "" = no cache).  A setting is charged its
+ * broad phase at its rate: the window's time without its broad-phase runs,
+ * plus the last run's cost over the steps between runs, estimated from the
+ * growth of the largest Verlet account.  The probe steps advance the
+ * simulation like any other steps.  dem_set_tuning on a batch view is
+ * refused: use the batch calls. */
 dem_status dem_get_tuning(dem_scene* s, dem_tuning* out);
 dem_status dem_set_tuning(dem_scene* s, const dem_tuning* t);
 dem_status dem_autotune(dem_scene* s, int64_t probe_steps, const char* cache_path, dem_tuning* out);

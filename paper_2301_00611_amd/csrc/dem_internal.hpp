@@ -500,6 +500,9 @@ void launch_integrate(const StepArgs* args, int parity, int grid, int precision,
 // controlled cell is on and the step is one of its updates) the
 // controller, from the contact and integrate kernels' partial sums.
 void launch_cell_update(const StepArgs* args, int parity, hipStream_t st);
+// largest Verlet account over the bodies, as the bits of a double, into
+// *out (which the caller zeroes)
+void launch_max_account(const Bodies& b, int n, unsigned long long* out, hipStream_t st);
 // first reduction level of the controller's partial sums (update steps only)
 void launch_ctrl_reduce(const StepArgs* args, int parity, hipStream_t st);
 void launch_body_forces(const StepArgs& a, int precision, double* f3, double* t3, hipStream_t st);

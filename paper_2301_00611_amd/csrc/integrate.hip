@@ -623,6 +623,22 @@ void launch_integrate(const StepArgs* args, int parity, int grid, int precision,
         launch_kind<DEM_FP64, false>(args, parity, grid, batched, periodic, block, st, ev0, ev1);
 }
 
+// Largest Verlet account (non-affine displacement since the last broad-phase
+// run, the fourth word of vm) over the bodies: wave maxima, then an integer
+// maximum on the bits (non-negative doubles order like their bits).
+__global__ void __launch_bounds__(256) k_max_account(Bodies b, int n, unsigned long long* __restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double v = i < n ? b.vm[i].w : 0.0;
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(v));
+}
+
+void launch_max_account(const Bodies& b, int n, unsigned long long* out, hipStream_t st)
+{
+    if (n > 0) hipLaunchKernelGGL(k_max_account, dim3((n + 255) / 256), dim3(256), 0, st, b, n, out);
+}
+
 void launch_ctrl_reduce(const StepArgs* args, int parity, hipStream_t st)
 {
     hipLaunchKernelGGL(k_ctrl_reduce, dim3(kCtrlReduceGrid), dim3(kCtrlReduceBlock), 0, st, args, parity);
