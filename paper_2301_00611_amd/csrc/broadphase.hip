@@ -605,7 +605,8 @@ __global__ void __launch_bounds__(kBlock) k_carry_find(PairBuildArgs a, int old_
     }
     bool touched = false;
     if (found >= 0) {
-        const HistRec h = a.hist_old.h[found];
+        const HistRec h = a.hist_f32 ? widen(reinterpret_cast<const HistRec32*>(a.hist_old.h)[found])
+                                     : a.hist_old.h[found];
         touched = h.nx != 0.0 || h.ny != 0.0 || h.nz != 0.0;
     }
     a.found[k] = found;
@@ -638,7 +639,11 @@ __global__ void __launch_bounds__(kBlock) k_partition(PairBuildArgs a)
     a.pr.cell[pos] = a.hist_new.cell[k];
     a.pr.pid[pos] = a.hist_new.pid[k];
     const int32_t f = a.found[k];
-    a.pr.h[pos] = f >= 0 ? a.hist_old.h[f] : HistRec{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (a.hist_f32)
+        reinterpret_cast<HistRec32*>(a.pr.h)[pos] =
+            f >= 0 ? reinterpret_cast<const HistRec32*>(a.hist_old.h)[f] : HistRec32{};
+    else
+        a.pr.h[pos] = f >= 0 ? a.hist_old.h[f] : HistRec{};
     a.pr.real[pos] = touched ? 1 : 0;
     a.hist_new.map[k] = (int32_t)pos;
 }

@@ -158,7 +158,8 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
         const gptr<const double4> wv = glb<const double4>(a.bod.w);
         const gptr<const uint16_t> mat = glb<const uint16_t>(a.bod.mat);
         const gptr<uint8_t> preal = glb(a.pr.real);
-        const gptr<HistRec> hist = glb(a.pr.h);
+        using H = typename HistOf<PREC>::T;
+        const gptr<H> hist = glb(reinterpret_cast<H*>(a.pr.h));
         const int s = BATCHED ? (int)glb<const uint16_t>(a.bod.scene)[sb] : 0;
         // an unbatched scene (periodic included) reads the descriptor's own
         // copy of its parameters: uniform, read-only here, so scalar loads
@@ -257,7 +258,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
         if (!real) {
             // the contact is erased: drop its history (once), no force
             if (was_real) {
-                hist[k] = HistRec{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                hist[k] = H{};
                 preal[k] = 0;
             }
         } else {
@@ -265,7 +266,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
             // bodies' velocities and spins, the history, the materials
             const double4 va = vm[s1], wa = wv[s1];
             const double4 vb = vm[sb], wb = wv[sb];
-            const HistRec hold = hist[k];
+            const H hold = hist[k];
             const Material M1 = glb<const Material>(a.mats)[m1];
             const Material M2 = glb<const Material>(a.mats)[m2];
             const double tanphi64 = glb<const double>(a.tanphi)[m1 * a.nmat + m2];
@@ -382,7 +383,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
             const V3<R> F = fn_mag * n + fsr;
             const V3<R> tau = cross(n, F);
 
-            hist[k] = HistRec{fs64.x, fs64.y, fs64.z, pen, (double)n.x, (double)n.y, (double)n.z, (double)fn_mag};
+            if constexpr (PREC == DEM_FP32_MIXED)
+                hist[k] = H{fs64.x, fs64.y, fs64.z, pen, (float)n.x, (float)n.y, (float)n.z, (float)fn_mag};
+            else
+                hist[k] = H{fs64.x, fs64.y, fs64.z, pen, (double)n.x, (double)n.y, (double)n.z, (double)fn_mag};
             // the force record as three pairs (a record starts on an 8-byte
             // (FP32) or 16-byte (FP64) boundary of a 256-byte aligned array);
             // the FP64 linear law's integrate kernel reads the history instead

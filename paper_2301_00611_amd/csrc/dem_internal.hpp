@@ -222,6 +222,37 @@ struct HistRec {
     double fn;                // signed normal force on #2 along n: k_n pen (linear law), k_n pen - c_n u_n (visco-elastic)
 };
 
+// The FP32-mixed history record (48 bytes): the shear force and the overlap
+// in FP64 as in FP64 mode, the normal and the normal force in FP32 (their
+// precision in this mode, so nothing is lost by storing them narrower).
+struct HistRec32 {
+    double fsx, fsy, fsz;
+    double pen;
+    float nx, ny, nz;
+    float fn;
+};
+static_assert(sizeof(HistRec) == 64 && sizeof(HistRec32) == 48, "history record sizes");
+template <int PREC>
+struct HistOf {
+    using T = HistRec;
+};
+template <>
+struct HistOf<DEM_FP32_MIXED> {
+    using T = HistRec32;
+};
+inline size_t hist_bytes(int precision) { return precision == DEM_FP32_MIXED ? sizeof(HistRec32) : sizeof(HistRec); }
+__host__ __device__ inline HistRec widen(const HistRec& h) { return h; }
+__host__ __device__ inline HistRec widen(const HistRec32& h)
+{
+    return HistRec{h.fsx, h.fsy, h.fsz, h.pen, (double)h.nx, (double)h.ny, (double)h.nz, (double)h.fn};
+}
+// record k of a history array of the precision's layout, widened
+template <int PREC>
+__device__ inline HistRec hist_load(const HistRec* base, size_t k)
+{
+    return widen(reinterpret_cast<const typename HistOf<PREC>::T*>(base)[k]);
+}
+
 // Candidate pairs after a broad-phase run, the pairs that touched at the
 // last evaluation first (a stable partition of the owner-sorted order), so
 // that the contact kernel's touching pairs, their history and force records
@@ -232,7 +263,7 @@ struct Pairs {
     int32_t *cell;            // packed image of #2 (periodic), 0 otherwise
     int32_t *pid;             // id of the non-owner partner (for history carry-over)
     uint8_t *real;            // 1 when the pair touched at the last evaluation
-    HistRec *h;               // history
+    HistRec *h;               // history (HistRec32 records in FP32-mixed mode: see HistOf)
     // force on #2 and n x F of the last step, one record of kForceWords
     // values per pair (one contiguous gather per real row entry); written
     // only where the history record is not enough (see uses_force_records)
@@ -471,6 +502,7 @@ struct PairBuildArgs {
     int32_t nent;
     int32_t npairs;
     int32_t has_old;
+    int32_t hist_f32;          // history records are HistRec32 (FP32-mixed)
 };
 // canonical pair arrays and rows (pair_build), history lookup (carry_find),
 // then, after the host scans `flag`, the partition into the final arrays

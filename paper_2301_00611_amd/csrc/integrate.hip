@@ -541,7 +541,7 @@ __global__ void __launch_bounds__(kMeasureBlock) k_body_measures(StepArgs a, int
         for (int e = beg; e < end; ++e) {
             const uint32_t k = a.rows.ent[e] & kPairMask;
             if (!a.pr.real[k]) continue;
-            const HistRec h = a.pr.h[k];
+            const HistRec h = hist_load<PREC>(a.pr.h, k);
             const double n[3] = {h.nx, h.ny, h.nz};
             const int sa = a.pr.a[k], sb = a.pr.b[k];
             const bool wall = sa < 0;

@@ -123,7 +123,7 @@ struct PairSet {
         n = std::max<size_t>(n, 1);
         for (DBuf* d : {&a, &b, &cell, &pid, &hpid, &hcell, &hmap}) d->ensure(n * 4);
         real.ensure(n);
-        hist.ensure(n * sizeof(HistRec));
+        hist.ensure(n * hist_bytes(fp32 ? DEM_FP32_MIXED : DEM_FP64));
         frec.ensure(n * kForceWords * (fp32 ? sizeof(float) : sizeof(double)));
         cap = n;
     }
@@ -1081,6 +1081,7 @@ struct World {
             pb.nent = (int)nent;
             pb.npairs = (int)np;
             pb.has_old = (OP.cap > 0 && OP.own_begin.p && old_ngids > 0) ? 1 : 0;
+            pb.hist_f32 = precision == DEM_FP32_MIXED ? 1 : 0;
             launch_pair_build(pb, stream);
             launch_carry_find(pb, stream, std::min(old_ngids, ng));
             // touching pairs first: ranks from a scan of the carried flags
@@ -1705,8 +1706,15 @@ struct World {
         gi(P.cell, p.cell);
         {
             std::vector<HistRec> h(n);
-            if (n) HIPC(hipMemcpyAsync(h.data(), P.hist.p, sizeof(HistRec) * n, hipMemcpyDeviceToHost, stream));
-            HIPC(hipStreamSynchronize(stream));
+            if (precision == DEM_FP32_MIXED) {
+                std::vector<HistRec32> h32(n);
+                if (n) HIPC(hipMemcpyAsync(h32.data(), P.hist.p, sizeof(HistRec32) * n, hipMemcpyDeviceToHost, stream));
+                HIPC(hipStreamSynchronize(stream));
+                for (size_t k = 0; k < n; ++k) h[k] = widen(h32[k]);
+            } else {
+                if (n) HIPC(hipMemcpyAsync(h.data(), P.hist.p, sizeof(HistRec) * n, hipMemcpyDeviceToHost, stream));
+                HIPC(hipStreamSynchronize(stream));
+            }
             for (auto* v : {&p.fsx, &p.fsy, &p.fsz, &p.nx, &p.ny, &p.nz, &p.pen, &p.fn}) v->resize(n);
             for (size_t k = 0; k < n; ++k) {
                 p.pen[k] = h[k].pen;
@@ -2335,10 +2343,14 @@ struct World {
         P.own_count.ensure(4 * (size_t)std::max(ng, 1));
         std::vector<int32_t> pid(m), cell(m);
         std::vector<HistRec> h(m);
+        std::vector<HistRec32> h32(precision == DEM_FP32_MIXED ? m : 0);
         for (size_t i = 0; i < m; ++i) {
             pid[i] = recs[i].partner;
             cell[i] = recs[i].cell;
             h[i] = HistRec{recs[i].fs[0], recs[i].fs[1], recs[i].fs[2], 0.0, recs[i].n[0], recs[i].n[1], recs[i].n[2], 0.0};
+            if (!h32.empty())
+                h32[i] = HistRec32{recs[i].fs[0], recs[i].fs[1], recs[i].fs[2], 0.0, (float)recs[i].n[0],
+                                   (float)recs[i].n[1], (float)recs[i].n[2], 0.0f};
         }
         HIPC(hipMemcpyAsync(P.own_begin.p, ob.data(), 4 * (size_t)ng, hipMemcpyHostToDevice, stream));
         HIPC(hipMemcpyAsync(P.own_count.p, oc.data(), 4 * (size_t)ng, hipMemcpyHostToDevice, stream));
@@ -2348,7 +2360,10 @@ struct World {
             HIPC(hipMemcpyAsync(P.hpid.p, pid.data(), 4 * m, hipMemcpyHostToDevice, stream));
             HIPC(hipMemcpyAsync(P.hcell.p, cell.data(), 4 * m, hipMemcpyHostToDevice, stream));
             HIPC(hipMemcpyAsync(P.hmap.p, ident.data(), 4 * m, hipMemcpyHostToDevice, stream));
-            HIPC(hipMemcpyAsync(P.hist.p, h.data(), sizeof(HistRec) * m, hipMemcpyHostToDevice, stream));
+            if (h32.empty())
+                HIPC(hipMemcpyAsync(P.hist.p, h.data(), sizeof(HistRec) * m, hipMemcpyHostToDevice, stream));
+            else
+                HIPC(hipMemcpyAsync(P.hist.p, h32.data(), sizeof(HistRec32) * m, hipMemcpyHostToDevice, stream));
         }
         HIPC(hipStreamSynchronize(stream));
         old_ngids = ng;

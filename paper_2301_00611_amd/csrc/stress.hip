@@ -36,7 +36,7 @@ __device__ inline void pair_force(const StepArgs& a, int k, double* F)
     F[0] = F[1] = F[2] = 0.0;
     if (!a.pr.real[k]) return;
     if (!a.use_frec) {
-        const HistRec h = a.pr.h[k];
+        const HistRec h = hist_load<PREC>(a.pr.h, k);
         F[0] = h.fn * h.nx + h.fsx;
         F[1] = h.fn * h.ny + h.fsy;
         F[2] = h.fn * h.nz + h.fsz;
@@ -85,7 +85,7 @@ __device__ inline void network_terms(const StepArgs& a, int k, int scene, double
     s[12] = sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]);
     s[13] = 1.0;
     if (sa < 0) return;
-    const HistRec h = P.h[k];
+    const HistRec h = hist_load<PREC>(P.h, k);
     const double n[3] = {h.nx, h.ny, h.nz};
     const double fn[3] = {F[0] - h.fsx, F[1] - h.fsy, F[2] - h.fsz};
     const double r1 = B.xr[sa].w, r2 = B.xr[sb].w;
