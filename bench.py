@@ -173,33 +173,48 @@ def _workload_spec(name, n, seed=0):
     return getattr(scenes, PERIODIC_WORKLOADS[name][0])(n=n, seed=seed)
 
 
-def prepare_periodic(name, n, seed=0, target_pressure=1e3, log=None):
+def prepare_periodic(name, n, seed=0, target_pressure=1e3, log=None, cache=None):
     """Unmeasured preparation of a periodic workload: its lattice cloud of
     n / tile^3 spheres compressed frictionless (friction 0, same stiffness
     and damping) by a schedule of compressions and velocity resets to a
     jammed packing, settled at a mean stress of -target_pressure by the
     library's isotropic compressor, then replicated tile^3 times into a cell
-    tile times wider (the same periodic packing, n spheres).  Returns the
-    spec of the n-sphere workload and its prepared state (positions,
-    velocities, spins, cell)."""
+    tile times wider (the same periodic packing, n spheres).  With `cache`
+    (an .npz path) the small packing is loaded from it when present, else
+    stored there after preparing it.  Returns the spec of the n-sphere
+    workload and its prepared state (positions, velocities, spins, cell)."""
     import numpy as np
     from paper_2301_00611_amd.prepare import jam_isotropic, mean_pressure, settle_iso, tile_periodic
     tile = PERIODIC_WORKLOADS[name][2]
     n0 = n // tile ** 3
-    spec0 = _workload_spec(name, n0, seed)
-    vs = float((4.0 / 3.0 * math.pi * spec0.radius ** 3).sum())
     t0 = time.perf_counter()
-    g = _periodic_scene(spec0.hsize, np.zeros((3, 3)), spec0, spec0.pos, None, None, 0, friction=0.0)
-    rec = jam_isotropic(g, spec0.dt_factor * g.pwave_dt(), vs, target_pressure, log=log)
-    rec["settle"] = settle_iso(g, target_pressure, log=log)
-    g.step(1)
-    rec["pressure_settled"] = mean_pressure(g)
-    rec["coordination_settled"] = g.stats()["coordination"]
-    st = g.get_state()
-    H, _ = g.get_cell()
-    rec["solid_fraction"] = vs / abs(np.linalg.det(H))
-    g.close()
-    pos, rad, vel, ang, H2 = tile_periodic(st["pos"], spec0.radius, st["vel"], st["angvel"], H, (tile,) * 3)
+    if cache and os.path.exists(cache):
+        d = np.load(cache)
+        if len(d["radius"]) != n0:
+            raise ValueError(f"{cache} holds {len(d['radius'])} spheres, the {name} preparation {n0}")
+        st = {"pos": d["pos"], "vel": d["vel"], "angvel": d["angvel"]}
+        radius, H = d["radius"], d["H"]
+        rec = {"loaded_from": cache, "pressure_settled": float(d["pressure"]),
+               "coordination_settled": float(d["coordination"]), "solid_fraction": float(d["solid_fraction"])}
+    else:
+        spec0 = _workload_spec(name, n0, seed)
+        radius = spec0.radius
+        vs = float((4.0 / 3.0 * math.pi * radius ** 3).sum())
+        g = _periodic_scene(spec0.hsize, np.zeros((3, 3)), spec0, spec0.pos, None, None, 0, friction=0.0)
+        rec = jam_isotropic(g, spec0.dt_factor * g.pwave_dt(), vs, target_pressure, log=log)
+        rec["settle"] = settle_iso(g, target_pressure, log=log)
+        g.step(1)
+        rec["pressure_settled"] = mean_pressure(g)
+        rec["coordination_settled"] = g.stats()["coordination"]
+        st = g.get_state()
+        H, _ = g.get_cell()
+        rec["solid_fraction"] = vs / abs(np.linalg.det(H))
+        g.close()
+        if cache:
+            np.savez(cache, pos=st["pos"], vel=st["vel"], angvel=st["angvel"], radius=radius, H=H,
+                     pressure=rec["pressure_settled"], coordination=rec["coordination_settled"],
+                     solid_fraction=rec["solid_fraction"])
+    pos, rad, vel, ang, H2 = tile_periodic(st["pos"], radius, st["vel"], st["angvel"], H, (tile,) * 3)
     spec = _workload_spec(name, 16, seed)  # parameters of the workload
     spec.pos, spec.radius = pos, rad
     rec["prepared_spheres"] = n0
@@ -242,16 +257,21 @@ def _fp32_vs_fp64_one_step(spec, st, H, L):
     return err
 
 
-def dense_run(spec, st, H, L, precision, steps, warmup, timing_steps=1000, probe_steps=100, log=None):
+def dense_run(spec, st, H, L, precision, steps, warmup, timing_steps=1000, probe_steps=100, log=None,
+              fixed_tuning=None):
     """One precision on the prepared packing: the autotuner's setting (found
-    on a copy of the state, which it advances), then `warmup` untimed steps
-    and exactly `steps` timed steps on a fresh scene, then `timing_steps`
-    more with kernel events (per-kernel durations, broad-phase runs)."""
+    on a copy of the state, which it advances; or `fixed_tuning`), then
+    `warmup` untimed steps and exactly `steps` timed steps on a fresh scene,
+    then `timing_steps` more with kernel events (per-kernel durations,
+    broad-phase runs)."""
     import torch
     n = len(spec.radius)
-    g = _periodic_scene(H, L, spec, st["pos"], st["vel"], st["angvel"], precision)
-    tune = g.autotune(probe_steps=probe_steps)
-    g.close()
+    if fixed_tuning:
+        tune = dict(fixed_tuning)
+    else:
+        g = _periodic_scene(H, L, spec, st["pos"], st["vel"], st["angvel"], precision)
+        tune = g.autotune(probe_steps=probe_steps)
+        g.close()
     tuning = {k: v for k, v in tune.items() if k != "ms_per_step"}
     g = _periodic_scene(H, L, spec, st["pos"], st["vel"], st["angvel"], precision)
     g.set_tuning(**tuning)
@@ -311,7 +331,7 @@ def dense_run(spec, st, H, L, precision, steps, warmup, timing_steps=1000, probe
 
 
 def periodic_leg(name="periodic_compression", steps=2000, warmup=20, n=None, log=None, prepared=None,
-                 with_controller=True, with_stats=True):
+                 with_controller=True, with_stats=True, cache=None):
     """A dense periodic workload (C3: isotropic compression at 0.01/s; C5:
     bidisperse simple shear at 1/s), FP64 vs FP32-mixed on the same prepared
     packing: throughput of each, kernel durations and rooflines, and the
@@ -322,7 +342,7 @@ def periodic_leg(name="periodic_compression", steps=2000, warmup=20, n=None, log
     log = log or (lambda m: None)
     n = n or PERIODIC_WORKLOADS[name][1]
     if prepared is None:
-        prepared = prepare_periodic(name, n, log=log)
+        prepared = prepare_periodic(name, n, log=log, cache=cache)
     spec, st, H, rec = prepared
     n = len(spec.radius)
     L = spec.velgrad
@@ -430,28 +450,26 @@ def cpu_baseline(budget_s=5.0, repeats=3, n=4096):
     }
 
 
+def parse_tuning(text):
+    """--tuning "block_contact,block_integrate,chunk,verlet_factor" -> dict (None: autotune)."""
+    if not text:
+        return None
+    bc, bi, ch, vf = text.split(",")
+    return {"block_contact": int(bc), "block_integrate": int(bi), "chunk": int(ch), "verlet_factor": float(vf)}
+
+
 def headline(args, log):
     """The N=1 line: C5 at FP64 (value), FP32-mixed beside it, the roofline
     of the dominant kernel, the CPU oracle baseline."""
     name = "periodic_shear"
     n = PERIODIC_WORKLOADS[name][1]
-    path = args.prepared_state
-    if path and os.path.exists(path):
-        import numpy as np
-        d = np.load(path)
-        spec = _workload_spec(name, 16)
-        spec.pos, spec.radius = d["pos"], d["radius"]
-        st = {"pos": d["pos"], "vel": d["vel"], "angvel": d["angvel"]}
-        H, rec = d["H"], {"loaded_from": path, "seconds": 0.0}
-    else:
-        log(f"preparing the {n}-sphere bidisperse packing (not timed)")
-        spec, st, H, rec = prepare_periodic(name, n, log=log)
-        if path:
-            import numpy as np
-            np.savez(path, pos=st["pos"], vel=st["vel"], angvel=st["angvel"], radius=spec.radius, H=H)
+    log(f"preparing the {n}-sphere bidisperse packing (not timed)")
+    spec, st, H, rec = prepare_periodic(name, n, log=log, cache=args.prepared_state)
     L = spec.velgrad
     log(f"prepared in {rec['seconds']:.1f} s: {_jsonable(rec)}")
-    r64 = dense_run(spec, st, H, L, 0, args.steps, args.warmup, timing_steps=args.timing_steps, log=log)
+    fixed = parse_tuning(args.tuning)
+    r64 = dense_run(spec, st, H, L, 0, args.steps, args.warmup, timing_steps=args.timing_steps, log=log,
+                    fixed_tuning=fixed)
     kern = r64["kernels_ms"]
     dom = max(("contact", "integrate"), key=lambda k: kern[k])
     rl = r64["rooflines"][dom]
@@ -491,7 +509,8 @@ def headline(args, log):
     if args.fp64_only:
         return out
     log("FP32-mixed on the same packing")
-    r32 = dense_run(spec, st, H, L, 1, args.steps, args.warmup, timing_steps=args.timing_steps, log=log)
+    r32 = dense_run(spec, st, H, L, 1, args.steps, args.warmup, timing_steps=args.timing_steps, log=log,
+                    fixed_tuning=fixed)
     out["fp32_mixed"] = r32
     out["fp32_vs_fp64_one_step"] = _fp32_vs_fp64_one_step(spec, st, H, L)
     return out
@@ -512,8 +531,11 @@ def main():
                              "facet_column", "viscel_column"),
                     help="headline: the N=1 line (default); the others run one leg alone")
     ap.add_argument("--prepared-state", default=None,
-                    help="headline: .npz holding the prepared packing (loaded if present, else written), so that "
-                         "profiled runs skip the preparation")
+                    help="headline and periodic legs: .npz holding the prepared packing before it is tiled (loaded "
+                         "if present, else written), so that profiled runs skip the preparation")
+    ap.add_argument("--tuning", default=None,
+                    help="headline: a fixed launch setting 'block_contact,block_integrate,chunk,verlet_factor' in "
+                         "place of the autotuner's (profiling runs)")
     ap.add_argument("--tuning-cache", default=None,
                     help="autotuner cache file for the column legs: reuse a stored setting, or store the one found")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -536,7 +558,8 @@ def main():
         return
     if args.workload in PERIODIC_WORKLOADS:
         out = periodic_leg(args.workload, steps=args.steps, warmup=args.warmup, log=log,
-                           with_controller=not args.no_extra, with_stats=not args.no_extra)
+                           with_controller=not args.no_extra, with_stats=not args.no_extra,
+                           cache=args.prepared_state)
         print(json.dumps(out), flush=True)
         return
     if args.workload == "batched":

@@ -645,17 +645,28 @@ __global__ void __launch_bounds__(kBlock) k_partition(PairBuildArgs a)
     else
         a.pr.h[pos] = f >= 0 ? a.hist_old.h[f] : HistRec{};
     a.pr.real[pos] = touched ? 1 : 0;
+    a.pr.ea[pos] = -1;  // set below from the rows (stays -1 for a boundary pair)
+    a.pr.eb[pos] = -1;
     a.hist_new.map[k] = (int32_t)pos;
 }
 
-// Row entries: canonical pair index -> partitioned index (the side bit kept).
+// Row entries: canonical pair index -> partitioned index (the side bit kept,
+// the touched bit from the carried history); each pair learns where its
+// entries sit, so that the contact kernel can update their touched bits.
 __global__ void __launch_bounds__(kBlock) k_remap_rows(PairBuildArgs a)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= a.nent) return;
     const uint32_t u = a.rows.ent[e];
     const uint32_t k = u & kPairMask;
-    if (k < (uint32_t)a.npairs) a.rows.ent[e] = (u & kNegSign) | (uint32_t)a.hist_new.map[k];
+    if (k < (uint32_t)a.npairs) {
+        const uint32_t pos = (uint32_t)a.hist_new.map[k];
+        a.rows.ent[e] = (u & kNegSign) | (a.flag[k] ? kRealBit : 0u) | pos;
+        if (u & kNegSign)
+            a.pr.ea[pos] = e;
+        else
+            a.pr.eb[pos] = e;
+    }
 }
 
 inline int nblocks(long n) { return (int)((n + kBlock - 1) / kBlock); }

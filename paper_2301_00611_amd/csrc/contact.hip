@@ -96,6 +96,18 @@ __device__ inline int xcd_pair(int npairs)
     return k < p1 ? (int)k : -1;
 }
 
+// A pair that starts or stops touching rewrites its two row entries with
+// the new touched bit (a boundary pair has only #2's), so that the force sum
+// reads the state from the entry itself; the pair is #1's and adds -F there.
+__device__ inline void set_row_bits(const StepArgs& a, int k, bool real)
+{
+    const gptr<uint32_t> ent = glb(a.rows.ent);
+    const int32_t ea = glb<const int32_t>(a.pr.ea)[k], eb = glb<const int32_t>(a.pr.eb)[k];
+    const uint32_t v = (uint32_t)k | (real ? kRealBit : 0u);
+    if (ea >= 0) ent[ea] = v | kNegSign;
+    if (eb >= 0) ent[eb] = v;
+}
+
 struct ContactPartial {
     double el, plast;
     unsigned long long ss, sw;
@@ -260,6 +272,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
             if (was_real) {
                 hist[k] = H{};
                 preal[k] = 0;
+                set_row_bits(a, k, false);
             }
         } else {
             // ---- every load of a touching pair, issued together: both
@@ -401,7 +414,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
                 q[1] = make_double2((double)F.z, (double)tau.x);
                 q[2] = make_double2((double)tau.y, (double)tau.z);
             }
-            if (!was_real) preal[k] = 1;
+            if (!was_real) {
+                preal[k] = 1;
+                set_row_bits(a, k, true);
+            }
             if (wall)
                 part.sw = 1;
             else

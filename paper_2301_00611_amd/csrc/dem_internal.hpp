@@ -18,8 +18,12 @@
 namespace dem {
 
 constexpr int kMaxWallsPerScene = 64;   // fixed boundaries (planes, boxes, facets) per scene
-constexpr uint32_t kNegSign = 0x80000000u;  // row entry: body is #1, adds -F
-constexpr uint32_t kPairMask = 0x7fffffffu;
+// A row entry: the pair's index, the body's side and whether the pair
+// touched at its last evaluation (kept current by the contact kernel, so
+// that a body's force sum reads no flag of its own).
+constexpr uint32_t kNegSign = 0x80000000u;  // body is #1, adds -F
+constexpr uint32_t kRealBit = 0x40000000u;  // the pair touches
+constexpr uint32_t kPairMask = 0x3fffffffu;
 
 // Per-scene parameters, read by the kernels through the body's scene index.
 struct SceneParams {
@@ -263,6 +267,8 @@ struct Pairs {
     int32_t *cell;            // packed image of #2 (periodic), 0 otherwise
     int32_t *pid;             // id of the non-owner partner (for history carry-over)
     uint8_t *real;            // 1 when the pair touched at the last evaluation
+    int32_t *ea;              // index of the pair's entry in #1's row (-1: #1 is a boundary)
+    int32_t *eb;              // index of the pair's entry in #2's row
     HistRec *h;               // history (HistRec32 records in FP32-mixed mode: see HistOf)
     // force on #2 and n x F of the last step, one record of kForceWords
     // values per pair (one contiguous gather per real row entry); written

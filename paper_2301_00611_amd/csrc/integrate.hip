@@ -39,11 +39,10 @@ __device__ inline void body_sum(const StepArgs& a, int beg, int end, double r, d
     F[0] = F[1] = F[2] = 0.0;
     T[0] = T[1] = T[2] = 0.0;
     const gptr<const uint32_t> ent = glb<const uint32_t>(a.rows.ent);
-    const gptr<const uint8_t> real = glb<const uint8_t>(a.pr.real);
     // entries are taken four at a time so that their loads are in flight
     // together (no branch between them: a position past the row's end reads
     // the row's last entry again and is then ignored); they are still added
-    // one by one in row order
+    // one by one in row order.  An entry carries its pair's touched bit.
     constexpr int kB = 4;
     for (int e0 = beg; e0 < end; e0 += kB) {
         uint32_t u[kB];
@@ -51,8 +50,7 @@ __device__ inline void body_sum(const StepArgs& a, int beg, int end, double r, d
         for (int j = 0; j < kB; ++j) u[j] = ent[min(e0 + j, end - 1)];
         for (int j = 0; j < kB; ++j) {
             const uint32_t k = u[j] & kPairMask;
-            const bool flag = real[k < (uint32_t)a.npairs ? k : 0u] != 0;
-            use[j] = (e0 + j < end) && k < (uint32_t)a.npairs && flag;
+            use[j] = (e0 + j < end) && k < (uint32_t)a.npairs && (u[j] & kRealBit) != 0u;
         }
         // a record is read as three pairs (it starts on an 8-byte (FP32) or
         // 16-byte (FP64) boundary of a 256-byte aligned array)

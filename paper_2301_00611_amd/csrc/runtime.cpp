@@ -114,14 +114,14 @@ struct BodySet {
 };
 
 struct PairSet {
-    DBuf a, b, cell, pid, real, hist, frec;     // partitioned order (touching pairs first)
+    DBuf a, b, cell, pid, real, ea, eb, hist, frec;  // partitioned order (touching pairs first)
     DBuf hpid, hcell, hmap;                     // canonical (owner-sorted) order, for the next run's lookup
     DBuf own_begin, own_count;  // by gid, into the canonical order
     size_t cap = 0;
     void ensure(size_t n, bool fp32)
     {
         n = std::max<size_t>(n, 1);
-        for (DBuf* d : {&a, &b, &cell, &pid, &hpid, &hcell, &hmap}) d->ensure(n * 4);
+        for (DBuf* d : {&a, &b, &cell, &pid, &ea, &eb, &hpid, &hcell, &hmap}) d->ensure(n * 4);
         real.ensure(n);
         hist.ensure(n * hist_bytes(fp32 ? DEM_FP32_MIXED : DEM_FP64));
         frec.ensure(n * kForceWords * (fp32 ? sizeof(float) : sizeof(double)));
@@ -135,6 +135,8 @@ struct PairSet {
         p.cell = cell.as<int32_t>();
         p.pid = pid.as<int32_t>();
         p.real = real.as<uint8_t>();
+        p.ea = ea.as<int32_t>();
+        p.eb = eb.as<int32_t>();
         p.h = hist.as<HistRec>();
         p.frec = frec.as<double>();
         p.frecf = frec.as<float>();
@@ -153,7 +155,8 @@ struct PairSet {
     }
     void release()
     {
-        for (DBuf* d : {&a, &b, &cell, &pid, &real, &hist, &frec, &hpid, &hcell, &hmap, &own_begin, &own_count})
+        for (DBuf* d : {&a, &b, &cell, &pid, &real, &ea, &eb, &hist, &frec, &hpid, &hcell, &hmap, &own_begin,
+                        &own_count})
             d->release();
         cap = 0;
     }
@@ -1042,6 +1045,7 @@ struct World {
             HIPC(hipMemcpyAsync(&np, d_total.p, 4, hipMemcpyDeviceToHost, stream));
             HIPC(hipStreamSynchronize(stream));
             HIPC(hipGetLastError());
+            if (np >= kPairMask) fail(DEM_ENOMEM, "too many candidate pairs");
             npairs_new = (int)np;
             n_candidates = np;
             // new pair set
