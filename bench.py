@@ -36,13 +36,14 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 
 # Algorithmic bytes (what the method must move):
-#   contact kernel: per body gathered once x, v, w, r = 80 B (FP32-mixed: x
-#   in FP64, v, w, r in FP32 = 52 B); per real contact ids 8 + shear force
-#   r/w 48 + previous normal r/w 48 = 104 B (FP32-mixed: normal in FP32,
-#   80 B); per non-real candidate its ids, 8 B.
+#   contact kernel: per body gathered once x, v, w, r = 80 B (FP64 in both
+#   precisions: the FP32-mixed kernel forms the relative velocity from the
+#   FP64 velocities); per real contact ids 8 + shear force r/w 48 + previous
+#   normal r/w 48 = 104 B (FP32-mixed: normal in FP32, 80 B); per non-real
+#   candidate its ids, 8 B.
 #   integrate kernel, per body: read x, v, w, q, r, m (14 doubles) + material
 #   and blocked bytes = 114 B; write x, v, w, q (13 doubles) = 104 B.
-CONTACT_BYTES = {0: (80, 104, 8), 1: (52, 80, 8)}
+CONTACT_BYTES = {0: (80, 104, 8), 1: (80, 80, 8)}
 INTEGRATE_BYTES_PER_BODY = 218
 
 
@@ -733,7 +734,7 @@ def _build_batch(spec, dt, precision=0):
 
 def _time_batch(b, steps):
     import torch
-    b.step(1)
+    b.step(0)  # a pending broad-phase run, outside the timed region
     s0 = b.stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -744,12 +745,25 @@ def _time_batch(b, steps):
     return t, s1["contact_steps"] - s0["contact_steps"]
 
 
-def batched_leg(n_scenes=512, steps=2000, sequential_steps=200, log=None):
+def _batch_kernels(b, steps):
+    """Per-kernel durations of `steps` more batch steps with kernel events."""
+    v = b.scene(0)
+    v.set_timing(True)
+    b.step(steps)
+    out = {k: v.get_timing(k)[0] for k in ("contact", "integrate", "rebuild")}
+    v.set_timing(False)
+    return out
+
+
+def batched_leg(n_scenes=512, steps=2000, sequential_steps=None, log=None):
     """C4: 512 independent deposition scenes (log-uniform sizes 500..50,000,
     per-scene friction and damping) stepped together, FP64 and FP32-mixed:
     scene-steps/s with the default launch setting and with the autotuner's
-    (its probe steps are not timed), against the same scenes stepped one
-    after another as single FP64 scenes (`sequential_steps` steps each)."""
+    (its probe steps are not timed), the kernel durations and the integrate
+    kernel's roofline, against the same scenes stepped one after another as
+    single FP64 scenes (`sequential_steps` steps each, by default as many as
+    the batch)."""
+    sequential_steps = sequential_steps or steps
     from paper_2301_00611_amd import dem
     from paper_2301_00611_amd.scenes import batched_deposition
     log = log or (lambda m: None)
@@ -762,10 +776,14 @@ def batched_leg(n_scenes=512, steps=2000, sequential_steps=200, log=None):
         t_def, c_def = _time_batch(b, steps)
         tune = b.autotune(probe_steps=100)
         t_tun, c_tun = _time_batch(b, steps)
+        kern = _batch_kernels(b, min(steps, 500))
         b.close()
+        ib = INTEGRATE_BYTES_PER_BODY * nbodies
         out[name] = {"value": n_scenes * steps / t_tun, "seconds": t_tun, "body_steps_per_s": nbodies * steps / t_tun,
                      "contact_steps_per_s": c_tun / t_tun, "default_setting_value": n_scenes * steps / t_def,
-                     "tuning": tune}
+                     "tuning": tune, "kernels_ms": kern,
+                     "integrate_roofline": {"bytes": ib, "frac": (ib / (kern["integrate"] * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                                                  if kern["integrate"] > 0 else None)}}
         log(f"batched {name}: {out[name]}")
     out["value"] = out["fp64"]["value"]
     # the same scenes one after another through the single-scene FP64 path
@@ -778,7 +796,7 @@ def batched_leg(n_scenes=512, steps=2000, sequential_steps=200, log=None):
             g.add_wall(w.axis, w.position, w.sense, m)
         g.add_spheres(s.pos, s.radius, default_mat=m)
         g.set_dt(dt)
-        g.step(1)
+        g.step(0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         g.step(sequential_steps)

@@ -614,11 +614,14 @@ __global__ void __launch_bounds__(kBlock) k_carry_find(PairBuildArgs a, int old_
 }
 
 // The stable partition, within each eighth [P_x, P_x+1) of the pairs
-// (P_x = x npairs / 8, the segment one XCD takes in the contact kernel):
-// touching pairs first, then the others, each group in canonical order; the
-// history moves with its pair, and the canonical -> final map is kept for
-// the next run.
+// (P_x = x npairs / 8, the segment one XCD takes in the contact kernel) and
+// within each chunk of kPartitionChunk pairs of it: touching pairs first,
+// then the others, each group in canonical order; the history moves with its
+// pair, and the canonical -> final map is kept for the next run.  Chunks keep
+// a body's touching and non-touching pairs close in time in the contact
+// kernel, so the positions the second group gathers are still cached.
 __device__ inline uint32_t segment_start(int x, int npairs) { return (uint32_t)(((int64_t)x * npairs) >> 3); }
+constexpr uint32_t kPartitionChunk = 1u << 14;
 
 __global__ void __launch_bounds__(kBlock) k_partition(PairBuildArgs a)
 {
@@ -628,7 +631,9 @@ __global__ void __launch_bounds__(kBlock) k_partition(PairBuildArgs a)
     if (x > 7) x = 7;
     while (x < 7 && (uint32_t)k >= segment_start(x + 1, a.npairs)) ++x;
     while (x > 0 && (uint32_t)k < segment_start(x, a.npairs)) --x;
-    const uint32_t p0 = segment_start(x, a.npairs), p1 = segment_start(x + 1, a.npairs);
+    const uint32_t x0 = segment_start(x, a.npairs), x1 = segment_start(x + 1, a.npairs);
+    const uint32_t p0 = x0 + (((uint32_t)k - x0) / kPartitionChunk) * kPartitionChunk;
+    const uint32_t p1 = min(p0 + kPartitionChunk, x1);
     const uint32_t s0 = a.flag_scan[p0];
     const uint32_t ntouch = a.flag_scan[p1] - s0;
     const uint32_t r = a.flag_scan[k] - s0;

@@ -29,20 +29,71 @@ __device__ inline int logical_block(int nb)
 
 __device__ inline double sgn(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
 
-// Resultant contact force and torque on slot i, in row order (ascending
-// partner id): the forces of its real pairs, negated where the body is #1.
-// FREC: from the force records (F on #2, n x F); otherwise from the history
-// records (FP64 linear law): F = fn n + Fs, n x F.
+// One touching pair as a row entry sees it: the force on #2 and n x F, from
+// the pair's force record (FREC: F on #2, n x F) or from its history record
+// (FP64 linear law: F = fn n + Fs).  Without contraction, so that every
+// walk over a row (one thread, or the wave together) gives the same bits.
 template <int PREC, bool FREC>
-__device__ inline void body_sum(const StepArgs& a, int beg, int end, double r, double* F, double* T)
+__device__ inline void pair_force(const StepArgs& a, uint32_t k, double* f)
 {
-    F[0] = F[1] = F[2] = 0.0;
-    T[0] = T[1] = T[2] = 0.0;
+#pragma clang fp contract(off)
+    if (!FREC) {
+        // the history record, one 64-byte segment read as two halves
+        const gptr<const double4> h = glb<const double4>(reinterpret_cast<const double4*>(a.pr.h)) + 2 * (size_t)k;
+        const double4 h0 = h[0], h1 = h[1];
+        const double fx = h1.w * h1.x + h0.x, fy = h1.w * h1.y + h0.y, fz = h1.w * h1.z + h0.z;
+        f[0] = fx;
+        f[1] = fy;
+        f[2] = fz;
+        f[3] = h1.y * fz - h1.z * fy;
+        f[4] = h1.z * fx - h1.x * fz;
+        f[5] = h1.x * fy - h1.y * fx;
+    } else if (PREC == DEM_FP32_MIXED) {
+        // a record is read as three pairs (it starts on an 8-byte boundary)
+        const gptr<const float2> q = glb<const float2>(reinterpret_cast<const float2*>(a.pr.frecf)) + 3 * (size_t)k;
+        for (int c = 0; c < 3; ++c) {
+            const float2 v = q[c];
+            f[2 * c] = v.x;
+            f[2 * c + 1] = v.y;
+        }
+    } else {
+        const gptr<const double2> q = glb<const double2>(reinterpret_cast<const double2*>(a.pr.frec)) + 3 * (size_t)k;
+        for (int c = 0; c < 3; ++c) {
+            const double2 v = q[c];
+            f[2 * c] = v.x;
+            f[2 * c + 1] = v.y;
+        }
+    }
+}
+
+// Adds one touching entry to the body's sums: the force negated where the
+// body is #1; both bodies of a pair feel -r_k (n x F) (lever arms r1 n and
+// -r2 n).
+__device__ inline void add_entry(uint32_t u, const double* f, double r, double* F, double* T)
+{
+#pragma clang fp contract(off)
+    if (u & kNegSign) {
+        F[0] += -f[0];
+        F[1] += -f[1];
+        F[2] += -f[2];
+    } else {
+        F[0] += f[0];
+        F[1] += f[1];
+        F[2] += f[2];
+    }
+    T[0] += -r * f[3];
+    T[1] += -r * f[4];
+    T[2] += -r * f[5];
+}
+
+// Entries [beg, end) of a row, added in row order (ascending partner id):
+// taken four at a time so that their loads are in flight together (no
+// branch between them: a position past the end reads the last entry again
+// and is then ignored).  An entry carries its pair's touched bit.
+template <int PREC, bool FREC>
+__device__ inline void row_walk(const StepArgs& a, int beg, int end, double r, double* F, double* T)
+{
     const gptr<const uint32_t> ent = glb<const uint32_t>(a.rows.ent);
-    // entries are taken four at a time so that their loads are in flight
-    // together (no branch between them: a position past the row's end reads
-    // the row's last entry again and is then ignored); they are still added
-    // one by one in row order.  An entry carries its pair's touched bit.
     constexpr int kB = 4;
     for (int e0 = beg; e0 < end; e0 += kB) {
         uint32_t u[kB];
@@ -52,55 +103,77 @@ __device__ inline void body_sum(const StepArgs& a, int beg, int end, double r, d
             const uint32_t k = u[j] & kPairMask;
             use[j] = (e0 + j < end) && k < (uint32_t)a.npairs && (u[j] & kRealBit) != 0u;
         }
-        // a record is read as three pairs (it starts on an 8-byte (FP32) or
-        // 16-byte (FP64) boundary of a 256-byte aligned array)
         double f[kB][kForceWords];
-        for (int j = 0; j < kB; ++j) {
-            const uint32_t k = u[j] & kPairMask;
-            if (!use[j]) continue;
-            if (!FREC) {
-                // the history record, one 64-byte segment read as two halves
-                const gptr<const double4> h = glb<const double4>(reinterpret_cast<const double4*>(a.pr.h)) + 2 * (size_t)k;
-                const double4 h0 = h[0], h1 = h[1];
-                const double fx = h1.w * h1.x + h0.x, fy = h1.w * h1.y + h0.y, fz = h1.w * h1.z + h0.z;
-                f[j][0] = fx;
-                f[j][1] = fy;
-                f[j][2] = fz;
-                f[j][3] = h1.y * fz - h1.z * fy;
-                f[j][4] = h1.z * fx - h1.x * fz;
-                f[j][5] = h1.x * fy - h1.y * fx;
-            } else if (PREC == DEM_FP32_MIXED) {
-                const gptr<const float2> q = glb<const float2>(reinterpret_cast<const float2*>(a.pr.frecf)) + 3 * (size_t)k;
-                for (int c = 0; c < 3; ++c) {
-                    const float2 v = q[c];
-                    f[j][2 * c] = v.x;
-                    f[j][2 * c + 1] = v.y;
-                }
-            } else {
-                const gptr<const double2> q = glb<const double2>(reinterpret_cast<const double2*>(a.pr.frec)) + 3 * (size_t)k;
-                for (int c = 0; c < 3; ++c) {
-                    const double2 v = q[c];
-                    f[j][2 * c] = v.x;
-                    f[j][2 * c + 1] = v.y;
-                }
-            }
+        for (int j = 0; j < kB; ++j)
+            if (use[j]) pair_force<PREC, FREC>(a, u[j] & kPairMask, f[j]);
+        for (int j = 0; j < kB; ++j)
+            if (use[j]) add_entry(u[j], f[j], r, F, T);
+    }
+}
+
+// Resultant contact force and torque on a slot whose row is [beg, end), in
+// row order: the forces of its touching pairs, negated where the body is #1.
+template <int PREC, bool FREC>
+__device__ inline void body_sum(const StepArgs& a, int beg, int end, double r, double* F, double* T)
+{
+    F[0] = F[1] = F[2] = 0.0;
+    T[0] = T[1] = T[2] = 0.0;
+    row_walk<PREC, FREC>(a, beg, end, r, F, T);
+}
+
+// The same sum in the integrate kernel, called by every lane of the wave.
+// A lane walks at most kSoloEntries entries of its row by itself; longer
+// rows (a large sphere among small ones has ~10x the entries of its
+// neighbours, and its lane would hold the whole wave) are finished by the
+// wave together, 64 entries at a time: each lane reads one entry and its
+// pair's record into the wave's slice of LDS, then the row's own lane adds
+// them in row order, with the same arithmetic as the walk.
+constexpr int kSoloEntries = 16;
+constexpr int kCoopWords = 64 * (kForceWords + 1);  // doubles per wave: 64 entries x 6, then 64 entry words
+template <int PREC, bool FREC>
+__device__ inline void body_sum_wave(const StepArgs& a, int beg, int end, double r, double* F, double* T,
+                                     double* lds)
+{
+    F[0] = F[1] = F[2] = 0.0;
+    T[0] = T[1] = T[2] = 0.0;
+    const int solo = min(end, beg + kSoloEntries);
+    row_walk<PREC, FREC>(a, beg, solo, r, F, T);
+    const int lane = threadIdx.x & 63;
+    uint32_t* lu = reinterpret_cast<uint32_t*>(lds + 64 * kForceWords);
+    int next = solo;
+    for (;;) {
+        const unsigned long long need = __ballot(next < end);
+        if (need == 0ull) break;
+        const int src = __builtin_ctzll(need);
+        const int c0 = __shfl(next, src, 64), c1 = __shfl(end, src, 64);
+        const int e = c0 + lane;
+        uint32_t u = 0u;
+        if (e < c1) u = glb<const uint32_t>(a.rows.ent)[e];
+        const uint32_t k = u & kPairMask;
+        const bool use = e < c1 && k < (uint32_t)a.npairs && (u & kRealBit) != 0u;
+        double f[kForceWords];
+        if (use) {
+            pair_force<PREC, FREC>(a, k, f);
+            for (int q = 0; q < kForceWords; ++q) lds[q * 64 + lane] = f[q];
         }
-        for (int j = 0; j < kB; ++j) {
-            if (!use[j]) continue;
-            if (u[j] & kNegSign) {
-                F[0] += -f[j][0];
-                F[1] += -f[j][1];
-                F[2] += -f[j][2];
-            } else {
-                F[0] += f[j][0];
-                F[1] += f[j][1];
-                F[2] += f[j][2];
+        lu[lane] = use ? u : 0u;
+        // the wave's own LDS writes are complete before its lanes read them
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (lane == src) {
+            const int n = min(64, c1 - c0);
+            for (int j = 0; j < n; ++j) {
+                const uint32_t uj = lu[j];
+                if (!(uj & kRealBit)) continue;
+                double fj[kForceWords];
+                for (int q = 0; q < kForceWords; ++q) fj[q] = lds[q * 64 + j];
+                add_entry(uj, fj, r, F, T);
             }
-            // both bodies of a pair feel -r_k (n x F) (lever arms r1 n and -r2 n)
-            T[0] += -r * f[j][3];
-            T[1] += -r * f[j][4];
-            T[2] += -r * f[j][5];
+            next = c0 + n;
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -151,6 +224,11 @@ __global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restr
     IntPartial part = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     bool bad = false;
     bool over = false;
+    // the contact force sum, by every lane of the wave (a lane past the last
+    // body has an empty row)
+    extern __shared__ double s_coop[];
+    double F[3], T[3];
+    body_sum_wave<PREC, FREC>(a, beg, end, xr0.w, F, T, s_coop + (threadIdx.x >> 6) * kCoopWords);
     if (live) {
         const int s = BATCHED ? (int)glb<const uint16_t>(a.bod.scene)[i] : 0;
         // an unbatched scene (periodic included) reads the descriptor's own
@@ -164,8 +242,6 @@ __global__ void __launch_bounds__(kMaxBlock) k_integrate(const StepArgs* __restr
         // FP64 division costs about ten FP64 instructions: the step divides
         // by m and by I once and multiplies after that
         const double inv_m = 1.0 / m, inv_I = 1.0 / I;
-        double F[3], T[3];
-        body_sum<PREC, FREC>(a, beg, end, r, F, T);
         if (measure && blocked != 63u) {
             part.fsum = sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]);
             part.fcnt = 1.0;
@@ -592,10 +668,12 @@ template <int PREC, bool BATCHED, bool PERIODIC, bool FREC>
 void launch_t(const StepArgs* args, int parity, int grid, int block, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
     const dim3 g(grid > 0 ? grid : 1), b(block);
+    // each wave's LDS slice for the long rows' cooperative walk
+    const size_t lds = sizeof(double) * kCoopWords * (size_t)((block + 63) / 64);
     if (ev0)
-        hipExtLaunchKernelGGL((k_integrate<PREC, BATCHED, PERIODIC, FREC>), g, b, 0, st, ev0, ev1, 0, args, parity);
+        hipExtLaunchKernelGGL((k_integrate<PREC, BATCHED, PERIODIC, FREC>), g, b, lds, st, ev0, ev1, 0, args, parity);
     else
-        hipLaunchKernelGGL((k_integrate<PREC, BATCHED, PERIODIC, FREC>), g, b, 0, st, args, parity);
+        hipLaunchKernelGGL((k_integrate<PREC, BATCHED, PERIODIC, FREC>), g, b, lds, st, args, parity);
 }
 
 template <int PREC, bool FREC>

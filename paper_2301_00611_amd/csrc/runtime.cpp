@@ -1353,7 +1353,7 @@ struct World {
         dem_tuning best = tuning();
         probe(probe_steps);  // warm the current setting (graph capture, first broad phase)
         best.ms_per_step = probe(probe_steps);
-        const int blocks[] = {128, 256, 512, 1024};
+        const int blocks[] = {64, 128, 256, 512, 1024};
         const int chunks[] = {16, 32, 64};
         const double vfs[] = {0.05, 0.1, 0.25, 0.5, 1.0};
         auto trial = [&](dem_tuning t) {

@@ -141,6 +141,61 @@ def test_bidisperse_shear_8m_spot():
     _check_spot(out, spot, ids, spec, dt, spec.material.young * 2.0e-3)
 
 
+def test_bidisperse_shear_8m_spot_after_1000_steps():
+    """The benchmark's 8,000,000-sphere packing (prepared as the benchmark
+    prepares it: jammed at 1 kPa, settled, tiled 4 x 4 x 4) sheared for 1,000
+    steps on the GPU (FP64): from the GPU's own state, sheared cell and
+    shear history at that step, one more step of fresh GPU scenes (FP64,
+    FP32-mixed) against the oracle's spot mode on 24 sampled spheres (16
+    random, 8 large), each evaluated against all bodies and their 27
+    images; the history handed over is every contact of a sampled sphere."""
+    import bench
+    from oracle import OracleScene
+    from paper_2301_00611_amd import dem
+    spec, st0, H0, _ = bench.prepare_periodic("periodic_shear", 8_000_000)
+    n = len(spec.radius)
+    m = spec.material
+
+    def scene(prec, pos, vel, angvel, H):
+        g = dem.Scene(periodic=True, hsize=H, velgrad=spec.velgrad, damping=spec.damping, gravity=spec.gravity,
+                      precision=prec)
+        mg = g.add_material(m.density, m.young, m.poisson, m.friction)
+        g.add_spheres(pos, spec.radius, vel=vel, angvel=angvel, default_mat=mg)
+        g.set_dt(spec.dt_factor * g.pwave_dt())
+        return g
+
+    g = scene(0, st0["pos"], st0["vel"], st0["angvel"], H0)
+    g.step(1000)
+    st = g.get_state()
+    H, _ = g.get_cell()
+    hist = g.get_history()
+    stats = g.stats()
+    g.close()
+    assert stats["n_contacts_ss"] > 10_000_000 and abs(H[0, 2]) > 0.0  # dense, and the cell has sheared
+    rng = np.random.default_rng(33)
+    large = np.nonzero(spec.radius > 1e-3)[0]
+    ids = np.concatenate([rng.choice(n, size=16, replace=False), rng.choice(large, size=8, replace=False)])
+    keep = np.isin(hist["id1"], ids) | np.isin(hist["id2"], ids)
+    h = hist[keep]
+    assert len(h) > len(ids) and np.abs(h["fs"]).max() > 0.0
+    out = {}
+    dt = None
+    for prec in (0, 1):
+        g = scene(prec, st["pos"], st["vel"], st["angvel"], H)
+        dt = spec.dt_factor * g.pwave_dt()
+        g.set_history(h["id1"], h["id2"], h["fs"], h["nprev"], cell=h["cell"])
+        g.step(1)
+        out[prec] = (g.get_state(), g.stats())
+        g.close()
+    o = OracleScene(dt=dt, periodic=True, hsize=H, velgrad=spec.velgrad, damping=spec.damping, gravity=spec.gravity)
+    mo = o.add_material(m.density, m.young, m.poisson, m.friction)
+    o.add_spheres(st["pos"], spec.radius, vel=st["vel"], angvel=st["angvel"], default_mat=mo)
+    o.set_contacts(h["id1"], h["id2"], h["fs"], h["nprev"], cell=h["cell"])
+    spot = o.spot_step(ids)
+    o.close()
+    _check_spot(out, spot, ids, spec, dt, spec.material.young * 2.0e-3)
+
+
 def test_lognormal_compression_2m_spot():
     """2,000,000 spheres with the compression workload's lognormal radii
     (0.41 to 2.46 mm) on its generator's cubic lattice, with the spacing
