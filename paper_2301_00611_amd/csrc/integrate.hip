@@ -128,7 +128,7 @@ __device__ inline void body_sum(const StepArgs& a, int beg, int end, double r, d
 // wave together, 64 entries at a time: each lane reads one entry and its
 // pair's record into the wave's slice of LDS, then the row's own lane adds
 // them in row order, with the same arithmetic as the walk.
-constexpr int kSoloEntries = 16;
+constexpr int kSoloEntries = 12;
 constexpr int kCoopWords = 64 * (kForceWords + 1);  // doubles per wave: 64 entries x 6, then 64 entry words
 template <int PREC, bool FREC>
 __device__ inline void body_sum_wave(const StepArgs& a, int beg, int end, double r, double* F, double* T,
