@@ -332,7 +332,7 @@ def dense_run(spec, st, H, L, precision, steps, warmup, timing_steps=1000, probe
 
 
 def periodic_leg(name="periodic_compression", steps=2000, warmup=20, n=None, log=None, prepared=None,
-                 with_controller=True, with_stats=True, cache=None):
+                 with_controller=True, with_stats=True, cache=None, fixed_tuning=None):
     """A dense periodic workload (C3: isotropic compression at 0.01/s; C5:
     bidisperse simple shear at 1/s), FP64 vs FP32-mixed on the same prepared
     packing: throughput of each, kernel durations and rooflines, and the
@@ -353,7 +353,7 @@ def periodic_leg(name="periodic_compression", steps=2000, warmup=20, n=None, log
            "preparation": _jsonable(rec), "steps": steps}
     out["fp32_vs_fp64_one_step"] = _fp32_vs_fp64_one_step(spec, st, H, L)
     for prec, key in ((0, "fp64"), (1, "fp32_mixed")):
-        out[key] = dense_run(spec, st, H, L, prec, steps, warmup, log=log)
+        out[key] = dense_run(spec, st, H, L, prec, steps, warmup, log=log, fixed_tuning=fixed_tuning)
     if with_controller:
         out["controlled_cell"] = controlled_cell_run(H, spec, st, min(steps, 1000), log)
     if with_stats:
@@ -522,7 +522,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--no-extra", action="store_true", help="skip the other workloads' legs")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other workloads' legs (with --workload: the leg's sub-runs: controlled cell, "
+                         "error statistics, the batch's sequential reference)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fp64-only", action="store_true", help="headline: skip the FP32-mixed leg (profiling runs)")
     ap.add_argument("--timing-steps", type=int, default=1000,
@@ -535,8 +537,8 @@ def main():
                     help="headline and periodic legs: .npz holding the prepared packing before it is tiled (loaded "
                          "if present, else written), so that profiled runs skip the preparation")
     ap.add_argument("--tuning", default=None,
-                    help="headline: a fixed launch setting 'block_contact,block_integrate,chunk,verlet_factor' in "
-                         "place of the autotuner's (profiling runs)")
+                    help="headline and periodic legs: a fixed launch setting "
+                         "'block_contact,block_integrate,chunk,verlet_factor' in place of the autotuner's (profiling runs)")
     ap.add_argument("--tuning-cache", default=None,
                     help="autotuner cache file for the column legs: reuse a stored setting, or store the one found")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -560,11 +562,11 @@ def main():
     if args.workload in PERIODIC_WORKLOADS:
         out = periodic_leg(args.workload, steps=args.steps, warmup=args.warmup, log=log,
                            with_controller=not args.no_extra, with_stats=not args.no_extra,
-                           cache=args.prepared_state)
+                           cache=args.prepared_state, fixed_tuning=parse_tuning(args.tuning))
         print(json.dumps(out), flush=True)
         return
     if args.workload == "batched":
-        print(json.dumps(batched_leg(steps=args.steps, log=log)), flush=True)
+        print(json.dumps(batched_leg(steps=args.steps, log=log, sequential=not args.no_extra)), flush=True)
         return
     if args.workload == "column":
         print(json.dumps(column_leg(args.steps, args.warmup, log=log, cache=args.tuning_cache)), flush=True)
@@ -755,7 +757,7 @@ def _batch_kernels(b, steps):
     return out
 
 
-def batched_leg(n_scenes=512, steps=2000, sequential_steps=None, log=None):
+def batched_leg(n_scenes=512, steps=2000, sequential_steps=None, log=None, sequential=True):
     """C4: 512 independent deposition scenes (log-uniform sizes 500..50,000,
     per-scene friction and damping) stepped together, FP64 and FP32-mixed:
     scene-steps/s with the default launch setting and with the autotuner's
@@ -786,6 +788,8 @@ def batched_leg(n_scenes=512, steps=2000, sequential_steps=None, log=None):
                                                                   if kern["integrate"] > 0 else None)}}
         log(f"batched {name}: {out[name]}")
     out["value"] = out["fp64"]["value"]
+    if not sequential:
+        return out
     # the same scenes one after another through the single-scene FP64 path
     import torch
     t_seq = 0.0

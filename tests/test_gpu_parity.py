@@ -366,3 +366,60 @@ def test_bidisperse_periodic_shear_one_step(precision, tol):
     g.step(10)
     o.step(10)
     assert keyset(g.get_contacts()) == keyset(o.get_contacts())
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-5)])
+def test_long_rows_summed_by_the_wave(precision, tol):
+    """Spheres with far more candidate pairs than their neighbours: three
+    4 mm spheres, each in a shell of 0.5 mm spheres that overlap it slightly
+    (200, 100 and 70 of them, spread by a Fibonacci lattice), so that their
+    rows run past what a lane walks alone and the wave finishes them in one
+    to four rounds of 64 entries. No gravity, no damping and the big spheres
+    at rest, so their velocity after one step is their force sum times
+    dt / m: forces and velocities against the oracle."""
+    from paper_2301_00611_amd.scenes import Material, Scene, random_velocities
+    rng = np.random.default_rng(17)
+    R, r = 4.0e-3, 0.5e-3
+    centres = np.array([[0.02, 0.02, 0.02], [0.05, 0.02, 0.02], [0.02, 0.05, 0.035]])
+    pos, rad = [], []
+    for c, k in zip(centres, (200, 100, 70)):
+        pos.append(c)
+        rad.append(R)
+        i = np.arange(k) + 0.5
+        z = 1.0 - 2.0 * i / k
+        phi = np.pi * (1.0 + 5 ** 0.5) * i
+        d = np.stack([np.sqrt(1 - z * z) * np.cos(phi), np.sqrt(1 - z * z) * np.sin(phi), z], axis=1)
+        d += rng.normal(scale=0.01, size=d.shape)
+        d /= np.linalg.norm(d, axis=1)[:, None]
+        pos.extend(c + d * (R + r - rng.uniform(1e-5, 5e-5, size=(k, 1))))
+        rad.extend([r] * k)
+    pos, rad = np.array(pos), np.array(rad)
+    spec = Scene(pos=pos, radius=rad, material=Material(2600.0, 1e7, 0.3, 0.5), gravity=(0.0, 0.0, 0.0),
+                 damping=0.0)
+    v, w = random_velocities(len(rad), 0.01, 18)
+    big = np.nonzero(rad == R)[0]
+    v[big] = 0.0
+    w[big] = 0.0
+    g, o, dt = twin(spec, precision=precision, vel=v, angvel=w)
+    g.step(1)
+    o.step(1)
+    cg, co = g.get_contacts(), o.get_contacts()
+    assert keyset(cg) == keyset(co)
+    deg = np.bincount(np.concatenate([co["id1"], co["id2"]]), minlength=len(rad))
+    assert deg[big].tolist()[0] > 64 + 12 and min(deg[big]) > 12
+    assert contact_errors(cg, co)["f"].max() <= tol
+    sg, so = g.get_state(), o.get_state()
+    ef, _ = body_force_errors(sg, so, co)
+    assert ef.max() <= tol
+    # the step's own sum (the integrator's) through the big spheres' new velocities
+    mag = np.linalg.norm(co["fn"] + co["fs"], axis=1)
+    scale = np.zeros(len(rad))
+    np.add.at(scale, co["id1"], mag)
+    np.add.at(scale, co["id2"], mag)
+    m = 4.0 / 3.0 * np.pi * R ** 3 * 2600.0
+    dv = np.linalg.norm(sg["vel"][big] - so["vel"][big], axis=1)
+    assert np.all(dv <= tol * scale[big] * dt / m + 4 * EPS * np.linalg.norm(so["vel"][big], axis=1))
+    assert np.linalg.norm(so["vel"][big], axis=1).min() > 0.0
+    dw = np.linalg.norm(sg["angvel"][big] - so["angvel"][big], axis=1)
+    inertia = 0.4 * m * R * R
+    assert np.all(dw <= tol * scale[big] * R * dt / inertia + 4 * EPS * np.linalg.norm(so["angvel"][big], axis=1))
