@@ -111,7 +111,6 @@ __device__ inline void set_row_bits(const StepArgs& a, int k, bool real)
 struct ContactPartial {
     double el, plast;
     unsigned long long ss, sw;
-    double ov;
     double visc;
 };
 
@@ -158,7 +157,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
         const CtrlConfig& c = *a.ctrl;
         a.ctr->measure = (c.active && (a.ctr->iter0 + a.ctr->steps_done + 1) % c.glob_update == 0) ? 1 : 0;
     }
-    ContactPartial part = {0.0, 0.0, 0ull, 0ull, 0.0, 0.0};
+    ContactPartial part = {0.0, 0.0, 0ull, 0ull, 0.0};
     bool unstable = false;
     // the measuring instantiation keeps what its terms need (force and
     // normal as stored, the branch length, k_n; zero for a pair not
@@ -424,7 +423,6 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
                 part.ss = 1;
             const double rmin = wall ? r2 : (r1 < r2 ? r1 : r2);
             unstable = pen > rmin && !in_box;
-            part.ov = pen / rmin;
             if constexpr (MEASURE) {
                 mf[0] = (double)F.x;
                 mf[1] = (double)F.y;
@@ -442,22 +440,24 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
         }
     }
 
-    // ---- block slot: counts always, energies when tracked (fixed-order
-    // wave and block combination, plain stores into this block's slot)
+    // ---- block slot: counts always (a wave counts its touching lanes with
+    // one ballot), energies when tracked (fixed-order wave and block
+    // combination, plain stores into this block's slot).  The largest
+    // overlap is not reduced here: it is read from the history records on
+    // request.
     __shared__ ContactPartial s_p[kMaxBlock / 64];
     __shared__ uint32_t s_bad[kMaxBlock / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const bool energy = a.track_energy != 0;
-    for (int off = 32; off > 0; off >>= 1) {
-        if (energy) {
+    if (energy) {
+        for (int off = 32; off > 0; off >>= 1) {
             part.el += __shfl_down(part.el, off, 64);
             part.plast += __shfl_down(part.plast, off, 64);
             if (VISCEL) part.visc += __shfl_down(part.visc, off, 64);
         }
-        part.ss += __shfl_down(part.ss, off, 64);
-        part.sw += __shfl_down(part.sw, off, 64);
-        part.ov = fmax(part.ov, __shfl_down(part.ov, off, 64));
     }
+    part.ss = (unsigned long long)__popcll(__ballot(part.ss != 0ull));
+    part.sw = (unsigned long long)__popcll(__ballot(part.sw != 0ull));
     const bool bad = __any(unstable);
     if (lane == 0) {
         s_p[wave] = part;
@@ -465,7 +465,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double el = 0.0, pl = 0.0, ov = 0.0, vi = 0.0;
+        double el = 0.0, pl = 0.0, vi = 0.0;
         unsigned long long ss = 0, sw = 0;
         uint32_t flags = 0;
         for (int w = 0; w < nwaves; ++w) {
@@ -474,7 +474,6 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
             if (VISCEL) vi += s_p[w].visc;
             ss += s_p[w].ss;
             sw += s_p[w].sw;
-            ov = fmax(ov, s_p[w].ov);
             flags |= s_bad[w];
         }
         ContactAcc& acc = a.acc_contact[blockIdx.x];
@@ -487,7 +486,6 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
         acc.sw = sw;
         acc.ss_cum += ss;
         acc.sw_cum += sw;
-        acc.max_ov = ov;
         if (flags) a.ctr->unstable = 1;
     }
     if constexpr (MEASURE) {

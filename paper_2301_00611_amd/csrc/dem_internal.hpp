@@ -363,7 +363,6 @@ struct ContactAcc {
     double plast;                   // plastic work, cumulative
     unsigned long long ss, sw;      // real contacts of the last step
     unsigned long long ss_cum, sw_cum;
-    double max_ov;                  // largest overlap / smaller radius, last step
     double visc;                    // dashpot work of the visco-elastic law, cumulative
 };
 
@@ -549,6 +548,10 @@ void launch_body_forces(const StepArgs& a, int precision, double* f3, double* t3
 // axis (3), sum of |F| and count (2); `scene` selects a batch scene.
 constexpr int kNetworkWords = 14;
 int stress_blocks(int npairs);
+// Largest overlap / smaller radius (a boundary's sphere's radius) over the
+// pairs that touched at the last step, from their history records, as the
+// bits of a non-negative double into *out (which the caller zeroes).
+void launch_max_overlap(const StepArgs& a, int precision, unsigned long long* out, hipStream_t st);
 // Force on #2 of every pair (3 doubles per pair; 0 for a pair not touching).
 void launch_pair_forces(const StepArgs& a, int precision, double* f3, hipStream_t st);
 void launch_network(const StepArgs& a, int precision, bool batched, int scene, double* part, hipStream_t st);

@@ -103,9 +103,11 @@ __device__ inline void row_walk(const StepArgs& a, int beg, int end, double r, d
             const uint32_t k = u[j] & kPairMask;
             use[j] = (e0 + j < end) && k < (uint32_t)a.npairs && (u[j] & kRealBit) != 0u;
         }
+        // the four gathers go out together, with no branch between them: an
+        // entry that does not count reads pair 0's record (always cached)
+        // and is then ignored
         double f[kB][kForceWords];
-        for (int j = 0; j < kB; ++j)
-            if (use[j]) pair_force<PREC, FREC>(a, u[j] & kPairMask, f[j]);
+        for (int j = 0; j < kB; ++j) pair_force<PREC, FREC>(a, use[j] ? (u[j] & kPairMask) : 0u, f[j]);
         for (int j = 0; j < kB; ++j)
             if (use[j]) add_entry(u[j], f[j], r, F, T);
     }

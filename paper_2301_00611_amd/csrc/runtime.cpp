@@ -252,7 +252,6 @@ struct World {
     // last-step values kept across a fold until the next step runs
     double last_el = 0.0, last_kin = 0.0, last_rot = 0.0;
     unsigned long long last_ss = 0, last_sw = 0;
-    double last_maxov = 0.0;
     bool slots_fresh = true;           // no step has written the slots since the last fold
     std::vector<SceneParams> sp;       // host copy of the scene table
     Counters* h_ctr = nullptr;         // pinned
@@ -1172,7 +1171,7 @@ struct World {
     // Sum the per-block slots in block order.  cum = true: add the running
     // sums to the bases and clear the slots (before the grids change).
     struct SlotSums {
-        double el = 0, plast = 0, kin = 0, rot = 0, grav = 0, damp = 0, maxov = 0, visc = 0;
+        double el = 0, plast = 0, kin = 0, rot = 0, grav = 0, damp = 0, visc = 0;
         unsigned long long ss = 0, sw = 0, cum = 0;
     };
     SlotSums read_slots()
@@ -1190,7 +1189,6 @@ struct World {
             t.ss += a.ss;
             t.sw += a.sw;
             t.cum += a.ss_cum + a.sw_cum;
-            t.maxov = std::max(t.maxov, a.max_ov);
         }
         for (const IntAcc& a : i) {
             t.kin += a.kin;
@@ -1215,13 +1213,28 @@ struct World {
             last_rot = t.rot;
             last_ss = t.ss;
             last_sw = t.sw;
-            last_maxov = t.maxov;
         }
         slots_fresh = true;
     }
+    // Largest overlap / smaller radius over the pairs that touched at the
+    // last step (0 before the first step), from their history records.
+    double max_overlap()
+    {
+        if (npairs <= 0 || !contacts_valid) return 0.0;
+        d_acct.ensure(8);
+        HIPC(hipMemsetAsync(d_acct.p, 0, 8, stream));
+        StepArgs a = step_args();
+        launch_max_overlap(a, precision, d_acct.as<unsigned long long>(), stream);
+        HIPC(hipGetLastError());
+        unsigned long long bits = 0;
+        HIPC(hipMemcpyAsync(&bits, d_acct.p, 8, hipMemcpyDeviceToHost, stream));
+        HIPC(hipStreamSynchronize(stream));
+        double v;
+        std::memcpy(&v, &bits, sizeof v);
+        return v;
+    }
     // Energies and contact counts as reported: bases + current slots.
-    void totals(dem_energy* e, unsigned long long* ss, unsigned long long* sw, unsigned long long* csteps,
-                double* maxov = nullptr)
+    void totals(dem_energy* e, unsigned long long* ss, unsigned long long* sw, unsigned long long* csteps)
     {
         const SlotSums t = read_slots();
         const bool fresh = slots_fresh;
@@ -1240,7 +1253,6 @@ struct World {
         if (ss) *ss = fresh ? last_ss : t.ss;
         if (sw) *sw = fresh ? last_sw : t.sw;
         if (csteps) *csteps = base_contact_steps + t.cum;
-        if (maxov) *maxov = fresh ? last_maxov : t.maxov;
     }
 
     // ------------------------------------------------------------ tuning
@@ -2809,8 +2821,7 @@ dem_status dem_get_energy(dem_scene* s, dem_energy* out)
 static void fill_stats(dem::World* w, int s, dem_stats* out)
 {
     unsigned long long ss = 0, sw = 0, csteps = 0;
-    double maxov = 0.0;
-    w->totals(nullptr, &ss, &sw, &csteps, &maxov);
+    w->totals(nullptr, &ss, &sw, &csteps);
     std::memset(out, 0, sizeof *out);
     int64_t nsph = 0, nw = 0;
     const int s0 = s < 0 ? 0 : s;
@@ -2832,7 +2843,7 @@ static void fill_stats(dem::World* w, int s, dem_stats* out)
     out->rebuilds = w->rebuilds;
     out->contact_steps = (int64_t)csteps;
     out->coordination = all ? 2.0 * (double)ss / (double)all : 0.0;
-    out->max_overlap_ratio = maxov;
+    out->max_overlap_ratio = w->max_overlap();
 }
 
 dem_status dem_get_unbalanced_force(dem_scene* s, int32_t use_max, double* out)

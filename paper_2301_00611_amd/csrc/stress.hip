@@ -29,10 +29,12 @@ namespace {
 constexpr int kStressBlock = 256;
 
 // Force on #2 of pair k (0 unless the pair touched at the last step): from
-// its force record, or (FP64 linear law) its history record, fn n + Fs.
+// its force record, or (FP64 linear law) its history record, fn n + Fs
+// (without contraction, as the force sum forms it).
 template <int PREC>
 __device__ inline void pair_force(const StepArgs& a, int k, double* F)
 {
+#pragma clang fp contract(off)
     F[0] = F[1] = F[2] = 0.0;
     if (!a.pr.real[k]) return;
     if (!a.use_frec) {
@@ -51,6 +53,24 @@ __device__ inline void pair_force(const StepArgs& a, int k, double* F)
         F[1] = q[1];
         F[2] = q[2];
     }
+}
+
+// The largest overlap ratio over the touching pairs: wave maxima, then an
+// integer maximum on the bits (non-negative doubles order like their bits).
+template <int PREC>
+__global__ void __launch_bounds__(kStressBlock) k_max_overlap(StepArgs a, unsigned long long* __restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    double v = 0.0;
+    if (k < a.npairs && a.pr.real[k]) {
+        const double pen = hist_load<PREC>(a.pr.h, k).pen;
+        const int32_t sa = a.pr.a[k], sb = a.pr.b[k];
+        const double r2 = a.bod.xr[sb].w;
+        const double rmin = sa < 0 ? r2 : fmin(a.bod.xr[sa].w, r2);
+        v = pen / rmin;
+    }
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    if ((threadIdx.x & 63) == 0 && v > 0.0) atomicMax(out, (unsigned long long)__double_as_longlong(v));
 }
 
 // Per-pair force on #2 (3 doubles per pair) for reporting.
@@ -245,6 +265,16 @@ void launch_pair_forces(const StepArgs& a, int precision, double* f3, hipStream_
 }
 
 int stress_blocks(int npairs) { return npairs > 0 ? (npairs + kStressBlock - 1) / kStressBlock : 0; }
+
+void launch_max_overlap(const StepArgs& a, int precision, unsigned long long* out, hipStream_t st)
+{
+    const int grid = stress_blocks(a.npairs);
+    if (grid == 0) return;
+    if (precision == DEM_FP32_MIXED)
+        hipLaunchKernelGGL(k_max_overlap<DEM_FP32_MIXED>, dim3(grid), dim3(kStressBlock), 0, st, a, out);
+    else
+        hipLaunchKernelGGL(k_max_overlap<DEM_FP64>, dim3(grid), dim3(kStressBlock), 0, st, a, out);
+}
 
 void launch_network(const StepArgs& a, int precision, bool batched, int scene, double* part, hipStream_t st)
 {
