@@ -391,6 +391,18 @@ def _jsonable(d):
 
 
 def cpu_model():
+    """The host CPU as lscpu names it (model name, sockets x cores x threads),
+    else /proc/cpuinfo's model name."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        f = dict(line.split(":", 1) for line in out.splitlines() if ":" in line)
+        f = {k.strip(): v.strip() for k, v in f.items()}
+        if "Model name" in f:
+            return (f"{f['Model name']} ({f.get('Socket(s)', '?')} sockets x {f.get('Core(s) per socket', '?')} cores x "
+                    f"{f.get('Thread(s) per core', '?')} threads, {f.get('CPU(s)', '?')} CPUs visible)")
+    except (OSError, subprocess.SubprocessError, ValueError):
+        pass
     try:
         for line in open("/proc/cpuinfo"):
             if line.startswith("model name"):
@@ -744,6 +756,7 @@ def _time_batch(b, steps):
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     s1 = b.stats()
+    _time_batch.rebuilds = s1["rebuilds"] - s0["rebuilds"]
     return t, s1["contact_steps"] - s0["contact_steps"]
 
 
@@ -778,12 +791,13 @@ def batched_leg(n_scenes=512, steps=2000, sequential_steps=None, log=None, seque
         t_def, c_def = _time_batch(b, steps)
         tune = b.autotune(probe_steps=100)
         t_tun, c_tun = _time_batch(b, steps)
+        runs = _time_batch.rebuilds
         kern = _batch_kernels(b, min(steps, 500))
         b.close()
         ib = INTEGRATE_BYTES_PER_BODY * nbodies
         out[name] = {"value": n_scenes * steps / t_tun, "seconds": t_tun, "body_steps_per_s": nbodies * steps / t_tun,
                      "contact_steps_per_s": c_tun / t_tun, "default_setting_value": n_scenes * steps / t_def,
-                     "tuning": tune, "kernels_ms": kern,
+                     "tuning": tune, "kernels_ms": kern, "broad_phase_runs_timed": runs,
                      "integrate_roofline": {"bytes": ib, "frac": (ib / (kern["integrate"] * 1e-3) / 1e9 / HBM_PEAK_GBS
                                                                   if kern["integrate"] > 0 else None)}}
         log(f"batched {name}: {out[name]}")

@@ -294,11 +294,13 @@ __global__ void __launch_bounds__(kMaxBlock) k_contact(const StepArgs* __restric
             const V3<double> w2d = v3(wb.x, wb.y, wb.z);
             if (PERIODIC) {
                 // the image of #2 moves with the cell: (H - H_prev) c / dt
+                // (one FP64 division, then three products)
                 const double* D = S.dH;
                 const double sx = (D[0] * (double)cc[0] + D[1] * (double)cc[1]) + D[2] * (double)cc[2];
                 const double sy = (D[3] * (double)cc[0] + D[4] * (double)cc[1]) + D[5] * (double)cc[2];
                 const double sz = (D[6] * (double)cc[0] + D[7] * (double)cc[1]) + D[8] * (double)cc[2];
-                v2d = v3(v2d.x + sx / dt, v2d.y + sy / dt, v2d.z + sz / dt);
+                const double inv_dt = 1.0 / dt;
+                v2d = v3(v2d.x + sx * inv_dt, v2d.y + sy * inv_dt, v2d.z + sz * inv_dt);
             }
             // relative translational velocity in double (difference of absolute values)
             const V3<double> dv64 = v2d - v1d;
