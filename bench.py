@@ -463,6 +463,26 @@ def cpu_baseline(budget_s=5.0, repeats=3, n=4096):
     }
 
 
+def copy_bandwidth(nbytes=1 << 30, repeats=5):
+    """The GPU's measured streaming bandwidth: a plain device-to-device copy
+    of `nbytes` (read + write) timed with device events, best of `repeats`."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = float("inf")
+    for _ in range(repeats):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / best / 1e9
+
+
 def parse_tuning(text):
     """--tuning "block_contact,block_integrate,chunk,verlet_factor" -> dict (None: autotune)."""
     if not text:
@@ -519,6 +539,10 @@ def headline(args, log):
         "tuning": r64["tuning"],
         "preparation": _jsonable(rec),
     }
+    # the same kernel against what a plain copy reaches on this GPU
+    cb = copy_bandwidth()
+    out["roofline"]["copy_GBs"] = cb
+    out["roofline"]["frac_of_copy"] = rl["achieved_GBs"] / cb
     if args.fp64_only:
         return out
     log("FP32-mixed on the same packing")
