@@ -780,8 +780,7 @@ def _time_batch(b, steps):
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     s1 = b.stats()
-    _time_batch.rebuilds = s1["rebuilds"] - s0["rebuilds"]
-    return t, s1["contact_steps"] - s0["contact_steps"]
+    return t, s1["contact_steps"] - s0["contact_steps"], s1["rebuilds"] - s0["rebuilds"]
 
 
 def _batch_kernels(b, steps):
@@ -812,10 +811,9 @@ def batched_leg(n_scenes=512, steps=2000, sequential_steps=None, log=None, seque
     out = {"unit": "scene-steps/s", "n_scenes": n_scenes, "n_spheres": nbodies, "steps": steps}
     for prec, name in ((0, "fp64"), (1, "fp32_mixed")):
         b = _build_batch(spec, dt, prec)
-        t_def, c_def = _time_batch(b, steps)
+        t_def, c_def, _ = _time_batch(b, steps)
         tune = b.autotune(probe_steps=100)
-        t_tun, c_tun = _time_batch(b, steps)
-        runs = _time_batch.rebuilds
+        t_tun, c_tun, runs = _time_batch(b, steps)
         kern = _batch_kernels(b, min(steps, 500))
         b.close()
         ib = INTEGRATE_BYTES_PER_BODY * nbodies
