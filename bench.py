@@ -460,6 +460,9 @@ def cpu_baseline(budget_s=5.0, repeats=3, n=4096):
                    f"{len(o.get_contacts())} contacts at the end"),
         "body_steps_per_s": statistics.median(body_rates),
         "repeats": rates,
+        # its pair detection is O(N^2): the same oracle on the 8,000,000
+        # spheres of the workload, extrapolated (not measured)
+        "extrapolated_s_per_step_at_8M": statistics.median(per_step) * (8_000_000 / n) ** 2,
     }
 
 

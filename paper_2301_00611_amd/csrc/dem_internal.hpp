@@ -383,7 +383,7 @@ struct StepArgs {
     const double* tanphi;           // nmat x nmat, tan(min(phi1, phi2))
     const ViscElPair* ve;           // nmat x nmat, visco-elastic pair constants
     int32_t nmat;
-    SceneParams* scenes;            // device table (the last integrate block updates a periodic cell)
+    SceneParams* scenes;            // device table (k_cell_update keeps a periodic cell's entry current)
     SceneParams scene0;             // copy of scene 0 for unbatched kernels
     int32_t nscenes;
     int32_t nslots;

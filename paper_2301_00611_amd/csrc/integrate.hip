@@ -1,8 +1,9 @@
 // integrate.hip -- ForceContainer sum + NewtonIntegrator (section 2.1.5).
 //
 // One thread per body: the body adds the forces of its candidate pairs one by
-// one, in ascending partner id (its row order), so the sum is deterministic
-// and needs no atomics; then gravity (damped like any force, dampGravity),
+// one, in ascending partner id (its row order; the wave helps with the
+// gathers of a long row), so the sum is deterministic and needs no atomics;
+// then gravity (damped like any force, dampGravity),
 // Cundall damping eq. 2.9 per component with the on-step velocity estimate
 // v + a dt/2, the leapfrog update, the spherical rotation and, in a periodic
 // cell, the homoDeform velocity terms (class Cell).  Energies use the
