@@ -476,10 +476,99 @@ __global__ void __launch_bounds__(kBlock) k_sweep_count(SweepArgs a)
     a.count[i] = n;
 }
 
-template <bool BATCHED, bool PERIODIC, bool LARGE>
-__global__ void __launch_bounds__(kBlock) k_sweep_fill(SweepArgs a)
+// How each row was left by the fill, kept in `count` (the counts are spent
+// once the rows are laid out): already sorted, in the order found (sorted by
+// the rank pass), or a level-1 row in the order found (sorted by the wave
+// rank pass).
+constexpr uint32_t kRowSorted = 0, kRowFound = 1, kRowLarge = 2;
+
+// LDS pool of the level-0 fill: 8 entries per sphere of the block on
+// average (24 KB, so that the six blocks per CU its registers allow fit).
+constexpr int kStageEntries = 8 * kBlock;
+
+// (partner id, packed image as unsigned) as one unsigned key
+__device__ inline uint64_t row_key(int32_t pid, int32_t cell)
 {
-    const int i = sweep_body<BATCHED, LARGE>(a);
+    return ((uint64_t)((uint32_t)pid ^ 0x80000000u) << 32) | (uint32_t)cell;
+}
+
+// The level-0 fill.  The rows of a block's spheres are contiguous, and the
+// block takes them, in slot order, into its LDS pool while they fit: such a
+// sweep stores nothing to memory (a store inside its loop would hold every
+// later load until the store is done), then ranks its row in LDS and writes
+// it sorted.  A row beyond the pool is written in the order found and
+// sorted by the rank pass.
+template <bool BATCHED, bool PERIODIC>
+__global__ void __launch_bounds__(kBlock) k_sweep_fill_staged(SweepArgs a)
+{
+    __shared__ int32_t s_slot[kStageEntries];
+    __shared__ int32_t s_pid[kStageEntries];
+    __shared__ int32_t s_cell[kStageEntries];
+    __shared__ uint32_t s_wave[kBlock / 64];
+    const int i = sweep_body<BATCHED, false>(a);
+    int beg = 0, len = 0;
+    if (i >= 0) {
+        beg = a.row_start[i];
+        len = a.row_start[i + 1] - beg;
+    }
+    // the block's exclusive scan of the row lengths, in slot order
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = (uint32_t)len;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += y;
+    }
+    if (lane == 63) s_wave[wave] = inc;
+    __syncthreads();
+    uint32_t base = 0;
+    for (int w = 0; w < wave; ++w) base += s_wave[w];
+    if (i < 0) return;
+    const uint32_t off = base + inc - (uint32_t)len;
+    const bool staged = off + (uint32_t)len <= (uint32_t)kStageEntries;
+    int n = 0;
+    for_each_candidate<BATCHED, PERIODIC>(a, i, [&](int32_t slot, int32_t pid, int32_t cell) {
+        if (n < len) {
+            if (staged) {
+                s_slot[off + n] = slot;
+                s_pid[off + n] = pid;
+                s_cell[off + n] = cell;
+            } else {
+                a.raw_slot[beg + n] = slot;
+                a.raw_pid[beg + n] = pid;
+                a.raw_cell[beg + n] = cell;
+            }
+        }
+        ++n;
+    });
+    for (int e = 0; e < len; ++e) a.ent_body[beg + e] = i;
+    if (!staged) {
+        a.count[i] = kRowFound;
+        return;
+    }
+    a.count[i] = kRowSorted;
+    const int32_t myid = a.g.bod.id[i];
+    for (int e = 0; e < len; ++e) {
+        const int32_t slot = s_slot[off + e], pid = s_pid[off + e], cell = s_cell[off + e];
+        const uint64_t ke = row_key(pid, cell);
+        int rank = 0;
+        for (int f = 0; f < len; ++f) {
+            const uint64_t kf = row_key(s_pid[off + f], s_cell[off + f]);
+            rank += (kf < ke || (kf == ke && f < e)) ? 1 : 0;
+        }
+        const int dst = beg + rank;
+        a.ent_slot[dst] = slot;
+        a.ent_pid[dst] = pid;
+        a.ent_cell[dst] = cell;
+        a.ent_own[dst] = (slot < 0 || myid < pid) ? 1u : 0u;
+    }
+}
+
+// The level-1 fill: rows in the order found.
+template <bool BATCHED, bool PERIODIC>
+__global__ void __launch_bounds__(kBlock) k_sweep_fill_large(SweepArgs a)
+{
+    const int i = sweep_body<BATCHED, true>(a);
     if (i < 0) return;
     const int beg = a.row_start[i];
     const int cap = a.row_start[i + 1] - beg;
@@ -493,18 +582,20 @@ __global__ void __launch_bounds__(kBlock) k_sweep_fill(SweepArgs a)
         }
         ++n;
     });
+    a.count[i] = kRowLarge;
 }
 
-// One thread per entry: its place in its row sorted by (partner id, image
-// as unsigned; ties by the order found, which cannot happen for distinct
-// candidates) is the number of the row's entries before it in that order.
-// Rows are short except those of the largest spheres, whose entries are
-// then spread over many threads; this order fixes the order of the force sum.
+// One thread per entry of a level-0 row that the fill left in the order
+// found: its place in its row sorted by (partner id, image as unsigned; ties
+// by the order found, which cannot happen for distinct candidates) is the
+// number of the row's entries before it in that order.  This order fixes the
+// order of the force sum.
 __global__ void __launch_bounds__(kBlock) k_row_rank(SweepArgs a)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= a.nent) return;
     const int i = a.ent_body[e];
+    if (a.count[i] != kRowFound) return;
     const int beg = a.row_start[i], end = a.row_start[i + 1];
     const int32_t pid = a.raw_pid[e];
     const uint32_t cell = (uint32_t)a.raw_cell[e];
@@ -520,6 +611,50 @@ __global__ void __launch_bounds__(kBlock) k_row_rank(SweepArgs a)
     a.ent_pid[dst] = pid;
     a.ent_cell[dst] = (int32_t)cell;
     a.ent_own[dst] = (slot < 0 || a.g.bod.id[i] < pid) ? 1u : 0u;
+}
+
+// One wave per level-1 sphere: its row, the longest kind, ranked as above
+// with the row's keys in LDS (a row longer than the wave's share is ranked
+// from memory).
+constexpr int kLargeRowLds = 1024;
+
+__global__ void __launch_bounds__(kBlock) k_row_rank_large(SweepArgs a)
+{
+    __shared__ uint64_t s_key[kBlock / 64][kLargeRowLds];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int t = blockIdx.x * (kBlock / 64) + wave;
+    if (t >= a.nlarge) return;  // the whole wave
+    const int i = (int)a.g.large_slot[t];
+    const int beg = a.row_start[i], len = a.row_start[i + 1] - beg;
+    const bool in_lds = len <= kLargeRowLds;
+    if (in_lds) {
+        for (int f = lane; f < len; f += 64) s_key[wave][f] = row_key(a.raw_pid[beg + f], a.raw_cell[beg + f]);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+    const int32_t myid = a.g.bod.id[i];
+    for (int e = lane; e < len; e += 64) {
+        const int32_t slot = a.raw_slot[beg + e], pid = a.raw_pid[beg + e], cell = a.raw_cell[beg + e];
+        const uint64_t ke = row_key(pid, cell);
+        int rank = 0;
+        if (in_lds) {
+            for (int f = 0; f < len; ++f) {
+                const uint64_t kf = s_key[wave][f];
+                rank += (kf < ke || (kf == ke && f < e)) ? 1 : 0;
+            }
+        } else {
+            for (int f = 0; f < len; ++f) {
+                const uint64_t kf = row_key(a.raw_pid[beg + f], a.raw_cell[beg + f]);
+                rank += (kf < ke || (kf == ke && f < e)) ? 1 : 0;
+            }
+        }
+        const int dst = beg + rank;
+        a.ent_slot[dst] = slot;
+        a.ent_pid[dst] = pid;
+        a.ent_cell[dst] = cell;
+        a.ent_own[dst] = (slot < 0 || myid < pid) ? 1u : 0u;
+    }
 }
 
 // -------------------------------------------------------- pairs and history
@@ -784,8 +919,20 @@ void launch_sweep_count(const SweepArgs& a, hipStream_t st)
 void launch_sweep_fill(const SweepArgs& a, hipStream_t st)
 {
     if (a.g.nslots <= 0) return;
-    DEM_SWEEP_LAUNCH(k_sweep_fill, a, st);
+    const dim3 blk(kBlock), g0(nblocks(a.g.nslots)), g1(nblocks(a.nlarge > 0 ? a.nlarge : 1));
+    if (a.g.nscenes > 1) {
+        hipLaunchKernelGGL((k_sweep_fill_staged<true, false>), g0, blk, 0, st, a);
+        if (a.nlarge > 0) hipLaunchKernelGGL((k_sweep_fill_large<true, false>), g1, blk, 0, st, a);
+    } else if (a.g.scene0.periodic) {
+        hipLaunchKernelGGL((k_sweep_fill_staged<false, true>), g0, blk, 0, st, a);
+        if (a.nlarge > 0) hipLaunchKernelGGL((k_sweep_fill_large<false, true>), g1, blk, 0, st, a);
+    } else {
+        hipLaunchKernelGGL((k_sweep_fill_staged<false, false>), g0, blk, 0, st, a);
+        if (a.nlarge > 0) hipLaunchKernelGGL((k_sweep_fill_large<false, false>), g1, blk, 0, st, a);
+    }
     if (a.nent > 0) hipLaunchKernelGGL(k_row_rank, dim3(nblocks(a.nent)), dim3(kBlock), 0, st, a);
+    if (a.nlarge > 0)
+        hipLaunchKernelGGL(k_row_rank_large, dim3((a.nlarge + kBlock / 64 - 1) / (kBlock / 64)), blk, 0, st, a);
 }
 
 void launch_pair_build(const PairBuildArgs& a, hipStream_t st)

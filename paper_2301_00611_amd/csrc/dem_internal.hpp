@@ -466,11 +466,12 @@ struct SweepArgs {
     const uint32_t* cell_start;
     const uint32_t* cell_end;
     const Wall* walls;
-    uint32_t* count;           // per slot
+    uint32_t* count;           // per slot: the count pass's counts, then how the fill left each row
     const int32_t* row_start;  // fill pass
-    // the fill pass writes each row's entries in the order found (raw_*, and
-    // the row of every entry), the rank pass sorts each row by (partner id,
-    // image) into ent_* and marks the entries that own their pair
+    // the fill pass writes each row sorted by (partner id, image) into ent_*
+    // where the row fits its block's LDS pool, else in the order found
+    // (raw_*), which the rank passes sort into ent_*; every entry's row goes
+    // to ent_body, and ent_own marks the entries that own their pair
     int32_t* raw_slot;         // partner slot or -1 - wall
     int32_t* raw_pid;          // partner id
     int32_t* raw_cell;         // packed image shift of the partner
