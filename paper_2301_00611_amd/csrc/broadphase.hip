@@ -347,10 +347,28 @@ __global__ void __launch_bounds__(kBlock) k_cells_large(GridArgs g, const uint64
 
 // ------------------------------------------------------------------- sweep
 
+// A neighbour cell's index along one axis, wrapped into [0, dim) with the
+// period crossed in w; outside an aperiodic grid the cell does not exist.
+template <bool PERIODIC>
+__device__ inline void wrap_axis(int& n, int dim, int& w, bool& skip)
+{
+    if (n < 0) {
+        if (!PERIODIC) skip = true;
+        n += dim;
+        w = -1;
+    } else if (n >= dim) {
+        if (!PERIODIC) skip = true;
+        n -= dim;
+        w = 1;
+    }
+}
+
 // Visit every candidate of home slot i (27 cells, then the scene's walls).
 // f(partner_slot_or_wall, partner_id, packed_cell) is called per candidate.
-template <bool BATCHED, bool PERIODIC, typename F>
-__device__ inline void for_each_candidate(const SweepArgs& a, int i, F&& f)
+// With SPLIT, the 64 lanes of a wave share one sphere's search: lane `part`
+// visits every 64th group of cells, and every 64th wall.
+template <bool BATCHED, bool PERIODIC, bool SPLIT = false, typename F>
+__device__ inline void for_each_candidate(const SweepArgs& a, int i, F&& f, int part = 0)
 {
     const GridArgs& g = a.g;
     const Bodies& B = g.bod;
@@ -373,67 +391,112 @@ __device__ inline void for_each_candidate(const SweepArgs& a, int i, F&& f)
     const double far = (ri + (lv == 0 && two ? P.r_split : P.rmax)) + reach;
     int kk[3];
     for (int q = 0; q < 3; ++q) kk[q] = max(1, (int)ceil(far / V.cellw[q]));
-    for (int dz = -kk[2]; dz <= kk[2]; ++dz)
-        for (int dy = -kk[1]; dy <= kk[1]; ++dy)
-            for (int dx = -kk[0]; dx <= kk[0]; ++dx) {
-                int n[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
-                int w[3] = {0, 0, 0};
-                bool skip = false;
-                for (int k = 0; k < 3; ++k) {
-                    if (n[k] < 0) {
-                        if (!PERIODIC) skip = true;
-                        n[k] += V.dims[k];
-                        w[k] = -1;
-                    } else if (n[k] >= V.dims[k]) {
-                        if (!PERIODIC) skip = true;
-                        n[k] -= V.dims[k];
-                        w[k] = 1;
-                    }
-                }
-                if (skip) continue;
-                const int lin = V.offset + n[0] + V.dims[0] * (n[1] + V.dims[1] * n[2]);
-                const uint32_t st = a.cell_start[lin];
-                if (st == kEmpty) continue;
-                const uint32_t en = a.cell_end[lin];
-                for (uint32_t q = st; q < en; ++q) {
-                    const uint32_t j = lv == 0 ? q : g.large_slot[q];
-                    if ((int)j == i) continue;
-                    const double4 pj = B.xr[j];
-                    const double rj = pj.w;
-                    if (lv == 0 && two && rj > P.r_split) continue;  // found on level 1
-                    const double sc = (ri + rj) + reach;
-                    double ddx, ddy, ddz;
-                    int32_t packed = kCellZero;
-                    if (PERIODIC) {
-                        int perj[3];
-                        unpack_cell(B.period[j], perj);
-                        const int cc[3] = {per_i[0] - perj[0] + w[0], per_i[1] - perj[1] + w[1],
-                                           per_i[2] - perj[2] + w[2]};
-                        packed = pack_cell(cc[0], cc[1], cc[2]);
-                        // evaluate from the lower id's side so that both bodies of
-                        // a pair take the same decision
-                        const bool from_i = myid < B.id[j];
-                        const int sg = from_i ? 1 : -1;
-                        const double* H = P.H;
-                        const double sx = (H[0] * (sg * cc[0]) + H[1] * (sg * cc[1])) + H[2] * (sg * cc[2]);
-                        const double sy = (H[3] * (sg * cc[0]) + H[4] * (sg * cc[1])) + H[5] * (sg * cc[2]);
-                        const double sz = (H[6] * (sg * cc[0]) + H[7] * (sg * cc[1])) + H[8] * (sg * cc[2]);
-                        const double ax = from_i ? xi : pj.x, ay = from_i ? yi : pj.y, az = from_i ? zi : pj.z;
-                        const double bx = from_i ? pj.x : xi, by = from_i ? pj.y : yi, bz = from_i ? pj.z : zi;
-                        ddx = (bx + sx) - ax;
-                        ddy = (by + sy) - ay;
-                        ddz = (bz + sz) - az;
-                    } else {
-                        ddx = pj.x - xi;
-                        ddy = pj.y - yi;
-                        ddz = pj.z - zi;
-                    }
-                    const double dd = (ddx * ddx + ddy * ddy) + ddz * ddz;
-                    if (dd < sc * sc) f((int32_t)j, B.id[j], packed);
-                }
+    // test one sphere j (position and radius pj, packed period perj, id idj)
+    // found across the periods (w0, w1, w2) of the home cell's neighbourhood
+    auto visit = [&](uint32_t j, const double4& pj, int32_t perj_packed, int32_t idj, int w0, int w1, int w2) {
+        if ((int)j == i) return;
+        const double rj = pj.w;
+        if (lv == 0 && two && rj > P.r_split) return;  // found on level 1
+        const double sc = (ri + rj) + reach;
+        double ddx, ddy, ddz;
+        int32_t packed = kCellZero;
+        if (PERIODIC) {
+            int perj[3];
+            unpack_cell(perj_packed, perj);
+            const int cc[3] = {per_i[0] - perj[0] + w0, per_i[1] - perj[1] + w1, per_i[2] - perj[2] + w2};
+            packed = pack_cell(cc[0], cc[1], cc[2]);
+            // evaluate from the lower id's side so that both bodies of
+            // a pair take the same decision
+            const bool from_i = myid < idj;
+            const int sg = from_i ? 1 : -1;
+            const double* H = P.H;
+            const double sx = (H[0] * (sg * cc[0]) + H[1] * (sg * cc[1])) + H[2] * (sg * cc[2]);
+            const double sy = (H[3] * (sg * cc[0]) + H[4] * (sg * cc[1])) + H[5] * (sg * cc[2]);
+            const double sz = (H[6] * (sg * cc[0]) + H[7] * (sg * cc[1])) + H[8] * (sg * cc[2]);
+            const double ax = from_i ? xi : pj.x, ay = from_i ? yi : pj.y, az = from_i ? zi : pj.z;
+            const double bx = from_i ? pj.x : xi, by = from_i ? pj.y : yi, bz = from_i ? pj.z : zi;
+            ddx = (bx + sx) - ax;
+            ddy = (by + sy) - ay;
+            ddz = (bz + sz) - az;
+        } else {
+            ddx = pj.x - xi;
+            ddy = pj.y - yi;
+            ddz = pj.z - zi;
+        }
+        const double dd = (ddx * ddx + ddy * ddy) + ddz * ddz;
+        if (dd < sc * sc) f((int32_t)j, idj, packed);
+    };
+    // one group of cells: up to three along x from (dx0, dy, dz); their
+    // ranges are loaded together, then their spheres are visited as one
+    // sequence, two at a time (the loads of both are issued before either
+    // is tested)
+    auto group = [&](int dz, int dy, int dx0) {
+        int ny = c[1] + dy, nz = c[2] + dz, wy = 0, wz = 0;
+        bool skip_row = false;
+        wrap_axis<PERIODIC>(ny, V.dims[1], wy, skip_row);
+        wrap_axis<PERIODIC>(nz, V.dims[2], wz, skip_row);
+        if (skip_row) return;
+        const int row_lin = V.offset + V.dims[0] * (ny + V.dims[1] * nz);
+        uint32_t st[3], en[3];
+        int wx[3];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            int nx = c[0] + dx0 + t;
+            bool skip = dx0 + t > kk[0];
+            wx[t] = 0;
+            wrap_axis<PERIODIC>(nx, V.dims[0], wx[t], skip);
+            st[t] = kEmpty;
+            en[t] = 0;
+            if (!skip) {
+                st[t] = a.cell_start[row_lin + nx];
+                en[t] = a.cell_end[row_lin + nx];
             }
+        }
+        const uint32_t c0 = st[0] == kEmpty ? 0u : en[0] - st[0];
+        const uint32_t c1 = st[1] == kEmpty ? 0u : en[1] - st[1];
+        const uint32_t c2 = st[2] == kEmpty ? 0u : en[2] - st[2];
+        const uint32_t tot = c0 + c1 + c2;
+        auto at = [&](uint32_t k, int& wk) -> uint32_t {
+            uint32_t q;
+            if (k < c0) {
+                q = st[0] + k;
+                wk = wx[0];
+            } else if (k < c0 + c1) {
+                q = st[1] + (k - c0);
+                wk = wx[1];
+            } else {
+                q = st[2] + (k - c0 - c1);
+                wk = wx[2];
+            }
+            return lv == 0 ? q : g.large_slot[q];
+        };
+        for (uint32_t k = 0; k < tot; k += 2) {
+            const bool two_here = k + 1 < tot;
+            int wa, wb;
+            const uint32_t ja = at(k, wa);
+            const uint32_t jb = at(two_here ? k + 1 : k, wb);
+            const double4 pa = B.xr[ja], pb = B.xr[jb];
+            const int32_t pera = PERIODIC ? B.period[ja] : 0, perb = PERIODIC ? B.period[jb] : 0;
+            const int32_t ida = B.id[ja], idb = B.id[jb];
+            visit(ja, pa, pera, ida, wa, wy, wz);
+            if (two_here) visit(jb, pb, perb, idb, wb, wy, wz);
+        }
+    };
+    if (SPLIT) {
+        // group gi = ((dz * ndy) + dy) * nch + chunk, lane `part` taking
+        // every 64th, so that the wave's lanes search at the same time
+        const int nch = (2 * kk[0] + 3) / 3, ndy = 2 * kk[1] + 1, ng = nch * ndy * (2 * kk[2] + 1);
+        for (int gi = part; gi < ng; gi += 64) {
+            const int ch = gi % nch, r = gi / nch;
+            group(r / ndy - kk[2], r % ndy - kk[1], 3 * ch - kk[0]);
+        }
+    } else {
+        for (int dz = -kk[2]; dz <= kk[2]; ++dz)
+            for (int dy = -kk[1]; dy <= kk[1]; ++dy)
+                for (int dx0 = -kk[0]; dx0 <= kk[0]; dx0 += 3) group(dz, dy, dx0);
     }
-    for (int k = 0; k < P.wall_count; ++k) {
+    }
+    for (int k = SPLIT ? part : 0; k < P.wall_count; k += SPLIT ? 64 : 1) {
         const int wi = P.wall_begin + k;
         const Wall W = a.walls[wi];
         if (W.kind == kPlane) {
@@ -449,14 +512,13 @@ __device__ inline void for_each_candidate(const SweepArgs& a, int i, F&& f)
 }
 
 // The sweeps run in two passes when a scene has two levels: the spheres of
-// level 0 first (LARGE = false; a large sphere's lane returns at once), then
-// the large ones through their index array (LARGE = true), so that a wave
-// holds sweeps of one kind (a large sphere searches many more cells).
-template <bool BATCHED, bool LARGE>
+// level 0 first, one per lane (a large sphere's lane returns at once), then
+// the large ones through their index array, one per wave (a large sphere
+// searches many more cells, which the wave's lanes share).
+template <bool BATCHED>
 __device__ inline int sweep_body(const SweepArgs& a)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (LARGE) return t < a.nlarge ? (int)a.g.large_slot[t] : -1;
     if (t >= a.g.nslots) return -1;
     if (a.nlarge > 0) {
         const int s = BATCHED ? (int)a.g.bod.scene[t] : 0;
@@ -466,14 +528,34 @@ __device__ inline int sweep_body(const SweepArgs& a)
     return t;
 }
 
-template <bool BATCHED, bool PERIODIC, bool LARGE>
+template <bool BATCHED, bool PERIODIC>
 __global__ void __launch_bounds__(kBlock) k_sweep_count(SweepArgs a)
 {
-    const int i = sweep_body<BATCHED, LARGE>(a);
+    const int i = sweep_body<BATCHED>(a);
     if (i < 0) return;
     uint32_t n = 0;
     for_each_candidate<BATCHED, PERIODIC>(a, i, [&](int32_t, int32_t, int32_t) { ++n; });
     a.count[i] = n;
+}
+
+// The level-1 sphere of a wave (-1 past the last: the whole wave returns).
+__device__ inline int large_sphere_of_wave(const SweepArgs& a)
+{
+    const int t = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    return t < a.nlarge ? (int)a.g.large_slot[t] : -1;
+}
+
+template <bool BATCHED, bool PERIODIC>
+__global__ void __launch_bounds__(kBlock) k_sweep_count_large(SweepArgs a)
+{
+    const int i = large_sphere_of_wave(a);
+    if (i < 0) return;
+    const int lane = threadIdx.x & 63;
+    uint32_t n = 0;
+    for_each_candidate<BATCHED, PERIODIC, true>(a, i, [&](int32_t, int32_t, int32_t) { ++n; }, lane);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) n += __shfl_down(n, off, 64);
+    if (lane == 0) a.count[i] = n;
 }
 
 // How each row was left by the fill, kept in `count` (the counts are spent
@@ -505,7 +587,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep_fill_staged(SweepArgs a)
     __shared__ int32_t s_pid[kStageEntries];
     __shared__ int32_t s_cell[kStageEntries];
     __shared__ uint32_t s_wave[kBlock / 64];
-    const int i = sweep_body<BATCHED, false>(a);
+    const int i = sweep_body<BATCHED>(a);
     int beg = 0, len = 0;
     if (i >= 0) {
         beg = a.row_start[i];
@@ -564,16 +646,27 @@ __global__ void __launch_bounds__(kBlock) k_sweep_fill_staged(SweepArgs a)
     }
 }
 
-// The level-1 fill: rows in the order found.
+// The level-1 fill, one wave per sphere: each lane counts the candidates
+// of its groups of cells, then writes them after those of the lanes before
+// it (the row is sorted afterwards, so this order only has to be complete).
 template <bool BATCHED, bool PERIODIC>
 __global__ void __launch_bounds__(kBlock) k_sweep_fill_large(SweepArgs a)
 {
-    const int i = sweep_body<BATCHED, true>(a);
+    const int i = large_sphere_of_wave(a);
     if (i < 0) return;
+    const int lane = threadIdx.x & 63;
+    uint32_t mine = 0;
+    for_each_candidate<BATCHED, PERIODIC, true>(a, i, [&](int32_t, int32_t, int32_t) { ++mine; }, lane);
+    uint32_t inc = mine;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += y;
+    }
     const int beg = a.row_start[i];
     const int cap = a.row_start[i + 1] - beg;
-    int n = 0;
-    for_each_candidate<BATCHED, PERIODIC>(a, i, [&](int32_t slot, int32_t pid, int32_t cell) {
+    int n = (int)(inc - mine);
+    for_each_candidate<BATCHED, PERIODIC, true>(a, i, [&](int32_t slot, int32_t pid, int32_t cell) {
         if (n < cap) {
             a.raw_slot[beg + n] = slot;
             a.raw_pid[beg + n] = pid;
@@ -581,8 +674,8 @@ __global__ void __launch_bounds__(kBlock) k_sweep_fill_large(SweepArgs a)
             a.ent_body[beg + n] = i;
         }
         ++n;
-    });
-    a.count[i] = kRowLarge;
+    }, lane);
+    if (lane == 0) a.count[i] = kRowLarge;
 }
 
 // One thread per entry of a level-0 row that the fill left in the order
@@ -895,44 +988,38 @@ void launch_cells_large(const GridArgs& g, const uint64_t* sorted_keys2, int nla
                            cell_start, cell_end, ncells);
 }
 
-#define DEM_SWEEP_LAUNCH(KERNEL, A, ST)                                                                          \
+// The level-0 pass (one sphere per lane) and, with two levels, the level-1
+// pass (one sphere per wave) of a sweep kernel pair.
+#define DEM_SWEEP_LAUNCH(SMALL, LARGE_K, A, ST)                                                                \
     do {                                                                                                      \
-        const dim3 blk(kBlock), g0(nblocks((A).g.nslots)), g1(nblocks((A).nlarge > 0 ? (A).nlarge : 1));     \
+        const dim3 blk(kBlock), g0(nblocks((A).g.nslots));                                                    \
+        const dim3 g1(((A).nlarge + kBlock / 64 - 1) / (kBlock / 64));                                        \
         if ((A).g.nscenes > 1) {                                                                              \
-            hipLaunchKernelGGL((KERNEL<true, false, false>), g0, blk, 0, ST, A);                              \
-            if ((A).nlarge > 0) hipLaunchKernelGGL((KERNEL<true, false, true>), g1, blk, 0, ST, A);           \
+            hipLaunchKernelGGL((SMALL<true, false>), g0, blk, 0, ST, A);                                      \
+            if ((A).nlarge > 0) hipLaunchKernelGGL((LARGE_K<true, false>), g1, blk, 0, ST, A);                \
         } else if ((A).g.scene0.periodic) {                                                                   \
-            hipLaunchKernelGGL((KERNEL<false, true, false>), g0, blk, 0, ST, A);                              \
-            if ((A).nlarge > 0) hipLaunchKernelGGL((KERNEL<false, true, true>), g1, blk, 0, ST, A);           \
+            hipLaunchKernelGGL((SMALL<false, true>), g0, blk, 0, ST, A);                                      \
+            if ((A).nlarge > 0) hipLaunchKernelGGL((LARGE_K<false, true>), g1, blk, 0, ST, A);                \
         } else {                                                                                              \
-            hipLaunchKernelGGL((KERNEL<false, false, false>), g0, blk, 0, ST, A);                             \
-            if ((A).nlarge > 0) hipLaunchKernelGGL((KERNEL<false, false, true>), g1, blk, 0, ST, A);          \
+            hipLaunchKernelGGL((SMALL<false, false>), g0, blk, 0, ST, A);                                     \
+            if ((A).nlarge > 0) hipLaunchKernelGGL((LARGE_K<false, false>), g1, blk, 0, ST, A);               \
         }                                                                                                     \
     } while (0)
 
 void launch_sweep_count(const SweepArgs& a, hipStream_t st)
 {
     if (a.g.nslots <= 0) return;
-    DEM_SWEEP_LAUNCH(k_sweep_count, a, st);
+    DEM_SWEEP_LAUNCH(k_sweep_count, k_sweep_count_large, a, st);
 }
 
 void launch_sweep_fill(const SweepArgs& a, hipStream_t st)
 {
     if (a.g.nslots <= 0) return;
-    const dim3 blk(kBlock), g0(nblocks(a.g.nslots)), g1(nblocks(a.nlarge > 0 ? a.nlarge : 1));
-    if (a.g.nscenes > 1) {
-        hipLaunchKernelGGL((k_sweep_fill_staged<true, false>), g0, blk, 0, st, a);
-        if (a.nlarge > 0) hipLaunchKernelGGL((k_sweep_fill_large<true, false>), g1, blk, 0, st, a);
-    } else if (a.g.scene0.periodic) {
-        hipLaunchKernelGGL((k_sweep_fill_staged<false, true>), g0, blk, 0, st, a);
-        if (a.nlarge > 0) hipLaunchKernelGGL((k_sweep_fill_large<false, true>), g1, blk, 0, st, a);
-    } else {
-        hipLaunchKernelGGL((k_sweep_fill_staged<false, false>), g0, blk, 0, st, a);
-        if (a.nlarge > 0) hipLaunchKernelGGL((k_sweep_fill_large<false, false>), g1, blk, 0, st, a);
-    }
+    DEM_SWEEP_LAUNCH(k_sweep_fill_staged, k_sweep_fill_large, a, st);
     if (a.nent > 0) hipLaunchKernelGGL(k_row_rank, dim3(nblocks(a.nent)), dim3(kBlock), 0, st, a);
     if (a.nlarge > 0)
-        hipLaunchKernelGGL(k_row_rank_large, dim3((a.nlarge + kBlock / 64 - 1) / (kBlock / 64)), blk, 0, st, a);
+        hipLaunchKernelGGL(k_row_rank_large, dim3((a.nlarge + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0, st,
+                           a);
 }
 
 void launch_pair_build(const PairBuildArgs& a, hipStream_t st)

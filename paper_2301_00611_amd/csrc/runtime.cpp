@@ -113,6 +113,36 @@ struct BodySet {
     }
 };
 
+// A growable pinned host buffer: a device-to-host copy into it is one DMA
+// transfer (pageable memory is copied through a staging buffer, piece by
+// piece, each piece waited for).
+struct HBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    void ensure(size_t need)
+    {
+        if (need <= bytes && p) return;
+        size_t nb = std::max<size_t>(need + need / 2, 256);
+        void* q = nullptr;
+        if (hipHostMalloc(&q, nb, hipHostMallocDefault) != hipSuccess)
+            fail(DEM_ENOMEM, "pinned host allocation of " + std::to_string(nb) + " bytes failed");
+        if (p) (void)hipHostFree(p);
+        p = q;
+        bytes = nb;
+    }
+    void release()
+    {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T>
+    T* as() const
+    {
+        return static_cast<T*>(p);
+    }
+};
+
 struct PairSet {
     DBuf a, b, cell, pid, real, ea, eb, hist, frec;  // partitioned order (touching pairs first)
     DBuf hpid, hcell, hmap;                     // canonical (owner-sorted) order, for the next run's lookup
@@ -255,6 +285,7 @@ struct World {
     bool slots_fresh = true;           // no step has written the slots since the last fold
     std::vector<SceneParams> sp;       // host copy of the scene table
     Counters* h_ctr = nullptr;         // pinned
+    HBuf h_slots_c, h_slots_i;         // the per-block slots as read back
     // pinned: what the host writes into the counters before a launch chain
     // (steps_done = 0, halt = 0, iter0), the 16 bytes from steps_done on
     struct ChunkStart {
@@ -312,6 +343,8 @@ struct World {
             d->release();
         if (h_ctr) (void)hipHostFree(h_ctr);
         h_ctr = nullptr;
+        h_slots_c.release();
+        h_slots_i.release();
         if (h_chunk) (void)hipHostFree(h_chunk);
         h_chunk = nullptr;
         if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -1094,6 +1127,14 @@ struct World {
             HIPC(hipGetLastError());
             pactive = 1 - pactive;
             old_ngids = ng;
+            // The previous list is not read again once this run's kernels
+            // are done: size it for the new list's pairs now, so that the next
+            // run (which fills it) allocates nothing.  A buffer it outgrows
+            // is freed by hipFree, which waits for the device first.
+            PairSet& spare = ps[1 - pactive];
+            spare.ensure(np, precision == DEM_FP32_MIXED);
+            spare.own_begin.ensure(4 * (size_t)std::max(ng, 1));
+            spare.own_count.ensure(4 * (size_t)std::max(ng, 1));
         } else {
             npairs_new = 0;
             n_candidates = 0;
@@ -1177,12 +1218,19 @@ struct World {
     SlotSums read_slots()
     {
         SlotSums t;
-        std::vector<ContactAcc> c((size_t)acc_c_n);
-        std::vector<IntAcc> i((size_t)acc_i_n);
-        if (acc_c_n) HIPC(hipMemcpyAsync(c.data(), d_part_c.p, sizeof(ContactAcc) * c.size(), hipMemcpyDeviceToHost, stream));
-        if (acc_i_n) HIPC(hipMemcpyAsync(i.data(), d_part_i.p, sizeof(IntAcc) * i.size(), hipMemcpyDeviceToHost, stream));
+        h_slots_c.ensure(sizeof(ContactAcc) * (size_t)std::max(acc_c_n, 1));
+        h_slots_i.ensure(sizeof(IntAcc) * (size_t)std::max(acc_i_n, 1));
+        const ContactAcc* c = h_slots_c.as<ContactAcc>();
+        const IntAcc* i = h_slots_i.as<IntAcc>();
+        if (acc_c_n)
+            HIPC(hipMemcpyAsync(h_slots_c.p, d_part_c.p, sizeof(ContactAcc) * (size_t)acc_c_n, hipMemcpyDeviceToHost,
+                                stream));
+        if (acc_i_n)
+            HIPC(hipMemcpyAsync(h_slots_i.p, d_part_i.p, sizeof(IntAcc) * (size_t)acc_i_n, hipMemcpyDeviceToHost,
+                                stream));
         HIPC(hipStreamSynchronize(stream));
-        for (const ContactAcc& a : c) {
+        for (int k = 0; k < acc_c_n; ++k) {
+            const ContactAcc& a = c[k];
             t.el += a.el;
             t.plast += a.plast;
             t.visc += a.visc;
@@ -1190,7 +1238,8 @@ struct World {
             t.sw += a.sw;
             t.cum += a.ss_cum + a.sw_cum;
         }
-        for (const IntAcc& a : i) {
+        for (int k = 0; k < acc_i_n; ++k) {
+            const IntAcc& a = i[k];
             t.kin += a.kin;
             t.rot += a.rot;
             t.grav += a.grav;
