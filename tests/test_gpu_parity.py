@@ -423,3 +423,32 @@ def test_long_rows_summed_by_the_wave(precision, tol):
     dw = np.linalg.norm(sg["angvel"][big] - so["angvel"][big], axis=1)
     inertia = 0.4 * m * R * R
     assert np.all(dw <= tol * scale[big] * R * dt / inertia + 4 * EPS * np.linalg.norm(so["angvel"][big], axis=1))
+
+
+@pytest.mark.parametrize("rmin,rmax", [(0.8e-3, 1.2e-3), (0.5e-3, 1.5e-3)])
+def test_rows_past_the_fill_pool(rmin, rmax):
+    """A Verlet distance of three smallest radii gives every sphere of a
+    dense walled cloud tens of candidates, far more than the 8 per sphere
+    that a block of the level-0 fill holds in LDS: the first rows of each
+    block are sorted there, the others are written in the order found and
+    sorted one thread per entry, and (size ratio 3, two grid levels) the
+    large spheres' rows, walls among them, are found and sorted one wave
+    per sphere. Pair sets bit-exact and forces within 1e-12 of the oracle
+    after one step and after ten more."""
+    from paper_2301_00611_amd.scenes import random_velocities
+    n, seed = 1500, 5
+    spec = _dense_spec(n, seed, rmin=rmin, rmax=rmax)
+    v, w = random_velocities(n, 0.05, seed + 100)
+    g, o, dt = twin(spec, vel=v, angvel=w * 0.05, verlet_dist=-3.0)
+    g.step(1)
+    o.step(1)
+    assert 2 * g.stats()["n_candidates"] > 16 * n, "rows should run well past the pool's 8 entries per sphere"
+    cg, co = g.get_contacts(), o.get_contacts()
+    assert len(co) > n // 8
+    assert keyset(cg) == keyset(co)
+    assert contact_errors(cg, co)["f"].max() <= 1e-12
+    ef, _ = body_force_errors(g.get_state(), o.get_state(), co)
+    assert ef.max() <= 1e-12
+    g.step(10)
+    o.step(10)
+    assert keyset(g.get_contacts()) == keyset(o.get_contacts())
