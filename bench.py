@@ -589,8 +589,8 @@ def main():
                     help="run a plain 256 MiB device copy three times (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(multi-GPU decomposition is a design note only)", file=sys.stderr)
+        print(f"bench.py: the library runs a scene on one GPU; --gpus {args.gpus} is not supported "
+              "(the decomposition over several GPUs is a design note only)", file=sys.stderr)
         sys.exit(2)
     log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)
     if args.copy_calibration:
