@@ -37,6 +37,12 @@ MUTATIONS = {
     "wall_reference_radius": ("n[w->axis] = (double)wall_sign(w, sp);\n        *R1 = sp->r;",
                               "n[w->axis] = (double)wall_sign(w, sp);\n        *R1 = 0.5 * sp->r;"),
     "plastic_work_without_fmax": ("*e_plast += (fs_norm - fmax) * fmax / ks;", "*e_plast += (fs_norm - fmax) / ks;"),
+    "plastic_work_at_trial_force": ("*e_plast += (fs_norm - fmax) * fmax / ks;",
+                                    "*e_plast += (fs_norm - fmax) * fs_norm / ks;"),
+    "shear_energy_with_kn": ("*e_el += 0.5 * (fn_mag * fn_mag / kn) + 0.5 * (dot3(fs, fs) / ks);",
+                             "*e_el += 0.5 * (fn_mag * fn_mag / kn) + 0.5 * (dot3(fs, fs) / kn);"),
+    "shear_energy_factor": ("*e_el += 0.5 * (fn_mag * fn_mag / kn) + 0.5 * (dot3(fs, fs) / ks);",
+                            "*e_el += 0.5 * (fn_mag * fn_mag / kn) + 1.0 * (dot3(fs, fs) / ks);"),
     "rotation_angle_doubled": ("double half = 0.5 * wn * dt;", "double half = wn * dt;"),
     "overlap_dependent_branch": ("rw[k] = R2 * w2[k] + R1 * w1[k];",
                                  "rw[k] = (R2 - 0.5 * pen) * w2[k] + (R1 - 0.5 * pen) * w1[k];"),

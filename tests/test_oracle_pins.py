@@ -445,6 +445,39 @@ def test_elastic_energy_conserved_frictionless():
     assert abs(drift2) < abs(drift1) or abs(drift2) < 2e-4
 
 
+def test_prescribed_slip_elastic_energy_and_plastic_work():
+    """A sphere with every DOF blocked, pressed into a floor by a fixed
+    overlap d and driven along it at a constant v0: the normal is constant
+    and the sphere does not spin, so the shear spring loads by ks v0 dt per
+    step. While it sticks, E_el = kn d^2/2 + ks (v0 t)^2/2 and nothing is
+    dissipated; once |Fs| passes the cap c = kn d tan(phi) it slides at
+    |Fs| = c, and the plastic work up to t is c (v0 t - c/ks): the driving
+    work past the point where the spring held c, which the per-step slips
+    (trial minus capped force, over ks, times the capped force) sum to
+    exactly.  Guards the elastic-energy halves and stiffnesses and the
+    plastic-dissipation formula (capped, not trial, force; the 1/ks)."""
+    r, E, nu, phi = 1e-3, 1e7, 0.3, 0.4
+    kn, ks = E * r, nu * E * r
+    d, dt = 1e-5, 1e-6
+    cap = kn * d * math.tan(phi)
+    v0 = cap / (ks * 100.5 * dt)  # the cap falls between steps 100 and 101
+    s = _floor_scene(dt, d, (0.0, 0.0, 0.0), phi=phi, blocked=63, vel=[[v0, 0.0, 0.0]], E=E, nu=nu)
+    for k in (40, 80):
+        s.step(40)
+        t = k * dt
+        e, c = s.get_energy(), s.get_contacts()
+        assert len(c) == 1 and c["fs"][0][0] < 0  # friction on the sphere opposes the drive
+        assert np.linalg.norm(c["fs"][0]) == pytest.approx(ks * v0 * t, rel=1e-12)
+        assert e["elastic"] == pytest.approx(0.5 * kn * d * d + 0.5 * ks * (v0 * t) ** 2, rel=1e-12)
+        assert e["plastic_dissip"] == 0.0
+    s.step(420)
+    t = 500 * dt
+    e, c = s.get_energy(), s.get_contacts()
+    assert np.linalg.norm(c["fs"][0]) == pytest.approx(cap, rel=1e-12)
+    assert e["elastic"] == pytest.approx(0.5 * kn * d * d + 0.5 * cap * cap / ks, rel=1e-12)
+    assert e["plastic_dissip"] == pytest.approx(cap * (v0 * t - cap / ks), rel=1e-9)
+
+
 def test_coulomb_bound_every_step():
     s = _gas(seed=11, vscale=0.3, phi=0.3, damping=0.1)
     eps = np.finfo(float).eps
