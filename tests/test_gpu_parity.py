@@ -452,3 +452,58 @@ def test_rows_past_the_fill_pool(rmin, rmax):
     g.step(10)
     o.step(10)
     assert keyset(g.get_contacts()) == keyset(o.get_contacts())
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-5)])
+def test_mixed_materials_one_step(precision, tol):
+    """Spheres of two materials (density, E, poisson and friction angle all
+    different) between walls of a third: each pair's stiffnesses come from
+    its two materials' springs in series and its friction angle is the
+    smaller one. One step from identical states with injected shear
+    history: pair sets bit-exact, forces within the precision's bar, every
+    combination of materials present; ten more steps: pair sets still
+    identical."""
+    from oracle import OracleScene
+    from paper_2301_00611_amd import dem
+    from paper_2301_00611_amd.scenes import random_velocities
+    n, seed = 1500, 11
+    spec = _dense_spec(n, seed)
+    which = np.random.default_rng(seed).integers(0, 2, size=n)
+    sphere_mats = [(2600.0, 1e7, 0.3, 0.5), (1800.0, 3e7, 0.2, 0.3)]
+    wall_mat = (2600.0, 5e6, 0.25, 0.7)
+    v, w = random_velocities(n, 0.05, seed + 100)
+    g = dem.Scene(gravity=spec.gravity, damping=spec.damping, track_energy=True, precision=precision,
+                  verlet_dist=-0.5)
+    gm = [g.add_material(*m) for m in sphere_mats]
+    gw = g.add_material(*wall_mat)
+    for wl in spec.walls:
+        g.add_wall(wl.axis, wl.position, wl.sense, gw)
+    g.add_spheres(spec.pos, spec.radius, vel=v, angvel=w * 0.05, mat=np.asarray(gm)[which])
+    dt = spec.dt_factor * g.pwave_dt()
+    g.set_dt(dt)
+    o = OracleScene(dt=dt, gravity=spec.gravity, damping=spec.damping)
+    om = [o.add_material(*m) for m in sphere_mats]
+    ow = o.add_material(*wall_mat)
+    for wl in spec.walls:
+        o.add_wall(wl.axis, wl.position, wl.sense, ow)
+    o.add_spheres(spec.pos, spec.radius, vel=v, angvel=w * 0.05, mat=np.asarray(om)[which])
+    assert o.pwave_dt() == g.pwave_dt()
+    hist = random_history(spec.pos, spec.radius, spec.walls, np.random.default_rng(seed + 7))
+    if hist is not None:
+        g.set_history(*hist)
+        o.set_contacts(*hist)
+    g.step(1)
+    o.step(1)
+    cg, co = g.get_contacts(), o.get_contacts()
+    assert len(co) > n // 8
+    assert keyset(cg) == keyset(co)
+    nw = len(spec.walls)
+    kind = lambda i: 2 if i < nw else int(which[i - nw])
+    combos = {tuple(sorted((kind(a), kind(b)))) for a, b in zip(co["id1"].tolist(), co["id2"].tolist())}
+    assert {(0, 0), (0, 1), (1, 1)} <= combos and any(2 in c for c in combos)
+    assert contact_errors(cg, co)["f"].max() <= tol
+    ef, _ = body_force_errors(g.get_state(), o.get_state(), co)
+    assert ef.max() <= tol
+    g.step(10)
+    o.step(10)
+    assert keyset(g.get_contacts()) == keyset(o.get_contacts())

@@ -159,10 +159,14 @@ def test_head_on_collision_closed_form():
 
 
 def _floor_scene(dt, pen0, gravity, phi=0.5, damping=0.0, blocked=None, vel=None, angvel=None,
-                 wall_phi=None, r=1e-3, E=1e7, nu=0.3):
+                 wall_phi=None, r=1e-3, E=1e7, nu=0.3, wall_E=None, wall_nu=None):
     s = OracleScene(dt=dt, gravity=gravity, damping=damping)
     sm = s.add_material(2600.0, E, nu, phi)
-    wm = sm if wall_phi is None else s.add_material(2600.0, E, nu, wall_phi)
+    if wall_phi is None and wall_E is None and wall_nu is None:
+        wm = sm
+    else:
+        wm = s.add_material(2600.0, E if wall_E is None else wall_E, nu if wall_nu is None else wall_nu,
+                            phi if wall_phi is None else wall_phi)
     s.add_wall(2, 0.0, 1, wm)
     s.add_spheres([[0, 0, r - pen0]], [r], vel=vel, angvel=angvel, default_mat=sm,
                   blocked=None if blocked is None else [blocked])
@@ -445,7 +449,8 @@ def test_elastic_energy_conserved_frictionless():
     assert abs(drift2) < abs(drift1) or abs(drift2) < 2e-4
 
 
-def test_prescribed_slip_elastic_energy_and_plastic_work():
+@pytest.mark.parametrize("wall", [None, (3e7, 0.2, 0.6)])
+def test_prescribed_slip_elastic_energy_and_plastic_work(wall):
     """A sphere with every DOF blocked, pressed into a floor by a fixed
     overlap d and driven along it at a constant v0: the normal is constant
     and the sphere does not spin, so the shear spring loads by ks v0 dt per
@@ -454,14 +459,27 @@ def test_prescribed_slip_elastic_energy_and_plastic_work():
     |Fs| = c, and the plastic work up to t is c (v0 t - c/ks): the driving
     work past the point where the spring held c, which the per-step slips
     (trial minus capped force, over ks, times the capped force) sum to
-    exactly.  Guards the elastic-energy halves and stiffnesses and the
-    plastic-dissipation formula (capped, not trial, force; the 1/ks)."""
+    exactly.  With a wall of another material (E, nu, phi) the two
+    materials' springs act in series (section 2.1.3: K_N^-1 = K_1^-1 +
+    K_2^-1 with K_i = E_i 2 r_i, the wall's reference radius being the
+    sphere's), the shear springs likewise with E_i nu_i 2 r_i, and the
+    smaller friction angle holds.  Guards the elastic-energy halves and
+    stiffnesses, the plastic-dissipation formula (capped, not trial, force;
+    the 1/ks) and how two materials combine."""
     r, E, nu, phi = 1e-3, 1e7, 0.3, 0.4
-    kn, ks = E * r, nu * E * r
+    if wall is None:
+        kn, ks, tanphi = E * r, nu * E * r, math.tan(phi)
+        extra = {}
+    else:
+        Ew, nuw, phiw = wall
+        kn = 1.0 / (1.0 / (E * 2 * r) + 1.0 / (Ew * 2 * r))
+        ks = 1.0 / (1.0 / (E * nu * 2 * r) + 1.0 / (Ew * nuw * 2 * r))
+        tanphi = math.tan(min(phi, phiw))
+        extra = dict(wall_E=Ew, wall_nu=nuw, wall_phi=phiw)
     d, dt = 1e-5, 1e-6
-    cap = kn * d * math.tan(phi)
+    cap = kn * d * tanphi
     v0 = cap / (ks * 100.5 * dt)  # the cap falls between steps 100 and 101
-    s = _floor_scene(dt, d, (0.0, 0.0, 0.0), phi=phi, blocked=63, vel=[[v0, 0.0, 0.0]], E=E, nu=nu)
+    s = _floor_scene(dt, d, (0.0, 0.0, 0.0), phi=phi, blocked=63, vel=[[v0, 0.0, 0.0]], E=E, nu=nu, **extra)
     for k in (40, 80):
         s.step(40)
         t = k * dt
@@ -613,6 +631,27 @@ def test_affine_motion_in_periodic_cell():
         res[hd] = np.linalg.norm(s.get_state()["pos"][0] - trsf @ x0)
     assert res[2] <= 1e-15
     assert res[1] > 1e-9
+
+
+def test_cell_follows_the_velocity_gradient_in_a_non_cubic_cell():
+    """Section 2.1.6: the cell's base vectors move with the velocity
+    gradient, H+ = (I + L dt) H, and so does the transformation from the
+    initial cell.  Under simple shear L^2 = 0, so k steps give exactly
+    H = (I + k dt L) H0 and trsf = I + k dt L.  The cell is neither cubic
+    nor diagonal, so that L H0 and H0 L differ (an update on the wrong
+    side, H (I + L dt), fails)."""
+    dt, k = 1e-4, 300
+    H0 = np.array([[0.10, 0.0, 0.02], [0.0, 0.08, 0.0], [0.0, 0.0, 0.12]])
+    L = np.zeros((3, 3))
+    L[0, 2] = 1.5
+    s = OracleScene(dt=dt, periodic=True, hsize=H0, velgrad=L, homo_deform=2)
+    s.add_material(2600.0, 1e7, 0.3, 0.5)
+    s.add_spheres([[0.05, 0.04, 0.06]], [1e-3])
+    s.step(k)
+    H, trsf = s.get_cell()
+    np.testing.assert_allclose(H, H0 + k * dt * (L @ H0), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(trsf, np.eye(3) + k * dt * L, rtol=0, atol=1e-14)
+    assert abs((L @ H0 - H0 @ L)[0, 2]) * k * dt > 1e-6  # the two sides differ by far more than that
 
 
 def _sheared_pair(shift_cells):
