@@ -37,6 +37,7 @@ MUTATIONS = {
     "wall_reference_radius": ("n[w->axis] = (double)wall_sign(w, sp);\n        *R1 = sp->r;",
                               "n[w->axis] = (double)wall_sign(w, sp);\n        *R1 = 0.5 * sp->r;"),
     "plastic_work_without_fmax": ("*e_plast += (fs_norm - fmax) * fmax / ks;", "*e_plast += (fs_norm - fmax) / ks;"),
+    "spin_radii_swapped": ("rw[k] = R2 * w2[k] + R1 * w1[k];", "rw[k] = R1 * w2[k] + R2 * w1[k];"),
     "cell_update_on_the_right": ("matmul(M, s->H, s->H);", "matmul(s->H, M, s->H);"),
     "normal_stiffness_arithmetic_mean": ("*kn = k1 * k2 / (k1 + k2);", "*kn = 0.25 * (k1 + k2);"),
     "shear_stiffness_from_one_material": ("*ks = s1 * s2 / (s1 + s2);", "*ks = *kn * m1->poisson;"),

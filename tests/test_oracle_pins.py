@@ -323,6 +323,37 @@ def test_ratchet_cycle_closes():
     assert np.linalg.norm(s.get_contacts()["fs"][0]) <= 1e-9 * ks * r * a
 
 
+@pytest.mark.parametrize("spinning", [0, 1])
+def test_spin_drags_the_contact_by_its_own_radius(spinning):
+    """Two blocked spheres of radii 2 and 1 mm at a fixed overlap, one of
+    them spinning at a constant W about an axis normal to the contact: its
+    surface at the contact point moves at W R (its own radius, the lever
+    arm the ScGeom relative velocity takes), the other's is at rest, the
+    normal never turns, so the shear force grows as ks W R t: the resting
+    sphere is dragged along the spinning one's surface velocity, and the
+    spinning one is held back against it.  Guards which radius multiplies
+    which spin."""
+    R = (2e-3, 1e-3)
+    E, nu, d, dt, W = 1e7, 0.3, 1e-5, 1e-6, 3.0
+    s = OracleScene(dt=dt)
+    s.add_material(2600.0, E, nu, 1.5)
+    ang = np.zeros((2, 3))
+    ang[spinning] = (0.0, 0.0, W)
+    s.add_spheres([[0.0, 0.0, 0.0], [R[0] + R[1] - d, 0.0, 0.0]], list(R), angvel=ang, blocked=[63, 63])
+    ks = 1.0 / (1.0 / (E * nu * 2 * R[0]) + 1.0 / (E * nu * 2 * R[1]))
+    k = 400
+    s.step(k)
+    c = s.get_contacts()
+    assert len(c) == 1
+    fs = c["fs"][0]
+    # the spinning sphere's surface at the contact moves along z x (+-x): +y
+    # for the first sphere (contact on its +x side), -y for the second.  The
+    # reported force acts on the second sphere: dragged along +y when the
+    # first spins, held back against its own -y motion when it spins itself.
+    assert fs[1] == pytest.approx(ks * W * R[spinning] * k * dt, rel=1e-12)
+    assert abs(fs[0]) <= 1e-12 * abs(fs[1]) and abs(fs[2]) <= 1e-12 * abs(fs[1])
+
+
 def _rigid_rotation(axis_kind):
     """Two overlapping spheres carrying a shear force, rotated as one rigid
     body at rate W.  Returns (Fs after K steps, Fs0 rotated by W t, normal)."""
