@@ -110,6 +110,18 @@ def test_stiffness_dt_diagonal_contact():
     assert stiffness_dt(s, 0.8) == pytest.approx(expected, rel=1e-12)
 
 
+def test_stiffness_dt_diagonal_contact_rotations_blocked():
+    """The diagonal contact with every rotation blocked: only eq. 2.14's
+    translational terms are left, K_xx = K_yy = (k_n + k_s)/2 and K_zz = k_s,
+    so dt = safety sqrt(2) sqrt(2 m / (E r (1 + nu))) (guards the tangential
+    k_s in the translational stiffness, which the rotation hides above)."""
+    c = 1.5 * R / math.sqrt(2.0)
+    s = _scene([[0, 0, 0], [c, c, 0]], blocked=[56, 56])
+    s.step(1)
+    expected = 0.8 * math.sqrt(2.0) * math.sqrt(2.0 * _mass() / (E * R * (1 + NU)))
+    assert stiffness_dt(s, 0.8) == pytest.approx(expected, rel=1e-12)
+
+
 def test_stiffness_dt_without_contacts_is_pwave():
     s = _scene([[0, 0, 0], [3.0 * R, 0, 0]])
     s.step(1)
@@ -212,6 +224,79 @@ def test_controller_done_at_once_when_at_goal():
     assert c.done and c.updates == 1
 
 
+def test_strain_axis_ends_at_the_log_strain():
+    """Strain axes only, on a cell holding one free sphere (no contact): each
+    update sets (goal - strain)/T with the strain the log of the cell
+    transformation's diagonal, so the cell converges to trsf_ii =
+    exp(goal_i), not 1 + goal_i, and the cell's side to its initial side
+    times that (guards the logarithmic strain; the goals are large enough
+    for the two to differ by percents)."""
+    H0 = np.diag([0.1, 0.12, 0.09])
+    s = OracleScene(dt=1.0, periodic=True, hsize=H0)
+    mat = s.add_material(RHO, E, NU, 0.5)
+    s.add_spheres([[0.05, 0.06, 0.045]], [R], default_mat=mat)
+    s.set_dt(0.2 * s.pwave_dt())
+    goal = (-0.2, 0.15, -0.1)
+    c = PeriTriax(s, goal=goal, stress_mask=0, glob_update=5, max_strain_rate=(1e9,) * 3)
+    c.run(400)
+    _, trsf = s.get_cell()
+    for i in range(3):
+        assert trsf[i, i] == pytest.approx(math.exp(goal[i]), rel=1e-9)
+        assert abs(math.exp(goal[i]) - (1.0 + goal[i])) > 1e-3
+    np.testing.assert_allclose(np.diag(s.get_cell()[0]), np.diag(H0) * np.exp(goal), rtol=1e-9)
+
+
+def test_controller_unbalanced_force_gates_the_goal():
+    """At the stress goal from the start but with a jittered lattice
+    (unbalanced force of order one): not done while max_unbalanced is below
+    that force, done at the first update once it is above (guards the
+    equilibrium condition of the stress-controlled cell)."""
+    s, a, delta = _lattice()
+    rng = np.random.default_rng(3)
+    st = s.get_state()
+    s.set_state(pos=st["pos"] + rng.uniform(-0.2, 0.2, st["pos"].shape) * delta)
+    s.step(1)
+    ub = unbalanced_force(s)
+    H = s.get_cell()[0]
+    sig = np.diag(s.get_stress(abs(np.linalg.det(H))))
+    c = PeriTriax(s, goal=tuple(sig), stress_mask=7, glob_update=1, max_unbalanced=0.5 * ub,
+                  abs_stress_tol=1e6)
+    c.update()
+    assert not c.done
+    c2 = PeriTriax(s, goal=tuple(sig), stress_mask=7, glob_update=1, max_unbalanced=10 * ub,
+                   abs_stress_tol=1e6)
+    c2.update()
+    assert c2.done and c2.strain_rate == [0.0, 0.0, 0.0]
+
+
+@pytest.mark.parametrize("which", ["absolute", "relative"])
+@pytest.mark.parametrize("controller", ["triax", "iso"])
+def test_either_stress_tolerance_suffices(which, controller):
+    """A goal 0.5 % away from the resting lattice's stress, with one
+    tolerance at 1 % and the other at 1e-9: reached at the first update
+    either way (the tolerance is the larger of the absolute and the
+    relative one), not reached when both are at 1e-9."""
+    from oracle.controls import PeriIsoCompressor
+    s, a, delta = _lattice()
+    sig = -E * R * delta / a ** 2
+    goal = 1.005 * sig
+    tight = 1e-9
+    abs_tol, rel_tol = (1e-2 * abs(sig), tight) if which == "absolute" else (tight * abs(sig), 1e-2)
+
+    def make(at, rt):
+        if controller == "triax":
+            return PeriTriax(s, goal=(goal,) * 3, stress_mask=7, glob_update=5, abs_stress_tol=at,
+                             rel_stress_tol=rt)
+        return PeriIsoCompressor(s, [goal], global_update_int=5, abs_stress_tol=at, rel_stress_tol=rt)
+
+    c = make(abs_tol, rel_tol)
+    c.run(5)
+    assert c.done
+    c2 = make(tight * abs(sig), tight)
+    c2.update()
+    assert not c2.done
+
+
 def test_modulus_of_a_diagonal_contact():
     """One contact along (1, 1, 0)/sqrt2 at centre distance l: d_i n_i =
     l n_i^2 = l/2 on x and y, 0 on z, so M = k_n l^2 / (4 V) on x and y
@@ -284,15 +369,18 @@ def test_iso_series_reaches_each_stress_in_turn():
     tol = 1e-3 * abs(sig0)
     c = PeriIsoCompressor(s, [1.5 * sig0, 2.0 * sig0], global_update_int=5, max_strain_rate=1e3,
                           abs_stress_tol=tol, rel_stress_tol=0.0, max_unbalanced=1e-6)
-    switched_at = None
+    switched_at = switch_rate = None
     for _ in range(1000):
         before = c.state
         c.run(5)
         if before == 0 and c.state == 1:
-            switched_at = c.sigma
+            switched_at, switch_rate = c.sigma, c.strain_rate
         if c.done:
             break
     assert switched_at is not None and abs(switched_at - 1.5 * sig0) <= tol
+    # the update that reaches the first stress already drives towards the
+    # second (more compression: a negative rate), it does not idle a period
+    assert switch_rate is not None and switch_rate < 0.0
     assert c.done and c.state == 1 and abs(c.sigma - 2.0 * sig0) <= tol
     assert c.strain_rate == 0.0
     h0 = s.get_cell()[0]

@@ -138,3 +138,68 @@ def test_viscel_pins_catch_mutation(name, tmp_path):
                        env=env, capture_output=True, text=True, cwd=ROOT, timeout=600)
     assert r.returncode != 0, f"no pin caught mutation {name}:\n{r.stdout[-2000:]}"
     assert "FAILED" in r.stdout
+
+
+# slips in the controllers (oracle/controls.py, Python), caught by
+# tests/test_oracle_controls.py: the mutated source is executed into the
+# module in a child process before the pins are collected there
+CONTROL_MUTATIONS = {
+    "control_no_grow_damping": ("rate = (1.0 - self.grow_damping) * err / (M[i] * T)",
+                                "rate = err / (M[i] * T)"),
+    "control_period_without_interval": ("T = self.glob_update * sc.dt", "T = sc.dt"),
+    "control_linear_strain": ("self.strain[i] = math.log(float(trsf[i, i]))",
+                              "self.strain[i] = float(trsf[i, i]) - 1.0"),
+    "control_goal_ignores_unbalanced": ("        if not (self.unbalanced <= self.max_unbalanced):\n"
+                                        "            reached = False\n", ""),
+    "control_tolerance_min": ("if abs(err) > max(self.abs_tol, self.rel_tol * abs(self.goal[i])):",
+                              "if abs(err) > min(self.abs_tol, self.rel_tol * abs(self.goal[i])):"),
+    "control_rate_not_capped": ("rates[i] = max(-self.max_rate[i], min(self.max_rate[i], rate))",
+                                "rates[i] = rate"),
+    "modulus_branch_not_squared": ('M[i] += float(c["kn"]) * (di * ni) * (di * ni)',
+                                   'M[i] += float(c["kn"]) * (di * ni)'),
+    "iso_modulus_sum_not_mean": ("self.stiff = (M[0] + M[1] + M[2]) / 3.0", "self.stiff = (M[0] + M[1] + M[2])"),
+    "iso_tolerance_min": ("return (abs(goal - self.sigma) <= max(self.abs_tol, self.rel_tol * abs(goal))",
+                          "return (abs(goal - self.sigma) <= min(self.abs_tol, self.rel_tol * abs(goal))"),
+    "iso_next_stress_a_period_late": ("        if reached and self.state + 1 < len(self.stresses):\n"
+                                      "            self.state += 1\n            reached = False\n",
+                                      "        if reached and self.state + 1 < len(self.stresses):\n"
+                                      "            self.state += 1\n            reached = False\n"
+                                      "            self.done = False\n            self.strain_rate = 0.0\n"
+                                      "            sc.set_velgrad(np.eye(3) * 0.0)\n            self.updates += 1\n"
+                                      "            return\n"),
+    "unbalanced_always_max": ("top = max(body) if use_max else sum(body) / len(body)", "top = max(body)"),
+    "unbalanced_counts_blocked": ("if sc.is_wall[i] or sc.blocked[i] == 63:", "if sc.is_wall[i]:"),
+    "stiffness_dt_without_sqrt2": ("best = min(best, math.sqrt(2.0) * math.sqrt(m[b] / K[b][i]))",
+                                   "best = min(best, math.sqrt(m[b] / K[b][i]))"),
+    "stiffness_without_tangential_term": ("K[body][i] += (kn - ks) * nv[i] * nv[i] + ks",
+                                          "K[body][i] += kn * nv[i] * nv[i]"),
+    "rotational_stiffness_without_lever": ("R[body][i] += ks * r * r * (1.0 - nv[i] * nv[i])",
+                                           "R[body][i] += ks * (1.0 - nv[i] * nv[i])"),
+}
+
+_CONTROL_DRIVER = """
+import json, sys
+sys.path.insert(0, {root!r})
+sys.path.insert(0, {tests!r})
+import oracle.controls as C
+before, after = json.loads(sys.argv[1])
+src = open(C.__file__).read()
+exec(compile(src.replace(before, after), C.__file__, "exec"), C.__dict__)
+import pytest
+sys.exit(pytest.main(["-q", "-p", "no:cacheprovider", {pins!r}]))
+"""
+
+
+@pytest.mark.parametrize("name", sorted(CONTROL_MUTATIONS))
+def test_control_pins_catch_mutation(name, tmp_path):
+    import json
+    before, after = CONTROL_MUTATIONS[name]
+    src = open(os.path.join(ROOT, "oracle", "controls.py")).read()
+    assert src.count(before) == 1, f"mutation anchor not found: {name}"
+    driver = tmp_path / "driver.py"
+    driver.write_text(_CONTROL_DRIVER.format(root=ROOT, tests=os.path.join(ROOT, "tests"),
+                                             pins=os.path.join(ROOT, "tests", "test_oracle_controls.py")))
+    r = subprocess.run([sys.executable, str(driver), json.dumps([before, after])], capture_output=True,
+                       text=True, cwd=str(tmp_path), timeout=600)
+    assert r.returncode == 1, f"no pin caught mutation {name} (exit {r.returncode}):\n{r.stdout[-2000:]}"
+    assert "FAILED" in r.stdout
