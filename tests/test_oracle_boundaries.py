@@ -75,11 +75,17 @@ def test_box_corner():
     _check(c, [1, 1, 1], R - d, E * R)
 
 
-def test_box_centre_inside():
-    """Centre inside the box, 0.3 r below the top face and deeper from every
-    other face: pushed out through the top, overlap r + 0.3 r."""
-    s, c = _one_contact(_box, [0.0, 0.0, BOX_H[2] - 0.3 * R])
-    _check(c, [0, 0, 1], 1.3 * R, E * R)
+@pytest.mark.parametrize("axis,side", [(k, sd) for k in range(3) for sd in (-1, 1)])
+def test_box_centre_inside(axis, side):
+    """Centre inside the box, 0.3 r from one face (each of the six in turn)
+    and deeper from every other one: pushed out through that face, along
+    its outward normal, overlap r + 0.3 r."""
+    centre = np.zeros(3)
+    centre[axis] = side * (BOX_H[axis] - 0.3 * R)
+    normal = np.zeros(3)
+    normal[axis] = side
+    s, c = _one_contact(_box, centre)
+    _check(c, normal, 1.3 * R, E * R)
 
 
 def test_box_no_contact_beyond_edge():

@@ -85,6 +85,13 @@ BOUNDARY_MUTATIONS = {
                                "if (!(dist < sp->r * 1.5)) return 0;\n            for (int k = 0; k < 3; ++k) n[k] = d[k] / dist;"),
     "facet_edge_clamp": ("if (t > 1.0) t = 1.0;", ""),
     "facet_one_sided": ("if (dot3(c, nn) < 0.0) inside = 0;", "if (dot3(c, nn) > 0.0) inside = 0;"),
+    "box_inside_low_face_pushed_inwards": ("                depth = dl;\n                ax = k;\n                sg = -1;",
+                                           "                depth = dl;\n                ax = k;\n                sg = 1;"),
+    "segment_lower_clamp_dropped": ("    if (t < 0.0) t = 0.0;\n", ""),
+    "triangle_inside_test_two_edges": ("    for (int i = 0; i < 3; ++i) {\n        const double* a = v[i];",
+                                       "    for (int i = 0; i < 2; ++i) {\n        const double* a = v[i];"),
+    "facet_face_normal_reversed": ("        cross3(e1, e2, n);\n        double len = sqrt(dot3(n, n));",
+                                   "        cross3(e2, e1, n);\n        double len = sqrt(dot3(n, n));"),
 }
 
 
