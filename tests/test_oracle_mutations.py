@@ -126,6 +126,11 @@ VISCEL_MUTATIONS = {
                                "if (fn_mag < 0.0) fn_mag = 0.0;\n        double fmax = fn_mag * tanphi;"),
     "viscel_restitution_product": ("double len = log(0.5 * (m1->en + m2->en));",
                                    "double len = log(m1->en * m2->en);"),
+    "viscel_contact_time_max": ("double tc = 0.5 * (m1->tc + m2->tc);",
+                                "double tc = (m1->tc > m2->tc ? m1->tc : m2->tc);"),
+    "viscel_shear_dashpot_while_sliding": ("        if (!slide)\n            for (int k = 0; k < 3; ++k) fsv[k] = -cs * vs[k];",
+                                           "        for (int k = 0; k < 3; ++k) fsv[k] = -cs * vs[k];"),
+    "viscel_shear_dashpot_work_dropped": ("(slide ? 0.0 : cs * dot3(vs, vs))", "0.0"),
 }
 
 

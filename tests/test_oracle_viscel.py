@@ -197,6 +197,66 @@ def test_energy_balance_with_dashpots():
     assert e["total"] == pytest.approx(e["kinetic"] + e["kin_rot"] + e["elastic"] + e["visc_dissip"], rel=1e-12)
 
 
+def test_two_contact_times_collide_over_their_mean():
+    """Equal spheres of two visco-elastic materials whose contact times are
+    t_c and 3 t_c: the pair takes the mean of the two (2 t_c), so the
+    collision lasts 2 t_c and still restitutes e_n."""
+    v, en = 0.05, 0.5
+    s = OracleScene(dt=TC / STEPS_PER_TC, gravity=(0.0, 0.0, 0.0), damping=0.0)
+    m1 = s.add_viscel_material(RHO, TC, en, 1.0, 0.3)
+    m2 = s.add_viscel_material(RHO, 3 * TC, en, 1.0, 0.3)
+    pos = np.array([[0.0, 0.0, 0.0], [2 * R + 1e-3 * R, 0.0, 0.0]])
+    s.add_spheres(pos, [R, R], vel=[[v, 0.0, 0.0], [-v, 0.0, 0.0]], mat=[m1, m2])
+    start, end = _run_collision(s, 6 * STEPS_PER_TC)
+    dt = TC / STEPS_PER_TC
+    assert (end - start) * dt == pytest.approx(2 * TC, abs=3 * dt)
+    vel = s.get_state()["vel"]
+    assert (vel[1, 0] - vel[0, 0]) / (2 * v) == pytest.approx(en, rel=3e-3)
+
+
+def test_prescribed_slip_with_the_shear_dashpot():
+    """A sphere at a fixed overlap d on a visco-elastic floor, driven along
+    it at v0 with its translations and its spins about x and y blocked (the
+    spin about z is left free, so that the sphere is not an immovable body,
+    and stays zero: the friction's torque is about y); the floor is fixed,
+    so the pair's mass is the sphere's.  No normal motion, so F_n = k_n d; while the
+    shear spring holds, the reported shear force is the spring's
+    k_s v0 t plus the dashpot's c_s v0 and the dashpot works c_s v0^2 per
+    unit time; once the spring passes tan(phi) F_n the contact slides at
+    exactly that force with the dashpot idle, and the plastic work is
+    c (v0 t - c/k_s) as for the linear law.  Guards the slider's series
+    arrangement (dashpot off while sliding) and the dashpot's work."""
+    en, et, phi = 0.6, 0.4, 0.35
+    dt = TC / STEPS_PER_TC
+    m = _mass(R)
+    kn = m * (math.pi ** 2 + math.log(en) ** 2) / TC ** 2
+    ks = 2.0 / 7.0 * m * (math.pi ** 2 + math.log(et) ** 2) / TC ** 2
+    cs = -2.0 / 7.0 * m * math.log(et) / TC
+    d = 1e-3 * R
+    cap = kn * d * math.tan(phi)
+    v0 = cap / (ks * 100.5 * dt)  # the spring passes the cap between steps 100 and 101
+    s = OracleScene(dt=dt, gravity=(0.0, 0.0, 0.0), damping=0.0)
+    mat = s.add_viscel_material(RHO, TC, en, et, phi)
+    s.add_wall(2, 0.0, 1, mat)
+    s.add_spheres([[0.0, 0.0, R - d]], [R], vel=[[v0, 0.0, 0.0]], default_mat=mat, blocked=[31])
+    for k in (40, 80):
+        s.step(40)
+        t = k * dt
+        c, e = s.get_contacts(), s.get_energy()
+        assert len(c) == 1 and c["fs"][0][0] < 0.0
+        assert np.linalg.norm(c["fs"][0]) == pytest.approx(ks * v0 * t + cs * v0, rel=1e-11)
+        assert np.linalg.norm(c["fn"][0]) == pytest.approx(kn * d, rel=1e-11)
+        assert e["visc_dissip"] == pytest.approx(cs * v0 * v0 * t, rel=1e-11)
+        assert e["plastic_dissip"] == 0.0
+    s.step(420)
+    t = 500 * dt
+    c, e = s.get_contacts(), s.get_energy()
+    assert np.linalg.norm(c["fs"][0]) == pytest.approx(cap, rel=1e-11)
+    assert e["visc_dissip"] == pytest.approx(cs * v0 * v0 * 100 * dt, rel=1e-11)
+    assert e["plastic_dissip"] == pytest.approx(cap * (v0 * t - cap / ks), rel=1e-9)
+    assert np.array_equal(s.get_state()["angvel"][1], [0.0, 0.0, 0.0])
+
+
 def test_contact_reports_the_dashpot_force():
     """Mid-collision the reported normal force is k_n pen - c_n (v2 - v1).n
     along n: at the first contact step of a head-on approach it exceeds the
