@@ -194,9 +194,13 @@ def test_closed_forms_through_the_gpu_path():
                                                      rel=1e-6)
 
 
-def test_periodic_shear_parity():
+@pytest.mark.parametrize("tilt", [0, 1])
+def test_periodic_shear_parity(tilt):
     """Periodic cube in simple shear (homoDeform 2): pairs across the
-    sheared boundaries, image velocities, cell update."""
+    sheared boundaries, image velocities, cell update; also with the same
+    lattice of images spanned by a tilted basis (x gains the z edge), where
+    the binning's cell widths are the distances between the cell's faces
+    and the image labels differ from the cube's."""
     from paper_2301_00611_amd.scenes import Material, Scene, compressed_cloud, random_velocities
     box = 0.016
     pos, rad = compressed_cloud(300, box, 0.6e-3, 1.0e-3, 0.92, 21)
@@ -204,7 +208,8 @@ def test_periodic_shear_parity():
                  damping=0.1, dt_factor=0.5)
     L = np.array([[0.0, 0.0, 5.0], [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
     v, w = random_velocities(300, 0.02, 3)
-    g, o, dt = twin(spec, periodic=True, hsize=np.eye(3) * box, velgrad=L, vel=v, angvel=w * 0.05)
+    hsize = box * np.array([[1.0, 0.0, float(tilt)], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+    g, o, dt = twin(spec, periodic=True, hsize=hsize, velgrad=L, vel=v, angvel=w * 0.05)
     crossing = 0
     for k in range(10):
         g.step(40)

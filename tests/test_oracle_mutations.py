@@ -37,6 +37,8 @@ MUTATIONS = {
     "wall_reference_radius": ("n[w->axis] = (double)wall_sign(w, sp);\n        *R1 = sp->r;",
                               "n[w->axis] = (double)wall_sign(w, sp);\n        *R1 = 0.5 * sp->r;"),
     "plastic_work_without_fmax": ("*e_plast += (fs_norm - fmax) * fmax / ks;", "*e_plast += (fs_norm - fmax) / ks;"),
+    "nearest_image_only": ("    for (int a = -1; a <= 1; ++a)\n        for (int b = -1; b <= 1; ++b)\n            for (int g = -1; g <= 1; ++g) {",
+                           "    for (int a = 0; a <= 0; ++a)\n        for (int b = 0; b <= 0; ++b)\n            for (int g = 0; g <= 0; ++g) {"),
     "spin_radii_swapped": ("rw[k] = R2 * w2[k] + R1 * w1[k];", "rw[k] = R1 * w2[k] + R2 * w1[k];"),
     "cell_update_on_the_right": ("matmul(M, s->H, s->H);", "matmul(s->H, M, s->H);"),
     "normal_stiffness_arithmetic_mean": ("*kn = k1 * k2 / (k1 + k2);", "*kn = 0.25 * (k1 + k2);"),

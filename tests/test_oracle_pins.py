@@ -736,6 +736,70 @@ def test_periodic_pair_detection_through_images():
     assert tuple(cell[0]) == (-3, 0, 0)
 
 
+def test_periodic_image_in_a_strongly_sheared_cell():
+    """A cell tilted by 2.3 cell widths (x per unit z): rounding the
+    fractional separation to the nearest integers names an image one cell
+    away from the one that touches.  Brute force over 9^3 images (here)
+    finds the single touching image; the oracle must report exactly it
+    (guards a nearest-image shortcut in place of a search around it)."""
+    a, r = 5e-3, 0.6e-3
+    H = np.array([[a, 0.0, 2.3 * a], [0.0, a, 0.0], [0.0, 0.0, a]])
+    x1 = np.array([1.1e-3, 2.0e-3, 1.3e-3])
+    c_true = np.array([1, 0, -1])
+    d = np.array([-0.5e-3, 0.0, 1.0e-3])   # the touching separation, |d| < 2r
+    x2 = x1 + d - H @ c_true                # so that x2 + H c_true - x1 = d
+    touching = [c for c in np.ndindex(9, 9, 9)
+                if np.linalg.norm(x2 + H @ (np.array(c) - 4) - x1) < 2 * r]
+    assert len(touching) == 1 and tuple(np.array(touching[0]) - 4) == tuple(c_true)
+    c_round = -np.floor(np.linalg.solve(H, x2 - x1) + 0.5).astype(int)
+    assert tuple(c_round) != tuple(c_true)  # the case a rounding shortcut gets wrong
+    s = OracleScene(dt=1e-7, periodic=True, hsize=H, homo_deform=2)
+    s.add_material(2600.0, 1e7, 0.3, 0.5)
+    s.add_spheres([x1, x2], [r, r])
+    id1, id2, cell = s.detect_pairs()
+    assert len(id1) == 1 and tuple(cell[0]) == tuple(c_true)
+
+
+def test_periodic_cell_basis_is_irrelevant():
+    """The same periodic lattice of images spanned by a cube's edges and by a
+    tilted basis H U (U integer, det 1: x gains twice the z edge): the same
+    sphere pairs touch, each through the image H c = (H U)(U^-1 c), and
+    after sixty steps of shear every force and position agrees to rounding
+    (guards the image search and shifts in a tilted basis, where the
+    nearest image of the fractional coordinates is often not the one that
+    touches)."""
+    from paper_2301_00611_amd.scenes import compressed_cloud, random_velocities
+    # a cloud squeezed into 15.4 mm, in a 15.3 mm periodic cell: ~420
+    # contacts at first, ~60 of them through the cell's faces; the squeezed
+    # cloud springs apart, to ~200 contacts after the sixty steps
+    pos, rad = compressed_cloud(600, 0.016, 0.6e-3, 1.0e-3, 0.92, 21)
+    box = 0.0153
+    v, w = random_velocities(600, 0.02, 3)
+    L = np.array([[0.0, 0.0, 5.0], [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    U = np.array([[1, 0, 2], [0, 1, 0], [0, 0, 1]])
+    runs = []
+    for basis in (np.eye(3, dtype=int), U):
+        s = OracleScene(dt=2e-6, periodic=True, hsize=box * basis.astype(float), velgrad=L, homo_deform=2,
+                        damping=0.1)
+        s.add_material(2600.0, 1e7, 0.3, 0.4)
+        s.add_spheres(pos, rad, vel=v, angvel=w * 0.05)
+        s.step(60)
+        runs.append((s.get_contacts(), s.get_state()))
+    (c0, s0), (c1, s1) = runs
+    assert len(c0) > 150 and int((np.abs(c0["cell"]).sum(axis=1) > 0).sum()) > 10
+    k0 = sorted(zip(c0["id1"].tolist(), c0["id2"].tolist(), map(tuple, c0["cell"].tolist())))
+    Uinv = np.round(np.linalg.inv(U)).astype(int)
+    k1 = sorted(zip(c1["id1"].tolist(), c1["id2"].tolist(), (tuple(U @ np.array(c)) for c in c1["cell"].tolist())))
+    assert k0 == k1 and np.array_equal(Uinv @ U, np.eye(3, dtype=int))
+    assert any(tuple(c) != tuple(U @ np.array(c)) for c in c1["cell"].tolist())  # labels do differ
+    o0 = np.lexsort((c0["id2"], c0["id1"]))
+    o1 = np.lexsort((c1["id2"], c1["id1"]))
+    f0 = c0["fn"][o0] + c0["fs"][o0]
+    f1 = c1["fn"][o1] + c1["fs"][o1]
+    assert np.abs(f1 - f0).max() <= 1e-9 * np.abs(f0).max()
+    assert np.abs(s1["pos"] - s0["pos"]).max() <= 1e-13
+
+
 def _sheared_lattice(delta=2e-6, fs=1e-3, gap=0.2e-3, r=1e-3, n=5):
     """The oracle on tests/lattice.py's sheared lattice (touching along x
     only, preset shear force along y)."""
