@@ -194,13 +194,14 @@ def test_closed_forms_through_the_gpu_path():
                                                      rel=1e-6)
 
 
-@pytest.mark.parametrize("tilt", [0, 1])
-def test_periodic_shear_parity(tilt):
+@pytest.mark.parametrize("basis", ["cube", "tilted", "left-handed"])
+def test_periodic_shear_parity(basis):
     """Periodic cube in simple shear (homoDeform 2): pairs across the
     sheared boundaries, image velocities, cell update; also with the same
     lattice of images spanned by a tilted basis (x gains the z edge), where
     the binning's cell widths are the distances between the cell's faces
-    and the image labels differ from the cube's."""
+    and the image labels differ from the cube's, and by a left-handed one
+    (x and y edges swapped: the volume is |det H|)."""
     from paper_2301_00611_amd.scenes import Material, Scene, compressed_cloud, random_velocities
     box = 0.016
     pos, rad = compressed_cloud(300, box, 0.6e-3, 1.0e-3, 0.92, 21)
@@ -208,7 +209,9 @@ def test_periodic_shear_parity(tilt):
                  damping=0.1, dt_factor=0.5)
     L = np.array([[0.0, 0.0, 5.0], [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
     v, w = random_velocities(300, 0.02, 3)
-    hsize = box * np.array([[1.0, 0.0, float(tilt)], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+    hsize = box * {"cube": np.eye(3),
+                   "tilted": np.array([[1.0, 0.0, 1.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]]),
+                   "left-handed": np.array([[0.0, 1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])}[basis]
     g, o, dt = twin(spec, periodic=True, hsize=hsize, velgrad=L, vel=v, angvel=w * 0.05)
     crossing = 0
     for k in range(10):

@@ -54,6 +54,11 @@ MUTATIONS = {
                                  "rw[k] = (R2 - 0.5 * pen) * w2[k] + (R1 - 0.5 * pen) * w1[k];"),
     "stress_transposed": ("acc[3 * i + j] += ct->f2[i] * (-ct->det_d[j]);",
                           "acc[3 * i + j] += ct->f2[j] * (-ct->det_d[i]);"),
+    "stress_volume_signed": ("        V = fabs(H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +",
+                             "        V = (H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +"),
+    "stress_volume_from_the_diagonal": ("        V = fabs(H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +\n"
+                                        "                 H[2] * (H[3] * H[7] - H[4] * H[6]));",
+                                        "        V = H[0] * H[4] * H[8];"),
     "stress_branch_sign": ("acc[3 * i + j] += ct->f2[i] * (-ct->det_d[j]);",
                            "acc[3 * i + j] += ct->f2[i] * (ct->det_d[j]);"),
     "gravity_work_sign": ("en->grav += -b->m * s->p.gravity[k] * v0[k] * dt;",
