@@ -36,6 +36,13 @@ def _one_step_parity(n, seed, precision=0, tol=1e-12):
     nw = len(spec.walls)
     v, w = random_velocities(n, 0.05, seed + 100)
     g, o, dt = twin(spec, precision=precision, vel=v, angvel=w * 0.05)
+    # random orientations, so that the order in which a step's rotation is
+    # composed with the orientation shows (from the identity it cannot)
+    q = np.random.default_rng(seed + 11).normal(size=(g.num_bodies, 4))
+    q /= np.linalg.norm(q, axis=1)[:, None]
+    q[:nw] = (1.0, 0.0, 0.0, 0.0)
+    g.set_state(ori=q)
+    o.set_state(ori=q)
     rng = np.random.default_rng(seed + 7)
     hist = random_history(spec.pos, spec.radius, spec.walls, rng)
     if hist is not None:

@@ -49,6 +49,9 @@ MUTATIONS = {
                              "*e_el += 0.5 * (fn_mag * fn_mag / kn) + 0.5 * (dot3(fs, fs) / kn);"),
     "shear_energy_factor": ("*e_el += 0.5 * (fn_mag * fn_mag / kn) + 0.5 * (dot3(fs, fs) / ks);",
                             "*e_el += 0.5 * (fn_mag * fn_mag / kn) + 1.0 * (dot3(fs, fs) / ks);"),
+    "rotation_composed_on_the_right": ("        qmul(dq, b->q, q);", "        qmul(b->q, dq, q);"),
+    "pwave_step_of_the_first_material": ("        const mat_t* m = &s->mats[b->mat];\n        double dt = b->r / sqrt(m->young / m->density);",
+                                         "        const mat_t* m = &s->mats[0];\n        double dt = b->r / sqrt(m->young / m->density);"),
     "rotation_angle_doubled": ("double half = 0.5 * wn * dt;", "double half = wn * dt;"),
     "overlap_dependent_branch": ("rw[k] = R2 * w2[k] + R1 * w1[k];",
                                  "rw[k] = (R2 - 0.5 * pen) * w2[k] + (R1 - 0.5 * pen) * w1[k];"),

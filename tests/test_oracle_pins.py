@@ -110,6 +110,46 @@ def test_free_spin_quaternion():
     np.testing.assert_allclose(q, expected, atol=1e-12)
 
 
+def _rotation_matrix(q):
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def test_spin_turns_the_orientation_about_the_global_axis():
+    """A sphere already turned by 90 degrees about x, spinning about the
+    global z axis: after time t its orientation is R_z(w t) R_x(90 deg) (the
+    angular velocity is a global vector, so each step's rotation acts on
+    the left of the orientation); acting on the right would turn it about
+    its own z axis, which is the global -y."""
+    dt, n, W = 1e-3, 700, 2.0
+    s = OracleScene(dt=dt)
+    s.add_material(2600.0, 1e7, 0.3, 0.5)
+    s.add_spheres([[0, 0, 0]], [1e-3], angvel=[[0.0, 0.0, W]])
+    h = math.pi / 4
+    s.set_state(ori=[[math.cos(h), math.sin(h), 0.0, 0.0]])
+    s.step(n)
+    q = s.get_state()["ori"][0]
+    th = W * n * dt
+    Rz = np.array([[math.cos(th), -math.sin(th), 0.0], [math.sin(th), math.cos(th), 0.0], [0.0, 0.0, 1.0]])
+    Rx = np.array([[1.0, 0.0, 0.0], [0.0, 0.0, -1.0], [0.0, 1.0, 0.0]])
+    np.testing.assert_allclose(_rotation_matrix(q), Rz @ Rx, atol=1e-12)
+    assert np.abs(Rz @ Rx - Rx @ Rz).max() > 0.1  # the two orders differ
+
+
+def test_pwave_timestep_takes_each_spheres_material():
+    """Two spheres of different materials: the P-wave step is the smallest
+    r sqrt(rho / E) over the spheres, each with its own material (here the
+    larger but much stiffer sphere sets it)."""
+    s = OracleScene(dt=1e-6)
+    ma = s.add_material(2600.0, 1e7, 0.3, 0.5)
+    mb = s.add_material(1000.0, 1e9, 0.3, 0.5)
+    s.add_spheres([[0, 0, 0], [0.1, 0, 0]], [1e-3, 2e-3], mat=[ma, mb])
+    assert s.pwave_dt() == pytest.approx(2e-3 * math.sqrt(1000.0 / 1e9), rel=1e-15)
+    assert 2e-3 * math.sqrt(1000.0 / 1e9) < 1e-3 * math.sqrt(2600.0 / 1e7)
+
+
 # ------------------------------------------------------------ contacts
 
 def _pair_scene(dt, r=1e-3, rho=2600.0, E=1e7, nu=0.3, phi=0.5, gap=0.0, vrel=0.1, damping=0.0):
