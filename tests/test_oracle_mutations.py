@@ -49,6 +49,10 @@ MUTATIONS = {
                              "*e_el += 0.5 * (fn_mag * fn_mag / kn) + 0.5 * (dot3(fs, fs) / kn);"),
     "shear_energy_factor": ("*e_el += 0.5 * (fn_mag * fn_mag / kn) + 0.5 * (dot3(fs, fs) / ks);",
                             "*e_el += 0.5 * (fn_mag * fn_mag / kn) + 1.0 * (dot3(fs, fs) / ks);"),
+    "contact_point_on_the_first_surface": ("for (int k = 0; k < 3; ++k) pt[k] = b1->x[k] + (R1 - 0.5 * pen) * n[k];",
+                                           "for (int k = 0; k < 3; ++k) pt[k] = b1->x[k] + R1 * n[k];"),
+    "wall_contact_point_on_the_sphere": ("for (int k = 0; k < 3; ++k) pt[k] = b2->x[k] - (b2->r - 0.5 * pen) * n[k];",
+                                         "for (int k = 0; k < 3; ++k) pt[k] = b2->x[k] - b2->r * n[k];"),
     "rotation_composed_on_the_right": ("        qmul(dq, b->q, q);", "        qmul(b->q, dq, q);"),
     "pwave_step_of_the_first_material": ("        const mat_t* m = &s->mats[b->mat];\n        double dt = b->r / sqrt(m->young / m->density);",
                                          "        const mat_t* m = &s->mats[0];\n        double dt = b->r / sqrt(m->young / m->density);"),

@@ -333,6 +333,33 @@ def test_torque_damping_while_slipping():
         assert s.get_energy()["damp_dissip"] == pytest.approx(damp, rel=1e-9)
 
 
+def test_contact_point_in_the_middle_of_the_overlap():
+    """Section 2.1.3 (eq. 2.8): the contact point lies in the middle of the
+    overlap zone, halfway between the two surfaces' innermost points along
+    the normal; for unequal spheres that is not the centres' midpoint, and
+    against a wall it is halfway between the plane and the sphere's
+    innermost point."""
+    r1, r2, d = 1e-3, 2e-3, 2e-4
+    n = np.array([0.3, -0.5, 0.8])
+    n /= np.linalg.norm(n)
+    x1 = np.array([0.01, 0.02, 0.01])
+    x2 = x1 + (r1 + r2 - d) * n
+    s = OracleScene(dt=1e-7)
+    m = s.add_material(2600.0, 1e7, 0.3, 0.5)
+    s.add_wall(2, 0.0, 1, m)
+    x3 = np.array([0.05, 0.05, r1 - 3e-5])  # on the floor, overlap 3e-5
+    s.add_spheres([x1, x2, x3], [r1, r2, r1], blocked=[63, 63, 63])
+    s.step(1)
+    c = s.get_contacts()
+    assert len(c) == 2
+    pair = c[c["is_wall"] == 0][0]
+    wall = c[c["is_wall"] == 1][0]
+    expected = 0.5 * ((x1 + r1 * n) + (x2 - r2 * n))
+    np.testing.assert_allclose(pair["point"], expected, rtol=0, atol=1e-17)
+    assert np.linalg.norm(expected - 0.5 * (x1 + x2)) > 1e-4
+    np.testing.assert_allclose(wall["point"], [0.05, 0.05, 0.5 * (0.0 + (x3[2] - r1))], rtol=0, atol=1e-17)
+
+
 def test_ratchet_cycle_closes():
     """Ig2_Sphere_Sphere_ScGeom.avoidGranularRatcheting: body 1 fixed, body
     2 pushed along the normal, rotated by a, pulled back, rotated by -a.
