@@ -49,6 +49,14 @@ MUTATIONS = {
                              "*e_el += 0.5 * (fn_mag * fn_mag / kn) + 0.5 * (dot3(fs, fs) / kn);"),
     "shear_energy_factor": ("*e_el += 0.5 * (fn_mag * fn_mag / kn) + 0.5 * (dot3(fs, fs) / ks);",
                             "*e_el += 0.5 * (fn_mag * fn_mag / kn) + 1.0 * (dot3(fs, fs) / ks);"),
+    "wall_position_sign": ("    double delta = sp->x[w->axis] - w->wpos;\n    if (!(fabs(delta) < sp->r)) return 0;",
+                           "    double delta = sp->x[w->axis] + w->wpos;\n    if (!(fabs(delta) < sp->r)) return 0;"),
+    "damping_estimate_a_whole_step": ("(v0[k] + a * dt / 2.0)", "(v0[k] + a * dt / 1.0)"),
+    "rotdamp_estimate_a_whole_step": ("(b->w[k] + a * dt / 2.0)", "(b->w[k] + a * dt / 1.0)"),
+    "twist_spin_component_subtracted": ("double wsum[3] = {w1[0] + w2[0], w1[1] + w2[1], w1[2] + w2[2]};",
+                                        "double wsum[3] = {w1[0] + w2[0], w1[1] - w2[1], w1[2] + w2[2]};"),
+    "cell_volume_cofactor_sign": ("V = fabs(H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1]",
+                                  "V = fabs(H[0] * (H[4] * H[8] + H[5] * H[7]) - H[1]"),
     "contact_point_on_the_first_surface": ("for (int k = 0; k < 3; ++k) pt[k] = b1->x[k] + (R1 - 0.5 * pen) * n[k];",
                                            "for (int k = 0; k < 3; ++k) pt[k] = b1->x[k] + R1 * n[k];"),
     "wall_contact_point_on_the_sphere": ("for (int k = 0; k < 3; ++k) pt[k] = b2->x[k] - (b2->r - 0.5 * pen) * n[k];",
@@ -99,6 +107,12 @@ BOUNDARY_MUTATIONS = {
                                "if (!(dist < sp->r * 1.5)) return 0;\n            for (int k = 0; k < 3; ++k) n[k] = d[k] / dist;"),
     "facet_edge_clamp": ("if (t > 1.0) t = 1.0;", ""),
     "facet_one_sided": ("if (dot3(c, nn) < 0.0) inside = 0;", "if (dot3(c, nn) > 0.0) inside = 0;"),
+    "triangle_edges_from_the_origin": ("        e1[k] = v[1][k] - v[0][k];\n        e2[k] = v[2][k] - v[0][k];",
+                                       "        e1[k] = v[1][k] + v[0][k];\n        e2[k] = v[2][k] + v[0][k];"),
+    "triangle_plane_height_sign": ("double h = (x[0] - v[0][0]) * nn[0] + (x[1] - v[0][1]) * nn[1]",
+                                   "double h = (x[0] - v[0][0]) * nn[0] - (x[1] - v[0][1]) * nn[1]"),
+    "facet_closest_point_vector": ("    closest_on_triangle(w->fv, sp->x, p);\n    double d[3] = {sp->x[0] - p[0], sp->x[1] - p[1], sp->x[2] - p[2]};",
+                                   "    closest_on_triangle(w->fv, sp->x, p);\n    double d[3] = {sp->x[0] - p[0], sp->x[1] - p[1], sp->x[2] + p[2]};"),
     "box_inside_low_face_pushed_inwards": ("                depth = dl;\n                ax = k;\n                sg = -1;",
                                            "                depth = dl;\n                ax = k;\n                sg = 1;"),
     "segment_lower_clamp_dropped": ("    if (t < 0.0) t = 0.0;\n", ""),

@@ -199,7 +199,7 @@ def test_head_on_collision_closed_form():
 
 
 def _floor_scene(dt, pen0, gravity, phi=0.5, damping=0.0, blocked=None, vel=None, angvel=None,
-                 wall_phi=None, r=1e-3, E=1e7, nu=0.3, wall_E=None, wall_nu=None):
+                 wall_phi=None, r=1e-3, E=1e7, nu=0.3, wall_E=None, wall_nu=None, floor=0.0):
     s = OracleScene(dt=dt, gravity=gravity, damping=damping)
     sm = s.add_material(2600.0, E, nu, phi)
     if wall_phi is None and wall_E is None and wall_nu is None:
@@ -207,20 +207,23 @@ def _floor_scene(dt, pen0, gravity, phi=0.5, damping=0.0, blocked=None, vel=None
     else:
         wm = s.add_material(2600.0, E if wall_E is None else wall_E, nu if wall_nu is None else wall_nu,
                             phi if wall_phi is None else wall_phi)
-    s.add_wall(2, 0.0, 1, wm)
-    s.add_spheres([[0, 0, r - pen0]], [r], vel=vel, angvel=angvel, default_mat=sm,
+    s.add_wall(2, floor, 1, wm)
+    s.add_spheres([[0, 0, floor + r - pen0]], [r], vel=vel, angvel=angvel, default_mat=sm,
                   blocked=None if blocked is None else [blocked])
     return s
 
 
-def test_static_overlap_on_floor():
+@pytest.mark.parametrize("floor", [0.0, 0.37])
+def test_static_overlap_on_floor(floor):
     """A damped sphere settles on a wall at pen = m g / kn with kn = E r
-    (Ig2_Wall_Sphere_ScGeom: the wall's reference radius is the sphere's)."""
+    (Ig2_Wall_Sphere_ScGeom: the wall's reference radius is the sphere's),
+    its centre at floor + r - pen, also with the wall away from the origin."""
     r, E = 1e-3, 1e7
     m = 4.0 / 3.0 * math.pi * r ** 3 * 2600.0
     dt = 0.5 * r * math.sqrt(2600.0 / E)
-    s = _floor_scene(dt, 0.0, (0, 0, -9.81), damping=0.2)
+    s = _floor_scene(dt, 0.0, (0, 0, -9.81), damping=0.2, floor=floor)
     s.step(20000)
+    assert s.get_state()["pos"][1, 2] == pytest.approx(floor + r - m * 9.81 / (E * r), rel=0, abs=1e-11)
     c = s.get_contacts()
     assert len(c) == 1 and c["is_wall"][0] == 1 and c["id1"][0] == 0
     assert c["kn"][0] == pytest.approx(E * r, rel=1e-15)
@@ -333,6 +336,48 @@ def test_torque_damping_while_slipping():
         assert s.get_energy()["damp_dissip"] == pytest.approx(damp, rel=1e-9)
 
 
+@pytest.mark.parametrize("c,factor", [(0.25, -1), (0.75, 1), (1.25, 1)])
+def test_damping_sign_from_the_on_step_velocity(c, factor):
+    """Eq. 2.9 takes the damping's sign from the on-step estimate
+    v + a dt/2.  A free sphere launched upward at v0 = c |g| dt: the
+    estimate is (c - 1/2) |g| dt, so for c = 1/4 it points along gravity
+    (the force is reduced to (1 - lambda) m g) and for c = 3/4 and 5/4 it
+    opposes it (increased to (1 + lambda) m g); one step gives
+    v1 = v0 - (1 -+ lambda) |g| dt.  Guards where the sign changes: at
+    a dt/2, not at 0 (no half step) nor at a dt (a whole step)."""
+    g, lam, dt = 9.81, 0.3, 1e-4
+    v0 = c * g * dt
+    s = OracleScene(dt=dt, gravity=(0.0, 0.0, -g), damping=lam)
+    s.add_material(2600.0, 1e7, 0.3, 0.5)
+    s.add_spheres([[0.0, 0.0, 0.0]], [1e-3], vel=[[0.0, 0.0, v0]])
+    s.step(1)
+    assert s.get_state()["vel"][0, 2] == pytest.approx(v0 - (1 + factor * lam) * g * dt, rel=1e-12)
+
+
+@pytest.mark.parametrize("c,factor", [(0.25, -1), (0.75, 1), (1.25, 1)])
+def test_torque_damping_sign_from_the_on_step_spin(c, factor):
+    """The torque's twin: the slipping sphere of the pin above, launched
+    with a counter-spin w0 = -c alpha dt (alpha = r F / I): the estimate
+    w0 + alpha dt/2 agrees with the friction torque for c = 1/4 (reduced to
+    (1 - lambda) r F) and opposes it for c = 3/4 and 5/4 (increased), so
+    w1 = w0 + (1 -+ lambda) alpha dt; the contact still slips (its point
+    moves faster than without spin)."""
+    r, E, g, v0, lam, phi = 1e-3, 1e7, 9.81, 0.1, 0.2, 0.5
+    m = 4.0 / 3.0 * math.pi * r ** 3 * 2600.0
+    inertia = 0.4 * m * r * r
+    kn = E * r
+    pen0 = m * g / kn
+    F = math.tan(phi) * kn * pen0
+    dt = 0.5 * r * math.sqrt(2600.0 / E)
+    alpha = r * F / inertia
+    w0 = -c * alpha * dt
+    s = _floor_scene(dt, pen0, (0, 0, -g), phi=phi, damping=lam, vel=[[v0, 0, 0]], angvel=[[0.0, w0, 0.0]])
+    s.step(1)
+    st = s.get_state()
+    assert st["angvel"][1, 1] == pytest.approx(w0 + (1 + factor * lam) * alpha * dt, rel=1e-10)
+    assert st["vel"][1, 0] == pytest.approx(v0 - (1 + lam) * F * dt / m, rel=1e-10)
+
+
 def test_contact_point_in_the_middle_of_the_overlap():
     """Section 2.1.3 (eq. 2.8): the contact point lies in the middle of the
     overlap zone, halfway between the two surfaces' innermost points along
@@ -423,17 +468,26 @@ def test_spin_drags_the_contact_by_its_own_radius(spinning):
 
 def _rigid_rotation(axis_kind):
     """Two overlapping spheres carrying a shear force, rotated as one rigid
-    body at rate W.  Returns (Fs after K steps, Fs0 rotated by W t, normal)."""
+    body at rate W, about an axis normal to the pair ('perp') or along it
+    ('twist'); '-skew' puts the pair along (1, 2, 2)/3 instead of x, so
+    that every component of the spins enters.  Returns (Fs after K steps,
+    Fs0 rotated by W t, normal, Fs0)."""
     r, dt, K, W = 1e-3, 1e-6, 2000, 400.0
     s = OracleScene(dt=dt)
     s.add_material(2600.0, 1e7, 0.3, 1.5)
     pen = 2e-5
-    x = np.array([[0.0, 0, 0], [2 * r - pen, 0, 0]])
+    if axis_kind.endswith("-skew"):
+        n0 = np.array([1.0, 2.0, 2.0]) / 3.0
+        t1 = np.cross(n0, [0.0, 0.0, 1.0])
+        t1 /= np.linalg.norm(t1)
+        t2 = np.cross(n0, t1)
+    else:
+        n0, t1, t2 = np.array([1.0, 0, 0]), np.array([0.0, 1, 0]), np.array([0.0, 0, 1])
+    x = np.array([[0.0, 0, 0], (2 * r - pen) * n0])
     s.add_spheres(x, [r, r], blocked=[63, 63])
-    n0 = np.array([1.0, 0, 0])
-    fs0 = np.array([0.0, 0.3, -0.4]) * 1e-3
+    fs0 = (0.3 * t1 - 0.4 * t2) * 1e-3
     s.set_contacts([0], [1], fs=[fs0], nprev=[n0])
-    Wv = np.array([0.0, 0.0, W]) if axis_kind == "perp" else np.array([W, 0.0, 0.0])
+    Wv = W * (t2 if axis_kind.startswith("perp") else n0)
     centre = x.mean(axis=0)
     for _ in range(K):
         p = s.get_state()["pos"]
@@ -448,12 +502,12 @@ def _rigid_rotation(axis_kind):
     return c["fs"][0], rot @ fs0, c["normal"][0], fs0
 
 
-@pytest.mark.parametrize("axis_kind", ["perp", "twist"])
+@pytest.mark.parametrize("axis_kind", ["perp", "twist", "perp-skew", "twist-skew"])
 def test_shear_objectivity_under_rigid_rotation(axis_kind):
     """Section 2.1.3: the shear vector must follow a rigid motion of the
     pair.  'perp' (rotation about an axis normal to n) exercises the
     n_prev x n term and the (r1+r2)/l factor; 'twist' (rotation about n)
-    exercises the dt/2 n.(w1+w2) term."""
+    exercises the dt/2 n.(w1+w2) term; the skew pair, every component."""
     fs, fs_expected, n, fs0 = _rigid_rotation(axis_kind)
     assert np.linalg.norm(fs - fs_expected) <= 2e-3 * np.linalg.norm(fs0)
     assert abs(np.dot(fs, n)) <= 2e-3 * np.linalg.norm(fs0)
@@ -830,7 +884,8 @@ def test_periodic_image_in_a_strongly_sheared_cell():
 def test_periodic_cell_basis_is_irrelevant():
     """The same periodic lattice of images spanned by a cube's edges and by
     other bases H U (U integer, det +-1): x gaining twice the z edge, a
-    basis that is not triangular, and two edges swapped (left-handed).  The
+    basis that is not triangular, one with every entry non-zero, and two
+    edges swapped (left-handed).  The
     same sphere pairs touch, each through the image H c = (H U)(U^-1 c),
     and after forty steps of shear every force, position and the stress
     over the cell's volume agree to rounding (guards the image search and
@@ -848,6 +903,7 @@ def test_periodic_cell_basis_is_irrelevant():
     bases = {"cube": np.eye(3, dtype=int),
              "tilted": np.array([[1, 0, 2], [0, 1, 0], [0, 0, 1]]),
              "skew": np.array([[1, 1, 0], [1, 2, 0], [0, 0, 1]]),
+             "skew in 3-d": np.array([[1, 1, 1], [1, 2, 2], [1, 2, 3]]),
              "left-handed": np.array([[0, 1, 0], [1, 0, 0], [0, 0, 1]])}
     runs = {}
     for name, U in bases.items():
@@ -863,7 +919,7 @@ def test_periodic_cell_basis_is_irrelevant():
     k0 = sorted(zip(c0["id1"].tolist(), c0["id2"].tolist(), map(tuple, c0["cell"].tolist())))
     o0 = np.lexsort((c0["id2"], c0["id1"]))
     f0 = c0["fn"][o0] + c0["fs"][o0]
-    for name in ("tilted", "skew", "left-handed"):
+    for name in ("tilted", "skew", "skew in 3-d", "left-handed"):
         U = bases[name]
         c1, s1, sig1 = runs[name]
         k1 = sorted(zip(c1["id1"].tolist(), c1["id2"].tolist(),
