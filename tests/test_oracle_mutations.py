@@ -55,6 +55,8 @@ MUTATIONS = {
     "rotdamp_estimate_a_whole_step": ("(b->w[k] + a * dt / 2.0)", "(b->w[k] + a * dt / 1.0)"),
     "twist_spin_component_subtracted": ("double wsum[3] = {w1[0] + w2[0], w1[1] + w2[1], w1[2] + w2[2]};",
                                         "double wsum[3] = {w1[0] + w2[0], w1[1] - w2[1], w1[2] + w2[2]};"),
+    "cell_volume_third_cofactor_multiplier": ("                 H[2] * (H[3] * H[7] - H[4] * H[6]));",
+                                              "                 H[0] * (H[3] * H[7] - H[4] * H[6]));"),
     "cell_volume_cofactor_sign": ("V = fabs(H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1]",
                                   "V = fabs(H[0] * (H[4] * H[8] + H[5] * H[7]) - H[1]"),
     "contact_point_on_the_first_surface": ("for (int k = 0; k < 3; ++k) pt[k] = b1->x[k] + (R1 - 0.5 * pen) * n[k];",

@@ -903,7 +903,7 @@ def test_periodic_cell_basis_is_irrelevant():
     bases = {"cube": np.eye(3, dtype=int),
              "tilted": np.array([[1, 0, 2], [0, 1, 0], [0, 0, 1]]),
              "skew": np.array([[1, 1, 0], [1, 2, 0], [0, 0, 1]]),
-             "skew in 3-d": np.array([[1, 1, 1], [1, 2, 2], [1, 2, 3]]),
+             "skew in 3-d": np.array([[2, 3, 1], [1, 2, 1], [1, 1, 1]]),
              "left-handed": np.array([[0, 1, 0], [1, 0, 0], [0, 0, 1]])}
     runs = {}
     for name, U in bases.items():
