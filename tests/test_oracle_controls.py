@@ -246,6 +246,20 @@ def test_strain_axis_ends_at_the_log_strain():
     np.testing.assert_allclose(np.diag(s.get_cell()[0]), np.diag(H0) * np.exp(goal), rtol=1e-9)
 
 
+def test_strain_axes_reached_within_their_tolerance():
+    """Strain axes only, on the resting lattice (in equilibrium): goals equal
+    to the current strain (0) are reached at the first update; a goal 1 %
+    below it is not (|goal - strain| is compared with the tolerance, in
+    either direction)."""
+    s, a, delta = _lattice()
+    c = PeriTriax(s, goal=(0.0, 0.0, 0.0), stress_mask=0, glob_update=5)
+    assert c.run(50, stop_when_done=True) == 5 and c.done
+    s, a, delta = _lattice()
+    c = PeriTriax(s, goal=(-0.01, 0.0, 0.0), stress_mask=0, glob_update=5, max_strain_rate=(1e-6,) * 3)
+    c.run(5)
+    assert c.updates == 1 and not c.done
+
+
 def test_controller_unbalanced_force_gates_the_goal():
     """At the stress goal from the start but with a jittered lattice
     (unbalanced force of order one): not done while max_unbalanced is below

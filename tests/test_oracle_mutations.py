@@ -195,6 +195,8 @@ CONTROL_MUTATIONS = {
                                         "            reached = False\n", ""),
     "control_tolerance_min": ("if abs(err) > max(self.abs_tol, self.rel_tol * abs(self.goal[i])):",
                               "if abs(err) > min(self.abs_tol, self.rel_tol * abs(self.goal[i])):"),
+    "control_strain_tolerance_inverted": ("                if abs(err) > STRAIN_TOL:", "                if abs(err) < STRAIN_TOL:"),
+    "control_strain_tolerance_without_abs": ("                if abs(err) > STRAIN_TOL:", "                if (err) > STRAIN_TOL:"),
     "control_rate_not_capped": ("rates[i] = max(-self.max_rate[i], min(self.max_rate[i], rate))",
                                 "rates[i] = rate"),
     "modulus_branch_not_squared": ('M[i] += float(c["kn"]) * (di * ni) * (di * ni)',
