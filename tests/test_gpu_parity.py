@@ -506,6 +506,44 @@ def test_long_rows_summed_by_the_wave(precision, tol):
     assert np.all(dw <= tol * scale[big] * R * dt / inertia + 4 * EPS * np.linalg.norm(so["angvel"][big], axis=1))
 
 
+def test_row_longer_than_a_waves_lds_share():
+    """A 9 mm sphere in a shell of 1,200 spheres of 0.5 mm that overlap it
+    slightly: its row (over 1,024 entries) is ranked from memory rather
+    than from the wave's LDS share, and summed by the whole wave in about
+    twenty rounds.  Pair set, forces and the big sphere's velocity after
+    one step (no gravity, no damping, big sphere at rest) against the
+    oracle."""
+    from paper_2301_00611_amd.scenes import Material, Scene, random_velocities
+    rng = np.random.default_rng(23)
+    R, r, k = 9.0e-3, 0.5e-3, 1200
+    c = np.array([0.03, 0.03, 0.03])
+    i = np.arange(k) + 0.5
+    z = 1.0 - 2.0 * i / k
+    phi = np.pi * (1.0 + 5 ** 0.5) * i
+    d = np.stack([np.sqrt(1 - z * z) * np.cos(phi), np.sqrt(1 - z * z) * np.sin(phi), z], axis=1)
+    pos = np.vstack([c, c + d * (R + r - rng.uniform(1e-5, 5e-5, size=(k, 1)))])
+    rad = np.array([R] + [r] * k)
+    spec = Scene(pos=pos, radius=rad, material=Material(2600.0, 1e7, 0.3, 0.5), gravity=(0.0, 0.0, 0.0),
+                 damping=0.0)
+    v, w = random_velocities(len(rad), 0.01, 24)
+    v[0] = 0.0
+    w[0] = 0.0
+    g, o, dt = twin(spec, vel=v, angvel=w)
+    g.step(1)
+    o.step(1)
+    cg, co = g.get_contacts(), o.get_contacts()
+    assert keyset(cg) == keyset(co)
+    assert int(np.sum((co["id1"] == 0) | (co["id2"] == 0))) > 1100   # the big sphere's row passes 1,024
+    assert contact_errors(cg, co)["f"].max() <= 1e-12
+    sg, so = g.get_state(), o.get_state()
+    ef, _ = body_force_errors(sg, so, co)
+    assert ef.max() <= 1e-12
+    mag = np.linalg.norm(co["fn"] + co["fs"], axis=1)
+    big = (co["id1"] == 0) | (co["id2"] == 0)
+    m = 4.0 / 3.0 * np.pi * R ** 3 * 2600.0
+    assert np.linalg.norm(sg["vel"][0] - so["vel"][0]) <= 1e-12 * mag[big].sum() * dt / m
+
+
 @pytest.mark.parametrize("rmin,rmax", [(0.8e-3, 1.2e-3), (0.5e-3, 1.5e-3)])
 def test_rows_past_the_fill_pool(rmin, rmax):
     """A Verlet distance of three smallest radii gives every sphere of a
