@@ -3,16 +3,61 @@
 Each case applies one deliberate mistake to a private copy of the oracle's
 C source (a dropped term, a flipped sign, a wrong factor), builds it, and
 runs the pin tests against that build: at least one pin must fail.  The
-mistakes are planted in the oracle on the CPU only.
+mistakes are planted in the oracle on the CPU only.  The builds and pin
+runs of a table go on a few workers at once, the first time one of its
+cases is asked for; each case then reports its own result.
 """
+import json
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "dem_oracle.c")
+WORKERS = max(1, min(8, os.cpu_count() or 1))
+
+
+def _run_c_mutant(name, before, after, pins, workdir):
+    """Build the oracle with one planted slip and run a pin file against it,
+    stopping at the first failure: (exit status, end of the output), or
+    (None, message) when the slip's anchor is not found exactly once."""
+    src = open(SRC).read()
+    if src.count(before) != 1:
+        return None, f"mutation anchor not found: {name}"
+    d = os.path.join(workdir, name)
+    os.makedirs(d, exist_ok=True)
+    mutated = os.path.join(d, "dem_oracle_mutated.c")
+    with open(mutated, "w") as f:
+        f.write(src.replace(before, after))
+    lib = os.path.join(d, "libdem_oracle_mutated.so")
+    subprocess.run(["gcc", "-std=c99", "-D_DEFAULT_SOURCE", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+                    "-I", os.path.join(ROOT, "oracle"), "-o", lib, mutated, "-lm"], check=True)
+    env = dict(os.environ, DEM_ORACLE_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider", pins],
+                       env=env, capture_output=True, text=True, cwd=ROOT, timeout=900)
+    return r.returncode, r.stdout[-2000:]
+
+
+def _run_all(table, run_one):
+    """Every slip of a table, run_one(name, before, after) on a few workers."""
+    with ThreadPoolExecutor(WORKERS) as ex:
+        futures = {name: ex.submit(run_one, name, *table[name]) for name in table}
+    return {name: f.result() for name, f in futures.items()}
+
+
+def _c_results(table, pin_file, tmp_path_factory):
+    pins = os.path.join(ROOT, "tests", pin_file)
+    work = str(tmp_path_factory.mktemp("mutants"))
+    return _run_all(table, lambda name, before, after: _run_c_mutant(name, before, after, pins, work))
+
+
+def _assert_caught(name, result):
+    rc, out = result
+    assert rc is not None, out
+    assert rc != 0 and "FAILED" in out, f"no pin caught mutation {name} (exit {rc}):\n{out}"
 
 MUTATIONS = {
     "drop_twist_term": ("cross3(fs_old, spinv, inc2);", "inc2[0] = inc2[1] = inc2[2] = 0.0;"),
@@ -83,22 +128,14 @@ MUTATIONS = {
 }
 
 
+@pytest.fixture(scope="module")
+def pins_results(tmp_path_factory):
+    return _c_results(MUTATIONS, "test_oracle_pins.py", tmp_path_factory)
+
+
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
-def test_pins_catch_mutation(name, tmp_path):
-    before, after = MUTATIONS[name]
-    src = open(SRC).read()
-    assert src.count(before) == 1, f"mutation anchor not found: {name}"
-    mutated = tmp_path / "dem_oracle_mutated.c"
-    mutated.write_text(src.replace(before, after))
-    lib = tmp_path / "libdem_oracle_mutated.so"
-    subprocess.run(["gcc", "-std=c99", "-D_DEFAULT_SOURCE", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
-                    "-I", os.path.join(ROOT, "oracle"), "-o", str(lib), str(mutated), "-lm"], check=True)
-    env = dict(os.environ, DEM_ORACLE_LIB=str(lib))
-    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
-                       env=env, capture_output=True, text=True, cwd=ROOT, timeout=600)
-    assert r.returncode != 0, f"no pin caught mutation {name}:\n{r.stdout[-2000:]}"
-    assert "FAILED" in r.stdout
+def test_pins_catch_mutation(name, pins_results):
+    _assert_caught(name, pins_results[name])
 
 
 # slips in the box and facet boundaries, caught by tests/test_oracle_boundaries.py
@@ -125,22 +162,14 @@ BOUNDARY_MUTATIONS = {
 }
 
 
+@pytest.fixture(scope="module")
+def boundary_results(tmp_path_factory):
+    return _c_results(BOUNDARY_MUTATIONS, "test_oracle_boundaries.py", tmp_path_factory)
+
+
 @pytest.mark.parametrize("name", sorted(BOUNDARY_MUTATIONS))
-def test_boundary_pins_catch_mutation(name, tmp_path):
-    before, after = BOUNDARY_MUTATIONS[name]
-    src = open(SRC).read()
-    assert src.count(before) == 1, f"mutation anchor not found: {name}"
-    mutated = tmp_path / "dem_oracle_mutated.c"
-    mutated.write_text(src.replace(before, after))
-    lib = tmp_path / "libdem_oracle_mutated.so"
-    subprocess.run(["gcc", "-std=c99", "-D_DEFAULT_SOURCE", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
-                    "-I", os.path.join(ROOT, "oracle"), "-o", str(lib), str(mutated), "-lm"], check=True)
-    env = dict(os.environ, DEM_ORACLE_LIB=str(lib))
-    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_boundaries.py")],
-                       env=env, capture_output=True, text=True, cwd=ROOT, timeout=600)
-    assert r.returncode != 0, f"no pin caught mutation {name}:\n{r.stdout[-2000:]}"
-    assert "FAILED" in r.stdout
+def test_boundary_pins_catch_mutation(name, boundary_results):
+    _assert_caught(name, boundary_results[name])
 
 
 # slips in the visco-elastic law, caught by tests/test_oracle_viscel.py
@@ -164,22 +193,14 @@ VISCEL_MUTATIONS = {
 }
 
 
+@pytest.fixture(scope="module")
+def viscel_results(tmp_path_factory):
+    return _c_results(VISCEL_MUTATIONS, "test_oracle_viscel.py", tmp_path_factory)
+
+
 @pytest.mark.parametrize("name", sorted(VISCEL_MUTATIONS))
-def test_viscel_pins_catch_mutation(name, tmp_path):
-    before, after = VISCEL_MUTATIONS[name]
-    src = open(SRC).read()
-    assert src.count(before) == 1, f"mutation anchor not found: {name}"
-    mutated = tmp_path / "dem_oracle_mutated.c"
-    mutated.write_text(src.replace(before, after))
-    lib = tmp_path / "libdem_oracle_mutated.so"
-    subprocess.run(["gcc", "-std=c99", "-D_DEFAULT_SOURCE", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
-                    "-I", os.path.join(ROOT, "oracle"), "-o", str(lib), str(mutated), "-lm"], check=True)
-    env = dict(os.environ, DEM_ORACLE_LIB=str(lib))
-    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_viscel.py")],
-                       env=env, capture_output=True, text=True, cwd=ROOT, timeout=600)
-    assert r.returncode != 0, f"no pin caught mutation {name}:\n{r.stdout[-2000:]}"
-    assert "FAILED" in r.stdout
+def test_viscel_pins_catch_mutation(name, viscel_results):
+    _assert_caught(name, viscel_results[name])
 
 
 # slips in the controllers (oracle/controls.py, Python), caught by
@@ -230,20 +251,30 @@ before, after = json.loads(sys.argv[1])
 src = open(C.__file__).read()
 exec(compile(src.replace(before, after), C.__file__, "exec"), C.__dict__)
 import pytest
-sys.exit(pytest.main(["-q", "-p", "no:cacheprovider", {pins!r}]))
+sys.exit(pytest.main(["-q", "-x", "-p", "no:cacheprovider", {pins!r}]))
 """
 
 
-@pytest.mark.parametrize("name", sorted(CONTROL_MUTATIONS))
-def test_control_pins_catch_mutation(name, tmp_path):
-    import json
-    before, after = CONTROL_MUTATIONS[name]
+def _run_control_mutant(name, before, after, workdir):
     src = open(os.path.join(ROOT, "oracle", "controls.py")).read()
-    assert src.count(before) == 1, f"mutation anchor not found: {name}"
-    driver = tmp_path / "driver.py"
-    driver.write_text(_CONTROL_DRIVER.format(root=ROOT, tests=os.path.join(ROOT, "tests"),
-                                             pins=os.path.join(ROOT, "tests", "test_oracle_controls.py")))
-    r = subprocess.run([sys.executable, str(driver), json.dumps([before, after])], capture_output=True,
-                       text=True, cwd=str(tmp_path), timeout=600)
-    assert r.returncode == 1, f"no pin caught mutation {name} (exit {r.returncode}):\n{r.stdout[-2000:]}"
-    assert "FAILED" in r.stdout
+    if src.count(before) != 1:
+        return None, f"mutation anchor not found: {name}"
+    driver = os.path.join(workdir, name + "_driver.py")
+    with open(driver, "w") as f:
+        f.write(_CONTROL_DRIVER.format(root=ROOT, tests=os.path.join(ROOT, "tests"),
+                                       pins=os.path.join(ROOT, "tests", "test_oracle_controls.py")))
+    r = subprocess.run([sys.executable, driver, json.dumps([before, after])], capture_output=True, text=True,
+                       cwd=workdir, timeout=900)
+    # 1: the pins ran and one failed (not a crash of the harness)
+    return (r.returncode if r.returncode in (0, 1) else None), r.stdout[-2000:] + r.stderr[-500:]
+
+
+@pytest.fixture(scope="module")
+def control_results(tmp_path_factory):
+    work = str(tmp_path_factory.mktemp("control_mutants"))
+    return _run_all(CONTROL_MUTATIONS, lambda name, before, after: _run_control_mutant(name, before, after, work))
+
+
+@pytest.mark.parametrize("name", sorted(CONTROL_MUTATIONS))
+def test_control_pins_catch_mutation(name, control_results):
+    _assert_caught(name, control_results[name])
